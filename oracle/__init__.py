@@ -1,0 +1,351 @@
+"""Python wrapper of the plain C FP64 oracle (``dg_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the reference the GPU library is checked against.
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  It imports nothing from the GPU
+library; the only code it shares with it is the seeded workload generator in
+``workloads`` (problem definitions and random numbers, no DG arithmetic).
+
+State arrays use the layout ``[nvar][N][nz][ny][nx]`` (x fastest, nz = 1 in
+2D), modes ordered by total degree, then x-exponent descending, then
+y-exponent descending; variables (rho, m_x, m_y[, m_z], E).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import itertools
+import os
+import subprocess
+
+import numpy as np
+
+import workloads
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "dg_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_CS = os.path.join(_HERE, "liboracle_cs.so")
+
+ORC_OK, ORC_EINVAL, ORC_ENEGATIVE = 0, -1, -2
+
+
+def build(force: bool = True) -> None:
+    """Compile the oracle (real and complex-step variants) with gcc."""
+    common = ["gcc", "-O2", "-ffp-contract=off", "-std=c11", "-fPIC", "-shared", "-Wall"]
+    for out, extra in ((_LIB, []), (_LIB_CS, ["-DORC_CS", "-fcx-limited-range"])):
+        if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+            tmp = out + ".tmp"
+            subprocess.run(common + extra + ["-o", tmp, _SRC, "-lm"], check=True)
+            os.replace(tmp, out)
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("k", C.c_int), ("n", C.c_int * 3),
+        ("x0", C.c_double * 3), ("len", C.c_double * 3),
+        ("gamma", C.c_double), ("cfl", C.c_double),
+        ("bc", C.c_int * 3), ("flux", C.c_int), ("limiter", C.c_int),
+        ("beta", C.c_double), ("mtilde", C.c_double),
+        ("positivity", C.c_int), ("eps", C.c_double),
+        ("refine_lo", C.c_int * 3), ("refine_hi", C.c_int * 3),
+    ]
+
+
+_lib = None
+_lib_cs = None
+
+
+def _load():
+    global _lib, _lib_cs
+    if _lib is None:
+        if not (os.path.exists(_LIB) and os.path.exists(_LIB_CS)):
+            build(force=False)
+        _lib = C.CDLL(_LIB)
+        _lib_cs = C.CDLL(_LIB_CS)
+        dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+        lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+        ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+        cp = C.POINTER(Config)
+        sig = {
+            "orc_sizes": [cp, lp],
+            "orc_gauss": [C.c_int, dp, dp],
+            "orc_gll": [C.c_int, dp, dp],
+            "orc_exponents": [cp, ip],
+            "orc_basis_at": [cp, C.c_long, dp, dp],
+            "orc_volume_rule": [cp, dp, dp],
+            "orc_node_coords": [cp, dp],
+            "orc_project": [cp, dp, dp],
+            "orc_eval_points": [cp, dp, C.c_long, dp, dp],
+            "orc_hllc": [cp, dp, dp, C.c_int, dp],
+            "orc_euler_flux": [cp, dp, C.c_int, dp],
+            "orc_rhs": [cp, dp, dp],
+            "orc_rhs_cells": [cp, dp, C.c_long, lp, dp],
+            "orc_terms_cell": [cp, dp, C.c_long, dp, dp],
+            "orc_max_dt": [cp, dp, dp],
+            "orc_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
+            "orc_limit": [cp, dp],
+            "orc_positivity_points": [cp, dp],
+        }
+        for name, args in sig.items():
+            f = getattr(_lib, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        _lib.orc_legendre.argtypes = [C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        _lib.orc_legendre.restype = None
+        _lib.orc_rk3_combine.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp, C.c_long]
+        _lib.orc_rk3_combine.restype = None
+        _lib_cs.orc_cs_rhs.argtypes = [cp, dp, dp, C.c_double, dp, dp]
+        _lib_cs.orc_cs_rhs.restype = C.c_int
+        _lib_cs.orc_cs_traj.argtypes = [cp, dp, dp, C.c_double, C.c_int, C.c_double, dp, dp]
+        _lib_cs.orc_cs_traj.restype = C.c_int
+    return _lib, _lib_cs
+
+
+def _check(st: int, what: str) -> None:
+    if st != ORC_OK:
+        raise RuntimeError(f"oracle {what} failed with status {st}")
+
+
+# ---------------------------------------------------------------------------
+# 1D rules and Legendre polynomials
+# ---------------------------------------------------------------------------
+
+def gauss(n: int):
+    lib, _ = _load()
+    x = np.zeros(n); w = np.zeros(n)
+    _check(lib.orc_gauss(n, x, w), "gauss")
+    return x, w
+
+
+def gll(m: int):
+    lib, _ = _load()
+    x = np.zeros(m); w = np.zeros(m)
+    _check(lib.orc_gll(m, x, w), "gll")
+    return x, w
+
+
+def legendre(n: int, x: float):
+    lib, _ = _load()
+    P = C.c_double(); dP = C.c_double()
+    lib.orc_legendre(n, float(x), C.byref(P), C.byref(dP))
+    return P.value, dP.value
+
+
+class Oracle:
+    """One configured DG run (uniform Cartesian grid)."""
+
+    def __init__(self, wl: dict):
+        self.wl = dict(wl)
+        c = Config()
+        c.dim = wl["dim"]; c.k = wl["k"]
+        c.n[:] = list(wl["n"])
+        c.x0[:] = list(wl["x0"]); c.len[:] = list(wl["length"])
+        c.gamma = wl["gamma"]; c.cfl = wl["cfl"]
+        c.bc[:] = list(wl.get("bc", (0, 0, 0)))
+        c.flux = wl.get("flux", 0)
+        c.limiter = wl.get("limiter", 0)
+        c.beta = wl.get("beta", 1.0); c.mtilde = wl.get("mtilde", 0.5)
+        c.positivity = wl.get("positivity", 0); c.eps = wl.get("eps", 1e-10)
+        c.refine_lo[:] = list(wl.get("refine_lo", (0, 0, 0)))
+        c.refine_hi[:] = list(wl.get("refine_hi", (0, 0, 0)))
+        self.c = c
+        lib, _ = _load()
+        sizes = np.zeros(7, dtype=np.int64)
+        _check(lib.orc_sizes(C.byref(c), sizes), "sizes")
+        self.N, self.Q, self.Qf, self.nvar, self.ncell, self.m, self.nS = (int(s) for s in sizes)
+        self.dim = c.dim
+        nz = wl["n"][2] if c.dim == 3 else 1
+        self.shape = (self.nvar, self.N, nz, wl["n"][1], wl["n"][0])
+        self.dx = wl["length"][0] / wl["n"][0]
+
+    # -- tables -------------------------------------------------------------
+    def exponents(self) -> np.ndarray:
+        lib, _ = _load()
+        e = np.zeros(self.N * 3, dtype=np.int32)
+        _check(lib.orc_exponents(C.byref(self.c), e), "exponents")
+        return e.reshape(self.N, 3)
+
+    def basis_at(self, xi) -> np.ndarray:
+        lib, _ = _load()
+        xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
+        out = np.zeros((xi.shape[0], self.N))
+        _check(lib.orc_basis_at(C.byref(self.c), xi.shape[0], xi, out), "basis_at")
+        return out
+
+    def volume_rule(self):
+        lib, _ = _load()
+        xi = np.zeros((self.Q, 3)); w = np.zeros(self.Q)
+        _check(lib.orc_volume_rule(C.byref(self.c), xi, w), "volume_rule")
+        return xi, w
+
+    def positivity_points(self) -> np.ndarray:
+        lib, _ = _load()
+        xi = np.zeros((self.nS, 3))
+        _check(lib.orc_positivity_points(C.byref(self.c), xi), "positivity_points")
+        return xi
+
+    # -- initial state ------------------------------------------------------
+    def node_coords(self) -> np.ndarray:
+        lib, _ = _load()
+        x = np.zeros((self.ncell, self.Q, 3))
+        _check(lib.orc_node_coords(C.byref(self.c), x), "node_coords")
+        return x
+
+    def project_prim(self, prim: np.ndarray) -> np.ndarray:
+        """L2 projection of primitives prim[ncell][Q][5] given at the nodes."""
+        lib, _ = _load()
+        prim = np.ascontiguousarray(prim, dtype=np.float64)
+        assert prim.shape == (self.ncell, self.Q, 5)
+        w = np.zeros(self.shape)
+        _check(lib.orc_project(C.byref(self.c), prim, w), "project")
+        return w
+
+    def initial_state(self, t: float = 0.0) -> np.ndarray:
+        """Project the workload's initial (or, with t > 0, exact) solution."""
+        x = self.node_coords()
+        cell = np.repeat(np.arange(self.ncell), self.Q).reshape(self.ncell, self.Q)
+        node = np.tile(np.arange(self.Q), self.ncell).reshape(self.ncell, self.Q)
+        wl = dict(self.wl); wl["nq"] = self.Q
+        prim = np.stack(workloads.primitives(wl, x[..., 0], x[..., 1], x[..., 2],
+                                             cell=cell, node=node, t=t), axis=-1)
+        return self.project_prim(prim)
+
+    # -- evaluation ---------------------------------------------------------
+    def eval_points(self, w: np.ndarray, xi) -> np.ndarray:
+        lib, _ = _load()
+        xi = np.ascontiguousarray(np.asarray(xi, dtype=np.float64).reshape(-1, 3))
+        out = np.zeros((self.ncell, xi.shape[0], self.nvar))
+        _check(lib.orc_eval_points(C.byref(self.c), self._s(w), xi.shape[0], xi, out), "eval")
+        return out
+
+    def hllc(self, UL, UR, axis: int) -> np.ndarray:
+        lib, _ = _load()
+        F = np.zeros(self.nvar)
+        _check(lib.orc_hllc(C.byref(self.c), np.ascontiguousarray(UL, dtype=np.float64),
+                            np.ascontiguousarray(UR, dtype=np.float64), axis, F), "hllc")
+        return F
+
+    def euler_flux(self, U, axis: int) -> np.ndarray:
+        lib, _ = _load()
+        F = np.zeros(self.nvar)
+        _check(lib.orc_euler_flux(C.byref(self.c), np.ascontiguousarray(U, dtype=np.float64), axis, F), "flux")
+        return F
+
+    # -- the scheme ---------------------------------------------------------
+    def _s(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        assert w.size == int(np.prod(self.shape)), (w.shape, self.shape)
+        return w
+
+    def rhs(self, w: np.ndarray) -> np.ndarray:
+        lib, _ = _load()
+        L = np.zeros(self.shape)
+        _check(lib.orc_rhs(C.byref(self.c), self._s(w), L), "rhs")
+        return L
+
+    def rhs_cells(self, w: np.ndarray, cells) -> np.ndarray:
+        """RHS of selected (flat-indexed) cells: out[nvar][N][len(cells)]."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((self.nvar, self.N, cells.size))
+        _check(lib.orc_rhs_cells(C.byref(self.c), self._s(w), cells.size, cells, out), "rhs_cells")
+        return out
+
+    def terms_cell(self, w: np.ndarray, cell: int):
+        lib, _ = _load()
+        V = np.zeros((self.nvar, self.N)); S = np.zeros((self.nvar, self.N))
+        _check(lib.orc_terms_cell(C.byref(self.c), self._s(w), cell, V, S), "terms")
+        return V, S
+
+    def max_dt(self, w: np.ndarray) -> float:
+        lib, _ = _load()
+        dt = np.zeros(1)
+        _check(lib.orc_max_dt(C.byref(self.c), self._s(w), dt), "max_dt")
+        return float(dt[0])
+
+    def rk3_stage(self, stage: int, dt: float, wn: np.ndarray, wp: np.ndarray) -> np.ndarray:
+        lib, _ = _load()
+        out = np.zeros(self.shape)
+        _check(lib.orc_rk3_stage(C.byref(self.c), stage, dt, self._s(wn), self._s(wp), out), "rk3_stage")
+        return out
+
+    def limit(self, w: np.ndarray) -> tuple[np.ndarray, int]:
+        """Slope then positivity limiter; returns (limited copy, status)."""
+        lib, _ = _load()
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_limit(C.byref(self.c), out)
+        return out, st
+
+    def stage(self, stage: int, dt: float, wn: np.ndarray, wp: np.ndarray) -> np.ndarray:
+        """RK stage followed by the limiters, if the run has any (main loop)."""
+        out = self.rk3_stage(stage, dt, wn, wp)
+        if self.c.limiter or self.c.positivity:
+            out, st = self.limit(out)
+            _check(st, "limit")
+        return out
+
+    def step(self, w: np.ndarray, dt: float | None = None) -> tuple[np.ndarray, float]:
+        if dt is None:
+            dt = self.max_dt(w)
+        w1 = self.stage(1, dt, w, w)
+        w2 = self.stage(2, dt, w, w1)
+        w3 = self.stage(3, dt, w, w2)
+        return w3, dt
+
+    def run(self, w: np.ndarray, steps: int, dt: float | None = None):
+        t = 0.0
+        for _ in range(steps):
+            w, h = self.step(w, dt)
+            t += h
+        return w, t
+
+    # -- derivatives (complex step) ------------------------------------------
+    def jvp_rhs(self, w: np.ndarray, v: np.ndarray, h: float = 1e-30):
+        """(L(w), dL/dw . v) by the complex step."""
+        _, cs = _load()
+        L = np.zeros(self.shape); dL = np.zeros(self.shape)
+        _check(cs.orc_cs_rhs(C.byref(self.c), self._s(w), self._s(v), h, L, dL), "cs_rhs")
+        return L, dL
+
+    def jvp_traj(self, w0: np.ndarray, v: np.ndarray, steps: int, dt: float, h: float = 1e-30):
+        """(w_T, dw_T/dw_0 . v) of `steps` unlimited SSP-RK3 steps at fixed dt."""
+        _, cs = _load()
+        wT = np.zeros(self.shape); dwT = np.zeros(self.shape)
+        _check(cs.orc_cs_traj(C.byref(self.c), self._s(w0), self._s(v), h, steps, dt, wT, dwT), "cs_traj")
+        return wT, dwT
+
+    # -- diagnostics -------------------------------------------------------
+    def totals(self, w: np.ndarray) -> np.ndarray:
+        """Domain integrals of the conserved variables: sum_K |K| w_1."""
+        w = np.asarray(w).reshape(self.nvar, self.N, -1)
+        return w[:, 0, :].sum(axis=1) * self.dx ** self.dim
+
+    def l1_density_error(self, w: np.ndarray, t: float) -> float:
+        """(1/V) int |rho_h - rho_exact(t)| dV with (k+3)^d Gauss points per cell."""
+        k, d = self.wl["k"], self.dim
+        g, gw = gauss(k + 3)
+        pts, wq = [], []
+        for idx in itertools.product(range(g.size), repeat=d):
+            idx = idx[::-1]  # x index fastest
+            p = [0.0, 0.0, 0.0]
+            ww = 1.0
+            for a in range(d):
+                p[a] = g[idx[a]]
+                ww *= gw[idx[a]]
+            pts.append(p)
+            wq.append(ww)
+        xi = np.array(pts)
+        wq = np.array(wq)
+        u = self.eval_points(w, xi)  # [ncell][npts][nvar]
+        nx, ny = self.wl["n"][0], self.wl["n"][1]
+        nz = self.wl["n"][2] if d == 3 else 1
+        cid = np.arange(self.ncell)
+        ix, iy, iz = cid % nx, (cid // nx) % ny, cid // (nx * ny)
+        x0 = self.wl["x0"]
+        X = x0[0] + (ix[:, None] + 0.5 + 0.5 * xi[None, :, 0]) * self.dx
+        Y = x0[1] + (iy[:, None] + 0.5 + 0.5 * xi[None, :, 1]) * self.dx
+        Z = (x0[2] + (iz[:, None] + 0.5 + 0.5 * xi[None, :, 2]) * self.dx) if d == 3 else np.zeros_like(X)
+        wl = dict(self.wl); wl["noise"] = 0.0
+        rho_ex = workloads.primitives(wl, X, Y, Z, t=t)[0]
+        err = np.abs(u[:, :, 0] - rho_ex)
+        return float((err * wq[None, :]).sum() / (2.0 ** d) / self.ncell)

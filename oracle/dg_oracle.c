@@ -1,0 +1,905 @@
+/*
+ * Plain single-threaded FP64 reference implementation of the modal DG scheme
+ * for the compressible Euler equations of Schaal et al. (2015), "Astrophysical
+ * hydrodynamics with a high order discontinuous Galerkin scheme and adaptive
+ * mesh refinement".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is the oracle against which the GPU library
+ * is checked.  Only the tests, the smoke check and the benchmark's CPU
+ * baseline may load it.  It shares no code with the GPU library: its own
+ * Legendre recurrence, Newton root finding, tables, flux, Riemann solver,
+ * limiters and time integrator live here and nowhere else.
+ *
+ * Written for clarity, not speed: dense loops over cells, quadrature nodes and
+ * basis functions, in the order the paper states the method.  Build with
+ * -O2 -ffp-contract=off so no fused multiply-add changes the rounding.
+ *
+ * The same file compiles twice:
+ *   - plain (real_t = double): the reference results;
+ *   - with -DORC_CS (real_t = double complex): the complex-step derivative
+ *     f'(x) v = Im f(x + i h v) / h, exact to rounding, used as the reference
+ *     for the discrete adjoint.  Branches compare real parts only.
+ *
+ * Sources (sections and equations of the paper):
+ *   Euler fluxes and EOS ............ Sec. 2.1, eqs. euler, flux_vectors, eos
+ *   modal basis, orthonormality ..... Sec. 2.2, eqs. weights, set_basis_functions
+ *   L2 projection of the ICs ........ Sec. 2.3
+ *   weak form, volume/face terms .... Sec. 2.4, eqs. dg_projected, dg_term2, dg_term3
+ *   time step ....................... Sec. 2.5 eq. time_step; Sec. 3.4 eq. time_step_pos
+ *   component-wise TVB minmod ....... Sec. 3.1 eq. comp_limiter; Sec. 3.3
+ *   positivity limiter .............. Sec. 3.4, eqs. union_quad_points, p_positivity
+ *   AMR faces / limiting ............ Sec. 4 (hanging-face quadrature), Sec. 4.4
+ *   refinement matrices ............. Sec. 4.2 eq. ref_pa_integral, App. F
+ *   Legendre, Gauss, GLL ............ App. A, B, C
+ *   SSP-RK3 ......................... App. D, table RK_3
+ * The HLLC Riemann solver is cited by the paper to Toro's textbook only; the
+ * textbook HLLC with Einfeldt-Batten (Roe-averaged) wave-speed bounds is
+ * used, with a Davis-bound option.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+#ifdef ORC_CS
+#include <complex.h>
+typedef double complex real_t;
+#define RE(x) creal(x)
+#define RSQRT(x) csqrt(x)
+#define API(name) orc_cs_##name
+#else
+typedef double real_t;
+#define RE(x) (x)
+#define RSQRT(x) sqrt(x)
+#define API(name) orc_##name
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENEGATIVE (-2)
+#define ORC_ENOMEM (-3)
+
+#define MAXK 4
+#define MAXN 35  /* N_3(4) */
+#define MAXQ 125 /* (k+1)^3 */
+#define MAXQF 25 /* (k+1)^2 */
+#define MAXV 5
+#define MAXM 4   /* GLL points */
+#define MAXS 300 /* d * m * (k+1)^(d-1) */
+
+/* Run description.  Mirrored field by field by the Python wrapper. */
+typedef struct {
+  int dim, k;
+  int n[3];
+  double x0[3], len[3];
+  double gamma, cfl;
+  int bc[3];       /* 0 periodic, 1 transmissive (ghost trace = own trace)   */
+  int flux;        /* 0 HLLC with Einfeldt-Batten speeds, 1 HLLC with Davis */
+  int limiter;     /* 0 none, 1 component-wise minmod with TVB bound        */
+  double beta, mtilde;
+  int positivity;  /* 0/1 Zhang-Shu positivity limiter                      */
+  double eps;
+  int refine_lo[3], refine_hi[3]; /* static 2:1 box in base-cell indices      */
+} orc_config;
+
+/* ------------------------------------------------------------------------ */
+/* Legendre polynomials (App. A) and quadrature rules (App. B, C)            */
+/* ------------------------------------------------------------------------ */
+
+/* P_n(x) and P_n'(x) by Bonnet's three-term recurrence,
+ * (m+1) P_{m+1} = (2m+1) x P_m - m P_{m-1}, with P'_{m+1} = P'_{m-1} + (2m+1) P_m. */
+static void legendre(int n, double x, double *P, double *dP) {
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+  if (n == 0) { *P = 1.0; *dP = 0.0; return; }
+  for (int m = 1; m < n; ++m) {
+    double p2 = ((2.0 * m + 1.0) * x * p1 - m * p0) / (m + 1.0);
+    double d2 = d0 + (2.0 * m + 1.0) * p1;
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  *P = p1; *dP = d1;
+}
+
+/* Scaled Legendre polynomial sqrt(2n+1) P_n and its derivative (App. A). */
+static double ptilde(int n, double x) { double P, dP; legendre(n, x, &P, &dP); return sqrt(2.0 * n + 1.0) * P; }
+static double dptilde(int n, double x) { double P, dP; legendre(n, x, &P, &dP); return sqrt(2.0 * n + 1.0) * dP; }
+
+/* n-point Gauss-Legendre rule (App. B): Newton on P_n from Lether's start
+ * value, weights 2 / ((1 - x^2) P_n'(x)^2).  Returned in ascending order. */
+static void gauss_rule(int n, double *x, double *w) {
+  for (int q = 1; q <= n; ++q) {
+    double nn = (double)n;
+    double xi = (1.0 - 1.0 / (8.0 * nn * nn) + 1.0 / (8.0 * nn * nn * nn)) *
+                cos(M_PI * (4.0 * q - 1.0) / (4.0 * nn + 2.0));
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(n, xi, &P, &dP);
+      double step = P / dP;
+      xi -= step;
+      if (fabs(step) < 1e-16) break;
+    }
+    double P, dP;
+    legendre(n, xi, &P, &dP);
+    x[n - q] = xi; /* q = 1 is the largest root */
+    w[n - q] = 2.0 / ((1.0 - xi * xi) * dP * dP);
+  }
+}
+
+/* m-point Gauss-Lobatto-Legendre rule (App. C): the end points and the roots
+ * of P'_{m-1}; weights 2 / (m (m-1) P_{m-1}(x)^2).  Interior roots by Newton
+ * on P'_{m-1}, whose derivative follows from Legendre's equation. */
+static void gll_rule(int m, double *x, double *w) {
+  int n = m - 1;
+  x[0] = -1.0; x[m - 1] = 1.0;
+  for (int j = 1; j < m - 1; ++j) {
+    double xi = -cos(M_PI * j / (double)(m - 1));
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(n, xi, &P, &dP);
+      double d2P = (2.0 * xi * dP - n * (n + 1.0) * P) / (1.0 - xi * xi);
+      double step = dP / d2P;
+      xi -= step;
+      if (fabs(step) < 1e-16) break;
+    }
+    x[j] = xi;
+  }
+  for (int j = 0; j < m; ++j) {
+    double P, dP;
+    legendre(n, x[j], &P, &dP);
+    w[j] = 2.0 / (m * (m - 1.0) * P * P);
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Context: sizes and the tables of Sec. 2.2-2.4                             */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  orc_config c;
+  int d, k, n1, N, Q, Qf, nvar;
+  long nx, ny, nz, ncell; /* one uniform block */
+  double dx;
+  double gx[MAXK + 1], gw[MAXK + 1];
+  int e[MAXN][3];                        /* exponents of mode l            */
+  double phiV[MAXQ][MAXN], dphiV[3][MAXQ][MAXN], wV[MAXQ];
+  double phiF[3][2][MAXQF][MAXN], wF[MAXQF];
+  int m; double lx[MAXM], lw[MAXM];      /* GLL rule for positivity       */
+  int nS; double phiS[MAXS][MAXN];       /* union points S of Sec. 3.4     */
+} ctx;
+
+static double phi_at(const ctx *X, int l, const double *xi) {
+  double v = 1.0;
+  for (int a = 0; a < X->d; ++a) v *= ptilde(X->e[l][a], xi[a]);
+  return v;
+}
+
+static double dphi_at(const ctx *X, int a, int l, const double *xi) {
+  double v = 1.0;
+  for (int b = 0; b < X->d; ++b) v *= (b == a) ? dptilde(X->e[l][b], xi[b]) : ptilde(X->e[l][b], xi[b]);
+  return v;
+}
+
+/* Tangential axes of a face with normal axis a, in increasing order. */
+static void tangential(int d, int a, int *t) {
+  int j = 0;
+  for (int b = 0; b < d; ++b) if (b != a) t[j++] = b;
+}
+
+static int ctx_init(const orc_config *c, ctx *X) {
+  memset(X, 0, sizeof(*X));
+  X->c = *c;
+  if (c->dim < 2 || c->dim > 3 || c->k < 0 || c->k > MAXK) return ORC_EINVAL;
+  X->d = c->dim; X->k = c->k; X->n1 = c->k + 1;
+  X->nvar = c->dim + 2;
+  X->nx = c->n[0]; X->ny = c->n[1]; X->nz = (c->dim == 3) ? c->n[2] : 1;
+  if (X->nx < 1 || X->ny < 1 || X->nz < 1) return ORC_EINVAL;
+  X->ncell = X->nx * X->ny * X->nz;
+  X->dx = c->len[0] / c->n[0];
+  for (int a = 1; a < X->d; ++a) /* the paper's cells are cubes */
+    if (fabs(c->len[a] / c->n[a] - X->dx) > 1e-12 * X->dx) return ORC_EINVAL;
+
+  /* Basis index set {u+v+w <= k} (eq. set_basis_functions), ordered by total
+   * degree, then x-exponent descending, then y-exponent descending. */
+  int l = 0;
+  for (int deg = 0; deg <= X->k; ++deg)
+    for (int ex = deg; ex >= 0; --ex)
+      for (int ey = deg - ex; ey >= 0; --ey) {
+        int ez = deg - ex - ey;
+        if (X->d == 2 && ez != 0) continue;
+        X->e[l][0] = ex; X->e[l][1] = ey; X->e[l][2] = ez;
+        ++l;
+      }
+  X->N = l;
+
+  gauss_rule(X->n1, X->gx, X->gw);
+  X->Q = 1; for (int a = 0; a < X->d; ++a) X->Q *= X->n1;
+  X->Qf = X->Q / X->n1;
+
+  /* Volume nodes: tensor Gauss rule, x index fastest. */
+  for (int q = 0; q < X->Q; ++q) {
+    int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+    double xi[3] = {0, 0, 0}, w = 1.0;
+    for (int a = 0; a < X->d; ++a) { xi[a] = X->gx[iq[a]]; w *= X->gw[iq[a]]; }
+    X->wV[q] = w;
+    for (int j = 0; j < X->N; ++j) {
+      X->phiV[q][j] = phi_at(X, j, xi);
+      for (int a = 0; a < X->d; ++a) X->dphiV[a][q][j] = dphi_at(X, a, j, xi);
+    }
+  }
+  /* Face nodes: tensor Gauss rule on the d-1 tangential axes. */
+  for (int r = 0; r < X->Qf; ++r) {
+    int ir[2] = {r % X->n1, r / X->n1};
+    double w = 1.0;
+    for (int j = 0; j < X->d - 1; ++j) w *= X->gw[ir[j]];
+    X->wF[r] = w;
+  }
+  for (int a = 0; a < X->d; ++a) {
+    int t[2]; tangential(X->d, a, t);
+    for (int s = 0; s < 2; ++s)
+      for (int r = 0; r < X->Qf; ++r) {
+        int ir[2] = {r % X->n1, r / X->n1};
+        double xi[3] = {0, 0, 0};
+        xi[a] = s ? 1.0 : -1.0;
+        for (int j = 0; j < X->d - 1; ++j) xi[t[j]] = X->gx[ir[j]];
+        for (int jb = 0; jb < X->N; ++jb) X->phiF[a][s][r][jb] = phi_at(X, jb, xi);
+      }
+  }
+  /* Positivity points: smallest m >= (k+3)/2, S = union over a of
+   * (GLL in axis a) x (Gauss in the others) (eq. union_quad_points). */
+  X->m = (X->k + 4) / 2; /* ceil((k+3)/2) */
+  if (X->m < 2) X->m = 2;
+  gll_rule(X->m, X->lx, X->lw);
+  X->nS = 0;
+  for (int a = 0; a < X->d; ++a) {
+    int t[2]; tangential(X->d, a, t);
+    for (int r = 0; r < X->m; ++r)
+      for (int q = 0; q < X->Qf; ++q) {
+        int ir[2] = {q % X->n1, q / X->n1};
+        double xi[3] = {0, 0, 0};
+        xi[a] = X->lx[r];
+        for (int j = 0; j < X->d - 1; ++j) xi[t[j]] = X->gx[ir[j]];
+        for (int jb = 0; jb < X->N; ++jb) X->phiS[X->nS][jb] = phi_at(X, jb, xi);
+        ++X->nS;
+      }
+  }
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Euler flux and HLLC (Sec. 2.1; Sec. 2.4 numerical flux)                   */
+/* ------------------------------------------------------------------------ */
+
+static inline real_t rabs(real_t x) { return RE(x) < 0 ? -x : x; }
+static inline real_t rmin(real_t a, real_t b) { return RE(b) < RE(a) ? b : a; }
+static inline real_t rmax(real_t a, real_t b) { return RE(b) > RE(a) ? b : a; }
+
+static real_t pressure(const ctx *X, const real_t *U) {
+  real_t ke = 0.0;
+  for (int b = 0; b < X->d; ++b) ke += U[1 + b] * U[1 + b] / U[0];
+  return (X->c.gamma - 1.0) * (U[X->d + 1] - 0.5 * ke);
+}
+
+/* Physical flux f_a(U) (eq. flux_vectors; in 2D without the third velocity). */
+static void euler_flux(const ctx *X, const real_t *U, int a, real_t *F) {
+  int d = X->d;
+  real_t rho = U[0], E = U[d + 1];
+  real_t p = pressure(X, U);
+  real_t va = U[1 + a] / rho;
+  F[0] = U[1 + a];
+  for (int b = 0; b < d; ++b) F[1 + b] = U[1 + b] * va + (b == a ? p : 0.0);
+  F[d + 1] = (E + p) * va;
+}
+
+/* HLLC flux in the +a direction between left state UL and right state UR. */
+static void hllc(const ctx *X, const real_t *UL, const real_t *UR, int a, real_t *F) {
+  int d = X->d, nv = X->nvar;
+  double g = X->c.gamma;
+  real_t rL = UL[0], rR = UR[0];
+  real_t vL[3], vR[3];
+  for (int b = 0; b < d; ++b) { vL[b] = UL[1 + b] / rL; vR[b] = UR[1 + b] / rR; }
+  real_t pL = pressure(X, UL), pR = pressure(X, UR);
+  real_t cL = RSQRT(g * pL / rL), cR = RSQRT(g * pR / rR);
+  real_t uL = vL[a], uR = vR[a];
+  real_t SL, SR;
+  if (X->c.flux == 1) { /* Davis bounds */
+    SL = rmin(uL - cL, uR - cR);
+    SR = rmax(uL + cL, uR + cR);
+  } else {              /* Einfeldt-Batten bounds with Roe averages */
+    real_t sL = RSQRT(rL), sR = RSQRT(rR);
+    real_t HL = (UL[d + 1] + pL) / rL, HR = (UR[d + 1] + pR) / rR;
+    real_t q2 = 0.0, vt[3];
+    for (int b = 0; b < d; ++b) { vt[b] = (sL * vL[b] + sR * vR[b]) / (sL + sR); q2 += vt[b] * vt[b]; }
+    real_t Ht = (sL * HL + sR * HR) / (sL + sR);
+    real_t ct2 = (g - 1.0) * (Ht - 0.5 * q2);
+    real_t ct = RE(ct2) > 0 ? RSQRT(ct2) : 0.0;
+    SL = rmin(uL - cL, vt[a] - ct);
+    SR = rmax(uR + cR, vt[a] + ct);
+  }
+  real_t Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+              (rL * (SL - uL) - rR * (SR - uR));
+  real_t FL[MAXV], FR[MAXV];
+  if (0.0 <= RE(SL)) { euler_flux(X, UL, a, F); return; }
+  if (0.0 <= RE(Ss)) {
+    euler_flux(X, UL, a, FL);
+    real_t fac = rL * (SL - uL) / (SL - Ss);
+    real_t Us[MAXV];
+    Us[0] = fac;
+    for (int b = 0; b < d; ++b) Us[1 + b] = fac * (b == a ? Ss : vL[b]);
+    Us[d + 1] = fac * (UL[d + 1] / rL + (Ss - uL) * (Ss + pL / (rL * (SL - uL))));
+    for (int v = 0; v < nv; ++v) F[v] = FL[v] + SL * (Us[v] - UL[v]);
+    return;
+  }
+  if (0.0 < RE(SR)) {
+    euler_flux(X, UR, a, FR);
+    real_t fac = rR * (SR - uR) / (SR - Ss);
+    real_t Us[MAXV];
+    Us[0] = fac;
+    for (int b = 0; b < d; ++b) Us[1 + b] = fac * (b == a ? Ss : vR[b]);
+    Us[d + 1] = fac * (UR[d + 1] / rR + (Ss - uR) * (Ss + pR / (rR * (SR - uR))));
+    for (int v = 0; v < nv; ++v) F[v] = FR[v] + SR * (Us[v] - UR[v]);
+    return;
+  }
+  euler_flux(X, UR, a, F);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Uniform-grid right-hand side (Sec. 2.4)                                   */
+/* ------------------------------------------------------------------------ */
+
+#define W(v, l, cell) w[((long)(v) * X->N + (l)) * X->ncell + (cell)]
+
+/* Neighbour of `cell` along axis a in direction dir (+1/-1); -1 if the face
+ * is a transmissive boundary. */
+static long neighbour(const ctx *X, long cell, int a, int dir) {
+  long i[3] = {cell % X->nx, (cell / X->nx) % X->ny, cell / (X->nx * X->ny)};
+  long n[3] = {X->nx, X->ny, X->nz};
+  i[a] += dir;
+  if (i[a] < 0 || i[a] >= n[a]) {
+    if (X->c.bc[a] == 1) return -1;
+    i[a] = (i[a] + n[a]) % n[a];
+  }
+  return (i[2] * X->ny + i[1]) * X->nx + i[0];
+}
+
+/* Volume term V_j = sum_a sum_q f_a(U(xi_q)) dphi_j/dxi_a(xi_q) w_q (eq. dg_term2). */
+static void volume_term(const ctx *X, const real_t *w, long cell, real_t V[MAXV][MAXN]) {
+  for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) V[v][j] = 0.0;
+  for (int q = 0; q < X->Q; ++q) {
+    real_t U[MAXV], F[MAXV];
+    for (int v = 0; v < X->nvar; ++v) {
+      U[v] = 0.0;
+      for (int l = 0; l < X->N; ++l) U[v] += W(v, l, cell) * X->phiV[q][l];
+    }
+    for (int a = 0; a < X->d; ++a) {
+      euler_flux(X, U, a, F);
+      for (int v = 0; v < X->nvar; ++v)
+        for (int j = 0; j < X->N; ++j) V[v][j] += F[v] * X->dphiV[a][q][j] * X->wV[q];
+    }
+  }
+}
+
+static void face_trace(const ctx *X, const real_t *w, long cell, int a, int s, int r, real_t *U) {
+  for (int v = 0; v < X->nvar; ++v) {
+    U[v] = 0.0;
+    for (int l = 0; l < X->N; ++l) U[v] += W(v, l, cell) * X->phiF[a][s][r][l];
+  }
+}
+
+/* Surface term S_j = sum over the 2d faces of the cell of
+ * sum_r fbar . n phi_j(xi_r) w_r (eq. dg_term3); fbar is the HLLC flux of the
+ * low-side and high-side traces, n the outward normal. */
+static void surface_term(const ctx *X, const real_t *w, long cell, real_t S[MAXV][MAXN]) {
+  for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
+  for (int a = 0; a < X->d; ++a)
+    for (int s = 0; s < 2; ++s) {
+      long nb = neighbour(X, cell, a, s ? +1 : -1);
+      for (int r = 0; r < X->Qf; ++r) {
+        real_t Uo[MAXV], Un[MAXV], F[MAXV];
+        face_trace(X, w, cell, a, s, r, Uo);
+        if (nb >= 0) face_trace(X, w, nb, a, 1 - s, r, Un);
+        else for (int v = 0; v < X->nvar; ++v) Un[v] = Uo[v];
+        if (s) hllc(X, Uo, Un, a, F); /* own cell is the low side  */
+        else   hllc(X, Un, Uo, a, F); /* own cell is the high side */
+        for (int v = 0; v < X->nvar; ++v)
+          for (int j = 0; j < X->N; ++j) {
+            real_t t = F[v] * X->phiF[a][s][r][j] * X->wF[r];
+            if (s) S[v][j] += t; else S[v][j] -= t;
+          }
+      }
+    }
+}
+
+/* dw_j/dt = -R = (|K|)^-1 (dx/2)^(d-1) (V_j - S_j) = (2/dx) 2^-d (V_j - S_j). */
+static void rhs_cell(const ctx *X, const real_t *w, long cell, real_t Lc[MAXV][MAXN]) {
+  real_t V[MAXV][MAXN], S[MAXV][MAXN];
+  volume_term(X, w, cell, V);
+  surface_term(X, w, cell, S);
+  double fac = 2.0 / X->dx / (double)(1 << X->d);
+  for (int v = 0; v < X->nvar; ++v)
+    for (int j = 0; j < X->N; ++j) Lc[v][j] = fac * (V[v][j] - S[v][j]);
+}
+
+static void rhs_all(const ctx *X, const real_t *w, real_t *L) {
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    real_t Lc[MAXV][MAXN];
+    rhs_cell(X, w, cell, Lc);
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) L[((long)v * X->N + j) * X->ncell + cell] = Lc[v][j];
+  }
+}
+
+/* SSP-RK3 (table RK_3) in its convex-combination (Shu-Osher) form:
+ * stage 1: w1 = w0 + dt L(w0); stage 2: w2 = 3/4 w0 + 1/4 (w1 + dt L(w1));
+ * stage 3: w3 = 1/3 w0 + 2/3 (w2 + dt L(w2)). */
+static const double RK3_A[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double RK3_B[3] = {1.0, 0.25, 2.0 / 3.0};
+
+static void rk3_combine(int stage, real_t dt, const real_t *wn, const real_t *wp, const real_t *L,
+                        real_t *out, long n) {
+  double a = RK3_A[stage - 1], b = RK3_B[stage - 1];
+  for (long i = 0; i < n; ++i)
+    out[i] = (stage == 1) ? wp[i] + dt * L[i] : a * wn[i] + b * (wp[i] + dt * L[i]);
+}
+
+static long state_size(const ctx *X) { return (long)X->nvar * X->N * X->ncell; }
+
+/* ------------------------------------------------------------------------ */
+/* Exported functions                                                         */
+/* ------------------------------------------------------------------------ */
+
+#ifndef ORC_CS
+
+int orc_sizes(const orc_config *c, long *out /* N, Q, Qf, nvar, ncell, m, nS */) {
+  ctx *X = malloc(sizeof(ctx));
+  if (!X) return ORC_ENOMEM;
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) {
+    out[0] = X->N; out[1] = X->Q; out[2] = X->Qf; out[3] = X->nvar; out[4] = X->ncell;
+    out[5] = X->m; out[6] = X->nS;
+  }
+  free(X);
+  return st;
+}
+
+int orc_gauss(int n, double *x, double *w) { if (n < 1 || n > 16) return ORC_EINVAL; gauss_rule(n, x, w); return ORC_OK; }
+int orc_gll(int m, double *x, double *w) { if (m < 2 || m > 16) return ORC_EINVAL; gll_rule(m, x, w); return ORC_OK; }
+void orc_legendre(int n, double x, double *P, double *dP) { legendre(n, x, P, dP); }
+
+/* Basis exponents e[N][3] in mode order. */
+int orc_exponents(const orc_config *c, int *e) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) for (int l = 0; l < X->N; ++l) for (int a = 0; a < 3; ++a) e[3 * l + a] = X->e[l][a];
+  free(X);
+  return st;
+}
+
+/* Basis values phi_l at arbitrary reference points xi[npts][3]: out[npts][N]. */
+int orc_basis_at(const orc_config *c, long npts, const double *xi, double *out) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK)
+    for (long p = 0; p < npts; ++p)
+      for (int l = 0; l < X->N; ++l) out[p * X->N + l] = phi_at(X, l, xi + 3 * p);
+  free(X);
+  return st;
+}
+
+/* Volume quadrature: nodes xi[Q][3], weights w[Q]. */
+int orc_volume_rule(const orc_config *c, double *xi, double *wq) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK)
+    for (int q = 0; q < X->Q; ++q) {
+      int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+      for (int a = 0; a < 3; ++a) xi[3 * q + a] = (a < X->d) ? X->gx[iq[a]] : 0.0;
+      wq[q] = X->wV[q];
+    }
+  free(X);
+  return st;
+}
+
+/* Physical coordinates of the projection nodes of every cell: x[ncell][Q][3]. */
+int orc_node_coords(const orc_config *c, double *x) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK)
+    for (long cell = 0; cell < X->ncell; ++cell) {
+      long i[3] = {cell % X->nx, (cell / X->nx) % X->ny, cell / (X->nx * X->ny)};
+      for (int q = 0; q < X->Q; ++q) {
+        int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+        for (int a = 0; a < 3; ++a) {
+          double v = 0.0;
+          if (a < X->d) v = c->x0[a] + (i[a] + 0.5) * X->dx + 0.5 * X->dx * X->gx[iq[a]];
+          x[(cell * X->Q + q) * 3 + a] = v;
+        }
+      }
+    }
+  free(X);
+  return st;
+}
+
+/* L2 projection of initial conditions (Sec. 2.3):
+ * w_j = 2^-d sum_q u(xi_q) phi_j(xi_q) w_q, with u the conserved state built
+ * from primitives prim[ncell][Q][5] = (rho, vx, vy, vz, p) at the nodes. */
+int orc_project(const orc_config *c, const double *prim, double *w) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  double scale = 1.0 / (double)(1 << X->d);
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    double acc[MAXV][MAXN];
+    memset(acc, 0, sizeof(acc));
+    for (int q = 0; q < X->Q; ++q) {
+      const double *pr = prim + (cell * X->Q + q) * 5;
+      double U[MAXV], ke = 0.0;
+      U[0] = pr[0];
+      for (int b = 0; b < X->d; ++b) { U[1 + b] = pr[0] * pr[1 + b]; ke += pr[1 + b] * pr[1 + b]; }
+      U[X->d + 1] = pr[4] / (c->gamma - 1.0) + 0.5 * pr[0] * ke;
+      for (int v = 0; v < X->nvar; ++v)
+        for (int j = 0; j < X->N; ++j) acc[v][j] += U[v] * X->phiV[q][j] * X->wV[q];
+    }
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) w[((long)v * X->N + j) * X->ncell + cell] = scale * acc[v][j];
+  }
+  free(X);
+  return ORC_OK;
+}
+
+/* Conserved state at reference points xi[npts][3] of every cell:
+ * out[ncell][npts][nvar]. */
+int orc_eval_points(const orc_config *c, const double *w, long npts, const double *xi, double *out) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  double *ph = malloc(sizeof(double) * npts * X->N);
+  for (long p = 0; p < npts; ++p)
+    for (int l = 0; l < X->N; ++l) ph[p * X->N + l] = phi_at(X, l, xi + 3 * p);
+  for (long cell = 0; cell < X->ncell; ++cell)
+    for (long p = 0; p < npts; ++p)
+      for (int v = 0; v < X->nvar; ++v) {
+        double s = 0.0;
+        for (int l = 0; l < X->N; ++l) s += W(v, l, cell) * ph[p * X->N + l];
+        out[(cell * npts + p) * X->nvar + v] = s;
+      }
+  free(ph); free(X);
+  return ORC_OK;
+}
+
+/* Numerical flux at one point (for unit tests of the Riemann solver). */
+int orc_hllc(const orc_config *c, const double *UL, const double *UR, int axis, double *F) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) hllc(X, UL, UR, axis, F);
+  free(X);
+  return st;
+}
+
+int orc_euler_flux(const orc_config *c, const double *U, int axis, double *F) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) euler_flux(X, U, axis, F);
+  free(X);
+  return st;
+}
+
+/* L = dw/dt for the whole grid. */
+int orc_rhs(const orc_config *c, const double *w, double *L) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) rhs_all(X, w, L);
+  free(X);
+  return st;
+}
+
+/* L for a list of cells only: out[nvar][N][ncells]. */
+int orc_rhs_cells(const orc_config *c, const double *w, long ncells, const long *cells, double *out) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  for (long i = 0; i < ncells; ++i) {
+    if (cells[i] < 0 || cells[i] >= X->ncell) { free(X); return ORC_EINVAL; }
+    double Lc[MAXV][MAXN];
+    rhs_cell(X, w, cells[i], Lc);
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) out[((long)v * X->N + j) * ncells + i] = Lc[v][j];
+  }
+  free(X);
+  return ORC_OK;
+}
+
+/* Volume and surface terms separately for one cell (unit tests). */
+int orc_terms_cell(const orc_config *c, const double *w, long cell, double *V, double *S) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) {
+    double Vc[MAXV][MAXN], Sc[MAXV][MAXN];
+    volume_term(X, w, cell, Vc);
+    surface_term(X, w, cell, Sc);
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) { V[v * X->N + j] = Vc[v][j]; S[v * X->N + j] = Sc[v][j]; }
+  }
+  free(X);
+  return st;
+}
+
+/* Global time step (eq. time_step; eq. time_step_pos when the positivity
+ * limiter is on): min over cells of CFL f_k / sum_a (|v_a| + c)/dx, from the
+ * cell means. */
+int orc_max_dt(const orc_config *c, const double *w, double *dt_out) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  double fk = 1.0 / (2.0 * X->k + 1.0);
+  if (c->positivity && X->lw[0] / 2.0 < fk) fk = X->lw[0] / 2.0;
+  double dt = INFINITY;
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    double U[MAXV];
+    for (int v = 0; v < X->nvar; ++v) U[v] = W(v, 0, cell);
+    double p = pressure(X, U);
+    double cs = sqrt(c->gamma * p / U[0]);
+    double rate = 0.0;
+    for (int a = 0; a < X->d; ++a) rate += (fabs(U[1 + a] / U[0]) + cs) / X->dx;
+    double dtc = c->cfl * fk / rate;
+    if (dtc < dt) dt = dtc;
+  }
+  *dt_out = dt;
+  free(X);
+  return ORC_OK;
+}
+
+/* Convex-combination step of SSP-RK3 alone (for the time-integrator pins). */
+void orc_rk3_combine(int stage, double dt, const double *wn, const double *wp, const double *L,
+                     double *out, long n) {
+  rk3_combine(stage, dt, wn, wp, L, out, n);
+}
+
+/* One SSP-RK3 stage: w_out = a w_n + b (w_prev + dt L(w_prev)). */
+int orc_rk3_stage(const orc_config *c, int stage, double dt, const double *wn, const double *wp,
+                  double *out) {
+  if (stage < 1 || stage > 3) return ORC_EINVAL;
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  long n = state_size(X);
+  double *L = malloc(sizeof(double) * n);
+  rhs_all(X, wp, L);
+  rk3_combine(stage, dt, wn, wp, L, out, n);
+  free(L); free(X);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Limiters (Sec. 3)                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* minmod of Sec. 3.1 and its TVB-bounded form of Sec. 3.3: a is returned
+ * unchanged when |a| <= M dx^2 = Mtilde dx. */
+static double minmod3(double a, double b, double c) {
+  if (a > 0 && b > 0 && c > 0) return fmin(a, fmin(b, c));
+  if (a < 0 && b < 0 && c < 0) return -fmin(-a, fmin(-b, -c));
+  return 0.0;
+}
+
+static double minmod_b(double a, double b, double c, double bound) {
+  if (fabs(a) <= bound) return a;
+  return minmod3(a, b, c);
+}
+
+/* Component-wise limiter (eq. comp_limiter, eq. comp_limiter_applied): for
+ * every conserved component i the slopes sqrt(3) w_{1+a,i} are limited
+ * against beta times the differences of the neighbouring means; if any slope
+ * changes, the component keeps only its mean and the limited slopes.
+ * `nbm` gives the neighbour means: nbm[(2a+s)*nvar*ncell + i*ncell + cell],
+ * s = 0 the low (west/south/bottom) neighbour, s = 1 the high one. */
+static void slope_limit(const ctx *X, double *w, const double *nbm, const double *dxc) {
+  long nc = X->ncell;
+  const double r3 = sqrt(3.0);
+  for (long cell = 0; cell < nc; ++cell) {
+    double bound = X->c.mtilde * dxc[cell];
+    for (int i = 0; i < X->nvar; ++i) {
+      double mean = W(i, 0, cell);
+      double mt[3];
+      int limited = 0;
+      for (int a = 0; a < X->d; ++a) {
+        double mW = nbm[((long)(2 * a + 0) * X->nvar + i) * nc + cell];
+        double mE = nbm[((long)(2 * a + 1) * X->nvar + i) * nc + cell];
+        double A = r3 * W(i, 1 + a, cell);
+        double m = minmod_b(A, X->c.beta * (mean - mW), X->c.beta * (mE - mean), bound);
+        mt[a] = m;
+        if (m != A) limited = 1;
+      }
+      if (limited) {
+        for (int a = 0; a < X->d; ++a) W(i, 1 + a, cell) = mt[a] / r3;
+        for (int l = X->d + 1; l < X->N; ++l) W(i, l, cell) = 0.0;
+      }
+    }
+  }
+}
+
+/* Root tau in [0,1] of p(ubar + tau (u - ubar)) = eps (eq. p_positivity, read
+ * with the high-order part u - ubar scaled): (E - eps/(g-1)) rho - |m|^2/2 is
+ * quadratic in tau.  Cancellation-free quadratic formula, then two Newton
+ * steps; bisection if the discriminant comes out negative. */
+static double tau_root(const ctx *X, const double *Ub, const double *Uq) {
+  int d = X->d;
+  double epsp = X->c.eps / (X->c.gamma - 1.0);
+  double dr = Uq[0] - Ub[0], dE = Uq[d + 1] - Ub[d + 1];
+  double dm2 = 0.0, mdm = 0.0, mb2 = 0.0;
+  for (int b = 0; b < d; ++b) {
+    double dm = Uq[1 + b] - Ub[1 + b];
+    dm2 += dm * dm; mdm += Ub[1 + b] * dm; mb2 += Ub[1 + b] * Ub[1 + b];
+  }
+  double A = dE * dr - 0.5 * dm2;
+  double B = dE * Ub[0] + (Ub[d + 1] - epsp) * dr - mdm;
+  double C = (Ub[d + 1] - epsp) * Ub[0] - 0.5 * mb2;
+  double t;
+  double disc = B * B - 4.0 * A * C;
+  if (A == 0.0) {
+    t = -C / B;
+  } else if (disc >= 0.0) {
+    double qq = -0.5 * (B + copysign(sqrt(disc), B));
+    double r1 = qq / A, r2 = (qq != 0.0) ? C / qq : r1;
+    int ok1 = r1 >= 0.0 && r1 <= 1.0, ok2 = r2 >= 0.0 && r2 <= 1.0;
+    t = (ok1 && ok2) ? fmin(r1, r2) : ok1 ? r1 : ok2 ? r2 : 0.0;
+  } else {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+      double mid = 0.5 * (lo + hi);
+      if ((A * mid + B) * mid + C > 0.0) lo = mid; else hi = mid;
+    }
+    t = lo;
+  }
+  for (int it = 0; it < 2; ++it) {
+    double gval = (A * t + B) * t + C, gd = 2.0 * A * t + B;
+    if (gd != 0.0) t -= gval / gd;
+  }
+  if (t < 0.0) t = 0.0;
+  if (t > 1.0) t = 1.0;
+  return t;
+}
+
+/* Positivity limiter (Sec. 3.4) on every cell; extra check points of
+ * individual cells are passed as (xcnt[cell], xphi) (the coarse side of
+ * hanging faces, Sec. 4.4), nx_pts per cell with basis values xphi[cell][..][N].
+ * Returns the number of cells whose mean density or mean pressure is <= eps. */
+static long positivity_limit(const ctx *X, double *w, const int *xcnt, const double *xphi, int xmax) {
+  long bad = 0;
+  int d = X->d, nv = X->nvar;
+  double eps = X->c.eps;
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    double Ub[MAXV];
+    for (int v = 0; v < nv; ++v) Ub[v] = W(v, 0, cell);
+    double pb = pressure(X, Ub);
+    if (!(Ub[0] > eps) || !(pb > eps)) { ++bad; continue; }
+    int np = X->nS + (xcnt ? xcnt[cell] : 0);
+    /* density */
+    double rmin = INFINITY;
+    for (int s = 0; s < np; ++s) {
+      const double *ph = (s < X->nS) ? X->phiS[s] : xphi + ((long)cell * xmax + (s - X->nS)) * X->N;
+      double r = 0.0;
+      for (int l = 0; l < X->N; ++l) r += W(0, l, cell) * ph[l];
+      if (r < rmin) rmin = r;
+    }
+    double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
+    for (int l = 1; l < X->N; ++l) W(0, l, cell) *= th1;
+    /* pressure */
+    double th2 = 1.0;
+    for (int s = 0; s < np; ++s) {
+      const double *ph = (s < X->nS) ? X->phiS[s] : xphi + ((long)cell * xmax + (s - X->nS)) * X->N;
+      double Uq[MAXV];
+      for (int v = 0; v < nv; ++v) {
+        Uq[v] = 0.0;
+        for (int l = 0; l < X->N; ++l) Uq[v] += W(v, l, cell) * ph[l];
+      }
+      double ke = 0.0;
+      for (int b = 0; b < d; ++b) ke += Uq[1 + b] * Uq[1 + b] / Uq[0];
+      double pq = (X->c.gamma - 1.0) * (Uq[d + 1] - 0.5 * ke);
+      if (pq < eps) {
+        double t = tau_root(X, Ub, Uq);
+        if (t < th2) th2 = t;
+      }
+    }
+    for (int v = 0; v < nv; ++v)
+      for (int l = 1; l < X->N; ++l) W(v, l, cell) *= th2;
+  }
+  return bad;
+}
+
+/* Neighbour means on the uniform grid (periodic or transmissive). */
+static void uniform_neighbour_means(const ctx *X, const double *w, double *nbm) {
+  long nc = X->ncell;
+  for (int a = 0; a < X->d; ++a)
+    for (int s = 0; s < 2; ++s)
+      for (long cell = 0; cell < nc; ++cell) {
+        long nb = neighbour(X, cell, a, s ? +1 : -1);
+        if (nb < 0) nb = cell;
+        for (int i = 0; i < X->nvar; ++i)
+          nbm[((long)(2 * a + s) * X->nvar + i) * nc + cell] = W(i, 0, nb);
+      }
+}
+
+/* Slope limiter, then positivity limiter, in place (main loop, Sec. 4.5).
+ * Returns ORC_ENEGATIVE if some cell mean is not positive. */
+int orc_limit(const orc_config *c, double *w) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  long bad = 0;
+  if (c->limiter) {
+    double *nbm = malloc(sizeof(double) * 2 * X->d * X->nvar * X->ncell);
+    double *dxc = malloc(sizeof(double) * X->ncell);
+    for (long i = 0; i < X->ncell; ++i) dxc[i] = X->dx;
+    uniform_neighbour_means(X, w, nbm);
+    slope_limit(X, w, nbm, dxc);
+    free(nbm); free(dxc);
+  }
+  if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0);
+  free(X);
+  return bad ? ORC_ENEGATIVE : ORC_OK;
+}
+
+/* Positivity check points S in reference coordinates: xi[nS][3]. */
+int orc_positivity_points(const orc_config *c, double *xi) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK) {
+    int s = 0;
+    for (int a = 0; a < X->d; ++a) {
+      int t[2]; tangential(X->d, a, t);
+      for (int r = 0; r < X->m; ++r)
+        for (int q = 0; q < X->Qf; ++q) {
+          int ir[2] = {q % X->n1, q / X->n1};
+          double p[3] = {0, 0, 0};
+          p[a] = X->lx[r];
+          for (int j = 0; j < X->d - 1; ++j) p[t[j]] = X->gx[ir[j]];
+          for (int b = 0; b < 3; ++b) xi[3 * s + b] = p[b];
+          ++s;
+        }
+    }
+  }
+  free(X);
+  return st;
+}
+
+#else /* ORC_CS: complex-step directional derivatives */
+
+/* Directional derivative of the RHS: dL = Im L(w + i h v) / h (and L = Re). */
+int orc_cs_rhs(const orc_config *c, const double *w, const double *v, double h, double *L, double *dL) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  long n = state_size(X);
+  real_t *wc = malloc(sizeof(real_t) * n), *Lc = malloc(sizeof(real_t) * n);
+  for (long i = 0; i < n; ++i) wc[i] = w[i] + I * h * v[i];
+  rhs_all(X, wc, Lc);
+  for (long i = 0; i < n; ++i) { L[i] = creal(Lc[i]); dL[i] = cimag(Lc[i]) / h; }
+  free(wc); free(Lc); free(X);
+  return ORC_OK;
+}
+
+/* Directional derivative of nsteps SSP-RK3 steps at fixed dt, unlimited. */
+int orc_cs_traj(const orc_config *c, const double *w0, const double *v, double h, int nsteps, double dt,
+                double *wT, double *dwT) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  long n = state_size(X);
+  real_t *u0 = malloc(sizeof(real_t) * n), *u1 = malloc(sizeof(real_t) * n),
+         *u2 = malloc(sizeof(real_t) * n), *L = malloc(sizeof(real_t) * n);
+  for (long i = 0; i < n; ++i) u0[i] = w0[i] + I * h * v[i];
+  for (int s = 0; s < nsteps; ++s) {
+    rhs_all(X, u0, L); rk3_combine(1, dt, u0, u0, L, u1, n);
+    rhs_all(X, u1, L); rk3_combine(2, dt, u0, u1, L, u2, n);
+    rhs_all(X, u2, L); rk3_combine(3, dt, u0, u2, L, u1, n);
+    real_t *t = u0; u0 = u1; u1 = t;
+  }
+  for (long i = 0; i < n; ++i) { wT[i] = creal(u0[i]); dwT[i] = cimag(u0[i]) / h; }
+  free(u0); free(u1); free(u2); free(L); free(X);
+  return ORC_OK;
+}
+
+#endif

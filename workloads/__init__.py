@@ -1,0 +1,179 @@
+"""Seeded synthetic workloads shared by the oracle, the tests and the benchmark.
+
+This module holds the *problem definitions* only: mesh sizes, run lengths, the
+initial primitive fields (density, velocity, pressure) of the paper's test
+problems, and a counter-based random generator for the seeded noise.  It holds
+none of the discontinuous Galerkin arithmetic (no basis, quadrature, projection,
+flux or update): each consumer evaluates these fields at quadrature points it
+computes itself and projects them with its own code.
+
+Random numbers come from SplitMix64 (Steele, Lea & Flood 2014) used as a
+counter-based generator: draw i of stream `seed` is mix(seed + (i+1)*GOLDEN),
+so any subset of draws can be generated in any order.  U(-1,1) variates are
+2*(z >> 11)*2^-53 - 1.
+
+Problem sources (the paper's validation section):
+  * isentropic vortex: primitive fields of the stationary vortex with
+    strength beta = 5 plus a uniform boost (Validation, isentropic vortex);
+  * shock tube: Sod states (1, 0, 1) | (0.125, 0, 0.1) (Validation, shock tube);
+  * shear layer: the KH layer profile rho in {1, 2}, v_x = -/+0.5, p = 2.5
+    (Validation, KH instability), here in 3D with cell-constant seeded
+    velocity noise in place of the single-mode perturbation;
+  * blast: a Sod-type spherical over-pressure region;
+  * density wave: rho = 1 + 0.2 sin(2 pi (x + y)) advected at constant velocity
+    and pressure.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+_GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+def splitmix64(seed: int, counter) -> np.ndarray:
+    """Draw number `counter` (array of non-negative ints) of SplitMix64 stream `seed`."""
+    c = np.asarray(counter, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (c + np.uint64(1)) * _GOLDEN
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+        z = z ^ (z >> np.uint64(31))
+    return z
+
+
+def uniform_pm1(seed: int, counter) -> np.ndarray:
+    """U(-1, 1) variates from draw `counter` of stream `seed` (53-bit mantissa)."""
+    z = splitmix64(seed, counter)
+    return 2.0 * (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) - 1.0
+
+
+# ---------------------------------------------------------------------------
+# Workload table.  Sizes follow the five benchmark configurations plus small
+# variants used by tests.  `n` is the base grid, `x0`/`length` the box.
+# ---------------------------------------------------------------------------
+
+WORKLOADS: dict[str, dict] = {
+    # 2D, k=1, 32^2, smooth density wave, CFL 0.3, 20 steps, no limiter.
+    "density_wave": dict(dim=2, k=1, n=(32, 32, 1), x0=(0.0, 0.0, 0.0),
+                         length=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.3, steps=20,
+                         limiter=0, positivity=0, ic="density_wave",
+                         velocity=(1.0, 1.0, 0.0)),
+    # 2D, k=2, 256^2, boosted isentropic vortex on [-5,5]^2 with seeded
+    # +-1e-3 density noise at every projection node; CFL 0.2, 200 steps.
+    "vortex": dict(dim=2, k=2, n=(256, 256, 1), x0=(-5.0, -5.0, 0.0),
+                   length=(10.0, 10.0, 1.0), gamma=1.4, cfl=0.2, steps=200,
+                   limiter=0, positivity=0, ic="vortex", noise=1e-3, seed=1506),
+    # 3D, k=2, 128^3 shear layer, minmod (TVB) + positivity, 10 steps.
+    "kh3d": dict(dim=3, k=2, n=(128, 128, 128), x0=(0.0, 0.0, 0.0),
+                 length=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.2, steps=10,
+                 limiter=1, positivity=1, ic="kh3d", noise=1e-2, seed=6140),
+    # 2D, k=3, 512^2 boosted vortex (no noise), fixed dt, 400 steps, adjoint.
+    "vortex_adjoint": dict(dim=2, k=3, n=(512, 512, 1), x0=(-5.0, -5.0, 0.0),
+                           length=(10.0, 10.0, 1.0), gamma=1.4, cfl=0.2,
+                           steps=400, limiter=0, positivity=0, ic="vortex",
+                           checkpoint=20),
+    # 3D, k=3 Sod-type blast on a 64^3 base grid whose central base cells
+    # [16,48)^3 are refined 2:1; minmod + positivity, 10 steps.
+    "blast_amr": dict(dim=3, k=3, n=(64, 64, 64), x0=(0.0, 0.0, 0.0),
+                      length=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.2, steps=10,
+                      limiter=1, positivity=1, ic="blast",
+                      refine_lo=(16, 16, 16), refine_hi=(48, 48, 48)),
+    # 2D Sod shock tube on [0,1]^2 (transmissive in x, periodic in y).
+    "sod": dict(dim=2, k=2, n=(64, 4, 1), x0=(0.0, 0.0, 0.0),
+                length=(1.0, 1.0 / 16.0, 1.0), gamma=1.4, cfl=0.2,
+                limiter=1, positivity=1, ic="sod", bc=(1, 0, 0), t_end=0.228),
+}
+
+VORTEX_BETA = 5.0
+VORTEX_BOOST = (1.0, 1.0)
+VORTEX_CENTRE = (0.0, 0.0)
+
+
+def workload(name: str, **overrides) -> dict:
+    """A copy of a named workload with fields overridden (e.g. n=(16,16,1))."""
+    w = dict(WORKLOADS[name])
+    w.update(overrides)
+    w.setdefault("bc", (0, 0, 0))
+    w.setdefault("beta", 1.0)
+    w.setdefault("mtilde", 0.5)
+    w.setdefault("eps", 1e-10)
+    w.setdefault("refine_lo", (0, 0, 0))
+    w.setdefault("refine_hi", (0, 0, 0))
+    w.setdefault("flux", 0)
+    w["name"] = name
+    return w
+
+
+def _wrap(d: np.ndarray, length: float) -> np.ndarray:
+    """Minimum-image offset in a periodic box of the given length."""
+    return d - length * np.round(d / length)
+
+
+def primitives(wl: dict, x, y, z, cell=None, node=None, t: float = 0.0):
+    """Primitive fields (rho, vx, vy, vz, p) of workload `wl` at points (x, y, z).
+
+    `cell` and `node` (integer arrays broadcastable with x) index the seeded
+    noise counters; `nq` in the workload (nodes per cell) must be set by the
+    caller for node-level noise.  `t` > 0 gives the exact solution of the
+    translating problems (density wave, boosted vortex) at time t.
+    """
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    g = wl["gamma"]
+    ic = wl["ic"]
+    zeros = np.zeros_like(x)
+    if ic == "density_wave":
+        u, v, w = wl.get("velocity", (1.0, 1.0, 0.0))
+        rho = 1.0 + 0.2 * np.sin(2.0 * math.pi * (x + y - (u + v) * t))
+        return rho, zeros + u, zeros + v, zeros + w, zeros + 1.0
+    if ic == "vortex":
+        bx, by = VORTEX_BOOST
+        dx = _wrap(x - VORTEX_CENTRE[0] - bx * t, wl["length"][0])
+        dy = _wrap(y - VORTEX_CENTRE[1] - by * t, wl["length"][1])
+        r2 = dx * dx + dy * dy
+        b = VORTEX_BETA
+        rho = (1.0 - (g - 1.0) * b * b / (8.0 * g * math.pi ** 2)
+               * np.exp(1.0 - r2)) ** (1.0 / (g - 1.0))
+        p = rho ** g
+        e = b / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+        vx = bx - dy * e
+        vy = by + dx * e
+        if wl.get("noise") and t == 0.0:
+            if cell is None or node is None:
+                raise ValueError("vortex noise needs cell and node indices")
+            ctr = np.asarray(cell, dtype=np.int64) * int(wl["nq"]) + np.asarray(node, dtype=np.int64)
+            rho = rho + wl["noise"] * uniform_pm1(wl["seed"], ctr)
+        return rho, vx, vy, zeros, p
+    if ic == "kh3d":
+        inner = (y > 0.25) & (y < 0.75)
+        rho = np.where(inner, 2.0, 1.0)
+        vx = np.where(inner, 0.5, -0.5)
+        vy = zeros.copy()
+        vz = zeros.copy()
+        if wl.get("noise"):
+            if cell is None:
+                raise ValueError("kh3d noise needs cell indices")
+            c3 = np.asarray(cell, dtype=np.int64) * 3
+            vx = vx + wl["noise"] * uniform_pm1(wl["seed"], c3 + 0)
+            vy = vy + wl["noise"] * uniform_pm1(wl["seed"], c3 + 1)
+            vz = vz + wl["noise"] * uniform_pm1(wl["seed"], c3 + 2)
+        return rho, vx, vy, vz, zeros + 2.5
+    if ic == "blast":
+        r2 = (x - 0.5) ** 2 + (y - 0.5) ** 2 + (z - 0.5) ** 2
+        inside = r2 < 0.2 ** 2
+        return (np.where(inside, 1.0, 0.125), zeros, zeros, zeros,
+                np.where(inside, 1.0, 0.1))
+    if ic == "sod":
+        left = x < 0.5
+        return (np.where(left, 1.0, 0.125), zeros, zeros, zeros,
+                np.where(left, 1.0, 0.1))
+    if ic == "uniform":
+        rho0, vel, p0 = wl["state"]
+        return (zeros + rho0, zeros + vel[0], zeros + vel[1], zeros + vel[2],
+                zeros + p0)
+    raise ValueError(f"unknown initial condition {ic!r}")
