@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the DG right-hand side + SSP-RK3 hot path on one MI355X.
+
+Workload: 2D isentropic vortex (strength 5, gamma 1.4, boost (1,1), periodic
+[-5,5]^2), 256^2 cells, degree k = 2 (N = 6 modes, 4 variables), FP64,
+seeded +-1e-3 density noise, CFL 0.2, no limiter.  One *step* is the whole
+hot path for one SSP-RK3 step: the CFL time step reduction and the three
+fused RHS + stage kernels.  The metric is DOF-updates per second per RK
+stage: cells * N * 3 / step time.
+
+The initial state is built by the library itself (seeded primitives from
+``workloads`` sampled at the library's Gauss nodes, L2-projected by
+``dg_project``); it is resident in HBM before the timed region starts.
+
+Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on a
+single GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
+METRIC = "DOF-updates/s per RK stage"
+KERNEL_SRC = os.path.join(ROOT, "paper_1506_06140_amd", "csrc", "dg_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rhs_stage_vortex256_k2_traffic.txt")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the stage kernel from the committed rocprofv3
+    counter summary, or None if absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not b or m.group(1) != kernel_hash():
+        return None
+    return float(b.group(1))
+
+
+def build_state(s, wl):
+    import torch
+    x = s.node_coords()  # [3][Q][cells]
+    cell = np.broadcast_to(np.arange(s.ncell)[None, :], (s.Q, s.ncell))
+    node = np.broadcast_to(np.arange(s.Q)[:, None], (s.Q, s.ncell))
+    wlq = dict(wl)
+    wlq["nq"] = s.Q
+    prim = np.stack(workloads.primitives(wlq, x[0], x[1], x[2], cell=cell, node=node), axis=0)
+    prim_d = torch.from_numpy(np.ascontiguousarray(prim)).cuda()
+    w = s.project(prim_d)
+    torch.cuda.synchronize()
+    return w
+
+
+def cpu_baseline(wl, budget_s: float = 12.0):
+    """The FP64 oracle, single-threaded, on a bounded number of RK stages of
+    the same workload."""
+    import oracle
+    o = oracle.Oracle(wl)
+    w0 = o.initial_state()
+    dt = o.max_dt(w0)
+    t0 = time.perf_counter()
+    stages = 0
+    u = w0
+    while True:
+        stage = stages % 3 + 1
+        u = o.rk3_stage(stage, dt, w0, u if stage > 1 else w0)
+        stages += 1
+        if time.perf_counter() - t0 > budget_s and stages >= 3:
+            break
+    el = time.perf_counter() - t0
+    dof = o.ncell * o.N
+    return {"value": dof * stages / el, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "sample": f"{stages} SSP-RK3 stages (RHS + update, no limiter) of the full 256^2 k=2 vortex "
+                      f"state, single-threaded C oracle, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import paper_1506_06140_amd as dg
+
+    wl = workloads.workload("vortex")
+    s = dg.Solver(wl)
+    A = build_state(s, wl)
+    B = s.empty()
+    u1, u2, dtbuf = s.empty(), s.empty(), s.scalar()
+    stream = torch.cuda.current_stream()
+
+    def two_steps():
+        # ping-pong: A -> B -> A, stage buffers u1, u2, device time step dtbuf
+        s.step(A, [u1, u2, B, dtbuf])
+        s.step(B, [u1, u2, A, dtbuf])
+
+    steps = args.steps + (args.steps % 2)
+    for _ in range((args.warmup + 1) // 2):
+        two_steps()
+    torch.cuda.synchronize()
+    if s.status() != 0:
+        raise RuntimeError("device error flag set during warm-up")
+
+    graph = None
+    if args.graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            two_steps()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            two_steps()
+        torch.cuda.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    if graph is not None:
+        for _ in range(steps // 2):
+            graph.replay()
+    else:
+        for _ in range(steps // 2):
+            two_steps()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = s.status()
+    if st != 0:
+        raise RuntimeError(f"device error flag {st} after the timed steps")
+    w = A
+    bufs = [u1, u2, B, dtbuf]
+    args.steps = steps
+
+    dof = s.ncell * s.N
+    ms_step = el / args.steps * 1e3
+    value = dof * 3 * args.steps / el
+
+    # average duration of the dominant kernel (fused RHS + stage), HIP events
+    # on the stream it is launched on
+    reps = 60
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    dt = s.max_dt(w, bufs[3])
+    for i in range(reps):
+        stage = i % 3 + 1
+        evs[i][0].record(stream)
+        s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], bufs[1] if stage == 1 else bufs[2])
+        evs[i][1].record(stream)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    state_bytes = s.nvar * s.N * s.ncell * 8
+    alg_bytes = 8.0 / 3.0 * state_bytes  # read w_prev (+ w_n in stages 2,3), write w_out
+    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic()
+
+    rec = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "isentropic vortex 2D, 256x256 cells, k=2 (N=6), FP64, SSP-RK3, CFL 0.2, "
+                               "no limiter, seeded 1e-3 density noise",
+                   "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(graph)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_rhs_stage<2,2>", "kernel_ms": k_ms,
+                     "alg_bytes_per_launch": alg_bytes},
+    }
+    if not args.no_cpu:
+        rec["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

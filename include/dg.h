@@ -1,0 +1,160 @@
+/*
+ * dg.h -- C ABI of the MI355X modal discontinuous Galerkin library (libdg.so).
+ *
+ * The library evaluates the right-hand side of the semi-discrete modal DG
+ * scheme for the compressible Euler equations on Cartesian cells and advances
+ * it with the third-order SSP Runge-Kutta method, following Schaal et al.
+ * (2015), "Astrophysical hydrodynamics with a high order discontinuous
+ * Galerkin scheme and adaptive mesh refinement":
+ *   - state and basis ............ Sec. 2.2 (eqs. solution_representation,
+ *                                  weights, set_basis_functions)
+ *   - right-hand side ............ Sec. 2.4 (eqs. dg_projected, dg_term2,
+ *                                  dg_term3, spatial_discretisation)
+ *   - time step .................. Sec. 2.5 (eq. time_step), Sec. 3.4
+ *                                  (eq. time_step_pos)
+ *   - SSP-RK3 .................... App. D (table RK_3)
+ *   - limiters ................... Sec. 3.1, 3.3, 3.4
+ * and a hand-written discrete adjoint of the right-hand side and of the
+ * SSP-RK3 stages (not part of the paper).
+ *
+ * Conventions shared by every call:
+ *   - A *state* is a device array of doubles with layout
+ *     [nvar][N][nz][ny][nx] (x fastest; nz = 1 in 2D), nvar = dim + 2
+ *     conserved variables (rho, m_x, m_y[, m_z], E) and N = N(k) modal
+ *     weights per variable.  Modes are ordered by total degree, then by
+ *     x-exponent descending, then by y-exponent descending, so mode 0 is the
+ *     cell mean and modes 1..dim are the x, y(, z) slopes.  The scaled
+ *     Legendre basis is orthonormal: (1/|K|) int_K phi_i phi_j = delta_ij.
+ *   - The caller allocates and owns every state, dt and output buffer; the
+ *     library never frees them.  The context owns its tables and scratch.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Calls enqueue work
+ *     and return without synchronising; the time step stays on the device.
+ *   - Outputs must not alias inputs unless a call says so.
+ *   - One context may be used from one stream at a time.
+ *   - Every call returns DG_OK (0) or a negative DG_E* code and never
+ *     throws.  Conditions detected on the device (a non-positive mean
+ *     density or pressure, a NaN) set a sticky flag read by dg_status().
+ */
+#ifndef DG_MI355X_H
+#define DG_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,       /* invalid argument (bad config, null pointer, stage) */
+  DG_EUNSUPPORTED = -2, /* dim, degree or option outside the built set       */
+  DG_ENOMEM = -3,       /* device or host allocation failed                  */
+  DG_EHIP = -4,         /* a HIP runtime call failed                         */
+  DG_ENEGATIVE = -5,    /* a cell mean has rho <= eps or p <= eps             */
+  DG_ENAN = -6          /* a NaN appeared in a right-hand side                */
+};
+
+enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
+enum { DG_HLLC_BATTEN = 0, DG_HLLC_DAVIS = 1 };
+enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16_VOL = 2 };
+enum { DG_LIM_NONE = 0, DG_LIM_MINMOD = 1 };
+
+typedef struct dg_ctx dg_ctx;
+
+/* Run description (all fields read by dg_init only). */
+typedef struct {
+  int dim;            /* 2 or 3                                              */
+  int k;              /* polynomial degree, 1..3 (spatial order k+1)          */
+  int n[3];           /* cells per axis (n[2] ignored in 2D)                  */
+  double x0[3];       /* lower corner of the box                              */
+  double len[3];      /* box edge lengths; cells must be cubes (len/n equal)  */
+  double gamma;       /* adiabatic index of the ideal-gas EOS (eq. eos)       */
+  double cfl;         /* CFL number of eq. time_step                          */
+  int bc[3];          /* DG_BC_* per axis                                     */
+  int flux;           /* DG_HLLC_BATTEN (Roe-averaged speed bounds) or DAVIS  */
+  int precision;      /* DG_FP64, DG_FP32 (contractions and fluxes in FP32),
+                         DG_BF16_VOL (volume contraction BF16 on MFMA)         */
+  int slope_limiter;  /* DG_LIM_NONE or DG_LIM_MINMOD (component-wise, TVB)    */
+  double beta;        /* minmod parameter beta in [0.5, 1] (Sec. 3.1)          */
+  double m_tilde;     /* TVB bound Mtilde; slopes |a| <= Mtilde dx kept (3.3)  */
+  int positivity;     /* 1: Zhang-Shu positivity limiter (Sec. 3.4)            */
+  double eps;         /* positivity floor (the paper uses about 1e-10)         */
+  int refine_lo[3];   /* reserved for a static 2:1 refined box; set equal to  */
+  int refine_hi[3];   /* refine_lo (e.g. all zero) for a uniform grid          */
+} dg_config;
+
+/* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton
+ * iteration, App. B; GLL nodes, App. C; scaled Legendre values, App. A),
+ * copies them to the current device and allocates scratch.  Host-to-device
+ * copies happen here only.  *out receives the context. */
+int dg_init(const dg_config *cfg, dg_ctx **out);
+
+/* Number of doubles in one state array (nvar * N * cells). */
+int dg_state_size(const dg_ctx *ctx, int64_t *n_fp64);
+
+/* Sizes: out[0..5] = nvar, N, Q (volume nodes), Qf (face nodes), cells, nS
+ * (positivity check points per cell). */
+int dg_sizes(const dg_ctx *ctx, int64_t out[6]);
+
+/* Reference coordinates of the (k+1)^dim Gauss volume nodes, xi[Q][3]
+ * (x index fastest; unused axes 0), and their weights w[Q] (host memory). */
+int dg_quadrature(const dg_ctx *ctx, double *xi, double *w);
+
+/* L2 projection of initial data (Sec. 2.3): prim is a device array
+ * [5][Q][cells] of primitive values (rho, v_x, v_y, v_z, p) at the Gauss
+ * volume nodes of every cell; w receives the state. */
+int dg_project(dg_ctx *ctx, const double *prim, double *w, void *stream);
+
+/* L = dw/dt = -R_K of eq. spatial_discretisation for every cell: volume
+ * integral (eq. dg_term2) minus surface integral (eq. dg_term3) with the HLLC
+ * flux, times (2/dx) 2^-dim.  w and L are states; L must not alias w. */
+int dg_rhs(dg_ctx *ctx, const double *w, double *L, void *stream);
+
+/* Global time step of eq. time_step (eq. time_step_pos with the positivity
+ * limiter) from the cell means of w, written to dt_dev[0] on the device. */
+int dg_max_dt(dg_ctx *ctx, const double *w, double *dt_dev, void *stream);
+
+/* One SSP-RK3 stage in convex-combination form (App. D, table RK_3):
+ *   stage 1: w_out = w_prev + dt L(w_prev)              (w_n unused)
+ *   stage 2: w_out = 3/4 w_n + 1/4 (w_prev + dt L(w_prev))
+ *   stage 3: w_out = 1/3 w_n + 2/3 (w_prev + dt L(w_prev))
+ * dt is read from dt_dev[0].  w_out must not alias w_prev or w_n. */
+int dg_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *w_n,
+                const double *w_prev, double *w_out, void *stream);
+
+/* Slope limiter (component-wise minmod with TVB bound, Sec. 3.1/3.3) then
+ * positivity limiter (Sec. 3.4), in place, as configured.  Cell means are
+ * never changed.  A cell whose mean density or pressure is <= eps sets the
+ * DG_ENEGATIVE flag and is left unlimited. */
+int dg_limit(dg_ctx *ctx, double *w, void *stream);
+
+/* Discrete adjoint of dg_rhs: mu = (dL/dw)^T lam at the state w (all
+ * states).  Exact transpose of the discrete operator, including the HLLC
+ * branch taken at w.  mu must not alias w or lam. */
+int dg_adjoint_rhs(dg_ctx *ctx, const double *w, const double *lam, double *mu, void *stream);
+
+/* Transpose of one SSP-RK3 stage, applied from stage 3 down to stage 1 with
+ * u the stage input state of that stage (u0, u1, u2) and dt fixed:
+ *   stage 3: lam_out = 2/3 (lam + dt J(u)^T lam);  acc_out = 1/3 lam
+ *   stage 2: lam_out = 1/4 (lam + dt J(u)^T lam);  acc_out = acc + 3/4 lam
+ *   stage 1: lam_out = acc + lam + dt J(u)^T lam    (acc_out unused)
+ * where J = dL/dw.  After stage 1, lam_out is dJ/dw_n of the step. */
+int dg_adjoint_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *u,
+                        const double *lam, const double *acc, double *lam_out,
+                        double *acc_out, void *stream);
+
+/* Synchronises `stream`, returns the sticky device flag (DG_OK,
+ * DG_ENEGATIVE or DG_ENAN) and clears it. */
+int dg_status(dg_ctx *ctx, void *stream);
+
+/* Frees the context's device tables and scratch. */
+void dg_destroy(dg_ctx *ctx);
+
+/* Static description of an error code. */
+const char *dg_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DG_MI355X_H */

@@ -1,0 +1,251 @@
+"""MI355X modal discontinuous Galerkin hot path: Python binding of libdg.so.
+
+The binding only marshals arguments: every step of the right-hand side, the
+SSP-RK3 stage, the time step, the limiters and the adjoint runs in the HIP
+kernels of ``libdg.so`` (see ``include/dg.h``).  PyTorch provides device
+memory and streams.  There is no CPU fallback: if the library is missing or
+no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
+DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
+PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}
+
+
+class DGError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class dg_config(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("k", C.c_int), ("n", C.c_int * 3),
+        ("x0", C.c_double * 3), ("len", C.c_double * 3),
+        ("gamma", C.c_double), ("cfl", C.c_double),
+        ("bc", C.c_int * 3), ("flux", C.c_int), ("precision", C.c_int),
+        ("slope_limiter", C.c_int), ("beta", C.c_double), ("m_tilde", C.c_double),
+        ("positivity", C.c_int), ("eps", C.c_double),
+        ("refine_lo", C.c_int * 3), ("refine_hi", C.c_int * 3),
+    ]
+
+
+EXPORTS = (
+    "dg_init", "dg_state_size", "dg_sizes", "dg_quadrature", "dg_project", "dg_rhs",
+    "dg_max_dt", "dg_rk_stage", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage",
+    "dg_status", "dg_destroy", "dg_strerror",
+)
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libdg.so and declare the C signatures (no GPU needed)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1506_06140_amd.build`")
+    lib = C.CDLL(path)
+    vp, dp = C.c_void_p, C.c_void_p
+    ctxp = C.c_void_p
+    lib.dg_init.argtypes = [C.POINTER(dg_config), C.POINTER(ctxp)]
+    lib.dg_state_size.argtypes = [ctxp, C.POINTER(C.c_int64)]
+    lib.dg_sizes.argtypes = [ctxp, C.POINTER(C.c_int64)]
+    lib.dg_quadrature.argtypes = [ctxp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.dg_project.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_rhs.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_max_dt.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, vp]
+    lib.dg_limit.argtypes = [ctxp, dp, vp]
+    lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
+    lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
+    lib.dg_status.argtypes = [ctxp, vp]
+    lib.dg_destroy.argtypes = [ctxp]
+    lib.dg_destroy.restype = None
+    lib.dg_strerror.argtypes = [C.c_int]
+    lib.dg_strerror.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("dg_destroy", "dg_strerror"):
+            getattr(lib, name).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load_library().dg_strerror(code).decode()
+
+
+def _check(code: int, what: str) -> None:
+    if code != DG_OK:
+        raise DGError(code, what)
+
+
+def make_config(wl: dict, precision: str = "fp64") -> dg_config:
+    c = dg_config()
+    c.dim = wl["dim"]; c.k = wl["k"]
+    c.n[:] = list(wl["n"])
+    c.x0[:] = list(wl["x0"]); c.len[:] = list(wl["length"])
+    c.gamma = wl["gamma"]; c.cfl = wl["cfl"]
+    c.bc[:] = list(wl.get("bc", (0, 0, 0)))
+    c.flux = wl.get("flux", 0)
+    c.precision = PRECISIONS[precision]
+    c.slope_limiter = wl.get("limiter", 0)
+    c.beta = wl.get("beta", 1.0); c.m_tilde = wl.get("mtilde", 0.5)
+    c.positivity = wl.get("positivity", 0); c.eps = wl.get("eps", 1e-10)
+    c.refine_lo[:] = list(wl.get("refine_lo", (0, 0, 0)))
+    c.refine_hi[:] = list(wl.get("refine_hi", (0, 0, 0)))
+    return c
+
+
+def _ptr(t, numel: int | None = None) -> int:
+    """Device pointer of a contiguous float64 CUDA tensor of the expected size."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 CUDA tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"tensor has {t.numel()} elements, expected {numel}")
+    return t.data_ptr()
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Solver:
+    """A configured DG discretisation on the current GPU (one libdg context)."""
+
+    def __init__(self, wl: dict, precision: str = "fp64"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("libdg needs a GPU: no HIP device is visible")
+        self.lib = load_library()
+        self.wl = dict(wl)
+        self.precision = precision
+        self.cfg = make_config(wl, precision)
+        ctx = C.c_void_p()
+        torch.cuda.init()
+        _check(self.lib.dg_init(C.byref(self.cfg), C.byref(ctx)), "dg_init")
+        self.ctx = ctx
+        sz = (C.c_int64 * 6)()
+        _check(self.lib.dg_sizes(self.ctx, sz), "dg_sizes")
+        self.nvar, self.N, self.Q, self.Qf, self.ncell, self.nS = (int(x) for x in sz)
+        nz = wl["n"][2] if wl["dim"] == 3 else 1
+        self.shape = (self.nvar, self.N, nz, wl["n"][1], wl["n"][0])
+        self.dx = wl["length"][0] / wl["n"][0]
+        self.size = self.nvar * self.N * self.ncell
+
+    def _s(self, t) -> int:
+        return _ptr(t, self.size)
+
+    def __del__(self):
+        ctx = getattr(self, "ctx", None)
+        if ctx is not None and ctx.value:
+            self.lib.dg_destroy(ctx)
+            self.ctx = None
+
+    # -- buffers -----------------------------------------------------------
+    def empty(self):
+        import torch
+        return torch.empty(self.shape, dtype=torch.float64, device="cuda")
+
+    def scalar(self):
+        import torch
+        return torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    # -- set-up ------------------------------------------------------------
+    def quadrature(self):
+        xi = np.zeros((self.Q, 3)); w = np.zeros(self.Q)
+        _check(self.lib.dg_quadrature(self.ctx, xi.ctypes.data_as(C.POINTER(C.c_double)),
+                                      w.ctypes.data_as(C.POINTER(C.c_double))), "dg_quadrature")
+        return xi, w
+
+    def node_coords(self) -> np.ndarray:
+        """Physical coordinates [3][Q][cells] of the Gauss nodes (host)."""
+        xi, _ = self.quadrature()
+        nx, ny = self.wl["n"][0], self.wl["n"][1]
+        cid = np.arange(self.ncell)
+        idx = [cid % nx, (cid // nx) % ny, cid // (nx * ny)]
+        out = np.zeros((3, self.Q, self.ncell))
+        for a in range(self.wl["dim"]):
+            out[a] = self.wl["x0"][a] + (idx[a][None, :] + 0.5 + 0.5 * xi[:, a][:, None]) * self.dx
+        return out
+
+    def project(self, prim, out=None, stream=None):
+        """L2 projection of primitives prim[5][Q][cells] (device) onto the basis."""
+        out = self.empty() if out is None else out
+        _check(self.lib.dg_project(self.ctx, _ptr(prim, 5 * self.Q * self.ncell), self._s(out), _stream(stream)),
+               "dg_project")
+        return out
+
+    # -- the hot path ----------------------------------------------------------
+    def rhs(self, w, out=None, stream=None):
+        out = self.empty() if out is None else out
+        _check(self.lib.dg_rhs(self.ctx, self._s(w), self._s(out), _stream(stream)), "dg_rhs")
+        return out
+
+    def max_dt(self, w, dt=None, stream=None):
+        dt = self.scalar() if dt is None else dt
+        _check(self.lib.dg_max_dt(self.ctx, self._s(w), _ptr(dt, 1), _stream(stream)), "dg_max_dt")
+        return dt
+
+    def rk_stage(self, stage, dt, wn, wp, out=None, stream=None):
+        out = self.empty() if out is None else out
+        wn_p = self._s(wn) if wn is not None else None
+        _check(self.lib.dg_rk_stage(self.ctx, stage, _ptr(dt, 1), wn_p, self._s(wp), self._s(out), _stream(stream)),
+               "dg_rk_stage")
+        return out
+
+    def limit(self, w, stream=None):
+        _check(self.lib.dg_limit(self.ctx, self._s(w), _stream(stream)), "dg_limit")
+        return w
+
+    def adjoint_rhs(self, w, lam, out=None, stream=None):
+        out = self.empty() if out is None else out
+        _check(self.lib.dg_adjoint_rhs(self.ctx, self._s(w), self._s(lam), self._s(out), _stream(stream)),
+               "dg_adjoint_rhs")
+        return out
+
+    def adjoint_rk_stage(self, stage, dt, u, lam, acc, lam_out, acc_out, stream=None):
+        _check(self.lib.dg_adjoint_rk_stage(self.ctx, stage, _ptr(dt, 1), self._s(u), self._s(lam),
+                                            self._s(acc) if acc is not None else None, self._s(lam_out),
+                                            self._s(acc_out) if acc_out is not None else None, _stream(stream)),
+               "dg_adjoint_rk_stage")
+        return lam_out
+
+    def status(self, stream=None) -> int:
+        return self.lib.dg_status(self.ctx, _stream(stream))
+
+    @property
+    def limited(self) -> bool:
+        return bool(self.cfg.slope_limiter or self.cfg.positivity)
+
+    def step(self, w, bufs, dt=None, stream=None):
+        """One SSP-RK3 step from w into bufs[2] using bufs[0], bufs[1] as stage
+        buffers (the main loop of Sec. 4.5 without refinement).  If dt (a
+        one-element device tensor) is None the CFL step is computed first into
+        bufs[3].  Returns the new state tensor (bufs[2])."""
+        u1, u2, u3 = bufs[0], bufs[1], bufs[2]
+        if dt is None:
+            dt = self.max_dt(w, bufs[3], stream)
+        self.rk_stage(1, dt, None, w, u1, stream)
+        if self.limited:
+            self.limit(u1, stream)
+        self.rk_stage(2, dt, w, u1, u2, stream)
+        if self.limited:
+            self.limit(u2, stream)
+        self.rk_stage(3, dt, w, u2, u3, stream)
+        if self.limited:
+            self.limit(u3, stream)
+        return u3

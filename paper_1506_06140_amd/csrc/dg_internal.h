@@ -1,0 +1,64 @@
+// Internal declarations of libdg: table layout shared by the host set-up and
+// the device kernels, and the context structure behind the opaque dg_ctx.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+
+namespace dg {
+
+// Sizes of one (dim, k) discretisation.
+struct Shape {
+  int d, k;
+  int n1;   // Gauss points per axis, k + 1
+  int nv;   // conserved variables, d + 2
+  int N;    // modes per variable
+  int Q;    // volume nodes (k+1)^d
+  int QF;   // nodes per face (k+1)^(d-1)
+  int M;    // GLL points of the positivity rule, smallest m >= (k+3)/2
+  int NS;   // positivity points per cell, d * M * QF
+};
+
+Shape make_shape(int d, int k);
+
+// Offsets (in doubles) of the tables in one contiguous buffer:
+//   B  [Q][N]        phi_l at the volume nodes
+//   DW [d][Q][N]     d phi_l / d xi_a at the volume nodes, times the node weight
+//   TF [d][2][QF][N] phi_l at the face nodes (side 0: xi_a = -1, side 1: +1)
+//   TW [d][2][QF][N] TF times the face-node weight
+//   WQ [Q]           volume-node weights
+//   PS [NS][N]       phi_l at the positivity points
+//   XQ [Q][3]        volume-node coordinates
+struct Layout {
+  int B, DW, TF, TW, WQ, PS, XQ, total;
+};
+
+Layout make_layout(const Shape &s);
+
+// Host tables for (d, k); also returns the first GLL weight.
+std::vector<double> build_tables(const Shape &s, double *gll_w1);
+
+// Exponent triples of the modes in the library's mode order.
+std::vector<int> mode_exponents(int d, int k);
+
+}  // namespace dg
+
+struct dg_ctx {
+  dg_config cfg;
+  dg::Shape sh;
+  dg::Layout lay;
+  long nx, ny, nz, ncell;
+  double dx;
+  double gll_w1;
+  double cfl_fk;  // CFL times the order factor of the time step
+  std::vector<double> host_tab;
+  double *tab = nullptr;     // FP64 tables on the device
+  float *tab32 = nullptr;    // FP32 copy
+  double *partial = nullptr; // per-block maxima of the time-step reduction
+  int npartial = 0;
+  int *flag = nullptr;       // sticky device error flag
+  int device = 0;
+};

@@ -1,0 +1,823 @@
+// HIP kernels of libdg for CDNA4 (gfx950) and the C ABI declared in dg.h.
+//
+// Work decomposition: one thread per cell.  A thread
+//   1. reads the cell's modal weights (coalesced: x-fastest SoA layout),
+//   2. evaluates the volume integral of eq. dg_term2: the state at each
+//      (k+1)^d Gauss node, the Euler flux there, and the projection onto
+//      the basis gradients,
+//   3. evaluates the face integral of eq. dg_term3 on its 2d faces: the own
+//      trace from registers, the neighbour trace from the neighbour's
+//      weights (cache resident), the HLLC flux, and the lift onto the basis,
+//   4. forms L = (2/dx) 2^-d (V - S) and, fused, the SSP-RK3 stage update.
+// Each interior face is evaluated by both of its cells with the same code and
+// the same inputs, so the two contributions are bitwise opposite: the cell
+// means are updated conservatively without atomics or a second pass.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "dg_internal.h"
+
+namespace dg {
+
+template <int D, int K>
+struct Cfg {
+  static constexpr int NV = D + 2;
+  static constexpr int N1 = K + 1;
+  static constexpr int N = D == 2 ? (K + 1) * (K + 2) / 2 : (K + 1) * (K + 2) * (K + 3) / 6;
+  static constexpr int Q = D == 2 ? N1 * N1 : N1 * N1 * N1;
+  static constexpr int QF = Q / N1;
+  static constexpr int M = (K + 4) / 2 < 2 ? 2 : (K + 4) / 2;
+  static constexpr int NS = D * M * QF;
+  static constexpr int B = 0;
+  static constexpr int DW = B + Q * N;
+  static constexpr int TF = DW + D * Q * N;
+  static constexpr int TW = TF + D * 2 * QF * N;
+  static constexpr int WQ = TW + D * 2 * QF * N;
+  static constexpr int PS = WQ + Q;
+  static constexpr int XQ = PS + NS * N;
+  static constexpr int TOTAL = XQ + 3 * Q;
+};
+
+struct Grid {
+  int nx, ny, nz;
+  long ncell;
+  int bc[3];
+  double fac;    // (2/dx) 2^-d
+  double gamma;
+  int davis;     // HLLC wave-speed bounds: 0 Einfeldt-Batten, 1 Davis
+};
+
+enum : int { FLAG_NEGATIVE = 1, FLAG_NAN = 2 };
+
+// Flat index of the neighbour of (ix,iy,iz) along axis a in direction dir,
+// or -1 at a transmissive boundary.
+__device__ inline long neighbour(const Grid &g, int ix, int iy, int iz, int a, int dir) {
+  int i[3] = {ix, iy, iz};
+  int n[3] = {g.nx, g.ny, g.nz};
+  i[a] += dir;
+  if (i[a] < 0 || i[a] >= n[a]) {
+    if (g.bc[a] == DG_BC_TRANSMISSIVE) return -1;
+    i[a] = i[a] < 0 ? i[a] + n[a] : i[a] - n[a];
+  }
+  return ((long)i[2] * g.ny + i[1]) * g.nx + i[0];
+}
+
+// Euler flux f_a(U) (eq. flux_vectors; 2D drops the third velocity).
+template <int D>
+__device__ inline void euler_flux(const double *U, int a, double gm1, double *F) {
+  const double ir = 1.0 / U[0];
+  double ke = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) ke = fma(U[1 + b], U[1 + b] * ir, ke);
+  const double p = gm1 * (U[D + 1] - 0.5 * ke);
+  const double va = U[1 + a] * ir;
+  F[0] = U[1 + a];
+#pragma unroll
+  for (int b = 0; b < D; ++b) F[1 + b] = fma(U[1 + b], va, b == a ? p : 0.0);
+  F[D + 1] = (U[D + 1] + p) * va;
+}
+
+// HLLC numerical flux in +a between traces UL (low side) and UR (high side),
+// in the compact form F = F_K + S_K^(-/+) (U*_K - U_K) with K = L if S* >= 0
+// (S_L^- = min(S_L, 0)) and K = R otherwise (S_R^+ = max(S_R, 0)); this
+// equals the four-region selection of the textbook solver.
+template <int D>
+__device__ inline void hllc(const double *UL, const double *UR, int a, double g, int davis, double *F) {
+  const double gm1 = g - 1.0;
+  const double irL = 1.0 / UL[0], irR = 1.0 / UR[0];
+  double vL[D], vR[D], keL = 0.0, keR = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    vL[b] = UL[1 + b] * irL;
+    vR[b] = UR[1 + b] * irR;
+    keL = fma(UL[1 + b], vL[b], keL);
+    keR = fma(UR[1 + b], vR[b], keR);
+  }
+  const double pL = gm1 * (UL[D + 1] - 0.5 * keL);
+  const double pR = gm1 * (UR[D + 1] - 0.5 * keR);
+  const double cL = sqrt(g * pL * irL), cR = sqrt(g * pR * irR);
+  const double uL = vL[a], uR = vR[a];
+  double SL, SR;
+  if (davis) {
+    SL = fmin(uL - cL, uR - cR);
+    SR = fmax(uL + cL, uR + cR);
+  } else {
+    const double sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+    const double is = 1.0 / (sL + sR);
+    double q2 = 0.0, ut = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double vt = (sL * vL[b] + sR * vR[b]) * is;
+      q2 = fma(vt, vt, q2);
+      if (b == a) ut = vt;
+    }
+    const double HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
+    const double Ht = (sL * HL + sR * HR) * is;
+    const double ct2 = gm1 * (Ht - 0.5 * q2);
+    const double ct = ct2 > 0.0 ? sqrt(ct2) : 0.0;
+    SL = fmin(uL - cL, ut - ct);
+    SR = fmax(uR + cR, ut + ct);
+  }
+  const double dL = SL - uL, dR = SR - uR;
+  const double Ss = (pR - pL + UL[1 + a] * dL - UR[1 + a] * dR) / (UL[0] * dL - UR[0] * dR);
+  const bool left = Ss >= 0.0;
+  const double *U = left ? UL : UR;
+  const double SK = left ? SL : SR;
+  const double SKc = left ? fmin(SL, 0.0) : fmax(SR, 0.0);
+  const double rK = U[0], irK = left ? irL : irR, pK = left ? pL : pR;
+  const double uK = left ? uL : uR, dK = left ? dL : dR;
+  double FK[D + 2];
+  // physical flux of the selected side
+  FK[0] = U[1 + a];
+#pragma unroll
+  for (int b = 0; b < D; ++b) FK[1 + b] = fma(U[1 + b], uK, b == a ? pK : 0.0);
+  FK[D + 1] = (U[D + 1] + pK) * uK;
+  // star state U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S* n + v_t, E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))))
+  const double fac = rK * dK / (SK - Ss);
+  double Us[D + 2];
+  Us[0] = fac;
+#pragma unroll
+  for (int b = 0; b < D; ++b) Us[1 + b] = fac * (b == a ? Ss : U[1 + b] * irK);
+  Us[D + 1] = fac * (U[D + 1] * irK + (Ss - uK) * (Ss + pK / (rK * dK)));
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) F[v] = fma(SKc, Us[v] - U[v], FK[v]);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side and fused SSP-RK3 stage.
+// mode 0: out = L;  mode 1: stage 1 (out = w + dt L);  mode 2: stages 2, 3
+// (out = ca wn + cb (w + dt L)).
+// ---------------------------------------------------------------------------
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const double *__restrict__ w,
+                                                   const double *__restrict__ wn, double *__restrict__ out,
+                                                   const double *__restrict__ dtp, Grid g, int mode, double ca,
+                                                   double cb, int *__restrict__ flag) {
+  using C = Cfg<D, K>;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const long nc = g.ncell;
+  const int ix = (int)(cell % g.nx);
+  const int iy = (int)((cell / g.nx) % g.ny);
+  const int iz = (int)(cell / ((long)g.nx * g.ny));
+  const double gm1 = g.gamma - 1.0;
+
+  double wc[C::NV][C::N];
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) wc[v][l] = w[(long)(v * C::N + l) * nc + cell];
+
+  double acc[C::NV][C::N];
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) acc[v][l] = 0.0;
+
+  // volume integral (eq. dg_term2)
+#pragma unroll 1
+  for (int q = 0; q < C::Q; ++q) {
+    double U[C::NV];
+    const double *bq = tab + C::B + q * C::N;
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) s = fma(wc[v][l], bq[l], s);
+      U[v] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double F[C::NV];
+      euler_flux<D>(U, a, gm1, F);
+      const double *dw = tab + C::DW + (a * C::Q + q) * C::N;
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+        for (int l = 0; l < C::N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+    }
+  }
+
+  // face integral (eq. dg_term3) over the 2d faces.  One call site of the
+  // Riemann solver: the low and high cell of a face feed it the same
+  // (U_low, U_high) and obtain the same flux bit for bit.
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
+      const long src = nb >= 0 ? nb : cell;
+      double wb[C::NV][C::N];
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+        for (int l = 0; l < C::N; ++l) wb[v][l] = w[(long)(v * C::N + l) * nc + src];
+      const double *to = tab + C::TF + (a * 2 + s) * C::QF * C::N;
+      const double *tn = tab + C::TF + (a * 2 + (1 - s)) * C::QF * C::N;
+      const double *tw = tab + C::TW + (a * 2 + s) * C::QF * C::N;
+#pragma unroll 1
+      for (int r = 0; r < C::QF; ++r) {
+        double Uo[C::NV], Un[C::NV], UL[C::NV], UR[C::NV], F[C::NV];
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) {
+          double so = 0.0, sn = 0.0;
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) {
+            so = fma(wc[v][l], to[r * C::N + l], so);
+            sn = fma(wb[v][l], tn[r * C::N + l], sn);
+          }
+          Uo[v] = so;
+          Un[v] = nb >= 0 ? sn : so;  // transmissive: ghost trace = own trace
+          UL[v] = s ? Uo[v] : Un[v];
+          UR[v] = s ? Un[v] : Uo[v];
+        }
+        hllc<D>(UL, UR, a, g.gamma, g.davis, F);
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) {
+          const double f = s ? -F[v] : F[v];
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) acc[v][l] = fma(f, tw[r * C::N + l], acc[v][l]);
+        }
+      }
+    }
+  }
+
+  bool bad = false;
+  if (mode == 0) {
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) {
+        const double L = g.fac * acc[v][l];
+        bad |= (L != L);
+        out[(long)(v * C::N + l) * nc + cell] = L;
+      }
+  } else {
+    const double dt = *dtp;
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) {
+        const long i = (long)(v * C::N + l) * nc + cell;
+        const double L = g.fac * acc[v][l];
+        bad |= (L != L);
+        const double o = wc[v][l] + dt * L;
+        out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
+      }
+  }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// ---------------------------------------------------------------------------
+// L2 projection of nodal primitive data (Sec. 2.3).
+// ---------------------------------------------------------------------------
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_project(const double *__restrict__ tab, const double *__restrict__ prim,
+                                                 double *__restrict__ w, long nc, double gamma) {
+  using C = Cfg<D, K>;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nc) return;
+  double acc[C::NV][C::N];
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) acc[v][l] = 0.0;
+  for (int q = 0; q < C::Q; ++q) {
+    double pr[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) pr[c] = prim[((long)c * C::Q + q) * nc + cell];
+    double U[C::NV];
+    double ke = 0.0;
+    U[0] = pr[0];
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      U[1 + b] = pr[0] * pr[1 + b];
+      ke += pr[1 + b] * pr[1 + b];
+    }
+    U[D + 1] = pr[4] / (gamma - 1.0) + 0.5 * pr[0] * ke;
+    const double wq = tab[C::WQ + q];
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) acc[v][l] = fma(U[v] * wq, tab[C::B + q * C::N + l], acc[v][l]);
+  }
+  const double scale = 1.0 / (double)(1 << D);
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = scale * acc[v][l];
+}
+
+// ---------------------------------------------------------------------------
+// Time step (eq. time_step / time_step_pos): max over cells of the signal
+// rate sum_a (|v_a| + c)/dx of the cell mean; dt = CFL f_k / max rate.
+// ---------------------------------------------------------------------------
+__device__ inline double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+  return x;
+}
+
+__device__ inline double block_max(double x) {
+  __shared__ double red[16];
+  x = wave_max(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  x = (threadIdx.x < nw) ? red[threadIdx.x] : 0.0;
+  if (wid == 0) x = wave_max(x);
+  return x;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long nc, int N, double gamma, double dx,
+                                              double *__restrict__ partial, int *__restrict__ flag) {
+  double m = 0.0;
+  bool bad = false;
+  for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += (long)gridDim.x * blockDim.x) {
+    double U[D + 2];
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) U[v] = w[(long)v * N * nc + cell];
+    double ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
+    const double p = (gamma - 1.0) * (U[D + 1] - 0.5 * ke);
+    bad |= !(U[0] > 0.0) || !(p > 0.0);
+    const double c = sqrt(gamma * p / U[0]);
+    double rate = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
+    m = fmax(m, rate);
+  }
+  if (bad) atomicOr(flag, FLAG_NEGATIVE);
+  m = block_max(m);
+  if (threadIdx.x == 0) partial[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(256) void k_dt_final(const double *__restrict__ partial, int n, double cfl_fk,
+                                                  double *__restrict__ dt) {
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, partial[i]);
+  m = block_max(m);
+  if (threadIdx.x == 0) dt[0] = cfl_fk / m;
+}
+
+// ---------------------------------------------------------------------------
+// Limiters (Sec. 3.1, 3.3, 3.4), one thread per cell, in place.  Cell means
+// are read from the neighbours and never written, so the pass is race free.
+// ---------------------------------------------------------------------------
+__device__ inline double minmod3(double a, double b, double c) {
+  if (a > 0.0 && b > 0.0 && c > 0.0) return fmin(a, fmin(b, c));
+  if (a < 0.0 && b < 0.0 && c < 0.0) return -fmin(-a, fmin(-b, -c));
+  return 0.0;
+}
+
+// Root in [0,1] of (E(t) - eps/(g-1)) rho(t) - |m(t)|^2/2 = 0 along
+// U(t) = Ub + t (Uq - Ub): quadratic formula without cancellation, then two
+// Newton steps; bisection when rounding makes the discriminant negative.
+template <int D>
+__device__ inline double tau_root(const double *Ub, const double *Uq, double gamma, double eps) {
+  const double e1 = eps / (gamma - 1.0);
+  const double dr = Uq[0] - Ub[0], dE = Uq[D + 1] - Ub[D + 1];
+  double dm2 = 0.0, mdm = 0.0, mb2 = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const double dm = Uq[1 + b] - Ub[1 + b];
+    dm2 += dm * dm;
+    mdm += Ub[1 + b] * dm;
+    mb2 += Ub[1 + b] * Ub[1 + b];
+  }
+  const double A = dE * dr - 0.5 * dm2;
+  const double Bq = dE * Ub[0] + (Ub[D + 1] - e1) * dr - mdm;
+  const double Cq = (Ub[D + 1] - e1) * Ub[0] - 0.5 * mb2;
+  double t;
+  const double disc = Bq * Bq - 4.0 * A * Cq;
+  if (A == 0.0) {
+    t = -Cq / Bq;
+  } else if (disc >= 0.0) {
+    const double qq = -0.5 * (Bq + copysign(sqrt(disc), Bq));
+    const double r1 = qq / A, r2 = (qq != 0.0) ? Cq / qq : r1;
+    const bool ok1 = r1 >= 0.0 && r1 <= 1.0, ok2 = r2 >= 0.0 && r2 <= 1.0;
+    t = (ok1 && ok2) ? fmin(r1, r2) : ok1 ? r1 : ok2 ? r2 : 0.0;
+  } else {
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 60; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if ((A * mid + Bq) * mid + Cq > 0.0) lo = mid; else hi = mid;
+    }
+    t = lo;
+  }
+  for (int it = 0; it < 2; ++it) {
+    const double gv = (A * t + Bq) * t + Cq, gd = 2.0 * A * t + Bq;
+    if (gd != 0.0) t -= gv / gd;
+  }
+  return fmin(fmax(t, 0.0), 1.0);
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, double *__restrict__ w, Grid g,
+                                               int slope, double beta, double bound, int posit, double eps,
+                                               int *__restrict__ flag) {
+  using C = Cfg<D, K>;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const long nc = g.ncell;
+  const int ix = (int)(cell % g.nx);
+  const int iy = (int)((cell / g.nx) % g.ny);
+  const int iz = (int)(cell / ((long)g.nx * g.ny));
+  double wc[C::NV][C::N];
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) wc[v][l] = w[(long)(v * C::N + l) * nc + cell];
+
+  if (slope && K >= 1) {
+    const double r3 = sqrt(3.0);
+    long nbl[D], nbh[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      nbl[a] = neighbour(g, ix, iy, iz, a, -1);
+      nbh[a] = neighbour(g, ix, iy, iz, a, 1);
+      if (nbl[a] < 0) nbl[a] = cell;
+      if (nbh[a] < 0) nbh[a] = cell;
+    }
+#pragma unroll
+    for (int i = 0; i < C::NV; ++i) {
+      const double mean = wc[i][0];
+      double mt[D];
+      bool limited = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double mlo = w[(long)(i * C::N) * nc + nbl[a]];
+        const double mhi = w[(long)(i * C::N) * nc + nbh[a]];
+        const double A = r3 * wc[i][1 + a];
+        const double m = (fabs(A) <= bound) ? A : minmod3(A, beta * (mean - mlo), beta * (mhi - mean));
+        mt[a] = m;
+        limited |= (m != A);
+      }
+      if (limited) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) wc[i][1 + a] = mt[a] / r3;
+#pragma unroll
+        for (int l = D + 1; l < C::N; ++l) wc[i][l] = 0.0;
+      }
+    }
+  }
+
+  if (posit) {
+    double Ub[C::NV];
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v) Ub[v] = wc[v][0];
+    double keb = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) keb += Ub[1 + b] * Ub[1 + b] / Ub[0];
+    const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
+    if (!(Ub[0] > eps) || !(pb > eps)) {
+      atomicOr(flag, FLAG_NEGATIVE);
+    } else {
+      double rmin = INFINITY;
+      for (int s = 0; s < C::NS; ++s) {
+        double r = 0.0;
+#pragma unroll
+        for (int l = 0; l < C::N; ++l) r = fma(wc[0][l], tab[C::PS + s * C::N + l], r);
+        rmin = fmin(rmin, r);
+      }
+      const double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
+#pragma unroll
+      for (int l = 1; l < C::N; ++l) wc[0][l] *= th1;
+      double th2 = 1.0;
+      for (int s = 0; s < C::NS; ++s) {
+        double Uq[C::NV];
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) {
+          double u = 0.0;
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) u = fma(wc[v][l], tab[C::PS + s * C::N + l], u);
+          Uq[v] = u;
+        }
+        double ke = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) ke += Uq[1 + b] * Uq[1 + b] / Uq[0];
+        const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
+        if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
+      }
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+        for (int l = 1; l < C::N; ++l) wc[v][l] *= th2;
+    }
+  }
+  // write back the modes j >= 2 (the means are unchanged)
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
+}
+
+}  // namespace dg
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+using dg::Cfg;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+thread_local char g_hip_msg[256];
+
+int hip_fail(hipError_t e) {
+  std::snprintf(g_hip_msg, sizeof(g_hip_msg), "%s", hipGetErrorString(e));
+  return DG_EHIP;
+}
+
+#define HIP_TRY(expr)                     \
+  do {                                    \
+    hipError_t e_ = (expr);               \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+dg::Grid make_grid(const dg_ctx *c) {
+  dg::Grid g;
+  g.nx = (int)c->nx;
+  g.ny = (int)c->ny;
+  g.nz = (int)c->nz;
+  g.ncell = c->ncell;
+  for (int a = 0; a < 3; ++a) g.bc[a] = c->cfg.bc[a];
+  g.fac = 2.0 / c->dx / (double)(1 << c->sh.d);
+  g.gamma = c->cfg.gamma;
+  g.davis = c->cfg.flux == DG_HLLC_DAVIS;
+  return g;
+}
+
+unsigned nblocks(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Calls F::template run<D, K>() for the context's (dim, k).
+template <class F>
+int dispatch(const dg_ctx *c, F &&f) {
+  const int d = c->sh.d, k = c->sh.k;
+  if (d == 2 && k == 1) return f.template run<2, 1>();
+  if (d == 2 && k == 2) return f.template run<2, 2>();
+  if (d == 2 && k == 3) return f.template run<2, 3>();
+  if (d == 3 && k == 1) return f.template run<3, 1>();
+  if (d == 3 && k == 2) return f.template run<3, 2>();
+  if (d == 3 && k == 3) return f.template run<3, 3>();
+  return DG_EUNSUPPORTED;
+}
+
+struct LayoutCheck {
+  const dg_ctx *c;
+  template <int D, int K>
+  int run() {
+    using C = Cfg<D, K>;
+    const dg::Layout &l = c->lay;
+    bool ok = l.B == C::B && l.DW == C::DW && l.TF == C::TF && l.TW == C::TW && l.WQ == C::WQ &&
+              l.PS == C::PS && l.XQ == C::XQ && l.total == C::TOTAL && c->sh.N == C::N && c->sh.NS == C::NS;
+    return ok ? DG_OK : DG_EINVAL;
+  }
+};
+
+int check_layout(const dg_ctx *c) { return dispatch(c, LayoutCheck{c}); }
+
+struct StageLaunch {
+  dg_ctx *c;
+  const double *w, *wn, *dt;
+  double *out;
+  int mode;
+  double ca, cb;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_rhs_stage<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, wn, out, dt,
+                       make_grid(c), mode, ca, cb, c->flag);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+struct ProjectLaunch {
+  dg_ctx *c;
+  const double *prim;
+  double *w;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, prim, w, c->ncell,
+                       c->cfg.gamma);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+struct LimitLaunch {
+  dg_ctx *c;
+  double *w;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_limit<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
+                       c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde * c->dx,
+                       c->cfg.positivity, c->cfg.eps, c->flag);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *dg_strerror(int code) {
+  switch (code) {
+    case DG_OK: return "success";
+    case DG_EINVAL: return "invalid argument";
+    case DG_EUNSUPPORTED: return "unsupported dimension, degree or option";
+    case DG_ENOMEM: return "out of memory";
+    case DG_EHIP: return g_hip_msg[0] ? g_hip_msg : "HIP runtime error";
+    case DG_ENEGATIVE: return "non-positive mean density or pressure";
+    case DG_ENAN: return "NaN in the right-hand side";
+    default: return "unknown error";
+  }
+}
+
+int dg_init(const dg_config *cfg, dg_ctx **out) {
+  if (!cfg || !out) return DG_EINVAL;
+  *out = nullptr;
+  if (cfg->dim != 2 && cfg->dim != 3) return DG_EUNSUPPORTED;
+  if (cfg->k < 1 || cfg->k > 3) return DG_EUNSUPPORTED;
+  for (int a = 0; a < cfg->dim; ++a) {
+    if (cfg->n[a] < 1 || !(cfg->len[a] > 0.0)) return DG_EINVAL;
+    if (cfg->bc[a] != DG_BC_PERIODIC && cfg->bc[a] != DG_BC_TRANSMISSIVE) return DG_EINVAL;
+  }
+  if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return DG_EINVAL;
+  if (cfg->flux != DG_HLLC_BATTEN && cfg->flux != DG_HLLC_DAVIS) return DG_EINVAL;
+  if (cfg->precision != DG_FP64) return DG_EUNSUPPORTED;
+  if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD) return DG_EUNSUPPORTED;
+  if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
+  if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (cfg->refine_lo[a] != cfg->refine_hi[a]) return DG_EUNSUPPORTED;
+  const double dx = cfg->len[0] / cfg->n[0];
+  for (int a = 1; a < cfg->dim; ++a)
+    if (std::fabs(cfg->len[a] / cfg->n[a] - dx) > 1e-12 * dx) return DG_EINVAL;
+  long long cells = 1;
+  for (int a = 0; a < cfg->dim; ++a) cells *= cfg->n[a];
+  if (cells > (1LL << 31)) return DG_EUNSUPPORTED;
+
+  dg_ctx *c = new (std::nothrow) dg_ctx();
+  if (!c) return DG_ENOMEM;
+  c->cfg = *cfg;
+  c->sh = dg::make_shape(cfg->dim, cfg->k);
+  c->lay = dg::make_layout(c->sh);
+  c->nx = cfg->n[0];
+  c->ny = cfg->n[1];
+  c->nz = cfg->dim == 3 ? cfg->n[2] : 1;
+  c->ncell = c->nx * c->ny * c->nz;
+  c->dx = dx;
+  try {
+    c->host_tab = dg::build_tables(c->sh, &c->gll_w1);
+  } catch (...) {
+    delete c;
+    return DG_EUNSUPPORTED;
+  }
+  if (check_layout(c) != DG_OK) {
+    delete c;
+    return DG_EINVAL;
+  }
+  double fk = 1.0 / (2.0 * cfg->k + 1.0);
+  if (cfg->positivity && c->gll_w1 / 2.0 < fk) fk = c->gll_w1 / 2.0;
+  c->cfl_fk = cfg->cfl * fk;
+  c->npartial = (int)std::min<long>(1024, (c->ncell + kBlock - 1) / kBlock);
+
+  auto fail = [&](hipError_t e) {
+    int r = hip_fail(e);
+    dg_destroy(c);
+    return r;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&c->device)) != hipSuccess) return fail(e);
+  const size_t nt = c->host_tab.size();
+  if ((e = hipMalloc((void **)&c->tab, nt * sizeof(double))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->partial, c->npartial * sizeof(double))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->flag, sizeof(int))) != hipSuccess) return fail(e);
+  std::vector<float> t32(nt);
+  for (size_t i = 0; i < nt; ++i) t32[i] = (float)c->host_tab[i];
+  if ((e = hipMemcpy(c->tab, c->host_tab.data(), nt * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
+  if ((e = hipMemcpy(c->tab32, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  int zero = 0;
+  if ((e = hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  *out = c;
+  return DG_OK;
+}
+
+void dg_destroy(dg_ctx *c) {
+  if (!c) return;
+  if (c->tab) (void)hipFree(c->tab);
+  if (c->tab32) (void)hipFree(c->tab32);
+  if (c->partial) (void)hipFree(c->partial);
+  if (c->flag) (void)hipFree(c->flag);
+  delete c;
+}
+
+int dg_state_size(const dg_ctx *c, int64_t *n) {
+  if (!c || !n) return DG_EINVAL;
+  *n = (int64_t)c->sh.nv * c->sh.N * c->ncell;
+  return DG_OK;
+}
+
+int dg_sizes(const dg_ctx *c, int64_t out[6]) {
+  if (!c || !out) return DG_EINVAL;
+  out[0] = c->sh.nv;
+  out[1] = c->sh.N;
+  out[2] = c->sh.Q;
+  out[3] = c->sh.QF;
+  out[4] = c->ncell;
+  out[5] = c->sh.NS;
+  return DG_OK;
+}
+
+int dg_quadrature(const dg_ctx *c, double *xi, double *w) {
+  if (!c || !xi || !w) return DG_EINVAL;
+  for (int q = 0; q < c->sh.Q; ++q) {
+    for (int a = 0; a < 3; ++a) xi[3 * q + a] = c->host_tab[c->lay.XQ + 3 * q + a];
+    w[q] = c->host_tab[c->lay.WQ + q];
+  }
+  return DG_OK;
+}
+
+int dg_project(dg_ctx *c, const double *prim, double *w, void *stream) {
+  if (!c || !prim || !w) return DG_EINVAL;
+  return dispatch(c, ProjectLaunch{c, prim, w, (hipStream_t)stream});
+}
+
+int dg_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
+  if (!c || !w || !L || w == L) return DG_EINVAL;
+  return dispatch(c, StageLaunch{c, w, nullptr, nullptr, L, 0, 0.0, 0.0, (hipStream_t)stream});
+}
+
+int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const double *wp, double *out,
+                void *stream) {
+  if (!c || !dt || !wp || !out || stage < 1 || stage > 3) return DG_EINVAL;
+  if (stage > 1 && !wn) return DG_EINVAL;
+  if (out == wp || out == wn) return DG_EINVAL;
+  static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+  return dispatch(c, StageLaunch{c, wp, wn, dt, out, stage == 1 ? 1 : 2, A[stage - 1], B[stage - 1],
+                                 (hipStream_t)stream});
+}
+
+int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
+  if (!c || !w || !dt) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->sh.d == 2)
+    hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                       c->dx, c->partial, c->flag);
+  else
+    hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                       c->dx, c->partial, c->flag);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(kBlock), 0, s, c->partial, c->npartial, c->cfl_fk, dt);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_limit(dg_ctx *c, double *w, void *stream) {
+  if (!c || !w) return DG_EINVAL;
+  if (c->cfg.slope_limiter == DG_LIM_NONE && !c->cfg.positivity) return DG_OK;
+  return dispatch(c, LimitLaunch{c, w, (hipStream_t)stream});
+}
+
+int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {
+  (void)stream;
+  if (!c || !w || !lam || !mu) return DG_EINVAL;
+  return DG_EUNSUPPORTED;
+}
+
+int dg_adjoint_rk_stage(dg_ctx *c, int stage, const double *dt, const double *u, const double *lam,
+                        const double *acc, double *lam_out, double *acc_out, void *stream) {
+  (void)stage; (void)dt; (void)u; (void)lam; (void)acc; (void)lam_out; (void)acc_out; (void)stream;
+  if (!c) return DG_EINVAL;
+  return DG_EUNSUPPORTED;
+}
+
+int dg_status(dg_ctx *c, void *stream) {
+  if (!c) return DG_EINVAL;
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  int f = 0, zero = 0;
+  HIP_TRY(hipMemcpy(&f, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice));
+  if (f & dg::FLAG_NEGATIVE) return DG_ENEGATIVE;
+  if (f & dg::FLAG_NAN) return DG_ENAN;
+  return DG_OK;
+}
+
+}  // extern "C"

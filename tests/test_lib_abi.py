@@ -1,0 +1,66 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/dg.h declares, and validates configurations on the host before any
+device work.  No compute call is made (no GPU here)."""
+import os
+import re
+
+import pytest
+
+import paper_1506_06140_amd as dg
+import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*\*?(dg_\w+)\s*\(", src, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = dg.load_library()
+    names = _declared()
+    assert "dg_init" in names and "dg_rk_stage" in names and "dg_adjoint_rhs" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(dg.EXPORTS)
+
+
+def test_strerror_covers_codes():
+    for code in range(0, -7, -1):
+        assert dg.strerror(code) != "unknown error"
+    assert dg.strerror(-99) == "unknown error"
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("dim", 4, dg.DG_EUNSUPPORTED),
+    ("k", 0, dg.DG_EUNSUPPORTED),
+    ("k", 4, dg.DG_EUNSUPPORTED),
+    ("gamma", 1.0, dg.DG_EINVAL),
+    ("cfl", 0.0, dg.DG_EINVAL),
+    ("flux", 7, dg.DG_EINVAL),
+])
+def test_init_rejects_bad_configs_on_the_host(field, value, code):
+    import ctypes as C
+    lib = dg.load_library()
+    cfg = dg.make_config(workloads.workload("density_wave"))
+    setattr(cfg, field, value)
+    ctx = C.c_void_p()
+    assert lib.dg_init(C.byref(cfg), C.byref(ctx)) == code
+    assert not ctx.value
+
+
+def test_init_rejects_non_cubic_cells():
+    import ctypes as C
+    lib = dg.load_library()
+    cfg = dg.make_config(workloads.workload("density_wave", n=(32, 16, 1)))
+    ctx = C.c_void_p()
+    assert lib.dg_init(C.byref(cfg), C.byref(ctx)) == dg.DG_EINVAL
+
+
+def test_null_arguments_are_rejected():
+    lib = dg.load_library()
+    assert lib.dg_init(None, None) == dg.DG_EINVAL
+    assert lib.dg_rhs(None, None, None, None) == dg.DG_EINVAL
+    assert lib.dg_status(None, None) == dg.DG_EINVAL
+    lib.dg_destroy(None)
