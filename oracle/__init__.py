@@ -81,6 +81,7 @@ def _load():
             "orc_rhs": [cp, dp, dp],
             "orc_rhs_cells": [cp, dp, C.c_long, lp, dp],
             "orc_terms_cell": [cp, dp, C.c_long, dp, dp],
+            "orc_terms_cells": [cp, dp, C.c_long, lp, dp, dp],
             "orc_max_dt": [cp, dp, dp],
             "orc_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
             "orc_limit": [cp, dp],
@@ -255,6 +256,15 @@ class Oracle:
         lib, _ = _load()
         V = np.zeros((self.nvar, self.N)); S = np.zeros((self.nvar, self.N))
         _check(lib.orc_terms_cell(C.byref(self.c), self._s(w), cell, V, S), "terms")
+        return V, S
+
+    def terms_cells(self, w: np.ndarray, cells=None):
+        """(fac V, fac S) of selected cells (all if None): [nvar][N][ncells] each."""
+        lib, _ = _load()
+        cells = np.arange(self.ncell) if cells is None else cells
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        V = np.zeros((self.nvar, self.N, cells.size)); S = np.zeros_like(V)
+        _check(lib.orc_terms_cells(C.byref(self.c), self._s(w), cells.size, cells, V, S), "terms_cells")
         return V, S
 
     def max_dt(self, w: np.ndarray) -> float:

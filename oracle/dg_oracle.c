@@ -611,6 +611,31 @@ int orc_rhs_cells(const orc_config *c, const double *w, long ncells, const long 
   return ORC_OK;
 }
 
+/* Volume and surface terms of a list of cells, scaled like L:
+ * V_out = fac V, S_out = fac S, each [nvar][N][ncells], so that L = V_out - S_out.
+ * Their magnitudes bound the rounding error of L (tests use them as the
+ * conditioning scale of the right-hand side). */
+int orc_terms_cells(const orc_config *c, const double *w, long ncells, const long *cells, double *V_out,
+                    double *S_out) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  double fac = 2.0 / X->dx / (double)(1 << X->d);
+  for (long i = 0; i < ncells; ++i) {
+    if (cells[i] < 0 || cells[i] >= X->ncell) { free(X); return ORC_EINVAL; }
+    double Vc[MAXV][MAXN], Sc[MAXV][MAXN];
+    volume_term(X, w, cells[i], Vc);
+    surface_term(X, w, cells[i], Sc);
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) {
+        V_out[((long)v * X->N + j) * ncells + i] = fac * Vc[v][j];
+        S_out[((long)v * X->N + j) * ncells + i] = fac * Sc[v][j];
+      }
+  }
+  free(X);
+  return ORC_OK;
+}
+
 /* Volume and surface terms separately for one cell (unit tests). */
 int orc_terms_cell(const orc_config *c, const double *w, long cell, double *V, double *S) {
   ctx *X = malloc(sizeof(ctx));

@@ -81,70 +81,115 @@ __device__ inline void euler_flux(const double *U, int a, double gm1, double *F)
   F[D + 1] = (U[D + 1] + p) * va;
 }
 
+// Scalar helpers so that the Riemann solver can run on doubles (the forward
+// pass) and on dual numbers (exact forward-mode derivatives for the adjoint)
+// with the same sequence of value operations, hence the same branches.
+__device__ inline double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline double vsqrt(double a) { return sqrt(a); }
+__device__ inline double vmin(double a, double b) { return b < a ? b : a; }
+__device__ inline double vmax(double a, double b) { return b > a ? b : a; }
+__device__ inline double val(double a) { return a; }
+
+// Dual number a + b eps (eps^2 = 0): value and one directional derivative.
+struct Dual {
+  double v, d;
+};
+__device__ inline Dual mkd(double v) { return Dual{v, 0.0}; }
+__device__ inline Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
+__device__ inline Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
+__device__ inline Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
+__device__ inline Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
+__device__ inline Dual operator*(double a, Dual b) { return Dual{a * b.v, a * b.d}; }
+__device__ inline Dual operator/(Dual a, Dual b) {
+  const double q = a.v / b.v;
+  return Dual{q, (a.d - q * b.d) / b.v};
+}
+__device__ inline Dual operator/(double a, Dual b) {
+  const double q = a / b.v;
+  return Dual{q, -q * b.d / b.v};
+}
+__device__ inline Dual vfma(Dual a, Dual b, Dual c) { return Dual{fma(a.v, b.v, c.v), fma(a.d, b.v, fma(a.v, b.d, c.d))}; }
+__device__ inline Dual vsqrt(Dual a) {
+  const double r = sqrt(a.v);
+  return Dual{r, r > 0.0 ? 0.5 * a.d / r : 0.0};
+}
+__device__ inline Dual vmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
+__device__ inline Dual vmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
+__device__ inline double val(Dual a) { return a.v; }
+
+template <class T>
+__device__ inline T cst(double x);
+template <>
+__device__ inline double cst<double>(double x) { return x; }
+template <>
+__device__ inline Dual cst<Dual>(double x) { return mkd(x); }
+
 // HLLC numerical flux in +a between traces UL (low side) and UR (high side),
 // in the compact form F = F_K + S_K^(-/+) (U*_K - U_K) with K = L if S* >= 0
 // (S_L^- = min(S_L, 0)) and K = R otherwise (S_R^+ = max(S_R, 0)); this
-// equals the four-region selection of the textbook solver.
-template <int D>
-__device__ inline void hllc(const double *UL, const double *UR, int a, double g, int davis, double *F) {
+// equals the four-region selection of the textbook solver.  Wave-speed
+// bounds: Einfeldt-Batten (Roe-averaged) or Davis.
+template <class T, int D>
+__device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis, T *F) {
   const double gm1 = g - 1.0;
-  const double irL = 1.0 / UL[0], irR = 1.0 / UR[0];
-  double vL[D], vR[D], keL = 0.0, keR = 0.0;
+  const T one = cst<T>(1.0), zero = cst<T>(0.0);
+  const T irL = one / UL[0], irR = one / UR[0];
+  T vL[D], vR[D], keL = zero, keR = zero;
 #pragma unroll
   for (int b = 0; b < D; ++b) {
     vL[b] = UL[1 + b] * irL;
     vR[b] = UR[1 + b] * irR;
-    keL = fma(UL[1 + b], vL[b], keL);
-    keR = fma(UR[1 + b], vR[b], keR);
+    keL = vfma(UL[1 + b], vL[b], keL);
+    keR = vfma(UR[1 + b], vR[b], keR);
   }
-  const double pL = gm1 * (UL[D + 1] - 0.5 * keL);
-  const double pR = gm1 * (UR[D + 1] - 0.5 * keR);
-  const double cL = sqrt(g * pL * irL), cR = sqrt(g * pR * irR);
-  const double uL = vL[a], uR = vR[a];
-  double SL, SR;
+  const T pL = gm1 * (UL[D + 1] - 0.5 * keL);
+  const T pR = gm1 * (UR[D + 1] - 0.5 * keR);
+  const T cL = vsqrt(g * pL * irL), cR = vsqrt(g * pR * irR);
+  const T uL = vL[a], uR = vR[a];
+  T SL, SR;
   if (davis) {
-    SL = fmin(uL - cL, uR - cR);
-    SR = fmax(uL + cL, uR + cR);
+    SL = vmin(uL - cL, uR - cR);
+    SR = vmax(uL + cL, uR + cR);
   } else {
-    const double sL = sqrt(UL[0]), sR = sqrt(UR[0]);
-    const double is = 1.0 / (sL + sR);
-    double q2 = 0.0, ut = 0.0;
+    const T sL = vsqrt(UL[0]), sR = vsqrt(UR[0]);
+    const T is = one / (sL + sR);
+    T q2 = zero, ut = zero;
 #pragma unroll
     for (int b = 0; b < D; ++b) {
-      const double vt = (sL * vL[b] + sR * vR[b]) * is;
-      q2 = fma(vt, vt, q2);
+      const T vt = (sL * vL[b] + sR * vR[b]) * is;
+      q2 = vfma(vt, vt, q2);
       if (b == a) ut = vt;
     }
-    const double HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
-    const double Ht = (sL * HL + sR * HR) * is;
-    const double ct2 = gm1 * (Ht - 0.5 * q2);
-    const double ct = ct2 > 0.0 ? sqrt(ct2) : 0.0;
-    SL = fmin(uL - cL, ut - ct);
-    SR = fmax(uR + cR, ut + ct);
+    const T HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
+    const T Ht = (sL * HL + sR * HR) * is;
+    const T ct2 = gm1 * (Ht - 0.5 * q2);
+    const T ct = val(ct2) > 0.0 ? vsqrt(ct2) : zero;
+    SL = vmin(uL - cL, ut - ct);
+    SR = vmax(uR + cR, ut + ct);
   }
-  const double dL = SL - uL, dR = SR - uR;
-  const double Ss = (pR - pL + UL[1 + a] * dL - UR[1 + a] * dR) / (UL[0] * dL - UR[0] * dR);
-  const bool left = Ss >= 0.0;
-  const double *U = left ? UL : UR;
-  const double SK = left ? SL : SR;
-  const double SKc = left ? fmin(SL, 0.0) : fmax(SR, 0.0);
-  const double rK = U[0], irK = left ? irL : irR, pK = left ? pL : pR;
-  const double uK = left ? uL : uR, dK = left ? dL : dR;
-  double FK[D + 2];
+  const T dL = SL - uL, dR = SR - uR;
+  const T Ss = (pR - pL + UL[1 + a] * dL - UR[1 + a] * dR) / (UL[0] * dL - UR[0] * dR);
+  const bool left = val(Ss) >= 0.0;
+  const T *U = left ? UL : UR;
+  const T SK = left ? SL : SR;
+  const T SKc = left ? vmin(SL, zero) : vmax(SR, zero);
+  const T rK = U[0], irK = left ? irL : irR, pK = left ? pL : pR;
+  const T uK = left ? uL : uR, dK = left ? dL : dR;
+  T FK[D + 2];
   // physical flux of the selected side
   FK[0] = U[1 + a];
 #pragma unroll
-  for (int b = 0; b < D; ++b) FK[1 + b] = fma(U[1 + b], uK, b == a ? pK : 0.0);
+  for (int b = 0; b < D; ++b) FK[1 + b] = vfma(U[1 + b], uK, b == a ? pK : zero);
   FK[D + 1] = (U[D + 1] + pK) * uK;
-  // star state U*_K = rho_K (S_K - u_K)/(S_K - S*) (1, S* n + v_t, E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))))
-  const double fac = rK * dK / (SK - Ss);
-  double Us[D + 2];
+  // star state rho_K (S_K - u_K)/(S_K - S*) (1, S* n + v_t, E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))))
+  const T fac = rK * dK / (SK - Ss);
+  T Us[D + 2];
   Us[0] = fac;
 #pragma unroll
   for (int b = 0; b < D; ++b) Us[1 + b] = fac * (b == a ? Ss : U[1 + b] * irK);
   Us[D + 1] = fac * (U[D + 1] * irK + (Ss - uK) * (Ss + pK / (rK * dK)));
 #pragma unroll
-  for (int v = 0; v < D + 2; ++v) F[v] = fma(SKc, Us[v] - U[v], FK[v]);
+  for (int v = 0; v < D + 2; ++v) F[v] = vfma(SKc, Us[v] - U[v], FK[v]);
 }
 
 // ---------------------------------------------------------------------------
@@ -235,7 +280,7 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
           UL[v] = s ? Uo[v] : Un[v];
           UR[v] = s ? Un[v] : Uo[v];
         }
-        hllc<D>(UL, UR, a, g.gamma, g.davis, F);
+        hllc<double, D>(UL, UR, a, g.gamma, g.davis, F);
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) {
           const double f = s ? -F[v] : F[v];
@@ -269,6 +314,197 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
         out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
       }
   }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.
+//
+// mu = (dL/dw)^T lam for L = fac (V - S):
+//   volume: mu_K[u][l] += sum_q B[q][l] sum_a (J_a(U_q)^T Lam_a,q)[u] with
+//           Lam_a,q[v] = sum_j lam_K[v][j] DW[a][q][j] and J_a = d f_a / dU
+//           (analytic transposed Euler Jacobian);
+//   faces:  for a face with low cell A and high cell B the flux enters
+//           L_A with -TW(+1) and L_B with +TW(-1); its cotangent is
+//           g = -lam_A . TW(+1) + lam_B . TW(-1), and the own cell receives
+//           (dF/dU_own)^T g lifted with TF, the Jacobian row of the Riemann
+//           solver being computed by forward-mode dual numbers through the
+//           same solver code (so the same branches as the forward pass).
+// mode 0: out = mu;  mode 3: out = cb (lam + dt mu), acc_out = ca lam;
+// mode 2: out = cb (lam + dt mu), acc_out = acc + ca lam;
+// mode 1: out = acc + lam + dt mu.
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ inline void euler_flux_vjp(const double *U, int a, double g, const double *Lam, double *G) {
+  const double gm1 = g - 1.0;
+  const double ir = 1.0 / U[0];
+  double v[D], q2 = 0.0, lv = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    v[b] = U[1 + b] * ir;
+    q2 = fma(v[b], v[b], q2);
+    lv = fma(Lam[1 + b], v[b], lv);
+  }
+  const double p = gm1 * (U[D + 1] - 0.5 * U[0] * q2);
+  const double H = (U[D + 1] + p) * ir;
+  const double va = v[a], la = Lam[1 + a], lE = Lam[D + 1];
+  const double hk = 0.5 * gm1 * q2;
+  G[0] += -va * lv + la * hk + lE * va * (hk - H);
+#pragma unroll
+  for (int c = 0; c < D; ++c)
+    G[1 + c] += (c == a ? Lam[0] + lv + lE * H : 0.0) + Lam[1 + c] * va - gm1 * v[c] * (la + lE * va);
+  G[D + 1] += la * gm1 + lE * g * va;
+}
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_adjoint(const double *__restrict__ tab, const double *__restrict__ w,
+                                                 const double *__restrict__ lam, const double *acc_in,
+                                                 double *__restrict__ out, double *acc_out,
+                                                 const double *__restrict__ dtp, Grid g, int mode, double ca,
+                                                 double cb, int *__restrict__ flag) {
+  using C = Cfg<D, K>;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncell) return;
+  const long nc = g.ncell;
+  const int ix = (int)(cell % g.nx);
+  const int iy = (int)((cell / g.nx) % g.ny);
+  const int iz = (int)(cell / ((long)g.nx * g.ny));
+
+  double wc[C::NV][C::N], lc[C::NV][C::N], mu[C::NV][C::N];
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) {
+      const long i = (long)(v * C::N + l) * nc + cell;
+      wc[v][l] = w[i];
+      lc[v][l] = lam[i];
+      mu[v][l] = 0.0;
+    }
+
+  // volume term
+#pragma unroll 1
+  for (int q = 0; q < C::Q; ++q) {
+    const double *bq = tab + C::B + q * C::N;
+    double U[C::NV], G[C::NV];
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) s = fma(wc[v][l], bq[l], s);
+      U[v] = s;
+      G[v] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const double *dw = tab + C::DW + (a * C::Q + q) * C::N;
+      double Lam[C::NV];
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < C::N; ++l) s = fma(lc[v][l], dw[l], s);
+        Lam[v] = s;
+      }
+      euler_flux_vjp<D>(U, a, g.gamma, Lam, G);
+    }
+#pragma unroll
+    for (int u = 0; u < C::NV; ++u)
+#pragma unroll
+      for (int l = 0; l < C::N; ++l) mu[u][l] = fma(G[u], bq[l], mu[u][l]);
+  }
+
+  // face terms
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
+      const long src = nb >= 0 ? nb : cell;
+      double wb[C::NV][C::N], lb[C::NV][C::N];
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+        for (int l = 0; l < C::N; ++l) {
+          const long i = (long)(v * C::N + l) * nc + src;
+          wb[v][l] = w[i];
+          lb[v][l] = lam[i];
+        }
+      const double *to = tab + C::TF + (a * 2 + s) * C::QF * C::N;
+      const double *tn = tab + C::TF + (a * 2 + (1 - s)) * C::QF * C::N;
+      const double *tw_hi = tab + C::TW + (a * 2 + 1) * C::QF * C::N;  // lift weights of the low cell (xi_a = +1)
+      const double *tw_lo = tab + C::TW + (a * 2 + 0) * C::QF * C::N;  // lift weights of the high cell (xi_a = -1)
+#pragma unroll 1
+      for (int r = 0; r < C::QF; ++r) {
+        double Uo[C::NV], Un[C::NV], gv[C::NV];
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) {
+          double so = 0.0, sn = 0.0, lo_c = 0.0, hi_c = 0.0;
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) {
+            so = fma(wc[v][l], to[r * C::N + l], so);
+            sn = fma(wb[v][l], tn[r * C::N + l], sn);
+          }
+          // lam of the low cell against TW(+1), of the high cell against TW(-1)
+          const double (*lowc)[C::N] = s ? lc : lb;
+          const double (*highc)[C::N] = s ? lb : lc;
+#pragma unroll
+          for (int l = 0; l < C::N; ++l) {
+            lo_c = fma(lowc[v][l], tw_hi[r * C::N + l], lo_c);
+            hi_c = fma(highc[v][l], tw_lo[r * C::N + l], hi_c);
+          }
+          if (nb < 0) {  // the ghost cell of a transmissive boundary has no equation
+            if (s) hi_c = 0.0; else lo_c = 0.0;
+          }
+          Uo[v] = so;
+          Un[v] = nb >= 0 ? sn : so;
+          gv[v] = hi_c - lo_c;
+        }
+#pragma unroll 1
+        for (int u = 0; u < C::NV; ++u) {
+          Dual UL[C::NV], UR[C::NV], F[C::NV];
+#pragma unroll
+          for (int v = 0; v < C::NV; ++v) {
+            const double t = (v == u) ? 1.0 : 0.0;
+            const double own = Uo[v], oth = Un[v];
+            const double to_own = t, to_oth = nb >= 0 ? 0.0 : t;
+            UL[v] = s ? Dual{own, to_own} : Dual{oth, to_oth};
+            UR[v] = s ? Dual{oth, to_oth} : Dual{own, to_own};
+          }
+          hllc<Dual, D>(UL, UR, a, g.gamma, g.davis, F);
+          double h = 0.0;
+#pragma unroll
+          for (int v = 0; v < C::NV; ++v) h = fma(gv[v], F[v].d, h);
+          // mu[u][l] += h * TF_own[r][l]; u is a runtime index, so update every
+          // row with a mask to keep mu in registers
+#pragma unroll
+          for (int uu = 0; uu < C::NV; ++uu) {
+            const double hh = (uu == u) ? h : 0.0;
+#pragma unroll
+            for (int l = 0; l < C::N; ++l) mu[uu][l] = fma(hh, to[r * C::N + l], mu[uu][l]);
+          }
+        }
+      }
+    }
+  }
+
+  const double dt = (mode == 0) ? 0.0 : *dtp;
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = 0; l < C::N; ++l) {
+      const long i = (long)(v * C::N + l) * nc + cell;
+      const double m = g.fac * mu[v][l];
+      bad |= (m != m);
+      if (mode == 0) {
+        out[i] = m;
+      } else if (mode == 1) {
+        out[i] = acc_in[i] + (lc[v][l] + dt * m);
+      } else {
+        out[i] = cb * (lc[v][l] + dt * m);
+        acc_out[i] = (mode == 3) ? ca * lc[v][l] : acc_in[i] + ca * lc[v][l];
+      }
+    }
   if (bad) atomicOr(flag, FLAG_NAN);
 }
 
@@ -630,6 +866,23 @@ struct LimitLaunch {
   }
 };
 
+struct AdjointLaunch {
+  dg_ctx *c;
+  const double *w, *lam, *acc;
+  double *out, *acc_out;
+  const double *dt;
+  int mode;
+  double ca, cb;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_adjoint<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, lam, acc, out,
+                       acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
 }  // namespace
 
 extern "C" {
@@ -797,16 +1050,21 @@ int dg_limit(dg_ctx *c, double *w, void *stream) {
 }
 
 int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {
-  (void)stream;
-  if (!c || !w || !lam || !mu) return DG_EINVAL;
-  return DG_EUNSUPPORTED;
+  if (!c || !w || !lam || !mu || mu == w || mu == lam) return DG_EINVAL;
+  return dispatch(c, AdjointLaunch{c, w, lam, nullptr, mu, nullptr, nullptr, 0, 0.0, 0.0, (hipStream_t)stream});
 }
 
 int dg_adjoint_rk_stage(dg_ctx *c, int stage, const double *dt, const double *u, const double *lam,
                         const double *acc, double *lam_out, double *acc_out, void *stream) {
-  (void)stage; (void)dt; (void)u; (void)lam; (void)acc; (void)lam_out; (void)acc_out; (void)stream;
-  if (!c) return DG_EINVAL;
-  return DG_EUNSUPPORTED;
+  if (!c || !dt || !u || !lam || !lam_out || stage < 1 || stage > 3) return DG_EINVAL;
+  if (lam_out == lam || lam_out == u || (acc && lam_out == acc)) return DG_EINVAL;
+  if (stage != 3 && !acc) return DG_EINVAL;
+  if (stage != 1 && !acc_out) return DG_EINVAL;
+  if (acc_out && (acc_out == lam || acc_out == u || acc_out == lam_out)) return DG_EINVAL;
+  const int mode = stage == 3 ? 3 : stage == 2 ? 2 : 1;
+  const double ca = stage == 3 ? 1.0 / 3.0 : 0.75;
+  const double cb = stage == 3 ? 2.0 / 3.0 : 0.25;
+  return dispatch(c, AdjointLaunch{c, u, lam, acc, lam_out, acc_out, dt, mode, ca, cb, (hipStream_t)stream});
 }
 
 int dg_status(dg_ctx *c, void *stream) {

@@ -1,6 +1,16 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
-same seeded inputs.  FP64 tolerance: relative L1 <= 1e-12 per conserved
-variable (sum |w_gpu - w_oracle| / sum |w_oracle| over all modes and cells)."""
+same seeded inputs.
+
+FP64 tolerances:
+  * states (after an RK stage, a step, a trajectory, the limiters): relative
+    L1 <= 1e-12 per conserved variable, sum |w_gpu - w_oracle| / sum |w_oracle|
+    over all modes and cells (a variable that is zero in exact arithmetic is
+    measured against 1e-6 of the largest variable's norm);
+  * the right-hand side L = fac (V - S) alone: sum |L_gpu - L_oracle| <= 1e-12
+    sum fac (|V| + |S|) per variable.  L is a difference of two nearly equal
+    integrals in smooth flow, so its rounding error scales with |V| + |S|, not
+    with |L|; this bound states that (about 1e4 unit roundoffs of the terms).
+"""
 import sys
 
 import numpy as np
@@ -26,7 +36,17 @@ def _host(t):
 def rel_l1(got, ref):
     got = np.asarray(got).reshape(got.shape[0], -1)
     ref = np.asarray(ref).reshape(ref.shape[0], -1)
-    return np.abs(got - ref).sum(axis=1) / np.maximum(np.abs(ref).sum(axis=1), 1e-300)
+    norm = np.abs(ref).sum(axis=1)
+    return np.abs(got - ref).sum(axis=1) / np.maximum(norm, 1e-6 * norm.max())
+
+
+def rhs_err(L, V, S):
+    """Per-variable error of L against the oracle's V - S, relative to |V| + |S|."""
+    nv = V.shape[0]
+    L = np.asarray(L).reshape(nv, -1)
+    V = V.reshape(nv, -1)
+    S = S.reshape(nv, -1)
+    return np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
 
 
 def _solver(wl):
@@ -76,18 +96,37 @@ def _wl(spec):
     return workloads.workload(name, **spec)
 
 
+def _inputs(o, case, wl):
+    w0 = o.initial_state()
+    if wl["ic"] in ("blast", "sod"):
+        # discontinuous data: the unlimited projection undershoots; use the
+        # limited state, positive at every face node
+        lim = oracle.Oracle(dict(wl, limiter=1, positivity=1))
+        w0, st = lim.limit(w0)
+        assert st == 0
+    return [w0, _rough(o, seed=len(case))]
+
+
 @pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
 def test_rhs_matches_oracle(case, spec):
     _say("case", case)
     wl = _wl(spec)
     o = oracle.Oracle(wl)
     s = _solver(wl)
-    for w in (o.initial_state(), _rough(o, seed=len(case))):
-        L_ref = o.rhs(w)
+    for w in _inputs(o, case, wl):
+        V, S = o.terms_cells(w)
         L = _host(s.rhs(_dev(w)))
-        err = rel_l1(L, L_ref)
-        _say(case, "rhs rel-L1", err)
+        err = rhs_err(L, V, S)
+        _say(case, "rhs error / (|V|+|S|)", err, "rel-L1 to L", rel_l1(L, (V - S).reshape(L.shape)))
         assert np.all(err <= TOL), err
+        # a stage from the same input: state-level relative L1
+        dt = 0.5 * o.max_dt(w)
+        ref = o.rk3_stage(1, dt, w, w)
+        dtd = _dev(np.array([dt]))
+        got = _host(s.rk_stage(1, dtd, None, _dev(w)))
+        serr = rel_l1(got, ref)
+        _say(case, "stage-1 state rel-L1", serr)
+        assert np.all(serr <= TOL), serr
     assert s.status() == 0
 
 
@@ -150,20 +189,30 @@ def test_vortex_trajectory_matches_oracle_reduced():
 
 
 def test_full_size_vortex_stage_sampled():
-    # 256^2, k=2 (the benchmark workload): one RHS on the GPU, checked on a
-    # seeded sample of cells that the oracle evaluates one by one, plus the
-    # global conservation property of the whole RHS.
+    # 256^2, k=2 (the benchmark workload): the RHS and a full stage on the
+    # GPU, checked on a seeded sample of cells that the oracle evaluates one
+    # by one, plus the global conservation property of the whole RHS.
     wl = workloads.workload("vortex")
     o = oracle.Oracle(wl)
     s = _solver(wl)
     w0 = o.initial_state()
-    L = _host(s.rhs(_dev(w0))).reshape(o.nvar, o.N, -1)
+    d0 = _dev(w0)
+    L = _host(s.rhs(d0)).reshape(o.nvar, o.N, -1)
+    dt = s.max_dt(d0)
+    dt_h = float(_host(dt)[0])
+    assert dt_h == pytest.approx(o.max_dt(w0), rel=1e-14)
+    u1 = _host(s.rk_stage(1, dt, None, d0)).reshape(o.nvar, o.N, -1)
     rng = np.random.default_rng(2024)
     cells = np.unique(np.concatenate([rng.integers(0, o.ncell, 3000), [0, 255, o.ncell - 256, o.ncell - 1]]))
-    ref = o.rhs_cells(w0, cells)
-    err = rel_l1(L[:, :, cells], ref)
-    _say("full-size sampled rhs rel-L1", err)
+    V, S = o.terms_cells(w0, cells)
+    err = rhs_err(L[:, :, cells], V, S)
+    _say("full-size sampled rhs error / (|V|+|S|)", err)
     assert np.all(err <= TOL), err
+    w0c = w0.reshape(o.nvar, o.N, -1)[:, :, cells]
+    ref = w0c + dt_h * o.rhs_cells(w0, cells)
+    serr = rel_l1(u1[:, :, cells], ref)
+    _say("full-size sampled stage-1 state rel-L1", serr)
+    assert np.all(serr <= TOL), serr
     tot = L[:, 0, :].sum(axis=1)
     scale = np.abs(L[:, 0, :]).sum(axis=1)
     assert np.all(np.abs(tot) <= 1e-13 * scale)
