@@ -94,6 +94,88 @@ def cpu_baseline(wl, budget_s: float = 12.0):
                       f"state, single-threaded C oracle, {el:.1f} s"}
 
 
+def time_steps(s, wl, steps, warmup, graph=True):
+    """Time `steps` SSP-RK3 steps (time step + 3 stages [+ limiters]) of the
+    workload on solver `s`; returns ms per step.  The state is built by the
+    library's projection (and limited first if the workload limits)."""
+    import torch
+    A = build_state(s, wl)
+    if s.limited:
+        s.limit(A)
+    B = s.empty()
+    u1, u2, dtbuf = s.empty(), s.empty(), s.scalar()
+    stream = torch.cuda.current_stream()
+
+    def two_steps():
+        s.step(A, [u1, u2, B, dtbuf])
+        s.step(B, [u1, u2, A, dtbuf])
+
+    steps = steps + (steps % 2)
+    for _ in range((warmup + 1) // 2):
+        two_steps()
+    torch.cuda.synchronize()
+    g = None
+    if graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            two_steps()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            two_steps()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // 2):
+        g.replay() if g is not None else two_steps()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = s.status()
+    if st != 0:
+        raise RuntimeError(f"device error flag {st} in {wl['name']}")
+    return el / steps * 1e3, A
+
+
+def variants():
+    """The other figures of the metric: FP32 vs FP64, the 3D limited
+    workload, and the adjoint/forward time ratio."""
+    import torch
+    import paper_1506_06140_amd as dg
+    from paper_1506_06140_amd import adjoint
+    out = {}
+    for name, steps in (("vortex", 400), ("kh3d", 10)):
+        wl = workloads.workload(name)
+        for prec in ("fp64", "fp32"):
+            s = dg.Solver(wl, prec)
+            ms, _ = time_steps(s, wl, steps, 4)
+            out[f"{name}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": s.ncell * s.N * 3 / (ms * 1e-3),
+                                     "cells": s.ncell, "k": wl["k"], "dim": wl["dim"],
+                                     "limited": bool(s.limited)}
+            del s
+            torch.cuda.empty_cache()
+    # adjoint: 512^2, k=3, J = int rho^2 after 400 steps at fixed dt, checkpoint 20
+    wl = workloads.workload("vortex_adjoint")
+    s = dg.Solver(wl)
+    w0 = build_state(s, wl)
+    dt = s.max_dt(w0)
+    nsteps, ck = wl["steps"], wl["checkpoint"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x = w0.clone().requires_grad_(True)
+    wT = adjoint.trajectory(s, x, nsteps, dt, ck)
+    J = adjoint.density_square_integral(s, wT)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out["adjoint_vortex512_k3"] = {"forward_s": t1 - t0, "backward_s": t2 - t1,
+                                   "adjoint_over_forward": (t2 - t1) / (t1 - t0), "steps": nsteps,
+                                   "checkpoint": ck, "J": float(J.detach())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -101,6 +183,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
+    ap.add_argument("--variants", type=int, default=1, help="also time FP32, the 3D workload and the adjoint")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
@@ -200,6 +283,8 @@ def main():
                      "kernel": "k_rhs_stage<2,2>", "kernel_ms": k_ms,
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if args.variants:
+        rec["variants"] = variants()
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -60,5 +60,6 @@ struct dg_ctx {
   double *partial = nullptr; // per-block maxima of the time-step reduction
   int npartial = 0;
   int *flag = nullptr;       // sticky device error flag
+  unsigned *counter = nullptr; // blocks finished in the time-step reduction
   int device = 0;
 };

@@ -66,18 +66,47 @@ __device__ inline long neighbour(const Grid &g, int ix, int iy, int iz, int a, i
   return ((long)i[2] * g.ny + i[1]) * g.nx + i[0];
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates plus
+// Newton steps (within an ulp or two; the IEEE-rounded division and square
+// root expand into much longer dependent sequences).  Used by the Riemann
+// solver and the volume flux.
+__device__ inline double vrcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ inline double vrsq(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  // y <- y (3 - x y^2) / 2, twice
+  double h = 0.5 * x;
+  double t = fma(-h, y * y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-h, y * y, 0.5);
+  return fma(y, t, y);
+}
+__device__ inline float vrcp(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+__device__ inline float vrsq(float x) {
+  float y = __builtin_amdgcn_rsqf(x);
+  return fmaf(y, fmaf(-0.5f * x, y * y, 0.5f), y);
+}
+
 // Euler flux f_a(U) (eq. flux_vectors; 2D drops the third velocity).
-template <int D>
-__device__ inline void euler_flux(const double *U, int a, double gm1, double *F) {
-  const double ir = 1.0 / U[0];
-  double ke = 0.0;
+template <int D, class R>
+__device__ inline void euler_flux(const R *U, int a, R gm1, R *F) {
+  const R ir = vrcp(U[0]);
+  R ke = R(0);
 #pragma unroll
   for (int b = 0; b < D; ++b) ke = fma(U[1 + b], U[1 + b] * ir, ke);
-  const double p = gm1 * (U[D + 1] - 0.5 * ke);
-  const double va = U[1 + a] * ir;
+  const R p = gm1 * (U[D + 1] - R(0.5) * ke);
+  const R va = U[1 + a] * ir;
   F[0] = U[1 + a];
 #pragma unroll
-  for (int b = 0; b < D; ++b) F[1 + b] = fma(U[1 + b], va, b == a ? p : 0.0);
+  for (int b = 0; b < D; ++b) F[1 + b] = fma(U[1 + b], va, b == a ? p : R(0));
   F[D + 1] = (U[D + 1] + p) * va;
 }
 
@@ -89,6 +118,11 @@ __device__ inline double vsqrt(double a) { return sqrt(a); }
 __device__ inline double vmin(double a, double b) { return b < a ? b : a; }
 __device__ inline double vmax(double a, double b) { return b > a ? b : a; }
 __device__ inline double val(double a) { return a; }
+__device__ inline float vfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline float vsqrt(float a) { return sqrtf(a); }
+__device__ inline float vmin(float a, float b) { return b < a ? b : a; }
+__device__ inline float vmax(float a, float b) { return b > a ? b : a; }
+__device__ inline double val(float a) { return a; }
 
 // Dual number a + b eps (eps^2 = 0): value and one directional derivative.
 struct Dual {
@@ -114,6 +148,14 @@ __device__ inline Dual vsqrt(Dual a) {
   return Dual{r, r > 0.0 ? 0.5 * a.d / r : 0.0};
 }
 __device__ inline Dual vmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
+__device__ inline Dual vrcp(Dual a) {
+  const double r = vrcp(a.v);
+  return Dual{r, -r * r * a.d};
+}
+__device__ inline Dual vrsq(Dual a) {
+  const double y = vrsq(a.v);
+  return Dual{y, -0.5 * y * y * y * a.d};
+}
 __device__ inline Dual vmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
 __device__ inline double val(Dual a) { return a.v; }
 
@@ -123,6 +165,8 @@ template <>
 __device__ inline double cst<double>(double x) { return x; }
 template <>
 __device__ inline Dual cst<Dual>(double x) { return mkd(x); }
+template <>
+__device__ inline float cst<float>(double x) { return (float)x; }
 
 // HLLC numerical flux in +a between traces UL (low side) and UR (high side),
 // in the compact form F = F_K + S_K^(-/+) (U*_K - U_K) with K = L if S* >= 0
@@ -131,28 +175,39 @@ __device__ inline Dual cst<Dual>(double x) { return mkd(x); }
 // bounds: Einfeldt-Batten (Roe-averaged) or Davis.
 template <class T, int D>
 __device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis, T *F) {
-  const double gm1 = g - 1.0;
-  const T one = cst<T>(1.0), zero = cst<T>(0.0);
-  const T irL = one / UL[0], irR = one / UR[0];
-  T vL[D], vR[D], keL = zero, keR = zero;
+  // The normal axis a may be a run-time value: components are picked with
+  // unrolled compares (no dynamic register indexing).  One reciprocal square
+  // root per side gives sqrt(rho) and 1/rho.
+  const T gm1 = cst<T>(g - 1.0), gg = cst<T>(g), half = cst<T>(0.5);
+  const T zero = cst<T>(0.0);
+  const T rsL = vrsq(UL[0]), rsR = vrsq(UR[0]);
+  const T irL = rsL * rsL, irR = rsR * rsR;
+  T vL[D], vR[D], keL = zero, keR = zero, uL = zero, uR = zero, mL = zero, mR = zero;
 #pragma unroll
   for (int b = 0; b < D; ++b) {
     vL[b] = UL[1 + b] * irL;
     vR[b] = UR[1 + b] * irR;
     keL = vfma(UL[1 + b], vL[b], keL);
     keR = vfma(UR[1 + b], vR[b], keR);
+    if (b == a) {
+      uL = vL[b];
+      uR = vR[b];
+      mL = UL[1 + b];
+      mR = UR[1 + b];
+    }
   }
-  const T pL = gm1 * (UL[D + 1] - 0.5 * keL);
-  const T pR = gm1 * (UR[D + 1] - 0.5 * keR);
-  const T cL = vsqrt(g * pL * irL), cR = vsqrt(g * pR * irR);
-  const T uL = vL[a], uR = vR[a];
+  const T pL = gm1 * (UL[D + 1] - half * keL);
+  const T pR = gm1 * (UR[D + 1] - half * keR);
+  // c = sqrt(g p / rho) = g p rsq(g p rho)
+  const T gpL = gg * pL, gpR = gg * pR;
+  const T cL = gpL * vrsq(gpL * UL[0]), cR = gpR * vrsq(gpR * UR[0]);
   T SL, SR;
   if (davis) {
     SL = vmin(uL - cL, uR - cR);
     SR = vmax(uL + cL, uR + cR);
   } else {
-    const T sL = vsqrt(UL[0]), sR = vsqrt(UR[0]);
-    const T is = one / (sL + sR);
+    const T sL = UL[0] * rsL, sR = UR[0] * rsR;
+    const T is = vrcp(sL + sR);
     T q2 = zero, ut = zero;
 #pragma unroll
     for (int b = 0; b < D; ++b) {
@@ -162,32 +217,35 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis
     }
     const T HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
     const T Ht = (sL * HL + sR * HR) * is;
-    const T ct2 = gm1 * (Ht - 0.5 * q2);
-    const T ct = val(ct2) > 0.0 ? vsqrt(ct2) : zero;
+    const T ct2 = gm1 * (Ht - half * q2);
+    const T ct = val(ct2) > 0.0 ? ct2 * vrsq(ct2) : zero;
     SL = vmin(uL - cL, ut - ct);
     SR = vmax(uR + cR, ut + ct);
   }
   const T dL = SL - uL, dR = SR - uR;
-  const T Ss = (pR - pL + UL[1 + a] * dL - UR[1 + a] * dR) / (UL[0] * dL - UR[0] * dR);
+  const T Ss = (pR - pL + mL * dL - mR * dR) * vrcp(UL[0] * dL - UR[0] * dR);
   const bool left = val(Ss) >= 0.0;
-  const T *U = left ? UL : UR;
+  T U[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) U[v] = left ? UL[v] : UR[v];
   const T SK = left ? SL : SR;
   const T SKc = left ? vmin(SL, zero) : vmax(SR, zero);
-  const T rK = U[0], irK = left ? irL : irR, pK = left ? pL : pR;
-  const T uK = left ? uL : uR, dK = left ? dL : dR;
+  const T irK = left ? irL : irR, pK = left ? pL : pR;
+  const T uK = left ? uL : uR, dK = left ? dL : dR, mK = left ? mL : mR;
   T FK[D + 2];
   // physical flux of the selected side
-  FK[0] = U[1 + a];
+  FK[0] = mK;
 #pragma unroll
   for (int b = 0; b < D; ++b) FK[1 + b] = vfma(U[1 + b], uK, b == a ? pK : zero);
   FK[D + 1] = (U[D + 1] + pK) * uK;
   // star state rho_K (S_K - u_K)/(S_K - S*) (1, S* n + v_t, E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))))
-  const T fac = rK * dK / (SK - Ss);
+  const T rd = U[0] * dK;
+  const T fac = rd * vrcp(SK - Ss);
   T Us[D + 2];
   Us[0] = fac;
 #pragma unroll
   for (int b = 0; b < D; ++b) Us[1 + b] = fac * (b == a ? Ss : U[1 + b] * irK);
-  Us[D + 1] = fac * (U[D + 1] * irK + (Ss - uK) * (Ss + pK / (rK * dK)));
+  Us[D + 1] = fac * (U[D + 1] * irK + (Ss - uK) * (Ss + pK * vrcp(rd)));
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) F[v] = vfma(SKc, Us[v] - U[v], FK[v]);
 }
@@ -197,11 +255,14 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis
 // mode 0: out = L;  mode 1: stage 1 (out = w + dt L);  mode 2: stages 2, 3
 // (out = ca wn + cb (w + dt L)).
 // ---------------------------------------------------------------------------
-template <int D, int K>
-__global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const double *__restrict__ w,
-                                                   const double *__restrict__ wn, double *__restrict__ out,
-                                                   const double *__restrict__ dtp, Grid g, int mode, double ca,
-                                                   double cb, int *__restrict__ flag) {
+template <int D, int K, class R>
+__global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const R *__restrict__ tabr,
+                                                   const double *__restrict__ w, const double *__restrict__ wn,
+                                                   double *__restrict__ out, const double *__restrict__ dtp, Grid g,
+                                                   int mode, double ca, double cb, int *__restrict__ flag) {
+  // R is the type of the contractions and fluxes (double, or float for the
+  // mixed-precision path); the lift of the cell mean and the stage update are
+  // always FP64.
   using C = Cfg<D, K>;
   const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= g.ncell) return;
@@ -209,41 +270,44 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
   const int ix = (int)(cell % g.nx);
   const int iy = (int)((cell / g.nx) % g.ny);
   const int iz = (int)(cell / ((long)g.nx * g.ny));
-  const double gm1 = g.gamma - 1.0;
+  const R gm1 = (R)(g.gamma - 1.0);
 
-  double wc[C::NV][C::N];
+  R wc[C::NV][C::N];
 #pragma unroll
   for (int v = 0; v < C::NV; ++v)
 #pragma unroll
-    for (int l = 0; l < C::N; ++l) wc[v][l] = w[(long)(v * C::N + l) * nc + cell];
+    for (int l = 0; l < C::N; ++l) wc[v][l] = (R)w[(long)(v * C::N + l) * nc + cell];
 
-  double acc[C::NV][C::N];
+  R acc[C::NV][C::N];  // modes l >= 1
+  double acc0[C::NV];  // mode 0 (the cell mean), FP64
 #pragma unroll
-  for (int v = 0; v < C::NV; ++v)
+  for (int v = 0; v < C::NV; ++v) {
+    acc0[v] = 0.0;
 #pragma unroll
-    for (int l = 0; l < C::N; ++l) acc[v][l] = 0.0;
+    for (int l = 0; l < C::N; ++l) acc[v][l] = R(0);
+  }
 
-  // volume integral (eq. dg_term2)
+  // volume integral (eq. dg_term2); dphi_1 = 0, so it never touches mode 0
 #pragma unroll 1
   for (int q = 0; q < C::Q; ++q) {
-    double U[C::NV];
-    const double *bq = tab + C::B + q * C::N;
+    R U[C::NV];
+    const R *bq = tabr + C::B + q * C::N;
 #pragma unroll
     for (int v = 0; v < C::NV; ++v) {
-      double s = 0.0;
+      R s = R(0);
 #pragma unroll
       for (int l = 0; l < C::N; ++l) s = fma(wc[v][l], bq[l], s);
       U[v] = s;
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      double F[C::NV];
-      euler_flux<D>(U, a, gm1, F);
-      const double *dw = tab + C::DW + (a * C::Q + q) * C::N;
+      R F[C::NV];
+      euler_flux<D, R>(U, a, gm1, F);
+      const R *dw = tabr + C::DW + (a * C::Q + q) * C::N;
 #pragma unroll
       for (int v = 0; v < C::NV; ++v)
 #pragma unroll
-        for (int l = 0; l < C::N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+        for (int l = 1; l < C::N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
     }
   }
 
@@ -256,20 +320,21 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
     for (int s = 0; s < 2; ++s) {
       const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
       const long src = nb >= 0 ? nb : cell;
-      double wb[C::NV][C::N];
+      R wb[C::NV][C::N];
 #pragma unroll
       for (int v = 0; v < C::NV; ++v)
 #pragma unroll
-        for (int l = 0; l < C::N; ++l) wb[v][l] = w[(long)(v * C::N + l) * nc + src];
-      const double *to = tab + C::TF + (a * 2 + s) * C::QF * C::N;
-      const double *tn = tab + C::TF + (a * 2 + (1 - s)) * C::QF * C::N;
-      const double *tw = tab + C::TW + (a * 2 + s) * C::QF * C::N;
+        for (int l = 0; l < C::N; ++l) wb[v][l] = (R)w[(long)(v * C::N + l) * nc + src];
+      const R *to = tabr + C::TF + (a * 2 + s) * C::QF * C::N;
+      const R *tn = tabr + C::TF + (a * 2 + (1 - s)) * C::QF * C::N;
+      const R *tw = tabr + C::TW + (a * 2 + s) * C::QF * C::N;
+      const double *tw0 = tab + C::TW + (a * 2 + s) * C::QF * C::N;
 #pragma unroll 1
       for (int r = 0; r < C::QF; ++r) {
-        double Uo[C::NV], Un[C::NV], UL[C::NV], UR[C::NV], F[C::NV];
+        R Uo[C::NV], Un[C::NV], UL[C::NV], UR[C::NV], F[C::NV];
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) {
-          double so = 0.0, sn = 0.0;
+          R so = R(0), sn = R(0);
 #pragma unroll
           for (int l = 0; l < C::N; ++l) {
             so = fma(wc[v][l], to[r * C::N + l], so);
@@ -280,39 +345,270 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
           UL[v] = s ? Uo[v] : Un[v];
           UR[v] = s ? Un[v] : Uo[v];
         }
-        hllc<double, D>(UL, UR, a, g.gamma, g.davis, F);
+        hllc<R, D>(UL, UR, a, g.gamma, g.davis, F);
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) {
-          const double f = s ? -F[v] : F[v];
+          const R f = s ? -F[v] : F[v];
+          acc0[v] = fma((double)f, tw0[r * C::N], acc0[v]);
 #pragma unroll
-          for (int l = 0; l < C::N; ++l) acc[v][l] = fma(f, tw[r * C::N + l], acc[v][l]);
+          for (int l = 1; l < C::N; ++l) acc[v][l] = fma(f, tw[r * C::N + l], acc[v][l]);
         }
       }
     }
   }
 
   bool bad = false;
-  if (mode == 0) {
+  const double dt = (mode == 0) ? 0.0 : *dtp;
 #pragma unroll
-    for (int v = 0; v < C::NV; ++v)
+  for (int v = 0; v < C::NV; ++v)
 #pragma unroll
-      for (int l = 0; l < C::N; ++l) {
-        const double L = g.fac * acc[v][l];
-        bad |= (L != L);
-        out[(long)(v * C::N + l) * nc + cell] = L;
-      }
-  } else {
-    const double dt = *dtp;
-#pragma unroll
-    for (int v = 0; v < C::NV; ++v)
-#pragma unroll
-      for (int l = 0; l < C::N; ++l) {
-        const long i = (long)(v * C::N + l) * nc + cell;
-        const double L = g.fac * acc[v][l];
-        bad |= (L != L);
-        const double o = wc[v][l] + dt * L;
+    for (int l = 0; l < C::N; ++l) {
+      const long i = (long)(v * C::N + l) * nc + cell;
+      const double L = g.fac * (l == 0 ? acc0[v] : (double)acc[v][l]);
+      bad |= (L != L);
+      if (mode == 0) {
+        out[i] = L;
+      } else {
+        const double o = w[i] + dt * L;
         out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
       }
+    }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// ---------------------------------------------------------------------------
+// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.
+//
+// In 2D there are four conserved variables and a workgroup owns a TX x TY
+// tile of cells with four adjacent lanes per cell (lane = 4 cell + sub), so a
+// 256^2 grid still gives four waves per SIMD to hide the latency of the
+// FP64 divisions and square roots of the flux evaluations.
+//   P0  weights of the tile and its one-cell halo (no corners) into LDS with
+//       coalesced row loads, all in flight together;
+//   P1  every face of the tile once: the (face, node) tasks are spread over
+//       the whole workgroup; each forms both traces from LDS, calls the HLLC
+//       solver and stores the flux in LDS;
+//   P2  the volume integral: the (k+1)^2 nodes of a cell are split over its
+//       four lanes, and a reduce-scatter across the four lanes (DPP quad
+//       permutations, no LDS) leaves lane `sub` with variable `sub`;
+//   P3  after a barrier each lane lifts the four face fluxes of its
+//       variable and applies the stage update to it.
+// A face on a tile boundary is evaluated by both tiles with identical code
+// and inputs, so the two cells receive bitwise-opposite contributions.
+// ---------------------------------------------------------------------------
+template <int K>
+struct Tile2D;
+template <>
+struct Tile2D<1> { static constexpr int TX = 16, TY = 16; };
+template <>
+struct Tile2D<2> { static constexpr int TX = 16, TY = 16; };
+template <>
+struct Tile2D<3> { static constexpr int TX = 16, TY = 8; };
+
+// Exchange of a value with the lane `sub ^ 1` or `sub ^ 2` of the same quad
+// (DPP quad permutation, no LDS traffic).
+template <int CTRL>
+__device__ inline double quad_swap(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const int lo2 = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  const int hi2 = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi2, lo2);
+}
+template <int CTRL>
+__device__ inline float quad_swap(float x) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+
+template <int K, class R>
+__global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
+    const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
+    const double *__restrict__ wn, double *__restrict__ out, const double *__restrict__ dtp, Grid g, int mode,
+    double ca, double cb, int *__restrict__ flag) {
+  // R: type of the contractions and fluxes (double, or float in the mixed
+  // path); the lift of the cell mean and the stage update are FP64.
+  using C = Cfg<2, K>;
+  constexpr int TX = Tile2D<K>::TX, TY = Tile2D<K>::TY, NCELL = TX * TY, NT = 4 * NCELL;
+  constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N;
+  static_assert(NV == 4, "four lanes per cell carry the four 2D variables");
+  constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
+  constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;  // x- and y-faces of the tile
+  constexpr int NTASK = (NFX + NFY) * QF;
+  __shared__ R sw[NW * HC];
+  __shared__ R sf[(NFX + NFY) * QF * NV];  // [face][node][var]
+
+  const int tid = threadIdx.x;
+  const int cidx = tid >> 2, sub = tid & 3;
+  const int tx = cidx % TX, ty = cidx / TX;
+  // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
+  // XCD b mod 8).  Give each XCD a contiguous band of tiles so that the halo
+  // rows it re-reads stay in its own L2: a bijection for any tile count.
+  const int ntx = (g.nx + TX - 1) / TX;
+  const int ntiles = gridDim.x;
+  const int xcd = blockIdx.x % 8, j = blockIdx.x / 8;
+  const int q8 = ntiles / 8, r8 = ntiles % 8;
+  const int tile = xcd * q8 + min(xcd, r8) + j;
+  const int bx0 = (tile % ntx) * TX, by0 = (tile / ntx) * TY;
+  const long nc = g.ncell;
+  const int nxt = min(TX, g.nx - bx0), nyt = min(TY, g.ny - by0);
+
+  // P0: tile and halo weights into LDS (periodic wrap; transmissive ghosts are
+  // resolved at the faces)
+  for (int i = tid; i < NW * HC; i += NT) {
+    const int h = i % HC, vl = i / HC;
+    const int lx = h % HX - 1, ly = h / HX - 1;
+    if ((lx < 0 || lx >= TX) && (ly < 0 || ly >= TY)) continue;
+    int gx = (bx0 + lx) % g.nx, gy = (by0 + ly) % g.ny;
+    gx = gx < 0 ? gx + g.nx : gx;
+    gy = gy < 0 ? gy + g.ny : gy;
+    sw[i] = (R)w[(long)vl * nc + (long)gy * g.nx + gx];
+  }
+  __syncthreads();
+
+  // P1: face-node tasks.  x-face (fx, fy) lies between halo cells
+  // (fx, fy+1) and (fx+1, fy+1); y-face (fx, fy) between (fx+1, fy) and
+  // (fx+1, fy+1).
+  const bool tr_x = g.bc[0] == DG_BC_TRANSMISSIVE, tr_y = g.bc[1] == DG_BC_TRANSMISSIVE;
+  for (int t = tid; t < NTASK; t += NT) {
+    const int f = t / QF, r = t % QF;
+    int a, pl, ph;
+    bool ghost_lo, ghost_hi;
+    if (f < NFX) {
+      const int fy = f / (TX + 1), fx = f % (TX + 1);
+      a = 0;
+      pl = (fy + 1) * HX + fx;
+      ph = pl + 1;
+      const int gxl = bx0 + fx - 1;  // global x of the low cell
+      ghost_lo = tr_x && gxl < 0;
+      ghost_hi = tr_x && gxl >= g.nx - 1;
+    } else {
+      const int f2 = f - NFX;
+      const int fy = f2 / TX, fx = f2 % TX;
+      a = 1;
+      pl = fy * HX + fx + 1;
+      ph = pl + HX;
+      const int gyl = by0 + fy - 1;
+      ghost_lo = tr_y && gyl < 0;
+      ghost_hi = tr_y && gyl >= g.ny - 1;
+    }
+    const R *tlo = tabr + C::TF + ((a * 2 + 1) * QF + r) * N;  // low cell at xi_a = +1
+    const R *thi = tabr + C::TF + ((a * 2 + 0) * QF + r) * N;  // high cell at xi_a = -1
+    R UL[NV], UR[NV], F[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R sl = R(0), sh = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        sl = fma(sw[(v * N + l) * HC + pl], tlo[l], sl);
+        sh = fma(sw[(v * N + l) * HC + ph], thi[l], sh);
+      }
+      UL[v] = ghost_lo ? sh : sl;
+      UR[v] = ghost_hi ? sl : sh;
+    }
+    hllc<R, 2>(UL, UR, a, g.gamma, g.davis, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sf[t * NV + v] = F[v];
+  }
+
+  // P2: volume integral (eq. dg_term2) over the nodes q = sub, sub+4, ...;
+  // dphi_1 = 0, so mode 0 receives nothing
+  const int own = (ty + 1) * HX + (tx + 1);
+  const bool real = tx < nxt && ty < nyt;
+  R acc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc[v][l] = R(0);
+  {
+    R wc[NV][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int l = 0; l < N; ++l) wc[v][l] = sw[(v * N + l) * HC + own];
+    const R gm1 = (R)(g.gamma - 1.0);
+#pragma unroll 1
+    for (int q = sub; q < Q; q += 4) {
+      const R *bq = tabr + C::B + q * N;
+      R U[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R s = R(0);
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(wc[v][l], bq[l], s);
+        U[v] = s;
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        R F[NV];
+        euler_flux<2, R>(U, a, gm1, F);
+        const R *dw = tabr + C::DW + (a * Q + q) * N;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int l = 1; l < N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+      }
+    }
+  }
+  // reduce-scatter over the quad: lane sub keeps variable sub
+  R part[2][N];
+  {
+    const bool hi2 = sub & 2;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int l = 1; l < N; ++l) {
+        const R keep = hi2 ? acc[2 + j][l] : acc[j][l];
+        const R send = hi2 ? acc[j][l] : acc[2 + j][l];
+        part[j][l] = keep + quad_swap<kQuadXor2>(send);
+      }
+  }
+  R accv[N];
+  accv[0] = R(0);
+  {
+    const bool hi1 = sub & 1;
+#pragma unroll
+    for (int l = 1; l < N; ++l) {
+      const R keep = hi1 ? part[1][l] : part[0][l];
+      const R send = hi1 ? part[0][l] : part[1][l];
+      accv[l] = keep + quad_swap<kQuadXor1>(send);
+    }
+  }
+  __syncthreads();
+  if (!real) return;
+
+  // P3: lift the four face fluxes of variable `sub` (eq. dg_term3) and update;
+  // the mean is lifted in FP64
+  const int v = sub;
+  const int fidx[4] = {ty * (TX + 1) + tx, ty * (TX + 1) + tx + 1, NFX + ty * TX + tx, NFX + (ty + 1) * TX + tx};
+  double acc0 = 0.0;
+#pragma unroll
+  for (int f = 0; f < 4; ++f) {
+    const int a = f >> 1, side = f & 1;  // side 0: low face (xi_a = -1), 1: high face
+#pragma unroll
+    for (int r = 0; r < QF; ++r) {
+      const R *tw = tabr + C::TW + ((a * 2 + side) * QF + r) * N;
+      const R F = sf[(fidx[f] * QF + r) * NV + v];
+      const R fv = side ? -F : F;
+      acc0 = fma((double)fv, tab[C::TW + ((a * 2 + side) * QF + r) * N], acc0);
+#pragma unroll
+      for (int l = 1; l < N; ++l) accv[l] = fma(fv, tw[l], accv[l]);
+    }
+  }
+  const long cell = (long)(by0 + ty) * g.nx + (bx0 + tx);
+  bool bad = false;
+  const double dt = (mode == 0) ? 0.0 : *dtp;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const long i = (long)(v * N + l) * nc + cell;
+    const double L = g.fac * (l == 0 ? acc0 : (double)accv[l]);
+    bad |= (L != L);
+    if (mode == 0) {
+      out[i] = L;
+    } else {
+      const double o = w[i] + dt * L;
+      out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
+    }
   }
   if (bad) atomicOr(flag, FLAG_NAN);
 }
@@ -571,8 +867,12 @@ __device__ inline double block_max(double x) {
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long nc, int N, double gamma, double dx,
-                                              double *__restrict__ partial, int *__restrict__ flag) {
+__global__ __launch_bounds__(256) void k_dt(const double *__restrict__ w, long nc, int N, double gamma, double dx,
+                                            double cfl_fk, double *partial, unsigned *counter,
+                                            double *__restrict__ dt, int *__restrict__ flag) {
+  // max over cells of sum_a (|v_a| + c)/dx of the cell mean; the last block to
+  // finish reduces the per-block maxima, writes dt = CFL f_k / max and resets
+  // the counter for the next launch
   double m = 0.0;
   bool bad = false;
   for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += (long)gridDim.x * blockDim.x) {
@@ -592,15 +892,24 @@ __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
-  if (threadIdx.x == 0) partial[blockIdx.x] = m;
-}
-
-__global__ __launch_bounds__(256) void k_dt_final(const double *__restrict__ partial, int n, double cfl_fk,
-                                                  double *__restrict__ dt) {
-  double m = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, partial[i]);
-  m = block_max(m);
-  if (threadIdx.x == 0) dt[0] = cfl_fk / m;
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(partial + blockIdx.x, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned done = atomicAdd(counter, 1u);
+    last = (done == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  double r = 0.0;
+  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
+    r = fmax(r, __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  r = block_max(r);
+  if (threadIdx.x == 0) {
+    dt[0] = cfl_fk / r;
+    atomicExch(counter, 0u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -829,12 +1138,24 @@ struct StageLaunch {
   int mode;
   double ca, cb;
   hipStream_t s;
-  template <int D, int K>
-  int run() {
-    hipLaunchKernelGGL((dg::k_rhs_stage<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, wn, out, dt,
-                       make_grid(c), mode, ca, cb, c->flag);
+  template <int D, int K, class R>
+  int launch(const R *tabr) {
+    if constexpr (D == 2) {
+      using T = dg::Tile2D<K>;
+      dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
+      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
+                         make_grid(c), mode, ca, cb, c->flag);
+    } else {
+      hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
+                         wn, out, dt, make_grid(c), mode, ca, cb, c->flag);
+    }
     HIP_TRY(hipGetLastError());
     return DG_OK;
+  }
+  template <int D, int K>
+  int run() {
+    if (c->cfg.precision == DG_FP32) return launch<D, K, float>(c->tab32);
+    return launch<D, K, double>(c->tab);
   }
 };
 
@@ -911,7 +1232,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   }
   if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return DG_EINVAL;
   if (cfg->flux != DG_HLLC_BATTEN && cfg->flux != DG_HLLC_DAVIS) return DG_EINVAL;
-  if (cfg->precision != DG_FP64) return DG_EUNSUPPORTED;
+  if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_EUNSUPPORTED;
   if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD) return DG_EUNSUPPORTED;
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
@@ -961,6 +1282,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->partial, c->npartial * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->flag, sizeof(int))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->counter, sizeof(unsigned))) != hipSuccess) return fail(e);
   std::vector<float> t32(nt);
   for (size_t i = 0; i < nt; ++i) t32[i] = (float)c->host_tab[i];
   if ((e = hipMemcpy(c->tab, c->host_tab.data(), nt * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
@@ -968,6 +1290,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMemcpy(c->tab32, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   int zero = 0;
   if ((e = hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if ((e = hipMemcpy(c->counter, &zero, sizeof(unsigned), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   *out = c;
   return DG_OK;
 }
@@ -978,6 +1301,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->tab32) (void)hipFree(c->tab32);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
+  if (c->counter) (void)hipFree(c->counter);
   delete c;
 }
 
@@ -1032,13 +1356,11 @@ int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
   if (!c || !w || !dt) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   if (c->sh.d == 2)
-    hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                       c->dx, c->partial, c->flag);
+    hipLaunchKernelGGL(dg::k_dt<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma, c->dx,
+                       c->cfl_fk, c->partial, c->counter, dt, c->flag);
   else
-    hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                       c->dx, c->partial, c->flag);
-  HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(kBlock), 0, s, c->partial, c->npartial, c->cfl_fk, dt);
+    hipLaunchKernelGGL(dg::k_dt<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma, c->dx,
+                       c->cfl_fk, c->partial, c->counter, dt, c->flag);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }

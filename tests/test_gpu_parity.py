@@ -4,8 +4,9 @@ same seeded inputs.
 FP64 tolerances:
   * states (after an RK stage, a step, a trajectory, the limiters): relative
     L1 <= 1e-12 per conserved variable, sum |w_gpu - w_oracle| / sum |w_oracle|
-    over all modes and cells (a variable that is zero in exact arithmetic is
-    measured against 1e-6 of the largest variable's norm);
+    over all modes and cells (a variable whose norm is below 1% of the largest
+    variable's norm, e.g. a momentum that vanishes in exact arithmetic, is
+    measured against that 1%);
   * the right-hand side L = fac (V - S) alone: sum |L_gpu - L_oracle| <= 1e-12
     sum fac (|V| + |S|) per variable.  L is a difference of two nearly equal
     integrals in smooth flow, so its rounding error scales with |V| + |S|, not
@@ -37,7 +38,7 @@ def rel_l1(got, ref):
     got = np.asarray(got).reshape(got.shape[0], -1)
     ref = np.asarray(ref).reshape(ref.shape[0], -1)
     norm = np.abs(ref).sum(axis=1)
-    return np.abs(got - ref).sum(axis=1) / np.maximum(norm, 1e-6 * norm.max())
+    return np.abs(got - ref).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
 
 
 def rhs_err(L, V, S):
@@ -100,11 +101,15 @@ def _inputs(o, case, wl):
     w0 = o.initial_state()
     if wl["ic"] in ("blast", "sod"):
         # discontinuous data: the unlimited projection undershoots; use the
-        # limited state, positive at every face node
-        lim = oracle.Oracle(dict(wl, limiter=1, positivity=1))
+        # limited state, positive at every face node.  The floor is 1e-3, not
+        # the run's 1e-10: at a 1e-10 floor the face-node densities come from
+        # cancellation of O(1) terms and carry ~1e-6 relative rounding in any
+        # implementation, which the 1e-12 bound cannot resolve.
+        lim = oracle.Oracle(dict(wl, limiter=1, positivity=1, eps=1e-3))
         w0, st = lim.limit(w0)
         assert st == 0
-    return [w0, _rough(o, seed=len(case))]
+    # random high modes scaled by 1/N keep every face-node density positive
+    return [w0, _rough(o, seed=len(case), amp=0.2 / o.N)]
 
 
 @pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
