@@ -86,6 +86,14 @@ def _load():
             "orc_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
             "orc_limit": [cp, dp],
             "orc_positivity_points": [cp, dp],
+            "orc_amr_sizes": [cp, lp],
+            "orc_amr_node_coords": [cp, dp],
+            "orc_amr_project": [cp, dp, dp],
+            "orc_amr_rhs": [cp, dp, dp],
+            "orc_amr_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
+            "orc_amr_max_dt": [cp, dp, dp],
+            "orc_amr_limit": [cp, dp],
+            "orc_refine_matrix": [cp, C.c_int, dp],
         }
         for name, args in sig.items():
             f = getattr(_lib, name)
@@ -359,3 +367,103 @@ class Oracle:
         rho_ex = workloads.primitives(wl, X, Y, Z, t=t)[0]
         err = np.abs(u[:, :, 0] - rho_ex)
         return float((err * wq[None, :]).sum() / (2.0 ** d) / self.ncell)
+
+
+class AmrOracle(Oracle):
+    """The oracle on a base grid with a static 2:1 refined box (Sec. 4).
+
+    State: coarse block [nvar][N][ncoarse] (base grid, hole cells ignored)
+    followed by the fine block [nvar][N][nfine], as one flat array."""
+
+    def __init__(self, wl: dict):
+        super().__init__(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)))
+        self.wl = dict(wl)
+        self.c.refine_lo[:] = list(wl["refine_lo"])
+        self.c.refine_hi[:] = list(wl["refine_hi"])
+        lib, _ = _load()
+        sz = np.zeros(5, dtype=np.int64)
+        _check(lib.orc_amr_sizes(C.byref(self.c), sz), "amr_sizes")
+        self.ncoarse, self.nfine = int(sz[0]), int(sz[1])
+        self.nf = tuple(int(x) for x in sz[2:5])
+        self.size = self.nvar * self.N * (self.ncoarse + self.nfine)
+        self.shape = (self.size,)
+        self.dxf = 0.5 * self.dx
+        d = self.dim
+        lo, hi = wl["refine_lo"], wl["refine_hi"]
+        n = wl["n"]
+        self.hole = np.zeros(self.ncoarse, dtype=bool)
+        cid = np.arange(self.ncoarse)
+        idx = [cid % n[0], (cid // n[0]) % n[1], cid // (n[0] * n[1])]
+        inside = np.ones(self.ncoarse, dtype=bool)
+        for a in range(d):
+            inside &= (idx[a] >= lo[a]) & (idx[a] < hi[a])
+        self.hole = inside
+
+    def blocks(self, w):
+        """(coarse [nvar][N][ncoarse], fine [nvar][N][nfine]) views of a state."""
+        w = np.asarray(w).reshape(-1)
+        nc = self.nvar * self.N * self.ncoarse
+        return (w[:nc].reshape(self.nvar, self.N, self.ncoarse),
+                w[nc:].reshape(self.nvar, self.N, self.nfine))
+
+    def node_coords(self):
+        lib, _ = _load()
+        x = np.zeros((self.ncoarse + self.nfine, self.Q, 3))
+        _check(lib.orc_amr_node_coords(C.byref(self.c), x), "amr_node_coords")
+        return x
+
+    def initial_state(self, t: float = 0.0):
+        lib, _ = _load()
+        x = self.node_coords()
+        nct = self.ncoarse + self.nfine
+        cell = np.repeat(np.arange(nct), self.Q).reshape(nct, self.Q)
+        node = np.tile(np.arange(self.Q), nct).reshape(nct, self.Q)
+        wl = dict(self.wl); wl["nq"] = self.Q
+        prim = np.ascontiguousarray(np.stack(workloads.primitives(wl, x[..., 0], x[..., 1], x[..., 2],
+                                                                  cell=cell, node=node, t=t), axis=-1))
+        w = np.zeros(self.size)
+        _check(lib.orc_amr_project(C.byref(self.c), prim, w), "amr_project")
+        return w
+
+    def rhs(self, w):
+        lib, _ = _load()
+        L = np.zeros(self.size)
+        _check(lib.orc_amr_rhs(C.byref(self.c), self._s(w), L), "amr_rhs")
+        return L
+
+    def max_dt(self, w):
+        lib, _ = _load()
+        dt = np.zeros(1)
+        _check(lib.orc_amr_max_dt(C.byref(self.c), self._s(w), dt), "amr_max_dt")
+        return float(dt[0])
+
+    def rk3_stage(self, stage, dt, wn, wp):
+        lib, _ = _load()
+        out = np.zeros(self.size)
+        _check(lib.orc_amr_rk3_stage(C.byref(self.c), stage, dt, self._s(wn), self._s(wp), out), "amr_rk3")
+        return out
+
+    def limit(self, w):
+        lib, _ = _load()
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_amr_limit(C.byref(self.c), out)
+        return out, st
+
+    def totals(self, w):
+        """Domain integrals of the conserved variables (hole cells excluded)."""
+        wc, wf = self.blocks(w)
+        d = self.dim
+        tc = wc[:, 0, ~self.hole].sum(axis=1) * self.dx ** d
+        tf = wf[:, 0, :].sum(axis=1) * self.dxf ** d
+        return tc + tf
+
+    def _s(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
+        assert w.size == self.size
+        return w
+
+    def refine_matrix(self, child: int):
+        lib, _ = _load()
+        P = np.zeros((self.N, self.N))
+        _check(lib.orc_refine_matrix(C.byref(self.c), child, P), "refine_matrix")
+        return P

@@ -720,10 +720,11 @@ static double minmod_b(double a, double b, double c, double bound) {
  * changes, the component keeps only its mean and the limited slopes.
  * `nbm` gives the neighbour means: nbm[(2a+s)*nvar*ncell + i*ncell + cell],
  * s = 0 the low (west/south/bottom) neighbour, s = 1 the high one. */
-static void slope_limit(const ctx *X, double *w, const double *nbm, const double *dxc) {
+static void slope_limit(const ctx *X, double *w, const double *nbm, const double *dxc, const unsigned char *skip) {
   long nc = X->ncell;
   const double r3 = sqrt(3.0);
   for (long cell = 0; cell < nc; ++cell) {
+    if (skip && skip[cell]) continue;
     double bound = X->c.mtilde * dxc[cell];
     for (int i = 0; i < X->nvar; ++i) {
       double mean = W(i, 0, cell);
@@ -791,11 +792,13 @@ static double tau_root(const ctx *X, const double *Ub, const double *Uq) {
  * individual cells are passed as (xcnt[cell], xphi) (the coarse side of
  * hanging faces, Sec. 4.4), nx_pts per cell with basis values xphi[cell][..][N].
  * Returns the number of cells whose mean density or mean pressure is <= eps. */
-static long positivity_limit(const ctx *X, double *w, const int *xcnt, const double *xphi, int xmax) {
+static long positivity_limit(const ctx *X, double *w, const int *xcnt, const double *xphi, int xmax,
+                             const unsigned char *skip) {
   long bad = 0;
   int d = X->d, nv = X->nvar;
   double eps = X->c.eps;
   for (long cell = 0; cell < X->ncell; ++cell) {
+    if (skip && skip[cell]) continue;
     double Ub[MAXV];
     for (int v = 0; v < nv; ++v) Ub[v] = W(v, 0, cell);
     double pb = pressure(X, Ub);
@@ -859,10 +862,10 @@ int orc_limit(const orc_config *c, double *w) {
     double *dxc = malloc(sizeof(double) * X->ncell);
     for (long i = 0; i < X->ncell; ++i) dxc[i] = X->dx;
     uniform_neighbour_means(X, w, nbm);
-    slope_limit(X, w, nbm, dxc);
+    slope_limit(X, w, nbm, dxc, NULL);
     free(nbm); free(dxc);
   }
-  if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0);
+  if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0, NULL);
   free(X);
   return bad ? ORC_ENEGATIVE : ORC_OK;
 }
@@ -888,6 +891,473 @@ int orc_positivity_points(const orc_config *c, double *xi) {
   }
   free(X);
   return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Static 2:1 refined box (Sec. 4 hanging-face quadrature, Sec. 4.4)         */
+/*                                                                            */
+/* The base grid n[] is the coarse block; the base cells in [lo, hi) are a    */
+/* hole covered by a fine block of 2(hi - lo) cells per axis with half the    */
+/* edge length.  State layout: coarse block [nvar][N][ncoarse] (hole cells    */
+/* present, ignored) followed by the fine block [nvar][N][nfine].            */
+/* A coarse face next to the fine block is integrated with the quadrature     */
+/* points of the 2^(d-1) fine faces covering it: the coarse trace is taken at */
+/* the mapped coordinates (eta + sigma)/2 and the flux is lifted into the     */
+/* coarse cell with weight w_r / 2^(d-1).                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  ctx Xc, Xf;            /* tables with the coarse / fine block geometry      */
+  int lo[3], hi[3];
+  long nf[3];
+  long ncc, ncf;
+  int nsub;              /* 2^(d-1) fine faces per coarse face               */
+  double phiH[3][2][4][MAXQF][MAXN]; /* coarse basis at hanging-face nodes   */
+  double cmean[8][MAXN]; /* mean of phi_l over child subcell c (first row of P_c) */
+} amr;
+
+static int amr_init(const orc_config *c, amr *M) {
+  int st = ctx_init(c, &M->Xc);
+  if (st != ORC_OK) return st;
+  int d = M->Xc.d;
+  for (int a = 0; a < 3; ++a) { M->lo[a] = c->refine_lo[a]; M->hi[a] = c->refine_hi[a]; M->nf[a] = 1; }
+  long nb[3] = {M->Xc.nx, M->Xc.ny, M->Xc.nz};
+  for (int a = 0; a < d; ++a) {
+    if (M->lo[a] < 1 || M->hi[a] > nb[a] - 1 || M->hi[a] <= M->lo[a]) return ORC_EINVAL;
+    M->nf[a] = 2L * (M->hi[a] - M->lo[a]);
+  }
+  M->Xf = M->Xc;
+  M->Xf.nx = M->nf[0]; M->Xf.ny = M->nf[1]; M->Xf.nz = (d == 3) ? M->nf[2] : 1;
+  M->Xf.ncell = M->Xf.nx * M->Xf.ny * M->Xf.nz;
+  M->Xf.dx = 0.5 * M->Xc.dx;
+  for (int a = 0; a < 3; ++a) M->Xf.c.bc[a] = 0;
+  M->ncc = M->Xc.ncell; M->ncf = M->Xf.ncell;
+  M->nsub = 1 << (d - 1);
+  const ctx *X = &M->Xc;
+  for (int a = 0; a < d; ++a) {
+    int t[2]; tangential(d, a, t);
+    for (int s = 0; s < 2; ++s)
+      for (int sub = 0; sub < M->nsub; ++sub)
+        for (int r = 0; r < X->Qf; ++r) {
+          int ir[2] = {r % X->n1, r / X->n1};
+          double xi[3] = {0, 0, 0};
+          xi[a] = s ? 1.0 : -1.0;
+          for (int j = 0; j < d - 1; ++j) {
+            double sig = ((sub >> j) & 1) ? 1.0 : -1.0;
+            xi[t[j]] = 0.5 * (X->gx[ir[j]] + sig);
+          }
+          for (int l = 0; l < X->N; ++l) M->phiH[a][s][sub][r][l] = phi_at(X, l, xi);
+        }
+  }
+  /* child means: 2^-d int phi_l((xi + c)/2) dxi with (k+1)^d Gauss points */
+  for (int ch = 0; ch < (1 << d); ++ch)
+    for (int l = 0; l < X->N; ++l) {
+      double acc = 0.0;
+      for (int q = 0; q < X->Q; ++q) {
+        int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+        double xi[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) xi[a] = 0.5 * (X->gx[iq[a]] + (((ch >> a) & 1) ? 1.0 : -1.0));
+        acc += phi_at(X, l, xi) * X->wV[q];
+      }
+      M->cmean[ch][l] = acc / (double)(1 << d);
+    }
+  return ORC_OK;
+}
+
+static void unflat(const ctx *X, long cell, long *i) {
+  i[0] = cell % X->nx; i[1] = (cell / X->nx) % X->ny; i[2] = cell / (X->nx * X->ny);
+}
+static long flat(const ctx *X, const long *i) { return (i[2] * X->ny + i[1]) * X->nx + i[0]; }
+
+static int amr_in_hole(const amr *M, const long *i) {
+  for (int a = 0; a < M->Xc.d; ++a)
+    if (i[a] < M->lo[a] || i[a] >= M->hi[a]) return 0;
+  return 1;
+}
+
+/* coarse base-cell neighbour index along a (periodic), or -1 at a transmissive wall */
+static int amr_coarse_nb(const amr *M, const long *i, int a, int dir, long *j) {
+  long n[3] = {M->Xc.nx, M->Xc.ny, M->Xc.nz};
+  for (int b = 0; b < 3; ++b) j[b] = i[b];
+  j[a] += dir;
+  if (j[a] < 0 || j[a] >= n[a]) {
+    if (M->Xc.c.bc[a] == 1) return -1;
+    j[a] = (j[a] + n[a]) % n[a];
+  }
+  return 0;
+}
+
+static void amr_state(const ctx *X, const double *wb, long cell, const double *ph, double *U) {
+  for (int v = 0; v < X->nvar; ++v) {
+    double s = 0.0;
+    for (int l = 0; l < X->N; ++l) s += wb[((long)v * X->N + l) * X->ncell + cell] * ph[l];
+    U[v] = s;
+  }
+}
+
+/* Surface term of a coarse cell, hanging faces included. */
+static void amr_surface_coarse(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN]) {
+  const ctx *X = &M->Xc, *Y = &M->Xf;
+  int d = X->d;
+  for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
+  long i[3]; unflat(X, cell, i);
+  for (int a = 0; a < d; ++a) {
+    int t[2]; tangential(d, a, t);
+    for (int s = 0; s < 2; ++s) {
+      long j[3];
+      int wall = amr_coarse_nb(M, i, a, s ? 1 : -1, j);
+      if (wall == 0 && amr_in_hole(M, j)) {
+        for (int sub = 0; sub < M->nsub; ++sub) {
+          long fi[3] = {0, 0, 0};
+          fi[a] = 2 * (j[a] - M->lo[a]) + (s ? 0 : 1);
+          for (int q = 0; q < d - 1; ++q) fi[t[q]] = 2 * (j[t[q]] - M->lo[t[q]]) + ((sub >> q) & 1);
+          long fcell = flat(Y, fi);
+          for (int r = 0; r < X->Qf; ++r) {
+            double Uc[MAXV], Uf[MAXV], F[MAXV];
+            amr_state(X, wc, cell, M->phiH[a][s][sub][r], Uc);
+            amr_state(Y, wf, fcell, Y->phiF[a][1 - s][r], Uf);
+            if (s) hllc(X, Uc, Uf, a, F); else hllc(X, Uf, Uc, a, F);
+            for (int v = 0; v < X->nvar; ++v)
+              for (int l = 0; l < X->N; ++l) {
+                double tt = F[v] * M->phiH[a][s][sub][r][l] * X->wF[r] / (double)M->nsub;
+                if (s) S[v][l] += tt; else S[v][l] -= tt;
+              }
+          }
+        }
+      } else {
+        long nb = wall ? -1 : flat(X, j);
+        for (int r = 0; r < X->Qf; ++r) {
+          double Uo[MAXV], Un[MAXV], F[MAXV];
+          amr_state(X, wc, cell, X->phiF[a][s][r], Uo);
+          if (nb >= 0) amr_state(X, wc, nb, X->phiF[a][1 - s][r], Un);
+          else for (int v = 0; v < X->nvar; ++v) Un[v] = Uo[v];
+          if (s) hllc(X, Uo, Un, a, F); else hllc(X, Un, Uo, a, F);
+          for (int v = 0; v < X->nvar; ++v)
+            for (int l = 0; l < X->N; ++l) {
+              double tt = F[v] * X->phiF[a][s][r][l] * X->wF[r];
+              if (s) S[v][l] += tt; else S[v][l] -= tt;
+            }
+        }
+      }
+    }
+  }
+}
+
+/* Surface term of a fine cell: neighbours outside the fine block are coarse. */
+static void amr_surface_fine(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN]) {
+  const ctx *X = &M->Xc, *Y = &M->Xf;
+  int d = Y->d;
+  for (int v = 0; v < Y->nvar; ++v) for (int j = 0; j < Y->N; ++j) S[v][j] = 0.0;
+  long f[3]; unflat(Y, cell, f);
+  for (int a = 0; a < d; ++a) {
+    int t[2]; tangential(d, a, t);
+    for (int s = 0; s < 2; ++s) {
+      long g2[3] = {f[0], f[1], f[2]};
+      g2[a] += s ? 1 : -1;
+      int inside = g2[a] >= 0 && g2[a] < M->nf[a];
+      for (int r = 0; r < Y->Qf; ++r) {
+        double Uo[MAXV], Un[MAXV], F[MAXV];
+        amr_state(Y, wf, cell, Y->phiF[a][s][r], Uo);
+        if (inside) {
+          amr_state(Y, wf, flat(Y, g2), Y->phiF[a][1 - s][r], Un);
+        } else {
+          long base[3] = {0, 0, 0}, j[3];
+          for (int b = 0; b < d; ++b) base[b] = M->lo[b] + f[b] / 2;
+          amr_coarse_nb(M, base, a, s ? 1 : -1, j);
+          int sub = 0;
+          for (int q = 0; q < d - 1; ++q) sub |= (int)(f[t[q]] % 2) << q;
+          amr_state(X, wc, flat(X, j), M->phiH[a][1 - s][sub][r], Un);
+        }
+        if (s) hllc(Y, Uo, Un, a, F); else hllc(Y, Un, Uo, a, F);
+        for (int v = 0; v < Y->nvar; ++v)
+          for (int l = 0; l < Y->N; ++l) {
+            double tt = F[v] * Y->phiF[a][s][r][l] * Y->wF[r];
+            if (s) S[v][l] += tt; else S[v][l] -= tt;
+          }
+      }
+    }
+  }
+}
+
+static void amr_rhs_all(const amr *M, const double *w, double *L) {
+  const double *wc = w, *wf = w + (long)M->Xc.nvar * M->Xc.N * M->ncc;
+  double *Lc = L, *Lf = L + (long)M->Xc.nvar * M->Xc.N * M->ncc;
+  int nv = M->Xc.nvar, N = M->Xc.N, d = M->Xc.d;
+  double facc = 2.0 / M->Xc.dx / (double)(1 << d), facf = 2.0 / M->Xf.dx / (double)(1 << d);
+  for (long cell = 0; cell < M->ncc; ++cell) {
+    long i[3]; unflat(&M->Xc, cell, i);
+    double V[MAXV][MAXN], S[MAXV][MAXN];
+    if (amr_in_hole(M, i)) {
+      for (int v = 0; v < nv; ++v) for (int j = 0; j < N; ++j) Lc[((long)v * N + j) * M->ncc + cell] = 0.0;
+      continue;
+    }
+    volume_term(&M->Xc, wc, cell, V);
+    amr_surface_coarse(M, wc, wf, cell, S);
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) Lc[((long)v * N + j) * M->ncc + cell] = facc * (V[v][j] - S[v][j]);
+  }
+  for (long cell = 0; cell < M->ncf; ++cell) {
+    double V[MAXV][MAXN], S[MAXV][MAXN];
+    volume_term(&M->Xf, wf, cell, V);
+    amr_surface_fine(M, wc, wf, cell, S);
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) Lf[((long)v * N + j) * M->ncf + cell] = facf * (V[v][j] - S[v][j]);
+  }
+}
+
+static long amr_state_size(const amr *M) { return (long)M->Xc.nvar * M->Xc.N * (M->ncc + M->ncf); }
+
+int orc_amr_sizes(const orc_config *c, long *out /* ncoarse, nfine, nf[3] */) {
+  amr *M = malloc(sizeof(amr));
+  if (!M) return ORC_ENOMEM;
+  int st = amr_init(c, M);
+  if (st == ORC_OK) { out[0] = M->ncc; out[1] = M->ncf; out[2] = M->nf[0]; out[3] = M->nf[1]; out[4] = M->nf[2]; }
+  free(M);
+  return st;
+}
+
+/* Projection nodes of both blocks: x[ncoarse + nfine][Q][3]. */
+int orc_amr_node_coords(const orc_config *c, double *x) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  const ctx *B[2] = {&M->Xc, &M->Xf};
+  double x0f[3];
+  for (int a = 0; a < 3; ++a) x0f[a] = c->x0[a] + M->lo[a] * M->Xc.dx;
+  long off = 0;
+  for (int b = 0; b < 2; ++b) {
+    const ctx *X = B[b];
+    for (long cell = 0; cell < X->ncell; ++cell) {
+      long i[3]; unflat(X, cell, i);
+      for (int q = 0; q < X->Q; ++q) {
+        int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+        for (int a = 0; a < 3; ++a) {
+          double v = 0.0;
+          if (a < X->d) v = (b ? x0f[a] : c->x0[a]) + (i[a] + 0.5) * X->dx + 0.5 * X->dx * X->gx[iq[a]];
+          x[((off + cell) * X->Q + q) * 3 + a] = v;
+        }
+      }
+    }
+    off += X->ncell;
+  }
+  free(M);
+  return ORC_OK;
+}
+
+/* L2 projection on both blocks (prim[ncoarse + nfine][Q][5]). */
+int orc_amr_project(const orc_config *c, const double *prim, double *w) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  const ctx *B[2] = {&M->Xc, &M->Xf};
+  long off = 0;
+  double *wb = w;
+  for (int b = 0; b < 2; ++b) {
+    const ctx *X = B[b];
+    double scale = 1.0 / (double)(1 << X->d);
+    for (long cell = 0; cell < X->ncell; ++cell) {
+      double acc[MAXV][MAXN];
+      memset(acc, 0, sizeof(acc));
+      for (int q = 0; q < X->Q; ++q) {
+        const double *pr = prim + ((off + cell) * X->Q + q) * 5;
+        double U[MAXV], ke = 0.0;
+        U[0] = pr[0];
+        for (int bb = 0; bb < X->d; ++bb) { U[1 + bb] = pr[0] * pr[1 + bb]; ke += pr[1 + bb] * pr[1 + bb]; }
+        U[X->d + 1] = pr[4] / (c->gamma - 1.0) + 0.5 * pr[0] * ke;
+        for (int v = 0; v < X->nvar; ++v)
+          for (int j = 0; j < X->N; ++j) acc[v][j] += U[v] * X->phiV[q][j] * X->wV[q];
+      }
+      for (int v = 0; v < X->nvar; ++v)
+        for (int j = 0; j < X->N; ++j) wb[((long)v * X->N + j) * X->ncell + cell] = scale * acc[v][j];
+    }
+    off += X->ncell;
+    wb += (long)X->nvar * X->N * X->ncell;
+  }
+  free(M);
+  return ORC_OK;
+}
+
+int orc_amr_rhs(const orc_config *c, const double *w, double *L) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st == ORC_OK) amr_rhs_all(M, w, L);
+  free(M);
+  return st;
+}
+
+int orc_amr_rk3_stage(const orc_config *c, int stage, double dt, const double *wn, const double *wp, double *out) {
+  if (stage < 1 || stage > 3) return ORC_EINVAL;
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  long n = amr_state_size(M);
+  double *L = malloc(sizeof(double) * n);
+  amr_rhs_all(M, wp, L);
+  rk3_combine(stage, dt, wn, wp, L, out, n);
+  free(L); free(M);
+  return ORC_OK;
+}
+
+/* Time step over both blocks, each cell with its own edge length. */
+int orc_amr_max_dt(const orc_config *c, const double *w, double *dt_out) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  double fk = 1.0 / (2.0 * M->Xc.k + 1.0);
+  if (c->positivity && M->Xc.lw[0] / 2.0 < fk) fk = M->Xc.lw[0] / 2.0;
+  double dt = INFINITY;
+  const ctx *B[2] = {&M->Xc, &M->Xf};
+  const double *wb = w;
+  for (int b = 0; b < 2; ++b) {
+    const ctx *X = B[b];
+    for (long cell = 0; cell < X->ncell; ++cell) {
+      long i[3]; unflat(X, cell, i);
+      if (b == 0 && amr_in_hole(M, i)) continue;
+      double U[MAXV];
+      for (int v = 0; v < X->nvar; ++v) U[v] = wb[((long)v * X->N) * X->ncell + cell];
+      double p = pressure(X, U);
+      double cs = sqrt(c->gamma * p / U[0]);
+      double rate = 0.0;
+      for (int a = 0; a < X->d; ++a) rate += (fabs(U[1 + a] / U[0]) + cs) / X->dx;
+      double dtc = c->cfl * fk / rate;
+      if (dtc < dt) dt = dtc;
+    }
+    wb += (long)X->nvar * X->N * X->ncell;
+  }
+  *dt_out = dt;
+  free(M);
+  return ORC_OK;
+}
+
+/* Limiters on the refined mesh (Sec. 4.4): a coarse cell sees, across a
+ * refined face, the mean of the 2^d fine cells of that base cell; a fine cell
+ * sees, across the block boundary, the mean of the coarse polynomial over the
+ * child subcell next to it.  Coarse cells with hanging faces also check
+ * positivity at the hanging-face quadrature points. */
+int orc_amr_limit(const orc_config *c, double *w) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  const ctx *X = &M->Xc, *Y = &M->Xf;
+  int d = X->d, nv = X->nvar, N = X->N;
+  double *wc = w, *wf = w + (long)nv * N * M->ncc;
+  long bad = 0;
+  unsigned char *hole = malloc(M->ncc);
+  for (long cell = 0; cell < M->ncc; ++cell) {
+    long i[3]; unflat(X, cell, i);
+    hole[cell] = (unsigned char)amr_in_hole(M, i);
+  }
+  if (c->limiter) {
+    double *nbc = malloc(sizeof(double) * 2 * d * nv * M->ncc);
+    double *nbf = malloc(sizeof(double) * 2 * d * nv * M->ncf);
+    double *dxc = malloc(sizeof(double) * M->ncc), *dxf = malloc(sizeof(double) * M->ncf);
+    for (long i = 0; i < M->ncc; ++i) dxc[i] = X->dx;
+    for (long i = 0; i < M->ncf; ++i) dxf[i] = Y->dx;
+    for (long cell = 0; cell < M->ncc; ++cell) {
+      long i[3]; unflat(X, cell, i);
+      for (int a = 0; a < d; ++a)
+        for (int s = 0; s < 2; ++s) {
+          long j[3];
+          int wall = amr_coarse_nb(M, i, a, s ? 1 : -1, j);
+          for (int v = 0; v < nv; ++v) {
+            double m;
+            if (wall) m = wc[((long)v * N) * M->ncc + cell];
+            else if (amr_in_hole(M, j)) {
+              m = 0.0;
+              for (int ch = 0; ch < (1 << d); ++ch) {
+                long fi[3] = {0, 0, 0};
+                for (int b = 0; b < d; ++b) fi[b] = 2 * (j[b] - M->lo[b]) + ((ch >> b) & 1);
+                m += wf[((long)v * N) * M->ncf + flat(Y, fi)];
+              }
+              m /= (double)(1 << d);
+            } else m = wc[((long)v * N) * M->ncc + flat(X, j)];
+            nbc[((long)(2 * a + s) * nv + v) * M->ncc + cell] = m;
+          }
+        }
+    }
+    for (long cell = 0; cell < M->ncf; ++cell) {
+      long f[3]; unflat(Y, cell, f);
+      for (int a = 0; a < d; ++a)
+        for (int s = 0; s < 2; ++s) {
+          long g2[3] = {f[0], f[1], f[2]};
+          g2[a] += s ? 1 : -1;
+          for (int v = 0; v < nv; ++v) {
+            double m;
+            if (g2[a] >= 0 && g2[a] < M->nf[a]) {
+              m = wf[((long)v * N) * M->ncf + flat(Y, g2)];
+            } else {
+              long base[3] = {0, 0, 0}, j[3];
+              for (int b = 0; b < d; ++b) base[b] = M->lo[b] + f[b] / 2;
+              amr_coarse_nb(M, base, a, s ? 1 : -1, j);
+              int ch = 0;
+              for (int b = 0; b < d; ++b) {
+                int bit = (b == a) ? (s ? 0 : 1) : (int)(f[b] % 2);
+                ch |= bit << b;
+              }
+              m = 0.0;
+              for (int l = 0; l < N; ++l) m += wc[((long)v * N + l) * M->ncc + flat(X, j)] * M->cmean[ch][l];
+            }
+            nbf[((long)(2 * a + s) * nv + v) * M->ncf + cell] = m;
+          }
+        }
+    }
+    slope_limit(X, wc, nbc, dxc, hole);
+    slope_limit(Y, wf, nbf, dxf, NULL);
+    free(nbc); free(nbf); free(dxc); free(dxf);
+  }
+  if (c->positivity) {
+    /* extra points: coarse trace at the hanging-face nodes */
+    int xmax = 2 * d * M->nsub * X->Qf;
+    int *xcnt = calloc(M->ncc, sizeof(int));
+    double *xphi = malloc(sizeof(double) * M->ncc * xmax * N);
+    for (long cell = 0; cell < M->ncc; ++cell) {
+      if (hole[cell]) continue;
+      long i[3]; unflat(X, cell, i);
+      for (int a = 0; a < d; ++a)
+        for (int s = 0; s < 2; ++s) {
+          long j[3];
+          if (amr_coarse_nb(M, i, a, s ? 1 : -1, j) == 0 && amr_in_hole(M, j))
+            for (int sub = 0; sub < M->nsub; ++sub)
+              for (int r = 0; r < X->Qf; ++r) {
+                memcpy(xphi + ((long)cell * xmax + xcnt[cell]) * N, M->phiH[a][s][sub][r], sizeof(double) * N);
+                ++xcnt[cell];
+              }
+        }
+    }
+    bad += positivity_limit(X, wc, xcnt, xphi, xmax, hole);
+    bad += positivity_limit(Y, wf, NULL, NULL, 0, NULL);
+    free(xcnt); free(xphi);
+  }
+  free(hole);
+  free(M);
+  return bad ? ORC_ENEGATIVE : ORC_OK;
+}
+
+/* (P_c)_{j,l} = 2^-d int phi_l((xi + c)/2) phi_j(xi) dxi: the L2 projection of
+ * a coarse polynomial onto child c (eq. ref_pa_integral and App. F, with the
+ * coarse basis at the mapped point).  Out: P[N][N] row-major. */
+int orc_refine_matrix(const orc_config *c, int child, double *P) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  int d = X->d;
+  if (child < 0 || child >= (1 << d)) { free(X); return ORC_EINVAL; }
+  for (int j = 0; j < X->N; ++j)
+    for (int l = 0; l < X->N; ++l) {
+      double acc = 0.0;
+      for (int q = 0; q < X->Q; ++q) {
+        int iq[3] = {q % X->n1, (q / X->n1) % X->n1, q / (X->n1 * X->n1)};
+        double xi[3] = {0, 0, 0}, xm[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) {
+          xi[a] = X->gx[iq[a]];
+          xm[a] = 0.5 * (xi[a] + (((child >> a) & 1) ? 1.0 : -1.0));
+        }
+        acc += phi_at(X, l, xm) * phi_at(X, j, xi) * X->wV[q];
+      }
+      P[j * X->N + l] = acc / (double)(1 << d);
+    }
+  free(X);
+  return ORC_OK;
 }
 
 #else /* ORC_CS: complex-step directional derivatives */

@@ -172,6 +172,14 @@ def primitives(wl: dict, x, y, z, cell=None, node=None, t: float = 0.0):
         left = x < 0.5
         return (np.where(left, 1.0, 0.125), zeros, zeros, zeros,
                 np.where(left, 1.0, 0.1))
+    if ic == "poly_contact":
+        # a polynomial density sum_t c x^ex y^ey z^ez advected at constant
+        # velocity and pressure (a contact): exact for degree <= k
+        rho = zeros + 0.0
+        for c, ex, ey, ez in wl["poly"]:
+            rho = rho + c * x ** ex * y ** ey * z ** ez
+        vel = wl.get("velocity", (0.7, -0.4, 0.3))
+        return rho, zeros + vel[0], zeros + vel[1], zeros + vel[2], zeros + wl.get("pressure", 1.0)
     if ic == "uniform":
         rho0, vel, p0 = wl["state"]
         return (zeros + rho0, zeros + vel[0], zeros + vel[1], zeros + vel[2],
