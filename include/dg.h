@@ -79,8 +79,10 @@ typedef struct {
   double m_tilde;     /* TVB bound Mtilde; slopes |a| <= Mtilde dx kept (3.3)  */
   int positivity;     /* 1: Zhang-Shu positivity limiter (Sec. 3.4)            */
   double eps;         /* positivity floor (the paper uses about 1e-10)         */
-  int refine_lo[3];   /* reserved for a static 2:1 refined box; set equal to  */
-  int refine_hi[3];   /* refine_lo (e.g. all zero) for a uniform grid          */
+  int refine_lo[3];   /* static 2:1 refined box: the base cells [lo, hi) per   */
+  int refine_hi[3];   /* axis are covered by 2(hi-lo) fine cells per axis of   */
+                      /* half the edge (Sec. 4); lo == hi (e.g. all zero) for  */
+                      /* a uniform grid.  Requires 1 <= lo < hi <= n-1.        */
 } dg_config;
 
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton
@@ -93,8 +95,20 @@ int dg_init(const dg_config *cfg, dg_ctx **out);
 int dg_state_size(const dg_ctx *ctx, int64_t *n_fp64);
 
 /* Sizes: out[0..5] = nvar, N, Q (volume nodes), Qf (face nodes), cells, nS
- * (positivity check points per cell). */
+ * (positivity check points per cell).  With a refined box, cells counts
+ * both blocks. */
 int dg_sizes(const dg_ctx *ctx, int64_t out[6]);
+
+/* Refined-box geometry: out[0] = cells of the coarse block (the base grid,
+ * hole included), out[1] = cells of the fine block, out[2..4] = fine block
+ * cells per axis (0 without a refined box).  With a refined box a state is
+ * the coarse block [nvar][N][coarse cells] followed by the fine block
+ * [nvar][N][fine cells]; the hole cells of the coarse block are ignored.
+ * Coarse faces next to the fine block are integrated at the Gauss points of
+ * the fine faces that cover them (Sec. 4, hanging faces); the limiters use
+ * the projected neighbour means of Sec. 4.4.  The adjoint calls return
+ * DG_EUNSUPPORTED with a refined box. */
+int dg_amr_sizes(const dg_ctx *ctx, int64_t out[5]);
 
 /* Reference coordinates of the (k+1)^dim Gauss volume nodes, xi[Q][3]
  * (x index fastest; unused axes 0), and their weights w[Q] (host memory). */
@@ -102,7 +116,8 @@ int dg_quadrature(const dg_ctx *ctx, double *xi, double *w);
 
 /* L2 projection of initial data (Sec. 2.3): prim is a device array
  * [5][Q][cells] of primitive values (rho, v_x, v_y, v_z, p) at the Gauss
- * volume nodes of every cell; w receives the state. */
+ * volume nodes of every cell (with a refined box: the coarse block's cells,
+ * then the fine block's); w receives the state. */
 int dg_project(dg_ctx *ctx, const double *prim, double *w, void *stream);
 
 /* L = dw/dt = -R_K of eq. spatial_discretisation for every cell: volume

@@ -94,6 +94,7 @@ def _load():
             "orc_amr_max_dt": [cp, dp, dp],
             "orc_amr_limit": [cp, dp],
             "orc_refine_matrix": [cp, C.c_int, dp],
+            "orc_amr_terms": [cp, dp, dp, dp],
         }
         for name, args in sig.items():
             f = getattr(_lib, name)
@@ -461,6 +462,13 @@ class AmrOracle(Oracle):
         w = np.ascontiguousarray(w, dtype=np.float64).reshape(-1)
         assert w.size == self.size
         return w
+
+    def terms_cells(self, w, cells=None):
+        """(fac V, fac S) of every cell of both blocks, flat like the state."""
+        lib, _ = _load()
+        V = np.zeros(self.size); S = np.zeros(self.size)
+        _check(lib.orc_amr_terms(C.byref(self.c), self._s(w), V, S), "amr_terms")
+        return V, S
 
     def refine_matrix(self, child: int):
         lib, _ = _load()

@@ -1105,6 +1105,41 @@ static void amr_rhs_all(const amr *M, const double *w, double *L) {
   }
 }
 
+/* fac V and fac S of every cell of both blocks (hole cells zero), so that
+ * L = V - S; their magnitudes are the conditioning scale of the RHS. */
+int orc_amr_terms(const orc_config *c, const double *w, double *Vo, double *So) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  const double *wc = w, *wf = w + (long)M->Xc.nvar * M->Xc.N * M->ncc;
+  int nv = M->Xc.nvar, N = M->Xc.N, d = M->Xc.d;
+  long off = (long)nv * N * M->ncc;
+  double facc = 2.0 / M->Xc.dx / (double)(1 << d), facf = 2.0 / M->Xf.dx / (double)(1 << d);
+  for (long cell = 0; cell < M->ncc; ++cell) {
+    long i[3]; unflat(&M->Xc, cell, i);
+    double V[MAXV][MAXN], S[MAXV][MAXN];
+    int hole = amr_in_hole(M, i);
+    if (!hole) { volume_term(&M->Xc, wc, cell, V); amr_surface_coarse(M, wc, wf, cell, S); }
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) {
+        Vo[((long)v * N + j) * M->ncc + cell] = hole ? 0.0 : facc * V[v][j];
+        So[((long)v * N + j) * M->ncc + cell] = hole ? 0.0 : facc * S[v][j];
+      }
+  }
+  for (long cell = 0; cell < M->ncf; ++cell) {
+    double V[MAXV][MAXN], S[MAXV][MAXN];
+    volume_term(&M->Xf, wf, cell, V);
+    amr_surface_fine(M, wc, wf, cell, S);
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) {
+        Vo[off + ((long)v * N + j) * M->ncf + cell] = facf * V[v][j];
+        So[off + ((long)v * N + j) * M->ncf + cell] = facf * S[v][j];
+      }
+  }
+  free(M);
+  return ORC_OK;
+}
+
 static long amr_state_size(const amr *M) { return (long)M->Xc.nvar * M->Xc.N * (M->ncc + M->ncf); }
 
 int orc_amr_sizes(const orc_config *c, long *out /* ncoarse, nfine, nf[3] */) {

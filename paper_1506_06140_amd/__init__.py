@@ -40,7 +40,7 @@ class dg_config(C.Structure):
 
 
 EXPORTS = (
-    "dg_init", "dg_state_size", "dg_sizes", "dg_quadrature", "dg_project", "dg_rhs",
+    "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
     "dg_max_dt", "dg_rk_stage", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage",
     "dg_status", "dg_destroy", "dg_strerror",
 )
@@ -61,6 +61,7 @@ def load_library(path: str = LIB_PATH):
     lib.dg_init.argtypes = [C.POINTER(dg_config), C.POINTER(ctxp)]
     lib.dg_state_size.argtypes = [ctxp, C.POINTER(C.c_int64)]
     lib.dg_sizes.argtypes = [ctxp, C.POINTER(C.c_int64)]
+    lib.dg_amr_sizes.argtypes = [ctxp, C.POINTER(C.c_int64)]
     lib.dg_quadrature.argtypes = [ctxp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.dg_project.argtypes = [ctxp, dp, dp, vp]
     lib.dg_rhs.argtypes = [ctxp, dp, dp, vp]
@@ -145,6 +146,13 @@ class Solver:
         self.shape = (self.nvar, self.N, nz, wl["n"][1], wl["n"][0])
         self.dx = wl["length"][0] / wl["n"][0]
         self.size = self.nvar * self.N * self.ncell
+        az = (C.c_int64 * 5)()
+        _check(self.lib.dg_amr_sizes(self.ctx, az), "dg_amr_sizes")
+        self.ncoarse, self.nfine = int(az[0]), int(az[1])
+        self.nf = tuple(int(x) for x in az[2:5])
+        self.amr = self.nfine > 0
+        if self.amr:
+            self.shape = (self.size,)
 
     def _s(self, t) -> int:
         return _ptr(t, self.size)
@@ -172,15 +180,24 @@ class Solver:
         return xi, w
 
     def node_coords(self) -> np.ndarray:
-        """Physical coordinates [3][Q][cells] of the Gauss nodes (host)."""
+        """Physical coordinates [3][Q][cells] of the Gauss nodes (host); with a
+        refined box the coarse block's cells come first, then the fine block's."""
         xi, _ = self.quadrature()
-        nx, ny = self.wl["n"][0], self.wl["n"][1]
-        cid = np.arange(self.ncell)
-        idx = [cid % nx, (cid // nx) % ny, cid // (nx * ny)]
-        out = np.zeros((3, self.Q, self.ncell))
-        for a in range(self.wl["dim"]):
-            out[a] = self.wl["x0"][a] + (idx[a][None, :] + 0.5 + 0.5 * xi[:, a][:, None]) * self.dx
-        return out
+        blocks = [(self.wl["n"], self.wl["x0"], self.dx)]
+        if self.amr:
+            lo = self.wl["refine_lo"]
+            x0f = [self.wl["x0"][a] + lo[a] * self.dx for a in range(3)]
+            blocks.append((self.nf, x0f, 0.5 * self.dx))
+        parts = []
+        for n, x0, h in blocks:
+            nc = n[0] * n[1] * (n[2] if self.wl["dim"] == 3 else 1)
+            cid = np.arange(nc)
+            idx = [cid % n[0], (cid // n[0]) % n[1], cid // (n[0] * n[1])]
+            out = np.zeros((3, self.Q, nc))
+            for a in range(self.wl["dim"]):
+                out[a] = x0[a] + (idx[a][None, :] + 0.5 + 0.5 * xi[:, a][:, None]) * h
+            parts.append(out)
+        return np.concatenate(parts, axis=2)
 
     def project(self, prim, out=None, stream=None):
         """L2 projection of primitives prim[5][Q][cells] (device) onto the basis."""

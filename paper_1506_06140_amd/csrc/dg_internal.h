@@ -32,8 +32,12 @@ Shape make_shape(int d, int k);
 //   WQ [Q]           volume-node weights
 //   PS [NS][N]       phi_l at the positivity points
 //   XQ [Q][3]        volume-node coordinates
+//   HG [d][2][4][QF][N] coarse basis at the nodes of the 2^(d-1) fine faces
+//                    covering a coarse face (static 2:1 refinement)
+//   HW [d][2][4][QF][N] HG times the fine-face weight / 2^(d-1) (coarse lift)
+//   CM [8][N]        mean of phi_l over each child subcell
 struct Layout {
-  int B, DW, TF, TW, WQ, PS, XQ, total;
+  int B, DW, TF, TW, WQ, PS, XQ, HG, HW, CM, total;
 };
 
 Layout make_layout(const Shape &s);
@@ -57,9 +61,14 @@ struct dg_ctx {
   std::vector<double> host_tab;
   double *tab = nullptr;     // FP64 tables on the device
   float *tab32 = nullptr;    // FP32 copy
-  double *partial = nullptr; // per-block maxima of the time-step reduction
-  int npartial = 0;
+  double *partial = nullptr; // 64-bit word holding the running maximum signal rate
+  int npartial = 0;          // blocks of the time-step reduction
   int *flag = nullptr;       // sticky device error flag
-  unsigned *counter = nullptr; // blocks finished in the time-step reduction
   int device = 0;
+  // static 2:1 refined box (amr = true): base grid nx,ny,nz is the coarse
+  // block, base cells [lo, hi) are covered by the fine block of nf cells
+  bool amr = false;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  long nf[3] = {1, 1, 1};
+  long ncc = 0, ncf = 0;
 };

@@ -39,7 +39,10 @@ struct Cfg {
   static constexpr int WQ = TW + D * 2 * QF * N;
   static constexpr int PS = WQ + Q;
   static constexpr int XQ = PS + NS * N;
-  static constexpr int TOTAL = XQ + 3 * Q;
+  static constexpr int HG = XQ + 3 * Q;
+  static constexpr int HW = HG + D * 2 * 4 * QF * N;
+  static constexpr int CM = HW + D * 2 * 4 * QF * N;
+  static constexpr int TOTAL = CM + 8 * N;
 };
 
 struct Grid {
@@ -809,7 +812,9 @@ __global__ __launch_bounds__(256) void k_adjoint(const double *__restrict__ tab,
 // ---------------------------------------------------------------------------
 template <int D, int K>
 __global__ __launch_bounds__(256) void k_project(const double *__restrict__ tab, const double *__restrict__ prim,
-                                                 double *__restrict__ w, long nc, double gamma) {
+                                                 long pstride, long poff, double *__restrict__ w, long nc,
+                                                 double gamma) {
+  // prim[c][q][pstride] holds the block's cells at offset poff; w is one block
   using C = Cfg<D, K>;
   const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= nc) return;
@@ -821,7 +826,7 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ tab,
   for (int q = 0; q < C::Q; ++q) {
     double pr[5];
 #pragma unroll
-    for (int c = 0; c < 5; ++c) pr[c] = prim[((long)c * C::Q + q) * nc + cell];
+    for (int c = 0; c < 5; ++c) pr[c] = prim[((long)c * C::Q + q) * pstride + poff + cell];
     double U[C::NV];
     double ke = 0.0;
     U[0] = pr[0];
@@ -866,13 +871,14 @@ __device__ inline double block_max(double x) {
   return x;
 }
 
+// max over cells of sum_a (|v_a| + c)/dx of the cell mean: every block folds
+// its maximum into one 64-bit word with an atomic max (non-negative doubles
+// order like their bit patterns); k_dt_final then writes dt = CFL f_k / max
+// and clears the word for the next call.  The kernel boundary orders the two,
+// so no device-scope fence is needed.
 template <int D>
-__global__ __launch_bounds__(256) void k_dt(const double *__restrict__ w, long nc, int N, double gamma, double dx,
-                                            double cfl_fk, double *partial, unsigned *counter,
-                                            double *__restrict__ dt, int *__restrict__ flag) {
-  // max over cells of sum_a (|v_a| + c)/dx of the cell mean; the last block to
-  // finish reduces the per-block maxima, writes dt = CFL f_k / max and resets
-  // the counter for the next launch
+__global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long nc, int N, double gamma, double dx,
+                                              unsigned long long *ratemax, int *__restrict__ flag) {
   double m = 0.0;
   bool bad = false;
   for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += (long)gridDim.x * blockDim.x) {
@@ -892,23 +898,13 @@ __global__ __launch_bounds__(256) void k_dt(const double *__restrict__ w, long n
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
-  __shared__ bool last;
+  if (threadIdx.x == 0) atomicMax(ratemax, (unsigned long long)__double_as_longlong(m));
+}
+
+__global__ void k_dt_final(unsigned long long *ratemax, double cfl_fk, double *__restrict__ dt) {
   if (threadIdx.x == 0) {
-    __hip_atomic_store(partial + blockIdx.x, m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned done = atomicAdd(counter, 1u);
-    last = (done == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  double r = 0.0;
-  for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x)
-    r = fmax(r, __hip_atomic_load(partial + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  r = block_max(r);
-  if (threadIdx.x == 0) {
-    dt[0] = cfl_fk / r;
-    atomicExch(counter, 0u);
+    dt[0] = cfl_fk / __longlong_as_double((long long)*ratemax);
+    *ratemax = 0ull;
   }
 }
 
@@ -1064,6 +1060,446 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
     for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
 }
 
+// ---------------------------------------------------------------------------
+// Static 2:1 refined box (hanging-face quadrature of Sec. 4, limiting at the
+// refinement boundary of Sec. 4.4).  State: coarse block [nvar][N][ncc]
+// (base grid; the base cells in [lo, hi) form a hole, ignored) followed by
+// the fine block [nvar][N][ncf] (2(hi - lo) cells per axis, half the edge).
+// A coarse face next to the hole is integrated at the Gauss points of the
+// 2^(d-1) fine faces covering it: the coarse trace at (eta + sigma)/2 (table
+// HG), lifted into the coarse cell with weight w_r / 2^(d-1) (table HW).
+// Both sides evaluate the flux of a hanging node from the same traces with
+// the same code, so the contributions cancel exactly in the sum of the means.
+// One thread per cell over both blocks.
+// ---------------------------------------------------------------------------
+struct AmrGrid {
+  int n[3];    // base (coarse) grid
+  int lo[3], hi[3];
+  int nf[3];   // fine block
+  long ncc, ncf;
+  int bc[3];
+  double facc, facf, dxc, dxf;
+  double gamma;
+  int davis;
+};
+
+template <int D>
+__device__ inline bool amr_in_hole(const AmrGrid &g, const int *i) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    if (i[a] < g.lo[a] || i[a] >= g.hi[a]) return false;
+  return true;
+}
+
+// base-grid neighbour along a (periodic); false at a transmissive wall
+template <int D>
+__device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int dir, int *j) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) j[b] = i[b];
+  j[a] += dir;
+  if (j[a] < 0 || j[a] >= g.n[a]) {
+    if (g.bc[a] == DG_BC_TRANSMISSIVE) return false;
+    j[a] = j[a] < 0 ? j[a] + g.n[a] : j[a] - g.n[a];
+  }
+  return true;
+}
+
+template <int D, int K, class R>
+__global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab, const R *__restrict__ tabr,
+                                                 const double *__restrict__ w, const double *__restrict__ wn,
+                                                 double *__restrict__ out, const double *__restrict__ dtp, AmrGrid g,
+                                                 int mode, double ca, double cb, int *__restrict__ flag) {
+  using C = Cfg<D, K>;
+  constexpr int NV = C::NV, N = C::N, QF = C::QF, NW = NV * N, NSUB = 1 << (D - 1);
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.ncc + g.ncf) return;
+  const bool fine = tid >= g.ncc;
+  const long cell = fine ? tid - g.ncc : tid;
+  const long ncb = fine ? g.ncf : g.ncc;
+  const double *wcb = w, *wfb = w + (long)NW * g.ncc;
+  const double *wb = fine ? wfb : wcb;
+  const long boff = fine ? (long)NW * g.ncc : 0;
+  const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
+  int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
+  const double dt = (mode == 0) ? 0.0 : *dtp;
+  if (!fine && amr_in_hole<D>(g, i)) {
+    // hole cells carry no solution: L = 0
+#pragma unroll 1
+    for (int vl = 0; vl < NW; ++vl) {
+      const long ii = boff + (long)vl * ncb + cell;
+      out[ii] = (mode == 0) ? 0.0 : (mode == 1) ? w[ii] : ca * wn[ii] + cb * w[ii];
+    }
+    return;
+  }
+  const R gm1 = (R)(g.gamma - 1.0);
+  R wc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) wc[v][l] = (R)wb[(long)(v * N + l) * ncb + cell];
+  R acc[NV][N];
+  double acc0[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    acc0[v] = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) acc[v][l] = R(0);
+  }
+  // volume integral
+#pragma unroll 1
+  for (int q = 0; q < C::Q; ++q) {
+    R U[NV];
+    const R *bq = tabr + C::B + q * N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R s = R(0);
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(wc[v][l], bq[l], s);
+      U[v] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      R F[NV];
+      euler_flux<D, R>(U, a, gm1, F);
+      const R *dw = tabr + C::DW + (a * C::Q + q) * N;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 1; l < N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+    }
+  }
+  // faces
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int t0 = 0, t1 = 0;  // tangential axes
+    {
+      int m = 0, tt[2] = {0, 0};
+#pragma unroll
+      for (int b = 0; b < D; ++b)
+        if (b != a) tt[m++] = b;
+      t0 = tt[0];
+      t1 = tt[1];
+    }
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      // classify the neighbour: 0 regular (same block), 1 wall, 2 hanging
+      // (coarse cell facing the fine block), 3 coarse neighbour of a fine cell
+      int kind = 0;
+      long nbcell = cell;
+      const double *nbb = wb;
+      long nbn = ncb;
+      int j[3], sub = 0;
+      if (!fine) {
+        if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
+          kind = 1;
+        } else if (amr_in_hole<D>(g, j)) {
+          kind = 2;
+        } else {
+          nbcell = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+        }
+      } else {
+        int f2[3] = {i[0], i[1], i[2]};
+        f2[a] += s ? 1 : -1;
+        if (f2[a] >= 0 && f2[a] < g.nf[a]) {
+          nbcell = ((long)f2[2] * g.nf[1] + f2[1]) * g.nf[0] + f2[0];
+        } else {
+          kind = 3;
+          int base[3] = {0, 0, 0};
+#pragma unroll
+          for (int b = 0; b < D; ++b) base[b] = g.lo[b] + i[b] / 2;
+          amr_coarse_nb<D>(g, base, a, s ? 1 : -1, j);
+          nbcell = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+          nbb = wcb;
+          nbn = g.ncc;
+          sub = (i[t0] & 1) | (D == 3 ? ((i[t1] & 1) << 1) : 0);
+        }
+      }
+      const int nsub = (kind == 2) ? NSUB : 1;
+#pragma unroll 1
+      for (int sb = 0; sb < nsub; ++sb) {
+        if (kind == 2) {
+          // the fine cell of sub-face sb behind this coarse face
+          int fi[3] = {0, 0, 0};
+          fi[a] = 2 * (j[a] - g.lo[a]) + (s ? 0 : 1);
+          fi[t0] = 2 * (j[t0] - g.lo[t0]) + (sb & 1);
+          if (D == 3) fi[t1] = 2 * (j[t1] - g.lo[t1]) + ((sb >> 1) & 1);
+          nbcell = ((long)fi[2] * g.nf[1] + fi[1]) * g.nf[0] + fi[0];
+          nbb = wfb;
+          nbn = g.ncf;
+          sub = sb;
+        }
+        R wnb[NV][N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int l = 0; l < N; ++l) wnb[v][l] = (R)nbb[(long)(v * N + l) * nbn + nbcell];
+        // own and neighbour evaluation tables, and the lift table
+        const R *to = (kind == 2) ? tabr + C::HG + ((a * 2 + s) * 4 + sub) * QF * N
+                                  : tabr + C::TF + (a * 2 + s) * QF * N;
+        const R *tn = (kind == 3) ? tabr + C::HG + ((a * 2 + (1 - s)) * 4 + sub) * QF * N
+                                  : tabr + C::TF + (a * 2 + (1 - s)) * QF * N;
+        const R *tw = (kind == 2) ? tabr + C::HW + ((a * 2 + s) * 4 + sub) * QF * N
+                                  : tabr + C::TW + (a * 2 + s) * QF * N;
+        const double *tw0 = (kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + sub) * QF * N
+                                        : tab + C::TW + (a * 2 + s) * QF * N;
+#pragma unroll 1
+        for (int r = 0; r < QF; ++r) {
+          R Uo[NV], Un[NV], UL[NV], UR[NV], F[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            R so = R(0), sn = R(0);
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              so = fma(wc[v][l], to[r * N + l], so);
+              sn = fma(wnb[v][l], tn[r * N + l], sn);
+            }
+            Uo[v] = so;
+            Un[v] = (kind == 1) ? so : sn;
+            UL[v] = s ? Uo[v] : Un[v];
+            UR[v] = s ? Un[v] : Uo[v];
+          }
+          hllc<R, D>(UL, UR, a, g.gamma, g.davis, F);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const R f = s ? -F[v] : F[v];
+            acc0[v] = fma((double)f, tw0[r * N], acc0[v]);
+#pragma unroll
+            for (int l = 1; l < N; ++l) acc[v][l] = fma(f, tw[r * N + l], acc[v][l]);
+          }
+        }
+      }
+    }
+  }
+  const double fac = fine ? g.facf : g.facc;
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const long ii = boff + (long)(v * N + l) * ncb + cell;
+      const double L = fac * (l == 0 ? acc0[v] : (double)acc[v][l]);
+      bad |= (L != L);
+      if (mode == 0) {
+        out[ii] = L;
+      } else {
+        const double o = w[ii] + dt * L;
+        out[ii] = (mode == 1) ? o : ca * wn[ii] + cb * o;
+      }
+    }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// Time step over both blocks (each cell with its own edge length); same
+// two-kernel reduction as k_rate / k_dt_final.
+template <int D>
+__global__ __launch_bounds__(256) void k_rate_amr(const double *__restrict__ w, AmrGrid g, int N,
+                                                  unsigned long long *ratemax, int *__restrict__ flag) {
+  double m = 0.0;
+  bool bad = false;
+  const long ntot = g.ncc + g.ncf;
+  for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < ntot; t += (long)gridDim.x * blockDim.x) {
+    const bool fine = t >= g.ncc;
+    const long cell = fine ? t - g.ncc : t;
+    if (!fine) {
+      int i[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+      if (amr_in_hole<D>(g, i)) continue;
+    }
+    const double *wb = fine ? w + (long)(D + 2) * N * g.ncc : w;
+    const long ncb = fine ? g.ncf : g.ncc;
+    const double dx = fine ? g.dxf : g.dxc;
+    double U[D + 2];
+#pragma unroll
+    for (int v = 0; v < D + 2; ++v) U[v] = wb[(long)v * N * ncb + cell];
+    double ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
+    const double p = (g.gamma - 1.0) * (U[D + 1] - 0.5 * ke);
+    bad |= !(U[0] > 0.0) || !(p > 0.0);
+    const double c = sqrt(g.gamma * p / U[0]);
+    double rate = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
+    m = fmax(m, rate);
+  }
+  if (bad) atomicOr(flag, FLAG_NEGATIVE);
+  m = block_max(m);
+  if (threadIdx.x == 0) atomicMax(ratemax, (unsigned long long)__double_as_longlong(m));
+}
+
+// Limiters on the refined mesh: neighbour means across the refinement
+// boundary are the children's average (coarse side) or the coarse polynomial's
+// mean over the adjacent child (fine side); coarse cells facing the fine block
+// also check positivity at the hanging-face points.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ tab, double *__restrict__ w, AmrGrid g,
+                                                   int slope, double beta, double mtilde, int posit, double eps,
+                                                   int *__restrict__ flag) {
+  using C = Cfg<D, K>;
+  constexpr int NV = C::NV, N = C::N, NW = NV * N, NSUB = 1 << (D - 1);
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= g.ncc + g.ncf) return;
+  const bool fine = tid >= g.ncc;
+  const long cell = fine ? tid - g.ncc : tid;
+  const long ncb = fine ? g.ncf : g.ncc;
+  double *wcb = w, *wfb = w + (long)NW * g.ncc;
+  double *wb = fine ? wfb : wcb;
+  const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
+  int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
+  if (!fine && amr_in_hole<D>(g, i)) return;
+  double wc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) wc[v][l] = wb[(long)(v * N + l) * ncb + cell];
+  // neighbour means [2D][NV]
+  double nbm[2 * D][NV];
+  bool hang[2 * D];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      hang[2 * a + s] = false;
+      if (!fine) {
+        int j[3];
+        if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) nbm[2 * a + s][v] = wc[v][0];
+        } else if (amr_in_hole<D>(g, j)) {
+          hang[2 * a + s] = true;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double m = 0.0;
+            for (int ch = 0; ch < (1 << D); ++ch) {
+              int fi[3] = {0, 0, 0};
+#pragma unroll
+              for (int b = 0; b < D; ++b) fi[b] = 2 * (j[b] - g.lo[b]) + ((ch >> b) & 1);
+              m += wfb[(long)(v * N) * g.ncf + ((long)fi[2] * g.nf[1] + fi[1]) * g.nf[0] + fi[0]];
+            }
+            nbm[2 * a + s][v] = m / (double)(1 << D);
+          }
+        } else {
+          const long nb = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) nbm[2 * a + s][v] = wcb[(long)(v * N) * g.ncc + nb];
+        }
+      } else {
+        int f2[3] = {i[0], i[1], i[2]};
+        f2[a] += s ? 1 : -1;
+        if (f2[a] >= 0 && f2[a] < g.nf[a]) {
+          const long nb = ((long)f2[2] * g.nf[1] + f2[1]) * g.nf[0] + f2[0];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) nbm[2 * a + s][v] = wfb[(long)(v * N) * g.ncf + nb];
+        } else {
+          int base[3] = {0, 0, 0}, j[3];
+#pragma unroll
+          for (int b = 0; b < D; ++b) base[b] = g.lo[b] + i[b] / 2;
+          amr_coarse_nb<D>(g, base, a, s ? 1 : -1, j);
+          const long nb = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+          int ch = 0;
+#pragma unroll
+          for (int b = 0; b < D; ++b) ch |= ((b == a) ? (s ? 0 : 1) : (i[b] & 1)) << b;
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            double m = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) m = fma(wcb[(long)(v * N + l) * g.ncc + nb], tab[C::CM + ch * N + l], m);
+            nbm[2 * a + s][v] = m;
+          }
+        }
+      }
+    }
+  const double dx = fine ? g.dxf : g.dxc;
+  if (slope && K >= 1) {
+    const double r3 = sqrt(3.0), bound = mtilde * dx;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const double mean = wc[v][0];
+      double mt[D];
+      bool limited = false;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double A = r3 * wc[v][1 + a];
+        const double m = (fabs(A) <= bound) ? A
+                                            : minmod3(A, beta * (mean - nbm[2 * a][v]), beta * (nbm[2 * a + 1][v] - mean));
+        mt[a] = m;
+        limited |= (m != A);
+      }
+      if (limited) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) wc[v][1 + a] = mt[a] / r3;
+#pragma unroll
+        for (int l = D + 1; l < N; ++l) wc[v][l] = 0.0;
+      }
+    }
+  }
+  if (posit) {
+    double Ub[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Ub[v] = wc[v][0];
+    double keb = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) keb += Ub[1 + b] * Ub[1 + b] / Ub[0];
+    const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
+    if (!(Ub[0] > eps) || !(pb > eps)) {
+      atomicOr(flag, FLAG_NEGATIVE);
+    } else {
+      // points: the union set S, then the hanging-face points of every
+      // refined face of a coarse cell
+      const int nextra = fine ? 0 : 2 * D * NSUB * C::QF;
+      double rmin = INFINITY;
+      for (int s2 = 0; s2 < C::NS + nextra; ++s2) {
+        const double *ph;
+        if (s2 < C::NS) {
+          ph = tab + C::PS + s2 * N;
+        } else {
+          const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
+          if (!hang[f]) continue;
+          ph = tab + C::HG + (((f >> 1) * 2 + (f & 1)) * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
+        }
+        double r = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) r = fma(wc[0][l], ph[l], r);
+        rmin = fmin(rmin, r);
+      }
+      const double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
+#pragma unroll
+      for (int l = 1; l < N; ++l) wc[0][l] *= th1;
+      double th2 = 1.0;
+      for (int s2 = 0; s2 < C::NS + nextra; ++s2) {
+        const double *ph;
+        if (s2 < C::NS) {
+          ph = tab + C::PS + s2 * N;
+        } else {
+          const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
+          if (!hang[f]) continue;
+          ph = tab + C::HG + (((f >> 1) * 2 + (f & 1)) * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
+        }
+        double Uq[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double u = 0.0;
+#pragma unroll
+          for (int l = 0; l < N; ++l) u = fma(wc[v][l], ph[l], u);
+          Uq[v] = u;
+        }
+        double ke = 0.0;
+#pragma unroll
+        for (int b = 0; b < D; ++b) ke += Uq[1 + b] * Uq[1 + b] / Uq[0];
+        const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
+        if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 1; l < N; ++l) wc[v][l] *= th2;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = wc[v][l];
+}
+
 }  // namespace dg
 
 // ===========================================================================
@@ -1104,6 +1540,28 @@ dg::Grid make_grid(const dg_ctx *c) {
 
 unsigned nblocks(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+dg::AmrGrid make_amr_grid(const dg_ctx *c) {
+  dg::AmrGrid g;
+  g.n[0] = (int)c->nx;
+  g.n[1] = (int)c->ny;
+  g.n[2] = (int)c->nz;
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = c->lo[a];
+    g.hi[a] = c->hi[a];
+    g.nf[a] = (int)c->nf[a];
+    g.bc[a] = c->cfg.bc[a];
+  }
+  g.ncc = c->ncc;
+  g.ncf = c->ncf;
+  g.dxc = c->dx;
+  g.dxf = 0.5 * c->dx;
+  g.facc = 2.0 / g.dxc / (double)(1 << c->sh.d);
+  g.facf = 2.0 / g.dxf / (double)(1 << c->sh.d);
+  g.gamma = c->cfg.gamma;
+  g.davis = c->cfg.flux == DG_HLLC_DAVIS;
+  return g;
+}
+
 // Calls F::template run<D, K>() for the context's (dim, k).
 template <class F>
 int dispatch(const dg_ctx *c, F &&f) {
@@ -1124,7 +1582,8 @@ struct LayoutCheck {
     using C = Cfg<D, K>;
     const dg::Layout &l = c->lay;
     bool ok = l.B == C::B && l.DW == C::DW && l.TF == C::TF && l.TW == C::TW && l.WQ == C::WQ &&
-              l.PS == C::PS && l.XQ == C::XQ && l.total == C::TOTAL && c->sh.N == C::N && c->sh.NS == C::NS;
+              l.PS == C::PS && l.XQ == C::XQ && l.HG == C::HG && l.HW == C::HW && l.CM == C::CM && l.total == C::TOTAL &&
+              c->sh.N == C::N && c->sh.NS == C::NS;
     return ok ? DG_OK : DG_EINVAL;
   }
 };
@@ -1140,7 +1599,10 @@ struct StageLaunch {
   hipStream_t s;
   template <int D, int K, class R>
   int launch(const R *tabr) {
-    if constexpr (D == 2) {
+    if (c->amr) {
+      hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, tabr,
+                         w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
+    } else if constexpr (D == 2) {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
       hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
@@ -1166,8 +1628,17 @@ struct ProjectLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
-    hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, prim, w, c->ncell,
-                       c->cfg.gamma);
+    if (!c->amr) {
+      hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, prim, c->ncell,
+                         0L, w, c->ncell, c->cfg.gamma);
+    } else {
+      const long nt = c->ncc + c->ncf;
+      hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncc)), dim3(kBlock), 0, s, c->tab, prim, nt, 0L, w,
+                         c->ncc, c->cfg.gamma);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncf)), dim3(kBlock), 0, s, c->tab, prim, nt, c->ncc,
+                         w + (long)c->sh.nv * c->sh.N * c->ncc, c->ncf, c->cfg.gamma);
+    }
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
@@ -1179,9 +1650,15 @@ struct LimitLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
-    hipLaunchKernelGGL((dg::k_limit<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
-                       c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde * c->dx,
-                       c->cfg.positivity, c->cfg.eps, c->flag);
+    if (c->amr) {
+      hipLaunchKernelGGL((dg::k_limit_amr<D, K>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w,
+                         make_amr_grid(c), c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde,
+                         c->cfg.positivity, c->cfg.eps, c->flag);
+    } else {
+      hipLaunchKernelGGL((dg::k_limit<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
+                         c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde * c->dx,
+                         c->cfg.positivity, c->cfg.eps, c->flag);
+    }
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
@@ -1236,8 +1713,13 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD) return DG_EUNSUPPORTED;
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
-  for (int a = 0; a < 3; ++a)
-    if (cfg->refine_lo[a] != cfg->refine_hi[a]) return DG_EUNSUPPORTED;
+  bool amr = false;
+  for (int a = 0; a < cfg->dim; ++a)
+    if (cfg->refine_lo[a] != cfg->refine_hi[a]) amr = true;
+  if (amr)
+    for (int a = 0; a < cfg->dim; ++a)
+      if (cfg->refine_lo[a] < 1 || cfg->refine_hi[a] > cfg->n[a] - 1 || cfg->refine_hi[a] <= cfg->refine_lo[a])
+        return DG_EINVAL;
   const double dx = cfg->len[0] / cfg->n[0];
   for (int a = 1; a < cfg->dim; ++a)
     if (std::fabs(cfg->len[a] / cfg->n[a] - dx) > 1e-12 * dx) return DG_EINVAL;
@@ -1255,6 +1737,18 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   c->nz = cfg->dim == 3 ? cfg->n[2] : 1;
   c->ncell = c->nx * c->ny * c->nz;
   c->dx = dx;
+  if (amr) {
+    c->amr = true;
+    c->ncc = c->ncell;
+    c->ncf = 1;
+    for (int a = 0; a < cfg->dim; ++a) {
+      c->lo[a] = cfg->refine_lo[a];
+      c->hi[a] = cfg->refine_hi[a];
+      c->nf[a] = 2L * (c->hi[a] - c->lo[a]);
+      c->ncf *= c->nf[a];
+    }
+    c->ncell = c->ncc + c->ncf;  // cells of both blocks (hole cells included)
+  }
   try {
     c->host_tab = dg::build_tables(c->sh, &c->gll_w1);
   } catch (...) {
@@ -1280,9 +1774,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const size_t nt = c->host_tab.size();
   if ((e = hipMalloc((void **)&c->tab, nt * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
-  if ((e = hipMalloc((void **)&c->partial, c->npartial * sizeof(double))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->partial, sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->flag, sizeof(int))) != hipSuccess) return fail(e);
-  if ((e = hipMalloc((void **)&c->counter, sizeof(unsigned))) != hipSuccess) return fail(e);
   std::vector<float> t32(nt);
   for (size_t i = 0; i < nt; ++i) t32[i] = (float)c->host_tab[i];
   if ((e = hipMemcpy(c->tab, c->host_tab.data(), nt * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
@@ -1290,7 +1783,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMemcpy(c->tab32, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   int zero = 0;
   if ((e = hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
-  if ((e = hipMemcpy(c->counter, &zero, sizeof(unsigned), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  const unsigned long long zero64 = 0ull;
+  if ((e = hipMemcpy(c->partial, &zero64, sizeof(zero64), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   *out = c;
   return DG_OK;
 }
@@ -1301,7 +1795,6 @@ void dg_destroy(dg_ctx *c) {
   if (c->tab32) (void)hipFree(c->tab32);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
-  if (c->counter) (void)hipFree(c->counter);
   delete c;
 }
 
@@ -1319,6 +1812,14 @@ int dg_sizes(const dg_ctx *c, int64_t out[6]) {
   out[3] = c->sh.QF;
   out[4] = c->ncell;
   out[5] = c->sh.NS;
+  return DG_OK;
+}
+
+int dg_amr_sizes(const dg_ctx *c, int64_t out[5]) {
+  if (!c || !out) return DG_EINVAL;
+  out[0] = c->amr ? c->ncc : c->ncell;
+  out[1] = c->amr ? c->ncf : 0;
+  for (int a = 0; a < 3; ++a) out[2 + a] = c->amr ? c->nf[a] : 0;
   return DG_OK;
 }
 
@@ -1355,12 +1856,24 @@ int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const 
 int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
   if (!c || !w || !dt) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  if (c->sh.d == 2)
-    hipLaunchKernelGGL(dg::k_dt<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma, c->dx,
-                       c->cfl_fk, c->partial, c->counter, dt, c->flag);
-  else
-    hipLaunchKernelGGL(dg::k_dt<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma, c->dx,
-                       c->cfl_fk, c->partial, c->counter, dt, c->flag);
+  unsigned long long *rm = reinterpret_cast<unsigned long long *>(c->partial);
+  if (c->amr) {
+    if (c->sh.d == 2)
+      hipLaunchKernelGGL(dg::k_rate_amr<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
+                         c->flag);
+    else
+      hipLaunchKernelGGL(dg::k_rate_amr<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
+                         c->flag);
+  } else {
+    if (c->sh.d == 2)
+      hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                         c->dx, rm, c->flag);
+    else
+      hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                         c->dx, rm, c->flag);
+  }
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(64), 0, s, rm, c->cfl_fk, dt);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }
@@ -1373,12 +1886,14 @@ int dg_limit(dg_ctx *c, double *w, void *stream) {
 
 int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {
   if (!c || !w || !lam || !mu || mu == w || mu == lam) return DG_EINVAL;
+  if (c->amr) return DG_EUNSUPPORTED;
   return dispatch(c, AdjointLaunch{c, w, lam, nullptr, mu, nullptr, nullptr, 0, 0.0, 0.0, (hipStream_t)stream});
 }
 
 int dg_adjoint_rk_stage(dg_ctx *c, int stage, const double *dt, const double *u, const double *lam,
                         const double *acc, double *lam_out, double *acc_out, void *stream) {
   if (!c || !dt || !u || !lam || !lam_out || stage < 1 || stage > 3) return DG_EINVAL;
+  if (c->amr) return DG_EUNSUPPORTED;
   if (lam_out == lam || lam_out == u || (acc && lam_out == acc)) return DG_EINVAL;
   if (stage != 3 && !acc) return DG_EINVAL;
   if (stage != 1 && !acc_out) return DG_EINVAL;

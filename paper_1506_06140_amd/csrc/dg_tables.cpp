@@ -129,6 +129,9 @@ Layout make_layout(const Shape &s) {
   L.WQ = o; o += s.Q;
   L.PS = o; o += s.NS * s.N;
   L.XQ = o; o += 3 * s.Q;
+  L.HG = o; o += s.d * 2 * 4 * s.QF * s.N;
+  L.HW = o; o += s.d * 2 * 4 * s.QF * s.N;
+  L.CM = o; o += 8 * s.N;
   L.total = o;
   return L;
 }
@@ -208,6 +211,46 @@ std::vector<double> build_tables(const Shape &s, double *gll_w1) {
         ++p;
       }
   }
+  // hanging faces: coarse basis at (eta + sigma)/2 on each of the 2^(d-1)
+  // fine faces (sub bit j = position along the j-th tangential axis)
+  for (int a = 0; a < s.d; ++a) {
+    int tang[2], nt = 0;
+    for (int b = 0; b < s.d; ++b)
+      if (b != a) tang[nt++] = b;
+    for (int side = 0; side < 2; ++side)
+      for (int sub = 0; sub < (1 << (s.d - 1)); ++sub)
+        for (int r = 0; r < s.QF; ++r) {
+          int idx[2] = {r % s.n1, r / s.n1};
+          double xi[3] = {0.0, 0.0, 0.0};
+          xi[a] = side ? 1.0 : -1.0;
+          double wr = 1.0;
+          for (int j = 0; j < nt; ++j) {
+            xi[tang[j]] = 0.5 * (gx[idx[j]] + (((sub >> j) & 1) ? 1.0 : -1.0));
+            wr *= gw[idx[j]];
+          }
+          for (int l = 0; l < s.N; ++l) {
+            const long o2 = (((a * 2 + side) * 4 + sub) * s.QF + r) * s.N + l;
+            const double v = basis(l, xi);
+            t[L.HG + o2] = v;
+            t[L.HW + o2] = v * wr / (double)(1 << (s.d - 1));
+          }
+        }
+  }
+  // child means: 2^-d sum_q w_q phi_l((xi_q + c)/2) (exact: degree <= k)
+  for (int ch = 0; ch < (1 << s.d); ++ch)
+    for (int l = 0; l < s.N; ++l) {
+      double acc = 0.0;
+      for (int q = 0; q < s.Q; ++q) {
+        int idx[3] = {q % s.n1, (q / s.n1) % s.n1, q / (s.n1 * s.n1)};
+        double xi[3] = {0.0, 0.0, 0.0}, wq = 1.0;
+        for (int a = 0; a < s.d; ++a) {
+          xi[a] = 0.5 * (gx[idx[a]] + (((ch >> a) & 1) ? 1.0 : -1.0));
+          wq *= gw[idx[a]];
+        }
+        acc += basis(l, xi) * wq;
+      }
+      t[L.CM + ch * s.N + l] = acc / (double)(1 << s.d);
+    }
   return t;
 }
 

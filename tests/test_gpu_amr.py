@@ -1,0 +1,160 @@
+"""GPU parity on the static 2:1 refined box (hanging faces, AMR limiting)
+against the FP64 oracle; tolerances as in test_gpu_parity (states: relative L1
+<= 1e-12 per variable; the RHS: <= 1e-12 of fac(|V| + |S|))."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _per_var(o, x):
+    """Flat AMR state -> [nvar][...] (both blocks, hole cells removed)."""
+    c, f = o.blocks(x)
+    return np.concatenate([c[:, :, ~o.hole].reshape(o.nvar, -1), f.reshape(o.nvar, -1)], axis=1)
+
+
+def rel_l1(o, got, ref):
+    g, r = _per_var(o, got), _per_var(o, ref)
+    norm = np.abs(r).sum(axis=1)
+    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
+
+
+def rhs_err(o, L, V, S):
+    L, V, S = _per_var(o, L), _per_var(o, V), _per_var(o, S)
+    return np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
+
+
+def _wl(dim, k, n, lo, hi, **kw):
+    h = 1.0 / 8.0
+    base = dict(limiter=1, positivity=1, ic="blast")
+    base.update(kw)
+    return workloads.workload("blast_amr", dim=dim, k=k, n=n, length=tuple(h * m for m in n),
+                              refine_lo=lo, refine_hi=hi, **base)
+
+
+CASES = [
+    ("2d_k2", dict(dim=2, k=2, n=(10, 9, 1), lo=(2, 3, 0), hi=(7, 6, 0))),
+    ("3d_k1", dict(dim=3, k=1, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4))),
+    ("3d_k2", dict(dim=3, k=2, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4))),
+    ("3d_k3", dict(dim=3, k=3, n=(8, 8, 8), lo=(2, 2, 2), hi=(6, 6, 6))),
+]
+
+
+def _limited_state(o):
+    w = o.initial_state()
+    lim = oracle.AmrOracle(dict(o.wl, eps=1e-3))
+    w, st = lim.limit(w)
+    assert st == 0
+    return w
+
+
+@pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
+def test_amr_rhs_stage_dt_match_oracle(case, spec):
+    import paper_1506_06140_amd as dg
+    wl = _wl(**spec)
+    o = oracle.AmrOracle(wl)
+    s = dg.Solver(wl)
+    assert s.amr and s.ncoarse == o.ncoarse and s.nfine == o.nfine
+    w = _limited_state(o)
+    d = _dev(w)
+    V, S = o.terms_cells(w)
+    L = _host(s.rhs(d))
+    err = rhs_err(o, L, V, S)
+    _say(case, "AMR rhs error / (|V|+|S|)", err)
+    assert np.all(err <= TOL), err
+    dt = o.max_dt(w)
+    dtd = s.max_dt(d)
+    assert float(_host(dtd)[0]) == pytest.approx(dt, rel=1e-14)
+    ref = o.rk3_stage(1, dt, w, w)
+    got = _host(s.rk_stage(1, dtd, None, d))
+    serr = rel_l1(o, got, ref)
+    _say(case, "AMR stage-1 rel-L1", serr)
+    assert np.all(serr <= TOL), serr
+    # conservation of the GPU right-hand side across the interface
+    Lc, Lf = o.blocks(L)
+    tot = Lc[:, 0, ~o.hole].sum(axis=1) * o.dx ** o.dim + Lf[:, 0, :].sum(axis=1) * o.dxf ** o.dim
+    scale = np.abs(Lc[:, 0, ~o.hole]).sum(axis=1) * o.dx ** o.dim + np.abs(Lf[:, 0, :]).sum(axis=1) * o.dxf ** o.dim
+    assert np.all(np.abs(tot) <= 1e-13 * scale)
+    assert s.status() == 0
+
+
+@pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
+def test_amr_limiter_matches_oracle(case, spec):
+    import paper_1506_06140_amd as dg
+    wl = _wl(**spec)
+    o = oracle.AmrOracle(wl)
+    s = dg.Solver(wl)
+    w = o.initial_state()  # discontinuous blast projection: many cells limited
+    ref, st = o.limit(w)
+    assert st == 0
+    d = _dev(w)
+    s.limit(d)
+    got = _host(d)
+    err = rel_l1(o, got, ref)
+    _say(case, "AMR limiter rel-L1", err, "cells changed",
+         int((np.abs(_per_var(o, ref) - _per_var(o, w)) > 0).any(axis=0).sum()))
+    assert np.all(err <= TOL), err
+    assert s.status() == 0
+
+
+def test_amr_limited_steps_match_oracle():
+    # the 3D k=3 blast on a 2:1 refined box: limit the initial state, then
+    # two full limited SSP-RK3 steps
+    import paper_1506_06140_amd as dg
+    wl = _wl(dim=3, k=3, n=(8, 8, 8), lo=(2, 2, 2), hi=(6, 6, 6))
+    o = oracle.AmrOracle(wl)
+    s = dg.Solver(wl)
+    w0, st = o.limit(o.initial_state())
+    assert st == 0
+    ref, _ = o.run(w0, 2)
+    bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+    w = _dev(w0)
+    for _ in range(2):
+        w = s.step(w, bufs).clone()
+    err = rel_l1(o, _host(w), ref)
+    _say("AMR blast 2 limited steps rel-L1", err)
+    assert np.all(err <= TOL), err
+    np.testing.assert_allclose(o.totals(_host(w)), o.totals(w0), rtol=1e-12, atol=1e-14)
+
+
+def test_amr_projection_matches_oracle():
+    import paper_1506_06140_amd as dg
+    wl = _wl(dim=3, k=2, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4))
+    o = oracle.AmrOracle(wl)
+    s = dg.Solver(wl)
+    x = o.node_coords()
+    nct = o.ncoarse + o.nfine
+    cell = np.repeat(np.arange(nct), o.Q).reshape(nct, o.Q)
+    node = np.tile(np.arange(o.Q), nct).reshape(nct, o.Q)
+    wlq = dict(wl); wlq["nq"] = o.Q
+    prim = np.stack(workloads.primitives(wlq, x[..., 0], x[..., 1], x[..., 2], cell=cell, node=node), axis=-1)
+    import oracle as _o
+    lib, _ = _o._load()
+    import ctypes as C
+    ref = np.zeros(o.size)
+    assert lib.orc_amr_project(C.byref(o.c), np.ascontiguousarray(prim), ref) == 0
+    got = _host(s.project(_dev(np.transpose(prim, (2, 1, 0)))))
+    assert np.all(rel_l1(o, got, ref) <= 1e-14)
+    # the library's own node coordinates agree with the oracle's
+    xs = s.node_coords()
+    np.testing.assert_allclose(np.transpose(xs, (2, 1, 0)), x, atol=1e-15)
