@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdg.so")
+# DG_LIBRARY may point at another build of the same sources (tuning runs)
+LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(_HERE, "libdg.so"))
 
 DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
@@ -151,8 +152,12 @@ class Solver:
         self.ncoarse, self.nfine = int(az[0]), int(az[1])
         self.nf = tuple(int(x) for x in az[2:5])
         self.amr = self.nfine > 0
+        self.nhole = 0
         if self.amr:
             self.shape = (self.size,)
+            self.nhole = 1
+            for a in range(wl["dim"]):
+                self.nhole *= wl["refine_hi"][a] - wl["refine_lo"][a]
 
     def _s(self, t) -> int:
         return _ptr(t, self.size)

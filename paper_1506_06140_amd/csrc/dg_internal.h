@@ -61,6 +61,8 @@ struct dg_ctx {
   std::vector<double> host_tab;
   double *tab = nullptr;     // FP64 tables on the device
   float *tab32 = nullptr;    // FP32 copy
+  void *tabbf = nullptr;     // BF16 tables of the MFMA volume kernel (padded)
+  float *vscratch = nullptr; // volume term from the MFMA kernel (BF16 path)
   double *partial = nullptr; // 64-bit word holding the running maximum signal rate
   int npartial = 0;          // blocks of the time-step reduction
   int *flag = nullptr;       // sticky device error flag

@@ -51,7 +51,6 @@ struct Grid {
   int bc[3];
   double fac;    // (2/dx) 2^-d
   double gamma;
-  int davis;     // HLLC wave-speed bounds: 0 Einfeldt-Batten, 1 Davis
 };
 
 enum : int { FLAG_NEGATIVE = 1, FLAG_NAN = 2 };
@@ -175,9 +174,15 @@ __device__ inline float cst<float>(double x) { return (float)x; }
 // in the compact form F = F_K + S_K^(-/+) (U*_K - U_K) with K = L if S* >= 0
 // (S_L^- = min(S_L, 0)) and K = R otherwise (S_R^+ = max(S_R, 0)); this
 // equals the four-region selection of the textbook solver.  Wave-speed
-// bounds: Einfeldt-Batten (Roe-averaged) or Davis.
-template <class T, int D>
-__device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis, T *F) {
+// bounds: Einfeldt-Batten (Roe-averaged, FX = 0) or Davis (FX = 1).
+//
+// The choice is a template parameter, not a run-time flag: with a uniform
+// flag branched on inside loops that run under different exec masks (the
+// hanging sub-faces of the refined box), the compiler built the flag's lane
+// mask under one exec mask and reused it under another, so lanes that had
+// been inactive took the other branch.
+template <class T, int D, int FX>
+__device__ inline void hllc(const T *UL, const T *UR, int a, double g, T *F) {
   // The normal axis a may be a run-time value: components are picked with
   // unrolled compares (no dynamic register indexing).  One reciprocal square
   // root per side gives sqrt(rho) and 1/rho.
@@ -205,7 +210,7 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis
   const T gpL = gg * pL, gpR = gg * pR;
   const T cL = gpL * vrsq(gpL * UL[0]), cR = gpR * vrsq(gpR * UR[0]);
   T SL, SR;
-  if (davis) {
+  if constexpr (FX == DG_HLLC_DAVIS) {
     SL = vmin(uL - cL, uR - cR);
     SR = vmax(uL + cL, uR + cR);
   } else {
@@ -258,11 +263,12 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, int davis
 // mode 0: out = L;  mode 1: stage 1 (out = w + dt L);  mode 2: stages 2, 3
 // (out = ca wn + cb (w + dt L)).
 // ---------------------------------------------------------------------------
-template <int D, int K, class R>
+template <int D, int K, class R, int FX>
 __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const R *__restrict__ tabr,
                                                    const double *__restrict__ w, const double *__restrict__ wn,
-                                                   double *__restrict__ out, const double *__restrict__ dtp, Grid g,
-                                                   int mode, double ca, double cb, int *__restrict__ flag) {
+                                                   double *__restrict__ out, const double *__restrict__ dtp,
+                                                   const float *__restrict__ vext, Grid g, int mode, double ca,
+                                                   double cb, int *__restrict__ flag) {
   // R is the type of the contractions and fluxes (double, or float for the
   // mixed-precision path); the lift of the cell mean and the stage update are
   // always FP64.
@@ -290,9 +296,16 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
     for (int l = 0; l < C::N; ++l) acc[v][l] = R(0);
   }
 
-  // volume integral (eq. dg_term2); dphi_1 = 0, so it never touches mode 0
+  // volume integral (eq. dg_term2); dphi_1 = 0, so it never touches mode 0.
+  // With vext the volume term comes precomputed (BF16 MFMA path).
+  if (vext) {
+#pragma unroll
+    for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+      for (int l = 1; l < C::N; ++l) acc[v][l] = (R)vext[(long)(v * C::N + l) * nc + cell];
+  }
 #pragma unroll 1
-  for (int q = 0; q < C::Q; ++q) {
+  for (int q = 0; q < (vext ? 0 : C::Q); ++q) {
     R U[C::NV];
     const R *bq = tabr + C::B + q * C::N;
 #pragma unroll
@@ -348,7 +361,7 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
           UL[v] = s ? Uo[v] : Un[v];
           UR[v] = s ? Un[v] : Uo[v];
         }
-        hllc<R, D>(UL, UR, a, g.gamma, g.davis, F);
+        hllc<R, D, FX>(UL, UR, a, g.gamma, F);
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) {
           const R f = s ? -F[v] : F[v];
@@ -401,12 +414,18 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
 // ---------------------------------------------------------------------------
 template <int K>
 struct Tile2D;
+#ifndef DG_TILE2D_TY2
+#define DG_TILE2D_TY2 16
+#endif
+#ifndef DG_TILE2D_TY3
+#define DG_TILE2D_TY3 8
+#endif
 template <>
 struct Tile2D<1> { static constexpr int TX = 16, TY = 16; };
 template <>
-struct Tile2D<2> { static constexpr int TX = 16, TY = 16; };
+struct Tile2D<2> { static constexpr int TX = 16, TY = DG_TILE2D_TY2; };
 template <>
-struct Tile2D<3> { static constexpr int TX = 16, TY = 8; };
+struct Tile2D<3> { static constexpr int TX = 16, TY = DG_TILE2D_TY3; };
 
 // Exchange of a value with the lane `sub ^ 1` or `sub ^ 2` of the same quad
 // (DPP quad permutation, no LDS traffic).
@@ -424,11 +443,11 @@ __device__ inline float quad_swap(float x) {
 constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 
-template <int K, class R>
+template <int K, class R, int FX>
 __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
     const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
-    const double *__restrict__ wn, double *__restrict__ out, const double *__restrict__ dtp, Grid g, int mode,
-    double ca, double cb, int *__restrict__ flag) {
+    const double *__restrict__ wn, double *__restrict__ out, const double *__restrict__ dtp,
+    const float *__restrict__ vext, Grid g, int mode, double ca, double cb, int *__restrict__ flag) {
   // R: type of the contractions and fluxes (double, or float in the mixed
   // path); the lift of the cell mean and the stage update are FP64.
   using C = Cfg<2, K>;
@@ -509,7 +528,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       UL[v] = ghost_lo ? sh : sl;
       UR[v] = ghost_hi ? sl : sh;
     }
-    hllc<R, 2>(UL, UR, a, g.gamma, g.davis, F);
+    hllc<R, 2, FX>(UL, UR, a, g.gamma, F);
 #pragma unroll
     for (int v = 0; v < NV; ++v) sf[t * NV + v] = F[v];
   }
@@ -531,7 +550,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       for (int l = 0; l < N; ++l) wc[v][l] = sw[(v * N + l) * HC + own];
     const R gm1 = (R)(g.gamma - 1.0);
 #pragma unroll 1
-    for (int q = sub; q < Q; q += 4) {
+    for (int q = sub; q < (vext ? 0 : Q); q += 4) {
       const R *bq = tabr + C::B + q * N;
       R U[NV];
 #pragma unroll
@@ -576,6 +595,11 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       const R send = hi1 ? part[0][l] : part[1][l];
       accv[l] = keep + quad_swap<kQuadXor1>(send);
     }
+  }
+  if (vext && real) {
+    const long c2 = (long)(by0 + ty) * g.nx + (bx0 + tx);
+#pragma unroll
+    for (int l = 1; l < N; ++l) accv[l] = (R)vext[(long)(sub * N + l) * nc + c2];
   }
   __syncthreads();
   if (!real) return;
@@ -655,7 +679,7 @@ __device__ inline void euler_flux_vjp(const double *U, int a, double g, const do
   G[D + 1] += la * gm1 + lE * g * va;
 }
 
-template <int D, int K>
+template <int D, int K, int FX>
 __global__ __launch_bounds__(256) void k_adjoint(const double *__restrict__ tab, const double *__restrict__ w,
                                                  const double *__restrict__ lam, const double *acc_in,
                                                  double *__restrict__ out, double *acc_out,
@@ -769,7 +793,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const double *__restrict__ tab,
             UL[v] = s ? Dual{own, to_own} : Dual{oth, to_oth};
             UR[v] = s ? Dual{oth, to_oth} : Dual{own, to_own};
           }
-          hllc<Dual, D>(UL, UR, a, g.gamma, g.davis, F);
+          hllc<Dual, D, FX>(UL, UR, a, g.gamma, F);
           double h = 0.0;
 #pragma unroll
           for (int v = 0; v < C::NV; ++v) h = fma(gv[v], F[v].d, h);
@@ -1061,6 +1085,114 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
 }
 
 // ---------------------------------------------------------------------------
+// Volume integral (eq. dg_term2) with BF16 inputs on MFMA, FP32 accumulation.
+//
+// Both contractions of the volume term are small GEMMs batched over cells:
+//   A  U[cell, q] = sum_m w[cell, m] phi_m(xi_q)            (per variable)
+//   B  V[cell, j] = sum_a sum_q F_a[cell, q] dphi_j/dxi_a(xi_q) w_q
+// One wave handles 16 cells with v_mfma_f32_16x16x32_bf16 (A: 16x32, B: 32x16,
+// C: 16x16 FP32).  Modes are padded to 32 and nodes to a multiple of 32 with
+// zero table entries.  The stage-A result leaves, for every variable, four
+// cells at one node in each lane, so the Euler flux is evaluated in-lane in
+// FP32; the fluxes go through LDS as BF16 to the A-operand layout of stage B.
+// V (FP32) is written to a scratch state that the stage kernel consumes.
+// Mode 0 of V is exactly zero (dphi_1 = 0).
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int D, int K>
+struct Mfma {
+  static constexpr int NP = 32;                                  // padded modes
+  static constexpr int QP = ((Cfg<D, K>::Q + 31) / 32) * 32;     // padded nodes
+  static constexpr int NQT = QP / 16;                            // node tiles (stage A)
+  static constexpr int NQC = QP / 32;                            // node chunks (stage B)
+  static constexpr int PB = 0;                                   // phi [QP][NP]
+  static constexpr int DB = PB + QP * NP;                        // dphi w, transposed [D][NP][QP]
+  static constexpr int TOTAL = DB + D * NP * QP;
+};
+
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ tb, const double *__restrict__ w,
+                                                     long nc, float *__restrict__ vout, double gamma) {
+  using C = Cfg<D, K>;
+  using M = Mfma<D, K>;
+  constexpr int NV = C::NV, N = C::N, QP = M::QP, NP = M::NP;
+  __shared__ __bf16 fs[4][NV][D][16][QP];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int row = lane & 15, grp = lane >> 4;
+  const long c0 = ((long)blockIdx.x * 4 + wv) * 16;
+  const float gm1 = (float)(gamma - 1.0);
+
+  // stage A: nodal values
+  f32x4 U[NV][M::NQT];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    bf16x8 A;
+    const long cell = c0 + row;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int m = 8 * grp + e;
+      A[e] = (m < N && cell < nc) ? (__bf16)(float)w[(long)(v * N + m) * nc + cell] : (__bf16)0.0f;
+    }
+#pragma unroll
+    for (int t = 0; t < M::NQT; ++t) {
+      const bf16x8 B = *reinterpret_cast<const bf16x8 *>(tb + M::PB + (16 * t + row) * NP + 8 * grp);
+      f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      U[v][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, z, 0, 0, 0);
+    }
+  }
+  // Euler flux at (cell 4 grp + i, node 16 t + row), stored as BF16
+#pragma unroll
+  for (int t = 0; t < M::NQT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int q = 16 * t + row;
+      const int cl = 4 * grp + i;
+      const bool ok = q < C::Q && c0 + cl < nc;
+      float Uq[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uq[v] = U[v][t][i];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        float F[NV];
+        if (ok) {
+          euler_flux<D, float>(Uq, a, gm1, F);
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) F[v] = 0.0f;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fs[wv][v][a][cl][q] = (__bf16)F[v];
+      }
+    }
+  __syncthreads();
+  // stage B: projection onto the basis gradients
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int mt = 0; mt < NP / 16; ++mt) {
+      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+#pragma unroll
+        for (int ch = 0; ch < M::NQC; ++ch) {
+          const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&fs[wv][v][a][row][ch * 32 + 8 * grp]);
+          const bf16x8 B =
+              *reinterpret_cast<const bf16x8 *>(tb + M::DB + (a * NP + mt * 16 + row) * QP + ch * 32 + 8 * grp);
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc, 0, 0, 0);
+        }
+      const int j = mt * 16 + row;
+      if (j < N)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const long cell = c0 + 4 * grp + i;
+          if (cell < nc) vout[(long)(v * N + j) * nc + cell] = acc[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Static 2:1 refined box (hanging-face quadrature of Sec. 4, limiting at the
 // refinement boundary of Sec. 4.4).  State: coarse block [nvar][N][ncc]
 // (base grid; the base cells in [lo, hi) form a hole, ignored) followed by
@@ -1080,7 +1212,6 @@ struct AmrGrid {
   int bc[3];
   double facc, facf, dxc, dxf;
   double gamma;
-  int davis;
 };
 
 template <int D>
@@ -1104,11 +1235,12 @@ __device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int 
   return true;
 }
 
-template <int D, int K, class R>
+template <int D, int K, class R, int FX>
 __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab, const R *__restrict__ tabr,
                                                  const double *__restrict__ w, const double *__restrict__ wn,
-                                                 double *__restrict__ out, const double *__restrict__ dtp, AmrGrid g,
-                                                 int mode, double ca, double cb, int *__restrict__ flag) {
+                                                 double *__restrict__ out, const double *__restrict__ dtp,
+                                                 const float *__restrict__ vext, AmrGrid g, int mode, double ca,
+                                                 double cb, int *__restrict__ flag) {
   using C = Cfg<D, K>;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, NW = NV * N, NSUB = 1 << (D - 1);
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1145,9 +1277,15 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
 #pragma unroll
     for (int l = 0; l < N; ++l) acc[v][l] = R(0);
   }
-  // volume integral
+  // volume integral (precomputed in vext on the BF16 MFMA path)
+  if (vext) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int l = 1; l < N; ++l) acc[v][l] = (R)vext[boff + (long)(v * N + l) * ncb + cell];
+  }
 #pragma unroll 1
-  for (int q = 0; q < C::Q; ++q) {
+  for (int q = 0; q < (vext ? 0 : C::Q); ++q) {
     R U[NV];
     const R *bq = tabr + C::B + q * N;
 #pragma unroll
@@ -1258,7 +1396,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
             UL[v] = s ? Uo[v] : Un[v];
             UR[v] = s ? Un[v] : Uo[v];
           }
-          hllc<R, D>(UL, UR, a, g.gamma, g.davis, F);
+          hllc<R, D, FX>(UL, UR, a, g.gamma, F);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             const R f = s ? -F[v] : F[v];
@@ -1534,7 +1672,6 @@ dg::Grid make_grid(const dg_ctx *c) {
   for (int a = 0; a < 3; ++a) g.bc[a] = c->cfg.bc[a];
   g.fac = 2.0 / c->dx / (double)(1 << c->sh.d);
   g.gamma = c->cfg.gamma;
-  g.davis = c->cfg.flux == DG_HLLC_DAVIS;
   return g;
 }
 
@@ -1558,7 +1695,6 @@ dg::AmrGrid make_amr_grid(const dg_ctx *c) {
   g.facc = 2.0 / g.dxc / (double)(1 << c->sh.d);
   g.facf = 2.0 / g.dxf / (double)(1 << c->sh.d);
   g.gamma = c->cfg.gamma;
-  g.davis = c->cfg.flux == DG_HLLC_DAVIS;
   return g;
 }
 
@@ -1598,26 +1734,53 @@ struct StageLaunch {
   double ca, cb;
   hipStream_t s;
   template <int D, int K, class R>
-  int launch(const R *tabr) {
+  int launch(const R *tabr, const float *vext) {
+    return c->cfg.flux == DG_HLLC_DAVIS ? launch_fx<D, K, R, DG_HLLC_DAVIS>(tabr, vext)
+                                        : launch_fx<D, K, R, DG_HLLC_BATTEN>(tabr, vext);
+  }
+  template <int D, int K, class R, int FX>
+  int launch_fx(const R *tabr, const float *vext) {
     if (c->amr) {
-      hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, tabr,
-                         w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, tabr,
+                         w, wn, out, dt, vext, make_amr_grid(c), mode, ca, cb, c->flag);
     } else if constexpr (D == 2) {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
-      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
-                         make_grid(c), mode, ca, cb, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
+                         vext, make_grid(c), mode, ca, cb, c->flag);
     } else {
-      hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
-                         wn, out, dt, make_grid(c), mode, ca, cb, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
+                         wn, out, dt, vext, make_grid(c), mode, ca, cb, c->flag);
+    }
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+  template <int D, int K>
+  int volume_bf16() {
+    const __bf16 *tb = reinterpret_cast<const __bf16 *>(c->tabbf);
+    if (!c->amr) {
+      hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(256), 0, s, tb, w,
+                         c->ncell, c->vscratch, c->cfg.gamma);
+    } else {
+      const long nw = (long)c->sh.nv * c->sh.N;
+      hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncc + 63) / 64)), dim3(256), 0, s, tb, w,
+                         c->ncc, c->vscratch, c->cfg.gamma);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncf + 63) / 64)), dim3(256), 0, s, tb,
+                         w + nw * c->ncc, c->ncf, c->vscratch + nw * c->ncc, c->cfg.gamma);
     }
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
   template <int D, int K>
   int run() {
-    if (c->cfg.precision == DG_FP32) return launch<D, K, float>(c->tab32);
-    return launch<D, K, double>(c->tab);
+    if (c->cfg.precision == DG_BF16_VOL) {
+      int st = volume_bf16<D, K>();
+      if (st != DG_OK) return st;
+      return launch<D, K, float>(c->tab32, c->vscratch);
+    }
+    if (c->cfg.precision == DG_FP32) return launch<D, K, float>(c->tab32, nullptr);
+    return launch<D, K, double>(c->tab, nullptr);
   }
 };
 
@@ -1674,12 +1837,47 @@ struct AdjointLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
-    hipLaunchKernelGGL((dg::k_adjoint<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, lam, acc, out,
-                       acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    if (c->cfg.flux == DG_HLLC_DAVIS)
+      hipLaunchKernelGGL((dg::k_adjoint<D, K, DG_HLLC_DAVIS>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w,
+                         lam, acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    else
+      hipLaunchKernelGGL((dg::k_adjoint<D, K, DG_HLLC_BATTEN>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w,
+                         lam, acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
 };
+
+// Round-to-nearest-even conversion of a float to BF16 bits.
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, sizeof(u));
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+struct Bf16Tables {
+  const dg_ctx *c;
+  std::vector<uint16_t> *out;
+  template <int D, int K>
+  int run() {
+    using C = Cfg<D, K>;
+    using M = dg::Mfma<D, K>;
+    std::vector<uint16_t> &t = *out;
+    t.assign(M::TOTAL, 0);
+    const std::vector<double> &h = c->host_tab;
+    for (int q = 0; q < C::Q; ++q)
+      for (int m = 0; m < C::N; ++m) t[M::PB + q * M::NP + m] = to_bf16((float)h[C::B + q * C::N + m]);
+    for (int a = 0; a < D; ++a)
+      for (int m = 0; m < C::N; ++m)
+        for (int q = 0; q < C::Q; ++q)
+          t[M::DB + (a * M::NP + m) * M::QP + q] = to_bf16((float)h[C::DW + (a * C::Q + q) * C::N + m]);
+    return DG_OK;
+  }
+};
+
+int bf16_tables(const dg_ctx *c, std::vector<uint16_t> &out) { return dispatch(c, Bf16Tables{c, &out}); }
 
 }  // namespace
 
@@ -1709,7 +1907,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   }
   if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0)) return DG_EINVAL;
   if (cfg->flux != DG_HLLC_BATTEN && cfg->flux != DG_HLLC_DAVIS) return DG_EINVAL;
-  if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32) return DG_EUNSUPPORTED;
+  if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32 && cfg->precision != DG_BF16_VOL)
+    return DG_EUNSUPPORTED;
   if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD) return DG_EUNSUPPORTED;
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
@@ -1783,6 +1982,19 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMemcpy(c->tab32, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   int zero = 0;
   if ((e = hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  if (cfg->precision == DG_BF16_VOL) {
+    std::vector<uint16_t> tb;
+    int st = bf16_tables(c, tb);
+    if (st != DG_OK) {
+      dg_destroy(c);
+      return st;
+    }
+    if ((e = hipMalloc((void **)&c->tabbf, tb.size() * sizeof(uint16_t))) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(c->tabbf, tb.data(), tb.size() * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e);
+    const size_t nv = (size_t)c->sh.nv * c->sh.N * c->ncell;
+    if ((e = hipMalloc((void **)&c->vscratch, nv * sizeof(float))) != hipSuccess) return fail(e);
+  }
   const unsigned long long zero64 = 0ull;
   if ((e = hipMemcpy(c->partial, &zero64, sizeof(zero64), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   *out = c;
@@ -1793,6 +2005,8 @@ void dg_destroy(dg_ctx *c) {
   if (!c) return;
   if (c->tab) (void)hipFree(c->tab);
   if (c->tab32) (void)hipFree(c->tab32);
+  if (c->tabbf) (void)hipFree(c->tabbf);
+  if (c->vscratch) (void)hipFree(c->vscratch);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
   delete c;

@@ -169,3 +169,37 @@ def test_trajectory_gradient_matches_oracle_directional_derivatives():
         _say("direction", j, "dJ gpu", dJ, "oracle", dJ_ref, "rel", abs(dJ - dJ_ref) / abs(dJ_ref))
         assert J == pytest.approx(J_ref, rel=1e-12)
         assert abs(dJ - dJ_ref) <= 1e-10 * abs(dJ_ref)
+
+
+def _J(s, w0, steps, dt):
+    import torch
+    from paper_1506_06140_amd import adjoint
+    with torch.no_grad():
+        wT = adjoint.trajectory(s, w0, steps, dt, steps)
+        return float(adjoint.density_square_integral(s, wT))
+
+
+def test_trajectory_gradient_central_differences():
+    # Central differences of J on 16 seeded +-1 directions scaled to
+    # |d|_2 = |w0|_2, steps h in {1e-5, 1e-6, 1e-7}; the best h per direction
+    # agrees with <grad J, d> to 1e-6 relative.
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("vortex_adjoint", n=(64, 64, 1))
+    o = oracle.Oracle(wl)
+    s = dg.Solver(wl)
+    w0 = o.initial_state()
+    dt = _dev(np.array([o.max_dt(w0)]))
+    steps = 40
+    J, g = _grad(s, _dev(w0), steps, dt, 10)
+    g = _host(g)
+    scale = np.linalg.norm(w0) / np.sqrt(w0.size)
+    for seed in range(1, 17):
+        d = workloads.sign_direction(seed, w0.size).reshape(w0.shape) * scale
+        dJ = float((g * d).sum())
+        errs = []
+        for h in (1e-5, 1e-6, 1e-7):
+            jp = _J(s, _dev(w0 + h * d), steps, dt)
+            jm = _J(s, _dev(w0 - h * d), steps, dt)
+            errs.append(abs((jp - jm) / (2 * h) - dJ) / abs(dJ))
+        _say("direction seed", seed, "dJ", dJ, "FD rel err per h", errs)
+        assert min(errs) <= 1e-6, errs

@@ -48,6 +48,12 @@ def _wl(dim, k, n, lo, hi, **kw):
     h = 1.0 / 8.0
     base = dict(limiter=1, positivity=1, ic="blast")
     base.update(kw)
+    if base["ic"] == "kh3d":
+        # shear layer: density and velocity jumps at y = 1/4 and 3/4 (on
+        # hanging faces of the boxes below) plus cell-wise velocity noise,
+        # so that the two traces differ on every hanging face
+        base.setdefault("noise", 1e-2)
+        base.setdefault("seed", 6140)
     return workloads.workload("blast_amr", dim=dim, k=k, n=n, length=tuple(h * m for m in n),
                               refine_lo=lo, refine_hi=hi, **base)
 
@@ -58,6 +64,12 @@ CASES = [
     ("3d_k2", dict(dim=3, k=2, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4))),
     ("3d_k3", dict(dim=3, k=3, n=(8, 8, 8), lo=(2, 2, 2), hi=(6, 6, 6))),
 ]
+# right-hand side cases: every box with the shear layer (jumps across hanging
+# faces), the 3D boxes with the blast, and both HLLC wave-speed bounds
+RHS_CASES = ([(c + "_kh", dict(s, ic="kh3d")) for c, s in CASES]
+             + [(c + "_blast", s) for c, s in CASES if s["dim"] == 3]
+             + [("3d_k2_kh_davis", dict(CASES[2][1], ic="kh3d", flux=1)),
+                ("2d_k2_kh_davis", dict(CASES[0][1], ic="kh3d", flux=1))])
 
 
 def _limited_state(o):
@@ -68,7 +80,7 @@ def _limited_state(o):
     return w
 
 
-@pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("case,spec", RHS_CASES, ids=[c[0] for c in RHS_CASES])
 def test_amr_rhs_stage_dt_match_oracle(case, spec):
     import paper_1506_06140_amd as dg
     wl = _wl(**spec)
@@ -117,11 +129,14 @@ def test_amr_limiter_matches_oracle(case, spec):
     assert s.status() == 0
 
 
-def test_amr_limited_steps_match_oracle():
-    # the 3D k=3 blast on a 2:1 refined box: limit the initial state, then
-    # two full limited SSP-RK3 steps
+@pytest.mark.parametrize("case,spec", [
+    ("3d_k3_blast", dict(dim=3, k=3, n=(8, 8, 8), lo=(2, 2, 2), hi=(6, 6, 6))),
+    ("3d_k2_kh", dict(dim=3, k=2, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4), ic="kh3d")),
+], ids=["3d_k3_blast", "3d_k2_kh"])
+def test_amr_limited_steps_match_oracle(case, spec):
+    # limit the initial state, then two full limited SSP-RK3 steps
     import paper_1506_06140_amd as dg
-    wl = _wl(dim=3, k=3, n=(8, 8, 8), lo=(2, 2, 2), hi=(6, 6, 6))
+    wl = _wl(**spec)
     o = oracle.AmrOracle(wl)
     s = dg.Solver(wl)
     w0, st = o.limit(o.initial_state())
@@ -132,7 +147,7 @@ def test_amr_limited_steps_match_oracle():
     for _ in range(2):
         w = s.step(w, bufs).clone()
     err = rel_l1(o, _host(w), ref)
-    _say("AMR blast 2 limited steps rel-L1", err)
+    _say(case, "AMR 2 limited steps rel-L1", err)
     assert np.all(err <= TOL), err
     np.testing.assert_allclose(o.totals(_host(w)), o.totals(w0), rtol=1e-12, atol=1e-14)
 

@@ -4,7 +4,13 @@ solver in FP32; cell-mean lift and stage update in FP64).
 Stated tolerances: relative L1 <= 1e-5 per variable against the FP64 GPU path
 after 10 steps; conservation of mass, momentum and energy to 1e-12 relative
 (the cell means are updated in FP64 with the face-mean flux shared bitwise by
-the two cells of every face)."""
+the two cells of every face).
+
+The reduced-precision paths evaluate pressures at the nodes from FP32 (or
+BF16) values, p = (gamma - 1)(E - |m|^2 / (2 rho)), whose cancellation error is
+about 1e-7 |E|: a positivity floor eps far below that (the FP64 default 1e-10)
+lets a node pressure round below zero in the Riemann solver.  The blast runs
+here therefore use eps = 1e-4."""
 import sys
 
 import numpy as np
@@ -43,22 +49,34 @@ def _run(s, w0, steps):
     return w
 
 
+def _active(o, x):
+    """The state without the ignored hole cells of a refined box."""
+    if not isinstance(o, oracle.AmrOracle):
+        return x
+    c, f = o.blocks(x)
+    return np.concatenate([c[:, :, ~o.hole].reshape(o.nvar, -1), f.reshape(o.nvar, -1)], axis=1)
+
+
+BLAST_AMR = dict(n=(16, 16, 16), refine_lo=(4, 4, 4), refine_hi=(12, 12, 12), eps=1e-4)
+
+
 @pytest.mark.parametrize("name,over", [
     ("vortex", dict(n=(64, 64, 1))),
     ("vortex_adjoint", dict(n=(48, 40, 1), length=(12.0, 10.0, 1.0))),
     ("kh3d", dict(n=(24, 24, 24))),
+    ("blast_amr", BLAST_AMR),
 ])
 def test_fp32_path_against_fp64(name, over):
     import paper_1506_06140_amd as dg
     wl = workloads.workload(name, **over)
-    o = oracle.Oracle(wl)
+    o = oracle.AmrOracle(wl) if name == "blast_amr" else oracle.Oracle(wl)
     w0 = _dev(o.initial_state())
     s64 = dg.Solver(wl, "fp64")
     s32 = dg.Solver(wl, "fp32")
     steps = 10
     a = _host(_run(s64, w0, steps))
     b = _host(_run(s32, w0, steps))
-    err = rel_l1(b, a)
+    err = rel_l1(_active(o, b), _active(o, a))
     tot0 = o.totals(_host(w0))
     drift32 = (o.totals(b) - tot0) / np.abs(tot0).clip(1e-300)
     drift64 = (o.totals(a) - tot0) / np.abs(tot0).clip(1e-300)
@@ -84,3 +102,57 @@ def test_fp32_rhs_error_against_oracle():
     tot = L.reshape(o.nvar, o.N, -1)[:, 0, :].sum(axis=1)
     scale = np.abs(L.reshape(o.nvar, o.N, -1)[:, 0, :]).sum(axis=1)
     assert np.all(np.abs(tot) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("name,over", [
+    ("vortex", dict(n=(64, 64, 1))),
+    ("kh3d", dict(n=(24, 24, 24))),
+    ("blast_amr", BLAST_AMR),
+])
+def test_bf16_volume_path_against_fp64(name, over):
+    # volume contraction in BF16 on MFMA (FP32 accumulation), faces in FP32,
+    # means in FP64: stated tolerance 1e-2 relative L1 after 10 steps (3e-2 for
+    # the blast momentum), conservation 1e-12
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload(name, **over)
+    o = oracle.AmrOracle(wl) if name == "blast_amr" else oracle.Oracle(wl)
+    w0 = _dev(o.initial_state())
+    s64 = dg.Solver(wl, "fp64")
+    sbf = dg.Solver(wl, "bf16")
+    steps = 10
+    a = _host(_run(s64, w0, steps))
+    b = _host(_run(sbf, w0, steps))
+    err = rel_l1(_active(o, b), _active(o, a))
+    tot0 = o.totals(_host(w0))
+    tb = o.totals(b)
+    print(name, "bf16-volume vs fp64 rel-L1 after", steps, "steps:", err, "drift", (tb - tot0) / np.abs(tot0).clip(1e-300),
+          flush=True)
+    # Every BF16 operand carries a relative rounding of up to 2^-9 (state and
+    # basis table into the nodal values, flux and gradient table into the
+    # projection), about 2e-3 of the volume term per stage.  On the blast the
+    # momentum starts at zero and is created by pressure gradients, so that
+    # error lands in a field whose norm is small: 3e-2 there (measured
+    # 1.6e-2 on 16^3 with the refined box), 1e-2 elsewhere.
+    tol = np.full(o.nvar, 1e-2)
+    if name == "blast_amr":
+        tol[1:1 + o.dim] = 3e-2
+    assert np.all(err <= tol), err
+    assert np.all(np.abs(tb - tot0) <= 1e-12 * np.abs(tot0).max())
+
+
+def test_bf16_volume_term_against_oracle():
+    # the volume term alone (a state whose face fluxes cancel: RHS = V - S
+    # with S from FP32 faces); relative to |V| + |S| the BF16 contraction is
+    # within a few BF16 roundings
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("blast_amr", n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), refine_lo=(0, 0, 0),
+                            refine_hi=(0, 0, 0), limiter=0, positivity=0, ic="kh3d", noise=1e-2, seed=6140)
+    o = oracle.Oracle(wl)
+    w = o.initial_state()
+    V, S = o.terms_cells(w)
+    L = _host(dg.Solver(wl, "bf16").rhs(_dev(w))).reshape(o.nvar, -1)
+    V = V.reshape(o.nvar, -1); S = S.reshape(o.nvar, -1)
+    err = np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
+    print("bf16 rhs error / (|V|+|S|):", err, flush=True)
+    assert np.all(err <= 2e-2), err
+    assert np.all(err >= 1e-9)  # it is really a reduced-precision contraction

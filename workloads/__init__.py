@@ -51,6 +51,12 @@ def uniform_pm1(seed: int, counter) -> np.ndarray:
     return 2.0 * (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) - 1.0
 
 
+def sign_direction(seed: int, size: int) -> np.ndarray:
+    """A seeded direction of +-1 entries (sign of U(-1, 1) draws 0..size-1 of
+    stream `seed`), used for finite-difference checks of gradients."""
+    return np.where(uniform_pm1(seed, np.arange(size)) >= 0.0, 1.0, -1.0)
+
+
 # ---------------------------------------------------------------------------
 # Workload table.  Sizes follow the five benchmark configurations plus small
 # variants used by tests.  `n` is the base grid, `x0`/`length` the box.
