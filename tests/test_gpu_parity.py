@@ -88,6 +88,14 @@ CASES = [
                       refine_lo=(0, 0, 0), refine_hi=(0, 0, 0))),
     ("sod_transmissive_davis", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), flux=1, limiter=0,
                                     positivity=0)),
+    # 3D: a grid thinner than one tile along z, and transmissive x/y with Davis bounds
+    ("kh3d_k2_thin", dict(name="kh3d", k=2, n=(8, 5, 3), length=(0.8, 0.5, 0.3), limiter=0, positivity=0)),
+    ("blast3d_k1_transmissive_davis", dict(name="blast_amr", k=1, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
+                                           limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
+                                           bc=(1, 1, 0), flux=1)),
+    ("blast3d_k2_transmissive", dict(name="blast_amr", k=2, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
+                                     limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
+                                     bc=(0, 1, 1))),
 ]
 
 
