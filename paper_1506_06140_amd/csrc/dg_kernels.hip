@@ -112,9 +112,8 @@ __device__ inline void euler_flux(const R *U, int a, R gm1, R *F) {
   F[D + 1] = (U[D + 1] + p) * va;
 }
 
-// Scalar helpers so that the Riemann solver can run on doubles (the forward
-// pass) and on dual numbers (exact forward-mode derivatives for the adjoint)
-// with the same sequence of value operations, hence the same branches.
+// Scalar helpers so that the Riemann solver runs on doubles and on floats
+// with the same sequence of operations.
 __device__ inline double vfma(double a, double b, double c) { return fma(a, b, c); }
 __device__ inline double vsqrt(double a) { return sqrt(a); }
 __device__ inline double vmin(double a, double b) { return b < a ? b : a; }
@@ -126,47 +125,11 @@ __device__ inline float vmin(float a, float b) { return b < a ? b : a; }
 __device__ inline float vmax(float a, float b) { return b > a ? b : a; }
 __device__ inline double val(float a) { return a; }
 
-// Dual number a + b eps (eps^2 = 0): value and one directional derivative.
-struct Dual {
-  double v, d;
-};
-__device__ inline Dual mkd(double v) { return Dual{v, 0.0}; }
-__device__ inline Dual operator+(Dual a, Dual b) { return Dual{a.v + b.v, a.d + b.d}; }
-__device__ inline Dual operator-(Dual a, Dual b) { return Dual{a.v - b.v, a.d - b.d}; }
-__device__ inline Dual operator-(Dual a) { return Dual{-a.v, -a.d}; }
-__device__ inline Dual operator*(Dual a, Dual b) { return Dual{a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
-__device__ inline Dual operator*(double a, Dual b) { return Dual{a * b.v, a * b.d}; }
-__device__ inline Dual operator/(Dual a, Dual b) {
-  const double q = a.v / b.v;
-  return Dual{q, (a.d - q * b.d) / b.v};
-}
-__device__ inline Dual operator/(double a, Dual b) {
-  const double q = a / b.v;
-  return Dual{q, -q * b.d / b.v};
-}
-__device__ inline Dual vfma(Dual a, Dual b, Dual c) { return Dual{fma(a.v, b.v, c.v), fma(a.d, b.v, fma(a.v, b.d, c.d))}; }
-__device__ inline Dual vsqrt(Dual a) {
-  const double r = sqrt(a.v);
-  return Dual{r, r > 0.0 ? 0.5 * a.d / r : 0.0};
-}
-__device__ inline Dual vmin(Dual a, Dual b) { return b.v < a.v ? b : a; }
-__device__ inline Dual vrcp(Dual a) {
-  const double r = vrcp(a.v);
-  return Dual{r, -r * r * a.d};
-}
-__device__ inline Dual vrsq(Dual a) {
-  const double y = vrsq(a.v);
-  return Dual{y, -0.5 * y * y * y * a.d};
-}
-__device__ inline Dual vmax(Dual a, Dual b) { return b.v > a.v ? b : a; }
-__device__ inline double val(Dual a) { return a.v; }
 
 template <class T>
 __device__ inline T cst(double x);
 template <>
 __device__ inline double cst<double>(double x) { return x; }
-template <>
-__device__ inline Dual cst<Dual>(double x) { return mkd(x); }
 template <>
 __device__ inline float cst<float>(double x) { return (float)x; }
 
@@ -247,15 +210,240 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, T *F) {
   for (int b = 0; b < D; ++b) FK[1 + b] = vfma(U[1 + b], uK, b == a ? pK : zero);
   FK[D + 1] = (U[D + 1] + pK) * uK;
   // star state rho_K (S_K - u_K)/(S_K - S*) (1, S* n + v_t, E_K/rho_K + (S* - u_K)(S* + p_K/(rho_K (S_K - u_K))))
-  const T rd = U[0] * dK;
-  const T fac = rd * vrcp(SK - Ss);
+  // with r = rho_K (S_K - u_K) and f = r / (S_K - S*): f p_K / r = p_K / (S_K - S*)
+  const T ivS = vrcp(SK - Ss);
+  const T fac = (U[0] * dK) * ivS;
   T Us[D + 2];
   Us[0] = fac;
 #pragma unroll
   for (int b = 0; b < D; ++b) Us[1 + b] = fac * (b == a ? Ss : U[1 + b] * irK);
-  Us[D + 1] = fac * (U[D + 1] * irK + (Ss - uK) * (Ss + pK * vrcp(rd)));
+  Us[D + 1] = vfma(fac, vfma(Ss - uK, Ss, U[D + 1] * irK), (Ss - uK) * pK * ivS);
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) F[v] = vfma(SKc, Us[v] - U[v], FK[v]);
+}
+
+// Reverse-mode derivative of hllc<double, D, FX>: for the cotangent gF of the
+// flux, gUL = (dF/dUL)^T gF and gUR = (dF/dUR)^T gF.  The forward values are
+// recomputed with the same expressions as hllc, so every branch (the
+// wave-speed bounds, S* >= 0, the min/max against 0) is taken as there; one
+// forward and one reverse sweep give both sides' rows at once.
+template <int D, int FX>
+__device__ inline void hllc_vjp(const double *UL, const double *UR, int a, double g, const double *gF,
+                                double *gUL, double *gUR) {
+  constexpr int NV = D + 2;
+  const double gm1 = g - 1.0;
+  // ---- forward
+  const double rsL = vrsq(UL[0]), rsR = vrsq(UR[0]);
+  const double irL = rsL * rsL, irR = rsR * rsR;
+  double vL[D], vR[D], keL = 0.0, keR = 0.0, uL = 0.0, uR = 0.0, mL = 0.0, mR = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    vL[b] = UL[1 + b] * irL;
+    vR[b] = UR[1 + b] * irR;
+    keL = fma(UL[1 + b], vL[b], keL);
+    keR = fma(UR[1 + b], vR[b], keR);
+    if (b == a) {
+      uL = vL[b];
+      uR = vR[b];
+      mL = UL[1 + b];
+      mR = UR[1 + b];
+    }
+  }
+  const double pL = gm1 * (UL[D + 1] - 0.5 * keL);
+  const double pR = gm1 * (UR[D + 1] - 0.5 * keR);
+  const double kpL = g * pL, kpR = g * pR;  // gamma p
+  const double yL = vrsq(kpL * UL[0]), yR = vrsq(kpR * UR[0]);
+  const double cL = kpL * yL, cR = kpR * yR;
+  double SL, SR;
+  bool sl2, sr2;  // the min/max took its second operand
+  double sL = 0.0, sR = 0.0, is = 0.0, vt[D], q2 = 0.0, ut = 0.0, HL = 0.0, HR = 0.0, ct2 = 0.0, ct = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) vt[b] = 0.0;
+  if constexpr (FX == DG_HLLC_DAVIS) {
+    const double x1 = uL - cL, y1 = uR - cR, x2 = uL + cL, y2 = uR + cR;
+    sl2 = y1 < x1;
+    sr2 = y2 > x2;
+    SL = sl2 ? y1 : x1;
+    SR = sr2 ? y2 : x2;
+  } else {
+    sL = UL[0] * rsL;
+    sR = UR[0] * rsR;
+    is = vrcp(sL + sR);
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      vt[b] = (sL * vL[b] + sR * vR[b]) * is;
+      q2 = fma(vt[b], vt[b], q2);
+      if (b == a) ut = vt[b];
+    }
+    HL = (UL[D + 1] + pL) * irL;
+    HR = (UR[D + 1] + pR) * irR;
+    const double Ht = (sL * HL + sR * HR) * is;
+    ct2 = gm1 * (Ht - 0.5 * q2);
+    ct = ct2 > 0.0 ? ct2 * vrsq(ct2) : 0.0;
+    const double x1 = uL - cL, y1 = ut - ct, x2 = uR + cR, y2 = ut + ct;
+    sl2 = y1 < x1;
+    sr2 = y2 > x2;
+    SL = sl2 ? y1 : x1;
+    SR = sr2 ? y2 : x2;
+  }
+  const double dL = SL - uL, dR = SR - uR;
+  const double iden = vrcp(UL[0] * dL - UR[0] * dR);
+  const double Ss = (pR - pL + mL * dL - mR * dR) * iden;
+  const bool left = Ss >= 0.0;
+  double UK[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) UK[v] = left ? UL[v] : UR[v];
+  const double SK = left ? SL : SR;
+  const bool pass = left ? !(0.0 < SL) : !(0.0 > SR);  // S_K^-/+ equals S_K (else 0)
+  const double SKc = pass ? SK : 0.0;
+  const double irK = left ? irL : irR, pK = left ? pL : pR, uK = left ? uL : uR, dK = left ? dL : dR;
+  const double ivS = vrcp(SK - Ss);
+  const double fac = (UK[0] * dK) * ivS;
+  const double A = fma(Ss - uK, Ss, UK[D + 1] * irK);
+  double Us[NV];
+  Us[0] = fac;
+#pragma unroll
+  for (int b = 0; b < D; ++b) Us[1 + b] = fac * (b == a ? Ss : UK[1 + b] * irK);
+  Us[D + 1] = fma(fac, A, (Ss - uK) * pK * ivS);
+
+  // ---- reverse: F = F_K + SKc (Us - U_K)
+  double gUK[NV], gSKc = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    gSKc = fma(gF[v], Us[v] - UK[v], gSKc);
+    gUK[v] = -SKc * gF[v];
+  }
+  double gfac = SKc * gF[0], gSs = 0.0, guK = 0.0, girK = 0.0, gpK = 0.0, givS = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const double gu = SKc * gF[1 + b];
+    if (b == a) {
+      gfac = fma(gu, Ss, gfac);
+      gSs = fma(gu, fac, gSs);
+    } else {
+      gfac = fma(gu, UK[1 + b] * irK, gfac);
+      gUK[1 + b] = fma(gu, fac * irK, gUK[1 + b]);
+      girK = fma(gu, fac * UK[1 + b], girK);
+    }
+  }
+  {
+    const double ge = SKc * gF[D + 1];
+    gfac = fma(ge, A, gfac);
+    const double gA = ge * fac;
+    gSs = fma(gA, 2.0 * Ss - uK, gSs);
+    guK = fma(-gA, Ss, guK);
+    gUK[D + 1] = fma(gA, irK, gUK[D + 1]);
+    girK = fma(gA, UK[D + 1], girK);
+    const double t = Ss - uK, gt = ge * pK * ivS;
+    gpK = fma(ge, t * ivS, gpK);
+    givS = fma(ge, t * pK, givS);
+    gSs += gt;
+    guK -= gt;
+  }
+  // fac = rho_K d_K ivS, ivS = 1/(S_K - S*)
+  gUK[0] = fma(gfac, dK * ivS, gUK[0]);
+  double gdK = gfac * UK[0] * ivS;
+  givS = fma(gfac, UK[0] * dK, givS);
+  double gSK = -givS * ivS * ivS;
+  gSs = fma(givS, ivS * ivS, gSs);
+  // F_K
+  gUK[1 + a] += gF[0];
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    gUK[1 + b] = fma(gF[1 + b], uK, gUK[1 + b]);
+    guK = fma(gF[1 + b], UK[1 + b], guK);
+  }
+  gpK += gF[1 + a];
+  gUK[D + 1] = fma(gF[D + 1], uK, gUK[D + 1]);
+  gpK = fma(gF[D + 1], uK, gpK);
+  guK = fma(gF[D + 1], UK[D + 1] + pK, guK);
+  if (pass) gSK += gSKc;
+  // d_K = S_K - u_K
+  gSK += gdK;
+  guK -= gdK;
+  // the K side back to L or R
+  double gSL = left ? gSK : 0.0, gSR = left ? 0.0 : gSK;
+  double gpL = left ? gpK : 0.0, gpR = left ? 0.0 : gpK;
+  double guL = left ? guK : 0.0, guR = left ? 0.0 : guK;
+  double girL = left ? girK : 0.0, girR = left ? 0.0 : girK;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    gUL[v] = left ? gUK[v] : 0.0;
+    gUR[v] = left ? 0.0 : gUK[v];
+  }
+  // S* = num / den
+  const double gnum = gSs * iden, gden = -gSs * Ss * iden;
+  gpR += gnum;
+  gpL -= gnum;
+  gUL[1 + a] = fma(gnum, dL, gUL[1 + a]);
+  gUR[1 + a] = fma(-gnum, dR, gUR[1 + a]);
+  double gdL = fma(gnum, mL, gden * UL[0]);
+  double gdR = fma(-gnum, mR, -gden * UR[0]);
+  gUL[0] = fma(gden, dL, gUL[0]);
+  gUR[0] = fma(-gden, dR, gUR[0]);
+  gSL += gdL;
+  guL -= gdL;
+  gSR += gdR;
+  guR -= gdR;
+  // wave-speed bounds
+  double gcL = 0.0, gcR = 0.0;
+  if constexpr (FX == DG_HLLC_DAVIS) {
+    if (sl2) { guR += gSL; gcR -= gSL; } else { guL += gSL; gcL -= gSL; }
+    if (sr2) { guR += gSR; gcR += gSR; } else { guL += gSR; gcL += gSR; }
+  } else {
+    double gut = 0.0, gct = 0.0;
+    if (sl2) { gut += gSL; gct -= gSL; } else { guL += gSL; gcL -= gSL; }
+    if (sr2) { gut += gSR; gct += gSR; } else { guR += gSR; gcR += gSR; }
+    const double gct2 = ct2 > 0.0 ? 0.5 * gct * vrsq(ct2) : 0.0;
+    const double gHt = gct2 * gm1, gq2 = -0.5 * gm1 * gct2;
+    double gsL = gHt * HL * is, gsR = gHt * HR * is, gis = gHt * (sL * HL + sR * HR);
+    const double gHL = gHt * sL * is, gHR = gHt * sR * is;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      const double gv = fma(2.0 * vt[b], gq2, b == a ? gut : 0.0);
+      gsL = fma(gv, vL[b] * is, gsL);
+      gsR = fma(gv, vR[b] * is, gsR);
+      gis = fma(gv, sL * vL[b] + sR * vR[b], gis);
+      // vt depends on vL, vR: folded into the velocity gradients below
+      gUL[1 + b] = fma(gv * sL * is, irL, gUL[1 + b]);
+      girL = fma(gv * sL * is, UL[1 + b], girL);
+      gUR[1 + b] = fma(gv * sR * is, irR, gUR[1 + b]);
+      girR = fma(gv * sR * is, UR[1 + b], girR);
+    }
+    gsL = fma(-gis, is * is, gsL);
+    gsR = fma(-gis, is * is, gsR);
+    // H = (E + p) / rho
+    gUL[D + 1] = fma(gHL, irL, gUL[D + 1]);
+    gpL = fma(gHL, irL, gpL);
+    girL = fma(gHL, UL[D + 1] + pL, girL);
+    gUR[D + 1] = fma(gHR, irR, gUR[D + 1]);
+    gpR = fma(gHR, irR, gpR);
+    girR = fma(gHR, UR[D + 1] + pR, girR);
+    // s = sqrt(rho)
+    gUL[0] = fma(gsL, 0.5 * rsL, gUL[0]);
+    gUR[0] = fma(gsR, 0.5 * rsR, gUR[0]);
+  }
+  // c = sqrt(g p / rho): dc/dp = g y / 2, dc/drho = -c / (2 rho)
+  gpL = fma(gcL, 0.5 * g * yL, gpL);
+  gUL[0] = fma(-gcL, 0.5 * cL * irL, gUL[0]);
+  gpR = fma(gcR, 0.5 * g * yR, gpR);
+  gUR[0] = fma(-gcR, 0.5 * cR * irR, gUR[0]);
+  // u = m_a / rho (as v_a); p = gm1 (E - ke/2), ke = sum m_b v_b, v_b = m_b / rho
+  const double gkeL = -0.5 * gm1 * gpL, gkeR = -0.5 * gm1 * gpR;
+  gUL[D + 1] = fma(gm1, gpL, gUL[D + 1]);
+  gUR[D + 1] = fma(gm1, gpR, gUR[D + 1]);
+#pragma unroll
+  for (int b = 0; b < D; ++b) {
+    const double gvL = fma(gkeL, UL[1 + b], b == a ? guL : 0.0);
+    const double gvR = fma(gkeR, UR[1 + b], b == a ? guR : 0.0);
+    gUL[1 + b] = fma(gkeL, vL[b], fma(gvL, irL, gUL[1 + b]));
+    gUR[1 + b] = fma(gkeR, vR[b], fma(gvR, irR, gUR[1 + b]));
+    girL = fma(gvL, UL[1 + b], girL);
+    girR = fma(gvR, UR[1 + b], girR);
+  }
+  // ir = 1 / rho
+  gUL[0] = fma(-girL, irL * irL, gUL[0]);
+  gUR[0] = fma(-girR, irR * irR, gUR[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,9 +669,13 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     const int h = i % HC, vl = i / HC;
     const int lx = h % HX - 1, ly = h / HX - 1;
     if ((lx < 0 || lx >= TX) && (ly < 0 || ly >= TY)) continue;
-    int gx = (bx0 + lx) % g.nx, gy = (by0 + ly) % g.ny;
-    gx = gx < 0 ? gx + g.nx : gx;
-    gy = gy < 0 ? gy + g.ny : gy;
+    // periodic wrap of the halo; positions past the first halo column/row of
+    // a partial tile are never read and are only kept inside the grid
+    int gx = bx0 + lx, gy = by0 + ly;
+    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+    gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+    gx = min(gx, g.nx - 1);
+    gy = min(gy, g.ny - 1);
     sw[i] = (R)w[(long)vl * nc + (long)gy * g.nx + gx];
   }
   __syncthreads();
@@ -650,9 +842,8 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
 //   faces:  for a face with low cell A and high cell B the flux enters
 //           L_A with -TW(+1) and L_B with +TW(-1); its cotangent is
 //           g = -lam_A . TW(+1) + lam_B . TW(-1), and the own cell receives
-//           (dF/dU_own)^T g lifted with TF, the Jacobian row of the Riemann
-//           solver being computed by forward-mode dual numbers through the
-//           same solver code (so the same branches as the forward pass).
+//           (dF/dU_own)^T g lifted with TF, from one reverse sweep through
+//           the Riemann solver (hllc_vjp, same branches as the forward pass).
 // mode 0: out = mu;  mode 3: out = cb (lam + dt mu), acc_out = ca lam;
 // mode 2: out = cb (lam + dt mu), acc_out = acc + ca lam;
 // mode 1: out = acc + lam + dt mu.
@@ -743,68 +934,46 @@ __global__ __launch_bounds__(256) void k_adjoint(const double *__restrict__ tab,
     for (int s = 0; s < 2; ++s) {
       const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
       const long src = nb >= 0 ? nb : cell;
-      double wb[C::NV][C::N], lb[C::NV][C::N];
-#pragma unroll
-      for (int v = 0; v < C::NV; ++v)
-#pragma unroll
-        for (int l = 0; l < C::N; ++l) {
-          const long i = (long)(v * C::N + l) * nc + src;
-          wb[v][l] = w[i];
-          lb[v][l] = lam[i];
-        }
+      // own side: trace with TF(s), lambda against TW(s); neighbour side with
+      // TF(1-s), TW(1-s) (the low cell's lambda meets TW(+1), the high cell's
+      // TW(-1)); the neighbour's weights are streamed from L1/L2 per node
       const double *to = tab + C::TF + (a * 2 + s) * C::QF * C::N;
       const double *tn = tab + C::TF + (a * 2 + (1 - s)) * C::QF * C::N;
-      const double *tw_hi = tab + C::TW + (a * 2 + 1) * C::QF * C::N;  // lift weights of the low cell (xi_a = +1)
-      const double *tw_lo = tab + C::TW + (a * 2 + 0) * C::QF * C::N;  // lift weights of the high cell (xi_a = -1)
+      const double *two = tab + C::TW + (a * 2 + s) * C::QF * C::N;
+      const double *twn = tab + C::TW + (a * 2 + (1 - s)) * C::QF * C::N;
 #pragma unroll 1
       for (int r = 0; r < C::QF; ++r) {
         double Uo[C::NV], Un[C::NV], gv[C::NV];
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) {
-          double so = 0.0, sn = 0.0, lo_c = 0.0, hi_c = 0.0;
+          double so = 0.0, sn = 0.0, lo = 0.0, ln = 0.0;
 #pragma unroll
           for (int l = 0; l < C::N; ++l) {
+            const long i = (long)(v * C::N + l) * nc + src;
             so = fma(wc[v][l], to[r * C::N + l], so);
-            sn = fma(wb[v][l], tn[r * C::N + l], sn);
+            sn = fma(w[i], tn[r * C::N + l], sn);
+            lo = fma(lc[v][l], two[r * C::N + l], lo);
+            ln = fma(lam[i], twn[r * C::N + l], ln);
           }
-          // lam of the low cell against TW(+1), of the high cell against TW(-1)
-          const double (*lowc)[C::N] = s ? lc : lb;
-          const double (*highc)[C::N] = s ? lb : lc;
-#pragma unroll
-          for (int l = 0; l < C::N; ++l) {
-            lo_c = fma(lowc[v][l], tw_hi[r * C::N + l], lo_c);
-            hi_c = fma(highc[v][l], tw_lo[r * C::N + l], hi_c);
-          }
-          if (nb < 0) {  // the ghost cell of a transmissive boundary has no equation
-            if (s) hi_c = 0.0; else lo_c = 0.0;
-          }
+          if (nb < 0) ln = 0.0;  // the ghost cell of a transmissive boundary has no equation
           Uo[v] = so;
           Un[v] = nb >= 0 ? sn : so;
-          gv[v] = hi_c - lo_c;
+          gv[v] = s ? ln - lo : lo - ln;  // lam_high . TW(-1) - lam_low . TW(+1)
         }
-#pragma unroll 1
+        // (dF/dU_own)^T g by one reverse sweep through the Riemann solver; a
+        // transmissive ghost copies the own trace, so both sides count
+        double UL[C::NV], UR[C::NV], gL[C::NV], gR[C::NV];
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) {
+          UL[v] = s ? Uo[v] : Un[v];
+          UR[v] = s ? Un[v] : Uo[v];
+        }
+        hllc_vjp<D, FX>(UL, UR, a, g.gamma, gv, gL, gR);
+#pragma unroll
         for (int u = 0; u < C::NV; ++u) {
-          Dual UL[C::NV], UR[C::NV], F[C::NV];
+          const double h = (s ? gL[u] : gR[u]) + (nb >= 0 ? 0.0 : (s ? gR[u] : gL[u]));
 #pragma unroll
-          for (int v = 0; v < C::NV; ++v) {
-            const double t = (v == u) ? 1.0 : 0.0;
-            const double own = Uo[v], oth = Un[v];
-            const double to_own = t, to_oth = nb >= 0 ? 0.0 : t;
-            UL[v] = s ? Dual{own, to_own} : Dual{oth, to_oth};
-            UR[v] = s ? Dual{oth, to_oth} : Dual{own, to_own};
-          }
-          hllc<Dual, D, FX>(UL, UR, a, g.gamma, F);
-          double h = 0.0;
-#pragma unroll
-          for (int v = 0; v < C::NV; ++v) h = fma(gv[v], F[v].d, h);
-          // mu[u][l] += h * TF_own[r][l]; u is a runtime index, so update every
-          // row with a mask to keep mu in registers
-#pragma unroll
-          for (int uu = 0; uu < C::NV; ++uu) {
-            const double hh = (uu == u) ? h : 0.0;
-#pragma unroll
-            for (int l = 0; l < C::N; ++l) mu[uu][l] = fma(hh, to[r * C::N + l], mu[uu][l]);
-          }
+          for (int l = 0; l < C::N; ++l) mu[u][l] = fma(h, to[r * C::N + l], mu[u][l]);
         }
       }
     }
