@@ -48,6 +48,26 @@ _FINGERPRINT_REGIONS = [
 ]
 
 
+FP32_PEAK_TFLOPS = 157.3
+
+
+def alg_work(d: int, k: int):
+    """Algorithmic bytes and flops per cell per RK stage (fused RHS + stage,
+    each face evaluated once): 8/3 state passes; modal->nodal, projection onto
+    the basis gradients, both traces of the d owned faces and the lifting as
+    dense multiply-adds (2 flops each), about 12 flops per volume node and
+    direction for the Euler flux and 110 per face node for HLLC."""
+    nvar = d + 2
+    n1 = k + 1
+    N = (k + 1) * (k + 2) // 2 if d == 2 else (k + 1) * (k + 2) * (k + 3) // 6
+    Q = n1 ** d
+    QF = Q // n1
+    bytes_ = 8.0 / 3.0 * nvar * N * 8
+    flops = (2 * nvar * N * Q + 2 * d * nvar * Q * (N - 1) + 2 * (2 * 2 * d * nvar * N * QF)
+             + 12 * Q * d + 110 * d * QF)
+    return bytes_, float(flops)
+
+
 def kernel_hash() -> str:
     """Fingerprint of the source of the benchmarked stage kernel (the tiled 2D
     kernel, the Riemann solver and its reciprocal helpers)."""
@@ -173,9 +193,16 @@ def variants():
             s = dg.Solver(wl, prec)
             ms, _ = time_steps(s, wl, steps, 4)
             cells = (s.ncoarse - s.nhole + s.nfine) if s.amr else s.ncell
+            b, f = alg_work(wl["dim"], wl["k"])
+            peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+            # fractions of one step's algorithmic work (3 stages) over the
+            # whole step time (time step and limiters included)
             out[f"{name}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": cells * s.N * 3 / (ms * 1e-3),
                                      "cells": cells, "k": wl["k"], "dim": wl["dim"],
-                                     "limited": bool(s.limited), "eps": wl["eps"], "status": s.status()}
+                                     "limited": bool(s.limited), "eps": wl["eps"], "status": s.status(),
+                                     "hbm_frac": 3 * b * cells / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                     "alu_frac": 3 * f * cells / (ms * 1e-3) / (peak * 1e12),
+                                     "alu_peak_tflops": peak}
             del s
             torch.cuda.empty_cache()
     # adjoint: 512^2, k=3, J = int rho^2 after 400 steps at fixed dt, checkpoint 20
@@ -282,22 +309,26 @@ def main():
     ms_step = el / args.steps * 1e3
     value = dof * 3 * args.steps / el
 
-    # average duration of the dominant kernel (fused RHS + stage), HIP events
-    # on the stream it is launched on
-    reps = 60
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    # average duration of the dominant kernel (fused RHS + stage): one pair of
+    # HIP events on the stream the kernels run on around a batch of launches
+    # queued back to back (stages 1, 2, 3 in turn)
+    reps = 300
     dt = s.max_dt(w, bufs[3])
+    for stage in (1, 2, 3):
+        s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], bufs[1] if stage == 1 else bufs[2])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
     for i in range(reps):
         stage = i % 3 + 1
-        evs[i][0].record(stream)
         s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], bufs[1] if stage == 1 else bufs[2])
-        evs[i][1].record(stream)
+    e1.record(stream)
     torch.cuda.synchronize()
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    k_ms = e0.elapsed_time(e1) / reps
     state_bytes = s.nvar * s.N * s.ncell * 8
     alg_bytes = 8.0 / 3.0 * state_bytes  # read w_prev (+ w_n in stages 2,3), write w_out
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     traffic = measured_traffic()
+    alg_flops = alg_work(2, 2)[1] * s.ncell
 
     rec = {
         "metric": METRIC,
@@ -319,6 +350,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_rhs_tile2d<2,double>", "kernel_ms": k_ms,
                      "alg_bytes_per_launch": alg_bytes},
+        # the same launch against the FP64 vector peak (algorithmic flops)
+        "roofline_fp64": {"bound": "alu", "achieved": alg_flops / (k_ms * 1e-3) / 1e12,
+                          "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                          "frac": alg_flops / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                          "alg_flops_per_launch": alg_flops},
     }
     if args.variants:
         rec["variants"] = variants()
