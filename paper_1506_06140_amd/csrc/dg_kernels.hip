@@ -793,6 +793,16 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
 #pragma unroll
     for (int l = 1; l < N; ++l) accv[l] = (R)vext[(long)(sub * N + l) * nc + c2];
   }
+  // the stage update's operands (variable sub of the own cell), loaded before
+  // the barrier so that their latency overlaps it and the lift
+  double wo[N], wno[N];
+  const long cell = (long)(by0 + min(ty, nyt - 1)) * g.nx + (bx0 + min(tx, nxt - 1));
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const long i = (long)(sub * N + l) * nc + cell;
+    wo[l] = (mode != 0) ? w[i] : 0.0;
+    wno[l] = (mode == 2) ? wn[i] : 0.0;
+  }
   __syncthreads();
   if (!real) return;
 
@@ -814,7 +824,6 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       for (int l = 1; l < N; ++l) accv[l] = fma(fv, tw[l], accv[l]);
     }
   }
-  const long cell = (long)(by0 + ty) * g.nx + (bx0 + tx);
   bool bad = false;
   const double dt = (mode == 0) ? 0.0 : *dtp;
 #pragma unroll
@@ -825,8 +834,8 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     if (mode == 0) {
       out[i] = L;
     } else {
-      const double o = w[i] + dt * L;
-      out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
+      const double o = wo[l] + dt * L;
+      out[i] = (mode == 1) ? o : ca * wno[l] + cb * o;
     }
   }
   if (bad) atomicOr(flag, FLAG_NAN);
@@ -1287,7 +1296,7 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
   using C = Cfg<D, K>;
   using M = Mfma<D, K>;
   constexpr int NV = C::NV, N = C::N, QP = M::QP, NP = M::NP;
-  __shared__ __bf16 fs[4][NV][D][16][QP];
+  __shared__ __bf16 fs[4][NV][16][QP];  // one flux direction at a time, per wave
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
   const long c0 = ((long)blockIdx.x * 4 + wv) * 16;
@@ -1311,20 +1320,27 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
       U[v][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, z, 0, 0, 0);
     }
   }
-  // Euler flux at (cell 4 grp + i, node 16 t + row), stored as BF16
+  // stages A' and B per direction: the Euler flux f_a at (cell 4 grp + i,
+  // node 16 t + row) into LDS as BF16, then its projection onto the gradient
+  // table of direction a, accumulated over a in FP32
+  constexpr int MT = (N + 15) / 16;  // only the tiles that hold modes
+  f32x4 acc[NV][MT];
 #pragma unroll
-  for (int t = 0; t < M::NQT; ++t)
+  for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int q = 16 * t + row;
-      const int cl = 4 * grp + i;
-      const bool ok = q < C::Q && c0 + cl < nc;
-      float Uq[NV];
+    for (int mt = 0; mt < MT; ++mt) acc[v][mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Uq[v] = U[v][t][i];
+  for (int a = 0; a < D; ++a) {
 #pragma unroll
-      for (int a = 0; a < D; ++a) {
-        float F[NV];
+    for (int t = 0; t < M::NQT; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int q = 16 * t + row;
+        const int cl = 4 * grp + i;
+        const bool ok = q < C::Q && c0 + cl < nc;
+        float Uq[NV], F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Uq[v] = U[v][t][i];
         if (ok) {
           euler_flux<D, float>(Uq, a, gm1, F);
         } else {
@@ -1332,32 +1348,40 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
           for (int v = 0; v < NV; ++v) F[v] = 0.0f;
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) fs[wv][v][a][cl][q] = (__bf16)F[v];
+        for (int v = 0; v < NV; ++v) fs[wv][v][cl][q] = (__bf16)F[v];
       }
-    }
-  __syncthreads();
-  // stage B: projection onto the basis gradients
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int ch = 0; ch < M::NQC; ++ch) {
+          const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&fs[wv][v][row][ch * 32 + 8 * grp]);
+          const bf16x8 B =
+              *reinterpret_cast<const bf16x8 *>(tb + M::DB + (a * NP + mt * 16 + row) * QP + ch * 32 + 8 * grp);
+          acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[v][mt], 0, 0, 0);
+        }
+    __syncthreads();  // the next direction overwrites fs
+  }
+  // lane (row, grp) holds mode j of the four consecutive cells c0 + 4 grp + i:
+  // one 16-byte store when they are all in range and the address is aligned
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
-    for (int mt = 0; mt < NP / 16; ++mt) {
-      f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-      for (int a = 0; a < D; ++a)
-#pragma unroll
-        for (int ch = 0; ch < M::NQC; ++ch) {
-          const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&fs[wv][v][a][row][ch * 32 + 8 * grp]);
-          const bf16x8 B =
-              *reinterpret_cast<const bf16x8 *>(tb + M::DB + (a * NP + mt * 16 + row) * QP + ch * 32 + 8 * grp);
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc, 0, 0, 0);
-        }
+    for (int mt = 0; mt < MT; ++mt) {
       const int j = mt * 16 + row;
-      if (j < N)
+      const long cb = c0 + 4 * grp;
+      if (j < N) {
+        float *dst = vout + (long)(v * N + j) * nc + cb;
+        if (cb + 3 < nc && (reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+          *reinterpret_cast<f32x4 *>(dst) = acc[v][mt];
+        } else {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const long cell = c0 + 4 * grp + i;
-          if (cell < nc) vout[(long)(v * N + j) * nc + cell] = acc[i];
+          for (int i = 0; i < 4; ++i)
+            if (cb + i < nc) dst[i] = acc[v][mt][i];
         }
+      }
     }
 }
 
