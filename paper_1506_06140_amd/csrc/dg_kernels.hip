@@ -1218,7 +1218,8 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
     for (int v = 0; v < C::NV; ++v) Ub[v] = wc[v][0];
     double keb = 0.0;
 #pragma unroll
-    for (int b = 0; b < D; ++b) keb += Ub[1 + b] * Ub[1 + b] / Ub[0];
+    for (int b = 0; b < D; ++b) keb = fma(Ub[1 + b], Ub[1 + b], keb);
+    keb *= vrcp(Ub[0]);
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
     if (!(Ub[0] > eps) || !(pb > eps)) {
       atomicOr(flag, FLAG_NEGATIVE);
@@ -1245,7 +1246,8 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
         }
         double ke = 0.0;
 #pragma unroll
-        for (int b = 0; b < D; ++b) ke += Uq[1 + b] * Uq[1 + b] / Uq[0];
+        for (int b = 0; b < D; ++b) ke = fma(Uq[1 + b], Uq[1 + b], ke);
+        ke *= vrcp(Uq[0]);  // |m|^2 / rho with one reciprocal per point
         const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
         if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
       }
@@ -1769,7 +1771,8 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
     for (int v = 0; v < NV; ++v) Ub[v] = wc[v][0];
     double keb = 0.0;
 #pragma unroll
-    for (int b = 0; b < D; ++b) keb += Ub[1 + b] * Ub[1 + b] / Ub[0];
+    for (int b = 0; b < D; ++b) keb = fma(Ub[1 + b], Ub[1 + b], keb);
+    keb *= vrcp(Ub[0]);
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
     if (!(Ub[0] > eps) || !(pb > eps)) {
       atomicOr(flag, FLAG_NEGATIVE);
@@ -1815,7 +1818,8 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
         }
         double ke = 0.0;
 #pragma unroll
-        for (int b = 0; b < D; ++b) ke += Uq[1 + b] * Uq[1 + b] / Uq[0];
+        for (int b = 0; b < D; ++b) ke = fma(Uq[1 + b], Uq[1 + b], ke);
+        ke *= vrcp(Uq[0]);  // |m|^2 / rho with one reciprocal per point
         const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
         if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
       }
