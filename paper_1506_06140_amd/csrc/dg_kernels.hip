@@ -1622,6 +1622,298 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
   if (bad) atomicOr(flag, FLAG_NAN);
 }
 
+// ---------------------------------------------------------------------------
+// Refined-box RHS + stage at d = 3 with four lanes per cell (a quad), for the
+// FP64 path at k = 3, where one thread per cell needs more registers than a
+// lane has.  Lane s owns variable s and the energy modes [s M4, (s+1) M4):
+// its weights, its accumulators, and per face the same slice of the
+// neighbour's weights.  Nodes are taken four at a time: every lane forms its
+// owned part of the traces (or nodal values) at the four nodes, a quad
+// transpose hands lane t the full state at node t (energy partials summed in
+// a fixed order), lane t evaluates the flux there, and a transpose back (plus
+// a broadcast of the energy flux) returns to lane s the fluxes of its own
+// variable at the four nodes for the projection or the lift.  Both cells of a
+// face form each trace from the same weights, tables and summation order, so
+// they still obtain the identical flux.
+// ---------------------------------------------------------------------------
+// value of lane J of the quad
+template <int J>
+__device__ inline double quad_from(double x) {
+  return quad_swap<J | (J << 2) | (J << 4) | (J << 6)>(x);
+}
+// lane s holds row s of a 4x4 block; afterwards it holds column s
+__device__ inline void quad_transpose(double (&x)[4], int sub) {
+  const bool b1 = sub & 2, b0 = sub & 1;
+  double r0 = quad_swap<kQuadXor2>(b1 ? x[0] : x[2]);
+  double r1 = quad_swap<kQuadXor2>(b1 ? x[1] : x[3]);
+  const double y0 = b1 ? r0 : x[0], y1 = b1 ? r1 : x[1], y2 = b1 ? x[2] : r0, y3 = b1 ? x[3] : r1;
+  r0 = quad_swap<kQuadXor1>(b0 ? y0 : y1);
+  r1 = quad_swap<kQuadXor1>(b0 ? y2 : y3);
+  x[0] = b0 ? r0 : y0;
+  x[1] = b0 ? y1 : r0;
+  x[2] = b0 ? r1 : y2;
+  x[3] = b0 ? y3 : r1;
+}
+
+template <int K, int FX>
+__global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__ tab, const double *__restrict__ w,
+                                                      const double *__restrict__ wn, double *__restrict__ out,
+                                                      const double *__restrict__ dtp, AmrGrid g, int mode, double ca,
+                                                      double cb, int *__restrict__ flag) {
+  constexpr int D = 3;
+  using C = Cfg<D, K>;
+  constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N, NSUB = 4;
+  constexpr int M4 = (N + 3) / 4;
+  static_assert(QF % 4 == 0 && Q % 4 == 0, "nodes in rounds of four");
+  const long tid = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const int sub = threadIdx.x & 3;
+  if (tid >= g.ncc + g.ncf) return;  // the four lanes of a cell leave together
+  const bool fine = tid >= g.ncc;
+  const long cell = fine ? tid - g.ncc : tid;
+  const long ncb = fine ? g.ncf : g.ncc;
+  const double *wcb = w, *wfb = w + (long)NW * g.ncc;
+  const double *wb = fine ? wfb : wcb;
+  const long boff = fine ? (long)NW * g.ncc : 0;
+  const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
+  int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
+  const double dt = (mode == 0) ? 0.0 : *dtp;
+  if (!fine && amr_in_hole<D>(g, i)) {
+#pragma unroll 1
+    for (int vl = sub; vl < NW; vl += 4) {
+      const long ii = boff + (long)vl * ncb + cell;
+      out[ii] = (mode == 0) ? 0.0 : (mode == 1) ? w[ii] : ca * wn[ii] + cb * w[ii];
+    }
+    return;
+  }
+  const double gm1 = g.gamma - 1.0;
+  double wo[N], we[M4], acc[N], acce[M4];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    wo[l] = wb[(long)(sub * N + l) * ncb + cell];
+    acc[l] = 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < M4; ++m) {
+    const int j = sub * M4 + m;
+    we[m] = (j < N) ? wb[(long)(4 * N + j) * ncb + cell] : 0.0;
+    acce[m] = 0.0;
+  }
+
+  // volume integral (eq. dg_term2), nodes q0 .. q0+3 per round
+#pragma unroll 1
+  for (int q0 = 0; q0 < Q; q0 += 4) {
+    double u[4], e[4];
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+      const double *bq = tab + C::B + (q0 + t) * N;
+      double su = 0.0, se = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) su = fma(wo[l], bq[l], su);
+#pragma unroll
+      for (int m = 0; m < M4; ++m) {
+        const int j = sub * M4 + m;
+        se = fma(we[m], bq[j < N ? j : 0], se);
+      }
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) {
+        u[tt] = (tt == t) ? su : u[tt];
+        e[tt] = (tt == t) ? se : e[tt];
+      }
+    }
+    quad_transpose(u, sub);
+    quad_transpose(e, sub);
+    double U[NV] = {u[0], u[1], u[2], u[3], (e[0] + e[1]) + (e[2] + e[3])};
+    const double ir = vrcp(U[0]);
+    double vel[D], ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+      vel[b] = U[1 + b] * ir;
+      ke = fma(U[1 + b], vel[b], ke);
+    }
+    const double p = gm1 * (U[4] - 0.5 * ke);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double fv[4] = {U[1 + a], 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int b = 0; b < D; ++b) fv[1 + b] = fma(U[1 + b], vel[a], b == a ? p : 0.0);
+      const double fe_own = (U[4] + p) * vel[a];
+      quad_transpose(fv, sub);  // fv[t]: flux of variable sub at node q0 + t
+      const double fe[4] = {quad_from<0>(fe_own), quad_from<1>(fe_own), quad_from<2>(fe_own), quad_from<3>(fe_own)};
+#pragma unroll 1
+      for (int t = 0; t < 4; ++t) {
+        const double *dw = tab + C::DW + (a * Q + q0 + t) * N;
+        double ft = fv[0], f4t = fe[0];
+#pragma unroll
+        for (int tt = 1; tt < 4; ++tt) {
+          ft = (tt == t) ? fv[tt] : ft;
+          f4t = (tt == t) ? fe[tt] : f4t;
+        }
+#pragma unroll
+        for (int l = 1; l < N; ++l) acc[l] = fma(ft, dw[l], acc[l]);
+#pragma unroll
+        for (int m = 0; m < M4; ++m) {
+          const int j = sub * M4 + m;
+          if (j >= 1 && j < N) acce[m] = fma(f4t, dw[j], acce[m]);
+        }
+      }
+    }
+  }
+
+  // faces (eq. dg_term3), hanging faces as in k_rhs_amr
+#pragma unroll 1
+  for (int a = 0; a < D; ++a) {
+    const int t0 = (a == 0) ? 1 : 0, t1 = (a == 2) ? 1 : 2;
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      int kind = 0;
+      long nbcell = cell;
+      const double *nbb = wb;
+      long nbn = ncb;
+      int j[3] = {0, 0, 0}, hsub = 0;
+      if (!fine) {
+        if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
+          kind = 1;
+        } else if (amr_in_hole<D>(g, j)) {
+          kind = 2;
+        } else {
+          nbcell = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+        }
+      } else {
+        int f2[3] = {i[0], i[1], i[2]};
+        f2[a] += s ? 1 : -1;
+        if (f2[a] >= 0 && f2[a] < g.nf[a]) {
+          nbcell = ((long)f2[2] * g.nf[1] + f2[1]) * g.nf[0] + f2[0];
+        } else {
+          kind = 3;
+          int base[3] = {0, 0, 0};
+#pragma unroll
+          for (int b = 0; b < D; ++b) base[b] = g.lo[b] + i[b] / 2;
+          amr_coarse_nb<D>(g, base, a, s ? 1 : -1, j);
+          nbcell = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+          nbb = wcb;
+          nbn = g.ncc;
+          hsub = (i[t0] & 1) | ((i[t1] & 1) << 1);
+        }
+      }
+      const int nsub = (kind == 2) ? NSUB : 1;
+#pragma unroll 1
+      for (int sb = 0; sb < nsub; ++sb) {
+        if (kind == 2) {
+          int fi[3] = {0, 0, 0};
+          fi[a] = 2 * (j[a] - g.lo[a]) + (s ? 0 : 1);
+          fi[t0] = 2 * (j[t0] - g.lo[t0]) + (sb & 1);
+          fi[t1] = 2 * (j[t1] - g.lo[t1]) + ((sb >> 1) & 1);
+          nbcell = ((long)fi[2] * g.nf[1] + fi[1]) * g.nf[0] + fi[0];
+          nbb = wfb;
+          nbn = g.ncf;
+          hsub = sb;
+        }
+        // the neighbour's slice of weights owned by this lane
+        double no[N], ne[M4];
+        {
+          const double *pn = nbb + (long)(sub * N) * nbn + nbcell;
+#pragma unroll
+          for (int l = 0; l < N; ++l, pn += nbn) no[l] = *pn;
+          const double *pe = nbb + (long)(4 * N + sub * M4) * nbn + nbcell;
+#pragma unroll
+          for (int m = 0; m < M4; ++m, pe += nbn) ne[m] = (sub * M4 + m < N) ? *pe : 0.0;
+        }
+        const double *to = (kind == 2) ? tab + C::HG + ((a * 2 + s) * 4 + hsub) * QF * N
+                                       : tab + C::TF + (a * 2 + s) * QF * N;
+        const double *tn = (kind == 3) ? tab + C::HG + ((a * 2 + (1 - s)) * 4 + hsub) * QF * N
+                                       : tab + C::TF + (a * 2 + (1 - s)) * QF * N;
+        const double *tw = (kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + hsub) * QF * N
+                                       : tab + C::TW + (a * 2 + s) * QF * N;
+#pragma unroll 1
+        for (int r0 = 0; r0 < QF; r0 += 4) {
+          // one node at a time (the tables of a hanging face differ between
+          // cells, so they are vector loads; this bounds how many are live)
+          double uo[4], eo[4], un[4], en[4];
+#pragma unroll 1
+          for (int t = 0; t < 4; ++t) {
+            const double *ro = to + (r0 + t) * N, *rn = tn + (r0 + t) * N;
+            double so = 0.0, sn = 0.0, xo = 0.0, xn = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) {
+              so = fma(wo[l], ro[l], so);
+              sn = fma(no[l], rn[l], sn);
+            }
+#pragma unroll
+            for (int m = 0; m < M4; ++m) {
+              const int jj = sub * M4 + m;
+              xo = fma(we[m], ro[jj < N ? jj : 0], xo);
+              xn = fma(ne[m], rn[jj < N ? jj : 0], xn);
+            }
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+              uo[tt] = (tt == t) ? so : uo[tt];
+              un[tt] = (tt == t) ? sn : un[tt];
+              eo[tt] = (tt == t) ? xo : eo[tt];
+              en[tt] = (tt == t) ? xn : en[tt];
+            }
+          }
+          quad_transpose(uo, sub);
+          quad_transpose(eo, sub);
+          quad_transpose(un, sub);
+          quad_transpose(en, sub);
+          double Uo[NV] = {uo[0], uo[1], uo[2], uo[3], (eo[0] + eo[1]) + (eo[2] + eo[3])};
+          double Un[NV] = {un[0], un[1], un[2], un[3], (en[0] + en[1]) + (en[2] + en[3])};
+          double UL[NV], UR[NV], F[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const double nv = (kind == 1) ? Uo[v] : Un[v];  // wall: ghost trace = own trace
+            UL[v] = s ? Uo[v] : nv;
+            UR[v] = s ? nv : Uo[v];
+          }
+          hllc<double, D, FX>(UL, UR, a, g.gamma, F);
+          double fv[4] = {F[0], F[1], F[2], F[3]};
+          quad_transpose(fv, sub);  // fv[t]: flux of variable sub at node r0 + t
+          const double fe[4] = {quad_from<0>(F[4]), quad_from<1>(F[4]), quad_from<2>(F[4]), quad_from<3>(F[4])};
+#pragma unroll 1
+          for (int t = 0; t < 4; ++t) {
+            const double *rw = tw + (r0 + t) * N;
+            double ft = fv[0], f4t = fe[0];
+#pragma unroll
+            for (int tt = 1; tt < 4; ++tt) {
+              ft = (tt == t) ? fv[tt] : ft;
+              f4t = (tt == t) ? fe[tt] : f4t;
+            }
+            const double f = s ? -ft : ft, f4 = s ? -f4t : f4t;
+#pragma unroll
+            for (int l = 0; l < N; ++l) acc[l] = fma(f, rw[l], acc[l]);
+#pragma unroll
+            for (int m = 0; m < M4; ++m) {
+              const int jj = sub * M4 + m;
+              if (jj < N) acce[m] = fma(f4, rw[jj], acce[m]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  const double fac = fine ? g.facf : g.facc;
+  bool bad = false;
+  auto emit = [&](int vl, double L) {
+    const long ii = boff + (long)vl * ncb + cell;
+    bad |= (L != L);
+    if (mode == 0) {
+      out[ii] = L;
+    } else {
+      const double o = w[ii] + dt * L;
+      out[ii] = (mode == 1) ? o : ca * wn[ii] + cb * o;
+    }
+  };
+#pragma unroll
+  for (int l = 0; l < N; ++l) emit(sub * N + l, fac * acc[l]);
+#pragma unroll
+  for (int m = 0; m < M4; ++m) {
+    const int jj = sub * M4 + m;
+    if (jj < N) emit(4 * N + jj, fac * acce[m]);
+  }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
 // Time step over both blocks (each cell with its own edge length); same
 // two-kernel reduction as k_rate / k_dt_final.
 template <int D>
@@ -1938,8 +2230,14 @@ struct StageLaunch {
   template <int D, int K, class R, int FX>
   int launch_fx(const R *tabr, const float *vext) {
     if (c->amr) {
-      hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, tabr,
-                         w, wn, out, dt, vext, make_amr_grid(c), mode, ca, cb, c->flag);
+      if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
+        // four lanes per cell (the one-thread kernel would spill)
+        hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0, s,
+                           c->tab, w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
+      } else {
+        hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab,
+                           tabr, w, wn, out, dt, vext, make_amr_grid(c), mode, ca, cb, c->flag);
+      }
     } else if constexpr (D == 2) {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
