@@ -141,12 +141,15 @@ def time_steps(s, wl, steps, warmup, graph=True):
     if s.limited:
         s.limit(A)
     B = s.empty()
-    u1, u2, dtbuf = s.empty(), s.empty(), s.scalar()
+    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.scalar()
     stream = torch.cuda.current_stream()
+    s.max_rate(A, rate)
 
     def two_steps():
-        s.step(A, [u1, u2, B, dtbuf])
-        s.step(B, [u1, u2, A, dtbuf])
+        # one library call per step; the signal rate of the new state is
+        # carried in `rate` to the next step's time step
+        s.rk_step(A, [u1, u2, B], dtbuf, rate)
+        s.rk_step(B, [u1, u2, A], dtbuf, rate)
 
     steps = steps + (steps % 2)
     for _ in range((warmup + 1) // 2):
@@ -262,13 +265,15 @@ def main():
     s = dg.Solver(wl)
     A = build_state(s, wl)
     B = s.empty()
-    u1, u2, dtbuf = s.empty(), s.empty(), s.scalar()
+    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.scalar()
     stream = torch.cuda.current_stream()
+    s.max_rate(A, rate)
 
     def two_steps():
-        # ping-pong: A -> B -> A, stage buffers u1, u2, device time step dtbuf
-        s.step(A, [u1, u2, B, dtbuf])
-        s.step(B, [u1, u2, A, dtbuf])
+        # ping-pong: A -> B -> A, stage buffers u1, u2, device time step
+        # dtbuf; each step is one dg_rk_step call (time step, 3 stages)
+        s.rk_step(A, [u1, u2, B], dtbuf, rate)
+        s.rk_step(B, [u1, u2, A], dtbuf, rate)
 
     steps = args.steps + (args.steps % 2)
     for _ in range((args.warmup + 1) // 2):

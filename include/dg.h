@@ -137,6 +137,29 @@ int dg_max_dt(dg_ctx *ctx, const double *w, double *dt_dev, void *stream);
 int dg_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *w_n,
                 const double *w_prev, double *w_out, void *stream);
 
+/* Maximum over cells of the signal rate sum_a (|v_a| + c)/dx of the cell
+ * means of w (the denominator of eq. time_step), written to rate_dev[0] on
+ * the device: the value dg_rk_step expects for the state it starts from.
+ * Sets DG_ENEGATIVE for a non-positive mean density or pressure. */
+int dg_max_rate(dg_ctx *ctx, const double *w, double *rate_dev, void *stream);
+
+/* One full SSP-RK3 step (App. D, table RK_3) with the configured limiters
+ * after every stage (Sec. 4.5 without refinement):
+ *   dt = CFL f_k / rate_dev[0]  (eq. time_step / time_step_pos),
+ *   u1 = stage 1 of w, u2 = stage 2, w_out = stage 3.
+ * On entry rate_dev[0] must hold the maximum signal rate of w, as written by
+ * dg_max_rate(w) or by the dg_rk_step that produced w; on return it holds
+ * that of w_out (the limiters keep cell means, so it is also the rate of the
+ * limited state), so that steps chain without a separate time-step pass.
+ * dt_dev[0] receives the step's dt.  Results equal dg_max_dt, three
+ * dg_rk_stage and dg_limit calls bit for bit.  w, u1, u2 and w_out must be
+ * four distinct states, dt_dev and rate_dev distinct device scalars;
+ * otherwise DG_EINVAL.  On a 2D grid without refinement the time-step work
+ * rides in the three stage kernels; elsewhere two small kernels carry it.
+ * Two calls that share rate_dev must not run concurrently. */
+int dg_rk_step(dg_ctx *ctx, const double *w, double *u1, double *u2, double *w_out,
+               double *dt_dev, double *rate_dev, void *stream);
+
 /* Slope limiter (component-wise minmod with TVB bound, Sec. 3.1/3.3) then
  * positivity limiter (Sec. 3.4), in place, as configured.  Cell means are
  * never changed.  A cell whose mean density or pressure is <= eps sets the

@@ -42,7 +42,7 @@ class dg_config(C.Structure):
 
 EXPORTS = (
     "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
-    "dg_max_dt", "dg_rk_stage", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage",
+    "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage",
     "dg_status", "dg_destroy", "dg_strerror",
 )
 
@@ -68,6 +68,8 @@ def load_library(path: str = LIB_PATH):
     lib.dg_rhs.argtypes = [ctxp, dp, dp, vp]
     lib.dg_max_dt.argtypes = [ctxp, dp, dp, vp]
     lib.dg_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, vp]
+    lib.dg_max_rate.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_rk_step.argtypes = [ctxp, dp, dp, dp, dp, dp, dp, vp]
     lib.dg_limit.argtypes = [ctxp, dp, vp]
     lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
     lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
@@ -227,6 +229,22 @@ class Solver:
         wn_p = self._s(wn) if wn is not None else None
         _check(self.lib.dg_rk_stage(self.ctx, stage, _ptr(dt, 1), wn_p, self._s(wp), self._s(out), _stream(stream)),
                "dg_rk_stage")
+        return out
+
+    def max_rate(self, w, rate=None, stream=None):
+        """Maximum signal rate of w's cell means into a one-element device tensor."""
+        rate = self.scalar() if rate is None else rate
+        _check(self.lib.dg_max_rate(self.ctx, self._s(w), _ptr(rate, 1), _stream(stream)), "dg_max_rate")
+        return rate
+
+    def rk_step(self, w, bufs, dt, rate, stream=None):
+        """One SSP-RK3 step with limiters from w into bufs[2] (bufs[0], bufs[1]
+        are the stage buffers) in one library call.  rate holds the maximum
+        signal rate of w on entry (max_rate, or the previous rk_step) and of
+        the result on return; dt receives the step.  Returns bufs[2]."""
+        u1, u2, out = bufs[0], bufs[1], bufs[2]
+        _check(self.lib.dg_rk_step(self.ctx, self._s(w), self._s(u1), self._s(u2), self._s(out), _ptr(dt, 1),
+                                   _ptr(rate, 1), _stream(stream)), "dg_rk_step")
         return out
 
     def limit(self, w, stream=None):

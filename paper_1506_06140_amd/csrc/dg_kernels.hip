@@ -97,6 +97,35 @@ __device__ inline float vrsq(float x) {
   return fmaf(y, fmaf(-0.5f * x, y * y, 0.5f), y);
 }
 
+// Signal rate sum_a (|v_a| + c)/dx of a cell mean U (eq. time_step); `bad`
+// records a non-positive density or pressure.  Shared by every kernel that
+// forms the time step, so that all of them obtain bitwise the same rate.
+template <int D>
+__device__ inline double cell_rate(const double *U, double gamma, double dx, bool &bad) {
+  double ke = 0.0;
+#pragma unroll
+  for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
+  const double p = (gamma - 1.0) * (U[D + 1] - 0.5 * ke);
+  bad |= !(U[0] > 0.0) || !(p > 0.0);
+  const double c = sqrt(gamma * p / U[0]);
+  double rate = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
+  return rate;
+}
+
+// Time-step work that the fused SSP-RK3 step hands to the stage kernels
+// (see k_rhs_tile2d): `word` holds the maximum signal rate as the bit
+// pattern of a non-negative double.
+enum : int { RATE_NONE = 0, RATE_DT = 1, RATE_CLEAR = 2, RATE_FOLD = 3 };
+struct RateOp {
+  unsigned long long *word;
+  double *dt_out;
+  double cfl_fk;  // CFL times the order factor of the time step
+  double dx;
+  int op;
+};
+
 // Euler flux f_a(U) (eq. flux_vectors; 2D drops the third velocity).
 template <int D, class R>
 __device__ inline void euler_flux(const R *U, int a, R gm1, R *F) {
@@ -630,14 +659,22 @@ __device__ inline float quad_swap(float x) {
 }
 constexpr int kQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+// value of lane J of the quad
+template <int J>
+__device__ inline double quad_from(double x) {
+  return quad_swap<J | (J << 2) | (J << 4) | (J << 6)>(x);
+}
 
 template <int K, class R, int FX>
 __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
     const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
     const double *__restrict__ wn, double *__restrict__ out, const double *__restrict__ dtp,
-    const float *__restrict__ vext, Grid g, int mode, double ca, double cb, int *__restrict__ flag) {
+    const float *__restrict__ vext, Grid g, int mode, double ca, double cb, int *__restrict__ flag, RateOp ro) {
   // R: type of the contractions and fluxes (double, or float in the mixed
   // path); the lift of the cell mean and the stage update are FP64.
+  // ro (fused step): RATE_DT takes dt = CFL f_k / max rate from ro.word
+  // instead of *dtp and block 0 stores it to ro.dt_out; RATE_CLEAR zeroes
+  // ro.word; RATE_FOLD folds the signal rate of the new cell means into it.
   using C = Cfg<2, K>;
   constexpr int TX = Tile2D<K>::TX, TY = Tile2D<K>::TY, NCELL = TX * TY, NT = 4 * NCELL;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N;
@@ -647,9 +684,19 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   constexpr int NTASK = (NFX + NFY) * QF;
   __shared__ R sw[NW * HC];
   __shared__ R sf[(NFX + NFY) * QF * NV];  // [face][node][var]
+  __shared__ unsigned long long smax;       // block maximum of the signal rate
+  __shared__ double sdt;                    // the stage's dt
 
   const int tid = threadIdx.x;
   const int cidx = tid >> 2, sub = tid & 3;
+  if (tid == 0) {
+    smax = 0ull;
+    double dt = 0.0;
+    if (mode != 0) dt = ro.op == RATE_DT ? ro.cfl_fk / __longlong_as_double((long long)*ro.word) : *dtp;
+    sdt = dt;
+    if (blockIdx.x == 0 && ro.op == RATE_DT) ro.dt_out[0] = dt;
+    if (blockIdx.x == 0 && ro.op == RATE_CLEAR) *ro.word = 0ull;
+  }
   const int tx = cidx % TX, ty = cidx / TX;
   // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
   // XCD b mod 8).  Give each XCD a contiguous band of tiles so that the halo
@@ -804,41 +851,60 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     wno[l] = (mode == 2) ? wn[i] : 0.0;
   }
   __syncthreads();
-  if (!real) return;
 
   // P3: lift the four face fluxes of variable `sub` (eq. dg_term3) and update;
   // the mean is lifted in FP64
-  const int v = sub;
-  const int fidx[4] = {ty * (TX + 1) + tx, ty * (TX + 1) + tx + 1, NFX + ty * TX + tx, NFX + (ty + 1) * TX + tx};
-  double acc0 = 0.0;
+  double mean = 0.0;  // new mean of variable sub
+  if (real) {
+    const int v = sub;
+    const int fidx[4] = {ty * (TX + 1) + tx, ty * (TX + 1) + tx + 1, NFX + ty * TX + tx, NFX + (ty + 1) * TX + tx};
+    double acc0 = 0.0;
 #pragma unroll
-  for (int f = 0; f < 4; ++f) {
-    const int a = f >> 1, side = f & 1;  // side 0: low face (xi_a = -1), 1: high face
+    for (int f = 0; f < 4; ++f) {
+      const int a = f >> 1, side = f & 1;  // side 0: low face (xi_a = -1), 1: high face
 #pragma unroll
-    for (int r = 0; r < QF; ++r) {
-      const R *tw = tabr + C::TW + ((a * 2 + side) * QF + r) * N;
-      const R F = sf[(fidx[f] * QF + r) * NV + v];
-      const R fv = side ? -F : F;
-      acc0 = fma((double)fv, tab[C::TW + ((a * 2 + side) * QF + r) * N], acc0);
+      for (int r = 0; r < QF; ++r) {
+        const R *tw = tabr + C::TW + ((a * 2 + side) * QF + r) * N;
+        const R F = sf[(fidx[f] * QF + r) * NV + v];
+        const R fv = side ? -F : F;
+        acc0 = fma((double)fv, tab[C::TW + ((a * 2 + side) * QF + r) * N], acc0);
 #pragma unroll
-      for (int l = 1; l < N; ++l) accv[l] = fma(fv, tw[l], accv[l]);
+        for (int l = 1; l < N; ++l) accv[l] = fma(fv, tw[l], accv[l]);
+      }
     }
-  }
-  bool bad = false;
-  const double dt = (mode == 0) ? 0.0 : *dtp;
+    bool bad = false;
+    const double dt = sdt;
 #pragma unroll
-  for (int l = 0; l < N; ++l) {
-    const long i = (long)(v * N + l) * nc + cell;
-    const double L = g.fac * (l == 0 ? acc0 : (double)accv[l]);
-    bad |= (L != L);
-    if (mode == 0) {
-      out[i] = L;
-    } else {
-      const double o = wo[l] + dt * L;
-      out[i] = (mode == 1) ? o : ca * wno[l] + cb * o;
+    for (int l = 0; l < N; ++l) {
+      const long i = (long)(v * N + l) * nc + cell;
+      const double L = g.fac * (l == 0 ? acc0 : (double)accv[l]);
+      bad |= (L != L);
+      double o = L;
+      if (mode != 0) {
+        o = wo[l] + dt * L;
+        if (mode != 1) o = ca * wno[l] + cb * o;
+      }
+      out[i] = o;
+      if (l == 0) mean = o;
     }
+    if (bad) atomicOr(flag, FLAG_NAN);
   }
-  if (bad) atomicOr(flag, FLAG_NAN);
+  if (ro.op == RATE_FOLD) {
+    // rate of the new cell mean (the limiters leave means unchanged, so it is
+    // the rate of the limited state too); one LDS max per cell, one global
+    // max per block
+    if (real) {
+      const double U[4] = {quad_from<0>(mean), quad_from<1>(mean), quad_from<2>(mean), quad_from<3>(mean)};
+      bool neg = false;
+      const double r = cell_rate<2>(U, g.gamma, ro.dx, neg);
+      if (sub == 0) {
+        atomicMax(&smax, (unsigned long long)__double_as_longlong(r));
+        if (neg) atomicOr(flag, FLAG_NEGATIVE);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) atomicMax(ro.word, smax);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1087,16 +1153,7 @@ __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long
     double U[D + 2];
 #pragma unroll
     for (int v = 0; v < D + 2; ++v) U[v] = w[(long)v * N * nc + cell];
-    double ke = 0.0;
-#pragma unroll
-    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
-    const double p = (gamma - 1.0) * (U[D + 1] - 0.5 * ke);
-    bad |= !(U[0] > 0.0) || !(p > 0.0);
-    const double c = sqrt(gamma * p / U[0]);
-    double rate = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
-    m = fmax(m, rate);
+    m = fmax(m, cell_rate<D>(U, gamma, dx, bad));
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
@@ -1108,6 +1165,12 @@ __global__ void k_dt_final(unsigned long long *ratemax, double cfl_fk, double *_
     dt[0] = cfl_fk / __longlong_as_double((long long)*ratemax);
     *ratemax = 0ull;
   }
+}
+
+// Clears a rate word (a kernel rather than a memset, so that the call can be
+// captured into a graph).
+__global__ void k_word_zero(unsigned long long *word) {
+  if (threadIdx.x == 0) *word = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -1636,11 +1699,6 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
 // face form each trace from the same weights, tables and summation order, so
 // they still obtain the identical flux.
 // ---------------------------------------------------------------------------
-// value of lane J of the quad
-template <int J>
-__device__ inline double quad_from(double x) {
-  return quad_swap<J | (J << 2) | (J << 4) | (J << 6)>(x);
-}
 // lane s holds row s of a 4x4 block; afterwards it holds column s
 __device__ inline void quad_transpose(double (&x)[4], int sub) {
   const bool b1 = sub & 2, b0 = sub & 1;
@@ -1935,16 +1993,7 @@ __global__ __launch_bounds__(256) void k_rate_amr(const double *__restrict__ w, 
     double U[D + 2];
 #pragma unroll
     for (int v = 0; v < D + 2; ++v) U[v] = wb[(long)v * N * ncb + cell];
-    double ke = 0.0;
-#pragma unroll
-    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
-    const double p = (g.gamma - 1.0) * (U[D + 1] - 0.5 * ke);
-    bad |= !(U[0] > 0.0) || !(p > 0.0);
-    const double c = sqrt(g.gamma * p / U[0]);
-    double rate = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
-    m = fmax(m, rate);
+    m = fmax(m, cell_rate<D>(U, g.gamma, dx, bad));
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
@@ -2222,6 +2271,7 @@ struct StageLaunch {
   int mode;
   double ca, cb;
   hipStream_t s;
+  dg::RateOp ro = {nullptr, nullptr, 0.0, 0.0, dg::RATE_NONE};  // only the 2D tile kernel takes one
   template <int D, int K, class R>
   int launch(const R *tabr, const float *vext) {
     return c->cfg.flux == DG_HLLC_DAVIS ? launch_fx<D, K, R, DG_HLLC_DAVIS>(tabr, vext)
@@ -2229,6 +2279,7 @@ struct StageLaunch {
   }
   template <int D, int K, class R, int FX>
   int launch_fx(const R *tabr, const float *vext) {
+    if ((c->amr || D != 2) && ro.op != dg::RATE_NONE) return DG_EINVAL;
     if (c->amr) {
       if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
         // four lanes per cell (the one-thread kernel would spill)
@@ -2242,7 +2293,7 @@ struct StageLaunch {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
       hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
-                         vext, make_grid(c), mode, ca, cb, c->flag);
+                         vext, make_grid(c), mode, ca, cb, c->flag, ro);
     } else {
       hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
                          wn, out, dt, vext, make_grid(c), mode, ca, cb, c->flag);
@@ -2373,6 +2424,29 @@ struct Bf16Tables {
 };
 
 int bf16_tables(const dg_ctx *c, std::vector<uint16_t> &out) { return dispatch(c, Bf16Tables{c, &out}); }
+
+// Folds the maximum signal rate of w's cell means into *rm (atomic max).
+int rate_fold(dg_ctx *c, const double *w, unsigned long long *rm, hipStream_t s) {
+  if (c->amr) {
+    if (c->sh.d == 2)
+      hipLaunchKernelGGL(dg::k_rate_amr<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
+                         c->flag);
+    else
+      hipLaunchKernelGGL(dg::k_rate_amr<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
+                         c->flag);
+  } else {
+    if (c->sh.d == 2)
+      hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                         c->dx, rm, c->flag);
+    else
+      hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
+                         c->dx, rm, c->flag);
+  }
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+bool limited(const dg_ctx *c) { return c->cfg.slope_limiter != DG_LIM_NONE || c->cfg.positivity; }
 
 }  // namespace
 
@@ -2562,29 +2636,55 @@ int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const 
                                  (hipStream_t)stream});
 }
 
+
 int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
   if (!c || !w || !dt) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long *rm = reinterpret_cast<unsigned long long *>(c->partial);
-  if (c->amr) {
-    if (c->sh.d == 2)
-      hipLaunchKernelGGL(dg::k_rate_amr<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
-                         c->flag);
-    else
-      hipLaunchKernelGGL(dg::k_rate_amr<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
-                         c->flag);
-  } else {
-    if (c->sh.d == 2)
-      hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                         c->dx, rm, c->flag);
-    else
-      hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                         c->dx, rm, c->flag);
-  }
-  HIP_TRY(hipGetLastError());
+  int st = rate_fold(c, w, rm, s);
+  if (st != DG_OK) return st;
   hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(64), 0, s, rm, c->cfl_fk, dt);
   HIP_TRY(hipGetLastError());
   return DG_OK;
+}
+
+int dg_max_rate(dg_ctx *c, const double *w, double *rate, void *stream) {
+  if (!c || !w || !rate) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
+  hipLaunchKernelGGL(dg::k_word_zero, dim3(1), dim3(64), 0, s, rm);
+  HIP_TRY(hipGetLastError());
+  return rate_fold(c, w, rm, s);
+}
+
+int dg_rk_step(dg_ctx *c, const double *w, double *u1, double *u2, double *out, double *dt, double *rate,
+               void *stream) {
+  if (!c || !w || !u1 || !u2 || !out || !dt || !rate) return DG_EINVAL;
+  const void *st_ptr[4] = {w, u1, u2, out};
+  for (int i = 0; i < 4; ++i)
+    for (int j = i + 1; j < 4; ++j)
+      if (st_ptr[i] == st_ptr[j]) return DG_EINVAL;
+  if (dt == rate) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
+  const bool fused = !c->amr && c->sh.d == 2;
+  if (!fused) {
+    // dt from the carried rate (the word is cleared for the fold below)
+    hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(64), 0, s, rm, c->cfl_fk, dt);
+    HIP_TRY(hipGetLastError());
+  }
+  auto op = [&](int k) { return dg::RateOp{rm, dt, c->cfl_fk, c->dx, fused ? k : dg::RATE_NONE}; };
+  const double *wp[3] = {w, u1, u2};
+  double *wo[3] = {u1, u2, out};
+  static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+  static const int R[3] = {dg::RATE_DT, dg::RATE_CLEAR, dg::RATE_FOLD};
+  for (int k = 0; k < 3; ++k) {
+    int st = dispatch(c, StageLaunch{c, wp[k], w, dt, wo[k], k == 0 ? 1 : 2, A[k], B[k], s, op(R[k])});
+    if (st != DG_OK) return st;
+    if (limited(c) && (st = dispatch(c, LimitLaunch{c, wo[k], s})) != DG_OK) return st;
+  }
+  return fused ? DG_OK : rate_fold(c, out, rm, s);
 }
 
 int dg_limit(dg_ctx *c, double *w, void *stream) {
