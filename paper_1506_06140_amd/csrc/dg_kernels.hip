@@ -711,19 +711,31 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   const int nxt = min(TX, g.nx - bx0), nyt = min(TY, g.ny - by0);
 
   // P0: tile and halo weights into LDS (periodic wrap; transmissive ghosts are
-  // resolved at the faces)
-  for (int i = tid; i < NW * HC; i += NT) {
-    const int h = i % HC, vl = i / HC;
+  // resolved at the faces).  Thread t owns halo position h = t mod HC for the
+  // weights vl = t / HC, t / HC + R0, ...: the cell index is formed once and
+  // the NW / R0 loads of a thread are all in flight together.
+  {
+    constexpr int R0 = NT / HC;
+    static_assert(R0 >= 1 && NW % R0 == 0, "whole rows of halo positions");
+    const int h = tid % HC, v0 = tid / HC;
     const int lx = h % HX - 1, ly = h / HX - 1;
-    if ((lx < 0 || lx >= TX) && (ly < 0 || ly >= TY)) continue;
-    // periodic wrap of the halo; positions past the first halo column/row of
-    // a partial tile are never read and are only kept inside the grid
-    int gx = bx0 + lx, gy = by0 + ly;
-    gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
-    gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
-    gx = min(gx, g.nx - 1);
-    gy = min(gy, g.ny - 1);
-    sw[i] = (R)w[(long)vl * nc + (long)gy * g.nx + gx];
+    const bool corner = (lx < 0 || lx >= TX) && (ly < 0 || ly >= TY);
+    if (v0 < R0 && !corner) {
+      // periodic wrap of the halo; positions past the first halo column/row
+      // of a partial tile are never read and are only kept inside the grid
+      int gx = bx0 + lx, gy = by0 + ly;
+      gx = gx < 0 ? gx + g.nx : (gx >= g.nx ? gx - g.nx : gx);
+      gy = gy < 0 ? gy + g.ny : (gy >= g.ny ? gy - g.ny : gy);
+      gx = min(gx, g.nx - 1);
+      gy = min(gy, g.ny - 1);
+      const double *src = w + (long)v0 * nc + (long)gy * g.nx + gx;
+      R *dst = sw + v0 * HC + h;
+      double vals[NW / R0];
+#pragma unroll
+      for (int j = 0; j < NW / R0; ++j) vals[j] = src[(long)j * R0 * nc];
+#pragma unroll
+      for (int j = 0; j < NW / R0; ++j) dst[j * R0 * HC] = (R)vals[j];
+    }
   }
   __syncthreads();
 
@@ -857,15 +869,17 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   double mean = 0.0;  // new mean of variable sub
   if (real) {
     const int v = sub;
-    const int fidx[4] = {ty * (TX + 1) + tx, ty * (TX + 1) + tx + 1, NFX + ty * TX + tx, NFX + (ty + 1) * TX + tx};
     double acc0 = 0.0;
-#pragma unroll
+    // one face per iteration keeps its lifting weights (uniform) in scalar
+    // registers without spilling the other faces' weights
+#pragma unroll 1
     for (int f = 0; f < 4; ++f) {
       const int a = f >> 1, side = f & 1;  // side 0: low face (xi_a = -1), 1: high face
+      const int fi = a == 0 ? ty * (TX + 1) + tx + side : NFX + (ty + side) * TX + tx;
 #pragma unroll
       for (int r = 0; r < QF; ++r) {
         const R *tw = tabr + C::TW + ((a * 2 + side) * QF + r) * N;
-        const R F = sf[(fidx[f] * QF + r) * NV + v];
+        const R F = sf[(fi * QF + r) * NV + v];
         const R fv = side ? -F : F;
         acc0 = fma((double)fv, tab[C::TW + ((a * 2 + side) * QF + r) * N], acc0);
 #pragma unroll
