@@ -686,6 +686,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   __shared__ R sf[(NFX + NFY) * QF * NV];  // [face][node][var]
   __shared__ unsigned long long smax;       // block maximum of the signal rate
   __shared__ double sdt;                    // the stage's dt
+  __shared__ R stab[C::TW];                 // basis, derivative-weight and trace tables
 
   const int tid = threadIdx.x;
   const int cidx = tid >> 2, sub = tid & 3;
@@ -714,6 +715,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   // resolved at the faces).  Thread t owns halo position h = t mod HC for the
   // weights vl = t / HC, t / HC + R0, ...: the cell index is formed once and
   // the NW / R0 loads of a thread are all in flight together.
+  for (int i = tid; i < C::TW; i += NT) stab[i] = tabr[i];
   {
     constexpr int R0 = NT / HC;
     static_assert(R0 >= 1 && NW % R0 == 0, "whole rows of halo positions");
@@ -765,8 +767,8 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       ghost_lo = tr_y && gyl < 0;
       ghost_hi = tr_y && gyl >= g.ny - 1;
     }
-    const R *tlo = tabr + C::TF + ((a * 2 + 1) * QF + r) * N;  // low cell at xi_a = +1
-    const R *thi = tabr + C::TF + ((a * 2 + 0) * QF + r) * N;  // high cell at xi_a = -1
+    const R *tlo = stab + C::TF + ((a * 2 + 1) * QF + r) * N;  // low cell at xi_a = +1
+    const R *thi = stab + C::TF + ((a * 2 + 0) * QF + r) * N;  // high cell at xi_a = -1
     R UL[NV], UR[NV], F[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -802,7 +804,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     const R gm1 = (R)(g.gamma - 1.0);
 #pragma unroll 1
     for (int q = sub; q < (vext ? 0 : Q); q += 4) {
-      const R *bq = tabr + C::B + q * N;
+      const R *bq = stab + C::B + q * N;
       R U[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
@@ -815,7 +817,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       for (int a = 0; a < 2; ++a) {
         R F[NV];
         euler_flux<2, R>(U, a, gm1, F);
-        const R *dw = tabr + C::DW + (a * Q + q) * N;
+        const R *dw = stab + C::DW + (a * Q + q) * N;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
