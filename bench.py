@@ -141,7 +141,7 @@ def time_steps(s, wl, steps, warmup, graph=True):
     if s.limited:
         s.limit(A)
     B = s.empty()
-    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.scalar()
+    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.rate_state()
     stream = torch.cuda.current_stream()
     s.max_rate(A, rate)
 
@@ -265,7 +265,7 @@ def main():
     s = dg.Solver(wl)
     A = build_state(s, wl)
     B = s.empty()
-    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.scalar()
+    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.rate_state()
     stream = torch.cuda.current_stream()
     s.max_rate(A, rate)
 

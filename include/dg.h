@@ -137,23 +137,32 @@ int dg_max_dt(dg_ctx *ctx, const double *w, double *dt_dev, void *stream);
 int dg_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *w_n,
                 const double *w_prev, double *w_out, void *stream);
 
+/* Doubles in the rate state that dg_max_rate writes and dg_rk_step carries:
+ * 8 slots at a stride of 16 doubles (one 128-byte line each, so that
+ * workgroups on different XCDs fold into different lines).  Each slot holds
+ * a partial maximum of the signal rate; the rate of the state is the largest
+ * slot (slots are non-negative doubles).  Which slot holds the overall
+ * maximum depends on the kernel that wrote the state. */
+#define DG_RATE_STATE 128
+
 /* Maximum over cells of the signal rate sum_a (|v_a| + c)/dx of the cell
- * means of w (the denominator of eq. time_step), written to rate_dev[0] on
- * the device: the value dg_rk_step expects for the state it starts from.
- * Sets DG_ENEGATIVE for a non-positive mean density or pressure. */
+ * means of w (the denominator of eq. time_step), written as a rate state
+ * (DG_RATE_STATE doubles on the device, caller-owned): the input dg_rk_step
+ * expects for the state it starts from.  Sets DG_ENEGATIVE for a
+ * non-positive mean density or pressure. */
 int dg_max_rate(dg_ctx *ctx, const double *w, double *rate_dev, void *stream);
 
 /* One full SSP-RK3 step (App. D, table RK_3) with the configured limiters
  * after every stage (Sec. 4.5 without refinement):
- *   dt = CFL f_k / rate_dev[0]  (eq. time_step / time_step_pos),
+ *   dt = CFL f_k / (maximum signal rate of w)  (eq. time_step / time_step_pos),
  *   u1 = stage 1 of w, u2 = stage 2, w_out = stage 3.
- * On entry rate_dev[0] must hold the maximum signal rate of w, as written by
- * dg_max_rate(w) or by the dg_rk_step that produced w; on return it holds
- * that of w_out (the limiters keep cell means, so it is also the rate of the
- * limited state), so that steps chain without a separate time-step pass.
- * dt_dev[0] receives the step's dt.  Results equal dg_max_dt, three
- * dg_rk_stage and dg_limit calls bit for bit.  w, u1, u2 and w_out must be
- * four distinct states, dt_dev and rate_dev distinct device scalars;
+ * On entry rate_dev (DG_RATE_STATE doubles) must hold the rate state of w, as
+ * written by dg_max_rate(w) or by the dg_rk_step that produced w; on return
+ * it holds that of w_out (the limiters keep cell means, so it is also the
+ * rate of the limited state), so that steps chain without a separate
+ * time-step pass.  dt_dev[0] receives the step's dt.  Results equal
+ * dg_max_dt, three dg_rk_stage and dg_limit calls bit for bit.  w, u1, u2
+ * and w_out must be four distinct states, dt_dev and rate_dev distinct;
  * otherwise DG_EINVAL.  On a 2D grid without refinement the time-step work
  * rides in the three stage kernels; elsewhere two small kernels carry it.
  * Two calls that share rate_dev must not run concurrently. */

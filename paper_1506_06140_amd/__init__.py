@@ -19,6 +19,8 @@ LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(_HERE, "libdg.so"))
 
 DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
+# doubles in the carried rate state (8 slots, 16 apart; the rate is the largest slot)
+DG_RATE_STATE, RATE_SLOTS, RATE_STRIDE = 128, 8, 16
 PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}
 
 
@@ -231,20 +233,31 @@ class Solver:
                "dg_rk_stage")
         return out
 
+    def rate_state(self):
+        """A zeroed device rate state (DG_RATE_STATE doubles) for max_rate / rk_step."""
+        import torch
+        return torch.zeros(DG_RATE_STATE, dtype=torch.float64, device="cuda")
+
+    @staticmethod
+    def rate_value(rate) -> float:
+        """The maximum signal rate a rate state holds (its largest slot)."""
+        return float(rate[::RATE_STRIDE][:RATE_SLOTS].max())
+
     def max_rate(self, w, rate=None, stream=None):
-        """Maximum signal rate of w's cell means into a one-element device tensor."""
-        rate = self.scalar() if rate is None else rate
-        _check(self.lib.dg_max_rate(self.ctx, self._s(w), _ptr(rate, 1), _stream(stream)), "dg_max_rate")
+        """Rate state (maximum signal rate of w's cell means) into a device tensor."""
+        rate = self.rate_state() if rate is None else rate
+        _check(self.lib.dg_max_rate(self.ctx, self._s(w), _ptr(rate, DG_RATE_STATE), _stream(stream)),
+               "dg_max_rate")
         return rate
 
     def rk_step(self, w, bufs, dt, rate, stream=None):
         """One SSP-RK3 step with limiters from w into bufs[2] (bufs[0], bufs[1]
-        are the stage buffers) in one library call.  rate holds the maximum
-        signal rate of w on entry (max_rate, or the previous rk_step) and of
-        the result on return; dt receives the step.  Returns bufs[2]."""
+        are the stage buffers) in one library call.  rate (a rate_state())
+        holds the rate state of w on entry (max_rate, or the previous rk_step)
+        and of the result on return; dt receives the step.  Returns bufs[2]."""
         u1, u2, out = bufs[0], bufs[1], bufs[2]
         _check(self.lib.dg_rk_step(self.ctx, self._s(w), self._s(u1), self._s(u2), self._s(out), _ptr(dt, 1),
-                                   _ptr(rate, 1), _stream(stream)), "dg_rk_step")
+                                   _ptr(rate, DG_RATE_STATE), _stream(stream)), "dg_rk_step")
         return out
 
     def limit(self, w, stream=None):

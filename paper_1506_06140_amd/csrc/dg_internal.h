@@ -63,7 +63,7 @@ struct dg_ctx {
   float *tab32 = nullptr;    // FP32 copy
   void *tabbf = nullptr;     // BF16 tables of the MFMA volume kernel (padded)
   float *vscratch = nullptr; // volume term from the MFMA kernel (BF16 path)
-  double *partial = nullptr; // 64-bit word holding the running maximum signal rate
+  double *partial = nullptr; // rate slots of dg_max_dt (DG_RATE_STATE doubles)
   int npartial = 0;          // blocks of the time-step reduction
   int *flag = nullptr;       // sticky device error flag
   int device = 0;

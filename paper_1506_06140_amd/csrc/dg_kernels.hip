@@ -114,9 +114,27 @@ __device__ inline double cell_rate(const double *U, double gamma, double dx, boo
   return rate;
 }
 
+// maximum over the 64 lanes of a wave (all lanes active)
+__device__ inline double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
+  return x;
+}
+
+// The maximum signal rate is reduced into RATE_SLOTS 64-bit words, one per
+// 128-byte line, each holding the bit pattern of a non-negative double (such
+// doubles order like their bits, so atomicMax on the pattern is a max); the
+// rate is the largest slot.  Workgroup b folds into slot b mod 8, i.e. one
+// slot per XCD: a single word taking every workgroup's atomic serialises
+// them.
+constexpr int RATE_SLOTS = 8, RATE_STRIDE = 16;
+static_assert(RATE_SLOTS * RATE_STRIDE == DG_RATE_STATE, "layout of the carried rate state");
+__device__ inline unsigned long long *rate_slot(unsigned long long *w, int b) {
+  return w + RATE_STRIDE * (b % RATE_SLOTS);
+}
+
 // Time-step work that the fused SSP-RK3 step hands to the stage kernels
-// (see k_rhs_tile2d): `word` holds the maximum signal rate as the bit
-// pattern of a non-negative double.
+// (see k_rhs_tile2d); `word` is the carried rate state (RATE_SLOTS slots).
 enum : int { RATE_NONE = 0, RATE_DT = 1, RATE_CLEAR = 2, RATE_FOLD = 3 };
 struct RateOp {
   unsigned long long *word;
@@ -672,9 +690,10 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     const float *__restrict__ vext, Grid g, int mode, double ca, double cb, int *__restrict__ flag, RateOp ro) {
   // R: type of the contractions and fluxes (double, or float in the mixed
   // path); the lift of the cell mean and the stage update are FP64.
-  // ro (fused step): RATE_DT takes dt = CFL f_k / max rate from ro.word
-  // instead of *dtp and block 0 stores it to ro.dt_out; RATE_CLEAR zeroes
-  // ro.word; RATE_FOLD folds the signal rate of the new cell means into it.
+  // ro (fused step): RATE_DT takes dt = CFL f_k / max rate from the slots of
+  // ro.word instead of *dtp and block 0 stores it to ro.dt_out; RATE_CLEAR
+  // zeroes the slots; RATE_FOLD folds the signal rate of the new cell means
+  // into them.
   using C = Cfg<2, K>;
   constexpr int TX = Tile2D<K>::TX, TY = Tile2D<K>::TY, NCELL = TX * TY, NT = 4 * NCELL;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N;
@@ -686,18 +705,26 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   __shared__ R sf[(NFX + NFY) * QF * NV];  // [face][node][var]
   __shared__ unsigned long long smax;       // block maximum of the signal rate
   __shared__ double sdt;                    // the stage's dt
-  __shared__ R stab[C::TW];                 // basis, derivative-weight and trace tables
+  __shared__ R stab[C::WQ];                 // basis, derivative-weight, trace and lifting tables
 
   const int tid = threadIdx.x;
   const int cidx = tid >> 2, sub = tid & 3;
-  if (tid == 0) {
-    smax = 0ull;
-    double dt = 0.0;
-    if (mode != 0) dt = ro.op == RATE_DT ? ro.cfl_fk / __longlong_as_double((long long)*ro.word) : *dtp;
-    sdt = dt;
-    if (blockIdx.x == 0 && ro.op == RATE_DT) ro.dt_out[0] = dt;
-    if (blockIdx.x == 0 && ro.op == RATE_CLEAR) *ro.word = 0ull;
+  // the stage's dt (or the carried rate) and the small tables are loaded
+  // before the halo and stored after it, so that no load waits on another
+  // (a relaxed atomic read keeps it a vector load: a scalar load would be
+  // waited for together with the kernel arguments, before the halo loads)
+  unsigned long long dbits = 0ull;  // dt, or one slot of the carried rate
+  if (mode != 0 && tid < (ro.op == RATE_DT ? RATE_SLOTS : 1)) {
+    const unsigned long long *src =
+        ro.op == RATE_DT ? ro.word + RATE_STRIDE * tid : reinterpret_cast<const unsigned long long *>(dtp);
+    dbits = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
+  constexpr int TPT = (C::WQ + NT - 1) / NT;
+  R tv[TPT];
+#pragma unroll
+  for (int j = 0; j < TPT; ++j) tv[j] = tid + j * NT < C::WQ ? tabr[tid + j * NT] : R(0);
+  if (tid == 0) smax = 0ull;
+  if (blockIdx.x == 0 && ro.op == RATE_CLEAR && tid < RATE_SLOTS) ro.word[RATE_STRIDE * tid] = 0ull;
   const int tx = cidx % TX, ty = cidx / TX;
   // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on
   // XCD b mod 8).  Give each XCD a contiguous band of tiles so that the halo
@@ -715,7 +742,6 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   // resolved at the faces).  Thread t owns halo position h = t mod HC for the
   // weights vl = t / HC, t / HC + R0, ...: the cell index is formed once and
   // the NW / R0 loads of a thread are all in flight together.
-  for (int i = tid; i < C::TW; i += NT) stab[i] = tabr[i];
   {
     constexpr int R0 = NT / HC;
     static_assert(R0 >= 1 && NW % R0 == 0, "whole rows of halo positions");
@@ -737,6 +763,25 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       for (int j = 0; j < NW / R0; ++j) vals[j] = src[(long)j * R0 * nc];
 #pragma unroll
       for (int j = 0; j < NW / R0; ++j) dst[j * R0 * HC] = (R)vals[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TPT; ++j)
+    if (tid + j * NT < C::WQ) stab[tid + j * NT] = tv[j];
+  if (tid < 64) {  // wave 0: the largest slot (lanes past the slots hold 0)
+    if (ro.op == RATE_DT) {
+#pragma unroll
+      for (int off = RATE_SLOTS / 2; off > 0; off >>= 1) {
+        const unsigned long long o =
+            (unsigned long long)__double_as_longlong(__shfl_xor(__longlong_as_double((long long)dbits), off));
+        dbits = o > dbits ? o : dbits;
+      }
+    }
+    if (tid == 0) {
+      const double dv = __longlong_as_double((long long)dbits);
+      const double dt = ro.op == RATE_DT ? ro.cfl_fk / dv : dv;
+      sdt = dt;
+      if (blockIdx.x == 0 && ro.op == RATE_DT) ro.dt_out[0] = dt;
     }
   }
   __syncthreads();
@@ -880,10 +925,15 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       const int fi = a == 0 ? ty * (TX + 1) + tx + side : NFX + (ty + side) * TX + tx;
 #pragma unroll
       for (int r = 0; r < QF; ++r) {
-        const R *tw = tabr + C::TW + ((a * 2 + side) * QF + r) * N;
+        const R *tw = stab + C::TW + ((a * 2 + side) * QF + r) * N;
         const R F = sf[(fi * QF + r) * NV + v];
         const R fv = side ? -F : F;
-        acc0 = fma((double)fv, tab[C::TW + ((a * 2 + side) * QF + r) * N], acc0);
+        double t0;
+        if constexpr (sizeof(R) == sizeof(double))
+          t0 = tw[0];
+        else
+          t0 = tab[C::TW + ((a * 2 + side) * QF + r) * N];
+        acc0 = fma((double)fv, t0, acc0);
 #pragma unroll
         for (int l = 1; l < N; ++l) accv[l] = fma(fv, tw[l], accv[l]);
       }
@@ -907,19 +957,19 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   }
   if (ro.op == RATE_FOLD) {
     // rate of the new cell mean (the limiters leave means unchanged, so it is
-    // the rate of the limited state too); one LDS max per cell, one global
-    // max per block
+    // the rate of the limited state too): a wave max, one LDS max per wave,
+    // one global max per block
+    double r = 0.0;
     if (real) {
       const double U[4] = {quad_from<0>(mean), quad_from<1>(mean), quad_from<2>(mean), quad_from<3>(mean)};
       bool neg = false;
-      const double r = cell_rate<2>(U, g.gamma, ro.dx, neg);
-      if (sub == 0) {
-        atomicMax(&smax, (unsigned long long)__double_as_longlong(r));
-        if (neg) atomicOr(flag, FLAG_NEGATIVE);
-      }
+      r = cell_rate<2>(U, g.gamma, ro.dx, neg);
+      if (neg && sub == 0) atomicOr(flag, FLAG_NEGATIVE);
     }
+    r = wave_max(r);
+    if ((tid & 63) == 0) atomicMax(&smax, (unsigned long long)__double_as_longlong(r));
     __syncthreads();
-    if (tid == 0) atomicMax(ro.word, smax);
+    if (tid == 0) atomicMax(rate_slot(ro.word, blockIdx.x), smax);
   }
 }
 
@@ -1137,11 +1187,6 @@ __global__ __launch_bounds__(256) void k_project(const double *__restrict__ tab,
 // Time step (eq. time_step / time_step_pos): max over cells of the signal
 // rate sum_a (|v_a| + c)/dx of the cell mean; dt = CFL f_k / max rate.
 // ---------------------------------------------------------------------------
-__device__ inline double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off));
-  return x;
-}
 
 __device__ inline double block_max(double x) {
   __shared__ double red[16];
@@ -1156,10 +1201,9 @@ __device__ inline double block_max(double x) {
 }
 
 // max over cells of sum_a (|v_a| + c)/dx of the cell mean: every block folds
-// its maximum into one 64-bit word with an atomic max (non-negative doubles
-// order like their bit patterns); k_dt_final then writes dt = CFL f_k / max
-// and clears the word for the next call.  The kernel boundary orders the two,
-// so no device-scope fence is needed.
+// its maximum into its rate slot with an atomic max; k_dt_final then writes
+// dt = CFL f_k / (largest slot) and clears the slots for the next call.  The
+// kernel boundary orders the two, so no device-scope fence is needed.
 template <int D>
 __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long nc, int N, double gamma, double dx,
                                               unsigned long long *ratemax, int *__restrict__ flag) {
@@ -1173,20 +1217,25 @@ __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
-  if (threadIdx.x == 0) atomicMax(ratemax, (unsigned long long)__double_as_longlong(m));
+  if (threadIdx.x == 0) atomicMax(rate_slot(ratemax, blockIdx.x), (unsigned long long)__double_as_longlong(m));
 }
 
 __global__ void k_dt_final(unsigned long long *ratemax, double cfl_fk, double *__restrict__ dt) {
   if (threadIdx.x == 0) {
-    dt[0] = cfl_fk / __longlong_as_double((long long)*ratemax);
-    *ratemax = 0ull;
+    unsigned long long m = 0ull;
+    for (int k = 0; k < RATE_SLOTS; ++k) {
+      const unsigned long long v = ratemax[RATE_STRIDE * k];
+      m = v > m ? v : m;
+      ratemax[RATE_STRIDE * k] = 0ull;
+    }
+    dt[0] = cfl_fk / __longlong_as_double((long long)m);
   }
 }
 
-// Clears a rate word (a kernel rather than a memset, so that the call can be
-// captured into a graph).
-__global__ void k_word_zero(unsigned long long *word) {
-  if (threadIdx.x == 0) *word = 0ull;
+// Clears the rate slots (a kernel rather than a memset, so that the call can
+// be captured into a graph).
+__global__ void k_rate_zero(unsigned long long *word) {
+  if (threadIdx.x < RATE_SLOTS) word[RATE_STRIDE * threadIdx.x] = 0ull;
 }
 
 // ---------------------------------------------------------------------------
@@ -2013,7 +2062,7 @@ __global__ __launch_bounds__(256) void k_rate_amr(const double *__restrict__ w, 
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
-  if (threadIdx.x == 0) atomicMax(ratemax, (unsigned long long)__double_as_longlong(m));
+  if (threadIdx.x == 0) atomicMax(rate_slot(ratemax, blockIdx.x), (unsigned long long)__double_as_longlong(m));
 }
 
 // Limiters on the refined mesh: neighbour means across the refinement
@@ -2558,7 +2607,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const size_t nt = c->host_tab.size();
   if ((e = hipMalloc((void **)&c->tab, nt * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
-  if ((e = hipMalloc((void **)&c->partial, sizeof(double))) != hipSuccess) return fail(e);
+  if ((e = hipMalloc((void **)&c->partial, DG_RATE_STATE * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->flag, sizeof(int))) != hipSuccess) return fail(e);
   std::vector<float> t32(nt);
   for (size_t i = 0; i < nt; ++i) t32[i] = (float)c->host_tab[i];
@@ -2580,8 +2629,9 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
     const size_t nv = (size_t)c->sh.nv * c->sh.N * c->ncell;
     if ((e = hipMalloc((void **)&c->vscratch, nv * sizeof(float))) != hipSuccess) return fail(e);
   }
-  const unsigned long long zero64 = 0ull;
-  if ((e = hipMemcpy(c->partial, &zero64, sizeof(zero64), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
+  const std::vector<double> zeros(DG_RATE_STATE, 0.0);
+  if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+    return fail(e);
   *out = c;
   return DG_OK;
 }
@@ -2668,7 +2718,7 @@ int dg_max_rate(dg_ctx *c, const double *w, double *rate, void *stream) {
   if (!c || !w || !rate) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
-  hipLaunchKernelGGL(dg::k_word_zero, dim3(1), dim3(64), 0, s, rm);
+  hipLaunchKernelGGL(dg::k_rate_zero, dim3(1), dim3(64), 0, s, rm);
   HIP_TRY(hipGetLastError());
   return rate_fold(c, w, rm, s);
 }
@@ -2680,7 +2730,7 @@ int dg_rk_step(dg_ctx *c, const double *w, double *u1, double *u2, double *out, 
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
       if (st_ptr[i] == st_ptr[j]) return DG_EINVAL;
-  if (dt == rate) return DG_EINVAL;
+  if (dt >= rate && dt < rate + DG_RATE_STATE) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
   const bool fused = !c->amr && c->sh.d == 2;

@@ -107,7 +107,7 @@ def test_step_equals_composed_calls(case, spec, precision):
     assert s.status() == 0
     # fused: rate carried from step to step
     fb = [s.empty() for _ in range(3)]
-    dt, rate = s.scalar(), s.scalar()
+    dt, rate = s.scalar(), s.rate_state()
     w = _dev(w0)
     s.max_rate(w, rate)
     for i in range(steps):
@@ -116,8 +116,8 @@ def test_step_equals_composed_calls(case, spec, precision):
         _say(case, "step", i, "dt", _host(dt)[0], ref_dts[i])
         assert _host(dt)[0] == ref_dts[i], (i, _host(dt)[0], ref_dts[i])
         assert np.array_equal(got, ref_states[i]), (i, np.abs(got - ref_states[i]).max())
-        fresh = _host(s.max_rate(w))[0]
-        assert _host(rate)[0] == fresh, (i, _host(rate)[0], fresh)
+        fresh = s.rate_value(s.max_rate(w))
+        assert s.rate_value(rate) == fresh, (i, s.rate_value(rate), fresh)
     assert s.status() == 0
 
 
@@ -127,7 +127,7 @@ def test_step_matches_oracle(case, spec, precision):
     _say("case", case)
     wl, o, s, w0 = _setup(spec, precision)
     fb = [s.empty() for _ in range(3)]
-    dt, rate = s.scalar(), s.scalar()
+    dt, rate = s.scalar(), s.rate_state()
     w = _dev(w0)
     s.max_rate(w, rate)
     ref = w0
@@ -156,7 +156,7 @@ def test_step_graph_replays():
     w0 = o.initial_state()
     # eager reference: 8 steps
     fb = [s.empty() for _ in range(3)]
-    dt, rate = s.scalar(), s.scalar()
+    dt, rate = s.scalar(), s.rate_state()
     w = _dev(w0)
     s.max_rate(w, rate)
     eager = []
@@ -165,7 +165,7 @@ def test_step_graph_replays():
         eager.append(_host(w))
     A, B = _dev(w0), s.empty()
     u1, u2 = s.empty(), s.empty()
-    dtb, rb = s.scalar(), s.scalar()
+    dtb, rb = s.scalar(), s.rate_state()
 
     def two():
         s.rk_step(A, [u1, u2, B], dtb, rb)
@@ -204,17 +204,21 @@ def test_step_graph_replays():
 
 
 def test_step_argument_errors():
+    import torch
     import paper_1506_06140_amd as dg
     wl = workloads.workload("vortex", n=(16, 16, 1), length=(4.0, 4.0, 1.0))
     s = dg.Solver(wl)
     a, b, c, d = (s.empty() for _ in range(4))
-    dt, rate = s.scalar(), s.scalar()
+    dt, rate = s.scalar(), s.rate_state()
     with pytest.raises(dg.DGError) as e:
         s.rk_step(a, [b, b, c], dt, rate)  # u1 == u2
     assert e.value.code == dg.DG_EINVAL
     with pytest.raises(dg.DGError) as e:
         s.rk_step(a, [b, c, a], dt, rate)  # out == w
     assert e.value.code == dg.DG_EINVAL
-    with pytest.raises(dg.DGError) as e:
-        s.rk_step(a, [b, c, d], dt, dt)  # dt == rate
-    assert e.value.code == dg.DG_EINVAL
+    # dt inside the rate state: rejected before anything is launched
+    st = s.lib.dg_rk_step(s.ctx, a.data_ptr(), b.data_ptr(), c.data_ptr(), d.data_ptr(), rate.data_ptr() + 8 * 5,
+                          rate.data_ptr(), torch.cuda.current_stream().cuda_stream)
+    assert st == dg.DG_EINVAL
+    with pytest.raises(ValueError):  # a one-element rate buffer is too small
+        s.rk_step(a, [b, c, d], dt, s.scalar())
