@@ -1778,16 +1778,19 @@ __device__ inline void quad_transpose(double (&x)[4], int sub) {
   x[3] = b0 ? y3 : r1;
 }
 
-template <int K, int FX>
+template <int K, int FX, bool UNI>
 __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__ tab, const double *__restrict__ w,
                                                       const double *__restrict__ wn, double *__restrict__ out,
                                                       const double *__restrict__ dtp, AmrGrid g, int mode, double ca,
                                                       double cb, int *__restrict__ flag) {
+  // UNI: a uniform grid (no fine block, an empty hole), so every face is a
+  // regular or a wall face and the face tables are the same for all lanes
   constexpr int D = 3;
   using C = Cfg<D, K>;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N, NSUB = 4;
   constexpr int M4 = (N + 3) / 4;
-  static_assert(QF % 4 == 0 && Q % 4 == 0, "nodes in rounds of four");
+  // nodes go in rounds of four; in a last, partial round the lanes past the
+  // end take the last node again and their contributions are dropped
   const long tid = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
   const int sub = threadIdx.x & 3;
   if (tid >= g.ncc + g.ncf) return;  // the four lanes of a cell leave together
@@ -1828,7 +1831,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
     double u[4], e[4];
 #pragma unroll 1
     for (int t = 0; t < 4; ++t) {
-      const double *bq = tab + C::B + (q0 + t) * N;
+      const double *bq = tab + C::B + min(q0 + t, Q - 1) * N;
       double su = 0.0, se = 0.0;
 #pragma unroll
       for (int l = 0; l < N; ++l) su = fma(wo[l], bq[l], su);
@@ -1863,7 +1866,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
       quad_transpose(fv, sub);  // fv[t]: flux of variable sub at node q0 + t
       const double fe[4] = {quad_from<0>(fe_own), quad_from<1>(fe_own), quad_from<2>(fe_own), quad_from<3>(fe_own)};
 #pragma unroll 1
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < (Q % 4 == 0 ? 4 : min(4, Q - q0)); ++t) {
         const double *dw = tab + C::DW + (a * Q + q0 + t) * N;
         double ft = fv[0], f4t = fe[0];
 #pragma unroll
@@ -1893,7 +1896,12 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
       const double *nbb = wb;
       long nbn = ncb;
       int j[3] = {0, 0, 0}, hsub = 0;
-      if (!fine) {
+      if constexpr (UNI) {
+        if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j))
+          kind = 1;
+        else
+          nbcell = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+      } else if (!fine) {
         if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
           kind = 1;
         } else if (amr_in_hole<D>(g, j)) {
@@ -1918,10 +1926,10 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
           hsub = (i[t0] & 1) | ((i[t1] & 1) << 1);
         }
       }
-      const int nsub = (kind == 2) ? NSUB : 1;
+      const int nsub = (!UNI && kind == 2) ? NSUB : 1;
 #pragma unroll 1
       for (int sb = 0; sb < nsub; ++sb) {
-        if (kind == 2) {
+        if (!UNI && kind == 2) {
           int fi[3] = {0, 0, 0};
           fi[a] = 2 * (j[a] - g.lo[a]) + (s ? 0 : 1);
           fi[t0] = 2 * (j[t0] - g.lo[t0]) + (sb & 1);
@@ -1941,12 +1949,12 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
 #pragma unroll
           for (int m = 0; m < M4; ++m, pe += nbn) ne[m] = (sub * M4 + m < N) ? *pe : 0.0;
         }
-        const double *to = (kind == 2) ? tab + C::HG + ((a * 2 + s) * 4 + hsub) * QF * N
-                                       : tab + C::TF + (a * 2 + s) * QF * N;
-        const double *tn = (kind == 3) ? tab + C::HG + ((a * 2 + (1 - s)) * 4 + hsub) * QF * N
-                                       : tab + C::TF + (a * 2 + (1 - s)) * QF * N;
-        const double *tw = (kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + hsub) * QF * N
-                                       : tab + C::TW + (a * 2 + s) * QF * N;
+        const double *to = (!UNI && kind == 2) ? tab + C::HG + ((a * 2 + s) * 4 + hsub) * QF * N
+                                               : tab + C::TF + (a * 2 + s) * QF * N;
+        const double *tn = (!UNI && kind == 3) ? tab + C::HG + ((a * 2 + (1 - s)) * 4 + hsub) * QF * N
+                                               : tab + C::TF + (a * 2 + (1 - s)) * QF * N;
+        const double *tw = (!UNI && kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + hsub) * QF * N
+                                               : tab + C::TW + (a * 2 + s) * QF * N;
 #pragma unroll 1
         for (int r0 = 0; r0 < QF; r0 += 4) {
           // one node at a time (the tables of a hanging face differ between
@@ -1954,7 +1962,8 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
           double uo[4], eo[4], un[4], en[4];
 #pragma unroll 1
           for (int t = 0; t < 4; ++t) {
-            const double *ro = to + (r0 + t) * N, *rn = tn + (r0 + t) * N;
+            const int rt = min(r0 + t, QF - 1);
+            const double *ro = to + rt * N, *rn = tn + rt * N;
             double so = 0.0, sn = 0.0, xo = 0.0, xn = 0.0;
 #pragma unroll
             for (int l = 0; l < N; ++l) {
@@ -1993,7 +2002,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
           quad_transpose(fv, sub);  // fv[t]: flux of variable sub at node r0 + t
           const double fe[4] = {quad_from<0>(F[4]), quad_from<1>(F[4]), quad_from<2>(F[4]), quad_from<3>(F[4])};
 #pragma unroll 1
-          for (int t = 0; t < 4; ++t) {
+          for (int t = 0; t < (QF % 4 == 0 ? 4 : min(4, QF - r0)); ++t) {
             const double *rw = tw + (r0 + t) * N;
             double ft = fv[0], f4t = fe[0];
 #pragma unroll
@@ -2301,6 +2310,19 @@ dg::AmrGrid make_amr_grid(const dg_ctx *c) {
   return g;
 }
 
+// The uniform grid as a refined box with no fine block and an empty hole.
+dg::AmrGrid make_uniform_amr_grid(const dg_ctx *c) {
+  dg::AmrGrid g = make_amr_grid(c);
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = 0;
+    g.hi[a] = 0;
+    g.nf[a] = 1;
+  }
+  g.ncc = c->ncell;
+  g.ncf = 0;
+  return g;
+}
+
 // Calls F::template run<D, K>() for the context's (dim, k).
 template <class F>
 int dispatch(const dg_ctx *c, F &&f) {
@@ -2348,8 +2370,8 @@ struct StageLaunch {
     if (c->amr) {
       if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
         // four lanes per cell (the one-thread kernel would spill)
-        hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0, s,
-                           c->tab, w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
+        hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0,
+                           s, c->tab, w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
       } else {
         hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab,
                            tabr, w, wn, out, dt, vext, make_amr_grid(c), mode, ca, cb, c->flag);
@@ -2359,6 +2381,15 @@ struct StageLaunch {
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
       hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
                          vext, make_grid(c), mode, ca, cb, c->flag, ro);
+    } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
+      // four lanes per cell: one thread per cell would hold two 100-double
+      // register sets (the weights and the accumulators) and spill 632 B per
+      // lane (at k = 2 the one-thread kernel, at one wave per SIMD, is twice
+      // as fast as this one, whose rounds of four nodes waste a quarter of the
+      // nine face nodes)
+      if (vext) return DG_EINVAL;
+      hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, true>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab,
+                         w, wn, out, dt, make_uniform_amr_grid(c), mode, ca, cb, c->flag);
     } else {
       hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
                          wn, out, dt, vext, make_grid(c), mode, ca, cb, c->flag);
