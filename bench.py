@@ -40,7 +40,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rhs_tile2d_vortex256_k2_traffic
 
 
 _FINGERPRINT_REGIONS = [
-    ("// Reciprocal and reciprocal square root from the hardware estimates plus", "// Dual number a + b eps"),
+    # reciprocal helpers, the time-step rate, the Euler flux
+    ("// Reciprocal and reciprocal square root from the hardware estimates plus",
+     "// HLLC numerical flux in +a between traces UL (low side) and UR (high side),"),
     ("// HLLC numerical flux in +a between traces UL (low side) and UR (high side),",
      "// ---------------------------------------------------------------------------\n// Right-hand side and fused SSP-RK3 stage."),
     ("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
@@ -76,8 +78,8 @@ def kernel_hash() -> str:
     for a, b in _FINGERPRINT_REGIONS:
         i = src.find(a)
         j = src.find(b, i + 1) if i >= 0 else -1
-        if i < 0 or j < 0:  # markers moved: fingerprint the whole file
-            return hashlib.sha256(src.encode()).hexdigest()[:16]
+        if i < 0 or j < 0:
+            raise RuntimeError(f"kernel fingerprint marker not found in {KERNEL_SRC}: {a if i < 0 else b!r}")
         parts.append(src[i:j])
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 

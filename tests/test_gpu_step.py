@@ -66,6 +66,8 @@ CASES = [
     ("vortex_k2_bf16", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0)), "bf16"),
     # 3D and the refined box: the two-kernel time step
     ("kh3d_k2_limited", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9)), "fp64"),
+    # uniform 3D at k = 3 runs the four-lanes-per-cell kernel
+    ("kh3d_k3_limited", dict(name="kh3d", k=3, n=(9, 8, 7), length=(0.9, 0.8, 0.7)), "fp64"),
     ("blast_amr_2d_k2", dict(amr=(2, 2, (10, 9, 1), (2, 3, 0), (7, 6, 0))), "fp64"),
     ("blast_amr_3d_k1", dict(amr=(3, 1, (8, 7, 6), (2, 2, 1), (6, 5, 4))), "fp64"),
 ]
@@ -121,8 +123,8 @@ def test_step_equals_composed_calls(case, spec, precision):
     assert s.status() == 0
 
 
-@pytest.mark.parametrize("case,spec,precision", [CASES[0], CASES[3], CASES[6], CASES[7]],
-                         ids=[CASES[i][0] for i in (0, 3, 6, 7)])
+@pytest.mark.parametrize("case,spec,precision", [CASES[0], CASES[3], CASES[6], CASES[7], CASES[8]],
+                         ids=[CASES[i][0] for i in (0, 3, 6, 7, 8)])
 def test_step_matches_oracle(case, spec, precision):
     _say("case", case)
     wl, o, s, w0 = _setup(spec, precision)
