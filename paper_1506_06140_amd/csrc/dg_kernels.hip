@@ -2046,6 +2046,165 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
   if (bad) atomicOr(flag, FLAG_NAN);
 }
 
+// ---------------------------------------------------------------------------
+// 2D adjoint with four lanes per cell: lane s owns variable s (its weights,
+// its lambda and its mu).  Nodes go in rounds of four (a last, partial round
+// repeats the last node and drops its contributions): each lane forms its
+// variable's part at the four nodes, a quad transpose hands lane t all four
+// variables at node t for the transposed Euler flux or the reverse sweep
+// through the Riemann solver, and a transpose back returns to lane s its
+// variable's cotangents.  The arithmetic and its order are those of
+// k_adjoint; one thread per cell holds three state-sized register sets there
+// and spills at k = 3.
+// ---------------------------------------------------------------------------
+template <int K, int FX>
+__global__ __launch_bounds__(256) void k_adjoint_quad2d(const double *__restrict__ tab, const double *__restrict__ w,
+                                                        const double *__restrict__ lam, const double *acc_in,
+                                                        double *__restrict__ out, double *acc_out,
+                                                        const double *__restrict__ dtp, Grid g, int mode, double ca,
+                                                        double cb, int *__restrict__ flag) {
+  constexpr int D = 2;
+  using C = Cfg<D, K>;
+  constexpr int NV = C::NV, N = C::N, Q = C::Q, QF = C::QF;
+  static_assert(NV == 4, "one lane per variable");
+  const long cell = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+  const int sub = threadIdx.x & 3;
+  if (cell >= g.ncell) return;  // the four lanes of a cell leave together
+  const long nc = g.ncell;
+  const int ix = (int)(cell % g.nx), iy = (int)((cell / g.nx) % g.ny);
+
+  double wv[N], lv[N], mu[N];
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const long i = (long)(sub * N + l) * nc + cell;
+    wv[l] = w[i];
+    lv[l] = lam[i];
+    mu[l] = 0.0;
+  }
+
+  // volume term
+#pragma unroll 1
+  for (int q0 = 0; q0 < Q; q0 += 4) {
+    double u[4], lx[4], ly[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int qt = min(q0 + t, Q - 1);
+      const double *bq = tab + C::B + qt * N;
+      const double *d0 = tab + C::DW + qt * N, *d1 = tab + C::DW + (Q + qt) * N;
+      double su = 0.0, s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        su = fma(wv[l], bq[l], su);
+        s0 = fma(lv[l], d0[l], s0);
+        s1 = fma(lv[l], d1[l], s1);
+      }
+      u[t] = su;
+      lx[t] = s0;
+      ly[t] = s1;
+    }
+    quad_transpose(u, sub);  // lane t: the four variables at node q0 + t
+    quad_transpose(lx, sub);
+    quad_transpose(ly, sub);
+    double G[NV] = {0.0, 0.0, 0.0, 0.0};
+    euler_flux_vjp<D>(u, 0, g.gamma, lx, G);
+    euler_flux_vjp<D>(u, 1, g.gamma, ly, G);
+    quad_transpose(G, sub);  // G[t]: component sub at node q0 + t
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (Q % 4 == 0 || q0 + t < Q) {
+        const double *bq = tab + C::B + (q0 + t) * N;
+#pragma unroll
+        for (int l = 0; l < N; ++l) mu[l] = fma(G[t], bq[l], mu[l]);
+      }
+    }
+  }
+
+  // face terms: own side with TF(s), TW(s); neighbour side with TF(1-s),
+  // TW(1-s) (see k_adjoint)
+#pragma unroll 1
+  for (int a = 0; a < D; ++a) {
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+      const long nb = neighbour(g, ix, iy, 0, a, s ? 1 : -1);
+      const long src = nb >= 0 ? nb : cell;
+      double wnb[N], lnb[N];
+#pragma unroll
+      for (int l = 0; l < N; ++l) {
+        const long i = (long)(sub * N + l) * nc + src;
+        wnb[l] = w[i];
+        lnb[l] = lam[i];
+      }
+      const double *to = tab + C::TF + (a * 2 + s) * QF * N;
+      const double *tn = tab + C::TF + (a * 2 + (1 - s)) * QF * N;
+      const double *two = tab + C::TW + (a * 2 + s) * QF * N;
+      const double *twn = tab + C::TW + (a * 2 + (1 - s)) * QF * N;
+#pragma unroll 1
+      for (int r0 = 0; r0 < QF; r0 += 4) {
+        double uo[4], un[4], lo[4], ln[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int rt = min(r0 + t, QF - 1);
+          double so = 0.0, sn = 0.0, xo = 0.0, xn = 0.0;
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            so = fma(wv[l], to[rt * N + l], so);
+            sn = fma(wnb[l], tn[rt * N + l], sn);
+            xo = fma(lv[l], two[rt * N + l], xo);
+            xn = fma(lnb[l], twn[rt * N + l], xn);
+          }
+          uo[t] = so;
+          un[t] = sn;
+          lo[t] = xo;
+          ln[t] = xn;
+        }
+        quad_transpose(uo, sub);  // lane t: the four variables at node r0 + t
+        quad_transpose(un, sub);
+        quad_transpose(lo, sub);
+        quad_transpose(ln, sub);
+        double UL[NV], UR[NV], gv[NV], gL[NV], gR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          if (nb < 0) ln[v] = 0.0;  // the ghost cell of a transmissive boundary has no equation
+          const double nv = nb >= 0 ? un[v] : uo[v];
+          gv[v] = s ? ln[v] - lo[v] : lo[v] - ln[v];  // lam_high . TW(-1) - lam_low . TW(+1)
+          UL[v] = s ? uo[v] : nv;
+          UR[v] = s ? nv : uo[v];
+        }
+        hllc_vjp<D, FX>(UL, UR, a, g.gamma, gv, gL, gR);
+        double h[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) h[v] = (s ? gL[v] : gR[v]) + (nb >= 0 ? 0.0 : (s ? gR[v] : gL[v]));
+        quad_transpose(h, sub);  // h[t]: component sub at node r0 + t
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          if (QF % 4 == 0 || r0 + t < QF) {
+#pragma unroll
+            for (int l = 0; l < N; ++l) mu[l] = fma(h[t], to[(r0 + t) * N + l], mu[l]);
+          }
+        }
+      }
+    }
+  }
+
+  const double dt = (mode == 0) ? 0.0 : *dtp;
+  bool bad = false;
+#pragma unroll
+  for (int l = 0; l < N; ++l) {
+    const long i = (long)(sub * N + l) * nc + cell;
+    const double m = g.fac * mu[l];
+    bad |= (m != m);
+    if (mode == 0) {
+      out[i] = m;
+    } else if (mode == 1) {
+      out[i] = acc_in[i] + (lv[l] + dt * m);
+    } else {
+      out[i] = cb * (lv[l] + dt * m);
+      acc_out[i] = (mode == 3) ? ca * lv[l] : acc_in[i] + ca * lv[l];
+    }
+  }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
 // Time step over both blocks (each cell with its own edge length); same
 // two-kernel reduction as k_rate / k_dt_final.
 template <int D>
@@ -2479,12 +2638,17 @@ struct AdjointLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
-    if (c->cfg.flux == DG_HLLC_DAVIS)
-      hipLaunchKernelGGL((dg::k_adjoint<D, K, DG_HLLC_DAVIS>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w,
-                         lam, acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
-    else
-      hipLaunchKernelGGL((dg::k_adjoint<D, K, DG_HLLC_BATTEN>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w,
-                         lam, acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    return c->cfg.flux == DG_HLLC_DAVIS ? run_fx<D, K, DG_HLLC_DAVIS>() : run_fx<D, K, DG_HLLC_BATTEN>();
+  }
+  template <int D, int K, int FX>
+  int run_fx() {
+    if constexpr (D == 2) {  // four lanes per cell
+      hipLaunchKernelGGL((dg::k_adjoint_quad2d<K, FX>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab, w, lam,
+                         acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    } else {
+      hipLaunchKernelGGL((dg::k_adjoint<D, K, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, lam, acc,
+                         out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
+    }
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
