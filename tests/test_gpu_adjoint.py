@@ -56,6 +56,7 @@ ADJ_CASES = [
     ("2d_k3", dict(dim=2, k=3, n=(9, 7, 1))),
     ("2d_k2_davis", dict(dim=2, k=2, n=(9, 7, 1), flux=1)),
     ("2d_k2_transmissive", dict(dim=2, k=2, n=(9, 7, 1), bc=(1, 0, 0))),
+    ("2d_k3_transmissive_xy_davis", dict(dim=2, k=3, n=(9, 7, 1), bc=(1, 1, 0), flux=1)),
     ("3d_k1", dict(dim=3, k=1, n=(5, 4, 3))),
     ("3d_k2", dict(dim=3, k=2, n=(5, 4, 3))),
 ]
