@@ -26,6 +26,18 @@ def test_library_exports_every_declared_function():
     assert set(names) == set(dg.EXPORTS)
 
 
+def test_rate_state_size_matches_header():
+    # the binding allocates and reads the carried rate state with the layout
+    # the header states (8 slots, 16 doubles apart)
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    m = re.search(r"#define\s+DG_RATE_STATE\s+(\d+)", src)
+    assert m and int(m.group(1)) == dg.DG_RATE_STATE
+    assert dg.RATE_SLOTS * dg.RATE_STRIDE == dg.DG_RATE_STATE
+    kern = open(os.path.join(ROOT, "paper_1506_06140_amd", "csrc", "dg_kernels.hip")).read()
+    k = re.search(r"RATE_SLOTS\s*=\s*(\d+),\s*RATE_STRIDE\s*=\s*(\d+)", kern)
+    assert k and (int(k.group(1)), int(k.group(2))) == (dg.RATE_SLOTS, dg.RATE_STRIDE)
+
+
 def test_strerror_covers_codes():
     for code in range(0, -7, -1):
         assert dg.strerror(code) != "unknown error"
