@@ -85,6 +85,7 @@ def _load():
             "orc_max_dt": [cp, dp, dp],
             "orc_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
             "orc_limit": [cp, dp],
+            "orc_eigvecs": [cp, dp, C.c_int, dp, dp],
             "orc_positivity_points": [cp, dp],
             "orc_amr_sizes": [cp, lp],
             "orc_amr_node_coords": [cp, dp],
@@ -294,6 +295,14 @@ class Oracle:
         out = np.array(self._s(w), copy=True)
         st = lib.orc_limit(C.byref(self.c), out)
         return out, st
+
+    def eigvecs(self, U, axis: int):
+        """(R, L): right and left eigenvectors of the flux Jacobian in `axis`
+        at the conserved state U (App. E)."""
+        lib, _ = _load()
+        R = np.zeros((self.nvar, self.nvar)); L = np.zeros((self.nvar, self.nvar))
+        _check(lib.orc_eigvecs(C.byref(self.c), np.ascontiguousarray(U, dtype=np.float64), axis, R, L), "eigvecs")
+        return R, L
 
     def stage(self, stage: int, dt: float, wn: np.ndarray, wp: np.ndarray) -> np.ndarray:
         """RK stage followed by the limiters, if the run has any (main loop)."""

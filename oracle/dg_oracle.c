@@ -27,6 +27,7 @@
  *   weak form, volume/face terms .... Sec. 2.4, eqs. dg_projected, dg_term2, dg_term3
  *   time step ....................... Sec. 2.5 eq. time_step; Sec. 3.4 eq. time_step_pos
  *   component-wise TVB minmod ....... Sec. 3.1 eq. comp_limiter; Sec. 3.3
+ *   characteristic TVB minmod ....... Sec. 3.2 eq. char_limiter; App. E
  *   positivity limiter .............. Sec. 3.4, eqs. union_quad_points, p_positivity
  *   AMR faces / limiting ............ Sec. 4 (hanging-face quadrature), Sec. 4.4
  *   refinement matrices ............. Sec. 4.2 eq. ref_pa_integral, App. F
@@ -79,7 +80,8 @@ typedef struct {
   double gamma, cfl;
   int bc[3];       /* 0 periodic, 1 transmissive (ghost trace = own trace)   */
   int flux;        /* 0 HLLC with Einfeldt-Batten speeds, 1 HLLC with Davis */
-  int limiter;     /* 0 none, 1 component-wise minmod with TVB bound        */
+  int limiter;     /* 0 none, 1 component-wise minmod with TVB bound,
+                      2 the same on the characteristic variables            */
   double beta, mtilde;
   int positivity;  /* 0/1 Zhang-Shu positivity limiter                      */
   double eps;
@@ -192,6 +194,7 @@ static int ctx_init(const orc_config *c, ctx *X) {
   memset(X, 0, sizeof(*X));
   X->c = *c;
   if (c->dim < 2 || c->dim > 3 || c->k < 0 || c->k > MAXK) return ORC_EINVAL;
+  if (c->limiter < 0 || c->limiter > 2) return ORC_EINVAL;
   X->d = c->dim; X->k = c->k; X->n1 = c->k + 1;
   X->nvar = c->dim + 2;
   X->nx = c->n[0]; X->ny = c->n[1]; X->nz = (c->dim == 3) ? c->n[2] : 1;
@@ -746,6 +749,143 @@ static void slope_limit(const ctx *X, double *w, const double *nbm, const double
   }
 }
 
+/* Right eigenvectors (columns of R) and left eigenvectors (rows of L = R^-1)
+ * of the flux Jacobian A_a = d f_a / d u at the state U, as App. E lists them
+ * for a = x, y, z: eigenvalues v_a - c, v_a, v_a + c and two shear waves at
+ * v_a; k = |v|^2 / 2 (the text prints v_3 cubed in k, a slip), the specific
+ * stagnation enthalpy h = c^2 / (gamma - 1) + k, gamma_1 = gamma - 1,
+ * phi = gamma_1 k and b = 1 / (2 c^2) (the text calls it beta).  In 2D the
+ * matrices are those of 3D at v_3 = 0 without the row and column of m_z and
+ * without the z shear wave, which decouple there.  R and L are nvar x nvar,
+ * row-major.  Returns 0 if U has no positive density and pressure. */
+static int eigvecs(const ctx *X, const double *U, int a, double *R, double *L) {
+  int d = X->d, nv = X->nvar;
+  double g = X->c.gamma, g1 = g - 1.0;
+  double rho = U[0];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int b = 0; b < d; ++b) v[b] = U[1 + b] / rho;
+  double k = 0.5 * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  double p = g1 * (U[d + 1] - rho * k);
+  if (!(rho > 0.0) || !(p > 0.0)) return 0;
+  double c = sqrt(g * p / rho);
+  double h = c * c / g1 + k;
+  double phi = g1 * k, b = 1.0 / (2.0 * c * c);
+  double v1 = v[0], v2 = v[1], v3 = v[2];
+  double R5[5][5], L5[5][5];
+  if (a == 0) {
+    double r[5][5] = {{1, 1, 1, 0, 0},
+                      {v1 - c, v1, v1 + c, 0, 0},
+                      {v2, v2, v2, -1, 0},
+                      {v3, v3, v3, 0, 1},
+                      {h - c * v1, k, h + c * v1, -v2, v3}};
+    double l[5][5] = {{b * (phi + c * v1), -b * (g1 * v1 + c), -b * g1 * v2, -b * g1 * v3, b * g1},
+                      {1 - 2 * b * phi, 2 * b * g1 * v1, 2 * b * g1 * v2, 2 * b * g1 * v3, -2 * b * g1},
+                      {b * (phi - c * v1), -b * (g1 * v1 - c), -b * g1 * v2, -b * g1 * v3, b * g1},
+                      {v2, 0, -1, 0, 0},
+                      {-v3, 0, 0, 1, 0}};
+    memcpy(R5, r, sizeof(r)); memcpy(L5, l, sizeof(l));
+  } else if (a == 1) {
+    double r[5][5] = {{1, 1, 1, 0, 0},
+                      {v1, v1, v1, 1, 0},
+                      {v2 - c, v2, v2 + c, 0, 0},
+                      {v3, v3, v3, 0, -1},
+                      {h - c * v2, k, h + c * v2, v1, -v3}};
+    double l[5][5] = {{b * (phi + c * v2), -b * g1 * v1, -b * (g1 * v2 + c), -b * g1 * v3, b * g1},
+                      {1 - 2 * b * phi, 2 * b * g1 * v1, 2 * b * g1 * v2, 2 * b * g1 * v3, -2 * b * g1},
+                      {b * (phi - c * v2), -b * g1 * v1, -b * (g1 * v2 - c), -b * g1 * v3, b * g1},
+                      {-v1, 1, 0, 0, 0},
+                      {v3, 0, 0, -1, 0}};
+    memcpy(R5, r, sizeof(r)); memcpy(L5, l, sizeof(l));
+  } else {
+    double r[5][5] = {{1, 1, 1, 0, 0},
+                      {v1, v1, v1, -1, 0},
+                      {v2, v2, v2, 0, 1},
+                      {v3 - c, v3, v3 + c, 0, 0},
+                      {h - c * v3, k, h + c * v3, -v1, v2}};
+    double l[5][5] = {{b * (phi + c * v3), -b * g1 * v1, -b * g1 * v2, -b * (g1 * v3 + c), b * g1},
+                      {1 - 2 * b * phi, 2 * b * g1 * v1, 2 * b * g1 * v2, 2 * b * g1 * v3, -2 * b * g1},
+                      {b * (phi - c * v3), -b * g1 * v1, -b * g1 * v2, -b * (g1 * v3 - c), b * g1},
+                      {v1, -1, 0, 0, 0},
+                      {-v2, 0, 1, 0, 0}};
+    memcpy(R5, r, sizeof(r)); memcpy(L5, l, sizeof(l));
+  }
+  /* conserved components and waves kept: all in 3D; in 2D rho, m_x, m_y, E
+   * and the waves v-c, v, v+c and the in-plane shear wave */
+  static const int cons2[4] = {0, 1, 2, 4}, wave2[4] = {0, 1, 2, 3};
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) {
+      int ci = d == 3 ? i : cons2[i], wj = d == 3 ? j : wave2[j];
+      int wi = d == 3 ? i : wave2[i], cj = d == 3 ? j : cons2[j];
+      R[i * nv + j] = R5[ci][wj];
+      L[i * nv + j] = L5[wi][cj];
+    }
+  return 1;
+}
+
+/* Characteristic limiter (Sec. 3.2, eq. char_limiter, with the bounded
+ * minmod of Sec. 3.3): in each direction a the slopes w_{1+a} and the
+ * differences of the neighbouring means go to characteristic variables with
+ * L_a of the cell mean; sqrt(3) c_{1+a} is limited against beta L_a (w_1^K -
+ * w_1^W) and beta L_a (w_1^E - w_1^K), field by field.  If any characteristic
+ * slope changes, every component keeps its mean and the slopes R_a c~ (the
+ * text writes R_x for the y and z directions as well; the inverses R_y, R_z
+ * of L_y, L_z are meant), and the higher modes are dropped.  A cell whose mean
+ * has no real sound speed is left as it is (the positivity limiter reports
+ * it).  Same neighbour means as slope_limit. */
+static void char_limit(const ctx *X, double *w, const double *nbm, const double *dxc, const unsigned char *skip) {
+  long nc = X->ncell;
+  int d = X->d, nv = X->nvar;
+  const double r3 = sqrt(3.0);
+  for (long cell = 0; cell < nc; ++cell) {
+    if (skip && skip[cell]) continue;
+    double bound = X->c.mtilde * dxc[cell];
+    double U[MAXV];
+    for (int i = 0; i < nv; ++i) U[i] = W(i, 0, cell);
+    double R[3][MAXV * MAXV], L[MAXV * MAXV], ct[3][MAXV];
+    int ok = 1, limited = 0;
+    for (int a = 0; a < d && ok; ++a) {
+      ok = eigvecs(X, U, a, R[a], L);
+      if (!ok) break;
+      double dW[MAXV], dE[MAXV];
+      for (int i = 0; i < nv; ++i) {
+        dW[i] = U[i] - nbm[((long)(2 * a + 0) * nv + i) * nc + cell];
+        dE[i] = nbm[((long)(2 * a + 1) * nv + i) * nc + cell] - U[i];
+      }
+      for (int p = 0; p < nv; ++p) {
+        double cs = 0.0, cw = 0.0, ce = 0.0;
+        for (int i = 0; i < nv; ++i) {
+          cs += L[p * nv + i] * W(i, 1 + a, cell);
+          cw += L[p * nv + i] * dW[i];
+          ce += L[p * nv + i] * dE[i];
+        }
+        double A = r3 * cs;
+        double m = minmod_b(A, X->c.beta * cw, X->c.beta * ce, bound);
+        ct[a][p] = m;
+        if (m != A) limited = 1;
+      }
+    }
+    if (!ok || !limited) continue;
+    for (int a = 0; a < d; ++a)
+      for (int i = 0; i < nv; ++i) {
+        double s2 = 0.0;
+        for (int p = 0; p < nv; ++p) s2 += R[a][i * nv + p] * (ct[a][p] / r3);
+        W(i, 1 + a, cell) = s2;
+      }
+    for (int i = 0; i < nv; ++i)
+      for (int l = d + 1; l < X->N; ++l) W(i, l, cell) = 0.0;
+  }
+}
+
+/* App. E matrices at U for tests: R, L (nvar x nvar row-major).  Returns
+ * ORC_EINVAL for a state without positive density and pressure. */
+int orc_eigvecs(const orc_config *c, const double *U, int a, double *R, double *L) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st == ORC_OK && (a < 0 || a >= X->d || !eigvecs(X, U, a, R, L))) st = ORC_EINVAL;
+  free(X);
+  return st;
+}
+
 /* Root tau in [0,1] of p(ubar + tau (u - ubar)) = eps (eq. p_positivity, read
  * with the high-order part u - ubar scaled): (E - eps/(g-1)) rho - |m|^2/2 is
  * quadratic in tau.  Cancellation-free quadratic formula, then two Newton
@@ -862,7 +1002,10 @@ int orc_limit(const orc_config *c, double *w) {
     double *dxc = malloc(sizeof(double) * X->ncell);
     for (long i = 0; i < X->ncell; ++i) dxc[i] = X->dx;
     uniform_neighbour_means(X, w, nbm);
-    slope_limit(X, w, nbm, dxc, NULL);
+    if (c->limiter == 2)
+      char_limit(X, w, nbm, dxc, NULL);
+    else
+      slope_limit(X, w, nbm, dxc, NULL);
     free(nbm); free(dxc);
   }
   if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0, NULL);
@@ -1336,8 +1479,13 @@ int orc_amr_limit(const orc_config *c, double *w) {
           }
         }
     }
-    slope_limit(X, wc, nbc, dxc, hole);
-    slope_limit(Y, wf, nbf, dxf, NULL);
+    if (c->limiter == 2) {
+      char_limit(X, wc, nbc, dxc, hole);
+      char_limit(Y, wf, nbf, dxf, NULL);
+    } else {
+      slope_limit(X, wc, nbc, dxc, hole);
+      slope_limit(Y, wf, nbf, dxf, NULL);
+    }
     free(nbc); free(nbf); free(dxc); free(dxf);
   }
   if (c->positivity) {
