@@ -189,10 +189,13 @@ def variants():
     out = {}
     # the refined-box blast in reduced precision needs a positivity floor above
     # the FP32 rounding of the energy (node pressures are formed in FP32)
-    runs = [("vortex", 400, {}, ("fp64", "fp32", "bf16")),
-            ("kh3d", 10, {}, ("fp64", "fp32", "bf16")),
-            ("blast_amr", 10, {"eps": 1e-4}, ("fp64", "fp32", "bf16"))]
-    for name, steps, over, precs in runs:
+    # (the *_char runs: the same workloads with the characteristic limiter)
+    runs = [("vortex", "vortex", 400, {}, ("fp64", "fp32", "bf16")),
+            ("kh3d", "kh3d", 10, {}, ("fp64", "fp32", "bf16")),
+            ("kh3d_char", "kh3d", 10, {"limiter": 2}, ("fp64",)),
+            ("blast_amr", "blast_amr", 10, {"eps": 1e-4}, ("fp64", "fp32", "bf16")),
+            ("blast_amr_char", "blast_amr", 10, {"eps": 1e-4, "limiter": 2}, ("fp64",))]
+    for label, name, steps, over, precs in runs:
         wl = workloads.workload(name, **over)
         for prec in precs:
             s = dg.Solver(wl, prec)
@@ -202,9 +205,10 @@ def variants():
             peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
             # fractions of one step's algorithmic work (3 stages) over the
             # whole step time (time step and limiters included)
-            out[f"{name}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": cells * s.N * 3 / (ms * 1e-3),
+            out[f"{label}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": cells * s.N * 3 / (ms * 1e-3),
                                      "cells": cells, "k": wl["k"], "dim": wl["dim"],
-                                     "limited": bool(s.limited), "eps": wl["eps"], "status": s.status(),
+                                     "limiter": wl["limiter"], "positivity": wl["positivity"],
+                                     "eps": wl["eps"], "status": s.status(),
                                      "hbm_frac": 3 * b * cells / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
                                      "alu_frac": 3 * f * cells / (ms * 1e-3) / (peak * 1e12),
                                      "alu_peak_tflops": peak}

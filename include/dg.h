@@ -57,7 +57,7 @@ enum {
 enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
 enum { DG_HLLC_BATTEN = 0, DG_HLLC_DAVIS = 1 };
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16_VOL = 2 };
-enum { DG_LIM_NONE = 0, DG_LIM_MINMOD = 1 };
+enum { DG_LIM_NONE = 0, DG_LIM_MINMOD = 1, DG_LIM_CHAR = 2 };
 
 typedef struct dg_ctx dg_ctx;
 
@@ -74,7 +74,9 @@ typedef struct {
   int flux;           /* DG_HLLC_BATTEN (Roe-averaged speed bounds) or DAVIS  */
   int precision;      /* DG_FP64, DG_FP32 (contractions and fluxes in FP32),
                          DG_BF16_VOL (volume contraction BF16 on MFMA)         */
-  int slope_limiter;  /* DG_LIM_NONE or DG_LIM_MINMOD (component-wise, TVB)    */
+  int slope_limiter;  /* DG_LIM_NONE, DG_LIM_MINMOD (component-wise, TVB,
+                         Sec. 3.1) or DG_LIM_CHAR (characteristic, TVB,
+                         Sec. 3.2 with the App. E eigenvectors)               */
   double beta;        /* minmod parameter beta in [0.5, 1] (Sec. 3.1)          */
   double m_tilde;     /* TVB bound Mtilde; slopes |a| <= Mtilde dx kept (3.3)  */
   int positivity;     /* 1: Zhang-Shu positivity limiter (Sec. 3.4)            */
@@ -169,10 +171,13 @@ int dg_max_rate(dg_ctx *ctx, const double *w, double *rate_dev, void *stream);
 int dg_rk_step(dg_ctx *ctx, const double *w, double *u1, double *u2, double *w_out,
                double *dt_dev, double *rate_dev, void *stream);
 
-/* Slope limiter (component-wise minmod with TVB bound, Sec. 3.1/3.3) then
- * positivity limiter (Sec. 3.4), in place, as configured.  Cell means are
- * never changed.  A cell whose mean density or pressure is <= eps sets the
- * DG_ENEGATIVE flag and is left unlimited. */
+/* Slope limiter (minmod with TVB bound, Sec. 3.3: component-wise on the
+ * conserved variables, Sec. 3.1, or on the characteristic variables of the
+ * cell mean, Sec. 3.2 eq. char_limiter) then positivity limiter (Sec. 3.4),
+ * in place, as configured.  Cell means are never changed.  A cell whose mean
+ * density or pressure is <= eps sets the DG_ENEGATIVE flag and is left
+ * unlimited; the characteristic limiter also leaves alone a mean without a
+ * positive density and pressure. */
 int dg_limit(dg_ctx *ctx, double *w, void *stream);
 
 /* Discrete adjoint of dg_rhs: mu = (dL/dw)^T lam at the state w (all

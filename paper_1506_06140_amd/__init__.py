@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(_HERE, "libdg.so"))
 
 DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
+DG_LIM_NONE, DG_LIM_MINMOD, DG_LIM_CHAR = 0, 1, 2
 # doubles in the carried rate state (8 slots, 16 apart; the rate is the largest slot)
 DG_RATE_STATE, RATE_SLOTS, RATE_STRIDE = 128, 8, 16
 PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}

@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "dg_internal.h"
 
@@ -1248,6 +1249,139 @@ __device__ inline double minmod3(double a, double b, double c) {
   return 0.0;
 }
 
+// Eigen-structure of the Euler flux Jacobian in direction a at a cell mean
+// (App. E), applied in factored form instead of as dense matrices.  With
+// k = |v|^2/2, h = c^2/(gamma-1) + k, b = 1/(2c^2), the pressure perturbation
+// P(x) = (gamma-1)(k x_rho - v.x_m + x_E) and U_a(x) = v_a x_rho - x_{m_a},
+// the characteristic variables of a conserved vector x are
+//   acoustic (v_a - c):  b (P + c U_a)
+//   entropy  (v_a):      x_rho - 2 b P
+//   acoustic (v_a + c):  b (P - c U_a)
+//   shear    (v_a):      x_{m_t} - v_t x_rho   for each direction t != a,
+// and to_cons is the inverse map.  The shear waves are oriented with a plus
+// sign throughout (App. E flips some of them): negating an eigenvector and its
+// left counterpart leaves R c~ unchanged, and minmod is odd, so the limited
+// slopes do not depend on the orientation.
+template <int D>
+struct CharBasis {
+  double v[D], k, c, h, g1, b;
+
+  // false if the mean has no positive density and pressure
+  __device__ bool init(const double *U, double gamma) {
+    const double ir = 1.0 / U[0];
+    k = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) {
+      v[t] = U[1 + t] * ir;
+      k = fma(v[t], v[t], k);
+    }
+    k *= 0.5;
+    g1 = gamma - 1.0;
+    const double p = g1 * (U[D + 1] - U[0] * k);
+    if (!(U[0] > 0.0) || !(p > 0.0)) return false;
+    const double c2 = gamma * p * ir;
+    c = sqrt(c2);
+    h = c2 / g1 + k;
+    b = 0.5 / c2;
+    return true;
+  }
+
+  template <int A>
+  __device__ void to_char(const double *x, double *ch) const {
+    double vm = 0.0;
+#pragma unroll
+    for (int t = 0; t < D; ++t) vm = fma(v[t], x[1 + t], vm);
+    const double P = g1 * (k * x[0] - vm + x[D + 1]);
+    const double Ua = v[A] * x[0] - x[1 + A];
+    ch[0] = b * (P + c * Ua);
+    ch[1] = x[0] - 2.0 * b * P;
+    ch[2] = b * (P - c * Ua);
+    int j = 3;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+      if (t != A) ch[j++] = x[1 + t] - v[t] * x[0];
+  }
+
+  template <int A>
+  __device__ void to_cons(const double *ch, double *x) const {
+    const double S = ch[0] + ch[1] + ch[2], Dc = ch[2] - ch[0];
+    x[0] = S;
+    x[1 + A] = v[A] * S + c * Dc;
+    double E = h * (ch[0] + ch[2]) + k * ch[1] + c * v[A] * Dc;
+    int j = 3;
+#pragma unroll
+    for (int t = 0; t < D; ++t)
+      if (t != A) {
+        x[1 + t] = v[t] * S + ch[j];
+        E = fma(v[t], ch[j], E);
+        ++j;
+      }
+    x[D + 1] = E;
+  }
+};
+
+// Characteristic TVB limiter of one cell (eq. char_limiter with the bound of
+// Sec. 3.3): in each direction the slope sqrt(3) w_{1+a} and the neighbour
+// mean differences go to characteristic variables at the cell mean and are
+// limited field by field; if any field changes, all slopes are rebuilt from
+// the limited characteristic slopes and the higher modes are dropped.  The
+// means are kept.  nbmean(a, s, m) writes the mean of the neighbour on side
+// s (0 low, 1 high) in direction a.  A mean without a real sound speed is
+// left alone (the positivity pass flags it).
+template <int D, int N, class NbMean>
+__device__ inline void char_limit_cell(double (&wc)[D + 2][N], NbMean &&nbmean, double gamma, double beta,
+                                       double bound) {
+  constexpr int NV = D + 2;
+  double U[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) U[v] = wc[v][0];
+  CharBasis<D> e;
+  if (!e.init(U, gamma)) return;
+  const double r3 = sqrt(3.0);
+  double ct[D][NV];
+  bool limited = false;
+  auto dir = [&](auto A_) {
+    constexpr int A = decltype(A_)::value;
+    double x[NV], lo[NV], hi[NV], cs[NV], cw[NV], ce[NV];
+    nbmean(A, 0, lo);
+    nbmean(A, 1, hi);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      x[v] = wc[v][1 + A];
+      lo[v] = U[v] - lo[v];
+      hi[v] = hi[v] - U[v];
+    }
+    e.template to_char<A>(x, cs);
+    e.template to_char<A>(lo, cw);
+    e.template to_char<A>(hi, ce);
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const double Aq = r3 * cs[q];
+      const double m = (fabs(Aq) <= bound) ? Aq : minmod3(Aq, beta * cw[q], beta * ce[q]);
+      ct[A][q] = m / r3;
+      limited |= (m != Aq);
+    }
+  };
+  dir(std::integral_constant<int, 0>{});
+  dir(std::integral_constant<int, 1>{});
+  if constexpr (D == 3) dir(std::integral_constant<int, 2>{});
+  if (!limited) return;
+  auto back = [&](auto A_) {
+    constexpr int A = decltype(A_)::value;
+    double x[NV];
+    e.template to_cons<A>(ct[A], x);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wc[v][1 + A] = x[v];
+  };
+  back(std::integral_constant<int, 0>{});
+  back(std::integral_constant<int, 1>{});
+  if constexpr (D == 3) back(std::integral_constant<int, 2>{});
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = D + 1; l < N; ++l) wc[v][l] = 0.0;
+}
+
 // Root in [0,1] of (E(t) - eps/(g-1)) rho(t) - |m(t)|^2/2 = 0 along
 // U(t) = Ub + t (Uq - Ub): quadratic formula without cancellation, then two
 // Newton steps; bisection when rounding makes the discriminant negative.
@@ -1290,7 +1424,9 @@ __device__ inline double tau_root(const double *Ub, const double *Uq, double gam
   return fmin(fmax(t, 0.0), 1.0);
 }
 
-template <int D, int K>
+// CHAR selects the characteristic limiter (eq. char_limiter) for the slope
+// pass, else the component-wise one (eq. comp_limiter).
+template <int D, int K, bool CHAR>
 __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, double *__restrict__ w, Grid g,
                                                int slope, double beta, double bound, int posit, double eps,
                                                int *__restrict__ flag) {
@@ -1317,6 +1453,14 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
       if (nbl[a] < 0) nbl[a] = cell;
       if (nbh[a] < 0) nbh[a] = cell;
     }
+    if constexpr (CHAR) {
+      auto nbmean = [&](int a, int s, double *m) {
+        const long nb = s ? nbh[a] : nbl[a];
+#pragma unroll
+        for (int v = 0; v < C::NV; ++v) m[v] = w[(long)(v * C::N) * nc + nb];
+      };
+      char_limit_cell<D, C::N>(wc, nbmean, g.gamma, beta, bound);
+    } else
 #pragma unroll
     for (int i = 0; i < C::NV; ++i) {
       const double mean = wc[i][0];
@@ -2237,7 +2381,7 @@ __global__ __launch_bounds__(256) void k_rate_amr(const double *__restrict__ w, 
 // boundary are the children's average (coarse side) or the coarse polynomial's
 // mean over the adjacent child (fine side); coarse cells facing the fine block
 // also check positivity at the hanging-face points.
-template <int D, int K>
+template <int D, int K, bool CHAR>
 __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ tab, double *__restrict__ w, AmrGrid g,
                                                    int slope, double beta, double mtilde, int posit, double eps,
                                                    int *__restrict__ flag) {
@@ -2318,6 +2462,13 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
   const double dx = fine ? g.dxf : g.dxc;
   if (slope && K >= 1) {
     const double r3 = sqrt(3.0), bound = mtilde * dx;
+    if constexpr (CHAR) {
+      auto nbmean = [&](int a, int s, double *m) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) m[v] = nbm[2 * a + s][v];
+      };
+      char_limit_cell<D, N>(wc, nbmean, g.gamma, beta, bound);
+    } else
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const double mean = wc[v][0];
@@ -2614,13 +2765,15 @@ struct LimitLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
+    const bool chr = c->cfg.slope_limiter == DG_LIM_CHAR;
+    const int slope = c->cfg.slope_limiter != DG_LIM_NONE;
     if (c->amr) {
-      hipLaunchKernelGGL((dg::k_limit_amr<D, K>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w,
-                         make_amr_grid(c), c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde,
-                         c->cfg.positivity, c->cfg.eps, c->flag);
+      hipLaunchKernelGGL((chr ? dg::k_limit_amr<D, K, true> : dg::k_limit_amr<D, K, false>),
+                         dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w, make_amr_grid(c), slope,
+                         c->cfg.beta, c->cfg.m_tilde, c->cfg.positivity, c->cfg.eps, c->flag);
     } else {
-      hipLaunchKernelGGL((dg::k_limit<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
-                         c->cfg.slope_limiter == DG_LIM_MINMOD, c->cfg.beta, c->cfg.m_tilde * c->dx,
+      hipLaunchKernelGGL((chr ? dg::k_limit<D, K, true> : dg::k_limit<D, K, false>), dim3(nblocks(c->ncell)),
+                         dim3(kBlock), 0, s, c->tab, w, make_grid(c), slope, c->cfg.beta, c->cfg.m_tilde * c->dx,
                          c->cfg.positivity, c->cfg.eps, c->flag);
     }
     HIP_TRY(hipGetLastError());
@@ -2738,7 +2891,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if (cfg->flux != DG_HLLC_BATTEN && cfg->flux != DG_HLLC_DAVIS) return DG_EINVAL;
   if (cfg->precision != DG_FP64 && cfg->precision != DG_FP32 && cfg->precision != DG_BF16_VOL)
     return DG_EUNSUPPORTED;
-  if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD) return DG_EUNSUPPORTED;
+  if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD && cfg->slope_limiter != DG_LIM_CHAR)
+    return DG_EUNSUPPORTED;
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
   bool amr = false;

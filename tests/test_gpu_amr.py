@@ -72,6 +72,17 @@ RHS_CASES = ([(c + "_kh", dict(s, ic="kh3d")) for c, s in CASES]
                 ("2d_k2_kh_davis", dict(CASES[0][1], ic="kh3d", flux=1))])
 
 
+def rough_amr_state(o, seed, amp=0.02):
+    """The projected initial state plus seeded random higher modes in both
+    blocks: a mix of limited and untouched cells on either side of the
+    refinement boundary."""
+    rng = np.random.default_rng(seed)
+    w = o.initial_state()
+    for b in o.blocks(w):  # views into w
+        b[:, 1:] += amp * rng.uniform(-1, 1, size=b[:, 1:].shape)
+    return w
+
+
 def _limited_state(o):
     w = o.initial_state()
     lim = oracle.AmrOracle(dict(o.wl, eps=1e-3))
@@ -110,13 +121,19 @@ def test_amr_rhs_stage_dt_match_oracle(case, spec):
     assert s.status() == 0
 
 
+@pytest.mark.parametrize("ic", ["blast", "kh3d_rough"])
 @pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
-def test_amr_limiter_matches_oracle(case, spec):
+def test_amr_limiter_matches_oracle(case, spec, ic):
     import paper_1506_06140_amd as dg
-    wl = _wl(**spec)
-    o = oracle.AmrOracle(wl)
+    if ic == "blast":
+        wl = _wl(**spec)
+        o = oracle.AmrOracle(wl)
+        w = o.initial_state()  # discontinuous blast projection (3D: many cells limited)
+    else:
+        wl = _wl(**spec, ic="kh3d")
+        o = oracle.AmrOracle(wl)
+        w = rough_amr_state(o, seed=17 + spec["dim"] * 4 + spec["k"])
     s = dg.Solver(wl)
-    w = o.initial_state()  # discontinuous blast projection: many cells limited
     ref, st = o.limit(w)
     assert st == 0
     d = _dev(w)

@@ -38,6 +38,12 @@ def test_rate_state_size_matches_header():
     assert k and (int(k.group(1)), int(k.group(2))) == (dg.RATE_SLOTS, dg.RATE_STRIDE)
 
 
+def test_limiter_codes_match_header():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    m = re.search(r"enum\s*\{\s*DG_LIM_NONE\s*=\s*(\d+),\s*DG_LIM_MINMOD\s*=\s*(\d+),\s*DG_LIM_CHAR\s*=\s*(\d+)", src)
+    assert m and tuple(int(x) for x in m.groups()) == (dg.DG_LIM_NONE, dg.DG_LIM_MINMOD, dg.DG_LIM_CHAR)
+
+
 def test_strerror_covers_codes():
     for code in range(0, -7, -1):
         assert dg.strerror(code) != "unknown error"
@@ -51,6 +57,7 @@ def test_strerror_covers_codes():
     ("gamma", 1.0, dg.DG_EINVAL),
     ("cfl", 0.0, dg.DG_EINVAL),
     ("flux", 7, dg.DG_EINVAL),
+    ("slope_limiter", 3, dg.DG_EUNSUPPORTED),
 ])
 def test_init_rejects_bad_configs_on_the_host(field, value, code):
     import ctypes as C
