@@ -105,6 +105,14 @@ def _load():
         _lib.orc_legendre.restype = None
         _lib.orc_rk3_combine.argtypes = [C.c_int, C.c_double, dp, dp, dp, dp, C.c_long]
         _lib.orc_rk3_combine.restype = None
+        for name, args in {
+            "orc_tableau_form": [C.c_int, dp, dp, dp, dp],
+            "orc_tableau_combine": [C.c_int, dp, dp, C.c_int, C.c_double, dp, dp, dp, C.c_long],
+            "orc_tableau_stage": [cp, C.c_int, dp, dp, C.c_int, C.c_double, dp, dp],
+            "orc_amr_tableau_stage": [cp, C.c_int, dp, dp, C.c_int, C.c_double, dp, dp],
+        }.items():
+            getattr(_lib, name).argtypes = args
+            getattr(_lib, name).restype = C.c_int
         _lib_cs.orc_cs_rhs.argtypes = [cp, dp, dp, C.c_double, dp, dp]
         _lib_cs.orc_cs_rhs.restype = C.c_int
         _lib_cs.orc_cs_traj.argtypes = [cp, dp, dp, C.c_double, C.c_int, C.c_double, dp, dp]
@@ -120,6 +128,49 @@ def _check(st: int, what: str) -> None:
 # ---------------------------------------------------------------------------
 # 1D rules and Legendre polynomials
 # ---------------------------------------------------------------------------
+
+# Butcher tableaus (A, b) of App. D as printed: table RK_2 (Heun), table RK_3,
+# table RK_4 (five stages, 14 printed digits; its weights sum to 1 - 8.8e-11).
+TABLEAUS = {
+    "rk2": ([[0.0, 0.0], [1.0, 0.0]], [0.5, 0.5]),
+    "rk3": ([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.25, 0.25, 0.0]], [1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0]),
+    "rk4": ([[0.0, 0.0, 0.0, 0.0, 0.0],
+             [0.39175222700392, 0.0, 0.0, 0.0, 0.0],
+             [0.21766909633821, 0.36841059262959, 0.0, 0.0, 0.0],
+             [0.08269208670950, 0.13995850206999, 0.25189177424738, 0.0, 0.0],
+             [0.06796628370320, 0.11503469844438, 0.20703489864929, 0.54497475021237, 0.0]],
+            [0.14681187618661, 0.24848290924556, 0.10425883036650, 0.27443890091960, 0.22600748319395]),
+}
+
+
+def _tab(A, b):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    s = b.size
+    if A.shape != (s, s):
+        raise ValueError("A must be s x s")
+    return s, A, b
+
+
+def tableau_form(A, b):
+    """(alpha, beta) of the tableau's Shu-Osher form (see shu_osher in the C source)."""
+    lib, _ = _load()
+    s, A, b = _tab(A, b)
+    alpha = np.zeros((s + 1, s + 1)); beta = np.zeros(s + 1)
+    _check(lib.orc_tableau_form(s, A, b, alpha, beta), "tableau_form")
+    return alpha, beta
+
+
+def tableau_combine(A, b, m: int, dt: float, Y, L):
+    """Stage value Y_m from Y_0..Y_{m-1} (a list of equal-size arrays) and L(Y_{m-1})."""
+    lib, _ = _load()
+    s, A, b = _tab(A, b)
+    Ys = np.ascontiguousarray(np.stack([np.asarray(y, dtype=np.float64).ravel() for y in Y]))
+    L = np.ascontiguousarray(np.asarray(L, dtype=np.float64).ravel())
+    out = np.zeros(L.size)
+    _check(lib.orc_tableau_combine(s, A, b, m, dt, Ys, L, out, L.size), "tableau_combine")
+    return out
+
 
 def gauss(n: int):
     lib, _ = _load()
@@ -304,6 +355,30 @@ class Oracle:
         _check(lib.orc_eigvecs(C.byref(self.c), np.ascontiguousarray(U, dtype=np.float64), axis, R, L), "eigvecs")
         return R, L
 
+    _tableau_stage_fn = "orc_tableau_stage"
+
+    def tableau_stage(self, A, b, m: int, dt: float, Y) -> np.ndarray:
+        """Stage value Y_m of the tableau (A, b) from Y_0..Y_{m-1}, unlimited."""
+        lib, _ = _load()
+        s, A, b = _tab(A, b)
+        Ys = np.ascontiguousarray(np.stack([np.asarray(self._s(y)).ravel() for y in Y]))
+        out = np.zeros(self.shape)
+        _check(getattr(lib, self._tableau_stage_fn)(C.byref(self.c), s, A, b, m, dt, Ys, out), "tableau_stage")
+        return out
+
+    def step_tableau(self, w, A, b, dt: float | None = None):
+        """One step of the tableau (A, b), the limiters after every stage."""
+        if dt is None:
+            dt = self.max_dt(w)
+        Y = [w]
+        for m in range(1, len(b) + 1):
+            out = self.tableau_stage(A, b, m, dt, Y)
+            if self.c.limiter or self.c.positivity:
+                out, st = self.limit(out)
+                _check(st, "limit")
+            Y.append(out)
+        return Y[-1], dt
+
     def stage(self, stage: int, dt: float, wn: np.ndarray, wp: np.ndarray) -> np.ndarray:
         """RK stage followed by the limiters, if the run has any (main loop)."""
         out = self.rk3_stage(stage, dt, wn, wp)
@@ -313,6 +388,10 @@ class Oracle:
         return out
 
     def step(self, w: np.ndarray, dt: float | None = None) -> tuple[np.ndarray, float]:
+        """One step of the workload's integrator ("rk" key; SSP-RK3 by default)."""
+        rk = self.wl.get("rk", "rk3")
+        if rk != "rk3":
+            return self.step_tableau(w, *TABLEAUS[rk], dt=dt)
         if dt is None:
             dt = self.max_dt(w)
         w1 = self.stage(1, dt, w, w)
@@ -380,6 +459,8 @@ class Oracle:
 
 
 class AmrOracle(Oracle):
+    _tableau_stage_fn = "orc_amr_tableau_stage"
+
     """The oracle on a base grid with a static 2:1 refined box (Sec. 4).
 
     State: coarse block [nvar][N][ncoarse] (base grid, hole cells ignored)

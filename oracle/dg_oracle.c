@@ -33,6 +33,8 @@
  *   refinement matrices ............. Sec. 4.2 eq. ref_pa_integral, App. F
  *   Legendre, Gauss, GLL ............ App. A, B, C
  *   SSP-RK3 ......................... App. D, table RK_3
+ *   general explicit RK (tableau) ... App. D, table butcher, eqs. for w^{n+1}
+ *                                     and rhs; tables RK_2, RK_4
  * The HLLC Riemann solver is cited by the paper to Toro's textbook only; the
  * textbook HLLC with Einfeldt-Batten (Roe-averaged) wave-speed bounds is
  * used, with a Davis-bound option.
@@ -696,6 +698,95 @@ int orc_rk3_stage(const orc_config *c, int stage, double dt, const double *wn, c
   double *L = malloc(sizeof(double) * n);
   rhs_all(X, wp, L);
   rk3_combine(stage, dt, wn, wp, L, out, n);
+  free(L); free(X);
+  return ORC_OK;
+}
+
+/* General explicit Runge-Kutta method given by its Butcher tableau (App. D:
+ * w^{n+1} = w^n + dt sum_i b_i k_i, k_i = L(w^n + dt sum_{j<i} a_ij k_j) with
+ * L = -R).  The main loop limits after every stage (Sec. 4.5); as for RK_3,
+ * the values limited are the stage values of the tableau's Shu-Osher form
+ * with a derivative term on the previous stage only:
+ *   Y_0 = w^n,  Y_m = sum_{j<m} alpha_mj Y_j + beta_m dt L(Y_{m-1}),  m = 1..s,
+ * and w^{n+1} = Y_s.  Writing every Y_j as w^n + dt sum_l Abar_jl k_l (Abar
+ * is A with b appended as row s) and comparing the coefficients of k_l:
+ *   beta_m = Abar_{m,m-1},
+ *   Abar_{m,l} = sum_{j=l+1}^{m-1} alpha_mj Abar_{j,l}     (l = m-2 .. 0),
+ * a triangular system for alpha_{m,1..m-1} with diagonal Abar_{l+1,l};
+ * alpha_m0 = 1 - sum of the others (the coefficients of w^n agree).  The
+ * form is unique when the subdiagonal of Abar is nonzero.  Without limiting
+ * it is the tableau's method exactly; for table RK_3 it gives 3/4, 1/4 and
+ * 1/3, 2/3, the form rk3_combine uses.  A is s x s row-major (only the strict
+ * lower triangle may be nonzero), alpha is (s+1) x (s+1) row-major. */
+#define MAXST 8
+static int shu_osher(int s, const double *A, const double *b, double *alpha, double *beta) {
+  if (s < 1 || s >= MAXST) return ORC_EINVAL;
+  double Ab[MAXST][MAXST];
+  for (int i = 0; i <= s; ++i)
+    for (int j = 0; j < s; ++j) {
+      Ab[i][j] = (i < s) ? A[i * s + j] : b[j];
+      if (i < s && j >= i && Ab[i][j] != 0.0) return ORC_EINVAL; /* not explicit */
+    }
+  for (int l = 0; l < s; ++l)
+    if (Ab[l + 1][l] == 0.0) return ORC_EINVAL;
+  for (int i = 0; i < (s + 1) * (s + 1); ++i) alpha[i] = 0.0;
+  beta[0] = 0.0;
+  for (int m = 1; m <= s; ++m) {
+    double *am = alpha + m * (s + 1);
+    beta[m] = Ab[m][m - 1];
+    for (int l = m - 2; l >= 0; --l) {
+      double r = Ab[m][l];
+      for (int j = l + 2; j <= m - 1; ++j) r -= am[j] * Ab[j][l];
+      am[l + 1] = r / Ab[l + 1][l];
+    }
+    double rest = 0.0;
+    for (int j = 1; j <= m - 1; ++j) rest += am[j];
+    am[0] = 1.0 - rest;
+  }
+  return ORC_OK;
+}
+
+/* Y_m from Y_0..Y_{m-1} (contiguous, n values each) and L = L(Y_{m-1}). */
+static void tableau_combine(int s, const double *alpha, const double *beta, int m, double dt, const double *Y,
+                            const double *L, double *out, long n) {
+  const double *am = alpha + m * (s + 1);
+  for (long i = 0; i < n; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += am[j] * Y[(long)j * n + i];
+    out[i] = acc + beta[m] * dt * L[i];
+  }
+}
+
+int orc_tableau_form(int s, const double *A, const double *b, double *alpha, double *beta) {
+  return shu_osher(s, A, b, alpha, beta);
+}
+
+/* Stage value Y_m (1 <= m <= s) of the combination alone (time-integrator
+ * pins with a scalar ODE). */
+int orc_tableau_combine(int s, const double *A, const double *b, int m, double dt, const double *Y,
+                        const double *L, double *out, long n) {
+  double alpha[MAXST * MAXST], beta[MAXST];
+  int st = shu_osher(s, A, b, alpha, beta);
+  if (st != ORC_OK) return st;
+  if (m < 1 || m > s) return ORC_EINVAL;
+  tableau_combine(s, alpha, beta, m, dt, Y, L, out, n);
+  return ORC_OK;
+}
+
+/* Stage value Y_m of the DG system: Y holds Y_0..Y_{m-1}, L is taken at Y_{m-1}. */
+int orc_tableau_stage(const orc_config *c, int s, const double *A, const double *b, int m, double dt,
+                      const double *Y, double *out) {
+  double alpha[MAXST * MAXST], beta[MAXST];
+  int st = shu_osher(s, A, b, alpha, beta);
+  if (st != ORC_OK) return st;
+  if (m < 1 || m > s) return ORC_EINVAL;
+  ctx *X = malloc(sizeof(ctx));
+  st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  long n = state_size(X);
+  double *L = malloc(sizeof(double) * n);
+  rhs_all(X, Y + (long)(m - 1) * n, L);
+  tableau_combine(s, alpha, beta, m, dt, Y, L, out, n);
   free(L); free(X);
   return ORC_OK;
 }
@@ -1372,6 +1463,25 @@ int orc_amr_rk3_stage(const orc_config *c, int stage, double dt, const double *w
   double *L = malloc(sizeof(double) * n);
   amr_rhs_all(M, wp, L);
   rk3_combine(stage, dt, wn, wp, L, out, n);
+  free(L); free(M);
+  return ORC_OK;
+}
+
+/* Stage value Y_m of a general tableau on the refined mesh (see
+ * orc_tableau_stage). */
+int orc_amr_tableau_stage(const orc_config *c, int s, const double *A, const double *b, int m, double dt,
+                          const double *Y, double *out) {
+  double alpha[MAXST * MAXST], beta[MAXST];
+  int st = shu_osher(s, A, b, alpha, beta);
+  if (st != ORC_OK) return st;
+  if (m < 1 || m > s) return ORC_EINVAL;
+  amr *M = malloc(sizeof(amr));
+  st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  long n = amr_state_size(M);
+  double *L = malloc(sizeof(double) * n);
+  amr_rhs_all(M, Y + (long)(m - 1) * n, L);
+  tableau_combine(s, alpha, beta, m, dt, Y, L, out, n);
   free(L); free(M);
   return ORC_OK;
 }

@@ -110,6 +110,7 @@ def workload(name: str, **overrides) -> dict:
     w.setdefault("refine_lo", (0, 0, 0))
     w.setdefault("refine_hi", (0, 0, 0))
     w.setdefault("flux", 0)
+    w.setdefault("rk", "rk3")  # time integrator: "rk2", "rk3" or "rk4" (App. D tables)
     w["name"] = name
     return w
 
