@@ -44,7 +44,7 @@ _FINGERPRINT_REGIONS = [
     ("// Reciprocal and reciprocal square root from the hardware estimates plus",
      "// HLLC numerical flux in +a between traces UL (low side) and UR (high side),"),
     ("// HLLC numerical flux in +a between traces UL (low side) and UR (high side),",
-     "// ---------------------------------------------------------------------------\n// Right-hand side and fused SSP-RK3 stage."),
+     "// ---------------------------------------------------------------------------\n// Right-hand side and fused stage."),
     ("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
      "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages."),
 ]

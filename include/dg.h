@@ -171,6 +171,45 @@ int dg_max_rate(dg_ctx *ctx, const double *w, double *rate_dev, void *stream);
 int dg_rk_step(dg_ctx *ctx, const double *w, double *u1, double *u2, double *w_out,
                double *dt_dev, double *rate_dev, void *stream);
 
+/* Most stages of a time integrator given to dg_set_tableau. */
+#define DG_MAX_STAGES 5
+
+/* Time integrator of dg_tableau_stage and dg_tableau_step: the explicit
+ * Runge-Kutta method of the Butcher tableau (App. D, table butcher: w^{n+1} =
+ * w^n + dt sum_i b_i k_i, k_i = L(w^n + dt sum_{j<i} a_ij k_j)), e.g. table
+ * RK_2 (Heun), RK_3 or the five-stage RK_4.  a is stages x stages, row-major,
+ * host memory, strictly lower triangular (entries on or above the diagonal
+ * must be zero); b has `stages` entries.  The method is run in its Shu-Osher
+ * form with a derivative term on the previous stage only,
+ *   Y_0 = w^n,  Y_m = sum_{j<m} alpha_mj Y_j + beta_m dt L(Y_{m-1}),  w^{n+1} = Y_s,
+ * whose stage values Y_m are what the limiters act on (the main loop of
+ * Sec. 4.5 limits after every stage); the form exists and is unique when
+ * a_{i+1,i} != 0 for every i and b_s != 0.  Returns DG_EINVAL for a NULL
+ * pointer, stages outside 1..DG_MAX_STAGES, a non-finite entry, an entry on
+ * or above the diagonal, or a zero a_{i+1,i} or b_s; the previous integrator
+ * is then kept.  Host-only: enqueues nothing.  dg_init sets table RK_3;
+ * dg_rk_stage and dg_rk_step are SSP-RK3 whatever is set here. */
+int dg_set_tableau(dg_ctx *ctx, int stages, const double *a, const double *b);
+
+/* Stage value Y_m (1 <= m <= stages) of the integrator set by
+ * dg_set_tableau: y is a host array of m device pointers to the states Y_0
+ * (= w^n) .. Y_{m-1}; out receives Y_m; dt_dev is the step on the device.
+ * Unlimited.  out must differ from every y[j]; otherwise, or for a NULL
+ * pointer or m out of range, DG_EINVAL. */
+int dg_tableau_stage(dg_ctx *ctx, int m, const double *dt_dev, const double *const *y, double *out,
+                     void *stream);
+
+/* One full step of the integrator set by dg_set_tableau with the configured
+ * limiters after every stage, like dg_rk_step: dt from the rate carried in
+ * rate_dev (written to dt_dev), the stage values into stage[0..s-2] (a host
+ * array of s-1 device states; may be NULL when s = 1), w^{n+1} into w_out,
+ * and rate_dev updated for the next step.  w, the stage states and w_out
+ * must all be distinct, dt_dev outside rate_dev; otherwise DG_EINVAL.  On a
+ * 2D grid without refinement (and s >= 2) the time-step work rides in the
+ * first and last stage kernels. */
+int dg_tableau_step(dg_ctx *ctx, const double *w, double *const *stage, double *w_out, double *dt_dev,
+                    double *rate_dev, void *stream);
+
 /* Slope limiter (minmod with TVB bound, Sec. 3.3: component-wise on the
  * conserved variables, Sec. 3.1, or on the characteristic variables of the
  * cell mean, Sec. 3.2 eq. char_limiter) then positivity limiter (Sec. 3.4),

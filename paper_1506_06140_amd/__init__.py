@@ -23,6 +23,22 @@ DG_LIM_NONE, DG_LIM_MINMOD, DG_LIM_CHAR = 0, 1, 2
 # doubles in the carried rate state (8 slots, 16 apart; the rate is the largest slot)
 DG_RATE_STATE, RATE_SLOTS, RATE_STRIDE = 128, 8, 16
 PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}
+DG_MAX_STAGES = 5
+# Butcher tableaus (a, b) of App. D for dg_set_tableau: table RK_2 (Heun),
+# table RK_3 and the five-stage table RK_4 as printed (14 digits).
+TABLEAUS = {
+    "rk2": ((0.0, 0.0,
+             1.0, 0.0), (0.5, 0.5)),
+    "rk3": ((0.0, 0.0, 0.0,
+             1.0, 0.0, 0.0,
+             0.25, 0.25, 0.0), (1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0)),
+    "rk4": ((0.0, 0.0, 0.0, 0.0, 0.0,
+             0.39175222700392, 0.0, 0.0, 0.0, 0.0,
+             0.21766909633821, 0.36841059262959, 0.0, 0.0, 0.0,
+             0.08269208670950, 0.13995850206999, 0.25189177424738, 0.0, 0.0,
+             0.06796628370320, 0.11503469844438, 0.20703489864929, 0.54497475021237, 0.0),
+            (0.14681187618661, 0.24848290924556, 0.10425883036650, 0.27443890091960, 0.22600748319395)),
+}
 
 
 class DGError(RuntimeError):
@@ -45,8 +61,8 @@ class dg_config(C.Structure):
 
 EXPORTS = (
     "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
-    "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage",
-    "dg_status", "dg_destroy", "dg_strerror",
+    "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
+    "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
 )
 
 _lib = None
@@ -73,6 +89,9 @@ def load_library(path: str = LIB_PATH):
     lib.dg_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, vp]
     lib.dg_max_rate.argtypes = [ctxp, dp, dp, vp]
     lib.dg_rk_step.argtypes = [ctxp, dp, dp, dp, dp, dp, dp, vp]
+    lib.dg_set_tableau.argtypes = [ctxp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    lib.dg_tableau_stage.argtypes = [ctxp, C.c_int, dp, C.POINTER(C.c_void_p), dp, vp]
+    lib.dg_tableau_step.argtypes = [ctxp, dp, C.POINTER(C.c_void_p), dp, dp, dp, vp]
     lib.dg_limit.argtypes = [ctxp, dp, vp]
     lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
     lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
@@ -163,6 +182,10 @@ class Solver:
             self.nhole = 1
             for a in range(wl["dim"]):
                 self.nhole *= wl["refine_hi"][a] - wl["refine_lo"][a]
+        self.rk = wl.get("rk", "rk3")
+        self.stages = 3
+        if self.rk != "rk3":
+            self.set_tableau(*TABLEAUS[self.rk])
 
     def _s(self, t) -> int:
         return _ptr(t, self.size)
@@ -251,11 +274,44 @@ class Solver:
                "dg_max_rate")
         return rate
 
+    def set_tableau(self, a, b):
+        """Time integrator of tableau_stage / tableau_step (and of rk_step and
+        step when it is not SSP-RK3): Butcher matrix a (s x s, row-major or
+        nested) and weights b."""
+        b = [float(x) for x in b]
+        a = [float(x) for x in np.asarray(a, dtype=np.float64).ravel()]
+        s = len(b)
+        if len(a) != s * s:
+            raise ValueError("a must have stages x stages entries")
+        _check(self.lib.dg_set_tableau(self.ctx, s, (C.c_double * (s * s))(*a), (C.c_double * s)(*b)),
+               "dg_set_tableau")
+        self.stages = s
+        self.rk = next((k for k, (ta, tb) in TABLEAUS.items() if list(ta) == a and list(tb) == b), "custom")
+
+    def tableau_stage(self, m, dt, ys, out=None, stream=None):
+        """Stage value Y_m of the configured tableau from ys = [Y_0, .., Y_{m-1}] (unlimited)."""
+        if len(ys) != m:
+            raise ValueError("tableau_stage needs the m stage values Y_0..Y_{m-1}")
+        out = self.empty() if out is None else out
+        ptrs = (C.c_void_p * m)(*[self._s(y) for y in ys])
+        _check(self.lib.dg_tableau_stage(self.ctx, m, _ptr(dt, 1), ptrs, self._s(out), _stream(stream)),
+               "dg_tableau_stage")
+        return out
+
     def rk_step(self, w, bufs, dt, rate, stream=None):
-        """One SSP-RK3 step with limiters from w into bufs[2] (bufs[0], bufs[1]
-        are the stage buffers) in one library call.  rate (a rate_state())
-        holds the rate state of w on entry (max_rate, or the previous rk_step)
-        and of the result on return; dt receives the step.  Returns bufs[2]."""
+        """One time step with limiters from w into bufs[s-1] (bufs[0..s-2] are
+        the stage buffers; s = 3 for SSP-RK3) in one library call: dg_rk_step
+        for SSP-RK3, dg_tableau_step otherwise.  rate (a rate_state()) holds
+        the rate state of w on entry (max_rate, or the previous rk_step) and of
+        the result on return; dt receives the step.  Returns bufs[s-1]."""
+        if self.rk != "rk3":
+            s = self.stages
+            if len(bufs) < s:
+                raise ValueError(f"rk_step needs {s} buffers")
+            ptrs = (C.c_void_p * max(s - 1, 1))(*[self._s(b) for b in bufs[:s - 1]])
+            _check(self.lib.dg_tableau_step(self.ctx, self._s(w), ptrs, self._s(bufs[s - 1]), _ptr(dt, 1),
+                                            _ptr(rate, DG_RATE_STATE), _stream(stream)), "dg_tableau_step")
+            return bufs[s - 1]
         u1, u2, out = bufs[0], bufs[1], bufs[2]
         _check(self.lib.dg_rk_step(self.ctx, self._s(w), self._s(u1), self._s(u2), self._s(out), _ptr(dt, 1),
                                    _ptr(rate, DG_RATE_STATE), _stream(stream)), "dg_rk_step")
@@ -286,10 +342,22 @@ class Solver:
         return bool(self.cfg.slope_limiter or self.cfg.positivity)
 
     def step(self, w, bufs, dt=None, stream=None):
-        """One SSP-RK3 step from w into bufs[2] using bufs[0], bufs[1] as stage
-        buffers (the main loop of Sec. 4.5 without refinement).  If dt (a
-        one-element device tensor) is None the CFL step is computed first into
-        bufs[3].  Returns the new state tensor (bufs[2])."""
+        """One step from w into bufs[s-1] using bufs[0..s-2] as stage buffers
+        (the main loop of Sec. 4.5 without refinement; s = 3 for SSP-RK3),
+        one call per stage and limiter.  If dt (a one-element device tensor)
+        is None the CFL step is computed first into bufs[s].  Returns the new
+        state tensor (bufs[s-1])."""
+        if self.rk != "rk3":
+            s = self.stages
+            if dt is None:
+                dt = self.max_dt(w, bufs[s], stream)
+            ys = [w]
+            for m in range(1, s + 1):
+                out = self.tableau_stage(m, dt, ys, bufs[m - 1], stream)
+                if self.limited:
+                    self.limit(out, stream)
+                ys.append(out)
+            return ys[-1]
         u1, u2, u3 = bufs[0], bufs[1], bufs[2]
         if dt is None:
             dt = self.max_dt(w, bufs[3], stream)

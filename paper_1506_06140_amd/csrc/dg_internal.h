@@ -73,4 +73,10 @@ struct dg_ctx {
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
   long nf[3] = {1, 1, 1};
   long ncc = 0, ncf = 0;
+  // time integrator of dg_tableau_stage / dg_tableau_step: stage m = 1..rk_s
+  // of the tableau's Shu-Osher form, Y_m = sum_{j<m} rk_alpha[m][j] Y_j +
+  // rk_beta[m] dt L(Y_{m-1}); SSP-RK3 (table RK_3) until dg_set_tableau
+  int rk_s = 0;
+  double rk_alpha[DG_MAX_STAGES + 1][DG_MAX_STAGES + 1] = {};
+  double rk_beta[DG_MAX_STAGES + 1] = {};
 };

@@ -495,16 +495,40 @@ __device__ inline void hllc_vjp(const double *UL, const double *UR, int a, doubl
 }
 
 // ---------------------------------------------------------------------------
-// Right-hand side and fused SSP-RK3 stage.
-// mode 0: out = L;  mode 1: stage 1 (out = w + dt L);  mode 2: stages 2, 3
-// (out = ca wn + cb (w + dt L)).
+// One stage of the time integrator in Shu-Osher form (App. D): with u the
+// stage input, out = cu u + cl dt L(u) + sum_k a_k y_k over earlier stage
+// values y_k (the stage values of an explicit Runge-Kutta tableau; SSP-RK3 is
+// cu = cl = 1, then 1/4, 1/4 with 3/4 w^n, then 2/3, 2/3 with 1/3 w^n).
+// ---------------------------------------------------------------------------
+constexpr int MIX_MAX = 4;
+struct Mix {
+  const double *y[MIX_MAX];
+  double a[MIX_MAX];
+  double cu, cl;
+  int n;
+};
+
+// the terms k >= k0 of the sum, added to o
+__device__ inline double mix_tail(const Mix &m, double o, long i, int k0) {
+#pragma unroll
+  for (int k = 0; k < MIX_MAX; ++k)
+    if (k >= k0 && k < m.n) o = fma(m.a[k], m.y[k][i], o);
+  return o;
+}
+
+__device__ inline double mix_out(const Mix &m, double u, double L, double cldt, long i) {
+  return mix_tail(m, fma(cldt, L, m.cu * u), i, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand side and fused stage.
+// mode 0: out = L;  mode 1: out = the stage combination mx (above).
 // ---------------------------------------------------------------------------
 template <int D, int K, class R, int FX>
 __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const R *__restrict__ tabr,
-                                                   const double *__restrict__ w, const double *__restrict__ wn,
-                                                   double *__restrict__ out, const double *__restrict__ dtp,
-                                                   const float *__restrict__ vext, Grid g, int mode, double ca,
-                                                   double cb, int *__restrict__ flag) {
+                                                   const double *__restrict__ w, double *__restrict__ out,
+                                                   const double *__restrict__ dtp, const float *__restrict__ vext,
+                                                   Grid g, int mode, Mix mx, int *__restrict__ flag) {
   // R is the type of the contractions and fluxes (double, or float for the
   // mixed-precision path); the lift of the cell mean and the stage update are
   // always FP64.
@@ -610,7 +634,7 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
   }
 
   bool bad = false;
-  const double dt = (mode == 0) ? 0.0 : *dtp;
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
 #pragma unroll
   for (int v = 0; v < C::NV; ++v)
 #pragma unroll
@@ -618,12 +642,7 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
       const long i = (long)(v * C::N + l) * nc + cell;
       const double L = g.fac * (l == 0 ? acc0[v] : (double)acc[v][l]);
       bad |= (L != L);
-      if (mode == 0) {
-        out[i] = L;
-      } else {
-        const double o = w[i] + dt * L;
-        out[i] = (mode == 1) ? o : ca * wn[i] + cb * o;
-      }
+      out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, cldt, i);
     }
   if (bad) atomicOr(flag, FLAG_NAN);
 }
@@ -687,8 +706,8 @@ __device__ inline double quad_from(double x) {
 template <int K, class R, int FX>
 __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
     const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
-    const double *__restrict__ wn, double *__restrict__ out, const double *__restrict__ dtp,
-    const float *__restrict__ vext, Grid g, int mode, double ca, double cb, int *__restrict__ flag, RateOp ro) {
+    double *__restrict__ out, const double *__restrict__ dtp, const float *__restrict__ vext, Grid g, int mode,
+    Mix mx, int *__restrict__ flag, RateOp ro) {
   // R: type of the contractions and fluxes (double, or float in the mixed
   // path); the lift of the cell mean and the stage update are FP64.
   // ro (fused step): RATE_DT takes dt = CFL f_k / max rate from the slots of
@@ -908,7 +927,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   for (int l = 0; l < N; ++l) {
     const long i = (long)(sub * N + l) * nc + cell;
     wo[l] = (mode != 0) ? w[i] : 0.0;
-    wno[l] = (mode == 2) ? wn[i] : 0.0;
+    wno[l] = (mode != 0 && mx.n > 0) ? mx.y[0][i] : 0.0;
   }
   __syncthreads();
 
@@ -940,7 +959,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       }
     }
     bool bad = false;
-    const double dt = sdt;
+    const double cldt = mx.cl * sdt;
 #pragma unroll
     for (int l = 0; l < N; ++l) {
       const long i = (long)(v * N + l) * nc + cell;
@@ -948,8 +967,9 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
       bad |= (L != L);
       double o = L;
       if (mode != 0) {
-        o = wo[l] + dt * L;
-        if (mode != 1) o = ca * wno[l] + cb * o;
+        o = fma(cldt, L, mx.cu * wo[l]);
+        if (mx.n > 0) o = fma(mx.a[0], wno[l], o);
+        o = mix_tail(mx, o, i, 1);
       }
       out[i] = o;
       if (l == 0) mean = o;
@@ -1704,10 +1724,9 @@ __device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int 
 
 template <int D, int K, class R, int FX>
 __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab, const R *__restrict__ tabr,
-                                                 const double *__restrict__ w, const double *__restrict__ wn,
-                                                 double *__restrict__ out, const double *__restrict__ dtp,
-                                                 const float *__restrict__ vext, AmrGrid g, int mode, double ca,
-                                                 double cb, int *__restrict__ flag) {
+                                                 const double *__restrict__ w, double *__restrict__ out,
+                                                 const double *__restrict__ dtp, const float *__restrict__ vext,
+                                                 AmrGrid g, int mode, Mix mx, int *__restrict__ flag) {
   using C = Cfg<D, K>;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, NW = NV * N, NSUB = 1 << (D - 1);
   const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1720,13 +1739,13 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
   const long boff = fine ? (long)NW * g.ncc : 0;
   const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
   int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
-  const double dt = (mode == 0) ? 0.0 : *dtp;
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
   if (!fine && amr_in_hole<D>(g, i)) {
     // hole cells carry no solution: L = 0
 #pragma unroll 1
     for (int vl = 0; vl < NW; ++vl) {
       const long ii = boff + (long)vl * ncb + cell;
-      out[ii] = (mode == 0) ? 0.0 : (mode == 1) ? w[ii] : ca * wn[ii] + cb * w[ii];
+      out[ii] = (mode == 0) ? 0.0 : mix_out(mx, w[ii], 0.0, 0.0, ii);
     }
     return;
   }
@@ -1884,12 +1903,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab,
       const long ii = boff + (long)(v * N + l) * ncb + cell;
       const double L = fac * (l == 0 ? acc0[v] : (double)acc[v][l]);
       bad |= (L != L);
-      if (mode == 0) {
-        out[ii] = L;
-      } else {
-        const double o = w[ii] + dt * L;
-        out[ii] = (mode == 1) ? o : ca * wn[ii] + cb * o;
-      }
+      out[ii] = (mode == 0) ? L : mix_out(mx, w[ii], L, cldt, ii);
     }
   if (bad) atomicOr(flag, FLAG_NAN);
 }
@@ -1924,9 +1938,8 @@ __device__ inline void quad_transpose(double (&x)[4], int sub) {
 
 template <int K, int FX, bool UNI>
 __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__ tab, const double *__restrict__ w,
-                                                      const double *__restrict__ wn, double *__restrict__ out,
-                                                      const double *__restrict__ dtp, AmrGrid g, int mode, double ca,
-                                                      double cb, int *__restrict__ flag) {
+                                                      double *__restrict__ out, const double *__restrict__ dtp,
+                                                      AmrGrid g, int mode, Mix mx, int *__restrict__ flag) {
   // UNI: a uniform grid (no fine block, an empty hole), so every face is a
   // regular or a wall face and the face tables are the same for all lanes
   constexpr int D = 3;
@@ -1946,12 +1959,12 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
   const long boff = fine ? (long)NW * g.ncc : 0;
   const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
   int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
-  const double dt = (mode == 0) ? 0.0 : *dtp;
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
   if (!fine && amr_in_hole<D>(g, i)) {
 #pragma unroll 1
     for (int vl = sub; vl < NW; vl += 4) {
       const long ii = boff + (long)vl * ncb + cell;
-      out[ii] = (mode == 0) ? 0.0 : (mode == 1) ? w[ii] : ca * wn[ii] + cb * w[ii];
+      out[ii] = (mode == 0) ? 0.0 : mix_out(mx, w[ii], 0.0, 0.0, ii);
     }
     return;
   }
@@ -2173,12 +2186,7 @@ __global__ __launch_bounds__(256) void k_rhs_amr_quad(const double *__restrict__
   auto emit = [&](int vl, double L) {
     const long ii = boff + (long)vl * ncb + cell;
     bad |= (L != L);
-    if (mode == 0) {
-      out[ii] = L;
-    } else {
-      const double o = w[ii] + dt * L;
-      out[ii] = (mode == 1) ? o : ca * wn[ii] + cb * o;
-    }
+    out[ii] = (mode == 0) ? L : mix_out(mx, w[ii], L, cldt, ii);
   };
 #pragma unroll
   for (int l = 0; l < N; ++l) emit(sub * N + l, fac * acc[l]);
@@ -2663,10 +2671,10 @@ int check_layout(const dg_ctx *c) { return dispatch(c, LayoutCheck{c}); }
 
 struct StageLaunch {
   dg_ctx *c;
-  const double *w, *wn, *dt;
+  const double *w, *dt;
   double *out;
-  int mode;
-  double ca, cb;
+  int mode;  // 0: out = L(w); 1: out = the combination mx
+  dg::Mix mx;
   hipStream_t s;
   dg::RateOp ro = {nullptr, nullptr, 0.0, 0.0, dg::RATE_NONE};  // only the 2D tile kernel takes one
   template <int D, int K, class R>
@@ -2681,16 +2689,16 @@ struct StageLaunch {
       if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
         // four lanes per cell (the one-thread kernel would spill)
         hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0,
-                           s, c->tab, w, wn, out, dt, make_amr_grid(c), mode, ca, cb, c->flag);
+                           s, c->tab, w, out, dt, make_amr_grid(c), mode, mx, c->flag);
       } else {
         hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab,
-                           tabr, w, wn, out, dt, vext, make_amr_grid(c), mode, ca, cb, c->flag);
+                           tabr, w, out, dt, vext, make_amr_grid(c), mode, mx, c->flag);
       }
     } else if constexpr (D == 2) {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
-      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, wn, out, dt,
-                         vext, make_grid(c), mode, ca, cb, c->flag, ro);
+      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, out, dt,
+                         vext, make_grid(c), mode, mx, c->flag, ro);
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
@@ -2699,10 +2707,10 @@ struct StageLaunch {
       // nine face nodes)
       if (vext) return DG_EINVAL;
       hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, true>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab,
-                         w, wn, out, dt, make_uniform_amr_grid(c), mode, ca, cb, c->flag);
+                         w, out, dt, make_uniform_amr_grid(c), mode, mx, c->flag);
     } else {
       hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
-                         wn, out, dt, vext, make_grid(c), mode, ca, cb, c->flag);
+                         out, dt, vext, make_grid(c), mode, mx, c->flag);
     }
     HIP_TRY(hipGetLastError());
     return DG_OK;
@@ -2861,6 +2869,73 @@ int rate_fold(dg_ctx *c, const double *w, unsigned long long *rm, hipStream_t s)
 
 bool limited(const dg_ctx *c) { return c->cfg.slope_limiter != DG_LIM_NONE || c->cfg.positivity; }
 
+// Shu-Osher form of an explicit tableau with the derivative on the previous
+// stage only (see dg_set_tableau).  Writing each stage value as w^n + dt
+// sum_l Abar_jl k_l (Abar: a with b appended as row s), stage m needs
+// beta_m = Abar_{m,m-1} and sum_{j>l} alpha_mj Abar_jl = Abar_ml for l < m-1;
+// the equation of l = j-1 is the first one in which alpha_mj appears, so
+// sweeping j downwards fixes alpha_mj from that equation and removes its
+// share from the residuals of the lower equations.
+int shu_osher_form(dg_ctx *c, int s, const double *a, const double *b) {
+  if (s < 1 || s > DG_MAX_STAGES) return DG_EINVAL;
+  double Ab[DG_MAX_STAGES + 1][DG_MAX_STAGES];
+  for (int i = 0; i <= s; ++i)
+    for (int j = 0; j < s; ++j) {
+      const double v = (i < s) ? a[i * s + j] : b[j];
+      if (!std::isfinite(v) || (i < s && j >= i && v != 0.0)) return DG_EINVAL;
+      Ab[i][j] = v;
+    }
+  for (int i = 0; i < s; ++i)
+    if (Ab[i + 1][i] == 0.0) return DG_EINVAL;
+  double al[DG_MAX_STAGES + 1][DG_MAX_STAGES + 1] = {}, be[DG_MAX_STAGES + 1] = {};
+  for (int m = 1; m <= s; ++m) {
+    be[m] = Ab[m][m - 1];
+    double res[DG_MAX_STAGES] = {};
+    for (int l = 0; l + 1 < m; ++l) res[l] = Ab[m][l];
+    double rest = 0.0;
+    for (int j = m - 1; j >= 1; --j) {
+      al[m][j] = res[j - 1] / Ab[j][j - 1];
+      rest += al[m][j];
+      for (int l = 0; l < j - 1; ++l) res[l] -= al[m][j] * Ab[j][l];
+    }
+    al[m][0] = 1.0 - rest;
+  }
+  c->rk_s = s;
+  std::memcpy(c->rk_alpha, al, sizeof(al));
+  std::memcpy(c->rk_beta, be, sizeof(be));
+  return DG_OK;
+}
+
+// The stage combination of SSP-RK3 (table RK_3): 1, 1; 1/4, 1/4 with 3/4 w^n;
+// 2/3, 2/3 with 1/3 w^n.
+dg::Mix rk3_mix(int stage, const double *wn) {
+  static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
+  static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
+  dg::Mix m{};
+  m.cu = m.cl = B[stage - 1];
+  if (stage > 1) {
+    m.y[0] = wn;
+    m.a[0] = A[stage - 1];
+    m.n = 1;
+  }
+  return m;
+}
+
+// Stage m of the configured tableau from the stage values y[0..m-1]: the
+// input is y[m-1]; earlier values with a nonzero weight are the extra terms.
+dg::Mix tableau_mix(const dg_ctx *c, int m, const double *const *y) {
+  dg::Mix mx{};
+  mx.cu = c->rk_alpha[m][m - 1];
+  mx.cl = c->rk_beta[m];
+  for (int j = 0; j + 1 < m; ++j)
+    if (c->rk_alpha[m][j] != 0.0) {
+      mx.y[mx.n] = y[j];
+      mx.a[mx.n] = c->rk_alpha[m][j];
+      ++mx.n;
+    }
+  return mx;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2944,6 +3019,11 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   double fk = 1.0 / (2.0 * cfg->k + 1.0);
   if (cfg->positivity && c->gll_w1 / 2.0 < fk) fk = c->gll_w1 / 2.0;
   c->cfl_fk = cfg->cfl * fk;
+  {
+    static const double a3[9] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.25, 0.25, 0.0};
+    static const double b3[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+    shu_osher_form(c, 3, a3, b3);
+  }
   c->npartial = (int)std::min<long>(1024, (c->ncell + kBlock - 1) / kBlock);
 
   auto fail = [&](hipError_t e) {
@@ -3037,7 +3117,7 @@ int dg_project(dg_ctx *c, const double *prim, double *w, void *stream) {
 
 int dg_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
   if (!c || !w || !L || w == L) return DG_EINVAL;
-  return dispatch(c, StageLaunch{c, w, nullptr, nullptr, L, 0, 0.0, 0.0, (hipStream_t)stream});
+  return dispatch(c, StageLaunch{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
 }
 
 int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const double *wp, double *out,
@@ -3045,10 +3125,19 @@ int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const 
   if (!c || !dt || !wp || !out || stage < 1 || stage > 3) return DG_EINVAL;
   if (stage > 1 && !wn) return DG_EINVAL;
   if (out == wp || out == wn) return DG_EINVAL;
-  static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
-  static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
-  return dispatch(c, StageLaunch{c, wp, wn, dt, out, stage == 1 ? 1 : 2, A[stage - 1], B[stage - 1],
-                                 (hipStream_t)stream});
+  return dispatch(c, StageLaunch{c, wp, dt, out, 1, rk3_mix(stage, wn), (hipStream_t)stream});
+}
+
+int dg_set_tableau(dg_ctx *c, int stages, const double *a, const double *b) {
+  if (!c || !a || !b || stages < 1 || stages > DG_MAX_STAGES) return DG_EINVAL;
+  return shu_osher_form(c, stages, a, b);  // leaves c alone on error
+}
+
+int dg_tableau_stage(dg_ctx *c, int m, const double *dt, const double *const *y, double *out, void *stream) {
+  if (!c || !dt || !y || !out || m < 1 || m > c->rk_s) return DG_EINVAL;
+  for (int j = 0; j < m; ++j)
+    if (!y[j] || y[j] == out) return DG_EINVAL;
+  return dispatch(c, StageLaunch{c, y[m - 1], dt, out, 1, tableau_mix(c, m, y), (hipStream_t)stream});
 }
 
 
@@ -3091,13 +3180,56 @@ int dg_rk_step(dg_ctx *c, const double *w, double *u1, double *u2, double *out, 
   auto op = [&](int k) { return dg::RateOp{rm, dt, c->cfl_fk, c->dx, fused ? k : dg::RATE_NONE}; };
   const double *wp[3] = {w, u1, u2};
   double *wo[3] = {u1, u2, out};
-  static const double A[3] = {0.0, 0.75, 1.0 / 3.0};
-  static const double B[3] = {1.0, 0.25, 2.0 / 3.0};
   static const int R[3] = {dg::RATE_DT, dg::RATE_CLEAR, dg::RATE_FOLD};
   for (int k = 0; k < 3; ++k) {
-    int st = dispatch(c, StageLaunch{c, wp[k], w, dt, wo[k], k == 0 ? 1 : 2, A[k], B[k], s, op(R[k])});
+    int st = dispatch(c, StageLaunch{c, wp[k], dt, wo[k], 1, rk3_mix(k + 1, w), s, op(R[k])});
     if (st != DG_OK) return st;
     if (limited(c) && (st = dispatch(c, LimitLaunch{c, wo[k], s})) != DG_OK) return st;
+  }
+  return fused ? DG_OK : rate_fold(c, out, rm, s);
+}
+
+int dg_tableau_step(dg_ctx *c, const double *w, double *const *stage, double *out, double *dt, double *rate,
+                    void *stream) {
+  if (!c || !w || !out || !dt || !rate) return DG_EINVAL;
+  const int ns = c->rk_s;
+  if (ns > 1 && !stage) return DG_EINVAL;
+  const double *Y[DG_MAX_STAGES + 1];
+  Y[0] = w;
+  for (int m = 1; m < ns; ++m) Y[m] = stage[m - 1];
+  Y[ns] = out;
+  for (int i = 0; i <= ns; ++i) {
+    if (!Y[i]) return DG_EINVAL;
+    for (int j = i + 1; j <= ns; ++j)
+      if (Y[i] == Y[j]) return DG_EINVAL;
+  }
+  if (dt >= rate && dt < rate + DG_RATE_STATE) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
+  // the stage kernels carry the time-step work on 2D grids: the first takes
+  // dt from the slots, the second clears them (or a clear kernel runs before
+  // the last stage of a two-stage method), the last folds the new rate in
+  const bool fused = !c->amr && c->sh.d == 2 && ns >= 2;
+  if (!fused) {
+    hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(64), 0, s, rm, c->cfl_fk, dt);
+    HIP_TRY(hipGetLastError());
+  }
+  for (int m = 1; m <= ns; ++m) {
+    int op = dg::RATE_NONE;
+    if (fused) {
+      if (m == 1) op = dg::RATE_DT;
+      else if (m == ns) op = dg::RATE_FOLD;
+      else if (m == 2) op = dg::RATE_CLEAR;
+      if (m == ns && ns == 2) {
+        hipLaunchKernelGGL(dg::k_rate_zero, dim3(1), dim3(64), 0, s, rm);
+        HIP_TRY(hipGetLastError());
+      }
+    }
+    double *o = const_cast<double *>(Y[m]);
+    int st = dispatch(c, StageLaunch{c, Y[m - 1], dt, o, 1, tableau_mix(c, m, Y), s,
+                                     dg::RateOp{rm, dt, c->cfl_fk, c->dx, op}});
+    if (st != DG_OK) return st;
+    if (limited(c) && (st = dispatch(c, LimitLaunch{c, o, s})) != DG_OK) return st;
   }
   return fused ? DG_OK : rate_fold(c, out, rm, s);
 }

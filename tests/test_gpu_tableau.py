@@ -1,0 +1,237 @@
+"""GPU: general explicit Runge-Kutta integrators (App. D: tables RK_2, RK_4 and
+any explicit tableau) through dg_set_tableau, dg_tableau_stage and
+dg_tableau_step, against the FP64 oracle's own Shu-Osher form of the same
+tableau (states: relative L1 <= 1e-12 per variable, dt: 1e-14)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from test_gpu_amr import _per_var, _wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _random_tableau(s, seed):
+    rng = np.random.default_rng(seed)
+    A = np.tril(rng.uniform(0.1, 0.5, size=(s, s)), -1)
+    return A, rng.uniform(0.05, 0.4, size=s)
+
+
+def _tableau(name):
+    if name == "random4":
+        return _random_tableau(4, 11)
+    A, b = oracle.TABLEAUS[name]
+    return np.array(A), np.array(b)
+
+
+def _setup(spec):
+    import paper_1506_06140_amd as dg
+    spec = dict(spec)
+    if "amr" in spec:
+        wl = _wl(**spec["amr"])
+        o = oracle.AmrOracle(wl)
+        view = lambda x: _per_var(o, x)  # noqa: E731
+    else:
+        wl = workloads.workload(spec.pop("name"), **spec)
+        o = oracle.Oracle(wl)
+        view = lambda x: np.asarray(x).reshape(o.nvar, -1)  # noqa: E731
+    w0, st = o.limit(o.initial_state()) if (wl["limiter"] or wl["positivity"]) else (o.initial_state(), 0)
+    assert st == 0
+    return wl, o, view, dg.Solver(wl), w0
+
+
+def _err(view, got, ref):
+    g, r = view(got), view(ref)
+    norm = np.abs(r).sum(axis=1)
+    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
+
+
+STAGE_CASES = [
+    ("vortex2d_k2", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0))),
+    ("kh3d_k2", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), limiter=0, positivity=0)),
+    ("kh3d_k3", dict(name="kh3d", k=3, n=(9, 8, 7), length=(0.9, 0.8, 0.7), limiter=0, positivity=0)),
+    ("amr2d_k2", dict(amr=dict(dim=2, k=2, n=(10, 9, 1), lo=(2, 3, 0), hi=(7, 6, 0), ic="kh3d", limiter=0,
+                               positivity=0))),
+    ("amr3d_k1", dict(amr=dict(dim=3, k=1, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4), ic="kh3d", limiter=0,
+                               positivity=0))),
+]
+
+
+@pytest.mark.parametrize("tab", ["rk2", "rk4", "random4"])
+@pytest.mark.parametrize("case,spec", STAGE_CASES, ids=[c[0] for c in STAGE_CASES])
+def test_tableau_stages_match_oracle(case, spec, tab):
+    _say("tableau stages", case, tab)
+    wl, o, view, s, w0 = _setup(spec)
+    A, b = _tableau(tab)
+    s.set_tableau(A, b)
+    dt = o.max_dt(w0)
+    dtd = _dev(np.array([dt]))
+    Y = [w0]
+    Yd = [_dev(w0)]
+    for m in range(1, len(b) + 1):
+        ref = o.tableau_stage(A, b, m, dt, Y)
+        got = s.tableau_stage(m, dtd, Yd)
+        err = _err(view, _host(got), ref)
+        _say(case, tab, "stage", m, "rel-L1", err)
+        assert np.all(err <= TOL), (m, err)
+        Y.append(ref)
+        Yd.append(got)
+    assert s.status() == 0
+
+
+STEP_CASES = [
+    # 2D uniform: the time step rides in the first and last stage kernels
+    ("vortex2d_k1_rk2", dict(name="vortex", k=1, n=(33, 17, 1), length=(11.0, 17 / 3, 1.0), rk="rk2")),
+    ("vortex2d_k3_rk4", dict(name="vortex", k=3, n=(20, 18, 1), length=(10.0, 9.0, 1.0), rk="rk4")),
+    ("sod_limited_rk4", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), eps=1e-3, rk="rk4")),
+    ("sod_char_rk2", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), eps=1e-3, limiter=2, rk="rk2")),
+    ("kh3d_k2_rk4", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), rk="rk4")),
+    ("amr3d_k1_rk2", dict(amr=dict(dim=3, k=1, n=(8, 7, 6), lo=(2, 2, 1), hi=(6, 5, 4), rk="rk2"))),
+]
+
+
+@pytest.mark.parametrize("case,spec", STEP_CASES, ids=[c[0] for c in STEP_CASES])
+def test_tableau_steps_match_oracle_and_composed_calls(case, spec):
+    _say("tableau steps", case)
+    wl, o, view, s, w0 = _setup(spec)
+    nst = s.stages
+    assert nst == len(oracle.TABLEAUS[wl["rk"]][1])
+    # composed: max_dt, then one call per stage and limiter
+    cb = [s.empty() for _ in range(nst)] + [s.scalar()]
+    w = _dev(w0)
+    comp, comp_dt = [], []
+    for _ in range(3):
+        w = s.step(w, cb).clone()
+        comp.append(_host(w))
+        comp_dt.append(float(_host(cb[nst])[0]))
+    # one call per step, rate carried
+    fb = [s.empty() for _ in range(nst)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    ref = w0
+    for i in range(3):
+        ref, dt_ref = o.step(ref)
+        w = s.rk_step(w, fb, dt, rate).clone()
+        got = _host(w)
+        assert float(_host(dt)[0]) == comp_dt[i]
+        assert np.array_equal(got, comp[i]), (i, np.abs(got - comp[i]).max())
+        assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
+        err = _err(view, got, ref)
+        _say(case, "step", i, "rel-L1", err)
+        assert np.all(err <= TOL), (i, err)
+    # the carried rate gives the oracle's next step
+    s.rk_step(w, fb, dt, rate)
+    assert float(_host(dt)[0]) == pytest.approx(o.max_dt(ref), rel=1e-14)
+    assert s.status() == 0
+
+
+def test_rk3_tableau_step_agrees_with_ssp_rk3_step():
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0))
+    s3 = dg.Solver(wl)
+    st = dg.Solver(wl)
+    st.set_tableau(*dg.TABLEAUS["rk3"])
+    assert st.rk == "rk3"
+    w0 = oracle.Oracle(wl).initial_state()
+    dt = _dev(np.array([0.01]))
+    a = _dev(w0)
+    ref = s3.rk_stage(3, dt, a, s3.rk_stage(2, dt, a, s3.rk_stage(1, dt, None, a)))
+    y1 = st.tableau_stage(1, dt, [a])
+    y2 = st.tableau_stage(2, dt, [a, y1])
+    y3 = st.tableau_stage(3, dt, [a, y1, y2])
+    np.testing.assert_allclose(_host(y3), _host(ref), rtol=0, atol=1e-14 * float(ref.abs().max()))
+
+
+def test_set_tableau_rejects_bad_tables_and_keeps_the_previous():
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("vortex", n=(16, 16, 1), length=(4.0, 4.0, 1.0), rk="rk2")
+    s = dg.Solver(wl)
+    for A, b in [([[0.5, 0.0], [0.5, 0.0]], [0.5, 0.5]),            # diagonal entry
+                 ([[0, 0, 0], [0, 0, 0], [0.5, 0.5, 0]], [0.2, 0.3, 0.5]),  # a_21 = 0
+                 ([[0.0, 0.0], [1.0, 0.0]], [1.0, 0.0]),            # b_s = 0
+                 (np.zeros((6, 6)), np.ones(6) / 6)]:               # more than 5 stages
+        with pytest.raises(dg.DGError) as e:
+            s.set_tableau(A, b)
+        assert e.value.code == dg.DG_EINVAL
+    assert s.stages == 2
+    # the two-stage integrator is still in place: a stage 3 does not exist
+    w = s.empty().zero_()
+    dt = s.scalar()
+    with pytest.raises(dg.DGError):
+        s.tableau_stage(3, dt, [w, s.empty(), s.empty()])
+    with pytest.raises(dg.DGError):  # the output aliasing an input
+        s.tableau_stage(2, dt, [w, s.empty()], out=w)
+
+
+def test_tableau_step_graph_replays():
+    # two RK_4 steps captured (ping-pong A -> B -> A) and replayed three
+    # times with eager work in between; every replay equals the eager chain
+    import torch
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("vortex", k=3, n=(48, 40, 1), length=(12.0, 10.0, 1.0), rk="rk4")
+    s = dg.Solver(wl)
+    w0 = oracle.Oracle(wl).initial_state()
+    fb = [s.empty() for _ in range(5)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    eager = []
+    for _ in range(8):
+        w = s.rk_step(w, fb, dt, rate).clone()
+        eager.append(_host(w))
+    A, B = _dev(w0), s.empty()
+    st = [s.empty() for _ in range(4)]
+    dtb, rb = s.scalar(), s.rate_state()
+
+    def two():
+        s.rk_step(A, st + [B], dtb, rb)
+        s.rk_step(B, st + [A], dtb, rb)
+
+    s.max_rate(A, rb)
+    two()
+    torch.cuda.synchronize()
+    assert np.array_equal(_host(A), eager[1])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    A_saved, r_saved = A.clone(), rb.clone()
+    with torch.cuda.stream(side):
+        two()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    assert np.array_equal(_host(A), eager[3])
+    A.copy_(A_saved)
+    rb.copy_(r_saved)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        two()
+    torch.cuda.synchronize()
+    for r in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = _host(A)
+        _say("replay", r, "max diff", np.abs(got - eager[3 + 2 * r]).max())
+        assert np.array_equal(got, eager[3 + 2 * r]), r
+        x = _dev(np.ones(16)) * 2.0
+        torch.cuda.synchronize()
+        assert float(x.sum()) == 32.0
+    assert s.status() == 0
