@@ -143,15 +143,16 @@ def time_steps(s, wl, steps, warmup, graph=True):
     if s.limited:
         s.limit(A)
     B = s.empty()
-    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.rate_state()
+    stage_bufs = [s.empty() for _ in range(s.stages - 1)]
+    dtbuf, rate = s.scalar(), s.rate_state()
     stream = torch.cuda.current_stream()
     s.max_rate(A, rate)
 
     def two_steps():
         # one library call per step; the signal rate of the new state is
         # carried in `rate` to the next step's time step
-        s.rk_step(A, [u1, u2, B], dtbuf, rate)
-        s.rk_step(B, [u1, u2, A], dtbuf, rate)
+        s.rk_step(A, stage_bufs + [B], dtbuf, rate)
+        s.rk_step(B, stage_bufs + [A], dtbuf, rate)
 
     steps = steps + (steps % 2)
     for _ in range((warmup + 1) // 2):
@@ -189,8 +190,11 @@ def variants():
     out = {}
     # the refined-box blast in reduced precision needs a positivity floor above
     # the FP32 rounding of the energy (node pressures are formed in FP32)
-    # (the *_char runs: the same workloads with the characteristic limiter)
+    # (the *_char runs: the same workloads with the characteristic limiter;
+    # DG-4 and DG-5: the vortex at k = 3 and k = 4 with the five-stage RK_4)
     runs = [("vortex", "vortex", 400, {}, ("fp64", "fp32", "bf16")),
+            ("vortex_dg4_rk4", "vortex", 200, {"k": 3, "rk": "rk4"}, ("fp64", "fp32")),
+            ("vortex_dg5_rk4", "vortex", 200, {"k": 4, "rk": "rk4"}, ("fp64", "fp32")),
             ("kh3d", "kh3d", 10, {}, ("fp64", "fp32", "bf16")),
             ("kh3d_char", "kh3d", 10, {"limiter": 2}, ("fp64",)),
             ("blast_amr", "blast_amr", 10, {"eps": 1e-4}, ("fp64", "fp32", "bf16")),
@@ -203,14 +207,15 @@ def variants():
             cells = (s.ncoarse - s.nhole + s.nfine) if s.amr else s.ncell
             b, f = alg_work(wl["dim"], wl["k"])
             peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
-            # fractions of one step's algorithmic work (3 stages) over the
+            # fractions of one step's algorithmic work (all stages) over the
             # whole step time (time step and limiters included)
-            out[f"{label}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": cells * s.N * 3 / (ms * 1e-3),
-                                     "cells": cells, "k": wl["k"], "dim": wl["dim"],
+            ns = s.stages
+            out[f"{label}_{prec}"] = {"ms_per_step": ms, "dof_updates_per_s": cells * s.N * ns / (ms * 1e-3),
+                                     "cells": cells, "k": wl["k"], "dim": wl["dim"], "stages": ns,
                                      "limiter": wl["limiter"], "positivity": wl["positivity"],
                                      "eps": wl["eps"], "status": s.status(),
-                                     "hbm_frac": 3 * b * cells / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                                     "alu_frac": 3 * f * cells / (ms * 1e-3) / (peak * 1e12),
+                                     "hbm_frac": ns * b * cells / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                                     "alu_frac": ns * f * cells / (ms * 1e-3) / (peak * 1e12),
                                      "alu_peak_tflops": peak}
             del s
             torch.cuda.empty_cache()

@@ -681,6 +681,8 @@ template <>
 struct Tile2D<2> { static constexpr int TX = 16, TY = DG_TILE2D_TY2; };
 template <>
 struct Tile2D<3> { static constexpr int TX = 16, TY = DG_TILE2D_TY3; };
+template <>
+struct Tile2D<4> { static constexpr int TX = 16, TY = 8; };
 
 // Exchange of a value with the lane `sub ^ 1` or `sub ^ 2` of the same quad
 // (DPP quad permutation, no LDS traffic).
@@ -2648,6 +2650,7 @@ int dispatch(const dg_ctx *c, F &&f) {
   if (d == 2 && k == 1) return f.template run<2, 1>();
   if (d == 2 && k == 2) return f.template run<2, 2>();
   if (d == 2 && k == 3) return f.template run<2, 3>();
+  if (d == 2 && k == 4) return f.template run<2, 4>();  // uniform grids, FP64/FP32 (dg_init checks)
   if (d == 3 && k == 1) return f.template run<3, 1>();
   if (d == 3 && k == 2) return f.template run<3, 2>();
   if (d == 3 && k == 3) return f.template run<3, 3>();
@@ -2686,7 +2689,9 @@ struct StageLaunch {
   int launch_fx(const R *tabr, const float *vext) {
     if ((c->amr || D != 2) && ro.op != dg::RATE_NONE) return DG_EINVAL;
     if (c->amr) {
-      if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
+      if constexpr (K > 3) {
+        return DG_EUNSUPPORTED;
+      } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
         // four lanes per cell (the one-thread kernel would spill)
         hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0,
                            s, c->tab, w, out, dt, make_amr_grid(c), mode, mx, c->flag);
@@ -2735,9 +2740,13 @@ struct StageLaunch {
   template <int D, int K>
   int run() {
     if (c->cfg.precision == DG_BF16_VOL) {
-      int st = volume_bf16<D, K>();
-      if (st != DG_OK) return st;
-      return launch<D, K, float>(c->tab32, c->vscratch);
+      if constexpr (K > 3) {
+        return DG_EUNSUPPORTED;
+      } else {
+        int st = volume_bf16<D, K>();
+        if (st != DG_OK) return st;
+        return launch<D, K, float>(c->tab32, c->vscratch);
+      }
     }
     if (c->cfg.precision == DG_FP32) return launch<D, K, float>(c->tab32, nullptr);
     return launch<D, K, double>(c->tab, nullptr);
@@ -2776,9 +2785,13 @@ struct LimitLaunch {
     const bool chr = c->cfg.slope_limiter == DG_LIM_CHAR;
     const int slope = c->cfg.slope_limiter != DG_LIM_NONE;
     if (c->amr) {
-      hipLaunchKernelGGL((chr ? dg::k_limit_amr<D, K, true> : dg::k_limit_amr<D, K, false>),
-                         dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w, make_amr_grid(c), slope,
-                         c->cfg.beta, c->cfg.m_tilde, c->cfg.positivity, c->cfg.eps, c->flag);
+      if constexpr (K > 3) {
+        return DG_EUNSUPPORTED;
+      } else {
+        hipLaunchKernelGGL((chr ? dg::k_limit_amr<D, K, true> : dg::k_limit_amr<D, K, false>),
+                           dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w, make_amr_grid(c), slope,
+                           c->cfg.beta, c->cfg.m_tilde, c->cfg.positivity, c->cfg.eps, c->flag);
+      }
     } else {
       hipLaunchKernelGGL((chr ? dg::k_limit<D, K, true> : dg::k_limit<D, K, false>), dim3(nblocks(c->ncell)),
                          dim3(kBlock), 0, s, c->tab, w, make_grid(c), slope, c->cfg.beta, c->cfg.m_tilde * c->dx,
@@ -2803,7 +2816,9 @@ struct AdjointLaunch {
   }
   template <int D, int K, int FX>
   int run_fx() {
-    if constexpr (D == 2) {  // four lanes per cell
+    if constexpr (K > 3) {
+      return DG_EUNSUPPORTED;
+    } else if constexpr (D == 2) {  // four lanes per cell
       hipLaunchKernelGGL((dg::k_adjoint_quad2d<K, FX>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab, w, lam,
                          acc, out, acc_out, dt, make_grid(c), mode, ca, cb, c->flag);
     } else {
@@ -2829,18 +2844,22 @@ struct Bf16Tables {
   std::vector<uint16_t> *out;
   template <int D, int K>
   int run() {
-    using C = Cfg<D, K>;
-    using M = dg::Mfma<D, K>;
-    std::vector<uint16_t> &t = *out;
-    t.assign(M::TOTAL, 0);
-    const std::vector<double> &h = c->host_tab;
-    for (int q = 0; q < C::Q; ++q)
-      for (int m = 0; m < C::N; ++m) t[M::PB + q * M::NP + m] = to_bf16((float)h[C::B + q * C::N + m]);
-    for (int a = 0; a < D; ++a)
-      for (int m = 0; m < C::N; ++m)
-        for (int q = 0; q < C::Q; ++q)
-          t[M::DB + (a * M::NP + m) * M::QP + q] = to_bf16((float)h[C::DW + (a * C::Q + q) * C::N + m]);
-    return DG_OK;
+    if constexpr (K > 3) {
+      return DG_EUNSUPPORTED;
+    } else {
+      using C = Cfg<D, K>;
+      using M = dg::Mfma<D, K>;
+      std::vector<uint16_t> &t = *out;
+      t.assign(M::TOTAL, 0);
+      const std::vector<double> &h = c->host_tab;
+      for (int q = 0; q < C::Q; ++q)
+        for (int m = 0; m < C::N; ++m) t[M::PB + q * M::NP + m] = to_bf16((float)h[C::B + q * C::N + m]);
+      for (int a = 0; a < D; ++a)
+        for (int m = 0; m < C::N; ++m)
+          for (int q = 0; q < C::Q; ++q)
+            t[M::DB + (a * M::NP + m) * M::QP + q] = to_bf16((float)h[C::DW + (a * C::Q + q) * C::N + m]);
+      return DG_OK;
+    }
   }
 };
 
@@ -2957,7 +2976,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if (!cfg || !out) return DG_EINVAL;
   *out = nullptr;
   if (cfg->dim != 2 && cfg->dim != 3) return DG_EUNSUPPORTED;
-  if (cfg->k < 1 || cfg->k > 3) return DG_EUNSUPPORTED;
+  if (cfg->k < 1 || cfg->k > 4) return DG_EUNSUPPORTED;
+  if (cfg->k == 4 && (cfg->dim != 2 || cfg->precision == DG_BF16_VOL)) return DG_EUNSUPPORTED;
   for (int a = 0; a < cfg->dim; ++a) {
     if (cfg->n[a] < 1 || !(cfg->len[a] > 0.0)) return DG_EINVAL;
     if (cfg->bc[a] != DG_BC_PERIODIC && cfg->bc[a] != DG_BC_TRANSMISSIVE) return DG_EINVAL;
@@ -2977,6 +2997,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
     for (int a = 0; a < cfg->dim; ++a)
       if (cfg->refine_lo[a] < 1 || cfg->refine_hi[a] > cfg->n[a] - 1 || cfg->refine_hi[a] <= cfg->refine_lo[a])
         return DG_EINVAL;
+  if (amr && cfg->k == 4) return DG_EUNSUPPORTED;
   const double dx = cfg->len[0] / cfg->n[0];
   for (int a = 1; a < cfg->dim; ++a)
     if (std::fabs(cfg->len[a] / cfg->n[a] - dx) > 1e-12 * dx) return DG_EINVAL;

@@ -46,7 +46,7 @@ def _touched(w, x, nvar):
 # amplitude 0.03 of the higher modes leaves 10-60 % of the cells limited (a
 # mix, so that the decision is tested both ways), 0.4 limits every cell
 @pytest.mark.parametrize("amp", [0.03, 0.4])
-@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)])
 def test_char_limiter_matches_oracle(dim, k, amp):
     import paper_1506_06140_amd as dg
     n = (9, 7, 5) if dim == 3 else (13, 11, 1)

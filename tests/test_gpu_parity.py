@@ -82,6 +82,8 @@ CASES = [
     ("dw_k1", dict(name="density_wave")),
     ("vortex_k2_40x24", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0), noise=1e-3)),
     ("vortex_k3_20x18", dict(name="vortex", k=3, n=(20, 18, 1), length=(10.0, 9.0, 1.0), noise=0.0)),
+    # k = 4 (2D only): 16x8 tiles, ragged in both directions
+    ("vortex_k4_37x21", dict(name="vortex", k=4, n=(37, 21, 1), length=(37 / 3.6, 21 / 3.6, 1.0), noise=1e-3)),
     ("kh3d_k1", dict(name="kh3d", k=1, n=(12, 10, 9), length=(1.2, 1.0, 0.9), limiter=0, positivity=0)),
     ("kh3d_k2", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), limiter=0, positivity=0)),
     ("blast_k3", dict(name="blast_amr", k=3, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), limiter=0, positivity=0,
@@ -249,7 +251,7 @@ def test_projection_matches_oracle():
         assert np.all(err <= 1e-14), err
 
 
-@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2), (3, 3)])
+@pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)])
 def test_limiter_matches_oracle(dim, k):
     n = (9, 7, 5) if dim == 3 else (13, 11, 1)
     h = 0.1

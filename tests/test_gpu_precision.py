@@ -62,6 +62,7 @@ BLAST_AMR = dict(n=(16, 16, 16), refine_lo=(4, 4, 4), refine_hi=(12, 12, 12), ep
 
 @pytest.mark.parametrize("name,over", [
     ("vortex", dict(n=(64, 64, 1))),
+    ("vortex", dict(k=4, n=(40, 36, 1), length=(10.0, 9.0, 1.0))),
     ("vortex_adjoint", dict(n=(48, 40, 1), length=(12.0, 10.0, 1.0))),
     ("kh3d", dict(n=(24, 24, 24))),
     ("blast_amr", BLAST_AMR),

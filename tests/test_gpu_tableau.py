@@ -101,6 +101,9 @@ STEP_CASES = [
     # 2D uniform: the time step rides in the first and last stage kernels
     ("vortex2d_k1_rk2", dict(name="vortex", k=1, n=(33, 17, 1), length=(11.0, 17 / 3, 1.0), rk="rk2")),
     ("vortex2d_k3_rk4", dict(name="vortex", k=3, n=(20, 18, 1), length=(10.0, 9.0, 1.0), rk="rk4")),
+    ("vortex2d_k4_rk4", dict(name="vortex", k=4, n=(37, 21, 1), length=(37 / 3.6, 21 / 3.6, 1.0), rk="rk4")),
+    ("sod_limited_k4_rk4", dict(name="sod", k=4, n=(40, 4, 1), length=(1.0, 0.1, 1.0), eps=1e-3, limiter=2,
+                                rk="rk4")),
     ("sod_limited_rk4", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), eps=1e-3, rk="rk4")),
     ("sod_char_rk2", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), eps=1e-3, limiter=2, rk="rk2")),
     ("kh3d_k2_rk4", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), rk="rk4")),

@@ -53,7 +53,7 @@ def test_strerror_covers_codes():
 @pytest.mark.parametrize("field,value,code", [
     ("dim", 4, dg.DG_EUNSUPPORTED),
     ("k", 0, dg.DG_EUNSUPPORTED),
-    ("k", 4, dg.DG_EUNSUPPORTED),
+    ("k", 5, dg.DG_EUNSUPPORTED),
     ("gamma", 1.0, dg.DG_EINVAL),
     ("cfl", 0.0, dg.DG_EINVAL),
     ("flux", 7, dg.DG_EINVAL),
@@ -66,6 +66,20 @@ def test_init_rejects_bad_configs_on_the_host(field, value, code):
     setattr(cfg, field, value)
     ctx = C.c_void_p()
     assert lib.dg_init(C.byref(cfg), C.byref(ctx)) == code
+    assert not ctx.value
+
+
+@pytest.mark.parametrize("over,precision", [
+    (dict(dim=3, n=(8, 8, 8), length=(1.0, 1.0, 1.0)), "fp64"),   # k = 4 is 2D only
+    ({}, "bf16"),                                                  # no BF16 tables at k = 4
+    (dict(refine_lo=(2, 2, 0), refine_hi=(4, 4, 0)), "fp64"),     # nor a refined box
+])
+def test_init_rejects_unsupported_k4(over, precision):
+    import ctypes as C
+    lib = dg.load_library()
+    cfg = dg.make_config(workloads.workload("density_wave", k=4, **over), precision)
+    ctx = C.c_void_p()
+    assert lib.dg_init(C.byref(cfg), C.byref(ctx)) == dg.DG_EUNSUPPORTED
     assert not ctx.value
 
 

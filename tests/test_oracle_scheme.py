@@ -187,7 +187,7 @@ def _order(errs, ns):
     return [math.log(errs[i] / errs[i + 1]) / math.log(ns[i + 1] / ns[i]) for i in range(len(ns) - 1)]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
 def test_density_wave_translates_with_order_k_plus_1(k):
     # rho = 1 + 0.2 sin(2 pi (x + y - 2t)) is the exact solution; the L1 error
     # (eq. L1_norm, integrated with (k+3)^2 points) must fall at order >= k+1
