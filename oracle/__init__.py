@@ -48,6 +48,7 @@ class Config(C.Structure):
         ("beta", C.c_double), ("mtilde", C.c_double),
         ("positivity", C.c_int), ("eps", C.c_double),
         ("refine_lo", C.c_int * 3), ("refine_hi", C.c_int * 3),
+        ("accel", C.POINTER(C.c_double)),
     ]
 
 
@@ -219,6 +220,13 @@ class Oracle:
         nz = wl["n"][2] if c.dim == 3 else 1
         self.shape = (self.nvar, self.N, nz, wl["n"][1], wl["n"][0])
         self.dx = wl["length"][0] / wl["n"][0]
+        self._accel = None
+        if wl.get("gravity") is not None:
+            # the external acceleration sampled at the oracle's own volume nodes
+            x = self.node_coords()  # [ncell][Q][3]
+            acc = workloads.acceleration(wl, x[..., 0].T, x[..., 1].T, x[..., 2].T)  # d x [Q][ncell]
+            self._accel = np.ascontiguousarray(np.stack(acc), dtype=np.float64)
+            c.accel = self._accel.ctypes.data_as(C.POINTER(C.c_double))
 
     # -- tables -------------------------------------------------------------
     def exponents(self) -> np.ndarray:

@@ -35,6 +35,7 @@
  *   SSP-RK3 ......................... App. D, table RK_3
  *   general explicit RK (tableau) ... App. D, table butcher, eqs. for w^{n+1}
  *                                     and rhs; tables RK_2, RK_4
+ *   gravity source and time step .... Sec. 2.4 eq. gravity_term; Sec. 2.5
  * The HLLC Riemann solver is cited by the paper to Toro's textbook only; the
  * textbook HLLC with Einfeldt-Batten (Roe-averaged) wave-speed bounds is
  * used, with a Davis-bound option.
@@ -88,6 +89,9 @@ typedef struct {
   int positivity;  /* 0/1 Zhang-Shu positivity limiter                      */
   double eps;
   int refine_lo[3], refine_hi[3]; /* static 2:1 box in base-cell indices      */
+  const double *accel; /* external acceleration a = -grad Phi at the volume
+                          nodes, [d][Q][ncell] (node order of
+                          orc_node_coords), or NULL; uniform grids only      */
 } orc_config;
 
 /* ------------------------------------------------------------------------ */
@@ -417,7 +421,33 @@ static void surface_term(const ctx *X, const real_t *w, long cell, real_t S[MAXV
     }
 }
 
-/* dw_j/dt = -R = (|K|)^-1 (dx/2)^(d-1) (V_j - S_j) = (2/dx) 2^-d (V_j - S_j). */
+/* Gravity source (eq. gravity_term): s = (0, rho a, rho v . a) with the
+ * external acceleration a = -grad Phi given at the volume nodes, projected
+ * onto phi_j with the volume rule: G_j = sum_q s(xi_q) phi_j(xi_q) w_q, the
+ * integral over the cell being (|K| / 2^d) G_j. */
+static void source_term(const ctx *X, const real_t *w, long cell, real_t G[MAXV][MAXN]) {
+  for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) G[v][j] = 0.0;
+  for (int q = 0; q < X->Q; ++q) {
+    real_t U[MAXV], s[MAXV];
+    for (int v = 0; v < X->nvar; ++v) {
+      U[v] = 0.0;
+      for (int l = 0; l < X->N; ++l) U[v] += W(v, l, cell) * X->phiV[q][l];
+    }
+    s[0] = 0.0;
+    real_t work = 0.0;
+    for (int a = 0; a < X->d; ++a) {
+      double acc = X->c.accel[((long)a * X->Q + q) * X->ncell + cell];
+      s[1 + a] = U[0] * acc;   /* rho a     */
+      work += U[1 + a] * acc;  /* m . a     */
+    }
+    s[X->d + 1] = work;
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) G[v][j] += s[v] * X->phiV[q][j] * X->wV[q];
+  }
+}
+
+/* dw_j/dt = -R = (|K|)^-1 (dx/2)^(d-1) (V_j - S_j) = (2/dx) 2^-d (V_j - S_j),
+ * plus |K|^-1 (|K| / 2^d) G_j with a gravity source. */
 static void rhs_cell(const ctx *X, const real_t *w, long cell, real_t Lc[MAXV][MAXN]) {
   real_t V[MAXV][MAXN], S[MAXV][MAXN];
   volume_term(X, w, cell, V);
@@ -425,6 +455,12 @@ static void rhs_cell(const ctx *X, const real_t *w, long cell, real_t Lc[MAXV][M
   double fac = 2.0 / X->dx / (double)(1 << X->d);
   for (int v = 0; v < X->nvar; ++v)
     for (int j = 0; j < X->N; ++j) Lc[v][j] = fac * (V[v][j] - S[v][j]);
+  if (X->c.accel) {
+    real_t G[MAXV][MAXN];
+    source_term(X, w, cell, G);
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) Lc[v][j] += G[v][j] / (double)(1 << X->d);
+  }
 }
 
 static void rhs_all(const ctx *X, const real_t *w, real_t *L) {
@@ -675,6 +711,23 @@ int orc_max_dt(const orc_config *c, const double *w, double *dt_out) {
     for (int a = 0; a < X->d; ++a) rate += (fabs(U[1 + a] / U[0]) + cs) / X->dx;
     double dtc = c->cfl * fk / rate;
     if (dtc < dt) dt = dtc;
+    if (c->accel) {
+      /* gravity step (Sec. 2.5): dt <= c / (sqrt(2 gamma (gamma-1)) |grad Phi|),
+       * |grad Phi| the largest over the cell's volume nodes */
+      double amax = 0.0;
+      for (int q = 0; q < X->Q; ++q) {
+        double a2 = 0.0;
+        for (int a = 0; a < X->d; ++a) {
+          double g = c->accel[((long)a * X->Q + q) * X->ncell + cell];
+          a2 += g * g;
+        }
+        if (sqrt(a2) > amax) amax = sqrt(a2);
+      }
+      if (amax > 0.0) {
+        double dtg = cs / (sqrt(2.0 * c->gamma * (c->gamma - 1.0)) * amax);
+        if (dtg < dt) dt = dtg;
+      }
+    }
   }
   *dt_out = dt;
   free(X);
@@ -1151,6 +1204,7 @@ typedef struct {
 } amr;
 
 static int amr_init(const orc_config *c, amr *M) {
+  if (c->accel) return ORC_EINVAL; /* gravity on uniform grids only */
   int st = ctx_init(c, &M->Xc);
   if (st != ORC_OK) return st;
   int d = M->Xc.d;

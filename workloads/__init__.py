@@ -21,7 +21,10 @@ Problem sources (the paper's validation section):
     velocity noise in place of the single-mode perturbation;
   * blast: a Sod-type spherical over-pressure region;
   * density wave: rho = 1 + 0.2 sin(2 pi (x + y)) advected at constant velocity
-    and pressure.
+    and pressure;
+  * cold Keplerian disc: a pressure-less ring on Keplerian orbits in a static
+    softened central potential (Validation, Keplerian disc), with its
+    external acceleration field (`acceleration`).
 """
 from __future__ import annotations
 
@@ -63,6 +66,12 @@ def sign_direction(seed: int, size: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 WORKLOADS: dict[str, dict] = {
+    # 2D cold Keplerian disc on [0,6]^2, gamma 5/3, to t = 120 (about 20 orbits
+    # at r = 1), DG-2 with the positivity limiter only and the central
+    # potential's acceleration as the gravity source.
+    "kepler": dict(dim=2, k=1, n=(128, 128, 1), x0=(0.0, 0.0, 0.0), length=(6.0, 6.0, 1.0),
+                   gamma=5.0 / 3.0, cfl=0.2, limiter=0, positivity=1, eps=1e-8, ic="kepler",
+                   gravity="kepler", rk="rk2", t_end=120.0),
     # 2D, k=1, 32^2, smooth density wave, CFL 0.3, 20 steps, no limiter.
     "density_wave": dict(dim=2, k=1, n=(32, 32, 1), x0=(0.0, 0.0, 0.0),
                          length=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.3, steps=20,
@@ -111,8 +120,56 @@ def workload(name: str, **overrides) -> dict:
     w.setdefault("refine_hi", (0, 0, 0))
     w.setdefault("flux", 0)
     w.setdefault("rk", "rk3")  # time integrator: "rk2", "rk3" or "rk4" (App. D tables)
+    w.setdefault("gravity", None)  # external acceleration field (see acceleration), or None
     w["name"] = name
     return w
+
+
+# Keplerian disc: background rho0 = p0 = 1e-5, disc density 1 between radii
+# 0.5 and 2 with linear ramps of width 0.1, centre (3, 3), potential softened
+# with eps = 0.25 inside r = 0.5 - 0.05.
+KEPLER = dict(centre=(3.0, 3.0), rho0=1e-5, p0=1e-5, rho_disc=1.0, r_in=0.5, r_out=2.0, dr=0.1, soft=0.25)
+
+
+def _kepler_primitives(x, y, over=None):
+    k = dict(KEPLER, **(over or {}))
+    dx, dy = x - k["centre"][0], y - k["centre"][1]
+    r = np.sqrt(dx * dx + dy * dy)
+    r_in, r_out, dr, r0, rd = k["r_in"], k["r_out"], k["dr"], k["rho0"], k["rho_disc"]
+    rho = np.full_like(r, r0)
+    ramp_in = (r >= r_in - dr / 2) & (r < r_in + dr / 2)
+    rho = np.where(ramp_in, (rd - r0) / dr * (r - (r_in - dr / 2)) + r0, rho)
+    rho = np.where((r >= r_in + dr / 2) & (r < r_out - dr / 2), rd, rho)
+    ramp_out = (r >= r_out - dr / 2) & (r < r_out + dr / 2)
+    rho = np.where(ramp_out, (r0 - rd) / dr * (r - (r_out - dr / 2)) + rd, rho)
+    moving = (r > r_in - 2 * dr) & (r < r_out + 2 * dr)
+    rs = np.where(r > 0.0, r, 1.0)
+    vx = np.where(moving, -dy / rs ** 1.5, 0.0)
+    vy = np.where(moving, dx / rs ** 1.5, 0.0)
+    return rho, vx, vy, np.full_like(r, k["p0"])
+
+
+def acceleration(wl: dict, x, y, z):
+    """External acceleration a = -grad Phi of workload `wl` at points (x, y, z),
+    as a tuple of `dim` arrays: the softened central field of the Keplerian
+    disc, or a uniform vector (`gravity` = ("uniform", (gx, gy, gz)))."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    d = wl["dim"]
+    gtype = wl["gravity"]
+    if isinstance(gtype, (tuple, list)) and gtype[0] == "uniform":
+        return tuple(np.full_like(x, gtype[1][a]) for a in range(d))
+    if gtype == "kepler":
+        k = KEPLER
+        dx, dy = x - k["centre"][0], y - k["centre"][1]
+        r = np.sqrt(dx * dx + dy * dy)
+        outer = r > k["r_in"] - 0.5 * k["dr"]
+        rs = np.where(r > 0.0, r, 1.0)
+        inv = np.where(outer, 1.0 / rs ** 3, 1.0 / (rs * (rs * rs + k["soft"] ** 2)))
+        inv = np.where(r > 0.0, inv, 0.0)
+        return (-dx * inv, -dy * inv)
+    raise ValueError(f"unknown gravity field {gtype!r}")
 
 
 def _wrap(d: np.ndarray, length: float) -> np.ndarray:
@@ -187,6 +244,10 @@ def primitives(wl: dict, x, y, z, cell=None, node=None, t: float = 0.0):
             rho = rho + c * x ** ex * y ** ey * z ** ez
         vel = wl.get("velocity", (0.7, -0.4, 0.3))
         return rho, zeros + vel[0], zeros + vel[1], zeros + vel[2], zeros + wl.get("pressure", 1.0)
+    if ic == "kepler":
+        # `kepler_params` may override the background values (rho0, p0)
+        rho, vx, vy, p = _kepler_primitives(x, y, wl.get("kepler_params"))
+        return rho, vx, vy, zeros, p
     if ic == "uniform":
         rho0, vel, p0 = wl["state"]
         return (zeros + rho0, zeros + vel[0], zeros + vel[1], zeros + vel[2],
