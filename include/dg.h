@@ -210,6 +210,21 @@ int dg_tableau_stage(dg_ctx *ctx, int m, const double *dt_dev, const double *con
 int dg_tableau_step(dg_ctx *ctx, const double *w, double *const *stage, double *w_out, double *dt_dev,
                     double *rate_dev, void *stream);
 
+/* External gravity: the source s = (0, rho a, m . a) of eq. gravity_term
+ * (Sec. 2.4), projected with the volume rule, is added to the right-hand side
+ * of every later dg_rhs / stage / step call, and the time step becomes the
+ * smaller of the CFL step and c / (sqrt(2 gamma (gamma-1)) |grad Phi|) per
+ * cell (Sec. 2.5; c of the cell mean, |grad Phi| the largest over the cell's
+ * volume nodes).  accel: device array of the acceleration a = -grad Phi at
+ * the volume nodes, [dim][Q][ncell] with the node order of dg_quadrature; it
+ * is read on `stream` before the call's work completes and may be freed or
+ * reused after that; NULL switches gravity off.  The library keeps its own
+ * copy (allocated on the first call: dim * Q + 1 doubles per cell).
+ * DG_EUNSUPPORTED for a refined box, a precision other than DG_FP64, or 3D
+ * with k = 3; dg_adjoint_rhs and dg_adjoint_rk_stage return DG_EUNSUPPORTED
+ * while gravity is on. */
+int dg_set_gravity(dg_ctx *ctx, const double *accel, void *stream);
+
 /* Slope limiter (minmod with TVB bound, Sec. 3.3: component-wise on the
  * conserved variables, Sec. 3.1, or on the characteristic variables of the
  * cell mean, Sec. 3.2 eq. char_limiter) then positivity limiter (Sec. 3.4),

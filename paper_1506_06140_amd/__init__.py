@@ -62,7 +62,7 @@ class dg_config(C.Structure):
 EXPORTS = (
     "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
     "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
-    "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
+    "dg_set_gravity", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
 )
 
 _lib = None
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
     lib.dg_tableau_stage.argtypes = [ctxp, C.c_int, dp, C.POINTER(C.c_void_p), dp, vp]
     lib.dg_tableau_step.argtypes = [ctxp, dp, C.POINTER(C.c_void_p), dp, dp, dp, vp]
     lib.dg_limit.argtypes = [ctxp, dp, vp]
+    lib.dg_set_gravity.argtypes = [ctxp, dp, vp]
     lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
     lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
     lib.dg_status.argtypes = [ctxp, vp]
@@ -186,6 +187,14 @@ class Solver:
         self.stages = 3
         if self.rk != "rk3":
             self.set_tableau(*TABLEAUS[self.rk])
+        self.gravity = None
+        if wl.get("gravity") is not None:
+            # the workload's external acceleration at the library's volume nodes
+            import torch
+            import workloads
+            x = self.node_coords()
+            acc = np.stack(workloads.acceleration(self.wl, x[0], x[1], x[2]))
+            self.set_gravity(torch.from_numpy(np.ascontiguousarray(acc)).cuda())
 
     def _s(self, t) -> int:
         return _ptr(t, self.size)
@@ -287,6 +296,13 @@ class Solver:
                "dg_set_tableau")
         self.stages = s
         self.rk = next((k for k, (ta, tb) in TABLEAUS.items() if list(ta) == a and list(tb) == b), "custom")
+
+    def set_gravity(self, accel, stream=None):
+        """External acceleration [dim][Q][ncell] at the volume nodes (device
+        tensor), or None to switch gravity off."""
+        ptr = _ptr(accel, self.wl["dim"] * self.Q * self.ncell) if accel is not None else None
+        _check(self.lib.dg_set_gravity(self.ctx, ptr, _stream(stream)), "dg_set_gravity")
+        self.gravity = accel
 
     def tableau_stage(self, m, dt, ys, out=None, stream=None):
         """Stage value Y_m of the configured tableau from ys = [Y_0, .., Y_{m-1}] (unlimited)."""

@@ -79,4 +79,9 @@ struct dg_ctx {
   int rk_s = 0;
   double rk_alpha[DG_MAX_STAGES + 1][DG_MAX_STAGES + 1] = {};
   double rk_beta[DG_MAX_STAGES + 1] = {};
+  // external gravity (dg_set_gravity): (dx/2) w_q a at the volume nodes
+  // [d][Q][ncell], the largest |a| per cell, and CFL f_k sqrt(2 gamma (gamma-1))
+  bool gravity = false;
+  double *grav = nullptr, *gmax = nullptr;
+  double grav_k = 0.0;
 };

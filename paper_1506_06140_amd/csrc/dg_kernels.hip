@@ -102,7 +102,8 @@ __device__ inline float vrsq(float x) {
 // records a non-positive density or pressure.  Shared by every kernel that
 // forms the time step, so that all of them obtain bitwise the same rate.
 template <int D>
-__device__ inline double cell_rate(const double *U, double gamma, double dx, bool &bad) {
+__device__ inline double cell_rate(const double *U, double gamma, double dx, bool &bad, double gk = 0.0,
+                                   double amax = 0.0) {
   double ke = 0.0;
 #pragma unroll
   for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b] / U[0];
@@ -112,6 +113,9 @@ __device__ inline double cell_rate(const double *U, double gamma, double dx, boo
   double rate = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) rate += (fabs(U[1 + a] / U[0]) + c) / dx;
+  // gravity step (Sec. 2.5) dt <= c / (sqrt(2 gamma (gamma-1)) |grad Phi|) as a
+  // rate against the same CFL f_k: gk = CFL f_k sqrt(2 gamma (gamma-1))
+  if (amax > 0.0) rate = fmax(rate, gk * amax / c);
   return rate;
 }
 
@@ -143,6 +147,8 @@ struct RateOp {
   double cfl_fk;  // CFL times the order factor of the time step
   double dx;
   int op;
+  const double *gmax = nullptr;  // per cell the largest |grad Phi| at its nodes (gravity), or null
+  double gk = 0.0;               // CFL f_k sqrt(2 gamma (gamma-1))
 };
 
 // Euler flux f_a(U) (eq. flux_vectors; 2D drops the third velocity).
@@ -524,11 +530,14 @@ __device__ inline double mix_out(const Mix &m, double u, double L, double cldt, 
 // Right-hand side and fused stage.
 // mode 0: out = L;  mode 1: out = the stage combination mx (above).
 // ---------------------------------------------------------------------------
-template <int D, int K, class R, int FX>
+// GRAV: add the gravity source (eq. gravity_term) from grav, the external
+// acceleration at the volume nodes times (dx/2) w_q, [D][Q][ncell] (FP64 only).
+template <int D, int K, class R, int FX, bool GRAV = false>
 __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ tab, const R *__restrict__ tabr,
                                                    const double *__restrict__ w, double *__restrict__ out,
                                                    const double *__restrict__ dtp, const float *__restrict__ vext,
-                                                   Grid g, int mode, Mix mx, int *__restrict__ flag) {
+                                                   Grid g, int mode, Mix mx, int *__restrict__ flag,
+                                                   const double *__restrict__ grav) {
   // R is the type of the contractions and fluxes (double, or float for the
   // mixed-precision path); the lift of the cell mean and the stage update are
   // always FP64.
@@ -584,6 +593,25 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
       for (int v = 0; v < C::NV; ++v)
 #pragma unroll
         for (int l = 1; l < C::N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+    }
+    if constexpr (GRAV) {
+      // s = (0, rho a, m . a) at the node, projected onto every mode
+      static_assert(sizeof(R) == sizeof(double), "the gravity source is FP64");
+      double sv[C::NV];
+      double work = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const double ga = grav[(long)(a * C::Q + q) * nc + cell];
+        sv[1 + a] = U[0] * ga;
+        work = fma(U[1 + a], ga, work);
+      }
+      sv[D + 1] = work;
+#pragma unroll
+      for (int v = 1; v < C::NV; ++v) {
+        acc0[v] = fma(sv[v], bq[0], acc0[v]);
+#pragma unroll
+        for (int l = 1; l < C::N; ++l) acc[v][l] = fma(sv[v], bq[l], acc[v][l]);
+      }
     }
   }
 
@@ -705,11 +733,12 @@ __device__ inline double quad_from(double x) {
   return quad_swap<J | (J << 2) | (J << 4) | (J << 6)>(x);
 }
 
-template <int K, class R, int FX>
+template <int K, class R, int FX, bool GRAV = false>
 __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
     const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
     double *__restrict__ out, const double *__restrict__ dtp, const float *__restrict__ vext, Grid g, int mode,
-    Mix mx, int *__restrict__ flag, RateOp ro) {
+    Mix mx, int *__restrict__ flag, RateOp ro, const double *__restrict__ grav) {
+  // GRAV: gravity source from grav as in k_rhs_stage (FP64 only).
   // R: type of the contractions and fluxes (double, or float in the mixed
   // path); the lift of the cell mean and the stage update are FP64.
   // ro (fused step): RATE_DT takes dt = CFL f_k / max rate from the slots of
@@ -854,9 +883,10 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   }
 
   // P2: volume integral (eq. dg_term2) over the nodes q = sub, sub+4, ...;
-  // dphi_1 = 0, so mode 0 receives nothing
+  // dphi_1 = 0, so mode 0 receives nothing (except from a gravity source)
   const int own = (ty + 1) * HX + (tx + 1);
   const bool real = tx < nxt && ty < nyt;
+  const long cellg = (long)(by0 + min(ty, nyt - 1)) * g.nx + (bx0 + min(tx, nxt - 1));
   R acc[NV][N];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -890,6 +920,17 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
 #pragma unroll
           for (int l = 1; l < N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
       }
+      if constexpr (GRAV) {
+        // s = (0, rho a, m . a) at the node, projected onto every mode (mode
+        // 0 included: acc[v][0] is only used by the source)
+        static_assert(sizeof(R) == sizeof(double), "the gravity source is FP64");
+        const double gx = grav[(long)q * nc + cellg], gy = grav[(long)(Q + q) * nc + cellg];
+        const double sv[NV] = {0.0, U[0] * gx, U[0] * gy, fma(U[1], gx, U[2] * gy)};
+#pragma unroll
+        for (int v = 1; v < NV; ++v)
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc[v][l] = fma(sv[v], bq[l], acc[v][l]);
+      }
     }
   }
   // reduce-scatter over the quad: lane sub keeps variable sub
@@ -899,7 +940,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int l = 1; l < N; ++l) {
+      for (int l = GRAV ? 0 : 1; l < N; ++l) {
         const R keep = hi2 ? acc[2 + j][l] : acc[j][l];
         const R send = hi2 ? acc[j][l] : acc[2 + j][l];
         part[j][l] = keep + quad_swap<kQuadXor2>(send);
@@ -910,7 +951,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   {
     const bool hi1 = sub & 1;
 #pragma unroll
-    for (int l = 1; l < N; ++l) {
+    for (int l = GRAV ? 0 : 1; l < N; ++l) {
       const R keep = hi1 ? part[1][l] : part[0][l];
       const R send = hi1 ? part[0][l] : part[1][l];
       accv[l] = keep + quad_swap<kQuadXor1>(send);
@@ -938,7 +979,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   double mean = 0.0;  // new mean of variable sub
   if (real) {
     const int v = sub;
-    double acc0 = 0.0;
+    double acc0 = GRAV ? (double)accv[0] : 0.0;  // the mean's volume term is the source's alone
     // one face per iteration keeps its lifting weights (uniform) in scalar
     // registers without spilling the other faces' weights
 #pragma unroll 1
@@ -986,7 +1027,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
     if (real) {
       const double U[4] = {quad_from<0>(mean), quad_from<1>(mean), quad_from<2>(mean), quad_from<3>(mean)};
       bool neg = false;
-      r = cell_rate<2>(U, g.gamma, ro.dx, neg);
+      r = cell_rate<2>(U, g.gamma, ro.dx, neg, ro.gk, ro.gmax ? ro.gmax[cell] : 0.0);
       if (neg && sub == 0) atomicOr(flag, FLAG_NEGATIVE);
     }
     r = wave_max(r);
@@ -1229,14 +1270,15 @@ __device__ inline double block_max(double x) {
 // kernel boundary orders the two, so no device-scope fence is needed.
 template <int D>
 __global__ __launch_bounds__(256) void k_rate(const double *__restrict__ w, long nc, int N, double gamma, double dx,
-                                              unsigned long long *ratemax, int *__restrict__ flag) {
+                                              unsigned long long *ratemax, int *__restrict__ flag,
+                                              const double *__restrict__ gmax, double gk) {
   double m = 0.0;
   bool bad = false;
   for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < nc; cell += (long)gridDim.x * blockDim.x) {
     double U[D + 2];
 #pragma unroll
     for (int v = 0; v < D + 2; ++v) U[v] = w[(long)v * N * nc + cell];
-    m = fmax(m, cell_rate<D>(U, gamma, dx, bad));
+    m = fmax(m, cell_rate<D>(U, gamma, dx, bad, gk, gmax ? gmax[cell] : 0.0));
   }
   if (bad) atomicOr(flag, FLAG_NEGATIVE);
   m = block_max(m);
@@ -1253,6 +1295,32 @@ __global__ void k_dt_final(unsigned long long *ratemax, double cfl_fk, double *_
     }
     dt[0] = cfl_fk / __longlong_as_double((long long)m);
   }
+}
+
+// Gravity set-up: from the external acceleration a at the volume nodes
+// ([D][Q][ncell]) the source kernels' operand (dx/2) w_q a and, per cell, the
+// largest |a| over its nodes for the time step.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_grav_setup(const double *__restrict__ tab, const double *__restrict__ accel,
+                                                    long nc, double hdx, double *__restrict__ grav,
+                                                    double *__restrict__ gmax) {
+  using C = Cfg<D, K>;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nc) return;
+  double amax = 0.0;
+  for (int q = 0; q < C::Q; ++q) {
+    const double wq = hdx * tab[C::WQ + q];
+    double a2 = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const long i = (long)(a * C::Q + q) * nc + cell;
+      const double ga = accel[i];
+      a2 = fma(ga, ga, a2);
+      grav[i] = wq * ga;
+    }
+    amax = fmax(amax, sqrt(a2));
+  }
+  gmax[cell] = amax;
 }
 
 // Clears the rate slots (a kernel rather than a memset, so that the call can
@@ -2702,20 +2770,43 @@ struct StageLaunch {
     } else if constexpr (D == 2) {
       using T = dg::Tile2D<K>;
       dim3 grid((unsigned)(((c->nx + T::TX - 1) / T::TX) * ((c->ny + T::TY - 1) / T::TY)));
-      hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, out, dt,
-                         vext, make_grid(c), mode, mx, c->flag, ro);
+      dg::RateOp r2 = ro;
+      if (r2.op == dg::RATE_FOLD && c->gravity) {
+        r2.gmax = c->gmax;
+        r2.gk = c->grav_k;
+      }
+      if (c->gravity) {
+        if constexpr (sizeof(R) == sizeof(double)) {
+          hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, true>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w,
+                             out, dt, vext, make_grid(c), mode, mx, c->flag, r2, c->grav);
+        } else {
+          return DG_EUNSUPPORTED;
+        }
+      } else {
+        hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, out,
+                           dt, vext, make_grid(c), mode, mx, c->flag, r2, nullptr);
+      }
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
       // lane (at k = 2 the one-thread kernel, at one wave per SIMD, is twice
       // as fast as this one, whose rounds of four nodes waste a quarter of the
       // nine face nodes)
-      if (vext) return DG_EINVAL;
+      if (vext || c->gravity) return DG_EUNSUPPORTED;
       hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, true>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab,
                          w, out, dt, make_uniform_amr_grid(c), mode, mx, c->flag);
     } else {
-      hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr, w,
-                         out, dt, vext, make_grid(c), mode, mx, c->flag);
+      if (c->gravity) {
+        if constexpr (sizeof(R) == sizeof(double)) {
+          hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX, true>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab,
+                             tabr, w, out, dt, vext, make_grid(c), mode, mx, c->flag, c->grav);
+        } else {
+          return DG_EUNSUPPORTED;
+        }
+      } else {
+        hipLaunchKernelGGL((dg::k_rhs_stage<D, K, R, FX>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, tabr,
+                           w, out, dt, vext, make_grid(c), mode, mx, c->flag, nullptr);
+      }
     }
     HIP_TRY(hipGetLastError());
     return DG_OK;
@@ -2875,12 +2966,13 @@ int rate_fold(dg_ctx *c, const double *w, unsigned long long *rm, hipStream_t s)
       hipLaunchKernelGGL(dg::k_rate_amr<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, make_amr_grid(c), c->sh.N, rm,
                          c->flag);
   } else {
+    const double *gm = c->gravity ? c->gmax : nullptr;
     if (c->sh.d == 2)
       hipLaunchKernelGGL(dg::k_rate<2>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                         c->dx, rm, c->flag);
+                         c->dx, rm, c->flag, gm, c->grav_k);
     else
       hipLaunchKernelGGL(dg::k_rate<3>, dim3(c->npartial), dim3(kBlock), 0, s, w, c->ncell, c->sh.N, c->cfg.gamma,
-                         c->dx, rm, c->flag);
+                         c->dx, rm, c->flag, gm, c->grav_k);
   }
   HIP_TRY(hipGetLastError());
   return DG_OK;
@@ -2939,6 +3031,19 @@ dg::Mix rk3_mix(int stage, const double *wn) {
   }
   return m;
 }
+
+struct GravSetup {
+  dg_ctx *c;
+  const double *accel;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_grav_setup<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, accel, c->ncell,
+                       0.5 * c->dx, c->grav, c->gmax);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
 
 // Stage m of the configured tableau from the stage values y[0..m-1]: the
 // input is y[m-1]; earlier values with a nonzero weight are the extra terms.
@@ -3094,6 +3199,8 @@ void dg_destroy(dg_ctx *c) {
   if (c->vscratch) (void)hipFree(c->vscratch);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
+  if (c->grav) (void)hipFree(c->grav);
+  if (c->gmax) (void)hipFree(c->gmax);
   delete c;
 }
 
@@ -3261,16 +3368,47 @@ int dg_limit(dg_ctx *c, double *w, void *stream) {
   return dispatch(c, LimitLaunch{c, w, (hipStream_t)stream});
 }
 
+int dg_set_gravity(dg_ctx *c, const double *accel, void *stream) {
+  if (!c) return DG_EINVAL;
+  if (!accel) {
+    c->gravity = false;
+    return DG_OK;
+  }
+  // the source is fused into the FP64 one-lane and tile stage kernels
+  if (c->amr || c->cfg.precision != DG_FP64 || (c->sh.d == 3 && c->sh.k > 2)) return DG_EUNSUPPORTED;
+  const size_t n = (size_t)c->sh.d * c->sh.Q * c->ncell;
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->grav) {
+    hipError_t e = hipMalloc(&c->grav, n * sizeof(double));
+    if (e != hipSuccess) {
+      c->grav = nullptr;
+      return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP;
+    }
+  }
+  if (!c->gmax) {
+    hipError_t e = hipMalloc(&c->gmax, (size_t)c->ncell * sizeof(double));
+    if (e != hipSuccess) {
+      c->gmax = nullptr;
+      return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP;
+    }
+  }
+  const int st = dispatch(c, GravSetup{c, accel, (hipStream_t)stream});
+  if (st != DG_OK) return st;
+  c->gravity = true;
+  c->grav_k = c->cfl_fk * std::sqrt(2.0 * c->cfg.gamma * (c->cfg.gamma - 1.0));
+  return DG_OK;
+}
+
 int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {
   if (!c || !w || !lam || !mu || mu == w || mu == lam) return DG_EINVAL;
-  if (c->amr) return DG_EUNSUPPORTED;
+  if (c->amr || c->gravity) return DG_EUNSUPPORTED;
   return dispatch(c, AdjointLaunch{c, w, lam, nullptr, mu, nullptr, nullptr, 0, 0.0, 0.0, (hipStream_t)stream});
 }
 
 int dg_adjoint_rk_stage(dg_ctx *c, int stage, const double *dt, const double *u, const double *lam,
                         const double *acc, double *lam_out, double *acc_out, void *stream) {
   if (!c || !dt || !u || !lam || !lam_out || stage < 1 || stage > 3) return DG_EINVAL;
-  if (c->amr) return DG_EUNSUPPORTED;
+  if (c->amr || c->gravity) return DG_EUNSUPPORTED;
   if (lam_out == lam || lam_out == u || (acc && lam_out == acc)) return DG_EINVAL;
   if (stage != 3 && !acc) return DG_EINVAL;
   if (stage != 1 && !acc_out) return DG_EINVAL;
