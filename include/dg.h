@@ -64,7 +64,8 @@ typedef struct dg_ctx dg_ctx;
 /* Run description (all fields read by dg_init only). */
 typedef struct {
   int dim;            /* 2 or 3                                              */
-  int k;              /* polynomial degree, 1..3 (spatial order k+1)          */
+  int k;              /* polynomial degree, 1..3 (spatial order k+1); 4 on 2D
+                         grids without refinement in DG_FP64 or DG_FP32     */
   int n[3];           /* cells per axis (n[2] ignored in 2D)                  */
   double x0[3];       /* lower corner of the box                              */
   double len[3];      /* box edge lengths; cells must be cubes (len/n equal)  */
