@@ -13,7 +13,9 @@
  *   - time step .................. Sec. 2.5 (eq. time_step), Sec. 3.4
  *                                  (eq. time_step_pos)
  *   - SSP-RK3 .................... App. D (table RK_3)
- *   - limiters ................... Sec. 3.1, 3.3, 3.4
+ *   - limiters ................... Sec. 3.1, 3.2 (with App. E), 3.3, 3.4
+ *   - other Runge-Kutta methods .. App. D (tables butcher, RK_2, RK_4)
+ *   - gravity source and step .... Sec. 2.4 (eq. gravity_term), Sec. 2.5
  * and a hand-written discrete adjoint of the right-hand side and of the
  * SSP-RK3 stages (not part of the paper).
  *
