@@ -111,6 +111,8 @@ def _load():
             "orc_tableau_combine": [C.c_int, dp, dp, C.c_int, C.c_double, dp, dp, dp, C.c_long],
             "orc_tableau_stage": [cp, C.c_int, dp, dp, C.c_int, C.c_double, dp, dp],
             "orc_amr_tableau_stage": [cp, C.c_int, dp, dp, C.c_int, C.c_double, dp, dp],
+            "orc_amr_flags": [cp, dp, C.c_double, C.c_double, ip],
+            "orc_amr_regrid": [cp, dp, cp, dp],
         }.items():
             getattr(_lib, name).argtypes = args
             getattr(_lib, name).restype = C.c_int
@@ -170,6 +172,50 @@ def tableau_combine(A, b, m: int, dt: float, Y, L):
     L = np.ascontiguousarray(np.asarray(L, dtype=np.float64).ravel())
     out = np.zeros(L.size)
     _check(lib.orc_tableau_combine(s, A, b, m, dt, Ys, L, out, L.size), "tableau_combine")
+    return out
+
+
+def make(wl: dict):
+    """Oracle for a workload: with a refined box (refine_lo != refine_hi) or without."""
+    boxed = any(a != b for a, b in zip(wl.get("refine_lo", (0, 0, 0)), wl.get("refine_hi", (0, 0, 0))))
+    return AmrOracle(wl) if boxed else Oracle(wl)
+
+
+def amr_flags(wl: dict, w, wt: float = 0.01, alpha: float = 1.1) -> np.ndarray:
+    """Refinement flags (0/1) of the base cells (Sec. 4.1, eqs. cell_ref, node_ref)."""
+    lib, _ = _load()
+    o = make(wl)
+    flags = np.zeros(o.ncoarse if isinstance(o, AmrOracle) else o.ncell, dtype=np.int32)
+    _check(lib.orc_amr_flags(C.byref(o.c), o._s(w), wt, alpha, flags), "amr_flags")
+    return flags
+
+
+def box_from_flags(wl: dict, flags, layer: int = 1):
+    """(refine_lo, refine_hi) of the box around the flagged base cells grown by
+    `layer` cells (the buffer layer of Sec. 4), kept inside [1, n-1] per axis;
+    None when no cell is flagged."""
+    d = wl["dim"]
+    n = list(wl["n"][:d])
+    f = np.asarray(flags).reshape([wl["n"][2] if d == 3 else 1, wl["n"][1], wl["n"][0]])
+    idx = np.argwhere(f)
+    if idx.size == 0:
+        return None
+    lo, hi = [0, 0, 0], [0, 0, 0]
+    for a in range(d):
+        col = idx[:, 2 - a]
+        lo[a] = max(1, int(col.min()) - layer)
+        hi[a] = min(n[a] - 1, int(col.max()) + 1 + layer)
+        if hi[a] <= lo[a]:
+            return None
+    return tuple(lo), tuple(hi)
+
+
+def regrid(wl_old: dict, w_old, wl_new: dict) -> np.ndarray:
+    """State on wl_new's grid from a state on wl_old's (Sec. 4.2, 4.3)."""
+    lib, _ = _load()
+    a, b = make(wl_old), make(wl_new)
+    out = np.zeros(b.shape)
+    _check(lib.orc_amr_regrid(C.byref(a.c), a._s(w_old), C.byref(b.c), out), "amr_regrid")
     return out
 
 

@@ -36,6 +36,9 @@
  *   general explicit RK (tableau) ... App. D, table butcher, eqs. for w^{n+1}
  *                                     and rhs; tables RK_2, RK_4
  *   gravity source and time step .... Sec. 2.4 eq. gravity_term; Sec. 2.5
+ *   refinement criterion ............ Sec. 4.1 eqs. cell_ref, node_ref
+ *   refine / derefine projections ... Sec. 4.2 eqs. ref_pa_integral,
+ *                                     ref_weights; Sec. 4.3 eq. deref_weights
  * The HLLC Riemann solver is cited by the paper to Toro's textbook only; the
  * textbook HLLC with Einfeldt-Batten (Roe-averaged) wave-speed bounds is
  * used, with a Davis-bound option.
@@ -1683,12 +1686,12 @@ int orc_amr_limit(const orc_config *c, double *w) {
 /* (P_c)_{j,l} = 2^-d int phi_l((xi + c)/2) phi_j(xi) dxi: the L2 projection of
  * a coarse polynomial onto child c (eq. ref_pa_integral and App. F, with the
  * coarse basis at the mapped point).  Out: P[N][N] row-major. */
-int orc_refine_matrix(const orc_config *c, int child, double *P) {
-  ctx *X = malloc(sizeof(ctx));
-  int st = ctx_init(c, X);
-  if (st != ORC_OK) { free(X); return st; }
+/* Refinement matrix of child c (eq. ref_pa_integral): (P_c)_jl = 2^-d
+ * int over the reference cell of phi_j(xi) phi_l(child map of xi), with the
+ * (k+1)^d Gauss rule (exact: degree 2k per axis).  Child c has bit a set if
+ * it is the upper half along axis a. */
+static void refine_matrix(const ctx *X, int child, double *P) {
   int d = X->d;
-  if (child < 0 || child >= (1 << d)) { free(X); return ORC_EINVAL; }
   for (int j = 0; j < X->N; ++j)
     for (int l = 0; l < X->N; ++l) {
       double acc = 0.0;
@@ -1703,7 +1706,159 @@ int orc_refine_matrix(const orc_config *c, int child, double *P) {
       }
       P[j * X->N + l] = acc / (double)(1 << d);
     }
+}
+
+int orc_refine_matrix(const orc_config *c, int child, double *P) {
+  ctx *X = malloc(sizeof(ctx));
+  int st = ctx_init(c, X);
+  if (st != ORC_OK) { free(X); return st; }
+  if (child < 0 || child >= (1 << X->d)) { free(X); return ORC_EINVAL; }
+  refine_matrix(X, child, P);
   free(X);
+  return ORC_OK;
+}
+
+/* A configuration with or without a refined box: the base grid (the coarse
+ * block) and, if the box is non-empty, the box [lo, hi) and its fine block. */
+typedef struct {
+  ctx X;
+  int box, lo[3], hi[3];
+  long nf[3], ncf;
+} grid2;
+
+static int grid2_init(const orc_config *c, grid2 *G) {
+  int st = ctx_init(c, &G->X);
+  if (st != ORC_OK) return st;
+  G->box = 0;
+  G->ncf = 0;
+  for (int a = 0; a < 3; ++a) { G->lo[a] = c->refine_lo[a]; G->hi[a] = c->refine_hi[a]; G->nf[a] = 1; }
+  for (int a = 0; a < G->X.d; ++a)
+    if (G->lo[a] != G->hi[a]) G->box = 1;
+  if (G->box) {
+    amr *M = malloc(sizeof(amr));
+    st = amr_init(c, M); /* validates the box */
+    free(M);
+    if (st != ORC_OK) return st;
+    G->ncf = 1;
+    for (int a = 0; a < G->X.d; ++a) { G->nf[a] = 2L * (G->hi[a] - G->lo[a]); G->ncf *= G->nf[a]; }
+  }
+  return ORC_OK;
+}
+
+static int grid2_in_box(const grid2 *G, const long *i) {
+  if (!G->box) return 0;
+  for (int a = 0; a < G->X.d; ++a)
+    if (i[a] < G->lo[a] || i[a] >= G->hi[a]) return 0;
+  return 1;
+}
+
+static void cell_ijk(const ctx *X, long cell, long *i) {
+  i[0] = cell % X->nx; i[1] = (cell / X->nx) % X->ny; i[2] = cell / ((long)X->nx * X->ny);
+}
+
+/* flat index in the fine block of child c of base cell i */
+static long grid2_fine(const grid2 *G, const long *i, int c) {
+  long f[3] = {0, 0, 0};
+  for (int a = 0; a < G->X.d; ++a) f[a] = 2 * (i[a] - G->lo[a]) + ((c >> a) & 1);
+  return (f[2] * G->nf[1] + f[1]) * G->nf[0] + f[0];
+}
+
+/* coefficient (v, l) of a state of grid G: coarse cell or fine cell */
+#define WC(G, w, v, l, cell) (w)[((long)(v) * (G)->X.N + (l)) * (G)->X.ncell + (cell)]
+#define WF(G, w, v, l, f) (w)[(long)(G)->X.nvar * (G)->X.N * (G)->X.ncell + ((long)(v) * (G)->X.N + (l)) * (G)->ncf + (f)]
+
+/* Refinement flags per base cell (Sec. 4.1): a cell of the base grid is
+ * flagged if max_a |w_rho,1+a| > alpha w_t (eq. cell_ref; the density slope
+ * coefficients are the changes across the half-cell divided by sqrt(3)); a
+ * base cell that is refined now stays flagged if the same holds for its node
+ * weights, the derefined projection of its 2^d children (eq. deref_weights),
+ * against w_t / alpha (eq. node_ref). */
+int orc_amr_flags(const orc_config *c, const double *w, double wt, double alpha, int *flags) {
+  grid2 *G = malloc(sizeof(grid2));
+  int st = grid2_init(c, G);
+  if (st != ORC_OK) { free(G); return st; }
+  const ctx *X = &G->X;
+  int d = X->d, nc = 1 << d;
+  double *P = malloc(sizeof(double) * 8 * MAXN * MAXN);
+  for (int ch = 0; ch < nc; ++ch) refine_matrix(X, ch, P + (long)ch * MAXN * MAXN);
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    long i[3];
+    cell_ijk(X, cell, i);
+    double m = 0.0, bound;
+    if (grid2_in_box(G, i)) {
+      for (int a = 0; a < d; ++a) {
+        double node = 0.0; /* node weight of mode 1+a of the density */
+        for (int ch = 0; ch < nc; ++ch) {
+          long f = grid2_fine(G, i, ch);
+          for (int l = 0; l < X->N; ++l) node += P[(long)ch * MAXN * MAXN + l * X->N + (1 + a)] * WF(G, w, 0, l, f);
+        }
+        node /= (double)nc;
+        if (fabs(node) > m) m = fabs(node);
+      }
+      bound = wt / alpha;
+    } else {
+      for (int a = 0; a < d; ++a)
+        if (fabs(WC(G, w, 0, 1 + a, cell)) > m) m = fabs(WC(G, w, 0, 1 + a, cell));
+      bound = alpha * wt;
+    }
+    flags[cell] = m > bound;
+  }
+  free(P); free(G);
+  return ORC_OK;
+}
+
+/* New state on the grid of c_new from a state on the grid of c_old (same base
+ * grid, either with or without a box): a base cell that stays unrefined is
+ * copied; one that leaves the box takes the derefinement of its children
+ * (eq. deref_weights: w^K = 2^-d sum_c P_c^T w^c); a fine cell of a base cell
+ * already refined is copied, one of a newly refined base cell is the
+ * refinement of the coarse polynomial (eq. ref_weights: w^c = P_c w^K).
+ * Base cells inside the new box (the hole) are set to zero. */
+int orc_amr_regrid(const orc_config *c_old, const double *w_old, const orc_config *c_new, double *w_new) {
+  grid2 *A = malloc(sizeof(grid2)), *B = malloc(sizeof(grid2));
+  int st = grid2_init(c_old, A);
+  if (st == ORC_OK) st = grid2_init(c_new, B);
+  if (st == ORC_OK && (A->X.d != B->X.d || A->X.k != B->X.k || A->X.ncell != B->X.ncell)) st = ORC_EINVAL;
+  if (st != ORC_OK) { free(A); free(B); return st; }
+  const ctx *X = &A->X;
+  int d = X->d, nc = 1 << d, N = X->N, nv = X->nvar;
+  double *P = malloc(sizeof(double) * 8 * MAXN * MAXN);
+  for (int ch = 0; ch < nc; ++ch) refine_matrix(X, ch, P + (long)ch * MAXN * MAXN);
+  for (long cell = 0; cell < X->ncell; ++cell) {
+    long i[3];
+    cell_ijk(X, cell, i);
+    int in_old = grid2_in_box(A, i), in_new = grid2_in_box(B, i);
+    for (int v = 0; v < nv; ++v) {
+      if (in_new) {
+        for (int l = 0; l < N; ++l) WC(B, w_new, v, l, cell) = 0.0;
+        for (int ch = 0; ch < nc; ++ch) {
+          long fn = grid2_fine(B, i, ch);
+          if (in_old) {
+            long fo = grid2_fine(A, i, ch);
+            for (int l = 0; l < N; ++l) WF(B, w_new, v, l, fn) = WF(A, w_old, v, l, fo);
+          } else {
+            for (int j = 0; j < N; ++j) {
+              double acc = 0.0;
+              for (int l = 0; l < N; ++l) acc += P[(long)ch * MAXN * MAXN + j * N + l] * WC(A, w_old, v, l, cell);
+              WF(B, w_new, v, j, fn) = acc;
+            }
+          }
+        }
+      } else if (in_old) {
+        for (int j = 0; j < N; ++j) {
+          double acc = 0.0;
+          for (int ch = 0; ch < nc; ++ch) {
+            long fo = grid2_fine(A, i, ch);
+            for (int l = 0; l < N; ++l) acc += P[(long)ch * MAXN * MAXN + l * N + j] * WF(A, w_old, v, l, fo);
+          }
+          WC(B, w_new, v, j, cell) = acc / (double)nc;
+        }
+      } else {
+        for (int l = 0; l < N; ++l) WC(B, w_new, v, l, cell) = WC(A, w_old, v, l, cell);
+      }
+    }
+  }
+  free(P); free(A); free(B);
   return ORC_OK;
 }
 

@@ -22,6 +22,8 @@ Problem sources (the paper's validation section):
   * blast: a Sod-type spherical over-pressure region;
   * density wave: rho = 1 + 0.2 sin(2 pi (x + y)) advected at constant velocity
     and pressure;
+  * KH instability (2D): the sharp two-layer setup with a single-mode v_y
+    seed (Validation, KH instability);
   * cold Keplerian disc: a pressure-less ring on Keplerian orbits in a static
     softened central potential (Validation, Keplerian disc), with its
     external acceleration field (`acceleration`).
@@ -66,6 +68,11 @@ def sign_direction(seed: int, size: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 WORKLOADS: dict[str, dict] = {
+    # 2D KH instability on [0,1]^2 (sharp layers at y = 0.25, 0.75, single-mode
+    # v_y seed), DG-4 with RK_4, characteristic limiter + positivity, base grid
+    # 64^2 refined where the density slope is steep (w_t = 0.01, alpha = 1.1).
+    "kh2d": dict(dim=2, k=3, n=(64, 64, 1), x0=(0.0, 0.0, 0.0), length=(1.0, 1.0, 1.0), gamma=1.4, cfl=0.2,
+                 limiter=2, positivity=1, eps=1e-8, ic="kh2d", rk="rk4", t_end=0.8, wt=0.01, alpha=1.1),
     # 2D cold Keplerian disc on [0,6]^2, gamma 5/3, to t = 120 (about 20 orbits
     # at r = 1), DG-2 with the positivity limiter only and the central
     # potential's acceleration as the gravity source.
@@ -244,6 +251,12 @@ def primitives(wl: dict, x, y, z, cell=None, node=None, t: float = 0.0):
             rho = rho + c * x ** ex * y ** ey * z ** ez
         vel = wl.get("velocity", (0.7, -0.4, 0.3))
         return rho, zeros + vel[0], zeros + vel[1], zeros + vel[2], zeros + wl.get("pressure", 1.0)
+    if ic == "kh2d":
+        inner = (y > 0.25) & (y < 0.75)
+        sig = 0.05 / math.sqrt(2.0)
+        vy = 0.1 * np.sin(4.0 * math.pi * x) * (np.exp(-(y - 0.25) ** 2 / (2 * sig * sig))
+                                                + np.exp(-(y - 0.75) ** 2 / (2 * sig * sig)))
+        return np.where(inner, 2.0, 1.0), np.where(inner, 0.5, -0.5), vy, zeros, zeros + 2.5
     if ic == "kepler":
         # `kepler_params` may override the background values (rho0, p0)
         rho, vx, vy, p = _kepler_primitives(x, y, wl.get("kepler_params"))
