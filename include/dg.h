@@ -16,6 +16,8 @@
  *   - limiters ................... Sec. 3.1, 3.2 (with App. E), 3.3, 3.4
  *   - other Runge-Kutta methods .. App. D (tables butcher, RK_2, RK_4)
  *   - gravity source and step .... Sec. 2.4 (eq. gravity_term), Sec. 2.5
+ *   - adaptive refinement ........ Sec. 4.1-4.3 (eqs. cell_ref, node_ref,
+ *                                  ref_pa_integral, ref_weights, deref_weights)
  * and a hand-written discrete adjoint of the right-hand side and of the
  * SSP-RK3 stages (not part of the paper).
  *
@@ -227,6 +229,29 @@ int dg_tableau_step(dg_ctx *ctx, const double *w, double *const *stage, double *
  * with k = 3; dg_adjoint_rhs and dg_adjoint_rk_stage return DG_EUNSUPPORTED
  * while gravity is on. */
 int dg_set_gravity(dg_ctx *ctx, const double *accel, void *stream);
+
+/* Refinement criterion on the one-box mesh (Sec. 4.1): flags[b] = 1 for
+ * each base cell b that should be refined: an unrefined base cell if its
+ * largest density slope coefficient |w_rho,1+a| (the change across the half
+ * cell over sqrt(3)) exceeds alpha * wt (eq. cell_ref); a refined one if that
+ * of its node weights, the derefined projection of its children (eq.
+ * deref_weights), exceeds wt / alpha (eq. node_ref).  flags: device, one int
+ * per base cell (base-grid order, x fastest); box: device, 6 ints, receives
+ * the smallest and then the largest index per axis of the flagged cells
+ * (smallest > largest when none is flagged).  The paper's values are
+ * wt = 0.01, alpha = 1.1.  DG_EINVAL for wt <= 0 or alpha < 1. */
+int dg_amr_flags(dg_ctx *ctx, const double *w, double wt, double alpha, int *flags, int *box, void *stream);
+
+/* Moves a state between two meshes over the same base grid (same dim, k,
+ * cells, edge and origin; each with or without a refined box): a base cell
+ * that stays unrefined is copied, one that leaves the box is derefined from
+ * its children by L2 projection (Sec. 4.3 eq. deref_weights), the children
+ * of a newly refined base cell are the L2 projections of its polynomial
+ * (Sec. 4.2 eq. ref_weights), children present in both boxes are copied.
+ * Hole cells of the new mesh are set to zero.  Mass, momentum and energy
+ * are kept to rounding.  w_to must not alias w_from; DG_EINVAL for meshes
+ * that do not share the base grid. */
+int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *w_to, void *stream);
 
 /* Slope limiter (minmod with TVB bound, Sec. 3.3: component-wise on the
  * conserved variables, Sec. 3.1, or on the characteristic variables of the

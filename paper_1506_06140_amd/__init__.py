@@ -62,7 +62,7 @@ class dg_config(C.Structure):
 EXPORTS = (
     "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
     "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
-    "dg_set_gravity", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
+    "dg_set_gravity", "dg_amr_flags", "dg_amr_regrid", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
 )
 
 _lib = None
@@ -94,6 +94,8 @@ def load_library(path: str = LIB_PATH):
     lib.dg_tableau_step.argtypes = [ctxp, dp, C.POINTER(C.c_void_p), dp, dp, dp, vp]
     lib.dg_limit.argtypes = [ctxp, dp, vp]
     lib.dg_set_gravity.argtypes = [ctxp, dp, vp]
+    lib.dg_amr_flags.argtypes = [ctxp, dp, C.c_double, C.c_double, dp, dp, vp]
+    lib.dg_amr_regrid.argtypes = [ctxp, dp, ctxp, dp, vp]
     lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
     lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
     lib.dg_status.argtypes = [ctxp, vp]
@@ -303,6 +305,48 @@ class Solver:
         ptr = _ptr(accel, self.wl["dim"] * self.Q * self.ncell) if accel is not None else None
         _check(self.lib.dg_set_gravity(self.ctx, ptr, _stream(stream)), "dg_set_gravity")
         self.gravity = accel
+
+    # -- adaptive refinement of the one-box mesh ------------------------------
+    def amr_flags(self, w, wt=0.01, alpha=1.1, stream=None):
+        """(flags, box): device int32 flags per base cell (Sec. 4.1) and, on
+        the host, (smallest, largest) flagged index per axis, or None."""
+        import torch
+        nb = self.ncoarse if self.amr else self.ncell
+        flags = torch.empty(nb, dtype=torch.int32, device="cuda")
+        box = torch.empty(6, dtype=torch.int32, device="cuda")
+        _check(self.lib.dg_amr_flags(self.ctx, self._s(w), wt, alpha, flags.data_ptr(), box.data_ptr(),
+                                     _stream(stream)), "dg_amr_flags")
+        b = box.cpu().tolist()
+        d = self.wl["dim"]
+        if any(b[a] > b[3 + a] for a in range(d)):
+            return flags, None
+        return flags, (tuple(b[:3]), tuple(b[3:]))
+
+    def box_for(self, flagged, layer=1):
+        """refine_lo/refine_hi around the flagged range grown by `layer` cells
+        (the buffer layer of Sec. 4), inside [1, n-1]; None for no box."""
+        if flagged is None:
+            return None
+        d = self.wl["dim"]
+        lo, hi = [0, 0, 0], [0, 0, 0]
+        for a in range(d):
+            lo[a] = max(1, flagged[0][a] - layer)
+            hi[a] = min(self.wl["n"][a] - 1, flagged[1][a] + 1 + layer)
+            if hi[a] <= lo[a]:
+                return None
+        return tuple(lo), tuple(hi)
+
+    def regrid(self, w, box, precision=None, stream=None):
+        """(solver, state) on the same base grid with the refined box `box`
+        ((lo, hi), or None for none), the state moved by L2 projection."""
+        wl = dict(self.wl)
+        wl["refine_lo"], wl["refine_hi"] = box if box is not None else ((0, 0, 0), (0, 0, 0))
+        s = Solver(wl, precision or self.precision)
+        if self.rk == "custom":
+            raise ValueError("regrid keeps the named integrators only")
+        out = s.empty()
+        _check(self.lib.dg_amr_regrid(self.ctx, self._s(w), s.ctx, s._s(out), _stream(stream)), "dg_amr_regrid")
+        return s, out
 
     def tableau_stage(self, m, dt, ys, out=None, stream=None):
         """Stage value Y_m of the configured tableau from ys = [Y_0, .., Y_{m-1}] (unlimited)."""

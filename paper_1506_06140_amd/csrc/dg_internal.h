@@ -44,6 +44,7 @@ Layout make_layout(const Shape &s);
 
 // Host tables for (d, k); also returns the first GLL weight.
 std::vector<double> build_tables(const Shape &s, double *gll_w1);
+std::vector<double> refine_matrices(const Shape &s);  // [2^d][N][N] (eq. ref_pa_integral)
 
 // Exponent triples of the modes in the library's mode order.
 std::vector<int> mode_exponents(int d, int k);
@@ -84,4 +85,5 @@ struct dg_ctx {
   bool gravity = false;
   double *grav = nullptr, *gmax = nullptr;
   double grav_k = 0.0;
+  double *prmat = nullptr;  // refinement matrices on the device (dg_amr_flags, dg_amr_regrid)
 };

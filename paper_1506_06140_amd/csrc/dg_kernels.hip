@@ -2455,6 +2455,142 @@ __global__ __launch_bounds__(256) void k_rate_amr(const double *__restrict__ w, 
   if (threadIdx.x == 0) atomicMax(rate_slot(ratemax, blockIdx.x), (unsigned long long)__double_as_longlong(m));
 }
 
+// ---------------------------------------------------------------------------
+// Adaptive refinement of the one-box mesh (Sec. 4.1-4.3).  A mesh is a base
+// grid plus, optionally, one box [lo, hi) of base cells split 2^d ways; a
+// state holds the base block, then the fine block.
+// ---------------------------------------------------------------------------
+struct BoxGrid {
+  int n[3], lo[3], hi[3], nf[3];
+  long ncc, ncf;
+  int box;  // 0: no refined box
+};
+
+template <int D>
+__device__ inline bool bg_in_box(const BoxGrid &g, const int *i) {
+  if (!g.box) return false;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    if (i[a] < g.lo[a] || i[a] >= g.hi[a]) return false;
+  return true;
+}
+
+// fine-block index of child ch (bit a: upper half along a) of base cell i
+template <int D>
+__device__ inline long bg_fine(const BoxGrid &g, const int *i, int ch) {
+  int f[3] = {0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < D; ++a) f[a] = 2 * (i[a] - g.lo[a]) + ((ch >> a) & 1);
+  return ((long)f[2] * g.nf[1] + f[1]) * g.nf[0] + f[0];
+}
+
+// Refinement flags (eqs. cell_ref, node_ref): per base cell, the largest
+// density slope coefficient |w_rho,1+a| against thr_cell = alpha w_t, or for a
+// refined base cell that of its node weights (the derefined projection of
+// its children, eq. deref_weights) against thr_node = w_t / alpha.  Flagged
+// cells also widen box = (min i, max i) by atomics.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_amr_flags(const double *__restrict__ w, const double *__restrict__ P,
+                                                   BoxGrid g, double thr_cell, double thr_node, int *__restrict__ flags,
+                                                   int *__restrict__ box) {
+  constexpr int N = Cfg<D, K>::N, NCH = 1 << D;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.ncc) return;
+  int i[3] = {(int)(cell % g.n[0]), (int)((cell / g.n[0]) % g.n[1]), (int)(cell / ((long)g.n[0] * g.n[1]))};
+  double m = 0.0;
+  bool flag;
+  if (bg_in_box<D>(g, i)) {
+    const double *wf = w + (long)(D + 2) * N * g.ncc;  // fine block; density is variable 0
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double node = 0.0;
+      for (int ch = 0; ch < NCH; ++ch) {
+        const long f = bg_fine<D>(g, i, ch);
+        for (int l = 0; l < N; ++l) node = fma(P[((long)ch * N + l) * N + 1 + a], wf[(long)l * g.ncf + f], node);
+      }
+      m = fmax(m, fabs(node / (double)NCH));
+    }
+    flag = m > thr_node;
+  } else {
+#pragma unroll
+    for (int a = 0; a < D; ++a) m = fmax(m, fabs(w[(long)(1 + a) * g.ncc + cell]));
+    flag = m > thr_cell;
+  }
+  flags[cell] = flag ? 1 : 0;
+  if (flag) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      atomicMin(box + a, i[a]);
+      atomicMax(box + 3 + a, i[a]);
+    }
+  }
+}
+
+__global__ void k_box_init(int *box) {
+  if (threadIdx.x < 3) box[threadIdx.x] = 0x7fffffff;
+  else if (threadIdx.x < 6) box[threadIdx.x] = -1;
+}
+
+// State on mesh B from a state on mesh A (same base grid): one thread per
+// base cell of B, then per fine cell of B.  A base cell outside B's box is
+// copied, or derefined (eq. deref_weights) if it was in A's box; one inside
+// B's box is zeroed (a hole cell).  A fine cell of B is copied from A if its
+// base cell was refined in A, else it is the refinement (eq. ref_weights) of
+// the base cell's polynomial.
+template <int D, int K>
+__global__ __launch_bounds__(256) void k_amr_regrid(const double *__restrict__ wa, BoxGrid A,
+                                                    const double *__restrict__ P, double *__restrict__ wb,
+                                                    BoxGrid B) {
+  constexpr int NV = D + 2, N = Cfg<D, K>::N, NCH = 1 << D;
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= B.ncc + B.ncf) return;
+  const double *wa_f = wa + (long)NV * N * A.ncc;
+  double *wb_f = wb + (long)NV * N * B.ncc;
+  if (tid < B.ncc) {
+    const long cell = tid;
+    int i[3] = {(int)(cell % B.n[0]), (int)((cell / B.n[0]) % B.n[1]), (int)(cell / ((long)B.n[0] * B.n[1]))};
+    if (bg_in_box<D>(B, i)) {
+      for (int vl = 0; vl < NV * N; ++vl) wb[(long)vl * B.ncc + cell] = 0.0;
+    } else if (bg_in_box<D>(A, i)) {
+      long f[NCH];
+#pragma unroll
+      for (int ch = 0; ch < NCH; ++ch) f[ch] = bg_fine<D>(A, i, ch);
+      for (int v = 0; v < NV; ++v)
+        for (int j = 0; j < N; ++j) {
+          double acc = 0.0;
+#pragma unroll
+          for (int ch = 0; ch < NCH; ++ch)
+            for (int l = 0; l < N; ++l)
+              acc = fma(P[((long)ch * N + l) * N + j], wa_f[(long)(v * N + l) * A.ncf + f[ch]], acc);
+          wb[(long)(v * N + j) * B.ncc + cell] = acc / (double)NCH;
+        }
+    } else {
+      for (int vl = 0; vl < NV * N; ++vl) wb[(long)vl * B.ncc + cell] = wa[(long)vl * A.ncc + cell];
+    }
+    return;
+  }
+  const long f = tid - B.ncc;
+  const int fi[3] = {(int)(f % B.nf[0]), (int)((f / B.nf[0]) % B.nf[1]), (int)(f / ((long)B.nf[0] * B.nf[1]))};
+  int i[3] = {0, 0, 0}, ch = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    i[a] = B.lo[a] + fi[a] / 2;
+    ch |= (fi[a] & 1) << a;
+  }
+  if (bg_in_box<D>(A, i)) {
+    const long fo = bg_fine<D>(A, i, ch);
+    for (int vl = 0; vl < NV * N; ++vl) wb_f[(long)vl * B.ncf + f] = wa_f[(long)vl * A.ncf + fo];
+  } else {
+    const long cell = ((long)i[2] * A.n[1] + i[1]) * A.n[0] + i[0];
+    for (int v = 0; v < NV; ++v)
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < N; ++l) acc = fma(P[((long)ch * N + j) * N + l], wa[(long)(v * N + l) * A.ncc + cell], acc);
+        wb_f[(long)(v * N + j) * B.ncf + f] = acc;
+      }
+  }
+}
+
 // Limiters on the refined mesh: neighbour means across the refinement
 // boundary are the children's average (coarse side) or the coarse polynomial's
 // mean over the adjacent child (fine side); coarse cells facing the fine block
@@ -3045,6 +3181,73 @@ struct GravSetup {
   }
 };
 
+dg::BoxGrid box_grid(const dg_ctx *c) {
+  dg::BoxGrid g{};
+  g.n[0] = (int)c->nx;
+  g.n[1] = (int)c->ny;
+  g.n[2] = (int)c->nz;
+  for (int a = 0; a < 3; ++a) {
+    g.lo[a] = c->amr ? c->lo[a] : 0;
+    g.hi[a] = c->amr ? c->hi[a] : 0;
+    g.nf[a] = c->amr ? (int)c->nf[a] : 1;
+  }
+  g.ncc = c->amr ? c->ncc : c->ncell;
+  g.ncf = c->amr ? c->ncf : 0;
+  g.box = c->amr ? 1 : 0;
+  return g;
+}
+
+// the refinement matrices on the device (allocated on first use)
+int ensure_prmat(dg_ctx *c) {
+  if (c->prmat) return DG_OK;
+  const std::vector<double> P = dg::refine_matrices(c->sh);
+  HIP_TRY(hipSetDevice(c->device));
+  double *d = nullptr;
+  hipError_t e = hipMalloc(&d, P.size() * sizeof(double));
+  if (e != hipSuccess) return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP;
+  e = hipMemcpy(d, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return hip_fail(e);
+  }
+  c->prmat = d;
+  return DG_OK;
+}
+
+struct AmrFlagsLaunch {
+  dg_ctx *c;
+  const double *w;
+  double thr_cell, thr_node;
+  int *flags, *box;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    const dg::BoxGrid g = box_grid(c);
+    hipLaunchKernelGGL(dg::k_box_init, dim3(1), dim3(64), 0, s, box);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL((dg::k_amr_flags<D, K>), dim3(nblocks(g.ncc)), dim3(kBlock), 0, s, w, c->prmat, g, thr_cell,
+                       thr_node, flags, box);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+struct AmrRegridLaunch {
+  const dg_ctx *a;
+  const double *wa;
+  dg_ctx *b;
+  double *wb;
+  hipStream_t s;
+  template <int D, int K>
+  int run() {
+    const dg::BoxGrid ga = box_grid(a), gb = box_grid(b);
+    hipLaunchKernelGGL((dg::k_amr_regrid<D, K>), dim3(nblocks(gb.ncc + gb.ncf)), dim3(kBlock), 0, s, wa, ga,
+                       b->prmat, wb, gb);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
 // Stage m of the configured tableau from the stage values y[0..m-1]: the
 // input is y[m-1]; earlier values with a nonzero weight are the extra terms.
 dg::Mix tableau_mix(const dg_ctx *c, int m, const double *const *y) {
@@ -3201,6 +3404,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->flag) (void)hipFree(c->flag);
   if (c->grav) (void)hipFree(c->grav);
   if (c->gmax) (void)hipFree(c->gmax);
+  if (c->prmat) (void)hipFree(c->prmat);
   delete c;
 }
 
@@ -3397,6 +3601,27 @@ int dg_set_gravity(dg_ctx *c, const double *accel, void *stream) {
   c->gravity = true;
   c->grav_k = c->cfl_fk * std::sqrt(2.0 * c->cfg.gamma * (c->cfg.gamma - 1.0));
   return DG_OK;
+}
+
+int dg_amr_flags(dg_ctx *c, const double *w, double wt, double alpha, int *flags, int *box, void *stream) {
+  if (!c || !w || !flags || !box || !(wt > 0.0) || !(alpha >= 1.0)) return DG_EINVAL;
+  if (c->sh.k > 3) return DG_EUNSUPPORTED;
+  const int st = ensure_prmat(c);
+  if (st != DG_OK) return st;
+  return dispatch(c, AmrFlagsLaunch{c, w, alpha * wt, wt / alpha, flags, box, (hipStream_t)stream});
+}
+
+int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *w_to, void *stream) {
+  if (!from || !to || !w_from || !w_to || w_from == w_to) return DG_EINVAL;
+  if (from->sh.d != to->sh.d || from->sh.k != to->sh.k || from->nx != to->nx || from->ny != to->ny ||
+      from->nz != to->nz || from->dx != to->dx || from->device != to->device)
+    return DG_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (from->cfg.x0[a] != to->cfg.x0[a]) return DG_EINVAL;
+  if (to->sh.k > 3) return DG_EUNSUPPORTED;
+  const int st = ensure_prmat(to);
+  if (st != DG_OK) return st;
+  return dispatch(to, AmrRegridLaunch{from, w_from, to, w_to, (hipStream_t)stream});
 }
 
 int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {

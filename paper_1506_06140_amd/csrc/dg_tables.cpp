@@ -254,4 +254,38 @@ std::vector<double> build_tables(const Shape &s, double *gll_w1) {
   return t;
 }
 
+// Refinement matrices (eq. ref_pa_integral): P[c][j][l] is the coefficient of
+// phi_j on child c of the coarse phi_l, i.e. 2^-d times the Gauss integral of
+// phi_j(xi) phi_l((xi + s_c) / 2) over the reference cell, s_c the child's
+// offset (+1 where bit a of c is set, else -1); exact at (k+1)^d nodes.
+std::vector<double> refine_matrices(const Shape &s) {
+  std::vector<int> e = mode_exponents(s.d, s.k);
+  double gx[16], gw[16];
+  gauss_legendre(s.n1, gx, gw);
+  auto basis = [&](int l, const double *xi) {
+    double v = 1.0;
+    for (int a = 0; a < s.d; ++a) v *= pt(e[3 * l + a], xi[a]);
+    return v;
+  };
+  const int nch = 1 << s.d;
+  std::vector<double> P((size_t)nch * s.N * s.N, 0.0);
+  for (int q = 0; q < s.Q; ++q) {
+    int idx[3] = {q % s.n1, (q / s.n1) % s.n1, q / (s.n1 * s.n1)};
+    double xi[3] = {0.0, 0.0, 0.0}, wq = 1.0;
+    for (int a = 0; a < s.d; ++a) {
+      xi[a] = gx[idx[a]];
+      wq *= gw[idx[a]];
+    }
+    for (int ch = 0; ch < nch; ++ch) {
+      double xm[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < s.d; ++a) xm[a] = 0.5 * (xi[a] + (((ch >> a) & 1) ? 1.0 : -1.0));
+      for (int j = 0; j < s.N; ++j) {
+        const double pj = basis(j, xi) * wq / (double)nch;
+        for (int l = 0; l < s.N; ++l) P[((size_t)ch * s.N + j) * s.N + l] += pj * basis(l, xm);
+      }
+    }
+  }
+  return P;
+}
+
 }  // namespace dg
