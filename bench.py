@@ -219,6 +219,48 @@ def variants():
                                      "alu_peak_tflops": peak}
             del s
             torch.cuda.empty_cache()
+    # adaptive KH (2D, 64^2 base, DG-4 with RK_4, characteristic limiter and
+    # positivity): every 10 steps the flags (w_t = 0.01, alpha = 1.1), the box
+    # around them with one buffer layer and, if it changed, the regrid
+    wl = workloads.workload("kh2d")
+    s = dg.Solver(wl)
+    w = build_state(s, wl)
+    s.limit(w)
+    nsteps, every = 200, 10
+    t_step = t_adapt = 0.0
+    dof_stages = 0
+    regrids = 0
+    box = None
+    for i in range(nsteps):
+        if i % every == 0:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rng = s.amr_flags(w, wl["wt"], wl["alpha"])
+            nb = s.box_for(rng)
+            if nb != box or i == 0:
+                if nb != box:
+                    s, w = s.regrid(w, nb)
+                    regrids += 1
+                    box = nb
+                stage_bufs = [s.empty() for _ in range(s.stages - 1)]
+                other, dtb, rate = s.empty(), s.scalar(), s.rate_state()
+                s.max_rate(w, rate)
+            torch.cuda.synchronize()
+            t_adapt += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        nxt = s.rk_step(w, stage_bufs + [other], dtb, rate)
+        w, other = nxt, w
+        torch.cuda.synchronize()
+        t_step += time.perf_counter() - t0
+        cells = (s.ncoarse - s.nhole + s.nfine) if s.amr else s.ncell
+        dof_stages += cells * s.N * s.stages
+    st = s.status()
+    out_box = {"lo": list(box[0]), "hi": list(box[1])} if box else None
+    out["kh2d_adaptive_fp64"] = {"steps": nsteps, "regrid_every": every, "regrids": regrids, "final_box": out_box,
+                                 "ms_per_step": t_step / nsteps * 1e3, "dof_updates_per_s": dof_stages / t_step,
+                                 "adapt_ms_per_check": t_adapt / (nsteps // every) * 1e3, "status": st}
+    del s
+    torch.cuda.empty_cache()
     # adjoint: 512^2, k=3, J = int rho^2 after 400 steps at fixed dt, checkpoint 20
     wl = workloads.workload("vortex_adjoint")
     s = dg.Solver(wl)
