@@ -95,7 +95,12 @@ typedef struct {
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton
  * iteration, App. B; GLL nodes, App. C; scaled Legendre values, App. A),
  * copies them to the current device and allocates scratch.  Host-to-device
- * copies happen here only.  *out receives the context. */
+ * copies happen here only.  *out receives the context.  On 2D grids without
+ * refinement the stage kernel works on tiles of 16 x 16 (k <= 2) or 16 x 8
+ * cells, or on 8 x 8 tiles when the grid has fewer large tiles than the GPU
+ * has compute units; the environment variable DG_TILE2D_SMALL = 0 or 1, read
+ * here, forces the large or the small tiles (results are the same to
+ * rounding). */
 int dg_init(const dg_config *cfg, dg_ctx **out);
 
 /* Number of doubles in one state array (nvar * N * cells). */

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <new>
 #include <type_traits>
 
@@ -695,8 +696,13 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
 // A face on a tile boundary is evaluated by both tiles with identical code
 // and inputs, so the two cells receive bitwise-opposite contributions.
 // ---------------------------------------------------------------------------
-template <int K>
-struct Tile2D;
+// TS = 1: 8x8 tiles for grids with fewer large tiles than compute units, so
+// that a small grid still spreads over many CUs (its stage time is the tile's
+// latency, not the chip's throughput)
+template <int K, int TS = 0>
+struct Tile2D {
+  static constexpr int TX = 8, TY = 8;
+};
 #ifndef DG_TILE2D_TY2
 #define DG_TILE2D_TY2 16
 #endif
@@ -704,13 +710,13 @@ struct Tile2D;
 #define DG_TILE2D_TY3 8
 #endif
 template <>
-struct Tile2D<1> { static constexpr int TX = 16, TY = 16; };
+struct Tile2D<1, 0> { static constexpr int TX = 16, TY = 16; };
 template <>
-struct Tile2D<2> { static constexpr int TX = 16, TY = DG_TILE2D_TY2; };
+struct Tile2D<2, 0> { static constexpr int TX = 16, TY = DG_TILE2D_TY2; };
 template <>
-struct Tile2D<3> { static constexpr int TX = 16, TY = DG_TILE2D_TY3; };
+struct Tile2D<3, 0> { static constexpr int TX = 16, TY = DG_TILE2D_TY3; };
 template <>
-struct Tile2D<4> { static constexpr int TX = 16, TY = 8; };
+struct Tile2D<4, 0> { static constexpr int TX = 16, TY = 8; };
 
 // Exchange of a value with the lane `sub ^ 1` or `sub ^ 2` of the same quad
 // (DPP quad permutation, no LDS traffic).
@@ -733,8 +739,8 @@ __device__ inline double quad_from(double x) {
   return quad_swap<J | (J << 2) | (J << 4) | (J << 6)>(x);
 }
 
-template <int K, class R, int FX, bool GRAV = false>
-__global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2d(
+template <int K, class R, int FX, bool GRAV = false, int TS = 0>
+__global__ __launch_bounds__((4 * Tile2D<K, TS>::TX * Tile2D<K, TS>::TY)) void k_rhs_tile2d(
     const double *__restrict__ tab, const R *__restrict__ tabr, const double *__restrict__ w,
     double *__restrict__ out, const double *__restrict__ dtp, const float *__restrict__ vext, Grid g, int mode,
     Mix mx, int *__restrict__ flag, RateOp ro, const double *__restrict__ grav) {
@@ -746,7 +752,7 @@ __global__ __launch_bounds__(4 * Tile2D<K>::TX * Tile2D<K>::TY) void k_rhs_tile2
   // zeroes the slots; RATE_FOLD folds the signal rate of the new cell means
   // into them.
   using C = Cfg<2, K>;
-  constexpr int TX = Tile2D<K>::TX, TY = Tile2D<K>::TY, NCELL = TX * TY, NT = 4 * NCELL;
+  constexpr int TX = Tile2D<K, TS>::TX, TY = Tile2D<K, TS>::TY, NCELL = TX * TY, NT = 4 * NCELL;
   constexpr int NV = C::NV, N = C::N, QF = C::QF, Q = C::Q, NW = NV * N;
   static_assert(NV == 4, "four lanes per cell carry the four 2D variables");
   constexpr int HX = TX + 2, HY = TY + 2, HC = HX * HY;
@@ -2785,6 +2791,8 @@ using dg::Cfg;
 namespace {
 
 constexpr int kBlock = 256;
+// a 2D grid with fewer large tiles than this (the CU count) runs 8x8 tiles
+constexpr long kSmallTileBelow = 256;
 
 thread_local char g_hip_msg[256];
 
@@ -2918,6 +2926,11 @@ struct StageLaunch {
         } else {
           return DG_EUNSUPPORTED;
         }
+      } else if (c->tile_small == 1 || (c->tile_small < 0 && (long)grid.x < kSmallTileBelow)) {
+        using T1 = dg::Tile2D<K, 1>;
+        dim3 grid1((unsigned)(((c->nx + T1::TX - 1) / T1::TX) * ((c->ny + T1::TY - 1) / T1::TY)));
+        hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, false, 1>), grid1, dim3(4 * T1::TX * T1::TY), 0, s, c->tab,
+                           tabr, w, out, dt, vext, make_grid(c), mode, mx, c->flag, r2, nullptr);
       } else {
         hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, out,
                            dt, vext, make_grid(c), mode, mx, c->flag, r2, nullptr);
@@ -3348,6 +3361,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   double fk = 1.0 / (2.0 * cfg->k + 1.0);
   if (cfg->positivity && c->gll_w1 / 2.0 < fk) fk = c->gll_w1 / 2.0;
   c->cfl_fk = cfg->cfl * fk;
+  if (const char *ts = std::getenv("DG_TILE2D_SMALL")) c->tile_small = (ts[0] == '1') ? 1 : (ts[0] == '0') ? 0 : -1;
   {
     static const double a3[9] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.25, 0.25, 0.0};
     static const double b3[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};

@@ -1,0 +1,69 @@
+"""GPU: both tile sizes of the 2D stage kernel (16-wide tiles, and the 8 x 8
+tiles small grids get) against the FP64 oracle on ragged grids: the RHS to
+1e-12 of fac(|V| + |S|), three one-call steps to relative L1 1e-12 and dt to
+1e-14, for k = 1..4, with the limiters and with transmissive walls."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+CASES = [
+    ("vortex_k1_33x17", dict(name="vortex", k=1, n=(33, 17, 1), length=(11.0, 17 / 3, 1.0))),
+    ("vortex_k2_40x24", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0))),
+    ("vortex_k3_20x18", dict(name="vortex", k=3, n=(20, 18, 1), length=(10.0, 9.0, 1.0))),
+    ("vortex_k4_37x21", dict(name="vortex", k=4, n=(37, 21, 1), length=(37 / 3.6, 21 / 3.6, 1.0))),
+    ("sod_char_davis", dict(name="sod", n=(40, 4, 1), length=(1.0, 0.1, 1.0), flux=1, eps=1e-3, limiter=2)),
+]
+
+
+@pytest.mark.parametrize("tiles", ["0", "1"])
+@pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
+def test_tile_sizes_match_oracle(case, spec, tiles, monkeypatch):
+    import paper_1506_06140_amd as dg
+    monkeypatch.setenv("DG_TILE2D_SMALL", tiles)
+    print("tiles", case, tiles, flush=True)
+    spec = dict(spec)
+    wl = workloads.workload(spec.pop("name"), **spec)
+    o = oracle.Oracle(wl)
+    w0 = o.initial_state()
+    if wl["limiter"] or wl["positivity"]:
+        w0, st = o.limit(w0)
+        assert st == 0
+    s = dg.Solver(wl)
+    L = _host(s.rhs(_dev(w0))).reshape(o.nvar, -1)
+    V, S = o.terms_cells(w0)
+    V, S = V.reshape(o.nvar, -1), S.reshape(o.nvar, -1)
+    err = np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
+    assert np.all(err <= TOL), err
+    fb = [s.empty() for _ in range(s.stages)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    ref = w0
+    for i in range(3):
+        ref, dt_ref = o.step(ref)
+        w = s.rk_step(w, fb, dt, rate).clone()
+        assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
+        g, r = _host(w).reshape(o.nvar, -1), ref.reshape(o.nvar, -1)
+        norm = np.abs(r).sum(axis=1)
+        e = np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
+        print(case, tiles, "step", i, e, flush=True)
+        assert np.all(e <= TOL), (i, e)
+    assert s.status() == 0
