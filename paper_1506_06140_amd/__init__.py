@@ -339,11 +339,11 @@ class Solver:
     def regrid(self, w, box, precision=None, stream=None):
         """(solver, state) on the same base grid with the refined box `box`
         ((lo, hi), or None for none), the state moved by L2 projection."""
+        if self.rk == "custom":
+            raise ValueError("regrid keeps the named integrators only")
         wl = dict(self.wl)
         wl["refine_lo"], wl["refine_hi"] = box if box is not None else ((0, 0, 0), (0, 0, 0))
         s = Solver(wl, precision or self.precision)
-        if self.rk == "custom":
-            raise ValueError("regrid keeps the named integrators only")
         out = s.empty()
         _check(self.lib.dg_amr_regrid(self.ctx, self._s(w), s.ctx, s._s(out), _stream(stream)), "dg_amr_regrid")
         return s, out
