@@ -1425,14 +1425,14 @@ struct CharBasis {
 // s (0 low, 1 high) in direction a.  A mean without a real sound speed is
 // left alone (the positivity pass flags it).
 template <int D, int N, class NbMean>
-__device__ inline void char_limit_cell(double (&wc)[D + 2][N], NbMean &&nbmean, double gamma, double beta,
+__device__ inline bool char_limit_cell(double (&wc)[D + 2][N], NbMean &&nbmean, double gamma, double beta,
                                        double bound) {
   constexpr int NV = D + 2;
   double U[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) U[v] = wc[v][0];
   CharBasis<D> e;
-  if (!e.init(U, gamma)) return;
+  if (!e.init(U, gamma)) return false;
   const double r3 = sqrt(3.0);
   double ct[D][NV];
   bool limited = false;
@@ -1461,7 +1461,7 @@ __device__ inline void char_limit_cell(double (&wc)[D + 2][N], NbMean &&nbmean, 
   dir(std::integral_constant<int, 0>{});
   dir(std::integral_constant<int, 1>{});
   if constexpr (D == 3) dir(std::integral_constant<int, 2>{});
-  if (!limited) return;
+  if (!limited) return false;
   auto back = [&](auto A_) {
     constexpr int A = decltype(A_)::value;
     double x[NV];
@@ -1476,6 +1476,7 @@ __device__ inline void char_limit_cell(double (&wc)[D + 2][N], NbMean &&nbmean, 
   for (int v = 0; v < NV; ++v)
 #pragma unroll
     for (int l = D + 1; l < N; ++l) wc[v][l] = 0.0;
+  return true;
 }
 
 // Root in [0,1] of (E(t) - eps/(g-1)) rho(t) - |m(t)|^2/2 = 0 along
@@ -1533,11 +1534,18 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
   const int ix = (int)(cell % g.nx);
   const int iy = (int)((cell / g.nx) % g.ny);
   const int iz = (int)(cell / ((long)g.nx * g.ny));
+  // the slope pass needs the means and slopes only: the higher modes are
+  // loaded after it (and not at all where it dropped them), which keeps the
+  // two register sets from being live together
+  constexpr int NL = D + 1 < C::N ? D + 1 : C::N;
   double wc[C::NV][C::N];
+  bool dropped[C::NV];
 #pragma unroll
-  for (int v = 0; v < C::NV; ++v)
+  for (int v = 0; v < C::NV; ++v) {
+    dropped[v] = false;
 #pragma unroll
-    for (int l = 0; l < C::N; ++l) wc[v][l] = w[(long)(v * C::N + l) * nc + cell];
+    for (int l = 0; l < NL; ++l) wc[v][l] = w[(long)(v * C::N + l) * nc + cell];
+  }
 
   if (slope && K >= 1) {
     const double r3 = sqrt(3.0);
@@ -1555,7 +1563,9 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
 #pragma unroll
         for (int v = 0; v < C::NV; ++v) m[v] = w[(long)(v * C::N) * nc + nb];
       };
-      char_limit_cell<D, C::N>(wc, nbmean, g.gamma, beta, bound);
+      const bool lim = char_limit_cell<D, C::N>(wc, nbmean, g.gamma, beta, bound);
+#pragma unroll
+      for (int v = 0; v < C::NV; ++v) dropped[v] = lim;
     } else
 #pragma unroll
     for (int i = 0; i < C::NV; ++i) {
@@ -1574,11 +1584,15 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
       if (limited) {
 #pragma unroll
         for (int a = 0; a < D; ++a) wc[i][1 + a] = mt[a] / r3;
-#pragma unroll
-        for (int l = D + 1; l < C::N; ++l) wc[i][l] = 0.0;
       }
+      dropped[i] = limited;
     }
   }
+  // the higher modes: zero where the slope pass dropped them
+#pragma unroll
+  for (int v = 0; v < C::NV; ++v)
+#pragma unroll
+    for (int l = NL; l < C::N; ++l) wc[v][l] = dropped[v] ? 0.0 : w[(long)(v * C::N + l) * nc + cell];
 
   if (posit) {
     double Ub[C::NV];
@@ -2617,11 +2631,16 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
   const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
   int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
   if (!fine && amr_in_hole<D>(g, i)) return;
+  // means and slopes first; the higher modes after the slope pass (as in k_limit)
+  constexpr int NL = D + 1 < N ? D + 1 : N;
   double wc[NV][N];
+  bool dropped[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NV; ++v) {
+    dropped[v] = false;
 #pragma unroll
-    for (int l = 0; l < N; ++l) wc[v][l] = wb[(long)(v * N + l) * ncb + cell];
+    for (int l = 0; l < NL; ++l) wc[v][l] = wb[(long)(v * N + l) * ncb + cell];
+  }
   // neighbour means [2D][NV]
   double nbm[2 * D][NV];
   bool hang[2 * D];
@@ -2687,7 +2706,9 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 #pragma unroll
         for (int v = 0; v < NV; ++v) m[v] = nbm[2 * a + s][v];
       };
-      char_limit_cell<D, N>(wc, nbmean, g.gamma, beta, bound);
+      const bool lim = char_limit_cell<D, N>(wc, nbmean, g.gamma, beta, bound);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) dropped[v] = lim;
     } else
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -2705,11 +2726,14 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
       if (limited) {
 #pragma unroll
         for (int a = 0; a < D; ++a) wc[v][1 + a] = mt[a] / r3;
-#pragma unroll
-        for (int l = D + 1; l < N; ++l) wc[v][l] = 0.0;
       }
+      dropped[v] = limited;
     }
   }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = NL; l < N; ++l) wc[v][l] = dropped[v] ? 0.0 : wb[(long)(v * N + l) * ncb + cell];
   if (posit) {
     double Ub[NV];
 #pragma unroll
