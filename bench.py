@@ -408,7 +408,7 @@ def main():
                    "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(graph)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_rhs_tile2d<2,double>", "kernel_ms": k_ms,
+                     "kernel": "k_rhs_tile2d<2,double> (8x8 tiles)", "kernel_ms": k_ms,
                      "alg_bytes_per_launch": alg_bytes},
         # the same launch against the FP64 vector peak (algorithmic flops)
         "roofline_fp64": {"bound": "alu", "achieved": alg_flops / (k_ms * 1e-3) / 1e12,

@@ -96,10 +96,11 @@ typedef struct {
  * iteration, App. B; GLL nodes, App. C; scaled Legendre values, App. A),
  * copies them to the current device and allocates scratch.  Host-to-device
  * copies happen here only.  *out receives the context.  On 2D grids without
- * refinement the stage kernel works on tiles of 16 x 16 (k <= 2) or 16 x 8
- * cells, or on 8 x 8 tiles when the grid has fewer large tiles than the GPU
- * has compute units; the environment variable DG_TILE2D_SMALL = 0 or 1, read
- * here, forces the large or the small tiles (results are the same to
+ * refinement the stage kernel works on tiles of 8 x 8 cells for k <= 3; at
+ * k = 4 on tiles of 16 x 8 cells, or of 8 x 8 when the grid has fewer 16 x 8
+ * tiles than the GPU has compute units.  The environment variable
+ * DG_TILE2D_SMALL = 0 or 1, read here, forces the large tiles (16 x 16 for
+ * k <= 2, 16 x 8 for k = 3, 4) or the 8 x 8 tiles (results are the same to
  * rounding). */
 int dg_init(const dg_config *cfg, dg_ctx **out);
 

@@ -696,9 +696,11 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
 // A face on a tile boundary is evaluated by both tiles with identical code
 // and inputs, so the two cells receive bitwise-opposite contributions.
 // ---------------------------------------------------------------------------
-// TS = 1: 8x8 tiles for grids with fewer large tiles than compute units, so
-// that a small grid still spreads over many CUs (its stage time is the tile's
-// latency, not the chip's throughput)
+// TS = 1: 8x8 tiles (256 threads).  Four such work-groups fit a CU (LDS
+// 35 KB each at k = 2), and once they drift apart the load, compute and
+// store phases of different tiles overlap, which one 1024-thread work-group
+// per CU cannot do; a small grid also spreads over more CUs.
+// TS = 0: 16x16 or 16x8 tiles (see tile2d_small for which runs when).
 template <int K, int TS = 0>
 struct Tile2D {
   static constexpr int TX = 8, TY = 8;
@@ -717,6 +719,16 @@ template <>
 struct Tile2D<3, 0> { static constexpr int TX = 16, TY = DG_TILE2D_TY3; };
 template <>
 struct Tile2D<4, 0> { static constexpr int TX = 16, TY = 8; };
+
+// Whether a stage runs on 8x8 tiles: always for k <= 3 (faster at every grid
+// size measured, 256^2 to 1024^2); at k = 4 an 8x8 tile holds only two
+// work-groups per CU, so the 16x8 tiles run unless the grid has fewer of
+// them than the GPU has CUs.  force = 0 or 1 overrides the choice.
+constexpr long kCusPerGpu = 256;
+inline bool tile2d_small(int k, long large_tiles, int force) {
+  if (force >= 0) return force == 1;
+  return k <= 3 || large_tiles < kCusPerGpu;
+}
 
 // Exchange of a value with the lane `sub ^ 1` or `sub ^ 2` of the same quad
 // (DPP quad permutation, no LDS traffic).
@@ -2815,8 +2827,6 @@ using dg::Cfg;
 namespace {
 
 constexpr int kBlock = 256;
-// a 2D grid with fewer large tiles than this (the CU count) runs 8x8 tiles
-constexpr long kSmallTileBelow = 256;
 
 thread_local char g_hip_msg[256];
 
@@ -2943,16 +2953,21 @@ struct StageLaunch {
         r2.gmax = c->gmax;
         r2.gk = c->grav_k;
       }
+      const bool small = dg::tile2d_small(K, (long)grid.x, c->tile_small);
+      using T1 = dg::Tile2D<K, 1>;
+      const dim3 grid1((unsigned)(((c->nx + T1::TX - 1) / T1::TX) * ((c->ny + T1::TY - 1) / T1::TY)));
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
-          hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, true>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w,
-                             out, dt, vext, make_grid(c), mode, mx, c->flag, r2, c->grav);
+          if (small)
+            hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, true, 1>), grid1, dim3(4 * T1::TX * T1::TY), 0, s, c->tab,
+                               tabr, w, out, dt, vext, make_grid(c), mode, mx, c->flag, r2, c->grav);
+          else
+            hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, true>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr,
+                               w, out, dt, vext, make_grid(c), mode, mx, c->flag, r2, c->grav);
         } else {
           return DG_EUNSUPPORTED;
         }
-      } else if (c->tile_small == 1 || (c->tile_small < 0 && (long)grid.x < kSmallTileBelow)) {
-        using T1 = dg::Tile2D<K, 1>;
-        dim3 grid1((unsigned)(((c->nx + T1::TX - 1) / T1::TX) * ((c->ny + T1::TY - 1) / T1::TY)));
+      } else if (small) {
         hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX, false, 1>), grid1, dim3(4 * T1::TX * T1::TY), 0, s, c->tab,
                            tabr, w, out, dt, vext, make_grid(c), mode, mx, c->flag, r2, nullptr);
       } else {

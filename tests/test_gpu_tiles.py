@@ -1,7 +1,8 @@
-"""GPU: both tile sizes of the 2D stage kernel (16-wide tiles, and the 8 x 8
-tiles small grids get) against the FP64 oracle on ragged grids: the RHS to
-1e-12 of fac(|V| + |S|), three one-call steps to relative L1 1e-12 and dt to
-1e-14, for k = 1..4, with the limiters and with transmissive walls."""
+"""GPU: both tile sizes of the 2D stage kernel (the 8 x 8 tiles, and the
+16-wide tiles that k = 4 runs on large grids), each forced in turn, against
+the FP64 oracle on ragged grids: the RHS to 1e-12 of fac(|V| + |S|), three
+one-call steps to relative L1 1e-12 and dt to 1e-14, for k = 1..4, with the
+limiters and with transmissive walls."""
 import os
 import sys
 
@@ -64,6 +65,50 @@ def test_tile_sizes_match_oracle(case, spec, tiles, monkeypatch):
         g, r = _host(w).reshape(o.nvar, -1), ref.reshape(o.nvar, -1)
         norm = np.abs(r).sum(axis=1)
         e = np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
+        print(case, tiles, "step", i, e, flush=True)
+        assert np.all(e <= TOL), (i, e)
+    assert s.status() == 0
+
+
+GRAV_CASES = [
+    ("kepler_k1_33x17", dict(name="kepler", n=(33, 17, 1), length=(6.0, 6.0 * 17 / 33, 1.0))),
+    ("kepler_k2_40x24", dict(name="kepler", k=2, n=(40, 24, 1), length=(6.0, 3.6, 1.0), rk="rk3")),
+    ("kepler_k4_37x21", dict(name="kepler", k=4, n=(37, 21, 1), length=(6.0, 6.0 * 21 / 37, 1.0))),
+]
+
+
+def _rel_l1(got, ref, nvar):
+    g, r = np.asarray(got).reshape(nvar, -1), np.asarray(ref).reshape(nvar, -1)
+    norm = np.abs(r).sum(axis=1)
+    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
+
+
+@pytest.mark.parametrize("tiles", ["0", "1"])
+@pytest.mark.parametrize("case,spec", GRAV_CASES, ids=[c[0] for c in GRAV_CASES])
+def test_tile_sizes_with_gravity_match_oracle(case, spec, tiles, monkeypatch):
+    # the gravity source of both tile shapes (Sec. 2.4): RHS and three steps
+    import paper_1506_06140_amd as dg
+    monkeypatch.setenv("DG_TILE2D_SMALL", tiles)
+    print("tiles gravity", case, tiles, flush=True)
+    spec = dict(spec)
+    wl = workloads.workload(spec.pop("name"), **spec)
+    o = oracle.Oracle(wl)
+    w0, st = o.limit(o.initial_state())
+    assert st == 0
+    s = dg.Solver(wl)
+    assert s.gravity is not None
+    err = _rel_l1(_host(s.rhs(_dev(w0))), o.rhs(w0), o.nvar)
+    assert np.all(err <= TOL), err
+    fb = [s.empty() for _ in range(s.stages)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    ref = w0
+    for i in range(3):
+        ref, dt_ref = o.step(ref)
+        w = s.rk_step(w, fb, dt, rate).clone()
+        assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
+        e = _rel_l1(_host(w), ref, o.nvar)
         print(case, tiles, "step", i, e, flush=True)
         assert np.all(e <= TOL), (i, e)
     assert s.status() == 0
