@@ -696,8 +696,8 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
 // A face on a tile boundary is evaluated by both tiles with identical code
 // and inputs, so the two cells receive bitwise-opposite contributions.
 // ---------------------------------------------------------------------------
-// TS = 1: 8x8 tiles (256 threads).  Four such work-groups fit a CU (LDS
-// 35 KB each at k = 2), and once they drift apart the load, compute and
+// TS = 1: 8x8 tiles (256 threads).  Four such work-groups fit a CU at k = 2
+// (LDS 35 KB, 124 VGPRs each), and once they drift apart the load, compute and
 // store phases of different tiles overlap, which one 1024-thread work-group
 // per CU cannot do; a small grid also spreads over more CUs.
 // TS = 0: 16x16 or 16x8 tiles (see tile2d_small for which runs when).
@@ -721,9 +721,10 @@ template <>
 struct Tile2D<4, 0> { static constexpr int TX = 16, TY = 8; };
 
 // Whether a stage runs on 8x8 tiles: always for k <= 3 (faster at every grid
-// size measured, 256^2 to 1024^2); at k = 4 an 8x8 tile holds only two
-// work-groups per CU, so the 16x8 tiles run unless the grid has fewer of
-// them than the GPU has CUs.  force = 0 or 1 overrides the choice.
+// size measured, 256^2 to 1024^2); at k = 4 an 8x8 work-group needs 85 KB of
+// LDS and more than 256 registers per lane, so a CU runs one wave per SIMD
+// and the 16x8 tiles (two per SIMD) run unless the grid has fewer of them
+// than the GPU has CUs.  force = 0 or 1 overrides the choice.
 constexpr long kCusPerGpu = 256;
 inline bool tile2d_small(int k, long large_tiles, int force) {
   if (force >= 0) return force == 1;

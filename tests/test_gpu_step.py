@@ -57,7 +57,7 @@ def _amr(dim, k, n, lo, hi, **kw):
 
 CASES = [
     # 2D grids take the fused path (time-step work inside the tile kernel);
-    # ragged with respect to the 16x16 tiles
+    # ragged with respect to the 8x8 and 16-wide tiles
     ("vortex_k2_40x24", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0)), "fp64"),
     ("vortex_k1_33x17", dict(name="vortex", k=1, n=(33, 17, 1), length=(11.0, 17 / 3, 1.0)), "fp64"),
     ("vortex_k3_20x18", dict(name="vortex", k=3, n=(20, 18, 1), length=(10.0, 9.0, 1.0), noise=0.0), "fp64"),
