@@ -233,6 +233,29 @@ def test_full_size_vortex_stage_sampled():
     assert np.all(np.abs(tot) <= 1e-13 * scale)
 
 
+def test_full_size_vortex_one_call_steps():
+    # the benchmark's launch configuration over the whole 256^2, k=2 mesh:
+    # the one-call step (dt from the carried signal rate, three fused stages
+    # on the default tiles), two steps against the oracle's steps
+    wl = workloads.workload("vortex")
+    o = oracle.Oracle(wl)
+    s = _solver(wl)
+    w0 = o.initial_state()
+    fb = [s.empty() for _ in range(s.stages)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    ref = w0
+    for i in range(2):
+        ref, dt_ref = o.step(ref)
+        w = s.rk_step(w, fb, dt, rate).clone()
+        assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
+        err = rel_l1(_host(w), ref)
+        _say("full-size one-call step", i, "rel-L1", err)
+        assert np.all(err <= TOL), (i, err)
+    assert s.status() == 0
+
+
 def test_projection_matches_oracle():
     for name, over in [("vortex", dict(n=(40, 24, 1), length=(10.0, 6.0, 1.0))),
                        ("kh3d", dict(n=(8, 8, 8)))]:
