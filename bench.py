@@ -1,16 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the DG right-hand side + SSP-RK3 hot path on one MI355X.
 
-Workload: 2D isentropic vortex (strength 5, gamma 1.4, boost (1,1), periodic
-[-5,5]^2), 256^2 cells, degree k = 2 (N = 6 modes, 4 variables), FP64,
-seeded +-1e-3 density noise, CFL 0.2, no limiter.  One *step* is the whole
-hot path for one SSP-RK3 step: the CFL time step reduction and the three
-fused RHS + stage kernels.  The metric is DOF-updates per second per RK
+Headline workload: 3D Kelvin-Helmholtz shear layer on the periodic unit cube,
+128^3 cells, degree k = 2 (N = 10 modes, 5 variables), FP64, layers rho = 2,
+v_x = +0.5 for 1/4 < y < 3/4 and rho = 1, v_x = -0.5 outside, p = 2.5, gamma
+1.4, seeded cell-constant velocity noise of 1e-2 (seed 6140), CFL 0.2, the
+component-wise TVB minmod limiter and the positivity limiter after every
+stage.  This is the largest of the five workloads that fits one GPU as a
+uniform grid.  One *step* is the whole hot path for one SSP-RK3 step: the
+time step from the carried signal rate, three fused RHS + stage kernels and
+the limiter pass after each stage, issued by one dg_rk_step call and
+replayed from a HIP graph.  The metric is DOF-updates per second per RK
 stage: cells * N * 3 / step time.
 
 The initial state is built by the library itself (seeded primitives from
 ``workloads`` sampled at the library's Gauss nodes, L2-projected by
-``dg_project``); it is resident in HBM before the timed region starts.
+``dg_project``, then limited); it is resident in HBM before the timed region
+starts.
+
+The `roofline` object is for the dominant kernel, the fused 3D RHS + stage
+kernel, against its binding roof, the FP64 vector peak (algorithmic flops
+per launch over the launch's mean duration, timed with HIP events on the
+stream it runs on), with its HBM fraction beside it; `traffic` is the HBM
+bytes per launch from the committed rocprofv3 counter summary while that
+summary's kernel-source fingerprint matches the source.  The 2D vortex
+(256^2, k = 2) line, the FP32 / BF16 paths, the refined-box blast, the
+adaptive 2D KH run and the adjoint are reported under `variants`.
 
 Prints one JSON line.  ``--gpus`` above 1 is refused: this build runs on a
 single GPU.
@@ -34,23 +49,28 @@ import workloads  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
 METRIC = "DOF-updates/s per RK stage"
 KERNEL_SRC = os.path.join(ROOT, "paper_1506_06140_amd", "csrc", "dg_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_rhs_tile2d_vortex256_k2_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
 
-
-_FINGERPRINT_REGIONS = [
-    # reciprocal helpers, the time-step rate, the Euler flux
+# source regions whose text fingerprints a kernel (a counter summary taken on
+# another version of the kernel is not reported)
+_HELPERS = [
+    # reciprocal helpers, the time-step rate, the Euler flux, the Riemann solver
     ("// Reciprocal and reciprocal square root from the hardware estimates plus",
      "// HLLC numerical flux in +a between traces UL (low side) and UR (high side),"),
     ("// HLLC numerical flux in +a between traces UL (low side) and UR (high side),",
      "// ---------------------------------------------------------------------------\n// Right-hand side and fused stage."),
-    ("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
-     "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages."),
 ]
-
-
-FP32_PEAK_TFLOPS = 157.3
+KERNELS = {
+    "stage3d": dict(name="k_rhs_stage<3,2,double>", traffic="k_rhs_stage_kh3d128_k2_traffic.txt",
+                    regions=_HELPERS + [("// Right-hand side and fused stage.",
+                                         "// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.")]),
+    "tile2d": dict(name="k_rhs_tile2d<2,double> (8x8 tiles)", traffic="k_rhs_tile2d_vortex256_k2_traffic.txt",
+                   regions=_HELPERS + [("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
+                                        "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
+}
 
 
 def alg_work(d: int, k: int):
@@ -70,12 +90,12 @@ def alg_work(d: int, k: int):
     return bytes_, float(flops)
 
 
-def kernel_hash() -> str:
-    """Fingerprint of the source of the benchmarked stage kernel (the tiled 2D
-    kernel, the Riemann solver and its reciprocal helpers)."""
+def kernel_hash(kernel: str) -> str:
+    """Fingerprint of the source of a benchmarked kernel (its own region plus
+    the Riemann solver and the reciprocal helpers)."""
     src = open(KERNEL_SRC).read()
     parts = []
-    for a, b in _FINGERPRINT_REGIONS:
+    for a, b in KERNELS[kernel]["regions"]:
         i = src.find(a)
         j = src.find(b, i + 1) if i >= 0 else -1
         if i < 0 or j < 0:
@@ -84,15 +104,16 @@ def kernel_hash() -> str:
     return hashlib.sha256("".join(parts).encode()).hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the stage kernel from the committed rocprofv3
-    counter summary, or None if absent or taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, or None if absent or taken on a different kernel source."""
+    path = os.path.join(PROFILES, KERNELS[kernel]["traffic"])
+    if not os.path.exists(path):
         return None
-    txt = open(TRAFFIC_FILE).read()
+    txt = open(path).read()
     m = re.search(r"kernel_source_sha256_16:\s*(\w+)", txt)
     b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
-    if not m or not b or m.group(1) != kernel_hash():
+    if not m or not b or m.group(1) != kernel_hash(kernel):
         return None
     return float(b.group(1))
 
@@ -111,27 +132,78 @@ def build_state(s, wl):
     return w
 
 
-def cpu_baseline(wl, budget_s: float = 12.0):
-    """The FP64 oracle, single-threaded, on a bounded number of RK stages of
-    the same workload."""
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, slab: int = 8):
+    """The FP64 oracle (single-threaded C, built -O2 -ffp-contract=off),
+    pinned to one host core, on a bounded sample of the headline workload:
+    one limited SSP-RK3 stage (right-hand side, stage update, slope and
+    positivity limiters) of the cells in `slab` z-planes of the full 128^3
+    state (the oracle's per-cell entries; the work per cell is that of the
+    whole mesh)."""
+    import oracle
+    o = oracle.Oracle(wl)
+    w0 = o.initial_state()
+    w0, _ = o.limit(w0)
+    dt = o.max_dt(w0)
+    nxy = wl["n"][0] * wl["n"][1]
+    cells = np.arange(slab * nxy, dtype=np.int64)
+    aff = os.sched_getaffinity(0)
+    core = min(aff)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        L = o.rhs_cells(w0, cells)
+        wc = w0.reshape(o.nvar, o.N, -1)[:, :, cells]
+        u = oracle.rk3_combine(1, dt, wc, wc, L)
+        t1 = time.perf_counter()
+        full = w0.copy()
+        full.reshape(o.nvar, o.N, -1)[:, :, cells] = u
+        t2 = time.perf_counter()
+        o.limit_cells(full, cells)
+        t3 = time.perf_counter()
+    finally:
+        os.sched_setaffinity(0, aff)
+    el = (t1 - t0) + (t3 - t2)
+    dof = cells.size * o.N
+    return {"value": dof / el, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "cpu_model": _cpu_model(), "host_cpus": len(aff), "pinned_core": core,
+            "sample": f"one limited SSP-RK3 stage (RHS + update {t1 - t0:.2f} s, limiters {t3 - t2:.2f} s) of "
+                      f"{cells.size} cells ({slab} z-planes) of the 128^3 k=2 shear-layer state, single-threaded "
+                      f"C oracle pinned to core {core} (sched_setaffinity, as taskset) of {len(aff)}"}
+
+
+def cpu_baseline_2d(wl, budget_s: float = 8.0):
+    """The oracle on whole-mesh SSP-RK3 stages of the 2D vortex (256^2, k=2)."""
     import oracle
     o = oracle.Oracle(wl)
     w0 = o.initial_state()
     dt = o.max_dt(w0)
-    t0 = time.perf_counter()
-    stages = 0
-    u = w0
-    while True:
-        stage = stages % 3 + 1
-        u = o.rk3_stage(stage, dt, w0, u if stage > 1 else w0)
-        stages += 1
-        if time.perf_counter() - t0 > budget_s and stages >= 3:
-            break
-    el = time.perf_counter() - t0
-    dof = o.ncell * o.N
-    return {"value": dof * stages / el, "unit": METRIC, "cores": 1, "kind": "oracle",
-            "sample": f"{stages} SSP-RK3 stages (RHS + update, no limiter) of the full 256^2 k=2 vortex "
-                      f"state, single-threaded C oracle, {el:.1f} s"}
+    aff = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {min(aff)})
+    try:
+        t0 = time.perf_counter()
+        stages = 0
+        u = w0
+        while True:
+            stage = stages % 3 + 1
+            u = o.rk3_stage(stage, dt, w0, u if stage > 1 else w0)
+            stages += 1
+            if time.perf_counter() - t0 > budget_s and stages >= 3:
+                break
+        el = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, aff)
+    return {"value": o.ncell * o.N * stages / el, "unit": METRIC, "cores": 1, "kind": "oracle",
+            "sample": f"{stages} SSP-RK3 stages of the full 256^2 k=2 vortex state, {el:.1f} s"}
 
 
 def time_steps(s, wl, steps, warmup, graph=True):
@@ -192,10 +264,10 @@ def variants():
     # the FP32 rounding of the energy (node pressures are formed in FP32)
     # (the *_char runs: the same workloads with the characteristic limiter;
     # DG-4 and DG-5: the vortex at k = 3 and k = 4 with the five-stage RK_4)
-    runs = [("vortex", "vortex", 400, {}, ("fp64", "fp32", "bf16")),
+    runs = [("vortex", "vortex", 400, {}, ("fp32", "bf16")),
             ("vortex_dg4_rk4", "vortex", 200, {"k": 3, "rk": "rk4"}, ("fp64", "fp32")),
             ("vortex_dg5_rk4", "vortex", 200, {"k": 4, "rk": "rk4"}, ("fp64", "fp32")),
-            ("kh3d", "kh3d", 10, {}, ("fp64", "fp32", "bf16")),
+            ("kh3d", "kh3d", 10, {}, ("fp32", "bf16")),
             ("kh3d_char", "kh3d", 10, {"limiter": 2}, ("fp64",)),
             ("blast_amr", "blast_amr", 10, {"eps": 1e-4}, ("fp64", "fp32", "bf16")),
             ("blast_amr_char", "blast_amr", 10, {"eps": 1e-4, "limiter": 2}, ("fp64",))]
@@ -235,8 +307,7 @@ def variants():
         if i % every == 0:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, rng = s.amr_flags(w, wl["wt"], wl["alpha"])
-            nb = s.box_for(rng)
+            _, nb = s.amr_flags(w, wl["wt"], wl["alpha"])
             if nb != box or i == 0:
                 if nb != box:
                     s, w = s.regrid(w, nb)
@@ -298,14 +369,66 @@ def variants():
     return out
 
 
+def kernel_ms(s, w, bufs, reps, limiter=False):
+    """Mean duration of the fused RHS + stage kernel (or of the limiter pass)
+    of solver s: HIP events on the stream the kernels run on around `reps`
+    launches queued back to back (stages 1, 2, 3 in turn)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    dt = s.max_dt(w, bufs[3])
+
+    def launch(i):
+        stage = i % 3 + 1
+        out = bufs[1] if stage == 1 else bufs[2]
+        if limiter:
+            s.limit(out)
+        else:
+            s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], out)
+
+    for i in range(3):
+        s.rk_stage(i + 1, dt, w, w if i == 0 else bufs[0], bufs[1] if i == 0 else bufs[2])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for i in range(reps):
+        launch(i)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def vortex2d_line(steps=400, warmup=20, with_cpu=True):
+    """The 2D vortex (256^2, k = 2, FP64, no limiter) with its stage kernel's
+    HBM roofline: the state (12.6 MB) stays in the 256 MB Infinity Cache."""
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("vortex")
+    s = dg.Solver(wl)
+    ms, w = time_steps(s, wl, steps, warmup)
+    bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
+    k = kernel_ms(s, w, bufs, 300)
+    b, f = alg_work(2, 2)
+    alg_bytes = b * s.ncell
+    achieved = alg_bytes / (k * 1e-3) / 1e9
+    out = {"workload": "isentropic vortex 2D, 256x256 cells, k=2 (N=6), FP64, SSP-RK3, CFL 0.2, no limiter, "
+                       "seeded 1e-3 density noise",
+           "ms_per_step": ms, "dof_updates_per_s": s.ncell * s.N * 3 / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("tile2d"),
+                        "kernel": KERNELS["tile2d"]["name"], "kernel_ms": k, "alg_bytes_per_launch": alg_bytes,
+                        "fp64_frac": f * s.ncell / (k * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+    if with_cpu:
+        out["cpu_baseline"] = cpu_baseline_2d(wl)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
     ap.add_argument("--variants", type=int, default=1, help="also time FP32, the 3D workload and the adjoint")
+    ap.add_argument("--kernel-reps", type=int, default=30, help="launches per kernel timing")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
@@ -314,88 +437,32 @@ def main():
     import torch
     import paper_1506_06140_amd as dg
 
-    wl = workloads.workload("vortex")
+    wl = workloads.workload("kh3d")
     s = dg.Solver(wl)
-    A = build_state(s, wl)
-    B = s.empty()
-    u1, u2, dtbuf, rate = s.empty(), s.empty(), s.scalar(), s.rate_state()
-    stream = torch.cuda.current_stream()
-    s.max_rate(A, rate)
-
-    def two_steps():
-        # ping-pong: A -> B -> A, stage buffers u1, u2, device time step
-        # dtbuf; each step is one dg_rk_step call (time step, 3 stages)
-        s.rk_step(A, [u1, u2, B], dtbuf, rate)
-        s.rk_step(B, [u1, u2, A], dtbuf, rate)
-
     steps = args.steps + (args.steps % 2)
-    for _ in range((args.warmup + 1) // 2):
-        two_steps()
-    torch.cuda.synchronize()
-    if s.status() != 0:
-        raise RuntimeError("device error flag set during warm-up")
-
-    graph = None
-    if args.graph:
-        side = torch.cuda.Stream()
-        side.wait_stream(stream)
-        with torch.cuda.stream(side):
-            two_steps()
-        stream.wait_stream(side)
-        torch.cuda.synchronize()
-        graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            two_steps()
-        torch.cuda.synchronize()
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if graph is not None:
-        for _ in range(steps // 2):
-            graph.replay()
-    else:
-        for _ in range(steps // 2):
-            two_steps()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    st = s.status()
-    if st != 0:
-        raise RuntimeError(f"device error flag {st} after the timed steps")
-    w = A
-    bufs = [u1, u2, B, dtbuf]
-    args.steps = steps
-
+    ms_step, w = time_steps(s, wl, steps, args.warmup, graph=bool(args.graph))
     dof = s.ncell * s.N
-    ms_step = el / args.steps * 1e3
-    value = dof * 3 * args.steps / el
+    value = dof * 3 / (ms_step * 1e-3)
 
-    # average duration of the dominant kernel (fused RHS + stage): one pair of
-    # HIP events on the stream the kernels run on around a batch of launches
-    # queued back to back (stages 1, 2, 3 in turn)
-    reps = 300
-    dt = s.max_dt(w, bufs[3])
-    for stage in (1, 2, 3):
-        s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], bufs[1] if stage == 1 else bufs[2])
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for i in range(reps):
-        stage = i % 3 + 1
-        s.rk_stage(stage, dt, w, w if stage == 1 else bufs[0], bufs[1] if stage == 1 else bufs[2])
-    e1.record(stream)
-    torch.cuda.synchronize()
-    k_ms = e0.elapsed_time(e1) / reps
-    state_bytes = s.nvar * s.N * s.ncell * 8
-    alg_bytes = 8.0 / 3.0 * state_bytes  # read w_prev (+ w_n in stages 2,3), write w_out
-    achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    traffic = measured_traffic()
-    alg_flops = alg_work(2, 2)[1] * s.ncell
+    # the dominant kernel (fused RHS + stage) and the limiter pass, timed alone
+    bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
+    k_ms = kernel_ms(s, w, bufs, args.kernel_reps)
+    lim_ms = kernel_ms(s, w, bufs, args.kernel_reps, limiter=True)
+    if s.status() != 0:
+        raise RuntimeError("device error flag set in the kernel timing")
+    b, f = alg_work(3, 2)
+    alg_flops = f * s.ncell
+    alg_bytes = b * s.ncell
+    achieved = alg_flops / (k_ms * 1e-3) / 1e12
+    # limiter: reads every coefficient once, writes the modes >= 1
+    lim_bytes = (2 * s.N - 1) * s.nvar * 8 * s.ncell
 
     rec = {
         "metric": METRIC,
         "value": value,
         "unit": "DOF-updates/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "higher_is_better": True,
@@ -403,21 +470,27 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "isentropic vortex 2D, 256x256 cells, k=2 (N=6), FP64, SSP-RK3, CFL 0.2, "
-                               "no limiter, seeded 1e-3 density noise",
-                   "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(graph)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_rhs_tile2d<2,double> (8x8 tiles)", "kernel_ms": k_ms,
-                     "alg_bytes_per_launch": alg_bytes},
-        # the same launch against the FP64 vector peak (algorithmic flops)
-        "roofline_fp64": {"bound": "alu", "achieved": alg_flops / (k_ms * 1e-3) / 1e12,
-                          "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                          "frac": alg_flops / (k_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                          "alg_flops_per_launch": alg_flops},
+        "config": {"workload": "3D Kelvin-Helmholtz shear layer, 128^3 cells, k=2 (N=10), FP64, SSP-RK3, CFL 0.2, "
+                               "component-wise TVB minmod + positivity limiter after every stage, seeded 1e-2 "
+                               "velocity noise",
+                   "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(args.graph)},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic("stage3d"),
+                     "kernel": KERNELS["stage3d"]["name"], "kernel_ms": k_ms,
+                     "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
+                     "hbm_achieved_gbs": alg_bytes / (k_ms * 1e-3) / 1e9,
+                     "hbm_frac": alg_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        "limiter": {"kernel": "k_limit<3,2,false>", "kernel_ms": lim_ms, "alg_bytes_per_launch": lim_bytes,
+                    "hbm_frac": lim_bytes / (lim_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        # the whole step's algorithmic work over the step time
+        "step_fracs": {"alu": 3 * alg_flops / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                       "hbm": 3 * alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    del s, w, bufs
+    torch.cuda.empty_cache()
     if args.variants:
-        rec["variants"] = variants()
+        rec["variants"] = {"vortex2d_fp64": vortex2d_line(with_cpu=not args.no_cpu)}
+        rec["variants"].update(variants())
     if not args.no_cpu:
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)

@@ -62,6 +62,7 @@ enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
 enum { DG_HLLC_BATTEN = 0, DG_HLLC_DAVIS = 1 };
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16_VOL = 2 };
 enum { DG_LIM_NONE = 0, DG_LIM_MINMOD = 1, DG_LIM_CHAR = 2 };
+enum { DG_TILE2D_AUTO = 0, DG_TILE2D_8X8 = 1, DG_TILE2D_LARGE = 2 };
 
 typedef struct dg_ctx dg_ctx;
 
@@ -90,18 +91,21 @@ typedef struct {
   int refine_hi[3];   /* axis are covered by 2(hi-lo) fine cells per axis of   */
                       /* half the edge (Sec. 4); lo == hi (e.g. all zero) for  */
                       /* a uniform grid.  Requires 1 <= lo < hi <= n-1.        */
+  int tile2d;         /* 2D uniform grids: cell tile of the stage kernel,      */
+                      /* DG_TILE2D_AUTO (0, the rule of dg_init),              */
+                      /* DG_TILE2D_8X8 or DG_TILE2D_LARGE (16 x 16 for k <= 2, */
+                      /* 16 x 8 for k = 3, 4); results equal to rounding       */
 } dg_config;
 
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton
- * iteration, App. B; GLL nodes, App. C; scaled Legendre values, App. A),
+ * iteration, App. B; GLL nodes, App. C; scaled Legendre values, App. A) and,
+ * for k <= 3, the refinement matrices of Sec. 4.2 (eq. ref_pa_integral),
  * copies them to the current device and allocates scratch.  Host-to-device
- * copies happen here only.  *out receives the context.  On 2D grids without
- * refinement the stage kernel works on tiles of 8 x 8 cells for k <= 3; at
- * k = 4 on tiles of 16 x 8 cells, or of 8 x 8 when the grid has fewer 16 x 8
- * tiles than the GPU has compute units.  The environment variable
- * DG_TILE2D_SMALL = 0 or 1, read here, forces the large tiles (16 x 16 for
- * k <= 2, 16 x 8 for k = 3, 4) or the 8 x 8 tiles (results are the same to
- * rounding). */
+ * copies happen here only.  *out receives the context.  With
+ * cfg->tile2d = DG_TILE2D_AUTO, on 2D grids without refinement the stage
+ * kernel works on tiles of 8 x 8 cells for k <= 3; at k = 4 on tiles of
+ * 16 x 8 cells, or of 8 x 8 when the grid has fewer 16 x 8 tiles than the GPU
+ * has compute units. */
 int dg_init(const dg_config *cfg, dg_ctx **out);
 
 /* Number of doubles in one state array (nvar * N * cells). */
@@ -243,9 +247,15 @@ int dg_set_gravity(dg_ctx *ctx, const double *accel, void *stream);
  * of its node weights, the derefined projection of its children (eq.
  * deref_weights), exceeds wt / alpha (eq. node_ref).  flags: device, one int
  * per base cell (base-grid order, x fastest); box: device, 6 ints, receives
- * the smallest and then the largest index per axis of the flagged cells
- * (smallest > largest when none is flagged).  The paper's values are
- * wt = 0.01, alpha = 1.1.  DG_EINVAL for wt <= 0 or alpha < 1. */
+ * the refined box of the next mesh in refine_lo[3], refine_hi[3] form: the
+ * range of the flagged cells grown by one buffer layer of cells on every
+ * side (Sec. 4: the neighbours of a refined cell are refined too, which
+ * keeps the level jump across every face at one), clipped to [1, n-1]; all
+ * six zero when no cell is flagged or the clipped range is empty (2D: the
+ * z entries are zero).  Pass it to dg_init's refine_lo / refine_hi and move
+ * the state with dg_amr_regrid.  The paper's values are wt = 0.01,
+ * alpha = 1.1.  DG_EINVAL for wt <= 0 or alpha < 1; DG_EUNSUPPORTED for
+ * k = 4. */
 int dg_amr_flags(dg_ctx *ctx, const double *w, double wt, double alpha, int *flags, int *box, void *stream);
 
 /* Moves a state between two meshes over the same base grid (same dim, k,

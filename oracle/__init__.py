@@ -82,7 +82,7 @@ def _load():
             "orc_rhs": [cp, dp, dp],
             "orc_rhs_cells": [cp, dp, C.c_long, lp, dp],
             "orc_terms_cell": [cp, dp, C.c_long, dp, dp],
-            "orc_terms_cells": [cp, dp, C.c_long, lp, dp, dp],
+            "orc_terms_cells": [cp, dp, C.c_long, lp, dp, dp, dp],
             "orc_max_dt": [cp, dp, dp],
             "orc_rk3_stage": [cp, C.c_int, C.c_double, dp, dp, dp],
             "orc_limit": [cp, dp],
@@ -96,7 +96,11 @@ def _load():
             "orc_amr_max_dt": [cp, dp, dp],
             "orc_amr_limit": [cp, dp],
             "orc_refine_matrix": [cp, C.c_int, dp],
-            "orc_amr_terms": [cp, dp, dp, dp],
+            "orc_amr_terms": [cp, dp, dp, dp, dp],
+            "orc_limit_cells": [cp, dp, C.c_long, lp],
+            "orc_amr_limit_cells": [cp, dp, C.c_long, lp],
+            "orc_amr_rhs_cells": [cp, dp, C.c_long, lp, dp],
+            "orc_amr_terms_cells": [cp, dp, C.c_long, lp, dp, dp, dp],
         }
         for name, args in sig.items():
             f = getattr(_lib, name)
@@ -162,6 +166,19 @@ def tableau_form(A, b):
     alpha = np.zeros((s + 1, s + 1)); beta = np.zeros(s + 1)
     _check(lib.orc_tableau_form(s, A, b, alpha, beta), "tableau_form")
     return alpha, beta
+
+
+def rk3_combine(stage: int, dt: float, wn, wp, L) -> np.ndarray:
+    """The SSP-RK3 stage combination (App. D, table RK_3, Shu-Osher form) of
+    arrays of any shape: wp + dt L (stage 1), a wn + b (wp + dt L) (2, 3)."""
+    lib, _ = _load()
+    wp = np.ascontiguousarray(wp, dtype=np.float64)
+    wn = np.ascontiguousarray(wn if wn is not None else wp, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    assert wn.shape == wp.shape == L.shape
+    out = np.zeros_like(wp)
+    lib.orc_rk3_combine(stage, dt, wn, wp, L, out, out.size)
+    return out
 
 
 def tableau_combine(A, b, m: int, dt: float, Y, L):
@@ -373,14 +390,16 @@ class Oracle:
         _check(lib.orc_terms_cell(C.byref(self.c), self._s(w), cell, V, S), "terms")
         return V, S
 
-    def terms_cells(self, w: np.ndarray, cells=None):
-        """(fac V, fac S) of selected cells (all if None): [nvar][N][ncells] each."""
+    def terms_cells(self, w: np.ndarray, cells=None, with_abs: bool = False):
+        """(fac V, fac S) of selected cells (all if None): [nvar][N][ncells] each;
+        with_abs adds fac times the summed magnitudes of all summands of V and S
+        (the per-element rounding scale of L = fac (V - S))."""
         lib, _ = _load()
         cells = np.arange(self.ncell) if cells is None else cells
         cells = np.ascontiguousarray(cells, dtype=np.int64)
-        V = np.zeros((self.nvar, self.N, cells.size)); S = np.zeros_like(V)
-        _check(lib.orc_terms_cells(C.byref(self.c), self._s(w), cells.size, cells, V, S), "terms_cells")
-        return V, S
+        V = np.zeros((self.nvar, self.N, cells.size)); S = np.zeros_like(V); A = np.zeros_like(V)
+        _check(lib.orc_terms_cells(C.byref(self.c), self._s(w), cells.size, cells, V, S, A), "terms_cells")
+        return (V, S, A) if with_abs else (V, S)
 
     def max_dt(self, w: np.ndarray) -> float:
         lib, _ = _load()
@@ -400,6 +419,15 @@ class Oracle:
         out = np.array(self._s(w), copy=True)
         st = lib.orc_limit(C.byref(self.c), out)
         return out, st
+
+    def limit_cells(self, w: np.ndarray, cells) -> tuple[np.ndarray, int]:
+        """The limiters applied to the listed (flat-indexed) cells of w, with
+        the neighbour means of w: ([nvar][N][len(cells)], status)."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_limit_cells(C.byref(self.c), out, cells.size, cells)
+        return out.reshape(self.nvar, self.N, -1)[:, :, cells], st
 
     def eigvecs(self, U, axis: int):
         """(R, L): right and left eigenvectors of the flux Jacobian in `axis`
@@ -594,6 +622,30 @@ class AmrOracle(Oracle):
         st = lib.orc_amr_limit(C.byref(self.c), out)
         return out, st
 
+    def cells_of(self, x, cells):
+        """[nvar][N][len(cells)] of a flat state at cells of the combined
+        numbering (coarse cells, then fine cells)."""
+        c, f = self.blocks(x)
+        full = np.concatenate([c, f], axis=2)
+        return full[:, :, np.asarray(cells, dtype=np.int64)]
+
+    def limit_cells(self, w, cells):
+        """The limiters on the listed cells (combined numbering) of w:
+        ([nvar][N][len(cells)], status)."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_amr_limit_cells(C.byref(self.c), out, cells.size, cells)
+        return self.cells_of(out, cells), st
+
+    def rhs_cells(self, w, cells):
+        """dw/dt of the listed cells (combined numbering): [nvar][N][len(cells)]."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.zeros((self.nvar, self.N, cells.size))
+        _check(lib.orc_amr_rhs_cells(C.byref(self.c), self._s(w), cells.size, cells, out), "amr_rhs_cells")
+        return out
+
     def totals(self, w):
         """Domain integrals of the conserved variables (hole cells excluded)."""
         wc, wf = self.blocks(w)
@@ -607,12 +659,21 @@ class AmrOracle(Oracle):
         assert w.size == self.size
         return w
 
-    def terms_cells(self, w, cells=None):
-        """(fac V, fac S) of every cell of both blocks, flat like the state."""
+    def terms_cells(self, w, cells=None, with_abs: bool = False):
+        """(fac V, fac S) of every cell of both blocks, flat like the state
+        (with_abs: and the summed magnitudes of their summands, as for the
+        uniform grid); with `cells` (combined numbering) only those cells,
+        [nvar][N][len(cells)] each."""
         lib, _ = _load()
-        V = np.zeros(self.size); S = np.zeros(self.size)
-        _check(lib.orc_amr_terms(C.byref(self.c), self._s(w), V, S), "amr_terms")
-        return V, S
+        if cells is not None:
+            cells = np.ascontiguousarray(cells, dtype=np.int64)
+            V = np.zeros((self.nvar, self.N, cells.size)); S = np.zeros_like(V); A = np.zeros_like(V)
+            _check(lib.orc_amr_terms_cells(C.byref(self.c), self._s(w), cells.size, cells, V, S, A),
+                   "amr_terms_cells")
+            return (V, S, A) if with_abs else (V, S)
+        V = np.zeros(self.size); S = np.zeros(self.size); A = np.zeros(self.size)
+        _check(lib.orc_amr_terms(C.byref(self.c), self._s(w), V, S, A), "amr_terms")
+        return (V, S, A) if with_abs else (V, S)
 
     def refine_matrix(self, child: int):
         lib, _ = _load()

@@ -376,8 +376,10 @@ static long neighbour(const ctx *X, long cell, int a, int dir) {
   return (i[2] * X->ny + i[1]) * X->nx + i[0];
 }
 
-/* Volume term V_j = sum_a sum_q f_a(U(xi_q)) dphi_j/dxi_a(xi_q) w_q (eq. dg_term2). */
-static void volume_term(const ctx *X, const real_t *w, long cell, real_t V[MAXV][MAXN]) {
+/* Volume term V_j = sum_a sum_q f_a(U(xi_q)) dphi_j/dxi_a(xi_q) w_q (eq. dg_term2).
+ * A, when not NULL, accumulates the absolute values of the summands (the
+ * rounding-error scale of V_j, used by the tests' per-element bounds). */
+static void volume_term(const ctx *X, const real_t *w, long cell, real_t V[MAXV][MAXN], double (*A)[MAXN]) {
   for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) V[v][j] = 0.0;
   for (int q = 0; q < X->Q; ++q) {
     real_t U[MAXV], F[MAXV];
@@ -388,7 +390,11 @@ static void volume_term(const ctx *X, const real_t *w, long cell, real_t V[MAXV]
     for (int a = 0; a < X->d; ++a) {
       euler_flux(X, U, a, F);
       for (int v = 0; v < X->nvar; ++v)
-        for (int j = 0; j < X->N; ++j) V[v][j] += F[v] * X->dphiV[a][q][j] * X->wV[q];
+        for (int j = 0; j < X->N; ++j) {
+          real_t t = F[v] * X->dphiV[a][q][j] * X->wV[q];
+          V[v][j] += t;
+          if (A) A[v][j] += fabs(RE(t));
+        }
     }
   }
 }
@@ -403,7 +409,7 @@ static void face_trace(const ctx *X, const real_t *w, long cell, int a, int s, i
 /* Surface term S_j = sum over the 2d faces of the cell of
  * sum_r fbar . n phi_j(xi_r) w_r (eq. dg_term3); fbar is the HLLC flux of the
  * low-side and high-side traces, n the outward normal. */
-static void surface_term(const ctx *X, const real_t *w, long cell, real_t S[MAXV][MAXN]) {
+static void surface_term(const ctx *X, const real_t *w, long cell, real_t S[MAXV][MAXN], double (*A)[MAXN]) {
   for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
   for (int a = 0; a < X->d; ++a)
     for (int s = 0; s < 2; ++s) {
@@ -419,6 +425,7 @@ static void surface_term(const ctx *X, const real_t *w, long cell, real_t S[MAXV
           for (int j = 0; j < X->N; ++j) {
             real_t t = F[v] * X->phiF[a][s][r][j] * X->wF[r];
             if (s) S[v][j] += t; else S[v][j] -= t;
+            if (A) A[v][j] += fabs(RE(t));
           }
       }
     }
@@ -453,8 +460,8 @@ static void source_term(const ctx *X, const real_t *w, long cell, real_t G[MAXV]
  * plus |K|^-1 (|K| / 2^d) G_j with a gravity source. */
 static void rhs_cell(const ctx *X, const real_t *w, long cell, real_t Lc[MAXV][MAXN]) {
   real_t V[MAXV][MAXN], S[MAXV][MAXN];
-  volume_term(X, w, cell, V);
-  surface_term(X, w, cell, S);
+  volume_term(X, w, cell, V, NULL);
+  surface_term(X, w, cell, S, NULL);
   double fac = 2.0 / X->dx / (double)(1 << X->d);
   for (int v = 0; v < X->nvar; ++v)
     for (int j = 0; j < X->N; ++j) Lc[v][j] = fac * (V[v][j] - S[v][j]);
@@ -658,22 +665,27 @@ int orc_rhs_cells(const orc_config *c, const double *w, long ncells, const long 
 /* Volume and surface terms of a list of cells, scaled like L:
  * V_out = fac V, S_out = fac S, each [nvar][N][ncells], so that L = V_out - S_out.
  * Their magnitudes bound the rounding error of L (tests use them as the
- * conditioning scale of the right-hand side). */
+ * conditioning scale of the right-hand side).  A_out (may be NULL) receives
+ * fac times the sum of the absolute values of every summand of V and S: the
+ * per-element rounding-error scale of L (a sum's rounding error is bounded by
+ * a multiple of the unit roundoff times the sum of its terms' magnitudes). */
 int orc_terms_cells(const orc_config *c, const double *w, long ncells, const long *cells, double *V_out,
-                    double *S_out) {
+                    double *S_out, double *A_out) {
   ctx *X = malloc(sizeof(ctx));
   int st = ctx_init(c, X);
   if (st != ORC_OK) { free(X); return st; }
   double fac = 2.0 / X->dx / (double)(1 << X->d);
   for (long i = 0; i < ncells; ++i) {
     if (cells[i] < 0 || cells[i] >= X->ncell) { free(X); return ORC_EINVAL; }
-    double Vc[MAXV][MAXN], Sc[MAXV][MAXN];
-    volume_term(X, w, cells[i], Vc);
-    surface_term(X, w, cells[i], Sc);
+    double Vc[MAXV][MAXN], Sc[MAXV][MAXN], Ac[MAXV][MAXN];
+    memset(Ac, 0, sizeof(Ac));
+    volume_term(X, w, cells[i], Vc, Ac);
+    surface_term(X, w, cells[i], Sc, Ac);
     for (int v = 0; v < X->nvar; ++v)
       for (int j = 0; j < X->N; ++j) {
         V_out[((long)v * X->N + j) * ncells + i] = fac * Vc[v][j];
         S_out[((long)v * X->N + j) * ncells + i] = fac * Sc[v][j];
+        if (A_out) A_out[((long)v * X->N + j) * ncells + i] = fac * Ac[v][j];
       }
   }
   free(X);
@@ -686,8 +698,8 @@ int orc_terms_cell(const orc_config *c, const double *w, long cell, double *V, d
   int st = ctx_init(c, X);
   if (st == ORC_OK) {
     double Vc[MAXV][MAXN], Sc[MAXV][MAXN];
-    volume_term(X, w, cell, Vc);
-    surface_term(X, w, cell, Sc);
+    volume_term(X, w, cell, Vc, NULL);
+    surface_term(X, w, cell, Sc, NULL);
     for (int v = 0; v < X->nvar; ++v)
       for (int j = 0; j < X->N; ++j) { V[v * X->N + j] = Vc[v][j]; S[v * X->N + j] = Sc[v][j]; }
   }
@@ -1137,9 +1149,11 @@ static void uniform_neighbour_means(const ctx *X, const double *w, double *nbm) 
       }
 }
 
-/* Slope limiter, then positivity limiter, in place (main loop, Sec. 4.5).
- * Returns ORC_ENEGATIVE if some cell mean is not positive. */
-int orc_limit(const orc_config *c, double *w) {
+/* Slope limiter, then positivity limiter, in place, on the cells that `skip`
+ * does not mark (all cells if skip is NULL).  The neighbour means are read
+ * before any cell is limited; the limiters never change a mean, so limiting a
+ * subset of the cells gives those cells exactly what limiting all would. */
+static int limit_masked(const orc_config *c, double *w, const unsigned char *skip) {
   ctx *X = malloc(sizeof(ctx));
   int st = ctx_init(c, X);
   if (st != ORC_OK) { free(X); return st; }
@@ -1150,14 +1164,35 @@ int orc_limit(const orc_config *c, double *w) {
     for (long i = 0; i < X->ncell; ++i) dxc[i] = X->dx;
     uniform_neighbour_means(X, w, nbm);
     if (c->limiter == 2)
-      char_limit(X, w, nbm, dxc, NULL);
+      char_limit(X, w, nbm, dxc, skip);
     else
-      slope_limit(X, w, nbm, dxc, NULL);
+      slope_limit(X, w, nbm, dxc, skip);
     free(nbm); free(dxc);
   }
-  if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0, NULL);
+  if (c->positivity) bad = positivity_limit(X, w, NULL, NULL, 0, skip);
   free(X);
   return bad ? ORC_ENEGATIVE : ORC_OK;
+}
+
+/* Slope limiter, then positivity limiter, in place (main loop, Sec. 4.5).
+ * Returns ORC_ENEGATIVE if some cell mean is not positive. */
+int orc_limit(const orc_config *c, double *w) { return limit_masked(c, w, NULL); }
+
+/* The same on the listed cells only (flat indices); the other cells of w are
+ * left as they are.  For sampled checks of large grids. */
+int orc_limit_cells(const orc_config *c, double *w, long ncells, const long *cells) {
+  long nc = 1;
+  for (int a = 0; a < c->dim; ++a) nc *= c->n[a];
+  unsigned char *skip = malloc(nc);
+  if (!skip) return ORC_ENOMEM;
+  memset(skip, 1, nc);
+  for (long i = 0; i < ncells; ++i) {
+    if (cells[i] < 0 || cells[i] >= nc) { free(skip); return ORC_EINVAL; }
+    skip[cells[i]] = 0;
+  }
+  int st = limit_masked(c, w, skip);
+  free(skip);
+  return st;
 }
 
 /* Positivity check points S in reference coordinates: xi[nS][3]. */
@@ -1287,7 +1322,8 @@ static void amr_state(const ctx *X, const double *wb, long cell, const double *p
 }
 
 /* Surface term of a coarse cell, hanging faces included. */
-static void amr_surface_coarse(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN]) {
+static void amr_surface_coarse(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN],
+                               double (*A)[MAXN]) {
   const ctx *X = &M->Xc, *Y = &M->Xf;
   int d = X->d;
   for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
@@ -1312,6 +1348,7 @@ static void amr_surface_coarse(const amr *M, const double *wc, const double *wf,
               for (int l = 0; l < X->N; ++l) {
                 double tt = F[v] * M->phiH[a][s][sub][r][l] * X->wF[r] / (double)M->nsub;
                 if (s) S[v][l] += tt; else S[v][l] -= tt;
+                if (A) A[v][l] += fabs(tt);
               }
           }
         }
@@ -1327,6 +1364,7 @@ static void amr_surface_coarse(const amr *M, const double *wc, const double *wf,
             for (int l = 0; l < X->N; ++l) {
               double tt = F[v] * X->phiF[a][s][r][l] * X->wF[r];
               if (s) S[v][l] += tt; else S[v][l] -= tt;
+              if (A) A[v][l] += fabs(tt);
             }
         }
       }
@@ -1335,7 +1373,8 @@ static void amr_surface_coarse(const amr *M, const double *wc, const double *wf,
 }
 
 /* Surface term of a fine cell: neighbours outside the fine block are coarse. */
-static void amr_surface_fine(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN]) {
+static void amr_surface_fine(const amr *M, const double *wc, const double *wf, long cell, double S[MAXV][MAXN],
+                             double (*A)[MAXN]) {
   const ctx *X = &M->Xc, *Y = &M->Xf;
   int d = Y->d;
   for (int v = 0; v < Y->nvar; ++v) for (int j = 0; j < Y->N; ++j) S[v][j] = 0.0;
@@ -1364,41 +1403,58 @@ static void amr_surface_fine(const amr *M, const double *wc, const double *wf, l
           for (int l = 0; l < Y->N; ++l) {
             double tt = F[v] * Y->phiF[a][s][r][l] * Y->wF[r];
             if (s) S[v][l] += tt; else S[v][l] -= tt;
+            if (A) A[v][l] += fabs(tt);
           }
       }
     }
   }
 }
 
-static void amr_rhs_all(const amr *M, const double *w, double *L) {
+/* dw/dt of one cell in the combined numbering (coarse cells 0..ncc-1, then
+ * fine cells), each block with its own dx in the factor of eq.
+ * spatial_discretisation; zero for a hole cell. */
+static void amr_rhs_cell(const amr *M, const double *w, long cell, double Lc[MAXV][MAXN]) {
   const double *wc = w, *wf = w + (long)M->Xc.nvar * M->Xc.N * M->ncc;
-  double *Lc = L, *Lf = L + (long)M->Xc.nvar * M->Xc.N * M->ncc;
   int nv = M->Xc.nvar, N = M->Xc.N, d = M->Xc.d;
-  double facc = 2.0 / M->Xc.dx / (double)(1 << d), facf = 2.0 / M->Xf.dx / (double)(1 << d);
-  for (long cell = 0; cell < M->ncc; ++cell) {
+  double V[MAXV][MAXN], S[MAXV][MAXN];
+  double fac;
+  if (cell < M->ncc) {
     long i[3]; unflat(&M->Xc, cell, i);
-    double V[MAXV][MAXN], S[MAXV][MAXN];
     if (amr_in_hole(M, i)) {
-      for (int v = 0; v < nv; ++v) for (int j = 0; j < N; ++j) Lc[((long)v * N + j) * M->ncc + cell] = 0.0;
-      continue;
+      for (int v = 0; v < nv; ++v) for (int j = 0; j < N; ++j) Lc[v][j] = 0.0;
+      return;
     }
-    volume_term(&M->Xc, wc, cell, V);
-    amr_surface_coarse(M, wc, wf, cell, S);
-    for (int v = 0; v < nv; ++v)
-      for (int j = 0; j < N; ++j) Lc[((long)v * N + j) * M->ncc + cell] = facc * (V[v][j] - S[v][j]);
+    fac = 2.0 / M->Xc.dx / (double)(1 << d);
+    volume_term(&M->Xc, wc, cell, V, NULL);
+    amr_surface_coarse(M, wc, wf, cell, S, NULL);
+  } else {
+    fac = 2.0 / M->Xf.dx / (double)(1 << d);
+    volume_term(&M->Xf, wf, cell - M->ncc, V, NULL);
+    amr_surface_fine(M, wc, wf, cell - M->ncc, S, NULL);
   }
-  for (long cell = 0; cell < M->ncf; ++cell) {
-    double V[MAXV][MAXN], S[MAXV][MAXN];
-    volume_term(&M->Xf, wf, cell, V);
-    amr_surface_fine(M, wc, wf, cell, S);
+  for (int v = 0; v < nv; ++v)
+    for (int j = 0; j < N; ++j) Lc[v][j] = fac * (V[v][j] - S[v][j]);
+}
+
+static void amr_rhs_all(const amr *M, const double *w, double *L) {
+  double *Lc = L, *Lf = L + (long)M->Xc.nvar * M->Xc.N * M->ncc;
+  int nv = M->Xc.nvar, N = M->Xc.N;
+  for (long cell = 0; cell < M->ncc + M->ncf; ++cell) {
+    double Lk[MAXV][MAXN];
+    amr_rhs_cell(M, w, cell, Lk);
     for (int v = 0; v < nv; ++v)
-      for (int j = 0; j < N; ++j) Lf[((long)v * N + j) * M->ncf + cell] = facf * (V[v][j] - S[v][j]);
+      for (int j = 0; j < N; ++j) {
+        if (cell < M->ncc) Lc[((long)v * N + j) * M->ncc + cell] = Lk[v][j];
+        else Lf[((long)v * N + j) * M->ncf + (cell - M->ncc)] = Lk[v][j];
+      }
   }
 }
 
 /* fac V and fac S of every cell of both blocks (hole cells zero), so that
- * L = V - S; their magnitudes are the conditioning scale of the RHS. */
-int orc_amr_terms(const orc_config *c, const double *w, double *Vo, double *So) {
+ * L = V - S; their magnitudes are the conditioning scale of the RHS.  Ao (may
+ * be NULL): fac times the summed magnitudes of every summand, as in
+ * orc_terms_cells. */
+int orc_amr_terms(const orc_config *c, const double *w, double *Vo, double *So, double *Ao) {
   amr *M = malloc(sizeof(amr));
   int st = amr_init(c, M);
   if (st != ORC_OK) { free(M); return st; }
@@ -1408,23 +1464,64 @@ int orc_amr_terms(const orc_config *c, const double *w, double *Vo, double *So) 
   double facc = 2.0 / M->Xc.dx / (double)(1 << d), facf = 2.0 / M->Xf.dx / (double)(1 << d);
   for (long cell = 0; cell < M->ncc; ++cell) {
     long i[3]; unflat(&M->Xc, cell, i);
-    double V[MAXV][MAXN], S[MAXV][MAXN];
+    double V[MAXV][MAXN], S[MAXV][MAXN], A[MAXV][MAXN];
+    memset(A, 0, sizeof(A));
     int hole = amr_in_hole(M, i);
-    if (!hole) { volume_term(&M->Xc, wc, cell, V); amr_surface_coarse(M, wc, wf, cell, S); }
+    if (!hole) { volume_term(&M->Xc, wc, cell, V, A); amr_surface_coarse(M, wc, wf, cell, S, A); }
     for (int v = 0; v < nv; ++v)
       for (int j = 0; j < N; ++j) {
         Vo[((long)v * N + j) * M->ncc + cell] = hole ? 0.0 : facc * V[v][j];
         So[((long)v * N + j) * M->ncc + cell] = hole ? 0.0 : facc * S[v][j];
+        if (Ao) Ao[((long)v * N + j) * M->ncc + cell] = hole ? 0.0 : facc * A[v][j];
       }
   }
   for (long cell = 0; cell < M->ncf; ++cell) {
-    double V[MAXV][MAXN], S[MAXV][MAXN];
-    volume_term(&M->Xf, wf, cell, V);
-    amr_surface_fine(M, wc, wf, cell, S);
+    double V[MAXV][MAXN], S[MAXV][MAXN], A[MAXV][MAXN];
+    memset(A, 0, sizeof(A));
+    volume_term(&M->Xf, wf, cell, V, A);
+    amr_surface_fine(M, wc, wf, cell, S, A);
     for (int v = 0; v < nv; ++v)
       for (int j = 0; j < N; ++j) {
         Vo[off + ((long)v * N + j) * M->ncf + cell] = facf * V[v][j];
         So[off + ((long)v * N + j) * M->ncf + cell] = facf * S[v][j];
+        if (Ao) Ao[off + ((long)v * N + j) * M->ncf + cell] = facf * A[v][j];
+      }
+  }
+  free(M);
+  return ORC_OK;
+}
+
+/* fac V, fac S and fac times the summed magnitudes of their summands for a
+ * list of cells in the combined numbering (coarse cells, then fine cells),
+ * each output [nvar][N][ncells]; hole cells give zeros.  L = V - S. */
+int orc_amr_terms_cells(const orc_config *c, const double *w, long ncells, const long *cells, double *Vo,
+                        double *So, double *Ao) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  const double *wc = w, *wf = w + (long)M->Xc.nvar * M->Xc.N * M->ncc;
+  int nv = M->Xc.nvar, N = M->Xc.N, d = M->Xc.d;
+  double facc = 2.0 / M->Xc.dx / (double)(1 << d), facf = 2.0 / M->Xf.dx / (double)(1 << d);
+  for (long n = 0; n < ncells; ++n) {
+    long cell = cells[n];
+    if (cell < 0 || cell >= M->ncc + M->ncf) { free(M); return ORC_EINVAL; }
+    double V[MAXV][MAXN], S[MAXV][MAXN], A[MAXV][MAXN];
+    memset(V, 0, sizeof(V)); memset(S, 0, sizeof(S)); memset(A, 0, sizeof(A));
+    double fac;
+    if (cell < M->ncc) {
+      long i[3]; unflat(&M->Xc, cell, i);
+      fac = facc;
+      if (!amr_in_hole(M, i)) { volume_term(&M->Xc, wc, cell, V, A); amr_surface_coarse(M, wc, wf, cell, S, A); }
+    } else {
+      fac = facf;
+      volume_term(&M->Xf, wf, cell - M->ncc, V, A);
+      amr_surface_fine(M, wc, wf, cell - M->ncc, S, A);
+    }
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) {
+        Vo[((long)v * N + j) * ncells + n] = fac * V[v][j];
+        So[((long)v * N + j) * ncells + n] = fac * S[v][j];
+        Ao[((long)v * N + j) * ncells + n] = fac * A[v][j];
       }
   }
   free(M);
@@ -1511,6 +1608,23 @@ int orc_amr_rhs(const orc_config *c, const double *w, double *L) {
   return st;
 }
 
+/* dw/dt of the listed cells (combined numbering): out[nvar][N][ncells]. */
+int orc_amr_rhs_cells(const orc_config *c, const double *w, long ncells, const long *cells, double *out) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  if (st != ORC_OK) { free(M); return st; }
+  int nv = M->Xc.nvar, N = M->Xc.N;
+  for (long n = 0; n < ncells; ++n) {
+    if (cells[n] < 0 || cells[n] >= M->ncc + M->ncf) { free(M); return ORC_EINVAL; }
+    double Lk[MAXV][MAXN];
+    amr_rhs_cell(M, w, cells[n], Lk);
+    for (int v = 0; v < nv; ++v)
+      for (int j = 0; j < N; ++j) out[((long)v * N + j) * ncells + n] = Lk[v][j];
+  }
+  free(M);
+  return ORC_OK;
+}
+
 int orc_amr_rk3_stage(const orc_config *c, int stage, double dt, const double *wn, const double *wp, double *out) {
   if (stage < 1 || stage > 3) return ORC_EINVAL;
   amr *M = malloc(sizeof(amr));
@@ -1579,7 +1693,9 @@ int orc_amr_max_dt(const orc_config *c, const double *w, double *dt_out) {
  * sees, across the block boundary, the mean of the coarse polynomial over the
  * child subcell next to it.  Coarse cells with hanging faces also check
  * positivity at the hanging-face quadrature points. */
-int orc_amr_limit(const orc_config *c, double *w) {
+/* sel (may be NULL: every cell) marks, in the combined numbering (coarse
+ * cells, then fine cells), the cells to limit. */
+static int amr_limit_masked(const orc_config *c, double *w, const unsigned char *sel) {
   amr *M = malloc(sizeof(amr));
   int st = amr_init(c, M);
   if (st != ORC_OK) { free(M); return st; }
@@ -1587,10 +1703,17 @@ int orc_amr_limit(const orc_config *c, double *w) {
   int d = X->d, nv = X->nvar, N = X->N;
   double *wc = w, *wf = w + (long)nv * N * M->ncc;
   long bad = 0;
+  /* hole[] marks the coarse cells that are not limited: the hole cells, and
+   * with a selection every unselected one; fskip[] the same for fine cells */
   unsigned char *hole = malloc(M->ncc);
+  unsigned char *fskip = NULL;
   for (long cell = 0; cell < M->ncc; ++cell) {
     long i[3]; unflat(X, cell, i);
-    hole[cell] = (unsigned char)amr_in_hole(M, i);
+    hole[cell] = (unsigned char)(amr_in_hole(M, i) || (sel && !sel[cell]));
+  }
+  if (sel) {
+    fskip = malloc(M->ncf);
+    for (long cell = 0; cell < M->ncf; ++cell) fskip[cell] = (unsigned char)!sel[M->ncc + cell];
   }
   if (c->limiter) {
     double *nbc = malloc(sizeof(double) * 2 * d * nv * M->ncc);
@@ -1648,10 +1771,10 @@ int orc_amr_limit(const orc_config *c, double *w) {
     }
     if (c->limiter == 2) {
       char_limit(X, wc, nbc, dxc, hole);
-      char_limit(Y, wf, nbf, dxf, NULL);
+      char_limit(Y, wf, nbf, dxf, fskip);
     } else {
       slope_limit(X, wc, nbc, dxc, hole);
-      slope_limit(Y, wf, nbf, dxf, NULL);
+      slope_limit(Y, wf, nbf, dxf, fskip);
     }
     free(nbc); free(nbf); free(dxc); free(dxf);
   }
@@ -1675,12 +1798,34 @@ int orc_amr_limit(const orc_config *c, double *w) {
         }
     }
     bad += positivity_limit(X, wc, xcnt, xphi, xmax, hole);
-    bad += positivity_limit(Y, wf, NULL, NULL, 0, NULL);
+    bad += positivity_limit(Y, wf, NULL, NULL, 0, fskip);
     free(xcnt); free(xphi);
   }
   free(hole);
+  free(fskip);
   free(M);
   return bad ? ORC_ENEGATIVE : ORC_OK;
+}
+
+int orc_amr_limit(const orc_config *c, double *w) { return amr_limit_masked(c, w, NULL); }
+
+/* The limiters on the listed cells only, in the combined numbering (coarse
+ * cells 0..ncoarse-1, then fine cells); other cells are left as they are. */
+int orc_amr_limit_cells(const orc_config *c, double *w, long ncells, const long *cells) {
+  amr *M = malloc(sizeof(amr));
+  int st = amr_init(c, M);
+  long nt = M->ncc + M->ncf;
+  free(M);
+  if (st != ORC_OK) return st;
+  unsigned char *sel = calloc(nt, 1);
+  if (!sel) return ORC_ENOMEM;
+  for (long i = 0; i < ncells; ++i) {
+    if (cells[i] < 0 || cells[i] >= nt) { free(sel); return ORC_EINVAL; }
+    sel[cells[i]] = 1;
+  }
+  st = amr_limit_masked(c, w, sel);
+  free(sel);
+  return st;
 }
 
 /* (P_c)_{j,l} = 2^-d int phi_l((xi + c)/2) phi_j(xi) dxi: the L2 projection of

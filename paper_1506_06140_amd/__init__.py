@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(_HERE, "libdg.so"))
 DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
 DG_LIM_NONE, DG_LIM_MINMOD, DG_LIM_CHAR = 0, 1, 2
+DG_TILE2D_AUTO, DG_TILE2D_8X8, DG_TILE2D_LARGE = 0, 1, 2
 # doubles in the carried rate state (8 slots, 16 apart; the rate is the largest slot)
 DG_RATE_STATE, RATE_SLOTS, RATE_STRIDE = 128, 8, 16
 PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}
@@ -56,6 +57,7 @@ class dg_config(C.Structure):
         ("slope_limiter", C.c_int), ("beta", C.c_double), ("m_tilde", C.c_double),
         ("positivity", C.c_int), ("eps", C.c_double),
         ("refine_lo", C.c_int * 3), ("refine_hi", C.c_int * 3),
+        ("tile2d", C.c_int),
     ]
 
 
@@ -133,6 +135,7 @@ def make_config(wl: dict, precision: str = "fp64") -> dg_config:
     c.positivity = wl.get("positivity", 0); c.eps = wl.get("eps", 1e-10)
     c.refine_lo[:] = list(wl.get("refine_lo", (0, 0, 0)))
     c.refine_hi[:] = list(wl.get("refine_hi", (0, 0, 0)))
+    c.tile2d = wl.get("tile2d", DG_TILE2D_AUTO)
     return c
 
 
@@ -309,7 +312,9 @@ class Solver:
     # -- adaptive refinement of the one-box mesh ------------------------------
     def amr_flags(self, w, wt=0.01, alpha=1.1, stream=None):
         """(flags, box): device int32 flags per base cell (Sec. 4.1) and, on
-        the host, (smallest, largest) flagged index per axis, or None."""
+        the host, the library's refined box of the next mesh ((refine_lo,
+        refine_hi): the flagged range plus the buffer layer, clipped), or
+        None when there is none."""
         import torch
         nb = self.ncoarse if self.amr else self.ncell
         flags = torch.empty(nb, dtype=torch.int32, device="cuda")
@@ -317,24 +322,9 @@ class Solver:
         _check(self.lib.dg_amr_flags(self.ctx, self._s(w), wt, alpha, flags.data_ptr(), box.data_ptr(),
                                      _stream(stream)), "dg_amr_flags")
         b = box.cpu().tolist()
-        d = self.wl["dim"]
-        if any(b[a] > b[3 + a] for a in range(d)):
+        if not any(b):
             return flags, None
         return flags, (tuple(b[:3]), tuple(b[3:]))
-
-    def box_for(self, flagged, layer=1):
-        """refine_lo/refine_hi around the flagged range grown by `layer` cells
-        (the buffer layer of Sec. 4), inside [1, n-1]; None for no box."""
-        if flagged is None:
-            return None
-        d = self.wl["dim"]
-        lo, hi = [0, 0, 0], [0, 0, 0]
-        for a in range(d):
-            lo[a] = max(1, flagged[0][a] - layer)
-            hi[a] = min(self.wl["n"][a] - 1, flagged[1][a] + 1 + layer)
-            if hi[a] <= lo[a]:
-                return None
-        return tuple(lo), tuple(hi)
 
     def regrid(self, w, box, precision=None, stream=None):
         """(solver, state) on the same base grid with the refined box `box`

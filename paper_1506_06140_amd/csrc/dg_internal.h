@@ -88,6 +88,6 @@ struct dg_ctx {
   double *prmat = nullptr;  // refinement matrices on the device (dg_amr_flags, dg_amr_regrid)
   // 2D tile size: -1 automatic (dg::tile2d_small: 8x8 tiles for k <= 3, and
   // for k = 4 on grids with fewer 16x8 tiles than CUs), 0 always the large
-  // tiles, 1 always 8x8 (environment variable DG_TILE2D_SMALL at dg_init)
+  // tiles, 1 always 8x8 (dg_config.tile2d)
   int tile_small = -1;
 };

@@ -1672,6 +1672,12 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
 // FP32; the fluxes go through LDS as BF16 to the A-operand layout of stage B.
 // V (FP32) is written to a scratch state that the stage kernel consumes.
 // Mode 0 of V is exactly zero (dphi_1 = 0).
+// Every operand x (weights, fluxes, tables) is carried as a BF16 pair
+// x = hi + lo, hi = bf16(x), lo = bf16(x - hi), and each product as the three
+// MFMAs lo*hi + hi*lo + hi*hi (the lo*lo term is below FP32 rounding of the
+// sum): about 16 significant bits per operand instead of 8, so the rounding
+// of a large flux (the pressure in a momentum flux) no longer swamps a small
+// field's volume term.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -1684,7 +1690,8 @@ struct Mfma {
   static constexpr int NQC = QP / 32;                            // node chunks (stage B)
   static constexpr int PB = 0;                                   // phi [QP][NP]
   static constexpr int DB = PB + QP * NP;                        // dphi w, transposed [D][NP][QP]
-  static constexpr int TOTAL = DB + D * NP * QP;
+  static constexpr int LO = DB + D * NP * QP;                    // the same tables' low parts
+  static constexpr int TOTAL = 2 * LO;
 };
 
 template <int D, int K>
@@ -1693,7 +1700,7 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
   using C = Cfg<D, K>;
   using M = Mfma<D, K>;
   constexpr int NV = C::NV, N = C::N, QP = M::QP, NP = M::NP;
-  __shared__ __bf16 fs[4][NV][16][QP];  // one flux direction at a time, per wave
+  __shared__ __bf16 fs[2][4][NV][16][QP];  // one flux direction at a time, per wave (hi, lo)
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int row = lane & 15, grp = lane >> 4;
   const long c0 = ((long)blockIdx.x * 4 + wv) * 16;
@@ -1703,17 +1710,22 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
   f32x4 U[NV][M::NQT];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    bf16x8 A;
+    bf16x8 A, Al;
     const long cell = c0 + row;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int m = 8 * grp + e;
-      A[e] = (m < N && cell < nc) ? (__bf16)(float)w[(long)(v * N + m) * nc + cell] : (__bf16)0.0f;
+      const float x = (m < N && cell < nc) ? (float)w[(long)(v * N + m) * nc + cell] : 0.0f;
+      A[e] = (__bf16)x;
+      Al[e] = (__bf16)(x - (float)A[e]);
     }
 #pragma unroll
     for (int t = 0; t < M::NQT; ++t) {
       const bf16x8 B = *reinterpret_cast<const bf16x8 *>(tb + M::PB + (16 * t + row) * NP + 8 * grp);
+      const bf16x8 Bl = *reinterpret_cast<const bf16x8 *>(tb + M::LO + M::PB + (16 * t + row) * NP + 8 * grp);
       f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B, z, 0, 0, 0);
+      z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bl, z, 0, 0, 0);
       U[v][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, z, 0, 0, 0);
     }
   }
@@ -1745,7 +1757,11 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
           for (int v = 0; v < NV; ++v) F[v] = 0.0f;
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) fs[wv][v][cl][q] = (__bf16)F[v];
+        for (int v = 0; v < NV; ++v) {
+          const __bf16 hi = (__bf16)F[v];
+          fs[0][wv][v][cl][q] = hi;
+          fs[1][wv][v][cl][q] = (__bf16)(F[v] - (float)hi);
+        }
       }
     __syncthreads();
 #pragma unroll
@@ -1754,9 +1770,13 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
       for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int ch = 0; ch < M::NQC; ++ch) {
-          const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&fs[wv][v][row][ch * 32 + 8 * grp]);
-          const bf16x8 B =
-              *reinterpret_cast<const bf16x8 *>(tb + M::DB + (a * NP + mt * 16 + row) * QP + ch * 32 + 8 * grp);
+          const bf16x8 A = *reinterpret_cast<const bf16x8 *>(&fs[0][wv][v][row][ch * 32 + 8 * grp]);
+          const bf16x8 Al = *reinterpret_cast<const bf16x8 *>(&fs[1][wv][v][row][ch * 32 + 8 * grp]);
+          const long tbo = M::DB + (a * NP + mt * 16 + row) * QP + ch * 32 + 8 * grp;
+          const bf16x8 B = *reinterpret_cast<const bf16x8 *>(tb + tbo);
+          const bf16x8 Bl = *reinterpret_cast<const bf16x8 *>(tb + M::LO + tbo);
+          acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, B, acc[v][mt], 0, 0, 0);
+          acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, Bl, acc[v][mt], 0, 0, 0);
           acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[v][mt], 0, 0, 0);
         }
     __syncthreads();  // the next direction overwrites fs
@@ -2564,6 +2584,29 @@ __global__ void k_box_init(int *box) {
   else if (threadIdx.x < 6) box[threadIdx.x] = -1;
 }
 
+// The refined box of the next mesh from the flagged range (min i, max i) per
+// axis: the range grown by the one buffer layer of Sec. 4 (every flagged
+// cell's neighbours are refined too), clipped to [1, n-1] so that the box
+// keeps one coarse layer to the domain boundary; box = (lo[3], hi[3]) in
+// refine_lo / refine_hi form, all zero when nothing is flagged or the
+// clipped box is empty along some axis.
+__global__ void k_box_final(int *box, int d, int nx, int ny, int nz) {
+  if (threadIdx.x != 0) return;
+  const int n[3] = {nx, ny, nz};
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  bool ok = true;
+  for (int a = 0; a < d; ++a) {
+    if (box[a] > box[3 + a]) ok = false;  // nothing flagged
+    lo[a] = max(1, box[a] - 1);
+    hi[a] = min(n[a] - 1, box[3 + a] + 2);
+    if (hi[a] <= lo[a]) ok = false;
+  }
+  for (int a = 0; a < 3; ++a) {
+    box[a] = ok ? lo[a] : 0;
+    box[3 + a] = ok ? hi[a] : 0;
+  }
+}
+
 // State on mesh B from a state on mesh A (same base grid): one thread per
 // base cell of B, then per fine cell of B.  A base cell outside B's box is
 // copied, or derefined (eq. deref_weights) if it was in A's box; one inside
@@ -3119,6 +3162,13 @@ uint16_t to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
+float from_bf16(uint16_t h) {
+  const uint32_t u = (uint32_t)h << 16;
+  float f;
+  std::memcpy(&f, &u, sizeof(f));
+  return f;
+}
+
 struct Bf16Tables {
   const dg_ctx *c;
   std::vector<uint16_t> *out;
@@ -3132,12 +3182,19 @@ struct Bf16Tables {
       std::vector<uint16_t> &t = *out;
       t.assign(M::TOTAL, 0);
       const std::vector<double> &h = c->host_tab;
+      // each table value x as hi = bf16(x) at offset o and lo = bf16(x - hi)
+      // at offset LO + o
+      auto put = [&](long o, double x) {
+        const uint16_t hi = to_bf16((float)x);
+        t[o] = hi;
+        t[M::LO + o] = to_bf16((float)(x - (double)from_bf16(hi)));
+      };
       for (int q = 0; q < C::Q; ++q)
-        for (int m = 0; m < C::N; ++m) t[M::PB + q * M::NP + m] = to_bf16((float)h[C::B + q * C::N + m]);
+        for (int m = 0; m < C::N; ++m) put(M::PB + q * M::NP + m, h[C::B + q * C::N + m]);
       for (int a = 0; a < D; ++a)
         for (int m = 0; m < C::N; ++m)
           for (int q = 0; q < C::Q; ++q)
-            t[M::DB + (a * M::NP + m) * M::QP + q] = to_bf16((float)h[C::DW + (a * C::Q + q) * C::N + m]);
+            put(M::DB + (a * M::NP + m) * M::QP + q, h[C::DW + (a * C::Q + q) * C::N + m]);
       return DG_OK;
     }
   }
@@ -3250,23 +3307,6 @@ dg::BoxGrid box_grid(const dg_ctx *c) {
   return g;
 }
 
-// the refinement matrices on the device (allocated on first use)
-int ensure_prmat(dg_ctx *c) {
-  if (c->prmat) return DG_OK;
-  const std::vector<double> P = dg::refine_matrices(c->sh);
-  HIP_TRY(hipSetDevice(c->device));
-  double *d = nullptr;
-  hipError_t e = hipMalloc(&d, P.size() * sizeof(double));
-  if (e != hipSuccess) return e == hipErrorOutOfMemory ? DG_ENOMEM : DG_EHIP;
-  e = hipMemcpy(d, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(d);
-    return hip_fail(e);
-  }
-  c->prmat = d;
-  return DG_OK;
-}
-
 struct AmrFlagsLaunch {
   dg_ctx *c;
   const double *w;
@@ -3280,6 +3320,8 @@ struct AmrFlagsLaunch {
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL((dg::k_amr_flags<D, K>), dim3(nblocks(g.ncc)), dim3(kBlock), 0, s, w, c->prmat, g, thr_cell,
                        thr_node, flags, box);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(dg::k_box_final, dim3(1), dim3(64), 0, s, box, D, g.n[0], g.n[1], g.n[2]);
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
@@ -3350,6 +3392,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if (cfg->slope_limiter != DG_LIM_NONE && cfg->slope_limiter != DG_LIM_MINMOD && cfg->slope_limiter != DG_LIM_CHAR)
     return DG_EUNSUPPORTED;
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
+  if (cfg->tile2d != DG_TILE2D_AUTO && cfg->tile2d != DG_TILE2D_8X8 && cfg->tile2d != DG_TILE2D_LARGE)
+    return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
   bool amr = false;
   for (int a = 0; a < cfg->dim; ++a)
@@ -3401,7 +3445,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   double fk = 1.0 / (2.0 * cfg->k + 1.0);
   if (cfg->positivity && c->gll_w1 / 2.0 < fk) fk = c->gll_w1 / 2.0;
   c->cfl_fk = cfg->cfl * fk;
-  if (const char *ts = std::getenv("DG_TILE2D_SMALL")) c->tile_small = (ts[0] == '1') ? 1 : (ts[0] == '0') ? 0 : -1;
+  c->tile_small = cfg->tile2d == DG_TILE2D_8X8 ? 1 : cfg->tile2d == DG_TILE2D_LARGE ? 0 : -1;
   {
     static const double a3[9] = {0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.25, 0.25, 0.0};
     static const double b3[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
@@ -3444,6 +3488,13 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const std::vector<double> zeros(DG_RATE_STATE, 0.0);
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
+  if (cfg->k <= 3) {
+    // refinement matrices of dg_amr_flags / dg_amr_regrid (eq. ref_pa_integral)
+    const std::vector<double> P = dg::refine_matrices(c->sh);
+    if ((e = hipMalloc((void **)&c->prmat, P.size() * sizeof(double))) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(c->prmat, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e);
+  }
   *out = c;
   return DG_OK;
 }
@@ -3660,8 +3711,6 @@ int dg_set_gravity(dg_ctx *c, const double *accel, void *stream) {
 int dg_amr_flags(dg_ctx *c, const double *w, double wt, double alpha, int *flags, int *box, void *stream) {
   if (!c || !w || !flags || !box || !(wt > 0.0) || !(alpha >= 1.0)) return DG_EINVAL;
   if (c->sh.k > 3) return DG_EUNSUPPORTED;
-  const int st = ensure_prmat(c);
-  if (st != DG_OK) return st;
   return dispatch(c, AmrFlagsLaunch{c, w, alpha * wt, wt / alpha, flags, box, (hipStream_t)stream});
 }
 
@@ -3673,8 +3722,6 @@ int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *
   for (int a = 0; a < 3; ++a)
     if (from->cfg.x0[a] != to->cfg.x0[a]) return DG_EINVAL;
   if (to->sh.k > 3) return DG_EUNSUPPORTED;
-  const int st = ensure_prmat(to);
-  if (st != DG_OK) return st;
   return dispatch(to, AmrRegridLaunch{from, w_from, to, w_to, (hipStream_t)stream});
 }
 

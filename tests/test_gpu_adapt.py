@@ -10,9 +10,9 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_state
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 def _dev(a):
@@ -27,19 +27,6 @@ def _host(t):
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def _err(o, got, ref):
-    if isinstance(o, oracle.AmrOracle):
-        g, r = np.asarray(got).reshape(-1), np.asarray(ref).reshape(-1)
-        c1, f1 = o.blocks(g)
-        c2, f2 = o.blocks(r)
-        g = np.concatenate([c1.reshape(o.nvar, -1), f1.reshape(o.nvar, -1)], axis=1)
-        r = np.concatenate([c2.reshape(o.nvar, -1), f2.reshape(o.nvar, -1)], axis=1)
-    else:
-        g, r = np.asarray(got).reshape(o.nvar, -1), np.asarray(ref).reshape(o.nvar, -1)
-    norm = np.abs(r).sum(axis=1)
-    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
 
 
 def _kh(k, n=26):
@@ -74,21 +61,19 @@ def test_flags_and_regrid_match_oracle(case, make, k):
     d = _dev(w)
     # flags on the base grid
     ref = oracle.amr_flags(wl, w)
-    flags, rng = s.amr_flags(d)
+    flags, gbox = s.amr_flags(d)
     got = _host(flags)
     _say(case, "flagged", int(ref.sum()), "of", ref.size)
     assert 0 < ref.sum() < ref.size
     assert np.array_equal(got, ref)
     box = oracle.box_from_flags(wl, ref)
-    assert s.box_for(rng) == box
+    assert gbox == box
     # refine into the box
     wlb = _with_box(wl, box)
     refw = oracle.regrid(wl, w, wlb)
     sb, db = s.regrid(d, box)
     ob = oracle.make(wlb)
-    err = _err(ob, _host(db), refw)
-    _say(case, "refine rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(ob, _host(db), refw, f"{case} refine")
     np.testing.assert_allclose(ob.totals(_host(db)), o.totals(w), rtol=0, atol=1e-14 * np.abs(o.totals(w)).max())
     # flags on the boxed mesh (node weights inside the box)
     refb = oracle.amr_flags(wlb, refw)
@@ -100,13 +85,10 @@ def test_flags_and_regrid_match_oracle(case, make, k):
     wlm = _with_box(wl, moved)
     refm = oracle.regrid(wlb, refw, wlm)
     sm, dm = sb.regrid(db, moved)
-    err = _err(oracle.make(wlm), _host(dm), refm)
-    assert np.all(err <= TOL), err
+    check_state(oracle.make(wlm), _host(dm), refm, f"{case} move")
     s0, d0 = sm.regrid(dm, None)
     ref0 = oracle.regrid(wlm, refm, wl)
-    err = _err(o, _host(d0), ref0)
-    _say(case, "derefine rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(d0), ref0, f"{case} derefine")
     np.testing.assert_allclose(o.totals(_host(d0)), o.totals(w), rtol=0, atol=1e-14 * np.abs(o.totals(w)).max())
     assert s0.status() == 0
 
@@ -139,8 +121,7 @@ def test_adaptive_kh_steps_follow_the_oracle():
         cur = new
         oc = oracle.make(cur)
         ref, dt_ref = oc.step(ref)
-        _, rng = s.amr_flags(d, wl["wt"], wl["alpha"])
-        gbox = s.box_for(rng)
+        _, gbox = s.amr_flags(d, wl["wt"], wl["alpha"])
         assert gbox == box, (i, gbox, box)
         s, d = s.regrid(d, gbox)
         bufs = [s.empty() for _ in range(3)]
@@ -148,7 +129,5 @@ def test_adaptive_kh_steps_follow_the_oracle():
         s.max_rate(d, rate)
         d = s.rk_step(d, bufs, dt, rate).clone()
         assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
-        err = _err(oc, _host(d), ref)
-        _say("adaptive KH step", i, "box", box, "rel-L1", err)
-        assert np.all(err <= TOL), (i, err)
+        check_state(oc, _host(d), ref, f"adaptive KH step {i} box {box}")
     assert s.status() == 0

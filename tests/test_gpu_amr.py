@@ -1,6 +1,6 @@
 """GPU parity on the static 2:1 refined box (hanging faces, AMR limiting)
-against the FP64 oracle; tolerances as in test_gpu_parity (states: relative L1
-<= 1e-12 per variable; the RHS: <= 1e-12 of fac(|V| + |S|))."""
+against the FP64 oracle; comparison rules of tests/parity.py (states: relative
+L1 and per-element bounds of 1e-12; the RHS against fac(|V| + |S|))."""
 import sys
 
 import numpy as np
@@ -8,9 +8,9 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_rhs, check_state
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 def _dev(a):
@@ -31,17 +31,6 @@ def _per_var(o, x):
     """Flat AMR state -> [nvar][...] (both blocks, hole cells removed)."""
     c, f = o.blocks(x)
     return np.concatenate([c[:, :, ~o.hole].reshape(o.nvar, -1), f.reshape(o.nvar, -1)], axis=1)
-
-
-def rel_l1(o, got, ref):
-    g, r = _per_var(o, got), _per_var(o, ref)
-    norm = np.abs(r).sum(axis=1)
-    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-
-
-def rhs_err(o, L, V, S):
-    L, V, S = _per_var(o, L), _per_var(o, V), _per_var(o, S)
-    return np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
 
 
 def _wl(dim, k, n, lo, hi, **kw):
@@ -100,19 +89,15 @@ def test_amr_rhs_stage_dt_match_oracle(case, spec):
     assert s.amr and s.ncoarse == o.ncoarse and s.nfine == o.nfine
     w = _limited_state(o)
     d = _dev(w)
-    V, S = o.terms_cells(w)
+    V, S, A = o.terms_cells(w, with_abs=True)
     L = _host(s.rhs(d))
-    err = rhs_err(o, L, V, S)
-    _say(case, "AMR rhs error / (|V|+|S|)", err)
-    assert np.all(err <= TOL), err
+    check_rhs(o, L, V, S, A, f"{case} AMR rhs")
     dt = o.max_dt(w)
     dtd = s.max_dt(d)
     assert float(_host(dtd)[0]) == pytest.approx(dt, rel=1e-14)
     ref = o.rk3_stage(1, dt, w, w)
     got = _host(s.rk_stage(1, dtd, None, d))
-    serr = rel_l1(o, got, ref)
-    _say(case, "AMR stage-1 rel-L1", serr)
-    assert np.all(serr <= TOL), serr
+    check_state(o, got, ref, f"{case} AMR stage-1")
     # conservation of the GPU right-hand side across the interface
     Lc, Lf = o.blocks(L)
     tot = Lc[:, 0, ~o.hole].sum(axis=1) * o.dx ** o.dim + Lf[:, 0, :].sum(axis=1) * o.dxf ** o.dim
@@ -139,10 +124,8 @@ def test_amr_limiter_matches_oracle(case, spec, ic):
     d = _dev(w)
     s.limit(d)
     got = _host(d)
-    err = rel_l1(o, got, ref)
-    _say(case, "AMR limiter rel-L1", err, "cells changed",
-         int((np.abs(_per_var(o, ref) - _per_var(o, w)) > 0).any(axis=0).sum()))
-    assert np.all(err <= TOL), err
+    _say(case, "cells changed by the limiter", int((np.abs(_per_var(o, ref) - _per_var(o, w)) > 0).any(axis=0).sum()))
+    check_state(o, got, ref, f"{case} AMR limiter")
     assert s.status() == 0
 
 
@@ -163,9 +146,7 @@ def test_amr_limited_steps_match_oracle(case, spec):
     w = _dev(w0)
     for _ in range(2):
         w = s.step(w, bufs).clone()
-    err = rel_l1(o, _host(w), ref)
-    _say(case, "AMR 2 limited steps rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(w), ref, f"{case} AMR 2 limited steps")
     np.testing.assert_allclose(o.totals(_host(w)), o.totals(w0), rtol=1e-12, atol=1e-14)
 
 
@@ -186,7 +167,7 @@ def test_amr_projection_matches_oracle():
     ref = np.zeros(o.size)
     assert lib.orc_amr_project(C.byref(o.c), np.ascontiguousarray(prim), ref) == 0
     got = _host(s.project(_dev(np.transpose(prim, (2, 1, 0)))))
-    assert np.all(rel_l1(o, got, ref) <= 1e-14)
+    check_state(o, got, ref, "AMR projection", tol=1e-14)
     # the library's own node coordinates agree with the oracle's
     xs = s.node_coords()
     np.testing.assert_allclose(np.transpose(xs, (2, 1, 0)), x, atol=1e-15)

@@ -1,23 +1,31 @@
-"""GPU: the 3D workloads at their full sizes, in the launch configuration the
-benchmark times.  The 128^3 k = 2 shear layer is checked on a seeded sample
-of cells that the oracle evaluates one by one (RHS in FP64 and with the
-FP32 contractions, an unlimited stage); its layers lie on cell faces, so the
-projected state needs no limiting.  The oracle's whole-mesh limiter (about
-40 s at either size) and RHS of the refined blast (about 90 s) are too slow
-for a test, so the limited paths are held at full size to properties that
-hold at any size: conservation of the RHS, a positive limited step, and the
-BF16 volume path against FP64 within the stated precision bound (parity of
-the limiters and the refined box at reduced sizes is in test_gpu_parity,
-test_gpu_amr and test_gpu_precision)."""
-import sys
+"""GPU parity at the workloads' full sizes, in the launch configuration the
+benchmark times, against the FP64 oracle (comparison rules of tests/parity.py).
 
+  * 2D vortex 256^2, k = 2: the whole 200-step trajectory of one-call steps
+    against the oracle's run (about a minute of oracle time).
+  * 3D shear layer 128^3, k = 2, minmod + positivity, and the 3D blast on the
+    64^3 base grid with the refined 32^3 box, k = 3: one limited SSP-RK3 step
+    taken as its parts (limit of the projected state, time step, each stage,
+    each limiter pass) and each part checked on a seeded sample of cells
+    against the oracle's per-cell entries applied to the GPU's own input of
+    that part; the sample of the refined mesh holds every kind of face next
+    to the refinement boundary (coarse cells with a hanging face on each of
+    the six sides, fine cells on every face, edge and corner of the fine
+    block).  The one-call step must equal the composed parts bit for bit.
+  * Conservation of the full right-hand sides and the reduced-precision
+    paths against FP64 at full size (FP32 contractions: RHS within 1e-6 of
+    |V| + |S|; BF16 volume: relative L1 1e-2 after one step).
+"""
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from parity import check_rhs_modes, check_state_modes, rel_l1, say, stage_scale
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+# Shu-Osher coefficients (a, b) of the SSP-RK3 stages u = a w^n + b (u_prev + dt L)
+RK3 = ((0.0, 1.0), (0.75, 0.25), (1.0 / 3.0, 2.0 / 3.0))
 
 
 def _dev(a):
@@ -29,51 +37,189 @@ def _host(t):
     return t.detach().cpu().numpy()
 
 
-def _say(*a):
-    print(*a, flush=True)
-    sys.stdout.flush()
-
-
-def test_full_size_kh3d_sampled():
+@pytest.mark.timeout(600)
+def test_full_size_vortex_trajectory():
+    # 256^2, k = 2, seeded noise, 200 SSP-RK3 steps, CFL 0.2, no limiter
     import paper_1506_06140_amd as dg
-    wl = workloads.workload("kh3d")  # 128^3, k = 2, minmod + positivity
+    wl = workloads.workload("vortex")
     o = oracle.Oracle(wl)
-    w0 = o.initial_state()
-    nv, N = o.nvar, o.N
-    rng = np.random.default_rng(128)
-    cells = np.unique(np.concatenate([rng.integers(0, o.ncell, 3000), [0, 127, o.ncell - 128, o.ncell - 1]]))
-    V, S = o.terms_cells(w0, cells)
-    d0 = _dev(w0)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
-        s = dg.Solver(wl, prec)
-        L = _host(s.rhs(d0)).reshape(nv, N, -1)[:, :, cells]
-        err = np.abs(L - (V - S)).reshape(nv, -1).sum(axis=1) / (np.abs(V) + np.abs(S)).reshape(nv, -1).sum(axis=1)
-        _say("kh3d 128^3", prec, "sampled rhs error / (|V|+|S|)", err)
-        assert np.all(err <= tol), (prec, err)
-        full = _host(s.rhs(d0)).reshape(nv, N, -1)[:, 0, :]
-        assert np.all(np.abs(full.sum(axis=1)) <= 1e-13 * np.abs(full).sum(axis=1))  # conservative
-    # one stage on the sample
     s = dg.Solver(wl)
+    w0 = o.initial_state()
+    fb = [s.empty() for _ in range(3)]
+    dt, rate = s.scalar(), s.rate_state()
+    w = _dev(w0)
+    s.max_rate(w, rate)
+    for _ in range(wl["steps"]):
+        w = s.rk_step(w, fb, dt, rate).clone()
+    got = _host(w)
+    assert s.status() == 0
+    say("vortex 256^2: GPU run done, oracle run of", wl["steps"], "steps")
+    ref, _ = o.run(w0, wl["steps"])
+    check_state_modes(got.reshape(o.nvar, o.N, -1), ref.reshape(o.nvar, o.N, -1), "vortex 256^2 200 steps")
+    tot0, tot = o.totals(w0), o.totals(got)
+    np.testing.assert_allclose(tot, tot0, rtol=1e-12, atol=1e-13)
+
+
+def _kh3d_cells(o):
+    n = o.wl["n"]
+    rng = np.random.default_rng(128)
+    cells = list(rng.integers(0, o.ncell, 2000))
+    # cells on both sides of the shear interfaces y = 32/128 and 96/128, and
+    # the corners of the periodic box
+    for iy in (31, 32, 95, 96):
+        for _ in range(100):
+            ix, iz = rng.integers(0, n[0]), rng.integers(0, n[2])
+            cells.append((iz * n[1] + iy) * n[0] + ix)
+    for iz in (0, n[2] - 1):
+        for iy in (0, n[1] - 1):
+            for ix in (0, n[0] - 1):
+                cells.append((iz * n[1] + iy) * n[0] + ix)
+    return np.unique(np.asarray(cells, dtype=np.int64))
+
+
+def _blast_cells(o):
+    n, lo, hi = o.wl["n"], o.wl["refine_lo"], o.wl["refine_hi"]
+    nf = o.nf
+    rng = np.random.default_rng(5)
+    coarse, fine = [], []
+
+    def cidx(i):
+        return (i[2] * n[1] + i[1]) * n[0] + i[0]
+
+    def fidx(f):
+        return o.ncoarse + (f[2] * nf[1] + f[1]) * nf[0] + f[0]
+
+    # coarse cells with a hanging face on each side of the box (faces, and
+    # along the box's edges: two hanging faces)
+    for a in range(3):
+        for side in (lo[a] - 1, hi[a]):
+            for _ in range(60):
+                i = [int(rng.integers(lo[b], hi[b])) for b in range(3)]
+                i[a] = side
+                coarse.append(cidx(i))
+            for b in range(3):
+                if b != a:
+                    i = [int(rng.integers(lo[c], hi[c])) for c in range(3)]
+                    i[a] = side
+                    i[b] = lo[b]
+                    coarse.append(cidx(i))
+    # fine cells on every face, edge and corner of the fine block
+    for a in range(3):
+        for side in (0, nf[a] - 1):
+            for _ in range(60):
+                f = [int(rng.integers(0, nf[b])) for b in range(3)]
+                f[a] = side
+                fine.append(fidx(f))
+    for c in range(8):
+        fine.append(fidx([(nf[a] - 1) if (c >> a) & 1 else 0 for a in range(3)]))
+    # random cells of both blocks (the coarse ones outside the hole)
+    ok = np.flatnonzero(~o.hole)
+    coarse += list(rng.choice(ok, 800, replace=False))
+    fine += list(o.ncoarse + rng.integers(0, o.nfine, 800))
+    return np.unique(np.asarray(coarse + fine, dtype=np.int64))
+
+
+def _take(o, x, cells):
+    """[nvar][N][len(cells)] of a state (either mesh kind)."""
+    if isinstance(o, oracle.AmrOracle):
+        return o.cells_of(x, cells)
+    return np.asarray(x).reshape(o.nvar, o.N, -1)[:, :, cells]
+
+
+def _limited_step_parts(name, o, s, w0, cells):
+    """One limited SSP-RK3 step as its parts, each checked on `cells`.
+    Returns the composed end state (device)."""
+    d0 = _dev(w0)
+    # the main loop limits the projected state first
+    s.limit(d0)
+    lim0 = _host(d0)
+    ref, st = o.limit_cells(w0, cells)
+    assert st == 0
+    check_state_modes(_take(o, lim0, cells), ref, f"{name}: limiter on the projected state")
+    # time step of the limited state
     dt = s.max_dt(d0)
     dt_h = float(_host(dt)[0])
-    assert dt_h == pytest.approx(o.max_dt(w0), rel=1e-14)
-    u1 = s.rk_stage(1, dt, None, d0)
-    got = _host(u1).reshape(nv, N, -1)
-    ref_cells = w0.reshape(nv, N, -1)[:, :, cells] + dt_h * o.rhs_cells(w0, cells)
-    g = got[:, :, cells].reshape(nv, -1)
-    r = ref_cells.reshape(nv, -1)
-    e = np.abs(g - r).sum(axis=1) / np.abs(r).sum(axis=1).clip(1e-300)
-    _say("kh3d 128^3 stage-1 sampled rel-L1", e)
-    assert np.all(e <= 1e-12), e
-    # the limiters keep the means of the full state, bit for bit
-    s.limit(u1)
-    assert np.array_equal(_host(u1).reshape(nv, N, -1)[:, 0], got[:, 0])
+    assert dt_h == pytest.approx(o.max_dt(lim0), rel=1e-14)
+    # the right-hand side of the step's input
+    V, S, A = o.terms_cells(lim0, cells, with_abs=True)
+    L = _host(s.rhs(d0))
+    check_rhs_modes(_take(o, L, cells), V, S, A, f"{name}: rhs")
+    prev = d0
+    for stage in (1, 2, 3):
+        u = s.rk_stage(stage, dt, None if stage == 1 else d0, prev)
+        uh = _host(u)
+        prev_host = _host(prev)
+        prev_h = _take(o, prev_host, cells)
+        wn_h = _take(o, lim0, cells)
+        ref = oracle.rk3_combine(stage, dt_h, wn_h, prev_h, o.rhs_cells(prev_host, cells))
+        _, _, A = o.terms_cells(prev_host, cells, with_abs=True)
+        a, b = RK3[stage - 1]
+        check_state_modes(_take(o, uh, cells), ref, f"{name}: stage {stage}",
+                          scale=stage_scale(a, b, dt_h, wn_h, prev_h, A))
+        s.limit(u)
+        ref, st = o.limit_cells(uh, cells)
+        assert st == 0
+        check_state_modes(_take(o, _host(u), cells), ref, f"{name}: limiters after stage {stage}")
+        prev = u
     assert s.status() == 0
+    # the benchmark's one-call step from the same limited state: bitwise the parts
+    fb = [s.empty() for _ in range(3)]
+    dtb, rate = s.scalar(), s.rate_state()
+    s.max_rate(d0, rate)
+    w1 = s.rk_step(d0, fb, dtb, rate)
+    assert float(_host(dtb)[0]) == dt_h
+    assert np.array_equal(_host(w1), _host(prev))
+    return prev
 
 
-def test_full_size_blast_amr_properties():
+@pytest.mark.timeout(600)
+def test_full_size_kh3d_limited_step_sampled():
+    # 128^3, k = 2, component-wise minmod (TVB) + positivity
     import paper_1506_06140_amd as dg
-    wl = workloads.workload("blast_amr", eps=1e-4)  # 64^3 + refined 32^3 box, k = 3
+    wl = workloads.workload("kh3d")
+    o = oracle.Oracle(wl)
+    w0 = o.initial_state()
+    cells = _kh3d_cells(o)
+    say("kh3d 128^3:", cells.size, "sampled cells")
+    s = dg.Solver(wl)
+    w1 = _host(_limited_step_parts("kh3d 128^3", o, s, w0, cells))
+    tot0 = o.totals(w0)
+    np.testing.assert_allclose(o.totals(w1), tot0, rtol=0, atol=1e-12 * np.abs(tot0).max())
+    # FP32 contractions at full size: RHS within 1e-6 of |V| + |S|, conservative
+    V, S = o.terms_cells(w0, cells)
+    d0 = _dev(w0)
+    L = _host(dg.Solver(wl, "fp32").rhs(d0)).reshape(o.nvar, o.N, -1)
+    err = np.abs(L[:, :, cells] - (V - S)).reshape(o.nvar, -1).sum(1) / (np.abs(V) + np.abs(S)).reshape(
+        o.nvar, -1).sum(1)
+    say("kh3d 128^3 fp32 sampled rhs error / (|V|+|S|)", err)
+    assert np.all(err <= 1e-6), err
+    assert np.all(np.abs(L[:, 0].sum(axis=1)) <= 1e-13 * np.abs(L[:, 0]).sum(axis=1))
+
+
+@pytest.mark.timeout(600)
+def test_full_size_blast_amr_limited_step_sampled():
+    # 64^3 base grid, central base cells [16, 48)^3 refined 2:1, k = 3,
+    # minmod + positivity.  The positivity floor is 1e-3 (the run's is
+    # 1e-10): at a 1e-10 floor the face-node densities come from cancellation
+    # of O(1) terms and carry ~1e-6 relative rounding in any implementation,
+    # which the 1e-12 bound cannot resolve.
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("blast_amr", eps=1e-3)
+    o = oracle.AmrOracle(wl)
+    w0 = o.initial_state()
+    cells = _blast_cells(o)
+    say("blast 64^3 + box:", cells.size, "sampled cells")
+    s = dg.Solver(wl)
+    w1 = _host(_limited_step_parts("blast 64^3 + box", o, s, w0, cells))
+    tot0 = o.totals(w0)
+    np.testing.assert_allclose(o.totals(w1), tot0, rtol=0, atol=1e-12 * np.abs(tot0).max())
+
+
+def test_full_size_blast_amr_reduced_precision():
+    # one limited step of the BF16-volume path against the FP64 path at full
+    # size: relative L1 <= 1e-2 per variable; both conservative
+    import paper_1506_06140_amd as dg
+    wl = workloads.workload("blast_amr", eps=1e-4)
     o = oracle.AmrOracle(wl)
     d0 = _dev(o.initial_state())
     dg.Solver(wl).limit(d0)  # the main loop limits the projected state first
@@ -86,20 +232,13 @@ def test_full_size_blast_amr_properties():
         Lc, Lf = o.blocks(L)
         tot = Lc[:, 0, ~o.hole].sum(axis=1) * o.dx ** 3 + Lf[:, 0, :].sum(axis=1) * o.dxf ** 3
         scale = np.abs(Lc[:, 0, ~o.hole]).sum(axis=1) * o.dx ** 3 + np.abs(Lf[:, 0, :]).sum(axis=1) * o.dxf ** 3
-        _say("blast", prec, "rhs total / scale", tot / scale)
+        say("blast", prec, "rhs total / scale", tot / scale)
         assert np.all(np.abs(tot) <= 1e-13 * scale)
         bufs = [s.empty() for _ in range(3)] + [s.scalar()]
         w = s.step(d0, bufs)
         assert s.status() == 0  # positive means after the limited step
         res[prec] = _host(w)
         np.testing.assert_allclose(o.totals(res[prec]), tot0, rtol=0, atol=1e-12 * np.abs(tot0).max())
-    c64, f64 = o.blocks(res["fp64"])
-    cbf, fbf = o.blocks(res["bf16"])
-    a = np.concatenate([c64[:, :, ~o.hole].reshape(o.nvar, -1), f64.reshape(o.nvar, -1)], axis=1)
-    b = np.concatenate([cbf[:, :, ~o.hole].reshape(o.nvar, -1), fbf.reshape(o.nvar, -1)], axis=1)
-    norm = np.abs(a).sum(axis=1)
-    err = np.abs(b - a).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-    _say("blast full size, one step, bf16 vs fp64 rel-L1", err)
-    tol = np.full(o.nvar, 1e-2)
-    tol[1:4] = 3e-2
-    assert np.all(err <= tol), err
+    err = rel_l1(o, res["bf16"], res["fp64"])
+    say("blast full size, one step, bf16 vs fp64 rel-L1", err)
+    assert np.all(err <= 1e-2), err

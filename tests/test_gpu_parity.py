@@ -1,16 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
-same seeded inputs.
-
-FP64 tolerances:
-  * states (after an RK stage, a step, a trajectory, the limiters): relative
-    L1 <= 1e-12 per conserved variable, sum |w_gpu - w_oracle| / sum |w_oracle|
-    over all modes and cells (a variable whose norm is below 1% of the largest
-    variable's norm, e.g. a momentum that vanishes in exact arithmetic, is
-    measured against that 1%);
-  * the right-hand side L = fac (V - S) alone: sum |L_gpu - L_oracle| <= 1e-12
-    sum fac (|V| + |S|) per variable.  L is a difference of two nearly equal
-    integrals in smooth flow, so its rounding error scales with |V| + |S|, not
-    with |L|; this bound states that (about 1e4 unit roundoffs of the terms).
+same seeded inputs.  The comparison rules (relative L1 and per-element bounds
+of 1e-12 on states, the right-hand side against |V| + |S|) are those of
+tests/parity.py.
 """
 import sys
 
@@ -19,10 +10,9 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_rhs_modes, check_state, check_state_modes
 
 pytestmark = pytest.mark.gpu
-
-TOL = 1e-12
 
 
 def _dev(a):
@@ -32,22 +22,6 @@ def _dev(a):
 
 def _host(t):
     return t.detach().cpu().numpy()
-
-
-def rel_l1(got, ref):
-    got = np.asarray(got).reshape(got.shape[0], -1)
-    ref = np.asarray(ref).reshape(ref.shape[0], -1)
-    norm = np.abs(ref).sum(axis=1)
-    return np.abs(got - ref).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-
-
-def rhs_err(L, V, S):
-    """Per-variable error of L against the oracle's V - S, relative to |V| + |S|."""
-    nv = V.shape[0]
-    L = np.asarray(L).reshape(nv, -1)
-    V = V.reshape(nv, -1)
-    S = S.reshape(nv, -1)
-    return np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
 
 
 def _solver(wl):
@@ -129,19 +103,15 @@ def test_rhs_matches_oracle(case, spec):
     o = oracle.Oracle(wl)
     s = _solver(wl)
     for w in _inputs(o, case, wl):
-        V, S = o.terms_cells(w)
-        L = _host(s.rhs(_dev(w)))
-        err = rhs_err(L, V, S)
-        _say(case, "rhs error / (|V|+|S|)", err, "rel-L1 to L", rel_l1(L, (V - S).reshape(L.shape)))
-        assert np.all(err <= TOL), err
+        V, S, A = o.terms_cells(w, with_abs=True)
+        L = _host(s.rhs(_dev(w))).reshape(V.shape)
+        check_rhs_modes(L, V, S, A, f"{case} rhs")
         # a stage from the same input: state-level relative L1
         dt = 0.5 * o.max_dt(w)
         ref = o.rk3_stage(1, dt, w, w)
         dtd = _dev(np.array([dt]))
         got = _host(s.rk_stage(1, dtd, None, _dev(w)))
-        serr = rel_l1(got, ref)
-        _say(case, "stage-1 state rel-L1", serr)
-        assert np.all(serr <= TOL), serr
+        check_state(o, got, ref, f"{case} stage-1 state")
     assert s.status() == 0
 
 
@@ -161,9 +131,7 @@ def test_rk_stages_and_dt_match_oracle(case, spec):
     for stage in (1, 2, 3):
         ref = o.rk3_stage(stage, dt_ref, w0, ref)
         u = s.rk_stage(stage, dt, d0, u)
-        err = rel_l1(_host(u), ref)
-        _say(case, "stage", stage, err)
-        assert np.all(err <= TOL), (stage, err)
+        check_state(o, _host(u), ref, f"{case} stage {stage}")
 
 
 def test_density_wave_trajectory_matches_oracle():
@@ -177,9 +145,7 @@ def test_density_wave_trajectory_matches_oracle():
     w = _dev(w0)
     for _ in range(wl["steps"]):
         w = s.step(w, bufs).clone()
-    err = rel_l1(_host(w), ref)
-    _say("density wave 20 steps rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(w), ref, "density wave 20 steps")
     # and it is the exact translated wave to the scheme's accuracy
     assert o.l1_density_error(_host(w), t_ref) < 2e-3
 
@@ -195,9 +161,7 @@ def test_vortex_trajectory_matches_oracle_reduced():
     w = _dev(w0)
     for _ in range(wl["steps"]):
         w = s.step(w, bufs).clone()
-    err = rel_l1(_host(w), ref)
-    _say("vortex 64^2 200 steps rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(w), ref, "vortex 64^2 200 steps")
     tot0, tot = o.totals(w0), o.totals(_host(w))
     _say("conservation drift", (tot - tot0) / np.abs(tot0).clip(1e-300))
     np.testing.assert_allclose(tot, tot0, rtol=1e-12, atol=1e-13)
@@ -219,15 +183,11 @@ def test_full_size_vortex_stage_sampled():
     u1 = _host(s.rk_stage(1, dt, None, d0)).reshape(o.nvar, o.N, -1)
     rng = np.random.default_rng(2024)
     cells = np.unique(np.concatenate([rng.integers(0, o.ncell, 3000), [0, 255, o.ncell - 256, o.ncell - 1]]))
-    V, S = o.terms_cells(w0, cells)
-    err = rhs_err(L[:, :, cells], V, S)
-    _say("full-size sampled rhs error / (|V|+|S|)", err)
-    assert np.all(err <= TOL), err
+    V, S, A = o.terms_cells(w0, cells, with_abs=True)
+    check_rhs_modes(L[:, :, cells], V, S, A, "full-size sampled rhs")
     w0c = w0.reshape(o.nvar, o.N, -1)[:, :, cells]
     ref = w0c + dt_h * o.rhs_cells(w0, cells)
-    serr = rel_l1(u1[:, :, cells], ref)
-    _say("full-size sampled stage-1 state rel-L1", serr)
-    assert np.all(serr <= TOL), serr
+    check_state_modes(u1[:, :, cells], ref, "full-size sampled stage-1 state")
     tot = L[:, 0, :].sum(axis=1)
     scale = np.abs(L[:, 0, :]).sum(axis=1)
     assert np.all(np.abs(tot) <= 1e-13 * scale)
@@ -250,9 +210,7 @@ def test_full_size_vortex_one_call_steps():
         ref, dt_ref = o.step(ref)
         w = s.rk_step(w, fb, dt, rate).clone()
         assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
-        err = rel_l1(_host(w), ref)
-        _say("full-size one-call step", i, "rel-L1", err)
-        assert np.all(err <= TOL), (i, err)
+        check_state(o, _host(w), ref, f"full-size one-call step {i}")
     assert s.status() == 0
 
 
@@ -269,9 +227,7 @@ def test_projection_matches_oracle():
         prim = np.stack(workloads.primitives(wlq, x[..., 0], x[..., 1], x[..., 2], cell=cell, node=node), axis=-1)
         ref = o.project_prim(prim)
         got = _host(s.project(_dev(np.transpose(prim, (2, 1, 0)))))
-        err = rel_l1(got, ref)
-        _say(name, "projection rel-L1", err)
-        assert np.all(err <= 1e-14), err
+        check_state(o, got, ref, f"{name} projection", tol=1e-14)
 
 
 @pytest.mark.parametrize("dim,k", [(2, 1), (2, 2), (2, 3), (2, 4), (3, 1), (3, 2), (3, 3)])
@@ -288,10 +244,9 @@ def test_limiter_matches_oracle(dim, k):
     s.limit(d)
     got = _host(d)
     assert np.array_equal(got[:, 0], w[:, 0])  # means untouched, bitwise
-    err = rel_l1(got, ref)
     changed = np.abs(ref - w).reshape(o.nvar, -1).max(axis=1)
-    _say("limiter", dim, k, "rel-L1", err, "max change", changed)
-    assert np.all(err <= TOL), err
+    _say("limiter", dim, k, "max change", changed)
+    check_state(o, got, ref, f"limiter {dim}D k={k}")
     assert s.status() == 0
 
 
@@ -308,9 +263,7 @@ def test_limited_stage_matches_oracle():
     assert _host(dtd)[0] == pytest.approx(dt, rel=1e-14)
     u = s.rk_stage(1, dtd, None, _dev(w0))
     s.limit(u)
-    err = rel_l1(_host(u), ref)
-    _say("kh3d 16^3 limited stage rel-L1", err)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(u), ref, "kh3d 16^3 limited stage")
 
 
 def test_error_flags():

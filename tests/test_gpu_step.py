@@ -4,8 +4,8 @@ composed calls (dg_max_dt, three dg_rk_stage, dg_limit) and the FP64 oracle.
 The fused step computes the same quantities in the same precision and order
 (the time step from the same per-cell rates, the stages from the same
 kernels), so it must equal the composed path bit for bit: dt, every state and
-the carried rate.  Against the oracle the state bound is that of
-test_gpu_parity (relative L1 <= 1e-12 per variable) and dt agrees to 1e-14.
+the carried rate.  Against the oracle the state bounds are those of
+tests/parity.py (relative L1 and per element 1e-12) and dt agrees to 1e-14.
 """
 import sys
 
@@ -14,9 +14,9 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_state
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 def _dev(a):
@@ -31,13 +31,6 @@ def _host(t):
 def _say(*a):
     print(*a, flush=True)
     sys.stdout.flush()
-
-
-def rel_l1(got, ref, nvar):
-    got = np.asarray(got).reshape(nvar, -1)
-    ref = np.asarray(ref).reshape(nvar, -1)
-    norm = np.abs(ref).sum(axis=1)
-    return np.abs(got - ref).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
 
 
 def _active(o, x):
@@ -137,9 +130,7 @@ def test_step_matches_oracle(case, spec, precision):
         ref, dt_ref = o.step(ref)
         w = s.rk_step(w, fb, dt, rate).clone()
         assert _host(dt)[0] == pytest.approx(dt_ref, rel=1e-14)
-        err = rel_l1(_active(o, _host(w)), _active(o, ref), o.nvar)
-        _say(case, "step", i, "rel-L1", err)
-        assert np.all(err <= TOL), (i, err)
+        check_state(o, _host(w), ref, f"{case} step {i}")
     # the carried rate gives the oracle's next time step
     dt_next = o.max_dt(ref)
     s.rk_step(w, fb, dt, rate)

@@ -1,7 +1,8 @@
 """GPU: general explicit Runge-Kutta integrators (App. D: tables RK_2, RK_4 and
 any explicit tableau) through dg_set_tableau, dg_tableau_stage and
 dg_tableau_step, against the FP64 oracle's own Shu-Osher form of the same
-tableau (states: relative L1 <= 1e-12 per variable, dt: 1e-14)."""
+tableau (states: relative L1 and per-element bounds of 1e-12 as in tests/parity.py,
+dt: 1e-14)."""
 import sys
 
 import numpy as np
@@ -9,10 +10,10 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_state
 from test_gpu_amr import _per_var, _wl
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 def _dev(a):
@@ -58,12 +59,6 @@ def _setup(spec):
     return wl, o, view, dg.Solver(wl), w0
 
 
-def _err(view, got, ref):
-    g, r = view(got), view(ref)
-    norm = np.abs(r).sum(axis=1)
-    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-
-
 STAGE_CASES = [
     ("vortex2d_k2", dict(name="vortex", n=(40, 24, 1), length=(10.0, 6.0, 1.0))),
     ("kh3d_k2", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), limiter=0, positivity=0)),
@@ -89,9 +84,7 @@ def test_tableau_stages_match_oracle(case, spec, tab):
     for m in range(1, len(b) + 1):
         ref = o.tableau_stage(A, b, m, dt, Y)
         got = s.tableau_stage(m, dtd, Yd)
-        err = _err(view, _host(got), ref)
-        _say(case, tab, "stage", m, "rel-L1", err)
-        assert np.all(err <= TOL), (m, err)
+        check_state(o, _host(got), ref, f"{case} {tab} stage {m}")
         Y.append(ref)
         Yd.append(got)
     assert s.status() == 0
@@ -138,9 +131,7 @@ def test_tableau_steps_match_oracle_and_composed_calls(case, spec):
         assert float(_host(dt)[0]) == comp_dt[i]
         assert np.array_equal(got, comp[i]), (i, np.abs(got - comp[i]).max())
         assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
-        err = _err(view, got, ref)
-        _say(case, "step", i, "rel-L1", err)
-        assert np.all(err <= TOL), (i, err)
+        check_state(o, got, ref, f"{case} step {i}")
     # the carried rate gives the oracle's next step
     s.rk_step(w, fb, dt, rate)
     assert float(_host(dt)[0]) == pytest.approx(o.max_dt(ref), rel=1e-14)

@@ -3,7 +3,6 @@
 the FP64 oracle on ragged grids: the RHS to 1e-12 of fac(|V| + |S|), three
 one-call steps to relative L1 1e-12 and dt to 1e-14, for k = 1..4, with the
 limiters and with transmissive walls."""
-import os
 import sys
 
 import numpy as np
@@ -11,9 +10,11 @@ import pytest
 
 import oracle
 import workloads
+from parity import check_rhs_modes, check_state
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
+# dg_config.tile2d values (DG_TILE2D_LARGE, DG_TILE2D_8X8)
+TILES = {"large": 2, "8x8": 1}
 
 
 def _dev(a):
@@ -34,25 +35,23 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("tiles", ["0", "1"])
+@pytest.mark.parametrize("tiles", ["large", "8x8"])
 @pytest.mark.parametrize("case,spec", CASES, ids=[c[0] for c in CASES])
-def test_tile_sizes_match_oracle(case, spec, tiles, monkeypatch):
+def test_tile_sizes_match_oracle(case, spec, tiles):
     import paper_1506_06140_amd as dg
-    monkeypatch.setenv("DG_TILE2D_SMALL", tiles)
     print("tiles", case, tiles, flush=True)
     spec = dict(spec)
     wl = workloads.workload(spec.pop("name"), **spec)
+    wl["tile2d"] = TILES[tiles]
     o = oracle.Oracle(wl)
     w0 = o.initial_state()
     if wl["limiter"] or wl["positivity"]:
         w0, st = o.limit(w0)
         assert st == 0
     s = dg.Solver(wl)
-    L = _host(s.rhs(_dev(w0))).reshape(o.nvar, -1)
-    V, S = o.terms_cells(w0)
-    V, S = V.reshape(o.nvar, -1), S.reshape(o.nvar, -1)
-    err = np.abs(L - (V - S)).sum(axis=1) / (np.abs(V) + np.abs(S)).sum(axis=1)
-    assert np.all(err <= TOL), err
+    V, S, A = o.terms_cells(w0, with_abs=True)
+    L = _host(s.rhs(_dev(w0))).reshape(V.shape)
+    check_rhs_modes(L, V, S, A, f"{case} tiles {tiles} rhs")
     fb = [s.empty() for _ in range(s.stages)]
     dt, rate = s.scalar(), s.rate_state()
     w = _dev(w0)
@@ -62,11 +61,7 @@ def test_tile_sizes_match_oracle(case, spec, tiles, monkeypatch):
         ref, dt_ref = o.step(ref)
         w = s.rk_step(w, fb, dt, rate).clone()
         assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
-        g, r = _host(w).reshape(o.nvar, -1), ref.reshape(o.nvar, -1)
-        norm = np.abs(r).sum(axis=1)
-        e = np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-        print(case, tiles, "step", i, e, flush=True)
-        assert np.all(e <= TOL), (i, e)
+        check_state(o, _host(w), ref, f"{case} tiles {tiles} step {i}")
     assert s.status() == 0
 
 
@@ -77,28 +72,21 @@ GRAV_CASES = [
 ]
 
 
-def _rel_l1(got, ref, nvar):
-    g, r = np.asarray(got).reshape(nvar, -1), np.asarray(ref).reshape(nvar, -1)
-    norm = np.abs(r).sum(axis=1)
-    return np.abs(g - r).sum(axis=1) / np.maximum(norm, 1e-2 * norm.max())
-
-
-@pytest.mark.parametrize("tiles", ["0", "1"])
+@pytest.mark.parametrize("tiles", ["large", "8x8"])
 @pytest.mark.parametrize("case,spec", GRAV_CASES, ids=[c[0] for c in GRAV_CASES])
-def test_tile_sizes_with_gravity_match_oracle(case, spec, tiles, monkeypatch):
+def test_tile_sizes_with_gravity_match_oracle(case, spec, tiles):
     # the gravity source of both tile shapes (Sec. 2.4): RHS and three steps
     import paper_1506_06140_amd as dg
-    monkeypatch.setenv("DG_TILE2D_SMALL", tiles)
     print("tiles gravity", case, tiles, flush=True)
     spec = dict(spec)
     wl = workloads.workload(spec.pop("name"), **spec)
+    wl["tile2d"] = TILES[tiles]
     o = oracle.Oracle(wl)
     w0, st = o.limit(o.initial_state())
     assert st == 0
     s = dg.Solver(wl)
     assert s.gravity is not None
-    err = _rel_l1(_host(s.rhs(_dev(w0))), o.rhs(w0), o.nvar)
-    assert np.all(err <= TOL), err
+    check_state(o, _host(s.rhs(_dev(w0))), o.rhs(w0), f"{case} tiles {tiles} rhs")
     fb = [s.empty() for _ in range(s.stages)]
     dt, rate = s.scalar(), s.rate_state()
     w = _dev(w0)
@@ -108,7 +96,5 @@ def test_tile_sizes_with_gravity_match_oracle(case, spec, tiles, monkeypatch):
         ref, dt_ref = o.step(ref)
         w = s.rk_step(w, fb, dt, rate).clone()
         assert float(_host(dt)[0]) == pytest.approx(dt_ref, rel=1e-14)
-        e = _rel_l1(_host(w), ref, o.nvar)
-        print(case, tiles, "step", i, e, flush=True)
-        assert np.all(e <= TOL), (i, e)
+        check_state(o, _host(w), ref, f"{case} tiles {tiles} step {i}")
     assert s.status() == 0
