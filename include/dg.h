@@ -55,8 +55,13 @@ enum {
   DG_ENOMEM = -3,       /* device or host allocation failed                  */
   DG_EHIP = -4,         /* a HIP runtime call failed                         */
   DG_ENEGATIVE = -5,    /* a cell mean has rho <= eps or p <= eps             */
-  DG_ENAN = -6          /* a NaN appeared in a right-hand side                */
+  DG_ENAN = -6,         /* a NaN appeared in a right-hand side                */
+  DG_ESCRATCH = -7      /* input larger than the static scratch (dg_rhs_noalloc) */
 };
+
+/* Floats in the library's static device scratch (32 MiB per GPU, held from
+ * the library's load until the process ends). */
+#define DG_STATIC_SCRATCH_FLOATS (8 * 1024 * 1024)
 
 enum { DG_BC_PERIODIC = 0, DG_BC_TRANSMISSIVE = 1 };
 enum { DG_HLLC_BATTEN = 0, DG_HLLC_DAVIS = 1 };
@@ -141,6 +146,20 @@ int dg_project(dg_ctx *ctx, const double *prim, double *w, void *stream);
  * integral (eq. dg_term2) minus surface integral (eq. dg_term3) with the HLLC
  * flux, times (2/dx) 2^-dim.  w and L are states; L must not alias w. */
 int dg_rhs(dg_ctx *ctx, const double *w, double *L, void *stream);
+
+/* dg_rhs for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and result as dg_rhs on a DG_BF16_VOL context, with the FP32
+ * volume term that dg_rhs keeps in the context's scratch held instead in
+ * the library's static device scratch of DG_STATIC_SCRATCH_FLOATS floats.
+ * The call allocates nothing and frees nothing.  It needs nvar * N * cells
+ * (both blocks with a refined box) <= DG_STATIC_SCRATCH_FLOATS, else it
+ * returns DG_ESCRATCH; DG_EINVAL for a context of another precision.  Every
+ * call on one GPU shares that GPU's scratch, so calls that overlap in time
+ * on one GPU (different streams, or different host threads) race and must
+ * be ordered by the caller; each call writes every scratch entry it reads
+ * before reading it. */
+int dg_rhs_noalloc(dg_ctx *ctx, const double *w, double *L, void *stream);
 
 /* Global time step of eq. time_step (eq. time_step_pos with the positivity
  * limiter) from the cell means of w, written to dt_dev[0] on the device. */

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # DG_LIBRARY may point at another build of the same sources (tuning runs)
 LIB_PATH = os.environ.get("DG_LIBRARY", os.path.join(_HERE, "libdg.so"))
 
-DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN = 0, -1, -2, -3, -4, -5, -6
+DG_OK, DG_EINVAL, DG_EUNSUPPORTED, DG_ENOMEM, DG_EHIP, DG_ENEGATIVE, DG_ENAN, DG_ESCRATCH = 0, -1, -2, -3, -4, -5, -6, -7
+DG_STATIC_SCRATCH_FLOATS = 8 * 1024 * 1024
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
 DG_LIM_NONE, DG_LIM_MINMOD, DG_LIM_CHAR = 0, 1, 2
 DG_TILE2D_AUTO, DG_TILE2D_8X8, DG_TILE2D_LARGE = 0, 1, 2
@@ -62,7 +63,7 @@ class dg_config(C.Structure):
 
 
 EXPORTS = (
-    "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs",
+    "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs", "dg_rhs_noalloc",
     "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
     "dg_set_gravity", "dg_amr_flags", "dg_amr_regrid", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
 )
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
     lib.dg_quadrature.argtypes = [ctxp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
     lib.dg_project.argtypes = [ctxp, dp, dp, vp]
     lib.dg_rhs.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_rhs_noalloc.argtypes = [ctxp, dp, dp, vp]
     lib.dg_max_dt.argtypes = [ctxp, dp, dp, vp]
     lib.dg_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, vp]
     lib.dg_max_rate.argtypes = [ctxp, dp, dp, vp]

@@ -16,6 +16,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <mutex>
 #include <cstring>
 #include <cstdlib>
 #include <new>
@@ -2868,11 +2869,24 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 
 using dg::Cfg;
 
+// Scratch of dg_rhs_noalloc: the FP32 volume term of the BF16 path in a
+// file-scope device array instead of the context's allocation.  Each GPU
+// holds its own copy; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (the array's name in
+// host code is not a device address).
+__device__ __align__(256) float scratch[DG_STATIC_SCRATCH_FLOATS];
+
 namespace {
 
 constexpr int kBlock = 256;
 
 thread_local char g_hip_msg[256];
+
+// per-device address of `scratch`, looked up once per device (in dg_init,
+// with that device current)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
 
 int hip_fail(hipError_t e) {
   std::snprintf(g_hip_msg, sizeof(g_hip_msg), "%s", hipGetErrorString(e));
@@ -2970,6 +2984,7 @@ struct StageLaunch {
   dg::Mix mx;
   hipStream_t s;
   dg::RateOp ro = {nullptr, nullptr, 0.0, 0.0, dg::RATE_NONE};  // only the 2D tile kernel takes one
+  float *vs = nullptr;  // volume-term scratch of the BF16 path (null: the context's)
   template <int D, int K, class R>
   int launch(const R *tabr, const float *vext) {
     return c->cfg.flux == DG_HLLC_DAVIS ? launch_fx<D, K, R, DG_HLLC_DAVIS>(tabr, vext)
@@ -3044,18 +3059,18 @@ struct StageLaunch {
     return DG_OK;
   }
   template <int D, int K>
-  int volume_bf16() {
+  int volume_bf16(float *v) {
     const __bf16 *tb = reinterpret_cast<const __bf16 *>(c->tabbf);
     if (!c->amr) {
       hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(256), 0, s, tb, w,
-                         c->ncell, c->vscratch, c->cfg.gamma);
+                         c->ncell, v, c->cfg.gamma);
     } else {
       const long nw = (long)c->sh.nv * c->sh.N;
       hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncc + 63) / 64)), dim3(256), 0, s, tb, w,
-                         c->ncc, c->vscratch, c->cfg.gamma);
+                         c->ncc, v, c->cfg.gamma);
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL((dg::k_volume_bf16<D, K>), dim3((unsigned)((c->ncf + 63) / 64)), dim3(256), 0, s, tb,
-                         w + nw * c->ncc, c->ncf, c->vscratch + nw * c->ncc, c->cfg.gamma);
+                         w + nw * c->ncc, c->ncf, v + nw * c->ncc, c->cfg.gamma);
     }
     HIP_TRY(hipGetLastError());
     return DG_OK;
@@ -3066,9 +3081,10 @@ struct StageLaunch {
       if constexpr (K > 3) {
         return DG_EUNSUPPORTED;
       } else {
-        int st = volume_bf16<D, K>();
+        float *v = vs ? vs : c->vscratch;
+        int st = volume_bf16<D, K>(v);
         if (st != DG_OK) return st;
-        return launch<D, K, float>(c->tab32, c->vscratch);
+        return launch<D, K, float>(c->tab32, v);
       }
     }
     if (c->cfg.precision == DG_FP32) return launch<D, K, float>(c->tab32, nullptr);
@@ -3371,6 +3387,7 @@ const char *dg_strerror(int code) {
     case DG_EHIP: return g_hip_msg[0] ? g_hip_msg : "HIP runtime error";
     case DG_ENEGATIVE: return "non-positive mean density or pressure";
     case DG_ENAN: return "NaN in the right-hand side";
+    case DG_ESCRATCH: return "state larger than the static scratch of dg_rhs_noalloc";
     default: return "unknown error";
   }
 }
@@ -3460,6 +3477,15 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   };
   hipError_t e;
   if ((e = hipGetDevice(&c->device)) != hipSuccess) return fail(e);
+  if (c->device >= 0 && c->device < kMaxDevices) {
+    // the address of this device's copy of the static scratch (dg_rhs_noalloc)
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+      void *p = nullptr;
+      if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return fail(e);
+      g_scratch_ptr[c->device] = static_cast<float *>(p);
+    }
+  }
   const size_t nt = c->host_tab.size();
   if ((e = hipMalloc((void **)&c->tab, nt * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
@@ -3555,6 +3581,22 @@ int dg_project(dg_ctx *c, const double *prim, double *w, void *stream) {
 int dg_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
   if (!c || !w || !L || w == L) return DG_EINVAL;
   return dispatch(c, StageLaunch{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
+}
+
+int dg_rhs_noalloc(dg_ctx *c, const double *w, double *L, void *stream) {
+  if (!c || !w || !L || w == L) return DG_EINVAL;
+  if (c->cfg.precision != DG_BF16_VOL) return DG_EINVAL;
+  if ((long long)c->sh.nv * c->sh.N * c->ncell > (long long)DG_STATIC_SCRATCH_FLOATS) return DG_ESCRATCH;
+  if (c->device < 0 || c->device >= kMaxDevices) return DG_EUNSUPPORTED;
+  float *vs;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    vs = g_scratch_ptr[c->device];
+  }
+  if (!vs) return DG_EHIP;  // dg_init failed to look it up (it returned an error then)
+  StageLaunch sl{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream};
+  sl.vs = vs;
+  return dispatch(c, sl);
 }
 
 int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const double *wp, double *out,

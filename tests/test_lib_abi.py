@@ -44,8 +44,15 @@ def test_limiter_codes_match_header():
     assert m and tuple(int(x) for x in m.groups()) == (dg.DG_LIM_NONE, dg.DG_LIM_MINMOD, dg.DG_LIM_CHAR)
 
 
+def test_static_scratch_size_matches_header():
+    src = open(os.path.join(ROOT, "include", "dg.h")).read()
+    m = re.search(r"#define\s+DG_STATIC_SCRATCH_FLOATS\s+\((\d+)\s*\*\s*(\d+)\s*\*\s*(\d+)\)", src)
+    assert m and int(m.group(1)) * int(m.group(2)) * int(m.group(3)) == dg.DG_STATIC_SCRATCH_FLOATS
+    assert re.search(r"DG_ESCRATCH\s*=\s*-7", src) and dg.DG_ESCRATCH == -7
+
+
 def test_strerror_covers_codes():
-    for code in range(0, -7, -1):
+    for code in range(0, -8, -1):
         assert dg.strerror(code) != "unknown error"
     assert dg.strerror(-99) == "unknown error"
 
