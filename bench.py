@@ -142,7 +142,7 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(wl, slab: int = 8):
+def cpu_baseline(wl, slab: int = 64):
     """The FP64 oracle (single-threaded C, built -O2 -ffp-contract=off),
     pinned to one host core, on a bounded sample of the headline workload:
     one limited SSP-RK3 stage (right-hand side, stage update, slope and
