@@ -64,12 +64,15 @@ _HELPERS = [
      "// ---------------------------------------------------------------------------\n// Right-hand side and fused stage."),
 ]
 KERNELS = {
-    "stage3d": dict(name="k_rhs_stage<3,2,double>", traffic="k_rhs_stage_kh3d128_k2_traffic.txt",
-                    regions=_HELPERS + [("// Right-hand side and fused stage.",
-                                         "// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.")]),
+    "stage3d": dict(name="k_rhs_mfma3d<2>", traffic="k_rhs_mfma3d_kh3d128_k2_traffic.txt",
+                    regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on FP64 MFMA.",
+                                         "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
+    "stage3d_valu": dict(name="k_rhs_stage<3,2,double>", traffic="k_rhs_stage_kh3d128_k2_traffic.txt",
+                         regions=_HELPERS + [("// Right-hand side and fused stage.",
+                                              "// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.")]),
     "tile2d": dict(name="k_rhs_tile2d<2,double> (8x8 tiles)", traffic="k_rhs_tile2d_vortex256_k2_traffic.txt",
                    regions=_HELPERS + [("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
-                                        "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
+                                        "// 3D right-hand side + stage with the contractions on FP64 MFMA.")]),
 }
 
 
@@ -474,7 +477,7 @@ def main():
                                "component-wise TVB minmod + positivity limiter after every stage, seeded 1e-2 "
                                "velocity noise",
                    "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(args.graph)},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic("stage3d"),
                      "kernel": KERNELS["stage3d"]["name"], "kernel_ms": k_ms,
                      "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
@@ -486,6 +489,17 @@ def main():
         "step_fracs": {"alu": 3 * alg_flops / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
                        "hbm": 3 * alg_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
     }
+    del s, w, bufs
+    torch.cuda.empty_cache()
+    # the same stage kernel on the vector ALU (one thread per cell), for comparison
+    s = dg.Solver(dict(wl, path3d=dg.DG_PATH3D_VALU))
+    w = build_state(s, wl)
+    s.limit(w)
+    bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
+    kv = kernel_ms(s, w, bufs, args.kernel_reps)
+    rec["roofline"]["valu_kernel"] = {"kernel": KERNELS["stage3d_valu"]["name"], "kernel_ms": kv,
+                                      "frac": alg_flops / (kv * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                                      "traffic": measured_traffic("stage3d_valu")}
     del s, w, bufs
     torch.cuda.empty_cache()
     if args.variants:

@@ -68,6 +68,7 @@ enum { DG_HLLC_BATTEN = 0, DG_HLLC_DAVIS = 1 };
 enum { DG_FP64 = 0, DG_FP32 = 1, DG_BF16_VOL = 2 };
 enum { DG_LIM_NONE = 0, DG_LIM_MINMOD = 1, DG_LIM_CHAR = 2 };
 enum { DG_TILE2D_AUTO = 0, DG_TILE2D_8X8 = 1, DG_TILE2D_LARGE = 2 };
+enum { DG_PATH3D_AUTO = 0, DG_PATH3D_VALU = 1 };
 
 typedef struct dg_ctx dg_ctx;
 
@@ -100,6 +101,10 @@ typedef struct {
                       /* DG_TILE2D_AUTO (0, the rule of dg_init),              */
                       /* DG_TILE2D_8X8 or DG_TILE2D_LARGE (16 x 16 for k <= 2, */
                       /* 16 x 8 for k = 3, 4); results equal to rounding       */
+  int path3d;         /* 3D uniform grids, k = 2, FP64, no gravity: the stage  */
+                      /* kernel's contractions on FP64 MFMA (DG_PATH3D_AUTO,  */
+                      /* 0) or on the vector ALU, one thread per cell         */
+                      /* (DG_PATH3D_VALU); results equal to rounding          */
 } dg_config;
 
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton

@@ -22,6 +22,7 @@ DG_STATIC_SCRATCH_FLOATS = 8 * 1024 * 1024
 DG_FP64, DG_FP32, DG_BF16_VOL = 0, 1, 2
 DG_LIM_NONE, DG_LIM_MINMOD, DG_LIM_CHAR = 0, 1, 2
 DG_TILE2D_AUTO, DG_TILE2D_8X8, DG_TILE2D_LARGE = 0, 1, 2
+DG_PATH3D_AUTO, DG_PATH3D_VALU = 0, 1
 # doubles in the carried rate state (8 slots, 16 apart; the rate is the largest slot)
 DG_RATE_STATE, RATE_SLOTS, RATE_STRIDE = 128, 8, 16
 PRECISIONS = {"fp64": DG_FP64, "fp32": DG_FP32, "bf16": DG_BF16_VOL}
@@ -58,7 +59,7 @@ class dg_config(C.Structure):
         ("slope_limiter", C.c_int), ("beta", C.c_double), ("m_tilde", C.c_double),
         ("positivity", C.c_int), ("eps", C.c_double),
         ("refine_lo", C.c_int * 3), ("refine_hi", C.c_int * 3),
-        ("tile2d", C.c_int),
+        ("tile2d", C.c_int), ("path3d", C.c_int),
     ]
 
 
@@ -138,6 +139,7 @@ def make_config(wl: dict, precision: str = "fp64") -> dg_config:
     c.refine_lo[:] = list(wl.get("refine_lo", (0, 0, 0)))
     c.refine_hi[:] = list(wl.get("refine_hi", (0, 0, 0)))
     c.tile2d = wl.get("tile2d", DG_TILE2D_AUTO)
+    c.path3d = wl.get("path3d", DG_PATH3D_AUTO)
     return c
 
 

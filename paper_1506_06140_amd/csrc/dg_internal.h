@@ -86,6 +86,7 @@ struct dg_ctx {
   double *grav = nullptr, *gmax = nullptr;
   double grav_k = 0.0;
   double *prmat = nullptr;  // refinement matrices on the device (dg_amr_flags, dg_amr_regrid)
+  double *tabmf = nullptr;  // A-operand tables of the 3D MFMA stage kernel (null: the VALU kernel)
   // 2D tile size: -1 automatic (dg::tile2d_small: 8x8 tiles for k <= 3, and
   // for k = 4 on grids with fewer 16x8 tiles than CUs), 0 always the large
   // tiles, 1 always 8x8 (dg_config.tile2d)

@@ -1058,6 +1058,201 @@ __global__ __launch_bounds__((4 * Tile2D<K, TS>::TX * Tile2D<K, TS>::TY)) void k
 }
 
 // ---------------------------------------------------------------------------
+// 3D right-hand side + stage with the contractions on FP64 MFMA.
+//
+// Every contraction of eqs. dg_term2 and dg_term3 is a small GEMM batched
+// over cells, run with v_mfma_f64_16x16x4f64 (D[16x16] += A[16x4] B[4x16]):
+// a wave owns 16 consecutive cells (the GEMM columns), lane l = 16 g + c
+// holds B[g][c] and A[c][g] and receives D[4r + g][c] in its register r,
+// r = 0..3 (the operand layouts, checked on the device).
+//   evaluation  U_v[p][c] = sum_l E[p][l] w_v[l][c]        (A = table E,
+//               rows p = volume nodes or the nine points of one face side;
+//               B = the cells' modal weights, K = modes in steps of 4);
+//   projection  acc_v[j][c] += sum_p T[j][p] F_v[p][c]     (A = table T,
+//               rows j = modes; B = fluxes at the points).
+// The evaluation leaves in lane (g, c) the state of cell c at points
+// 4r + g, r = 0..3, all five variables, so the Euler flux and the HLLC flux
+// are computed in-lane (VALU, overlapping the matrix pipe), and register r of
+// that result is directly the B operand of the projection over the points
+// {4r + k : k = 0..3}: the tables' K order follows it, so no data moves
+// between lanes.  Tables (the A operands, laid out per lane) sit in LDS.
+// Point and mode indices 4r + g make whole registers r padding (points or
+// modes past the end), which are skipped at compile time.
+// As in k_rhs_stage, each face is evaluated by both of its cells from the
+// same weights, tables and operation order, so both obtain the same flux.
+// ---------------------------------------------------------------------------
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int K>
+struct Mf3 {
+  using C = Cfg<3, K>;
+  static constexpr int N = C::N, Q = C::Q, QF = C::QF, NV = C::NV;
+  static constexpr int NKS = (N + 3) / 4;    // K steps of the evaluation (modes)
+  static constexpr int NQT = (Q + 15) / 16;  // volume-node tiles
+  static constexpr int NFT = (QF + 15) / 16; // face-point tiles per side
+  static constexpr int NMT = (N + 15) / 16;  // mode tiles of the result
+  // operand blocks of 64 doubles (one per lane)
+  static constexpr int EV = 0;                              // [NQT][NKS]
+  static constexpr int EF = EV + NQT * NKS;                 // [3][2][NFT][NKS]
+  static constexpr int PV = EF + 6 * NFT * NKS;             // [3][NQT][4][NMT]
+  static constexpr int LF = PV + 3 * NQT * 4 * NMT;         // [3][2][NFT][4][NMT]
+  static constexpr int OPS = LF + 6 * NFT * 4 * NMT;
+};
+
+// Two waves per SIMD (<= 256 registers per lane): at one wave the matrix
+// pipe idled while the wave waited on its own MFMA results and loads
+// (5.3 ms against 3.2 ms per 128^3 launch).
+template <int K, int FX>
+__global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict__ tmf, const double *__restrict__ w,
+                                                    double *__restrict__ out, const double *__restrict__ dtp, Grid g,
+                                                    int mode, Mix mx, int *__restrict__ flag) {
+  using M = Mf3<K>;
+  constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q;
+  __shared__ double tl[M::OPS * 64];
+  for (int i = threadIdx.x; i < M::OPS * 64; i += blockDim.x) tl[i] = tmf[i];
+  __syncthreads();
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int gq = lane >> 4, col = lane & 15;
+  const long nc = g.ncell;
+  const long cell = ((long)blockIdx.x * 4 + wv) * 16 + col;
+  const bool valid = cell < nc;
+  const long cs = valid ? cell : nc - 1;  // a valid address for the padding columns
+  const int ix = (int)(cs % g.nx);
+  const int iy = (int)((cs / g.nx) % g.ny);
+  const int iz = (int)(cs / ((long)g.nx * g.ny));
+  const double gm1 = g.gamma - 1.0;
+  auto op = [&](int o) { return tl[o * 64 + lane]; };
+
+  // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq]
+  double wb[NV][NKS];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      const int m = 4 * ks + gq;
+      wb[v][ks] = (m < N && valid) ? w[(long)(v * N + m) * nc + cell] : 0.0;
+    }
+
+  d4 acc[NV][NMT];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt) acc[v][mt] = d4{0.0, 0.0, 0.0, 0.0};
+
+  // volume integral (eq. dg_term2)
+#pragma unroll
+  for (int t = 0; t < M::NQT; ++t) {
+    d4 U[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) z = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EV + t * NKS + ks), wb[v][ks], z, 0, 0, 0);
+      U[v] = z;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (16 * t + 4 * r >= Q) continue;
+      const bool ok = 16 * t + 4 * r + gq < Q;
+      double Ur[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Ur[v] = ok ? U[v][r] : (v == 0 ? 1.0 : (v == NV - 1 ? 1.0 : 0.0));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        double F[NV];
+        euler_flux<3, double>(Ur, a, gm1, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double f = ok ? F[v] : 0.0;
+#pragma unroll
+          for (int mt = 0; mt < NMT; ++mt)
+            acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::PV + ((a * M::NQT + t) * 4 + r) * NMT + mt), f,
+                                                              acc[v][mt], 0, 0, 0);
+        }
+      }
+    }
+  }
+
+  // face integral (eq. dg_term3), each of the 2d sides from this cell's side
+  // (unrolled: the next side's neighbour loads and table reads are issued
+  // while the current side's Riemann solves run)
+#pragma unroll
+  for (int fs = 0; fs < 6; ++fs) {
+    const int a = fs >> 1, s = fs & 1;
+    const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
+    const long src = nb >= 0 ? nb : cs;
+    double nbw[NV][NKS];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const int m = 4 * ks + gq;
+        nbw[v][ks] = m < N ? w[(long)(v * N + m) * nc + src] : 0.0;
+      }
+#pragma unroll
+    for (int ft = 0; ft < M::NFT; ++ft) {
+      d4 To[NV], Tn[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        d4 zo = {0.0, 0.0, 0.0, 0.0}, zn = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+          zo = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EF + ((a * 2 + s) * M::NFT + ft) * NKS + ks), wb[v][ks], zo,
+                                                   0, 0, 0);
+          zn = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS + ks),
+                                                   nbw[v][ks], zn, 0, 0, 0);
+        }
+        To[v] = zo;
+        Tn[v] = nb >= 0 ? zn : zo;  // transmissive: ghost trace = own trace
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (16 * ft + 4 * r >= QF) continue;
+        double Fh[NV];
+        if (16 * ft + 4 * r + gq < QF) {
+          double UL[NV], UR[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            UL[v] = s ? To[v][r] : Tn[v][r];
+            UR[v] = s ? Tn[v][r] : To[v][r];
+          }
+          hllc<double, 3, FX>(UL, UR, a, g.gamma, Fh);
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Fh[v] = 0.0;
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int mt = 0; mt < NMT; ++mt)
+            acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                op(M::LF + ((((a * 2 + s) * M::NFT + ft) * 4 + r) * NMT + mt)), Fh[v], acc[v][mt], 0, 0, 0);
+      }
+    }
+  }
+
+  // assembly (L = (2/dx) 2^-d (V - S)) and the fused stage update
+  bool bad = false;
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int mt = 0; mt < NMT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * mt + 4 * r + gq;
+        if (j < N && valid) {
+          const long i = (long)(v * N + j) * nc + cell;
+          const double L = g.fac * acc[v][mt][r];
+          bad |= (L != L);
+          out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, cldt, i);
+        }
+      }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// ---------------------------------------------------------------------------
 // Discrete adjoint of the right-hand side and of the SSP-RK3 stages.
 //
 // mu = (dL/dw)^T lam for L = fac (V - S):
@@ -3042,6 +3237,10 @@ struct StageLaunch {
       if (vext || c->gravity) return DG_EUNSUPPORTED;
       hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, true>), dim3(nblocks(4 * c->ncell)), dim3(kBlock), 0, s, c->tab,
                          w, out, dt, make_uniform_amr_grid(c), mode, mx, c->flag);
+    } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
+      // contractions on FP64 MFMA, 16 cells per wave
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s,
+                         c->tabmf, w, out, dt, make_grid(c), mode, mx, c->flag);
     } else {
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
@@ -3217,6 +3416,51 @@ struct Bf16Tables {
 };
 
 int bf16_tables(const dg_ctx *c, std::vector<uint16_t> &out) { return dispatch(c, Bf16Tables{c, &out}); }
+
+// A operands of k_rhs_mfma3d, 64 doubles per operand block: lane l holds
+// A[i = l % 16][k = l / 16] (evaluation: rows = points, k = modes 4 ks + k;
+// projection and lifting: rows = modes j, k = points 4 r + k).  The lifting
+// tables carry the side's sign (- on the +a side of the cell).
+template <int K>
+std::vector<double> mf3_tables(const dg_ctx *c) {
+  using C = Cfg<3, K>;
+  using M = dg::Mf3<K>;
+  std::vector<double> t((size_t)M::OPS * 64, 0.0);
+  const std::vector<double> &h = c->host_tab;
+  for (int l = 0; l < 64; ++l) {
+    const int i = l % 16, k = l / 16;
+    for (int tt = 0; tt < M::NQT; ++tt)
+      for (int ks = 0; ks < M::NKS; ++ks) {
+        const int q = 16 * tt + i, m = 4 * ks + k;
+        t[(size_t)(M::EV + tt * M::NKS + ks) * 64 + l] = (q < C::Q && m < C::N) ? h[C::B + q * C::N + m] : 0.0;
+      }
+    for (int fs = 0; fs < 6; ++fs)
+      for (int ft = 0; ft < M::NFT; ++ft)
+        for (int ks = 0; ks < M::NKS; ++ks) {
+          const int pt = 16 * ft + i, m = 4 * ks + k;
+          t[(size_t)(M::EF + (fs * M::NFT + ft) * M::NKS + ks) * 64 + l] =
+              (pt < C::QF && m < C::N) ? h[C::TF + (fs * C::QF + pt) * C::N + m] : 0.0;
+        }
+    for (int a = 0; a < 3; ++a)
+      for (int tt = 0; tt < M::NQT; ++tt)
+        for (int r = 0; r < 4; ++r)
+          for (int mt = 0; mt < M::NMT; ++mt) {
+            const int q = 16 * tt + 4 * r + k, j = 16 * mt + i;
+            t[(size_t)(M::PV + ((a * M::NQT + tt) * 4 + r) * M::NMT + mt) * 64 + l] =
+                (q < C::Q && j < C::N && j >= 1) ? h[C::DW + (a * C::Q + q) * C::N + j] : 0.0;
+          }
+    for (int fs = 0; fs < 6; ++fs)
+      for (int ft = 0; ft < M::NFT; ++ft)
+        for (int r = 0; r < 4; ++r)
+          for (int mt = 0; mt < M::NMT; ++mt) {
+            const int pt = 16 * ft + 4 * r + k, j = 16 * mt + i;
+            const double sg = (fs & 1) ? -1.0 : 1.0;
+            t[(size_t)(M::LF + (((fs * M::NFT + ft) * 4 + r) * M::NMT + mt)) * 64 + l] =
+                (pt < C::QF && j < C::N) ? sg * h[C::TW + (fs * C::QF + pt) * C::N + j] : 0.0;
+          }
+  }
+  return t;
+}
 
 // Folds the maximum signal rate of w's cell means into *rm (atomic max).
 int rate_fold(dg_ctx *c, const double *w, unsigned long long *rm, hipStream_t s) {
@@ -3411,6 +3655,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if (cfg->positivity != 0 && cfg->positivity != 1) return DG_EINVAL;
   if (cfg->tile2d != DG_TILE2D_AUTO && cfg->tile2d != DG_TILE2D_8X8 && cfg->tile2d != DG_TILE2D_LARGE)
     return DG_EINVAL;
+  if (cfg->path3d != DG_PATH3D_AUTO && cfg->path3d != DG_PATH3D_VALU) return DG_EINVAL;
   if (cfg->positivity && !(cfg->eps > 0.0)) return DG_EINVAL;
   bool amr = false;
   for (int a = 0; a < cfg->dim; ++a)
@@ -3514,6 +3759,12 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const std::vector<double> zeros(DG_RATE_STATE, 0.0);
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
+  if (cfg->dim == 3 && cfg->k == 2 && !amr && cfg->precision == DG_FP64 && cfg->path3d != DG_PATH3D_VALU) {
+    const std::vector<double> T = mf3_tables<2>(c);
+    if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
+    if ((e = hipMemcpy(c->tabmf, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+      return fail(e);
+  }
   if (cfg->k <= 3) {
     // refinement matrices of dg_amr_flags / dg_amr_regrid (eq. ref_pa_integral)
     const std::vector<double> P = dg::refine_matrices(c->sh);
@@ -3536,6 +3787,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->grav) (void)hipFree(c->grav);
   if (c->gmax) (void)hipFree(c->gmax);
   if (c->prmat) (void)hipFree(c->prmat);
+  if (c->tabmf) (void)hipFree(c->tabmf);
   delete c;
 }
 

@@ -72,6 +72,19 @@ CASES = [
     ("blast3d_k2_transmissive", dict(name="blast_amr", k=2, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
                                      limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
                                      bc=(0, 1, 1))),
+    # 3D k = 2 also on the vector-ALU stage kernel (path3d = DG_PATH3D_VALU;
+    # the default is the MFMA kernel), ragged, periodic and transmissive
+    ("kh3d_k2_valu", dict(name="kh3d", k=2, n=(12, 10, 9), length=(1.2, 1.0, 0.9), limiter=0, positivity=0,
+                          path3d=1)),
+    ("blast3d_k2_transmissive_davis_valu", dict(name="blast_amr", k=2, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
+                                                limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
+                                                bc=(1, 0, 1), flux=1, path3d=1)),
+    # MFMA kernel: Davis bounds with transmissive x and y walls; a grid of
+    # 2 x 3 x 5 = 30 cells (one partial wave of 16 columns, two waves)
+    ("blast3d_k2_transmissive_davis", dict(name="blast_amr", k=2, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
+                                           limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
+                                           bc=(1, 1, 0), flux=1)),
+    ("kh3d_k2_tiny", dict(name="kh3d", k=2, n=(2, 3, 5), length=(0.2, 0.3, 0.5), limiter=0, positivity=0)),
 ]
 
 
