@@ -1732,6 +1732,70 @@ __device__ inline double tau_root(const double *Ub, const double *Uq, double gam
 
 // CHAR selects the characteristic limiter (eq. char_limiter) for the slope
 // pass, else the component-wise one (eq. comp_limiter).
+// Exponent of axis a in mode l (modes ordered by total degree, then
+// x-exponent descending, then y-exponent descending).
+template <int D>
+__host__ __device__ constexpr int mode_exp(int l, int a) {
+  int n = 0;
+  for (int t = 0; t <= 8; ++t)
+    for (int ex = t; ex >= 0; --ex)
+      for (int ey = t - ex; ey >= 0; --ey) {
+        const int ez = t - ex - ey;
+        if (D == 2 && ez > 0) continue;
+        if (n == l) return a == 0 ? ex : a == 1 ? ey : ez;
+        ++n;
+      }
+  return 0;
+}
+
+static_assert(mode_exp<3>(1, 0) == 1 && mode_exp<3>(2, 1) == 1 && mode_exp<3>(3, 2) == 1 && mode_exp<3>(4, 0) == 2 &&
+                  mode_exp<3>(5, 1) == 1 && mode_exp<3>(6, 2) == 1 && mode_exp<3>(9, 2) == 2 && mode_exp<2>(3, 0) == 2 &&
+                  mode_exp<2>(5, 1) == 2 && mode_exp<3>(10, 0) == 3,
+              "mode order: total degree, then x-exponent descending, then y-exponent descending");
+
+// max over the reference cell of |phi_l| = prod_a sqrt(2 e_a + 1), from
+// |P_n| <= 1 on [-1, 1]
+template <int D>
+__device__ constexpr double basis_bound(int l) {
+  constexpr double r[9] = {1.0, 1.7320508075688772, 2.2360679774997898, 2.6457513110645907, 3.0,
+                           3.3166247903554, 3.6055512754639891, 3.872983346207417, 4.1231056256176606};
+  double b = 1.0;
+  for (int a = 0; a < D; ++a) b *= r[mode_exp<D>(l, a)];
+  return b;
+}
+
+// True when the cell's polynomial has, at every point of the reference cell,
+// a density and a pressure above eps by a margin (1e-10 of the quantities'
+// scale) far above the rounding of the point evaluations: then the
+// positivity pass of Sec. 3.4 finds every point value >= eps, so theta_1 =
+// theta_2 = 1 exactly and it would leave the cell unchanged; the point loop
+// is skipped.  Bounds: |u(xi) - u_mean| <= sum_{l>=1} |w_l| max|phi_l| per
+// variable, and p = (gamma-1)(E - |m|^2 / (2 rho)) >= (gamma-1)(E_lo -
+// |m|_hi^2 / (2 rho_lo)).
+template <int D, int N>
+__device__ inline bool positivity_certain(const double (&wc)[D + 2][N], double gamma, double eps) {
+  double R[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) {
+    double r = 0.0;
+#pragma unroll
+    for (int l = 1; l < N; ++l) r = fma(fabs(wc[v][l]), basis_bound<D>(l), r);
+    R[v] = r;
+  }
+  const double rlo = wc[0][0] - R[0];
+  if (!(rlo > eps + 1e-10 * (fabs(wc[0][0]) + R[0]))) return false;
+  double m2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    const double m = fabs(wc[1 + a][0]) + R[1 + a];
+    m2 = fma(m, m, m2);
+  }
+  const double ke = 0.5 * m2 / rlo;
+  const double plo = (gamma - 1.0) * ((wc[D + 1][0] - R[D + 1]) - ke);
+  const double scale = (gamma - 1.0) * (fabs(wc[D + 1][0]) + R[D + 1] + ke);
+  return plo > eps + 1e-10 * scale;
+}
+
 template <int D, int K, bool CHAR>
 __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, double *__restrict__ w, Grid g,
                                                int slope, double beta, double bound, int posit, double eps,
@@ -1814,7 +1878,7 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
     if (!(Ub[0] > eps) || !(pb > eps)) {
       atomicOr(flag, FLAG_NEGATIVE);
-    } else {
+    } else if (!positivity_certain<D, C::N>(wc, g.gamma, eps)) {
       double rmin = INFINITY;
       for (int s = 0; s < C::NS; ++s) {
         double r = 0.0;
@@ -2997,9 +3061,10 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
     if (!(Ub[0] > eps) || !(pb > eps)) {
       atomicOr(flag, FLAG_NEGATIVE);
-    } else {
+    } else if (!positivity_certain<D, N>(wc, g.gamma, eps)) {
       // points: the union set S, then the hanging-face points of every
-      // refined face of a coarse cell
+      // refined face of a coarse cell (all inside the reference cell, so
+      // the bound of positivity_certain covers them too)
       const int nextra = fine ? 0 : 2 * D * NSUB * C::QF;
       double rmin = INFINITY;
       for (int s2 = 0; s2 < C::NS + nextra; ++s2) {
