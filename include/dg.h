@@ -101,10 +101,11 @@ typedef struct {
                       /* DG_TILE2D_AUTO (0, the rule of dg_init),              */
                       /* DG_TILE2D_8X8 or DG_TILE2D_LARGE (16 x 16 for k <= 2, */
                       /* 16 x 8 for k = 3, 4); results equal to rounding       */
-  int path3d;         /* 3D uniform grids, k = 2, FP64, no gravity: the stage  */
-                      /* kernel's contractions on FP64 MFMA (DG_PATH3D_AUTO,  */
-                      /* 0) or on the vector ALU, one thread per cell         */
-                      /* (DG_PATH3D_VALU); results equal to rounding          */
+  int path3d;         /* 3D uniform grids, k = 2 or 3, FP64, no gravity: the   */
+                      /* stage kernel's contractions on FP64 MFMA             */
+                      /* (DG_PATH3D_AUTO, 0) or on the vector ALU             */
+                      /* (DG_PATH3D_VALU: one thread per cell at k = 2, four  */
+                      /* lanes per cell at k = 3); results equal to rounding  */
 } dg_config;
 
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton

@@ -1091,25 +1091,32 @@ struct Mf3 {
   static constexpr int NQT = (Q + 15) / 16;  // volume-node tiles
   static constexpr int NFT = (QF + 15) / 16; // face-point tiles per side
   static constexpr int NMT = (N + 15) / 16;  // mode tiles of the result
-  // operand blocks of 64 doubles (one per lane)
+  // operand blocks of 64 doubles (one per lane): the volume phase's, then
+  // the face phase's
   static constexpr int EV = 0;                              // [NQT][NKS]
-  static constexpr int EF = EV + NQT * NKS;                 // [3][2][NFT][NKS]
-  static constexpr int PV = EF + 6 * NFT * NKS;             // [3][NQT][4][NMT]
-  static constexpr int LF = PV + 3 * NQT * 4 * NMT;         // [3][2][NFT][4][NMT]
+  static constexpr int PV = EV + NQT * NKS;                 // [3][NQT][4][NMT]
+  static constexpr int EF = PV + 3 * NQT * 4 * NMT;         // [3][2][NFT][NKS]
+  static constexpr int LF = EF + 6 * NFT * NKS;             // [3][2][NFT][4][NMT]
   static constexpr int OPS = LF + 6 * NFT * 4 * NMT;
+  // when all of them exceed 64 KB (k = 3: 97 KB), LDS holds one phase's
+  // blocks at a time (k = 3: 58 KB), the face phase's loaded after the volume
+  static constexpr bool SPLIT = OPS * 64 * 8 > 65536;
+  static constexpr int VOPS = EF, FOPS = OPS - EF;
+  static constexpr int LDSOPS = !SPLIT ? OPS : (VOPS > FOPS ? VOPS : FOPS);
+  static constexpr int FBASE = SPLIT ? EF : 0;  // LDS block of face-phase operand o: o - FBASE
 };
 
 // Two waves per SIMD (<= 256 registers per lane): at one wave the matrix
 // pipe idled while the wave waited on its own MFMA results and loads
 // (5.3 ms against 3.2 ms per 128^3 launch).
 template <int K, int FX>
-__global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict__ tmf, const double *__restrict__ w,
+__global__ __launch_bounds__(256, K == 2 ? 2 : 1) void k_rhs_mfma3d(const double *__restrict__ tmf, const double *__restrict__ w,
                                                     double *__restrict__ out, const double *__restrict__ dtp, Grid g,
                                                     int mode, Mix mx, int *__restrict__ flag) {
   using M = Mf3<K>;
   constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q;
-  __shared__ double tl[M::OPS * 64];
-  for (int i = threadIdx.x; i < M::OPS * 64; i += blockDim.x) tl[i] = tmf[i];
+  __shared__ double tl[M::LDSOPS * 64];
+  for (int i = threadIdx.x; i < (M::SPLIT ? M::VOPS : M::OPS) * 64; i += blockDim.x) tl[i] = tmf[i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1122,7 +1129,8 @@ __global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict_
   const int iy = (int)((cs / g.nx) % g.ny);
   const int iz = (int)(cs / ((long)g.nx * g.ny));
   const double gm1 = g.gamma - 1.0;
-  auto op = [&](int o) { return tl[o * 64 + lane]; };
+  auto op = [&](int o) { return tl[o * 64 + lane]; };               // volume-phase operand
+  auto opf = [&](int o) { return tl[(o - M::FBASE) * 64 + lane]; };  // face-phase operand
 
   // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq]
   double wb[NV][NKS];
@@ -1174,6 +1182,12 @@ __global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict_
     }
   }
 
+  if constexpr (M::SPLIT) {
+    __syncthreads();  // every wave is done with the volume-phase operands
+    for (int i = threadIdx.x; i < M::FOPS * 64; i += blockDim.x) tl[i] = tmf[M::EF * 64 + i];
+    __syncthreads();
+  }
+
   // face integral (eq. dg_term3), each of the 2d sides from this cell's side
   // (unrolled: the next side's neighbour loads and table reads are issued
   // while the current side's Riemann solves run)
@@ -1198,9 +1212,9 @@ __global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict_
         d4 zo = {0.0, 0.0, 0.0, 0.0}, zn = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
-          zo = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EF + ((a * 2 + s) * M::NFT + ft) * NKS + ks), wb[v][ks], zo,
-                                                   0, 0, 0);
-          zn = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS + ks),
+          zo = __builtin_amdgcn_mfma_f64_16x16x4f64(opf(M::EF + ((a * 2 + s) * M::NFT + ft) * NKS + ks), wb[v][ks],
+                                                   zo, 0, 0, 0);
+          zn = __builtin_amdgcn_mfma_f64_16x16x4f64(opf(M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS + ks),
                                                    nbw[v][ks], zn, 0, 0, 0);
         }
         To[v] = zo;
@@ -1227,7 +1241,7 @@ __global__ __launch_bounds__(256, 2) void k_rhs_mfma3d(const double *__restrict_
 #pragma unroll
           for (int mt = 0; mt < NMT; ++mt)
             acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                op(M::LF + ((((a * 2 + s) * M::NFT + ft) * 4 + r) * NMT + mt)), Fh[v], acc[v][mt], 0, 0, 0);
+                opf(M::LF + ((((a * 2 + s) * M::NFT + ft) * 4 + r) * NMT + mt)), Fh[v], acc[v][mt], 0, 0, 0);
       }
     }
   }
@@ -3293,6 +3307,10 @@ struct StageLaunch {
         hipLaunchKernelGGL((dg::k_rhs_tile2d<K, R, FX>), grid, dim3(4 * T::TX * T::TY), 0, s, c->tab, tabr, w, out,
                            dt, vext, make_grid(c), mode, mx, c->flag, r2, nullptr);
       }
+    } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
+      // contractions on FP64 MFMA, 16 cells per wave
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s,
+                         c->tabmf, w, out, dt, make_grid(c), mode, mx, c->flag);
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
@@ -3824,8 +3842,9 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const std::vector<double> zeros(DG_RATE_STATE, 0.0);
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
-  if (cfg->dim == 3 && cfg->k == 2 && !amr && cfg->precision == DG_FP64 && cfg->path3d != DG_PATH3D_VALU) {
-    const std::vector<double> T = mf3_tables<2>(c);
+  if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && !amr && cfg->precision == DG_FP64 &&
+      cfg->path3d != DG_PATH3D_VALU) {
+    const std::vector<double> T = cfg->k == 2 ? mf3_tables<2>(c) : mf3_tables<3>(c);
     if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
     if ((e = hipMemcpy(c->tabmf, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e);

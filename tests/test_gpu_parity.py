@@ -85,6 +85,13 @@ CASES = [
                                            limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
                                            bc=(1, 1, 0), flux=1)),
     ("kh3d_k2_tiny", dict(name="kh3d", k=2, n=(2, 3, 5), length=(0.2, 0.3, 0.5), limiter=0, positivity=0)),
+    # 3D k = 3: MFMA kernel (tables in LDS one phase at a time), transmissive
+    # walls with Davis bounds; and the four-lanes-per-cell VALU kernel
+    ("blast3d_k3_transmissive_davis", dict(name="blast_amr", k=3, n=(9, 6, 5), length=(9 / 8, 6 / 8, 5 / 8),
+                                           limiter=0, positivity=0, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0),
+                                           bc=(1, 1, 0), flux=1)),
+    ("blast_k3_valu", dict(name="blast_amr", k=3, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), limiter=0, positivity=0,
+                           refine_lo=(0, 0, 0), refine_hi=(0, 0, 0), path3d=1)),
 ]
 
 
