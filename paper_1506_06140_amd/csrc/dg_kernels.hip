@@ -1057,6 +1057,38 @@ __global__ __launch_bounds__((4 * Tile2D<K, TS>::TX * Tile2D<K, TS>::TY)) void k
   }
 }
 
+// The refined box's geometry (see k_rhs_amr below).
+struct AmrGrid {
+  int n[3];    // base (coarse) grid
+  int lo[3], hi[3];
+  int nf[3];   // fine block
+  long ncc, ncf;
+  int bc[3];
+  double facc, facf, dxc, dxf;
+  double gamma;
+};
+
+template <int D>
+__device__ inline bool amr_in_hole(const AmrGrid &g, const int *i) {
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    if (i[a] < g.lo[a] || i[a] >= g.hi[a]) return false;
+  return true;
+}
+
+// base-grid neighbour along a (periodic); false at a transmissive wall
+template <int D>
+__device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int dir, int *j) {
+#pragma unroll
+  for (int b = 0; b < 3; ++b) j[b] = i[b];
+  j[a] += dir;
+  if (j[a] < 0 || j[a] >= g.n[a]) {
+    if (g.bc[a] == DG_BC_TRANSMISSIVE) return false;
+    j[a] = j[a] < 0 ? j[a] + g.n[a] : j[a] - g.n[a];
+  }
+  return true;
+}
+
 // ---------------------------------------------------------------------------
 // 3D right-hand side + stage with the contractions on FP64 MFMA.
 //
@@ -1098,6 +1130,11 @@ struct Mf3 {
   static constexpr int EF = PV + 3 * NQT * 4 * NMT;         // [3][2][NFT][NKS]
   static constexpr int LF = EF + 6 * NFT * NKS;             // [3][2][NFT][4][NMT]
   static constexpr int OPS = LF + 6 * NFT * 4 * NMT;
+  // refined box only (read from global memory): the coarse trace at the
+  // points of each of a side's four sub-faces, and the sub-face lift
+  static constexpr int HGA = OPS;                            // [3][2][4][NFT][NKS]
+  static constexpr int HWA = HGA + 24 * NFT * NKS;           // [3][2][4][NFT][4][NMT]
+  static constexpr int AOPS = HWA + 24 * NFT * 4 * NMT;
   // when all of them exceed 64 KB (k = 3: 97 KB), LDS holds one phase's
   // blocks at a time (k = 3: 58 KB), the face phase's loaded after the volume
   static constexpr bool SPLIT = OPS * 64 * 8 > 65536;
@@ -1106,31 +1143,73 @@ struct Mf3 {
   static constexpr int FBASE = SPLIT ? EF : 0;  // LDS block of face-phase operand o: o - FBASE
 };
 
-// Two waves per SIMD (<= 256 registers per lane): at one wave the matrix
-// pipe idled while the wave waited on its own MFMA results and loads
+// Two waves per SIMD at k = 2 (<= 256 registers per lane): at one wave the
+// matrix pipe idled while the wave waited on its own MFMA results and loads
 // (5.3 ms against 3.2 ms per 128^3 launch).
-template <int K, int FX>
-__global__ __launch_bounds__(256, K == 2 ? 2 : 1) void k_rhs_mfma3d(const double *__restrict__ tmf, const double *__restrict__ w,
-                                                    double *__restrict__ out, const double *__restrict__ dtp, Grid g,
-                                                    int mode, Mix mx, int *__restrict__ flag) {
+//
+// AMR: the refined box of Sec. 4 (static 2:1 box; state = coarse block, then
+// fine block).  Blocks of the grid cover the coarse block's cells, then the
+// fine block's, so a wave holds 16 cells of one block.  Faces are classified
+// per column as in k_rhs_amr_quad: regular, wall, hanging (a coarse cell
+// facing the fine block: four sub-faces, the coarse trace at the sub-face's
+// points (eq. ref_pa_integral's mapped points, table HG) against the fine
+// cell's own trace, lifted with the sub-face weights w_r / 2^(d-1), table HW)
+// and coarse-neighbour (a fine cell on the block boundary: its own trace
+// against the coarse trace at its sub-face's points).  Each kind's traces
+// come from their own MFMA chain started at zero and are selected per
+// column, so both cells of a hanging face form each trace from the same
+// table, the same weights and the same chain: the same flux bit for bit.
+// The hanging and coarse-neighbour chains run only in waves that hold such
+// a column, with their tables read from global memory.
+template <int K, int FX, bool AMR>
+__global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(const double *__restrict__ tmf,
+                                                                 const double *__restrict__ w,
+                                                                 double *__restrict__ out,
+                                                                 const double *__restrict__ dtp, Grid g, AmrGrid ag,
+                                                                 int mode, Mix mx, int *__restrict__ flag) {
   using M = Mf3<K>;
-  constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q;
+  constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q, NW = NV * N;
   __shared__ double tl[M::LDSOPS * 64];
   for (int i = threadIdx.x; i < (M::SPLIT ? M::VOPS : M::OPS) * 64; i += blockDim.x) tl[i] = tmf[i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int gq = lane >> 4, col = lane & 15;
-  const long nc = g.ncell;
-  const long cell = ((long)blockIdx.x * 4 + wv) * 16 + col;
+  // the block of cells this wave works on: the uniform grid, or (AMR) the
+  // coarse or the fine block, at offset boff in the state
+  long nc, blk = blockIdx.x, boff = 0;
+  bool fine = false;
+  int bn[3];
+  double fac, gam;
+  if constexpr (AMR) {
+    const long nbc = (ag.ncc + 63) / 64;
+    fine = blk >= nbc;
+    if (fine) blk -= nbc;
+    nc = fine ? ag.ncf : ag.ncc;
+    boff = fine ? (long)NW * ag.ncc : 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) bn[a] = fine ? ag.nf[a] : ag.n[a];
+    fac = fine ? ag.facf : ag.facc;
+    gam = ag.gamma;
+  } else {
+    nc = g.ncell;
+    bn[0] = g.nx;
+    bn[1] = g.ny;
+    bn[2] = g.nz;
+    fac = g.fac;
+    gam = g.gamma;
+  }
+  const double *wbk = w + boff;  // this block's state
+  const long cell = (blk * 4 + wv) * 16 + col;
   const bool valid = cell < nc;
   const long cs = valid ? cell : nc - 1;  // a valid address for the padding columns
-  const int ix = (int)(cs % g.nx);
-  const int iy = (int)((cs / g.nx) % g.ny);
-  const int iz = (int)(cs / ((long)g.nx * g.ny));
-  const double gm1 = g.gamma - 1.0;
+  int ci[3] = {(int)(cs % bn[0]), (int)((cs / bn[0]) % bn[1]), (int)(cs / ((long)bn[0] * bn[1]))};
+  bool hole = false;
+  if constexpr (AMR) hole = !fine && amr_in_hole<3>(ag, ci);
+  const double gm1 = gam - 1.0;
   auto op = [&](int o) { return tl[o * 64 + lane]; };               // volume-phase operand
   auto opf = [&](int o) { return tl[(o - M::FBASE) * 64 + lane]; };  // face-phase operand
+  auto opg = [&](int o) { return tmf[(long)o * 64 + lane]; };        // hanging-face operand (global)
 
   // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq]
   double wb[NV][NKS];
@@ -1139,7 +1218,7 @@ __global__ __launch_bounds__(256, K == 2 ? 2 : 1) void k_rhs_mfma3d(const double
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int m = 4 * ks + gq;
-      wb[v][ks] = (m < N && valid) ? w[(long)(v * N + m) * nc + cell] : 0.0;
+      wb[v][ks] = (m < N && valid) ? wbk[(long)(v * N + m) * nc + cell] : 0.0;
     }
 
   d4 acc[NV][NMT];
@@ -1188,65 +1267,157 @@ __global__ __launch_bounds__(256, K == 2 ? 2 : 1) void k_rhs_mfma3d(const double
     __syncthreads();
   }
 
+  // one MFMA chain over the K steps: D = sum_ks A(o0 + ks) B[ks]
+  auto chain = [&](auto &&A, int o0, const double (&B)[NKS]) {
+    d4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) z = __builtin_amdgcn_mfma_f64_16x16x4f64(A(o0 + ks), B[ks], z, 0, 0, 0);
+    return z;
+  };
+  // Riemann solves at this lane's points of one face tile and their lift
+  // (table op L0 + r NMT + mt), the flux zeroed in the columns `drop`
+  auto solve_lift = [&](auto &&A, int L0, int a, int s, int ft, const d4 (&To)[NV], const d4 (&Tn)[NV], bool drop) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (16 * ft + 4 * r >= QF) continue;
+      double Fh[NV];
+      if (16 * ft + 4 * r + gq < QF) {
+        double UL[NV], UR[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          UL[v] = s ? To[v][r] : Tn[v][r];
+          UR[v] = s ? Tn[v][r] : To[v][r];
+        }
+        hllc<double, 3, FX>(UL, UR, a, gam, Fh);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fh[v] = 0.0;
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double f = drop ? 0.0 : Fh[v];
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt)
+          acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A(L0 + r * NMT + mt), f, acc[v][mt], 0, 0, 0);
+      }
+    }
+  };
+
   // face integral (eq. dg_term3), each of the 2d sides from this cell's side
   // (unrolled: the next side's neighbour loads and table reads are issued
   // while the current side's Riemann solves run)
 #pragma unroll
   for (int fs = 0; fs < 6; ++fs) {
     const int a = fs >> 1, s = fs & 1;
-    const long nb = neighbour(g, ix, iy, iz, a, s ? 1 : -1);
-    const long src = nb >= 0 ? nb : cs;
+    const int dir = s ? 1 : -1;
+    // kind 0 regular, 1 wall (ghost = own trace), 2 hanging, 3 coarse neighbour
+    int kind = 0, hsub = 0, j[3] = {0, 0, 0};
+    long src = cs;
+    const double *nsrc = wbk;
+    long nn = nc;
+    if constexpr (AMR) {
+      if (!valid || hole) {
+        kind = 1;
+      } else if (!fine) {
+        if (!amr_coarse_nb<3>(ag, ci, a, dir, j)) kind = 1;
+        else if (amr_in_hole<3>(ag, j)) kind = 2;
+        else src = ((long)j[2] * ag.n[1] + j[1]) * ag.n[0] + j[0];
+      } else {
+        int f2[3] = {ci[0], ci[1], ci[2]};
+        f2[a] += dir;
+        if (f2[a] >= 0 && f2[a] < ag.nf[a]) {
+          src = ((long)f2[2] * ag.nf[1] + f2[1]) * ag.nf[0] + f2[0];
+        } else {
+          const int t0 = (a == 0) ? 1 : 0, t1 = (a == 2) ? 1 : 2;
+          int base[3];
+#pragma unroll
+          for (int b = 0; b < 3; ++b) base[b] = ag.lo[b] + ci[b] / 2;
+          amr_coarse_nb<3>(ag, base, a, dir, j);
+          kind = 3;
+          src = ((long)j[2] * ag.n[1] + j[1]) * ag.n[0] + j[0];
+          nsrc = w;
+          nn = ag.ncc;
+          hsub = (ci[t0] & 1) | ((ci[t1] & 1) << 1);
+        }
+      }
+    } else {
+      const long nb = neighbour(g, ci[0], ci[1], ci[2], a, dir);
+      if (nb >= 0) src = nb;
+      else kind = 1;
+    }
     double nbw[NV][NKS];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
       for (int ks = 0; ks < NKS; ++ks) {
         const int m = 4 * ks + gq;
-        nbw[v][ks] = m < N ? w[(long)(v * N + m) * nc + src] : 0.0;
+        nbw[v][ks] = m < N ? nsrc[(long)(v * N + m) * nn + src] : 0.0;
       }
 #pragma unroll
     for (int ft = 0; ft < M::NFT; ++ft) {
       d4 To[NV], Tn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        d4 zo = {0.0, 0.0, 0.0, 0.0}, zn = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) {
-          zo = __builtin_amdgcn_mfma_f64_16x16x4f64(opf(M::EF + ((a * 2 + s) * M::NFT + ft) * NKS + ks), wb[v][ks],
-                                                   zo, 0, 0, 0);
-          zn = __builtin_amdgcn_mfma_f64_16x16x4f64(opf(M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS + ks),
-                                                   nbw[v][ks], zn, 0, 0, 0);
-        }
-        To[v] = zo;
-        Tn[v] = nb >= 0 ? zn : zo;  // transmissive: ghost trace = own trace
+        To[v] = chain(opf, M::EF + ((a * 2 + s) * M::NFT + ft) * NKS, wb[v]);
+        const d4 zn = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, nbw[v]);
+        Tn[v] = kind == 0 ? zn : To[v];  // wall: ghost trace = own trace
       }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (16 * ft + 4 * r >= QF) continue;
-        double Fh[NV];
-        if (16 * ft + 4 * r + gq < QF) {
-          double UL[NV], UR[NV];
+      if constexpr (AMR) {
+        // a fine cell facing the coarse block: the coarse neighbour's trace
+        // at this cell's sub-face points
+#pragma unroll 1
+        for (int hs = 0; hs < 4; ++hs) {
+          if (!__any(kind == 3 && hsub == hs)) continue;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            UL[v] = s ? To[v][r] : Tn[v][r];
-            UR[v] = s ? Tn[v][r] : To[v][r];
+            const d4 zh = chain(opg, M::HGA + (((a * 2 + (1 - s)) * 4 + hs) * M::NFT + ft) * NKS, nbw[v]);
+            Tn[v] = (kind == 3 && hsub == hs) ? zh : Tn[v];
           }
-          hllc<double, 3, FX>(UL, UR, a, g.gamma, Fh);
-        } else {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) Fh[v] = 0.0;
         }
+      }
+      solve_lift(opf, M::LF + (((a * 2 + s) * M::NFT + ft) * 4) * NMT, a, s, ft, To, Tn, kind == 2);
+    }
+    if constexpr (AMR) {
+      // a coarse cell facing the fine block: its 2^(d-1) sub-faces
+      if (__any(kind == 2)) {
+        const int t0 = (a == 0) ? 1 : 0, t1 = (a == 2) ? 1 : 2;
+#pragma unroll 1
+        for (int sb = 0; sb < 4; ++sb) {
+          long fcell = 0;
+          if (kind == 2) {
+            int fi[3] = {0, 0, 0};
+            fi[a] = 2 * (j[a] - ag.lo[a]) + (s ? 0 : 1);
+            fi[t0] = 2 * (j[t0] - ag.lo[t0]) + (sb & 1);
+            fi[t1] = 2 * (j[t1] - ag.lo[t1]) + ((sb >> 1) & 1);
+            fcell = ((long)fi[2] * ag.nf[1] + fi[1]) * ag.nf[0] + fi[0];
+          }
+          const double *wf = w + (long)NW * ag.ncc;
+          double fw[NV][NKS];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+          for (int v = 0; v < NV; ++v)
 #pragma unroll
-          for (int mt = 0; mt < NMT; ++mt)
-            acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(
-                opf(M::LF + ((((a * 2 + s) * M::NFT + ft) * 4 + r) * NMT + mt)), Fh[v], acc[v][mt], 0, 0, 0);
+            for (int ks = 0; ks < NKS; ++ks) {
+              const int m = 4 * ks + gq;
+              fw[v][ks] = m < N ? wf[(long)(v * N + m) * ag.ncf + fcell] : 0.0;
+            }
+#pragma unroll
+          for (int ft = 0; ft < M::NFT; ++ft) {
+            d4 To[NV], Tn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+              To[v] = chain(opg, M::HGA + (((a * 2 + s) * 4 + sb) * M::NFT + ft) * NKS, wb[v]);
+              Tn[v] = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, fw[v]);
+            }
+            solve_lift(opg, M::HWA + ((((a * 2 + s) * 4 + sb) * M::NFT + ft) * 4) * NMT, a, s, ft, To, Tn,
+                       kind != 2);
+          }
+        }
       }
     }
   }
 
-  // assembly (L = (2/dx) 2^-d (V - S)) and the fused stage update
+  // assembly (L = (2/dx) 2^-d (V - S)) and the fused stage update; a hole
+  // cell of the coarse block gets L = 0
   bool bad = false;
   const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
 #pragma unroll
@@ -1255,12 +1426,12 @@ __global__ __launch_bounds__(256, K == 2 ? 2 : 1) void k_rhs_mfma3d(const double
     for (int mt = 0; mt < NMT; ++mt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int j = 16 * mt + 4 * r + gq;
-        if (j < N && valid) {
-          const long i = (long)(v * N + j) * nc + cell;
-          const double L = g.fac * acc[v][mt][r];
+        const int jm = 16 * mt + 4 * r + gq;
+        if (jm < N && valid) {
+          const long i = boff + (long)(v * N + jm) * nc + cell;
+          const double L = hole ? 0.0 : fac * acc[v][mt][r];
           bad |= (L != L);
-          out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, cldt, i);
+          out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, hole ? 0.0 : cldt, i);
         }
       }
   if (bad) atomicOr(flag, FLAG_NAN);
@@ -2088,37 +2259,6 @@ __global__ __launch_bounds__(256) void k_volume_bf16(const __bf16 *__restrict__ 
 // the same code, so the contributions cancel exactly in the sum of the means.
 // One thread per cell over both blocks.
 // ---------------------------------------------------------------------------
-struct AmrGrid {
-  int n[3];    // base (coarse) grid
-  int lo[3], hi[3];
-  int nf[3];   // fine block
-  long ncc, ncf;
-  int bc[3];
-  double facc, facf, dxc, dxf;
-  double gamma;
-};
-
-template <int D>
-__device__ inline bool amr_in_hole(const AmrGrid &g, const int *i) {
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-    if (i[a] < g.lo[a] || i[a] >= g.hi[a]) return false;
-  return true;
-}
-
-// base-grid neighbour along a (periodic); false at a transmissive wall
-template <int D>
-__device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int dir, int *j) {
-#pragma unroll
-  for (int b = 0; b < 3; ++b) j[b] = i[b];
-  j[a] += dir;
-  if (j[a] < 0 || j[a] >= g.n[a]) {
-    if (g.bc[a] == DG_BC_TRANSMISSIVE) return false;
-    j[a] = j[a] < 0 ? j[a] + g.n[a] : j[a] - g.n[a];
-  }
-  return true;
-}
-
 template <int D, int K, class R, int FX>
 __global__ __launch_bounds__(256) void k_rhs_amr(const double *__restrict__ tab, const R *__restrict__ tabr,
                                                  const double *__restrict__ w, double *__restrict__ out,
@@ -3270,6 +3410,20 @@ struct StageLaunch {
     if (c->amr) {
       if constexpr (K > 3) {
         return DG_EUNSUPPORTED;
+      } else if constexpr (D == 3 && (K == 2 || K == 3) && sizeof(R) == sizeof(double)) {
+        if (c->tabmf && !vext) {
+          // contractions on FP64 MFMA: coarse-block cells, then fine-block cells
+          const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
+          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, w, out, dt,
+                             make_grid(c), make_amr_grid(c), mode, mx, c->flag);
+        } else if constexpr (K == 3) {
+          // four lanes per cell (the one-thread kernel would spill)
+          hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock),
+                             0, s, c->tab, w, out, dt, make_amr_grid(c), mode, mx, c->flag);
+        } else {
+          hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s,
+                             c->tab, tabr, w, out, dt, vext, make_amr_grid(c), mode, mx, c->flag);
+        }
       } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
         // four lanes per cell (the one-thread kernel would spill)
         hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock), 0,
@@ -3309,8 +3463,8 @@ struct StageLaunch {
       }
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
-      hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s,
-                         c->tabmf, w, out, dt, make_grid(c), mode, mx, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
+                         s, c->tabmf, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
@@ -3322,8 +3476,8 @@ struct StageLaunch {
                          w, out, dt, make_uniform_amr_grid(c), mode, mx, c->flag);
     } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
-      hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s,
-                         c->tabmf, w, out, dt, make_grid(c), mode, mx, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
+                         s, c->tabmf, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else {
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
@@ -3508,7 +3662,7 @@ template <int K>
 std::vector<double> mf3_tables(const dg_ctx *c) {
   using C = Cfg<3, K>;
   using M = dg::Mf3<K>;
-  std::vector<double> t((size_t)M::OPS * 64, 0.0);
+  std::vector<double> t((size_t)(c->amr ? M::AOPS : M::OPS) * 64, 0.0);
   const std::vector<double> &h = c->host_tab;
   for (int l = 0; l < 64; ++l) {
     const int i = l % 16, k = l / 16;
@@ -3541,6 +3695,25 @@ std::vector<double> mf3_tables(const dg_ctx *c) {
             t[(size_t)(M::LF + (((fs * M::NFT + ft) * 4 + r) * M::NMT + mt)) * 64 + l] =
                 (pt < C::QF && j < C::N) ? sg * h[C::TW + (fs * C::QF + pt) * C::N + j] : 0.0;
           }
+    if (!c->amr) continue;
+    // refined box: per side and sub-face, the coarse basis at the sub-face's
+    // points (table HG) and the signed sub-face lift (table HW)
+    for (int fs = 0; fs < 6; ++fs)
+      for (int sb = 0; sb < 4; ++sb)
+        for (int ft = 0; ft < M::NFT; ++ft) {
+          for (int ks = 0; ks < M::NKS; ++ks) {
+            const int pt = 16 * ft + i, m = 4 * ks + k;
+            t[(size_t)(M::HGA + ((fs * 4 + sb) * M::NFT + ft) * M::NKS + ks) * 64 + l] =
+                (pt < C::QF && m < C::N) ? h[C::HG + ((fs * 4 + sb) * C::QF + pt) * C::N + m] : 0.0;
+          }
+          for (int r = 0; r < 4; ++r)
+            for (int mt = 0; mt < M::NMT; ++mt) {
+              const int pt = 16 * ft + 4 * r + k, j = 16 * mt + i;
+              const double sg = (fs & 1) ? -1.0 : 1.0;
+              t[(size_t)(M::HWA + (((fs * 4 + sb) * M::NFT + ft) * 4 + r) * M::NMT + mt) * 64 + l] =
+                  (pt < C::QF && j < C::N) ? sg * h[C::HW + ((fs * 4 + sb) * C::QF + pt) * C::N + j] : 0.0;
+            }
+        }
   }
   return t;
 }
@@ -3842,8 +4015,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const std::vector<double> zeros(DG_RATE_STATE, 0.0);
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
-  if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && !amr && cfg->precision == DG_FP64 &&
-      cfg->path3d != DG_PATH3D_VALU) {
+  if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && cfg->precision == DG_FP64 && cfg->path3d != DG_PATH3D_VALU) {
     const std::vector<double> T = cfg->k == 2 ? mf3_tables<2>(c) : mf3_tables<3>(c);
     if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
     if ((e = hipMemcpy(c->tabmf, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
