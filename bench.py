@@ -67,6 +67,9 @@ KERNELS = {
     "stage3d": dict(name="k_rhs_mfma3d<2>", traffic="k_rhs_mfma3d_kh3d128_k2_traffic.txt",
                     regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on FP64 MFMA.",
                                          "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
+    "stage3d_amr": dict(name="k_rhs_mfma3d<3,AMR>", traffic="k_rhs_mfma3d_blast64box_k3_traffic.txt",
+                        regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on FP64 MFMA.",
+                                             "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
     "stage3d_valu": dict(name="k_rhs_stage<3,2,double>", traffic="k_rhs_stage_kh3d128_k2_traffic.txt",
                          regions=_HELPERS + [("// Right-hand side and fused stage.",
                                               "// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.")]),
@@ -294,6 +297,30 @@ def variants():
                                      "alu_peak_tflops": peak}
             del s
             torch.cuda.empty_cache()
+    # the refined-box blast's stage kernel (MFMA) against the FP64 peak, with
+    # the four-lanes-per-cell VALU kernel and the limiter beside it
+    wl = workloads.workload("blast_amr", eps=1e-4)
+    kern = {}
+    for label, path in (("mfma", dg.DG_PATH3D_AUTO), ("valu", dg.DG_PATH3D_VALU)):
+        s = dg.Solver(dict(wl, path3d=path))
+        w = build_state(s, wl)
+        s.limit(w)
+        bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
+        kern[label] = kernel_ms(s, w, bufs, 10)
+        if label == "mfma":
+            kern["limiter"] = kernel_ms(s, w, bufs, 10, limiter=True)
+        cells = s.ncoarse - s.nhole + s.nfine
+        del s, w, bufs
+        torch.cuda.empty_cache()
+    b3, f3 = alg_work(3, 3)
+    out["blast_amr_kernels"] = {
+        "workload": "3D blast, 64^3 base grid + refined 32^3 box (64^3 fine cells), k=3, FP64",
+        "cells": cells, "alg_flops_per_launch": f3 * cells,
+        "mfma_kernel": "k_rhs_mfma3d<3,AMR>", "mfma_ms": kern["mfma"],
+        "mfma_frac": f3 * cells / (kern["mfma"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "valu_kernel": "k_rhs_amr_quad<3>", "valu_ms": kern["valu"],
+        "valu_frac": f3 * cells / (kern["valu"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+        "limiter_ms": kern["limiter"]}
     # adaptive KH (2D, 64^2 base, DG-4 with RK_4, characteristic limiter and
     # positivity): every 10 steps the flags (w_t = 0.01, alpha = 1.1), the box
     # around them with one buffer layer and, if it changed, the regrid
@@ -432,6 +459,9 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
     ap.add_argument("--variants", type=int, default=1, help="also time FP32, the 3D workload and the adjoint")
     ap.add_argument("--kernel-reps", type=int, default=30, help="launches per kernel timing")
+    ap.add_argument("--workload", default="kh3d", choices=("kh3d", "blast_amr"),
+                    help="the timed workload: the 128^3 shear layer (the headline) or the 64^3 blast with its refined "
+                         "box (k = 3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
@@ -440,11 +470,13 @@ def main():
     import torch
     import paper_1506_06140_amd as dg
 
-    wl = workloads.workload("kh3d")
+    wl = workloads.workload(args.workload)
+    kname = "stage3d" if args.workload == "kh3d" else "stage3d_amr"
     s = dg.Solver(wl)
     steps = args.steps + (args.steps % 2)
     ms_step, w = time_steps(s, wl, steps, args.warmup, graph=bool(args.graph))
-    dof = s.ncell * s.N
+    cells = (s.ncoarse - s.nhole + s.nfine) if s.amr else s.ncell
+    dof = cells * s.N
     value = dof * 3 / (ms_step * 1e-3)
 
     # the dominant kernel (fused RHS + stage) and the limiter pass, timed alone
@@ -453,12 +485,12 @@ def main():
     lim_ms = kernel_ms(s, w, bufs, args.kernel_reps, limiter=True)
     if s.status() != 0:
         raise RuntimeError("device error flag set in the kernel timing")
-    b, f = alg_work(3, 2)
-    alg_flops = f * s.ncell
-    alg_bytes = b * s.ncell
+    b, f = alg_work(3, wl["k"])
+    alg_flops = f * cells
+    alg_bytes = b * cells
     achieved = alg_flops / (k_ms * 1e-3) / 1e12
     # limiter: reads every coefficient once, writes the modes >= 1
-    lim_bytes = (2 * s.N - 1) * s.nvar * 8 * s.ncell
+    lim_bytes = (2 * s.N - 1) * s.nvar * 8 * cells
 
     rec = {
         "metric": METRIC,
@@ -473,17 +505,20 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "3D Kelvin-Helmholtz shear layer, 128^3 cells, k=2 (N=10), FP64, SSP-RK3, CFL 0.2, "
-                               "component-wise TVB minmod + positivity limiter after every stage, seeded 1e-2 "
-                               "velocity noise",
-                   "cells": s.ncell, "dof": dof, "stages_per_step": 3, "graph": bool(args.graph)},
+        "config": {"workload": ("3D Kelvin-Helmholtz shear layer, 128^3 cells, k=2 (N=10), FP64, SSP-RK3, CFL 0.2, "
+                                "component-wise TVB minmod + positivity limiter after every stage, seeded 1e-2 "
+                                "velocity noise") if args.workload == "kh3d" else
+                               ("3D Sod-type blast, 64^3 base grid + refined central 32^3 base cells (64^3 fine "
+                                "cells), k=3 (N=20), FP64, SSP-RK3, CFL 0.2, minmod + positivity limiter"),
+                   "cells": cells, "dof": dof, "stages_per_step": 3, "graph": bool(args.graph)},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic("stage3d"),
-                     "kernel": KERNELS["stage3d"]["name"], "kernel_ms": k_ms,
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": measured_traffic(kname),
+                     "kernel": KERNELS[kname]["name"], "kernel_ms": k_ms,
                      "alg_flops_per_launch": alg_flops, "alg_bytes_per_launch": alg_bytes,
                      "hbm_achieved_gbs": alg_bytes / (k_ms * 1e-3) / 1e9,
                      "hbm_frac": alg_bytes / (k_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
-        "limiter": {"kernel": "k_limit<3,2,false>", "kernel_ms": lim_ms, "alg_bytes_per_launch": lim_bytes,
+        "limiter": {"kernel": "k_limit<3,2,false>" if args.workload == "kh3d" else "k_limit_amr<3,3,false>",
+                    "kernel_ms": lim_ms, "alg_bytes_per_launch": lim_bytes,
                     "hbm_frac": lim_bytes / (lim_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         # the whole step's algorithmic work over the step time
         "step_fracs": {"alu": 3 * alg_flops / (ms_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
@@ -497,15 +532,16 @@ def main():
     s.limit(w)
     bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
     kv = kernel_ms(s, w, bufs, args.kernel_reps)
-    rec["roofline"]["valu_kernel"] = {"kernel": KERNELS["stage3d_valu"]["name"], "kernel_ms": kv,
+    rec["roofline"]["valu_kernel"] = {"kernel": "k_rhs_stage<3,2,double>" if args.workload == "kh3d" else
+                                      "k_rhs_amr_quad<3>", "kernel_ms": kv,
                                       "frac": alg_flops / (kv * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-                                      "traffic": measured_traffic("stage3d_valu")}
+                                      "traffic": measured_traffic("stage3d_valu") if args.workload == "kh3d" else None}
     del s, w, bufs
     torch.cuda.empty_cache()
     if args.variants:
         rec["variants"] = {"vortex2d_fp64": vortex2d_line(with_cpu=not args.no_cpu)}
         rec["variants"].update(variants())
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "kh3d":
         rec["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(rec), flush=True)
 
