@@ -1057,6 +1057,30 @@ __global__ __launch_bounds__((4 * Tile2D<K, TS>::TX * Tile2D<K, TS>::TY)) void k
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3D right-hand side + stage with the contractions on FP64 MFMA.
+//
+// Every contraction of eqs. dg_term2 and dg_term3 is a small GEMM batched
+// over cells, run with v_mfma_f64_16x16x4f64 (D[16x16] += A[16x4] B[4x16]):
+// a wave owns 16 consecutive cells (the GEMM columns), lane l = 16 g + c
+// holds B[g][c] and A[c][g] and receives D[4r + g][c] in its register r,
+// r = 0..3 (the operand layouts, checked on the device).
+//   evaluation  U_v[p][c] = sum_l E[p][l] w_v[l][c]        (A = table E,
+//               rows p = volume nodes or the nine points of one face side;
+//               B = the cells' modal weights, K = modes in steps of 4);
+//   projection  acc_v[j][c] += sum_p T[j][p] F_v[p][c]     (A = table T,
+//               rows j = modes; B = fluxes at the points).
+// The evaluation leaves in lane (g, c) the state of cell c at points
+// 4r + g, r = 0..3, all five variables, so the Euler flux and the HLLC flux
+// are computed in-lane (VALU, overlapping the matrix pipe), and register r of
+// that result is directly the B operand of the projection over the points
+// {4r + k : k = 0..3}: the tables' K order follows it, so no data moves
+// between lanes.  Tables (the A operands, laid out per lane) sit in LDS.
+// Point and mode indices 4r + g make whole registers r padding (points or
+// modes past the end), which are skipped at compile time.
+// As in k_rhs_stage, each face is evaluated by both of its cells from the
+// same weights, tables and operation order, so both obtain the same flux.
+// ---------------------------------------------------------------------------
 // The refined box's geometry (see k_rhs_amr below).
 struct AmrGrid {
   int n[3];    // base (coarse) grid
@@ -1089,30 +1113,6 @@ __device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int 
   return true;
 }
 
-// ---------------------------------------------------------------------------
-// 3D right-hand side + stage with the contractions on FP64 MFMA.
-//
-// Every contraction of eqs. dg_term2 and dg_term3 is a small GEMM batched
-// over cells, run with v_mfma_f64_16x16x4f64 (D[16x16] += A[16x4] B[4x16]):
-// a wave owns 16 consecutive cells (the GEMM columns), lane l = 16 g + c
-// holds B[g][c] and A[c][g] and receives D[4r + g][c] in its register r,
-// r = 0..3 (the operand layouts, checked on the device).
-//   evaluation  U_v[p][c] = sum_l E[p][l] w_v[l][c]        (A = table E,
-//               rows p = volume nodes or the nine points of one face side;
-//               B = the cells' modal weights, K = modes in steps of 4);
-//   projection  acc_v[j][c] += sum_p T[j][p] F_v[p][c]     (A = table T,
-//               rows j = modes; B = fluxes at the points).
-// The evaluation leaves in lane (g, c) the state of cell c at points
-// 4r + g, r = 0..3, all five variables, so the Euler flux and the HLLC flux
-// are computed in-lane (VALU, overlapping the matrix pipe), and register r of
-// that result is directly the B operand of the projection over the points
-// {4r + k : k = 0..3}: the tables' K order follows it, so no data moves
-// between lanes.  Tables (the A operands, laid out per lane) sit in LDS.
-// Point and mode indices 4r + g make whole registers r padding (points or
-// modes past the end), which are skipped at compile time.
-// As in k_rhs_stage, each face is evaluated by both of its cells from the
-// same weights, tables and operation order, so both obtain the same flux.
-// ---------------------------------------------------------------------------
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int K>
@@ -1941,13 +1941,24 @@ static_assert(mode_exp<3>(1, 0) == 1 && mode_exp<3>(2, 1) == 1 && mode_exp<3>(3,
 // max over the reference cell of |phi_l| = prod_a sqrt(2 e_a + 1), from
 // |P_n| <= 1 on [-1, 1]
 template <int D>
-__device__ constexpr double basis_bound(int l) {
+__host__ __device__ constexpr double basis_bound(int l) {
   constexpr double r[9] = {1.0, 1.7320508075688772, 2.2360679774997898, 2.6457513110645907, 3.0,
                            3.3166247903554, 3.6055512754639891, 3.872983346207417, 4.1231056256176606};
   double b = 1.0;
   for (int a = 0; a < D; ++a) b *= r[mode_exp<D>(l, a)];
   return b;
 }
+
+// basis_bound of modes 0..N-1, evaluated by the compiler (a call left to run
+// time would index the table with a computed exponent and put it in scratch
+// memory)
+template <int D, int N>
+struct BasisBounds {
+  double b[N];
+  __host__ __device__ constexpr BasisBounds() : b() {
+    for (int l = 0; l < N; ++l) b[l] = basis_bound<D>(l);
+  }
+};
 
 // True when the cell's polynomial has, at every point of the reference cell,
 // a density and a pressure above eps by a margin (1e-10 of the quantities'
@@ -1959,12 +1970,13 @@ __device__ constexpr double basis_bound(int l) {
 // |m|_hi^2 / (2 rho_lo)).
 template <int D, int N>
 __device__ inline bool positivity_certain(const double (&wc)[D + 2][N], double gamma, double eps) {
+  constexpr BasisBounds<D, N> bb;
   double R[D + 2];
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) {
     double r = 0.0;
 #pragma unroll
-    for (int l = 1; l < N; ++l) r = fma(fabs(wc[v][l]), basis_bound<D>(l), r);
+    for (int l = 1; l < N; ++l) r = fma(fabs(wc[v][l]), bb.b[l], r);
     R[v] = r;
   }
   const double rlo = wc[0][0] - R[0];
@@ -3111,21 +3123,22 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 #pragma unroll
     for (int l = 0; l < NL; ++l) wc[v][l] = wb[(long)(v * N + l) * ncb + cell];
   }
-  // neighbour means [2D][NV]
+  // neighbour means [2D][NV]; bit f of hmask: side f is a hanging face (a
+  // bit mask rather than an array, which a run-time index would put in
+  // scratch memory)
   double nbm[2 * D][NV];
-  bool hang[2 * D];
+  int hmask = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      hang[2 * a + s] = false;
       if (!fine) {
         int j[3];
         if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) nbm[2 * a + s][v] = wc[v][0];
         } else if (amr_in_hole<D>(g, j)) {
-          hang[2 * a + s] = true;
+          hmask |= 1 << (2 * a + s);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             double m = 0.0;
@@ -3218,18 +3231,28 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
     } else if (!positivity_certain<D, N>(wc, g.gamma, eps)) {
       // points: the union set S, then the hanging-face points of every
       // refined face of a coarse cell (all inside the reference cell, so
-      // the bound of positivity_certain covers them too)
-      const int nextra = fine ? 0 : 2 * D * NSUB * C::QF;
-      double rmin = INFINITY;
-      for (int s2 = 0; s2 < C::NS + nextra; ++s2) {
-        const double *ph;
-        if (s2 < C::NS) {
-          ph = tab + C::PS + s2 * N;
-        } else {
-          const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
-          if (!hang[f]) continue;
-          ph = tab + C::HG + (((f >> 1) * 2 + (f & 1)) * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
+      // the bound of positivity_certain covers them too); point s2 of the
+      // combined list, s2 >= NS: face (s2 - NS) / (NSUB QF), sub-face point
+      // (s2 - NS) mod (NSUB QF), rows of table HG
+      auto point = [&](int s2) {
+        if (s2 < C::NS) return tab + C::PS + s2 * N;
+        const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
+        return tab + C::HG + (f * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
+      };
+      // the faces' point ranges are walked only for the hanging faces
+      auto next = [&](int s2) {
+        ++s2;
+        while (s2 >= C::NS && s2 < C::NS + 2 * D * NSUB * C::QF) {
+          const int f = (s2 - C::NS) / (NSUB * C::QF);
+          if ((hmask >> f) & 1) break;
+          s2 = C::NS + (f + 1) * NSUB * C::QF;
         }
+        return s2;
+      };
+      const int send = C::NS + 2 * D * NSUB * C::QF;
+      double rmin = INFINITY;
+      for (int s2 = 0; s2 < send; s2 = next(s2)) {
+        const double *ph = point(s2);
         double r = 0.0;
 #pragma unroll
         for (int l = 0; l < N; ++l) r = fma(wc[0][l], ph[l], r);
@@ -3239,15 +3262,8 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 #pragma unroll
       for (int l = 1; l < N; ++l) wc[0][l] *= th1;
       double th2 = 1.0;
-      for (int s2 = 0; s2 < C::NS + nextra; ++s2) {
-        const double *ph;
-        if (s2 < C::NS) {
-          ph = tab + C::PS + s2 * N;
-        } else {
-          const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
-          if (!hang[f]) continue;
-          ph = tab + C::HG + (((f >> 1) * 2 + (f & 1)) * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
-        }
+      for (int s2 = 0; s2 < send; s2 = next(s2)) {
+        const double *ph = point(s2);
         double Uq[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {

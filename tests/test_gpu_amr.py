@@ -58,7 +58,15 @@ CASES = [
 RHS_CASES = ([(c + "_kh", dict(s, ic="kh3d")) for c, s in CASES]
              + [(c + "_blast", s) for c, s in CASES if s["dim"] == 3]
              + [("3d_k2_kh_davis", dict(CASES[2][1], ic="kh3d", flux=1)),
-                ("2d_k2_kh_davis", dict(CASES[0][1], ic="kh3d", flux=1))])
+                ("2d_k2_kh_davis", dict(CASES[0][1], ic="kh3d", flux=1)),
+                # 3D FP64 runs the MFMA kernel by default; the vector-ALU
+                # kernels (path3d = DG_PATH3D_VALU) on the same boxes
+                ("3d_k2_kh_valu", dict(CASES[2][1], ic="kh3d", path3d=1)),
+                ("3d_k3_kh_valu", dict(CASES[3][1], ic="kh3d", path3d=1)),
+                ("3d_k3_blast_valu", dict(CASES[3][1], path3d=1)),
+                # a box touching the periodic wrap of the base grid's x axis
+                # and a box one cell wide along z
+                ("3d_k3_kh_edges", dict(dim=3, k=3, n=(8, 7, 6), lo=(1, 2, 2), hi=(7, 5, 3), ic="kh3d"))])
 
 
 def rough_amr_state(o, seed, amp=0.02):
