@@ -101,11 +101,14 @@ typedef struct {
                       /* DG_TILE2D_AUTO (0, the rule of dg_init),              */
                       /* DG_TILE2D_8X8 or DG_TILE2D_LARGE (16 x 16 for k <= 2, */
                       /* 16 x 8 for k = 3, 4); results equal to rounding       */
-  int path3d;         /* 3D uniform grids, k = 2 or 3, FP64, no gravity: the   */
-                      /* stage kernel's contractions on FP64 MFMA             */
-                      /* (DG_PATH3D_AUTO, 0) or on the vector ALU             */
-                      /* (DG_PATH3D_VALU: one thread per cell at k = 2, four  */
-                      /* lanes per cell at k = 3); results equal to rounding  */
+  int path3d;         /* 3D, k = 2 or 3, no gravity: DG_PATH3D_AUTO (0) runs   */
+                      /* the stage kernel's contractions on MFMA: FP64 on     */
+                      /* FP64 MFMA; FP32 on FP32 MFMA at k = 3 and on refined */
+                      /* boxes (FP32 at k = 2 on a uniform grid keeps the     */
+                      /* one-thread-per-cell kernel, faster there);           */
+                      /* DG_PATH3D_VALU runs them on the vector ALU (one      */
+                      /* thread per cell; FP64 at k = 3 four lanes per cell); */
+                      /* results equal to rounding                            */
 } dg_config;
 
 /* Builds the basis and quadrature tables (Gauss-Legendre nodes by Newton
@@ -116,7 +119,8 @@ typedef struct {
  * cfg->tile2d = DG_TILE2D_AUTO, on 2D grids without refinement the stage
  * kernel works on tiles of 8 x 8 cells for k <= 3; at k = 4 on tiles of
  * 16 x 8 cells, or of 8 x 8 when the grid has fewer 16 x 8 tiles than the GPU
- * has compute units. */
+ * has compute units.  DG_EUNSUPPORTED for a base grid or a fine block of more
+ * than 2^31 cells (kernels index a block's cells in 32 bits). */
 int dg_init(const dg_config *cfg, dg_ctx **out);
 
 /* Number of doubles in one state array (nvar * N * cells). */

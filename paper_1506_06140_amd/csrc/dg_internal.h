@@ -87,6 +87,8 @@ struct dg_ctx {
   double grav_k = 0.0;
   double *prmat = nullptr;  // refinement matrices on the device (dg_amr_flags, dg_amr_regrid)
   double *tabmf = nullptr;  // A-operand tables of the 3D MFMA stage kernel (null: the VALU kernel)
+  float *tabmf32 = nullptr; // the same in FP32, rows in the FP32 MFMA's order (FP32 path)
+  double *tablw = nullptr;  // FP64 mode-0 lift weights of the FP32 MFMA kernel
   // 2D tile size: -1 automatic (dg::tile2d_small: 8x8 tiles for k <= 3, and
   // for k = 4 on grids with fewer 16x8 tiles than CUs), 0 always the large
   // tiles, 1 always 8x8 (dg_config.tile2d)

@@ -200,11 +200,16 @@ __device__ inline float cst<float>(double x) { return (float)x; }
 // hanging sub-faces of the refined box), the compiler built the flag's lane
 // mask under one exec mask and reused it under another, so lanes that had
 // been inactive took the other branch.
-template <class T, int D, int FX>
+template <class T, int D, int FX, bool SEL = false>
 __device__ inline void hllc(const T *UL, const T *UR, int a, double g, T *F) {
   // The normal axis a may be a run-time value: components are picked with
   // unrolled compares (no dynamic register indexing).  One reciprocal square
-  // root per side gives sqrt(rho) and 1/rho.
+  // root per side gives sqrt(rho) and 1/rho.  SEL: every arm of a
+  // conditional is evaluated and the result selected, so the solver contains
+  // no branch (a conditional with a costly arm otherwise becomes a divergent
+  // branch, which splits the caller's code into separately scheduled blocks;
+  // the one-thread-per-cell kernels run faster with the branches).  The
+  // results are the same bit for bit.
   const T gm1 = cst<T>(g - 1.0), gg = cst<T>(g), half = cst<T>(0.5);
   const T zero = cst<T>(0.0);
   const T rsL = vrsq(UL[0]), rsR = vrsq(UR[0]);
@@ -245,7 +250,13 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, T *F) {
     const T HL = (UL[D + 1] + pL) * irL, HR = (UR[D + 1] + pR) * irR;
     const T Ht = (sL * HL + sR * HR) * is;
     const T ct2 = gm1 * (Ht - half * q2);
-    const T ct = val(ct2) > 0.0 ? ct2 * vrsq(ct2) : zero;
+    T ct;
+    if constexpr (SEL) {
+      const T rq = vrsq(ct2);
+      ct = val(ct2) > 0.0 ? ct2 * rq : zero;
+    } else {
+      ct = val(ct2) > 0.0 ? ct2 * vrsq(ct2) : zero;
+    }
     SL = vmin(uL - cL, ut - ct);
     SR = vmax(uR + cR, ut + ct);
   }
@@ -256,7 +267,13 @@ __device__ inline void hllc(const T *UL, const T *UR, int a, double g, T *F) {
 #pragma unroll
   for (int v = 0; v < D + 2; ++v) U[v] = left ? UL[v] : UR[v];
   const T SK = left ? SL : SR;
-  const T SKc = left ? vmin(SL, zero) : vmax(SR, zero);
+  T SKc;
+  if constexpr (SEL) {
+    const T SLc = vmin(SL, zero), SRc = vmax(SR, zero);
+    SKc = left ? SLc : SRc;
+  } else {
+    SKc = left ? vmin(SL, zero) : vmax(SR, zero);
+  }
   const T irK = left ? irL : irR, pK = left ? pL : pR;
   const T uK = left ? uL : uR, dK = left ? dL : dR, mK = left ? mL : mR;
   T FK[D + 2];
@@ -1114,8 +1131,27 @@ __device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int 
 }
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int K>
+// D += A B on the 16x16x4 MFMA of the contraction type.  The FP32 form's
+// result rows lie transposed within each group of four: register r of lane
+// (g, c) holds D[4 g + r][c] (FP64: D[4 r + g][c]), which the FP32 tables
+// undo by storing row 4 g + r at operand row 4 r + g (mf3_tables_f32), so
+// the kernel's register and lane bookkeeping is that of the FP64 form.
+template <class R>
+struct Mv4;
+template <>
+struct Mv4<double> {
+  using T = d4;
+  static __device__ inline T mma(double a, double b, T c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+};
+template <>
+struct Mv4<float> {
+  using T = f4;
+  static __device__ inline T mma(float a, float b, T c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+};
+
+template <int K, class R = double>
 struct Mf3 {
   using C = Cfg<3, K>;
   static constexpr int N = C::N, Q = C::Q, QF = C::QF, NV = C::NV;
@@ -1135,9 +1171,12 @@ struct Mf3 {
   static constexpr int HGA = OPS;                            // [3][2][4][NFT][NKS]
   static constexpr int HWA = HGA + 24 * NFT * NKS;           // [3][2][4][NFT][4][NMT]
   static constexpr int AOPS = HWA + 24 * NFT * 4 * NMT;
-  // when all of them exceed 64 KB (k = 3: 97 KB), LDS holds one phase's
-  // blocks at a time (k = 3: 58 KB), the face phase's loaded after the volume
-  static constexpr bool SPLIT = OPS * 64 * 8 > 65536;
+  // when all of them exceed 64 KB (k = 3, FP64: 97 KB), LDS holds one
+  // phase's blocks at a time (58 KB), the face phase's loaded after the volume
+  static constexpr bool SPLIT = OPS * 64 * (int)sizeof(R) > 65536;
+  // FP32 path: the FP64 lift weights of mode 0, per lane group g, [6][NFT][4][4]
+  // (regular faces), then [6][4][NFT][4][4] (refined box: sub-faces)
+  static constexpr int LW = 6 * NFT * 16, LWH = LW, LWTOT = LW + 24 * NFT * 16;
   static constexpr int VOPS = EF, FOPS = OPS - EF;
   static constexpr int LDSOPS = !SPLIT ? OPS : (VOPS > FOPS ? VOPS : FOPS);
   static constexpr int FBASE = SPLIT ? EF : 0;  // LDS block of face-phase operand o: o - FBASE
@@ -1145,7 +1184,9 @@ struct Mf3 {
 
 // Two waves per SIMD at k = 2 (<= 256 registers per lane): at one wave the
 // matrix pipe idled while the wave waited on its own MFMA results and loads
-// (5.3 ms against 3.2 ms per 128^3 launch).
+// (5.3 ms against 3.2 ms per 128^3 launch).  One wave where two would spill:
+// k = 3, and the refined box at k = 2 in FP64 (FP32 at k = 2: three waves
+// would spill 53 registers).
 //
 // AMR: the refined box of Sec. 4 (static 2:1 box; state = coarse block, then
 // fine block).  Blocks of the grid cover the coarse block's cells, then the
@@ -1161,16 +1202,24 @@ struct Mf3 {
 // table, the same weights and the same chain: the same flux bit for bit.
 // The hanging and coarse-neighbour chains run only in waves that hold such
 // a column, with their tables read from global memory.
-template <int K, int FX, bool AMR>
-__global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(const double *__restrict__ tmf,
-                                                                 const double *__restrict__ w,
-                                                                 double *__restrict__ out,
-                                                                 const double *__restrict__ dtp, Grid g, AmrGrid ag,
-                                                                 int mode, Mix mx, int *__restrict__ flag) {
-  using M = Mf3<K>;
+//
+// R = float (the FP32 path): contractions, fluxes and Riemann solves in FP32
+// on v_mfma_f32_16x16x4f32; the lift of mode 0 (the cell mean) is summed in
+// FP64 from the FP32 face fluxes (tlw: its FP64 weights per lane group), and
+// the stage update is FP64, as in k_rhs_stage.
+template <int K, int FX, bool AMR, class R = double>
+__global__ __launch_bounds__(256, (K == 2 && (!AMR || sizeof(R) == 4)) ? 2 : 1) void k_rhs_mfma3d(
+    const R *__restrict__ tmf, const double *__restrict__ tlw, const double *__restrict__ w, double *__restrict__ out,
+    const double *__restrict__ dtp, Grid g, AmrGrid ag, int mode, Mix mx, int *__restrict__ flag) {
+  using M = Mf3<K, R>;
+  using V4 = typename Mv4<R>::T;
   constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q, NW = NV * N;
-  __shared__ double tl[M::LDSOPS * 64];
+  constexpr bool LO64 = sizeof(R) == sizeof(float);  // mode 0 lifted in FP64
+  __shared__ R tl[M::LDSOPS * 64];
+  __shared__ double lws[LO64 ? M::LW : 1];
   for (int i = threadIdx.x; i < (M::SPLIT ? M::VOPS : M::OPS) * 64; i += blockDim.x) tl[i] = tmf[i];
+  if constexpr (LO64)
+    for (int i = threadIdx.x; i < M::LW; i += blockDim.x) lws[i] = tlw[i];
   __syncthreads();
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1203,59 +1252,79 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
   const long cell = (blk * 4 + wv) * 16 + col;
   const bool valid = cell < nc;
   const long cs = valid ? cell : nc - 1;  // a valid address for the padding columns
-  int ci[3] = {(int)(cs % bn[0]), (int)((cs / bn[0]) % bn[1]), (int)(cs / ((long)bn[0] * bn[1]))};
+  // 32-bit index arithmetic (dg_init admits blocks of at most 2^31 cells)
+  const unsigned cu = (unsigned)cs, pl = (unsigned)bn[0] * (unsigned)bn[1];
+  int ci[3] = {(int)(cu % (unsigned)bn[0]), (int)((cu / (unsigned)bn[0]) % (unsigned)bn[1]), (int)(cu / pl)};
   bool hole = false;
   if constexpr (AMR) hole = !fine && amr_in_hole<3>(ag, ci);
-  const double gm1 = gam - 1.0;
+  const R gm1 = (R)(gam - 1.0);
   auto op = [&](int o) { return tl[o * 64 + lane]; };               // volume-phase operand
   auto opf = [&](int o) { return tl[(o - M::FBASE) * 64 + lane]; };  // face-phase operand
   auto opg = [&](int o) { return tmf[(long)o * 64 + lane]; };        // hanging-face operand (global)
 
-  // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq]
-  double wb[NV][NKS];
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
+  // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq].  Loads
+  // of padding (modes past N, columns past the grid) read a valid address
+  // and are zeroed by a select: no branches, so the scheduler can overlap
+  // loads, matrix and vector work across the whole kernel
+  // (addresses: a per-lane offset per K step plus the variable's uniform
+  // offset, which keeps the 64-bit index arithmetic out of the vector ALU)
+  auto lane_offsets = [&](long stride, long cellidx, long (&o)[NKS]) {
 #pragma unroll
     for (int ks = 0; ks < NKS; ++ks) {
       const int m = 4 * ks + gq;
-      wb[v][ks] = (m < N && valid) ? wbk[(long)(v * N + m) * nc + cell] : 0.0;
+      o[ks] = (long)(m < N ? m : N - 1) * stride + cellidx;
     }
+  };
+  R wb[NV][NKS];
+  {
+    long o[NKS];
+    lane_offsets(nc, cs, o);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) {
+        const double x = wbk[(long)(v * N) * nc + o[ks]];
+        wb[v][ks] = (4 * ks + gq < N && valid) ? (R)x : R(0);
+      }
+  }
 
-  d4 acc[NV][NMT];
+  V4 acc[NV][NMT];
+  double acc0[NV];  // FP32 path: this lane's share of the mode-0 lift, FP64
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
+  for (int v = 0; v < NV; ++v) {
+    acc0[v] = 0.0;
 #pragma unroll
-    for (int mt = 0; mt < NMT; ++mt) acc[v][mt] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int mt = 0; mt < NMT; ++mt) acc[v][mt] = V4{R(0), R(0), R(0), R(0)};
+  }
 
   // volume integral (eq. dg_term2)
 #pragma unroll
   for (int t = 0; t < M::NQT; ++t) {
-    d4 U[NV];
+    V4 U[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      d4 z = {0.0, 0.0, 0.0, 0.0};
+      V4 z = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) z = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::EV + t * NKS + ks), wb[v][ks], z, 0, 0, 0);
+      for (int ks = 0; ks < NKS; ++ks) z = Mv4<R>::mma(op(M::EV + t * NKS + ks), wb[v][ks], z);
       U[v] = z;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (16 * t + 4 * r >= Q) continue;
       const bool ok = 16 * t + 4 * r + gq < Q;
-      double Ur[NV];
+      R Ur[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Ur[v] = ok ? U[v][r] : (v == 0 ? 1.0 : (v == NV - 1 ? 1.0 : 0.0));
+      for (int v = 0; v < NV; ++v) Ur[v] = ok ? U[v][r] : (v == 0 ? R(1) : (v == NV - 1 ? R(1) : R(0)));
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        double F[NV];
-        euler_flux<3, double>(Ur, a, gm1, F);
+        R F[NV];
+        euler_flux<3, R>(Ur, a, gm1, F);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const double f = ok ? F[v] : 0.0;
+          const R f = ok ? F[v] : R(0);
 #pragma unroll
           for (int mt = 0; mt < NMT; ++mt)
-            acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(op(M::PV + ((a * M::NQT + t) * 4 + r) * NMT + mt), f,
-                                                              acc[v][mt], 0, 0, 0);
+            acc[v][mt] = Mv4<R>::mma(op(M::PV + ((a * M::NQT + t) * 4 + r) * NMT + mt), f, acc[v][mt]);
         }
       }
     }
@@ -1268,37 +1337,36 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
   }
 
   // one MFMA chain over the K steps: D = sum_ks A(o0 + ks) B[ks]
-  auto chain = [&](auto &&A, int o0, const double (&B)[NKS]) {
-    d4 z = {0.0, 0.0, 0.0, 0.0};
+  auto chain = [&](auto &&A, int o0, const R (&B)[NKS]) {
+    V4 z = {R(0), R(0), R(0), R(0)};
 #pragma unroll
-    for (int ks = 0; ks < NKS; ++ks) z = __builtin_amdgcn_mfma_f64_16x16x4f64(A(o0 + ks), B[ks], z, 0, 0, 0);
+    for (int ks = 0; ks < NKS; ++ks) z = Mv4<R>::mma(A(o0 + ks), B[ks], z);
     return z;
   };
   // Riemann solves at this lane's points of one face tile and their lift
-  // (table op L0 + r NMT + mt), the flux zeroed in the columns `drop`
-  auto solve_lift = [&](auto &&A, int L0, int a, int s, int ft, const d4 (&To)[NV], const d4 (&Tn)[NV], bool drop) {
+  // (table op L0 + r NMT + mt; FP32 path: mode 0 in FP64 with the weights
+  // lw[4 r + gq]), the flux zeroed in the columns `drop`
+  auto solve_lift = [&](auto &&A, int L0, const double *lw, int a, int s, int ft, const V4 (&To)[NV],
+                        const V4 (&Tn)[NV], bool drop) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (16 * ft + 4 * r >= QF) continue;
-      double Fh[NV];
-      if (16 * ft + 4 * r + gq < QF) {
-        double UL[NV], UR[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          UL[v] = s ? To[v][r] : Tn[v][r];
-          UR[v] = s ? Tn[v][r] : To[v][r];
-        }
-        hllc<double, 3, FX>(UL, UR, a, gam, Fh);
-      } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Fh[v] = 0.0;
-      }
+      // every lane solves (points past QF: zero traces, the result discarded
+      // by the select below), so that no branch splits the kernel
+      const bool pt = 16 * ft + 4 * r + gq < QF;
+      R Fh[NV], UL[NV], UR[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const double f = drop ? 0.0 : Fh[v];
+        UL[v] = s ? To[v][r] : Tn[v][r];
+        UR[v] = s ? Tn[v][r] : To[v][r];
+      }
+      hllc<R, 3, FX, true>(UL, UR, a, gam, Fh);
 #pragma unroll
-        for (int mt = 0; mt < NMT; ++mt)
-          acc[v][mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(A(L0 + r * NMT + mt), f, acc[v][mt], 0, 0, 0);
+      for (int v = 0; v < NV; ++v) {
+        const R f = (drop || !pt) ? R(0) : Fh[v];
+        if constexpr (LO64) acc0[v] = fma((double)f, lw[4 * r + gq], acc0[v]);
+#pragma unroll
+        for (int mt = 0; mt < NMT; ++mt) acc[v][mt] = Mv4<R>::mma(A(L0 + r * NMT + mt), f, acc[v][mt]);
       }
     }
   };
@@ -1341,25 +1409,34 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
         }
       }
     } else {
-      const long nb = neighbour(g, ci[0], ci[1], ci[2], a, dir);
-      if (nb >= 0) src = nb;
-      else kind = 1;
+      // periodic wrap or (transmissive) the cell itself, as selects
+      int j2[3] = {ci[0], ci[1], ci[2]};
+      const int n = bn[a], i2 = j2[a] + dir;
+      const bool outside = (i2 < 0) | (i2 >= n);
+      j2[a] = i2 < 0 ? i2 + n : (i2 >= n ? i2 - n : i2);
+      kind = (outside & (g.bc[a] == DG_BC_TRANSMISSIVE)) ? 1 : 0;
+      const long nb = ((long)j2[2] * bn[1] + j2[1]) * bn[0] + j2[0];
+      src = kind ? cs : nb;
     }
-    double nbw[NV][NKS];
+    R nbw[NV][NKS];
+    {
+      long o[NKS];
+      lane_offsets(nn, src, o);
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+      for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int ks = 0; ks < NKS; ++ks) {
-        const int m = 4 * ks + gq;
-        nbw[v][ks] = m < N ? nsrc[(long)(v * N + m) * nn + src] : 0.0;
-      }
+        for (int ks = 0; ks < NKS; ++ks) {
+          const double x = nsrc[(long)(v * N) * nn + o[ks]];
+          nbw[v][ks] = 4 * ks + gq < N ? (R)x : R(0);
+        }
+    }
 #pragma unroll
     for (int ft = 0; ft < M::NFT; ++ft) {
-      d4 To[NV], Tn[NV];
+      V4 To[NV], Tn[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         To[v] = chain(opf, M::EF + ((a * 2 + s) * M::NFT + ft) * NKS, wb[v]);
-        const d4 zn = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, nbw[v]);
+        const V4 zn = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, nbw[v]);
         Tn[v] = kind == 0 ? zn : To[v];  // wall: ghost trace = own trace
       }
       if constexpr (AMR) {
@@ -1370,12 +1447,13 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
           if (!__any(kind == 3 && hsub == hs)) continue;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const d4 zh = chain(opg, M::HGA + (((a * 2 + (1 - s)) * 4 + hs) * M::NFT + ft) * NKS, nbw[v]);
+            const V4 zh = chain(opg, M::HGA + (((a * 2 + (1 - s)) * 4 + hs) * M::NFT + ft) * NKS, nbw[v]);
             Tn[v] = (kind == 3 && hsub == hs) ? zh : Tn[v];
           }
         }
       }
-      solve_lift(opf, M::LF + (((a * 2 + s) * M::NFT + ft) * 4) * NMT, a, s, ft, To, Tn, kind == 2);
+      solve_lift(opf, M::LF + (((a * 2 + s) * M::NFT + ft) * 4) * NMT,
+                 LO64 ? lws + ((a * 2 + s) * M::NFT + ft) * 16 : nullptr, a, s, ft, To, Tn, kind == 2);
     }
     if constexpr (AMR) {
       // a coarse cell facing the fine block: its 2^(d-1) sub-faces
@@ -1392,27 +1470,42 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
             fcell = ((long)fi[2] * ag.nf[1] + fi[1]) * ag.nf[0] + fi[0];
           }
           const double *wf = w + (long)NW * ag.ncc;
-          double fw[NV][NKS];
+          R fw[NV][NKS];
+          long o[NKS];
+          lane_offsets(ag.ncf, fcell, o);
 #pragma unroll
           for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
-              const int m = 4 * ks + gq;
-              fw[v][ks] = m < N ? wf[(long)(v * N + m) * ag.ncf + fcell] : 0.0;
+              const double x = wf[(long)(v * N) * ag.ncf + o[ks]];
+              fw[v][ks] = 4 * ks + gq < N ? (R)x : R(0);
             }
 #pragma unroll
           for (int ft = 0; ft < M::NFT; ++ft) {
-            d4 To[NV], Tn[NV];
+            V4 To[NV], Tn[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
               To[v] = chain(opg, M::HGA + (((a * 2 + s) * 4 + sb) * M::NFT + ft) * NKS, wb[v]);
               Tn[v] = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, fw[v]);
             }
-            solve_lift(opg, M::HWA + ((((a * 2 + s) * 4 + sb) * M::NFT + ft) * 4) * NMT, a, s, ft, To, Tn,
-                       kind != 2);
+            solve_lift(opg, M::HWA + ((((a * 2 + s) * 4 + sb) * M::NFT + ft) * 4) * NMT,
+                       LO64 ? tlw + M::LWH + (((a * 2 + s) * 4 + sb) * M::NFT + ft) * 16 : nullptr, a, s, ft, To,
+                       Tn, kind != 2);
           }
         }
       }
+    }
+  }
+
+  // FP32 path: the four lane groups' shares of the mode-0 lift, summed in
+  // the same order in every lane
+  if constexpr (LO64) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double t = acc0[v];
+      t += __shfl_xor(t, 16);
+      t += __shfl_xor(t, 32);
+      acc0[v] = t;
     }
   }
 
@@ -1420,6 +1513,7 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
   // cell of the coarse block gets L = 0
   bool bad = false;
   const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
+  const long ol = boff + (long)gq * nc + cs;  // this lane's part of the output index
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -1428,8 +1522,9 @@ __global__ __launch_bounds__(256, (K == 2 && !AMR) ? 2 : 1) void k_rhs_mfma3d(co
       for (int r = 0; r < 4; ++r) {
         const int jm = 16 * mt + 4 * r + gq;
         if (jm < N && valid) {
-          const long i = boff + (long)(v * N + jm) * nc + cell;
-          const double L = hole ? 0.0 : fac * acc[v][mt][r];
+          const long i = (long)(v * N + 16 * mt + 4 * r) * nc + ol;
+          const double Lv = (LO64 && jm == 0) ? acc0[v] : (double)acc[v][mt][r];
+          const double L = hole ? 0.0 : fac * Lv;
           bad |= (L != L);
           out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, hole ? 0.0 : cldt, i);
         }
@@ -3426,12 +3521,22 @@ struct StageLaunch {
     if (c->amr) {
       if constexpr (K > 3) {
         return DG_EUNSUPPORTED;
+      } else if constexpr (D == 3 && (K == 2 || K == 3) && sizeof(R) == sizeof(float)) {
+        if (c->tabmf32 && !vext) {
+          // contractions on FP32 MFMA: coarse-block cells, then fine-block cells
+          const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
+          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true, float>), dim3(nb), dim3(kBlock), 0, s, c->tabmf32,
+                             c->tablw, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
+        } else {
+          hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s,
+                             c->tab, tabr, w, out, dt, vext, make_amr_grid(c), mode, mx, c->flag);
+        }
       } else if constexpr (D == 3 && (K == 2 || K == 3) && sizeof(R) == sizeof(double)) {
         if (c->tabmf && !vext) {
           // contractions on FP64 MFMA: coarse-block cells, then fine-block cells
           const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
-          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, w, out, dt,
-                             make_grid(c), make_amr_grid(c), mode, mx, c->flag);
+          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, nullptr, w, out,
+                             dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
         } else if constexpr (K == 3) {
           // four lanes per cell (the one-thread kernel would spill)
           hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock),
@@ -3480,7 +3585,14 @@ struct StageLaunch {
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+                         s, c->tabmf, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+    } else if (D == 3 && K == 3 && sizeof(R) == sizeof(float) && !c->gravity && !vext && c->tabmf32) {
+      // contractions on FP32 MFMA, 16 cells per wave, the mean's lift in FP64
+      // (at k = 2 the one-thread-per-cell FP32 kernel is faster: 1.77 ms
+      // against 2.4 ms per 128^3 launch)
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false, float>), dim3((unsigned)((c->ncell + 63) / 64)),
+                         dim3(kBlock), 0, s, c->tabmf32, c->tablw, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx,
+                         c->flag);
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
@@ -3493,7 +3605,7 @@ struct StageLaunch {
     } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+                         s, c->tabmf, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else {
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
@@ -3734,6 +3846,33 @@ std::vector<double> mf3_tables(const dg_ctx *c) {
   return t;
 }
 
+// The FP32 kernel's tables from the FP64 ones: operand row 4 g + r holds the
+// FP64 operand's row 4 r + g (the FP32 MFMA's result rows are transposed
+// within groups of four), and the FP64 weights of mode 0 of every lift
+// operand, per K step r and lane group g, for the mean's FP64 lift.
+template <int K>
+void mf3_tables_f32(const std::vector<double> &T, bool amr, std::vector<float> &t32, std::vector<double> &lw) {
+  using M = dg::Mf3<K, float>;
+  t32.assign(T.size(), 0.0f);
+  for (size_t o = 0; o < T.size() / 64; ++o)
+    for (int l = 0; l < 64; ++l) {
+      const int k = l / 16, i = l % 16, ip = 4 * (i % 4) + i / 4;
+      t32[o * 64 + l] = (float)T[o * 64 + 16 * k + ip];
+    }
+  lw.assign(M::LWTOT, 0.0);
+  for (int fs = 0; fs < 6; ++fs)
+    for (int ft = 0; ft < M::NFT; ++ft)
+      for (int r = 0; r < 4; ++r)
+        for (int g = 0; g < 4; ++g) {
+          // row j = 0 of the lift operand of K step r sits in lane 16 g
+          lw[((fs * M::NFT + ft) * 4 + r) * 4 + g] = T[(size_t)(M::LF + ((fs * M::NFT + ft) * 4 + r) * M::NMT) * 64 + 16 * g];
+          if (!amr) continue;
+          for (int sb = 0; sb < 4; ++sb)
+            lw[M::LWH + (((fs * 4 + sb) * M::NFT + ft) * 4 + r) * 4 + g] =
+                T[(size_t)(M::HWA + (((fs * 4 + sb) * M::NFT + ft) * 4 + r) * M::NMT) * 64 + 16 * g];
+        }
+}
+
 // Folds the maximum signal rate of w's cell means into *rm (atomic max).
 int rate_fold(dg_ctx *c, const double *w, unsigned long long *rm, hipStream_t s) {
   if (c->amr) {
@@ -3965,6 +4104,10 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
       c->ncf *= c->nf[a];
     }
     c->ncell = c->ncc + c->ncf;  // cells of both blocks (hole cells included)
+    if (c->ncf > (1L << 31)) {  // kernels index a block's cells in 32 bits
+      delete c;
+      return DG_EUNSUPPORTED;
+    }
   }
   try {
     c->host_tab = dg::build_tables(c->sh, &c->gll_w1);
@@ -4031,11 +4174,27 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   const std::vector<double> zeros(DG_RATE_STATE, 0.0);
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
-  if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && cfg->precision == DG_FP64 && cfg->path3d != DG_PATH3D_VALU) {
+  if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && cfg->path3d != DG_PATH3D_VALU &&
+      (cfg->precision == DG_FP64 || (cfg->precision == DG_FP32 && (cfg->k == 3 || amr)))) {
     const std::vector<double> T = cfg->k == 2 ? mf3_tables<2>(c) : mf3_tables<3>(c);
-    if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
-    if ((e = hipMemcpy(c->tabmf, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
-      return fail(e);
+    if (cfg->precision == DG_FP64) {
+      if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
+      if ((e = hipMemcpy(c->tabmf, T.data(), T.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    } else {
+      std::vector<float> t32;
+      std::vector<double> lw;
+      if (cfg->k == 2)
+        mf3_tables_f32<2>(T, c->amr, t32, lw);
+      else
+        mf3_tables_f32<3>(T, c->amr, t32, lw);
+      if ((e = hipMalloc((void **)&c->tabmf32, t32.size() * sizeof(float))) != hipSuccess) return fail(e);
+      if ((e = hipMemcpy(c->tabmf32, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+      if ((e = hipMalloc((void **)&c->tablw, lw.size() * sizeof(double))) != hipSuccess) return fail(e);
+      if ((e = hipMemcpy(c->tablw, lw.data(), lw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    }
   }
   if (cfg->k <= 3) {
     // refinement matrices of dg_amr_flags / dg_amr_regrid (eq. ref_pa_integral)
@@ -4060,6 +4219,8 @@ void dg_destroy(dg_ctx *c) {
   if (c->gmax) (void)hipFree(c->gmax);
   if (c->prmat) (void)hipFree(c->prmat);
   if (c->tabmf) (void)hipFree(c->tabmf);
+  if (c->tabmf32) (void)hipFree(c->tabmf32);
+  if (c->tablw) (void)hipFree(c->tablw);
   delete c;
 }
 

@@ -139,3 +139,43 @@ def test_bf16_volume_term_against_oracle(case):
     print("bf16 rhs error / (|V|+|S|):", err, flush=True)
     assert np.all(err <= 2e-2), err
     assert np.all(err >= 1e-9)  # it is really a reduced-precision contraction
+
+
+FP32_3D = [
+    ("kh3d_k2_8x7x6", dict(k=2, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), refine_lo=(0, 0, 0), refine_hi=(0, 0, 0))),
+    ("kh3d_k3_8x7x6", dict(k=3, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), refine_lo=(0, 0, 0), refine_hi=(0, 0, 0))),
+    ("box_k2_8x7x6", dict(k=2, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), refine_lo=(2, 2, 1), refine_hi=(6, 5, 4))),
+    ("box_k3_8x8x8", dict(k=3, n=(8, 8, 8), length=(1.0, 1.0, 1.0), refine_lo=(2, 2, 2), refine_hi=(6, 6, 6))),
+]
+
+
+@pytest.mark.parametrize("path3d", [0, 1], ids=["mfma", "valu"])
+@pytest.mark.parametrize("case,spec", FP32_3D, ids=[c[0] for c in FP32_3D])
+def test_fp32_rhs_3d_against_oracle(case, spec, path3d):
+    # both 3D FP32 kernels (contractions on FP32 MFMA, and the vector-ALU
+    # kernels) on uniform grids and refined boxes (hanging faces), shear layer
+    # with noise: relative to |V| + |S| within 1e-6 per variable, and per
+    # element within 1e-5 of the summand scale A (FP32 rounding, 6e-8, of sums
+    # of up to a few hundred terms); the means conservative to FP64 round-off
+    import paper_1506_06140_amd as dg
+    from parity import modes, rhs_errors_modes
+    wl = workloads.workload("blast_amr", limiter=0, positivity=0, ic="kh3d", noise=1e-2, seed=6140, path3d=path3d,
+                            **spec)
+    amr = spec["refine_hi"] != (0, 0, 0)
+    o = oracle.AmrOracle(wl) if amr else oracle.Oracle(wl)
+    w = o.initial_state()
+    V, S, A = o.terms_cells(w, with_abs=True)
+    L = _host(dg.Solver(wl, "fp32").rhs(_dev(w)))
+    err, elem, rell, cond = rhs_errors_modes(modes(o, L), modes(o, V), modes(o, S), modes(o, A))
+    print(case, path3d, "fp32 rhs error / (|V|+|S|):", err, "per-element / A:", elem, flush=True)
+    assert np.all(err <= 1e-6), err
+    assert np.all(elem <= 1e-5), elem
+    assert np.all(err >= 1e-12)  # FP32 contractions really ran
+    Lm = modes(o, L)
+    if amr:
+        Lc, Lf = o.blocks(L)
+        tot = Lc[:, 0, ~o.hole].sum(axis=1) * o.dx ** 3 + Lf[:, 0, :].sum(axis=1) * o.dxf ** 3
+        scale = np.abs(Lc[:, 0, ~o.hole]).sum(axis=1) * o.dx ** 3 + np.abs(Lf[:, 0, :]).sum(axis=1) * o.dxf ** 3
+    else:
+        tot, scale = Lm[:, 0].sum(axis=1), np.abs(Lm[:, 0]).sum(axis=1)
+    assert np.all(np.abs(tot) <= 1e-13 * scale), tot / scale
