@@ -85,7 +85,9 @@ typedef struct {
   int bc[3];          /* DG_BC_* per axis                                     */
   int flux;           /* DG_HLLC_BATTEN (Roe-averaged speed bounds) or DAVIS  */
   int precision;      /* DG_FP64, DG_FP32 (contractions and fluxes in FP32),
-                         DG_BF16_VOL (volume contraction BF16 on MFMA)         */
+                         DG_BF16_VOL (volume contraction BF16 on MFMA, faces
+                         FP32; on 3D grids at k = 2, 3 fused into the FP32
+                         MFMA stage kernel, else a separate volume pass)     */
   int slope_limiter;  /* DG_LIM_NONE, DG_LIM_MINMOD (component-wise, TVB,
                          Sec. 3.1) or DG_LIM_CHAR (characteristic, TVB,
                          Sec. 3.2 with the App. E eigenvectors)               */
@@ -161,10 +163,13 @@ int dg_rhs(dg_ctx *ctx, const double *w, double *L, void *stream);
  * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
  * same kernels and result as dg_rhs on a DG_BF16_VOL context, with the FP32
  * volume term that dg_rhs keeps in the context's scratch held instead in
- * the library's static device scratch of DG_STATIC_SCRATCH_FLOATS floats.
- * The call allocates nothing and frees nothing.  It needs nvar * N * cells
- * (both blocks with a refined box) <= DG_STATIC_SCRATCH_FLOATS, else it
- * returns DG_ESCRATCH; DG_EINVAL for a context of another precision.  Every
+ * the library's static device scratch of DG_STATIC_SCRATCH_FLOATS floats
+ * (3D grids at k = 2, 3 with path3d = DG_PATH3D_AUTO keep the volume term in
+ * registers of the fused stage kernel and use no scratch at all).
+ * The call allocates nothing and frees nothing.  Where it stages the volume
+ * term it needs nvar * N * cells (both blocks with a refined box) <=
+ * DG_STATIC_SCRATCH_FLOATS, else it returns DG_ESCRATCH; DG_EINVAL for a
+ * context of another precision.  Every
  * call on one GPU shares that GPU's scratch, so calls that overlap in time
  * on one GPU (different streams, or different host threads) race and must
  * be ordered by the caller; each call writes every scratch entry it reads

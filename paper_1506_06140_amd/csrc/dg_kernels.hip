@@ -1132,6 +1132,8 @@ __device__ inline bool amr_coarse_nb(const AmrGrid &g, const int *i, int a, int 
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // D += A B on the 16x16x4 MFMA of the contraction type.  The FP32 form's
 // result rows lie transposed within each group of four: register r of lane
@@ -1177,6 +1179,11 @@ struct Mf3 {
   // FP32 path: the FP64 lift weights of mode 0, per lane group g, [6][NFT][4][4]
   // (regular faces), then [6][4][NFT][4][4] (refined box: sub-faces)
   static constexpr int LW = 6 * NFT * 16, LWH = LW, LWTOT = LW + 24 * NFT * 16;
+  // BF16 path: the volume's A operands as BF16 pairs, blocks of 64 lanes x 8
+  // values, hi then lo: evaluation [NQT][2], projection [3][NQC][NMT][2]
+  // (NQC chunks of two node tiles, the 32 K values of v_mfma_f32_16x16x32_bf16)
+  static constexpr int NQC = (NQT + 1) / 2;
+  static constexpr int BEV = 0, BPV = BEV + NQT * 2, BOPS = BPV + 3 * NQC * NMT * 2;
   static constexpr int VOPS = EF, FOPS = OPS - EF;
   static constexpr int LDSOPS = !SPLIT ? OPS : (VOPS > FOPS ? VOPS : FOPS);
   static constexpr int FBASE = SPLIT ? EF : 0;  // LDS block of face-phase operand o: o - FBASE
@@ -1184,9 +1191,11 @@ struct Mf3 {
 
 // Two waves per SIMD at k = 2 (<= 256 registers per lane): at one wave the
 // matrix pipe idled while the wave waited on its own MFMA results and loads
-// (5.3 ms against 3.2 ms per 128^3 launch).  One wave where two would spill:
-// k = 3, and the refined box at k = 2 in FP64 (FP32 at k = 2: three waves
-// would spill 53 registers).
+// (5.3 ms against 3.2 ms per 128^3 launch).  FP64 at k = 3 and on the
+// refined box at k = 2 runs one wave (two would spill).  FP32 and BF16 run
+// two waves at k = 3 as well, where the uniform-grid kernels spill 12 to 19
+// registers but still gain (96^3, k = 3: 3.09 -> 2.35 ms FP32, 3.26 -> 2.26
+// ms BF16); three FP32 waves at k = 2 were slower (2.56 against 2.39 ms).
 //
 // AMR: the refined box of Sec. 4 (static 2:1 box; state = coarse block, then
 // fine block).  Blocks of the grid cover the coarse block's cells, then the
@@ -1207,17 +1216,37 @@ struct Mf3 {
 // on v_mfma_f32_16x16x4f32; the lift of mode 0 (the cell mean) is summed in
 // FP64 from the FP32 face fluxes (tlw: its FP64 weights per lane group), and
 // the stage update is FP64, as in k_rhs_stage.
-template <int K, int FX, bool AMR, class R = double>
-__global__ __launch_bounds__(256, (K == 2 && (!AMR || sizeof(R) == 4)) ? 2 : 1) void k_rhs_mfma3d(
-    const R *__restrict__ tmf, const double *__restrict__ tlw, const double *__restrict__ w, double *__restrict__ out,
-    const double *__restrict__ dtp, Grid g, AmrGrid ag, int mode, Mix mx, int *__restrict__ flag) {
+// VB (the BF16 path, R = float): the volume integral's two contractions on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation, every operand a BF16 pair
+// x = hi + lo and every product the three MFMAs lo hi + hi lo + hi hi (as in
+// k_volume_bf16), straight into the FP32 accumulators that the faces then
+// continue: evaluation D[p][c] = sum_m E[p][m] w[m][c] over the modes padded
+// to 32 (lane (g, c) holds modes 8 g + e of cell c as B), projection
+// D[j][c] = sum_q T[j][q] F[q][c] over two node tiles at a time (K index
+// 8 g + e = node 16 (2 tp + e / 4) + 4 (e % 4) + g, which is register e % 4
+// of tile 2 tp + e / 4 in lane (g, c): the FP32 evaluation result is the B
+// operand without moving data between lanes).
+template <int K, int FX, bool AMR, class R = double, bool VB = false>
+__global__ __launch_bounds__(256, (sizeof(R) == 4 || (K == 2 && !AMR)) ? 2 : 1) void k_rhs_mfma3d(
+    const R *__restrict__ tmf, const double *__restrict__ tlw, const bf16x8 *__restrict__ tvb,
+    const double *__restrict__ w, double *__restrict__ out, const double *__restrict__ dtp, Grid g, AmrGrid ag,
+    int mode, Mix mx, int *__restrict__ flag) {
   using M = Mf3<K, R>;
   using V4 = typename Mv4<R>::T;
   constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q, NW = NV * N;
   constexpr bool LO64 = sizeof(R) == sizeof(float);  // mode 0 lifted in FP64
-  __shared__ R tl[M::LDSOPS * 64];
+  static_assert(!VB || (LO64 && N <= 32), "BF16 volume: FP32 kernel, at most 32 modes");
+  // VB: LDS holds the face phase's FP32 operands and the BF16 volume operands
+  constexpr int FB = VB ? M::EF : M::FBASE;  // LDS block of face-phase operand o: o - FB
+  __shared__ R tl[(VB ? M::FOPS : M::LDSOPS) * 64];
   __shared__ double lws[LO64 ? M::LW : 1];
-  for (int i = threadIdx.x; i < (M::SPLIT ? M::VOPS : M::OPS) * 64; i += blockDim.x) tl[i] = tmf[i];
+  __shared__ bf16x8 tvl[VB ? M::BOPS * 64 : 1];
+  if constexpr (VB) {
+    for (int i = threadIdx.x; i < M::FOPS * 64; i += blockDim.x) tl[i] = tmf[M::EF * 64 + i];
+    for (int i = threadIdx.x; i < M::BOPS * 64; i += blockDim.x) tvl[i] = tvb[i];
+  } else {
+    for (int i = threadIdx.x; i < (M::SPLIT ? M::VOPS : M::OPS) * 64; i += blockDim.x) tl[i] = tmf[i];
+  }
   if constexpr (LO64)
     for (int i = threadIdx.x; i < M::LW; i += blockDim.x) lws[i] = tlw[i];
   __syncthreads();
@@ -1259,7 +1288,7 @@ __global__ __launch_bounds__(256, (K == 2 && (!AMR || sizeof(R) == 4)) ? 2 : 1) 
   if constexpr (AMR) hole = !fine && amr_in_hole<3>(ag, ci);
   const R gm1 = (R)(gam - 1.0);
   auto op = [&](int o) { return tl[o * 64 + lane]; };               // volume-phase operand
-  auto opf = [&](int o) { return tl[(o - M::FBASE) * 64 + lane]; };  // face-phase operand
+  auto opf = [&](int o) { return tl[(o - FB) * 64 + lane]; };      // face-phase operand
   auto opg = [&](int o) { return tmf[(long)o * 64 + lane]; };        // hanging-face operand (global)
 
   // the cell's weights as B operands: wb[v][ks] = w_v[mode 4 ks + gq].  Loads
@@ -1298,6 +1327,75 @@ __global__ __launch_bounds__(256, (K == 2 && (!AMR || sizeof(R) == 4)) ? 2 : 1) 
   }
 
   // volume integral (eq. dg_term2)
+  if constexpr (VB) {
+    // B operands of the evaluation: modes 8 gq + e of this column's cell
+    bf16x8 wh[NV], wl[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int m = 8 * gq + e, mc = m < N ? m : N - 1;
+        const double xd = wbk[(long)(v * N + mc) * nc + cs];
+        const float x = (m < N && valid) ? (float)xd : 0.0f;
+        const __bf16 hi = (__bf16)x;
+        wh[v][e] = hi;
+        wl[v][e] = (__bf16)(x - (float)hi);
+      }
+#pragma unroll
+    for (int tp = 0; tp < M::NQC; ++tp) {
+      f4 U[NV][2];
+#pragma unroll
+      for (int dt = 0; dt < 2; ++dt) {
+        const int t = 2 * tp + dt;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          f4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+          if (t < M::NQT) {
+            const bf16x8 eh = tvl[(M::BEV + 2 * t) * 64 + lane], el = tvl[(M::BEV + 2 * t + 1) * 64 + lane];
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(el, wh[v], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh, wl[v], z, 0, 0, 0);
+            z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(eh, wh[v], z, 0, 0, 0);
+          }
+          U[v][dt] = z;
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        bf16x8 fh[NV], fl[NV];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int dt = e >> 2, i = e & 3, p0 = 16 * (2 * tp + dt) + 4 * i;
+          if (p0 >= Q) {  // a whole register of padding nodes
+#pragma unroll
+            for (int v = 0; v < NV; ++v) fh[v][e] = fl[v][e] = (__bf16)0.0f;
+            continue;
+          }
+          const bool ok = p0 + gq < Q;
+          R Ur[NV], F[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) Ur[v] = ok ? U[v][dt][i] : (v == 0 ? R(1) : (v == NV - 1 ? R(1) : R(0)));
+          euler_flux<3, R>(Ur, a, gm1, F);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const float f = ok ? F[v] : 0.0f;
+            const __bf16 hi = (__bf16)f;
+            fh[v][e] = hi;
+            fl[v][e] = (__bf16)(f - (float)hi);
+          }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int mt = 0; mt < NMT; ++mt) {
+            const int o = M::BPV + ((a * M::NQC + tp) * NMT + mt) * 2;
+            const bf16x8 th = tvl[o * 64 + lane], tlo = tvl[(o + 1) * 64 + lane];
+            acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(tlo, fh[v], acc[v][mt], 0, 0, 0);
+            acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, fl[v], acc[v][mt], 0, 0, 0);
+            acc[v][mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(th, fh[v], acc[v][mt], 0, 0, 0);
+          }
+      }
+    }
+  } else
 #pragma unroll
   for (int t = 0; t < M::NQT; ++t) {
     V4 U[NV];
@@ -1330,7 +1428,7 @@ __global__ __launch_bounds__(256, (K == 2 && (!AMR || sizeof(R) == 4)) ? 2 : 1) 
     }
   }
 
-  if constexpr (M::SPLIT) {
+  if constexpr (M::SPLIT && !VB) {
     __syncthreads();  // every wave is done with the volume-phase operands
     for (int i = threadIdx.x; i < M::FOPS * 64; i += blockDim.x) tl[i] = tmf[M::EF * 64 + i];
     __syncthreads();
@@ -2231,9 +2329,6 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
 // of a large flux (the pressure in a momentum flux) no longer swamps a small
 // field's volume term.
 // ---------------------------------------------------------------------------
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
 template <int D, int K>
 struct Mfma {
   static constexpr int NP = 32;                                  // padded modes
@@ -3526,7 +3621,7 @@ struct StageLaunch {
           // contractions on FP32 MFMA: coarse-block cells, then fine-block cells
           const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
           hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true, float>), dim3(nb), dim3(kBlock), 0, s, c->tabmf32,
-                             c->tablw, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
+                             c->tablw, nullptr, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
         } else {
           hipLaunchKernelGGL((dg::k_rhs_amr<D, K, R, FX>), dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s,
                              c->tab, tabr, w, out, dt, vext, make_amr_grid(c), mode, mx, c->flag);
@@ -3535,7 +3630,7 @@ struct StageLaunch {
         if (c->tabmf && !vext) {
           // contractions on FP64 MFMA: coarse-block cells, then fine-block cells
           const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
-          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, nullptr, w, out,
+          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w, out,
                              dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
         } else if constexpr (K == 3) {
           // four lanes per cell (the one-thread kernel would spill)
@@ -3585,14 +3680,14 @@ struct StageLaunch {
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+                         s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(float) && !c->gravity && !vext && c->tabmf32) {
       // contractions on FP32 MFMA, 16 cells per wave, the mean's lift in FP64
       // (at k = 2 the one-thread-per-cell FP32 kernel is faster: 1.77 ms
       // against 2.4 ms per 128^3 launch)
       hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false, float>), dim3((unsigned)((c->ncell + 63) / 64)),
-                         dim3(kBlock), 0, s, c->tabmf32, c->tablw, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx,
-                         c->flag);
+                         dim3(kBlock), 0, s, c->tabmf32, c->tablw, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{},
+                         mode, mx, c->flag);
     } else if constexpr (D == 3 && K == 3 && sizeof(R) == 8) {
       // four lanes per cell: one thread per cell would hold two 100-double
       // register sets (the weights and the accumulators) and spill 632 B per
@@ -3605,7 +3700,7 @@ struct StageLaunch {
     } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+                         s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else {
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
@@ -3639,8 +3734,33 @@ struct StageLaunch {
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
+  // BF16 path on 3D grids at k = 2, 3: the volume term fused into the FP32
+  // MFMA stage kernel (no scratch)
+  template <int K, int FX>
+  int launch_vb() {
+    const dg::bf16x8 *tv = static_cast<const dg::bf16x8 *>(c->tabvb);
+    if (c->amr) {
+      const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true, float, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf32,
+                         c->tablw, tv, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
+    } else {
+      hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, false, float, true>), dim3((unsigned)((c->ncell + 63) / 64)),
+                         dim3(kBlock), 0, s, c->tabmf32, c->tablw, tv, w, out, dt, make_grid(c), dg::AmrGrid{}, mode,
+                         mx, c->flag);
+    }
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
   template <int D, int K>
   int run() {
+    if (c->cfg.precision == DG_BF16_VOL && c->tabvb) {
+      if constexpr (D == 3 && (K == 2 || K == 3)) {
+        if (ro.op != dg::RATE_NONE) return DG_EINVAL;
+        return c->cfg.flux == DG_HLLC_DAVIS ? launch_vb<K, DG_HLLC_DAVIS>() : launch_vb<K, DG_HLLC_BATTEN>();
+      } else {
+        return DG_EUNSUPPORTED;
+      }
+    }
     if (c->cfg.precision == DG_BF16_VOL) {
       if constexpr (K > 3) {
         return DG_EUNSUPPORTED;
@@ -3871,6 +3991,41 @@ void mf3_tables_f32(const std::vector<double> &T, bool amr, std::vector<float> &
             lw[M::LWH + (((fs * 4 + sb) * M::NFT + ft) * 4 + r) * 4 + g] =
                 T[(size_t)(M::HWA + (((fs * 4 + sb) * M::NFT + ft) * 4 + r) * M::NMT) * 64 + 16 * g];
         }
+}
+
+// BF16 volume operands of the fused BF16 kernel (k_rhs_mfma3d, VB): per lane
+// (g = lane / 16, row = lane % 16) eight BF16 values of A[row][8 g + e] as
+// pairs hi, lo; rows in the FP32 result order (row 4 g' + i stands for node
+// or mode 4 i + g' of its tile).  Evaluation: nodes x modes (table B);
+// projection: modes j >= 1 x nodes 16 (2 tp + e / 4) + 4 (e % 4) + g (table DW).
+template <int K>
+std::vector<uint16_t> mf3_tables_bf16(const dg_ctx *c) {
+  using C = Cfg<3, K>;
+  using M = dg::Mf3<K, float>;
+  std::vector<uint16_t> t((size_t)M::BOPS * 64 * 8, 0);
+  const std::vector<double> &h = c->host_tab;
+  auto put = [&](int o, int lane, int e, double x) {
+    const uint16_t hi = to_bf16((float)x);
+    t[((size_t)o * 64 + lane) * 8 + e] = hi;
+    t[((size_t)(o + 1) * 64 + lane) * 8 + e] = to_bf16((float)(x - (double)from_bf16(hi)));
+  };
+  for (int lane = 0; lane < 64; ++lane) {
+    const int row = lane % 16, g = lane / 16, pr = 4 * (row % 4) + row / 4;
+    for (int tt = 0; tt < M::NQT; ++tt)
+      for (int e = 0; e < 8; ++e) {
+        const int q = 16 * tt + pr, m = 8 * g + e;
+        put(M::BEV + 2 * tt, lane, e, (q < C::Q && m < C::N) ? h[C::B + q * C::N + m] : 0.0);
+      }
+    for (int a = 0; a < 3; ++a)
+      for (int tp = 0; tp < M::NQC; ++tp)
+        for (int mt = 0; mt < M::NMT; ++mt)
+          for (int e = 0; e < 8; ++e) {
+            const int q = 16 * (2 * tp + e / 4) + 4 * (e % 4) + g, j = 16 * mt + pr;
+            put(M::BPV + ((a * M::NQC + tp) * M::NMT + mt) * 2, lane, e,
+                (q < C::Q && j < C::N && j >= 1) ? h[C::DW + (a * C::Q + q) * C::N + j] : 0.0);
+          }
+  }
+  return t;
 }
 
 // Folds the maximum signal rate of w's cell means into *rm (atomic max).
@@ -4158,7 +4313,10 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMemcpy(c->tab32, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
   int zero = 0;
   if ((e = hipMemcpy(c->flag, &zero, sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) return fail(e);
-  if (cfg->precision == DG_BF16_VOL) {
+  // the fused BF16 stage kernel (3D, k = 2, 3) needs no separate volume pass
+  const bool vb_fused = cfg->precision == DG_BF16_VOL && cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) &&
+                        cfg->path3d != DG_PATH3D_VALU;
+  if (cfg->precision == DG_BF16_VOL && !vb_fused) {
     std::vector<uint16_t> tb;
     int st = bf16_tables(c, tb);
     if (st != DG_OK) {
@@ -4175,7 +4333,7 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMemcpy(c->partial, zeros.data(), DG_RATE_STATE * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
     return fail(e);
   if (cfg->dim == 3 && (cfg->k == 2 || cfg->k == 3) && cfg->path3d != DG_PATH3D_VALU &&
-      (cfg->precision == DG_FP64 || (cfg->precision == DG_FP32 && (cfg->k == 3 || amr)))) {
+      (cfg->precision == DG_FP64 || (cfg->precision == DG_FP32 && (cfg->k == 3 || amr)) || vb_fused)) {
     const std::vector<double> T = cfg->k == 2 ? mf3_tables<2>(c) : mf3_tables<3>(c);
     if (cfg->precision == DG_FP64) {
       if ((e = hipMalloc((void **)&c->tabmf, T.size() * sizeof(double))) != hipSuccess) return fail(e);
@@ -4193,6 +4351,12 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
         return fail(e);
       if ((e = hipMalloc((void **)&c->tablw, lw.size() * sizeof(double))) != hipSuccess) return fail(e);
       if ((e = hipMemcpy(c->tablw, lw.data(), lw.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    }
+    if (vb_fused) {
+      const std::vector<uint16_t> tv = cfg->k == 2 ? mf3_tables_bf16<2>(c) : mf3_tables_bf16<3>(c);
+      if ((e = hipMalloc(&c->tabvb, tv.size() * sizeof(uint16_t))) != hipSuccess) return fail(e);
+      if ((e = hipMemcpy(c->tabvb, tv.data(), tv.size() * sizeof(uint16_t), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
     }
   }
@@ -4221,6 +4385,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->tabmf) (void)hipFree(c->tabmf);
   if (c->tabmf32) (void)hipFree(c->tabmf32);
   if (c->tablw) (void)hipFree(c->tablw);
+  if (c->tabvb) (void)hipFree(c->tabvb);
   delete c;
 }
 
@@ -4271,6 +4436,8 @@ int dg_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
 int dg_rhs_noalloc(dg_ctx *c, const double *w, double *L, void *stream) {
   if (!c || !w || !L || w == L) return DG_EINVAL;
   if (c->cfg.precision != DG_BF16_VOL) return DG_EINVAL;
+  // the fused 3D kernel keeps its volume term in registers: nothing to stage
+  if (c->tabvb) return dispatch(c, StageLaunch{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
   if ((long long)c->sh.nv * c->sh.N * c->ncell > (long long)DG_STATIC_SCRATCH_FLOATS) return DG_ESCRATCH;
   if (c->device < 0 || c->device >= kMaxDevices) return DG_EUNSUPPORTED;
   float *vs;
