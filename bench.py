@@ -65,17 +65,17 @@ _HELPERS = [
 ]
 KERNELS = {
     "stage3d": dict(name="k_rhs_mfma3d<2>", traffic="k_rhs_mfma3d_kh3d128_k2_traffic.txt",
-                    regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on FP64 MFMA.",
+                    regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on MFMA (FP64; FP32 and",
                                          "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
     "stage3d_amr": dict(name="k_rhs_mfma3d<3,AMR>", traffic="k_rhs_mfma3d_blast64box_k3_traffic.txt",
-                        regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on FP64 MFMA.",
+                        regions=_HELPERS + [("// 3D right-hand side + stage with the contractions on MFMA (FP64; FP32 and",
                                              "// Discrete adjoint of the right-hand side and of the SSP-RK3 stages.")]),
     "stage3d_valu": dict(name="k_rhs_stage<3,2,double>", traffic="k_rhs_stage_kh3d128_k2_traffic.txt",
                          regions=_HELPERS + [("// Right-hand side and fused stage.",
                                               "// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.")]),
     "tile2d": dict(name="k_rhs_tile2d<2,double> (8x8 tiles)", traffic="k_rhs_tile2d_vortex256_k2_traffic.txt",
                    regions=_HELPERS + [("// 2D right-hand side + SSP-RK3 stage on LDS tiles, four lanes per cell.",
-                                        "// 3D right-hand side + stage with the contractions on FP64 MFMA.")]),
+                                        "// 3D right-hand side + stage with the contractions on MFMA (FP64; FP32 and")]),
 }
 
 
@@ -297,30 +297,42 @@ def variants():
                                      "alu_peak_tflops": peak}
             del s
             torch.cuda.empty_cache()
-    # the refined-box blast's stage kernel (MFMA) against the FP64 peak, with
-    # the four-lanes-per-cell VALU kernel and the limiter beside it
-    wl = workloads.workload("blast_amr", eps=1e-4)
-    kern = {}
-    for label, path in (("mfma", dg.DG_PATH3D_AUTO), ("valu", dg.DG_PATH3D_VALU)):
-        s = dg.Solver(dict(wl, path3d=path))
-        w = build_state(s, wl)
-        s.limit(w)
-        bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
-        kern[label] = kernel_ms(s, w, bufs, 10)
-        if label == "mfma":
-            kern["limiter"] = kernel_ms(s, w, bufs, 10, limiter=True)
-        cells = s.ncoarse - s.nhole + s.nfine
-        del s, w, bufs
-        torch.cuda.empty_cache()
-    b3, f3 = alg_work(3, 3)
-    out["blast_amr_kernels"] = {
-        "workload": "3D blast, 64^3 base grid + refined 32^3 box (64^3 fine cells), k=3, FP64",
-        "cells": cells, "alg_flops_per_launch": f3 * cells,
-        "mfma_kernel": "k_rhs_mfma3d<3,AMR>", "mfma_ms": kern["mfma"],
-        "mfma_frac": f3 * cells / (kern["mfma"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "valu_kernel": "k_rhs_amr_quad<3>", "valu_ms": kern["valu"],
-        "valu_frac": f3 * cells / (kern["valu"] * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
-        "limiter_ms": kern["limiter"]}
+    # the stage kernels of the two 3D workloads per precision and path (one
+    # fused RHS + stage launch, HIP events), with the limiter pass
+    kinds = {
+        "kh3d": ("3D shear layer 128^3, k=2", {},
+                 {"fp64_mfma": "k_rhs_mfma3d<2>", "fp64_valu": "k_rhs_stage<3,2,double>",
+                  "fp32_valu": "k_rhs_stage<3,2,float>", "fp32_mfma": None,
+                  "bf16_mfma": "k_rhs_mfma3d<2,float,BF16 volume>"}),
+        "blast_amr": ("3D blast, 64^3 base grid + refined 32^3 box (64^3 fine cells), k=3", {"eps": 1e-4},
+                      {"fp64_mfma": "k_rhs_mfma3d<3,AMR>", "fp64_valu": "k_rhs_amr_quad<3>",
+                       "fp32_valu": "k_rhs_amr<3,3,float>", "fp32_mfma": "k_rhs_mfma3d<3,AMR,float>",
+                       "bf16_mfma": "k_rhs_mfma3d<3,AMR,float,BF16 volume>"}),
+    }
+    for name, (desc, over, kernels) in kinds.items():
+        wl = workloads.workload(name, **over)
+        rec = {"workload": desc, "kernels": {}}
+        for label, kname in kernels.items():
+            if kname is None:
+                continue  # FP32 on a uniform k = 2 grid has no MFMA form (the VALU kernel is faster)
+            prec, path = label.split("_")
+            s = dg.Solver(dict(wl, path3d=dg.DG_PATH3D_VALU if path == "valu" else dg.DG_PATH3D_AUTO), prec)
+            w = build_state(s, wl)
+            s.limit(w)
+            bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
+            kms = kernel_ms(s, w, bufs, 10)
+            cells = (s.ncoarse - s.nhole + s.nfine) if s.amr else s.ncell
+            b3, f3 = alg_work(3, wl["k"])
+            peak = FP64_PEAK_TFLOPS if prec == "fp64" else FP32_PEAK_TFLOPS
+            rec["kernels"][label] = {"kernel": kname, "ms": kms, "alu_frac": f3 * cells / (kms * 1e-3) / 1e12 / peak,
+                                     "alu_peak_tflops": peak}
+            if label == "fp64_mfma":
+                rec["limiter_ms"] = kernel_ms(s, w, bufs, 10, limiter=True)
+                rec["cells"] = cells
+                rec["alg_flops_per_launch"] = f3 * cells
+            del s, w, bufs
+            torch.cuda.empty_cache()
+        out[f"{name}_stage_kernels"] = rec
     # adaptive KH (2D, 64^2 base, DG-4 with RK_4, characteristic limiter and
     # positivity): every 10 steps the flags (w_t = 0.01, alpha = 1.1), the box
     # around them with one buffer layer and, if it changed, the regrid
@@ -426,7 +438,7 @@ def kernel_ms(s, w, bufs, reps, limiter=False):
     return e0.elapsed_time(e1) / reps
 
 
-def vortex2d_line(steps=400, warmup=20, with_cpu=True):
+def vortex2d_line(steps=400, warmup=20, with_cpu=True, reps=300):
     """The 2D vortex (256^2, k = 2, FP64, no limiter) with its stage kernel's
     HBM roofline: the state (12.6 MB) stays in the 256 MB Infinity Cache."""
     import paper_1506_06140_amd as dg
@@ -434,7 +446,7 @@ def vortex2d_line(steps=400, warmup=20, with_cpu=True):
     s = dg.Solver(wl)
     ms, w = time_steps(s, wl, steps, warmup)
     bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
-    k = kernel_ms(s, w, bufs, 300)
+    k = kernel_ms(s, w, bufs, reps)
     b, f = alg_work(2, 2)
     alg_bytes = b * s.ncell
     achieved = alg_bytes / (k * 1e-3) / 1e9
@@ -459,9 +471,9 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
     ap.add_argument("--variants", type=int, default=1, help="also time FP32, the 3D workload and the adjoint")
     ap.add_argument("--kernel-reps", type=int, default=30, help="launches per kernel timing")
-    ap.add_argument("--workload", default="kh3d", choices=("kh3d", "blast_amr"),
-                    help="the timed workload: the 128^3 shear layer (the headline) or the 64^3 blast with its refined "
-                         "box (k = 3)")
+    ap.add_argument("--workload", default="kh3d", choices=("kh3d", "blast_amr", "vortex"),
+                    help="the timed workload: the 128^3 shear layer (the headline), the 64^3 blast with its refined "
+                         "box (k = 3), or the 2D vortex 256^2 (its line alone, for profiling the 2D kernel)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on a single GPU; --gpus must be 1"}))
@@ -469,6 +481,11 @@ def main():
 
     import torch
     import paper_1506_06140_amd as dg
+
+    if args.workload == "vortex":
+        print(json.dumps(vortex2d_line(steps=args.steps, warmup=args.warmup, with_cpu=not args.no_cpu,
+                                       reps=args.kernel_reps)), flush=True)
+        return
 
     wl = workloads.workload(args.workload)
     kname = "stage3d" if args.workload == "kh3d" else "stage3d_amr"
