@@ -90,6 +90,7 @@ struct dg_ctx {
   float *tabmf32 = nullptr; // the same in FP32, rows in the FP32 MFMA's order (FP32 path)
   double *tablw = nullptr;  // FP64 mode-0 lift weights of the FP32 MFMA kernel
   void *tabvb = nullptr;    // BF16 volume operands of the fused BF16 MFMA kernel (3D, k = 2, 3)
+  int *plist = nullptr;     // positivity: count, then the ids of the cells that need the point loop
   // 2D tile size: -1 automatic (dg::tile2d_small: 8x8 tiles for k <= 3, and
   // for k = 4 on grids with fewer 16x8 tiles than CUs), 0 always the large
   // tiles, 1 always 8x8 (dg_config.tile2d)

@@ -1075,7 +1075,8 @@ __global__ __launch_bounds__((4 * Tile2D<K, TS>::TX * Tile2D<K, TS>::TY)) void k
 }
 
 // ---------------------------------------------------------------------------
-// 3D right-hand side + stage with the contractions on FP64 MFMA.
+// 3D right-hand side + stage with the contractions on MFMA (FP64; FP32 and
+// BF16 forms below).
 //
 // Every contraction of eqs. dg_term2 and dg_term3 is a small GEMM batched
 // over cells, run with v_mfma_f64_16x16x4f64 (D[16x16] += A[16x4] B[4x16]):
@@ -2108,6 +2109,88 @@ __device__ inline double tau_root(const double *Ub, const double *Uq, double gam
   return fmin(fmax(t, 0.0), 1.0);
 }
 
+// Smallest x over the 64 lanes of the wave (every lane active).
+__device__ inline double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) x = fmin(x, __shfl_xor(x, o));
+  return x;
+}
+
+// Appends the cells of this wave with need set to the list plist (plist[0]
+// counts, plist[1 + i] holds the i-th cell id): one atomic per wave.  Every
+// lane of the wave must call.
+__device__ inline void wave_append(bool need, int id, int *plist) {
+  const unsigned long long m = __ballot(need);
+  if (!m) return;
+  const int lane = threadIdx.x & 63, leader = __ffsll(m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(plist, __popcll(m));
+  base = __shfl(base, leader);
+  if (need) plist[1 + base + __popcll(m & ((1ull << lane) - 1))] = id;
+}
+
+// The point loop of the positivity pass (Sec. 3.4) for one cell, its
+// points shared by the 64 lanes of a wave (every lane calls with the same
+// cell): the cell's coefficient (v, l) is c[(v N + l) st]; h is its
+// hanging-side mask (0 on uniform grids), passed to pts.count(h) and
+// pts.row(h, i), the number of its points and the basis row of point i.
+// Every lane evaluates its share of the points, theta_1 and theta_2 come
+// from minima over the wave, and lane 0 stores the scaled modes l >= 1.
+// Point values, theta_1 and theta_2 are formed with the same operations in
+// the same order as a single-lane loop, so the result is the same bit for
+// bit.
+template <int D, int N, class Pts>
+__device__ inline void positivity_cell(double *c, long st, int h, const Pts &pts, double gamma, double eps) {
+  constexpr int NV = D + 2;
+  const int lane = threadIdx.x & 63;
+  const int np = pts.count(h);
+  double cf[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) cf[v][l] = c[(long)(v * N + l) * st];
+  double rmin = INFINITY;
+  for (int i = lane; i < np; i += 64) {
+    const double *ph = pts.row(h, i);
+    double r = 0.0;
+#pragma unroll
+    for (int l = 0; l < N; ++l) r = fma(cf[0][l], ph[l], r);
+    rmin = fmin(rmin, r);
+  }
+  rmin = wave_min(rmin);
+  double Ub[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Ub[v] = cf[v][0];
+  const double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
+#pragma unroll
+  for (int l = 1; l < N; ++l) cf[0][l] *= th1;
+  double th2 = 1.0;
+  for (int i = lane; i < np; i += 64) {
+    const double *ph = pts.row(h, i);
+    double Uq[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double u = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) u = fma(cf[v][l], ph[l], u);
+      Uq[v] = u;
+    }
+    double ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ke = fma(Uq[1 + b], Uq[1 + b], ke);
+    ke *= vrcp(Uq[0]);  // |m|^2 / rho with one reciprocal per point
+    const double pq = (gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
+    if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, gamma, eps));
+  }
+  th2 = wave_min(th2);
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int l = 1; l < N; ++l) c[(long)(v * N + l) * st] = cf[v][l] * th2;
+  }
+}
+
 // CHAR selects the characteristic limiter (eq. char_limiter) for the slope
 // pass, else the component-wise one (eq. comp_limiter).
 // Exponent of axis a in mode l (modes ordered by total degree, then
@@ -2189,10 +2272,13 @@ __device__ inline bool positivity_certain(const double (&wc)[D + 2][N], double g
 template <int D, int K, bool CHAR>
 __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, double *__restrict__ w, Grid g,
                                                int slope, double beta, double bound, int posit, double eps,
-                                               int *__restrict__ flag) {
+                                               int *__restrict__ flag, int *__restrict__ plist) {
   using C = Cfg<D, K>;
-  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= g.ncell) return;
+  // lanes past the grid stay in the wave (the list of troubled cells is
+  // appended per wave) on a copy of the last cell, and store nothing
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = tid < g.ncell;
+  const long cell = act ? tid : g.ncell - 1;
   const long nc = g.ncell;
   const int ix = (int)(cell % g.nx);
   const int iy = (int)((cell / g.nx) % g.ny);
@@ -2266,47 +2352,18 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
     for (int b = 0; b < D; ++b) keb = fma(Ub[1 + b], Ub[1 + b], keb);
     keb *= vrcp(Ub[0]);
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
-    if (!(Ub[0] > eps) || !(pb > eps)) {
-      atomicOr(flag, FLAG_NEGATIVE);
-    } else if (!positivity_certain<D, C::N>(wc, g.gamma, eps)) {
-      double rmin = INFINITY;
-      for (int s = 0; s < C::NS; ++s) {
-        double r = 0.0;
-#pragma unroll
-        for (int l = 0; l < C::N; ++l) r = fma(wc[0][l], tab[C::PS + s * C::N + l], r);
-        rmin = fmin(rmin, r);
-      }
-      const double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
-#pragma unroll
-      for (int l = 1; l < C::N; ++l) wc[0][l] *= th1;
-      double th2 = 1.0;
-      for (int s = 0; s < C::NS; ++s) {
-        double Uq[C::NV];
-#pragma unroll
-        for (int v = 0; v < C::NV; ++v) {
-          double u = 0.0;
-#pragma unroll
-          for (int l = 0; l < C::N; ++l) u = fma(wc[v][l], tab[C::PS + s * C::N + l], u);
-          Uq[v] = u;
-        }
-        double ke = 0.0;
-#pragma unroll
-        for (int b = 0; b < D; ++b) ke = fma(Uq[1 + b], Uq[1 + b], ke);
-        ke *= vrcp(Uq[0]);  // |m|^2 / rho with one reciprocal per point
-        const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
-        if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
-      }
-#pragma unroll
-      for (int v = 0; v < C::NV; ++v)
-#pragma unroll
-        for (int l = 1; l < C::N; ++l) wc[v][l] *= th2;
-    }
+    const bool bad = !(Ub[0] > eps) || !(pb > eps);
+    if (bad && act) atomicOr(flag, FLAG_NEGATIVE);
+    // a cell whose bounds leave positivity open goes to k_positivity's list
+    wave_append(act && !bad && !positivity_certain<D, C::N>(wc, g.gamma, eps), (int)cell, plist);
   }
-  // write back the modes j >= 2 (the means are unchanged)
+  // write back the modes j >= 1 (the means are unchanged)
+  if (act) {
 #pragma unroll
-  for (int v = 0; v < C::NV; ++v)
+    for (int v = 0; v < C::NV; ++v)
 #pragma unroll
-    for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
+      for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -3286,15 +3343,24 @@ __global__ __launch_bounds__(256) void k_amr_regrid(const double *__restrict__ w
 // Limiters on the refined mesh: neighbour means across the refinement
 // boundary are the children's average (coarse side) or the coarse polynomial's
 // mean over the adjacent child (fine side); coarse cells facing the fine block
-// also check positivity at the hanging-face points.
+// also check positivity at the hanging-face points (k_positivity).  One
+// launch covers the ids [t0, t0 + tn) of the combined numbering (coarse
+// cells, then fine cells): a fine cell on the block boundary reads the whole
+// coarse neighbour polynomial, which the coarse cell's own pass rewrites, so
+// the fine block is limited first and the coarse block after it (every
+// neighbour value then comes from the state before limiting, as the
+// limiter's definition has it; means are never written).
 template <int D, int K, bool CHAR>
-__global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ tab, double *__restrict__ w, AmrGrid g,
-                                                   int slope, double beta, double mtilde, int posit, double eps,
-                                                   int *__restrict__ flag) {
+__global__ __launch_bounds__(256, 2) void k_limit_amr(const double *__restrict__ tab, double *__restrict__ w, AmrGrid g,
+                                                      long t0, long tn, int slope, double beta, double mtilde,
+                                                      int posit, double eps, int *__restrict__ flag,
+                                                      int *__restrict__ plist) {
   using C = Cfg<D, K>;
   constexpr int NV = C::NV, N = C::N, NW = NV * N, NSUB = 1 << (D - 1);
-  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (tid >= g.ncc + g.ncf) return;
+  // lanes past the grid and on hole cells stay in the wave (the list of
+  // troubled cells is appended per wave) and store nothing
+  const long tid0 = t0 + (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long tid = tid0 < t0 + tn ? tid0 : t0 + tn - 1;
   const bool fine = tid >= g.ncc;
   const long cell = fine ? tid - g.ncc : tid;
   const long ncb = fine ? g.ncf : g.ncc;
@@ -3302,7 +3368,7 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
   double *wb = fine ? wfb : wcb;
   const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
   int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
-  if (!fine && amr_in_hole<D>(g, i)) return;
+  const bool act = tid0 < t0 + tn && (fine || !amr_in_hole<D>(g, i));
   // means and slopes first; the higher modes after the slope pass (as in k_limit)
   constexpr int NL = D + 1 < N ? D + 1 : N;
   double wc[NV][N];
@@ -3313,11 +3379,8 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 #pragma unroll
     for (int l = 0; l < NL; ++l) wc[v][l] = wb[(long)(v * N + l) * ncb + cell];
   }
-  // neighbour means [2D][NV]; bit f of hmask: side f is a hanging face (a
-  // bit mask rather than an array, which a run-time index would put in
-  // scratch memory)
+  // neighbour means [2D][NV]
   double nbm[2 * D][NV];
-  int hmask = 0;
 #pragma unroll
   for (int a = 0; a < D; ++a)
 #pragma unroll
@@ -3328,7 +3391,6 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
 #pragma unroll
           for (int v = 0; v < NV; ++v) nbm[2 * a + s][v] = wc[v][0];
         } else if (amr_in_hole<D>(g, j)) {
-          hmask |= 1 << (2 * a + s);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             double m = 0.0;
@@ -3416,69 +3478,85 @@ __global__ __launch_bounds__(256) void k_limit_amr(const double *__restrict__ ta
     for (int b = 0; b < D; ++b) keb = fma(Ub[1 + b], Ub[1 + b], keb);
     keb *= vrcp(Ub[0]);
     const double pb = (g.gamma - 1.0) * (Ub[D + 1] - 0.5 * keb);
-    if (!(Ub[0] > eps) || !(pb > eps)) {
-      atomicOr(flag, FLAG_NEGATIVE);
-    } else if (!positivity_certain<D, N>(wc, g.gamma, eps)) {
-      // points: the union set S, then the hanging-face points of every
-      // refined face of a coarse cell (all inside the reference cell, so
-      // the bound of positivity_certain covers them too); point s2 of the
-      // combined list, s2 >= NS: face (s2 - NS) / (NSUB QF), sub-face point
-      // (s2 - NS) mod (NSUB QF), rows of table HG
-      auto point = [&](int s2) {
-        if (s2 < C::NS) return tab + C::PS + s2 * N;
-        const int e = s2 - C::NS, f = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
-        return tab + C::HG + (f * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
-      };
-      // the faces' point ranges are walked only for the hanging faces
-      auto next = [&](int s2) {
-        ++s2;
-        while (s2 >= C::NS && s2 < C::NS + 2 * D * NSUB * C::QF) {
-          const int f = (s2 - C::NS) / (NSUB * C::QF);
-          if ((hmask >> f) & 1) break;
-          s2 = C::NS + (f + 1) * NSUB * C::QF;
-        }
-        return s2;
-      };
-      const int send = C::NS + 2 * D * NSUB * C::QF;
-      double rmin = INFINITY;
-      for (int s2 = 0; s2 < send; s2 = next(s2)) {
-        const double *ph = point(s2);
-        double r = 0.0;
+    const bool bad = !(Ub[0] > eps) || !(pb > eps);
+    if (bad && act) atomicOr(flag, FLAG_NEGATIVE);
+    // a cell whose bounds leave positivity open goes to k_positivity's list
+    // (ids over both blocks: the coarse cells, then the fine cells)
+    wave_append(act && !bad && !positivity_certain<D, N>(wc, g.gamma, eps), (int)tid, plist);
+  }
+  if (act) {
 #pragma unroll
-        for (int l = 0; l < N; ++l) r = fma(wc[0][l], ph[l], r);
-        rmin = fmin(rmin, r);
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = wc[v][l];
+  }
+}
+
+__global__ void k_zero_count(int *p) { p[0] = 0; }
+
+// The point loop of the positivity pass (Sec. 3.4) for every cell that
+// k_limit or k_limit_amr listed (those whose bounds left positivity open),
+// after those kernels have stored the cells' slope-limited coefficients: a
+// wave takes one listed cell at a time and its 64 lanes share the cell's
+// points (positivity_cell), so a troubled cell no longer holds its whole
+// work-group while one lane walks ~150 points alone.  AMR: ids over both
+// blocks (the coarse cells, then the fine cells); a coarse cell facing the
+// fine block also checks the points of its hanging faces (table HG), all
+// inside the reference cell.
+template <int D, int K, bool AMR>
+__global__ __launch_bounds__(256) void k_positivity(const double *__restrict__ tab, double *__restrict__ w, Grid g,
+                                                    AmrGrid ag, const int *__restrict__ plist, double eps) {
+  using C = Cfg<D, K>;
+  constexpr int N = C::N, NW = C::NV * N, NSUB = 1 << (D - 1);
+  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  const int cnt = plist[0];
+  for (long t = wave; t < cnt; t += nwaves) {
+    const long id = plist[1 + t];
+    if constexpr (!AMR) {
+      struct {
+        const double *ps;
+        __device__ int count(int) const { return C::NS; }
+        __device__ const double *row(int, int i) const { return ps + i * N; }
+      } pts{tab + C::PS};
+      positivity_cell<D, N>(w + id, g.ncell, 0, pts, g.gamma, eps);
+    } else {
+      const bool fine = id >= ag.ncc;
+      const long cell = fine ? id - ag.ncc : id;
+      int hm = 0;  // bit 2a + s: side (a, s) is a hanging face
+      if (!fine) {
+        int i[3] = {(int)(cell % ag.n[0]), (int)((cell / ag.n[0]) % ag.n[1]),
+                    (int)(cell / ((long)ag.n[0] * ag.n[1]))};
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) {
+            int j[3];
+            if (amr_coarse_nb<D>(ag, i, a, s ? 1 : -1, j) && amr_in_hole<D>(ag, j)) hm |= 1 << (2 * a + s);
+          }
       }
-      const double th1 = (Ub[0] == rmin) ? 1.0 : fmin(fabs((Ub[0] - eps) / (Ub[0] - rmin)), 1.0);
+      // point i >= NS: side = the (i - NS) / (NSUB QF)-th set bit of hm,
+      // sub-face point (i - NS) mod (NSUB QF), rows of table HG
+      struct {
+        const double *t;
+        __device__ int count(int h) const { return C::NS + __popc(h) * NSUB * C::QF; }
+        __device__ const double *row(int h, int i) const {
+          if (i < C::NS) return t + C::PS + i * N;
+          const int e = i - C::NS, k = e / (NSUB * C::QF), rem = e % (NSUB * C::QF);
+          int f = 0, seen = 0;
 #pragma unroll
-      for (int l = 1; l < N; ++l) wc[0][l] *= th1;
-      double th2 = 1.0;
-      for (int s2 = 0; s2 < send; s2 = next(s2)) {
-        const double *ph = point(s2);
-        double Uq[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          double u = 0.0;
-#pragma unroll
-          for (int l = 0; l < N; ++l) u = fma(wc[v][l], ph[l], u);
-          Uq[v] = u;
+          for (int b = 0; b < 2 * D; ++b)
+            if ((h >> b) & 1) {
+              if (seen == k) f = b;
+              ++seen;
+            }
+          return t + C::HG + (f * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
         }
-        double ke = 0.0;
-#pragma unroll
-        for (int b = 0; b < D; ++b) ke = fma(Uq[1 + b], Uq[1 + b], ke);
-        ke *= vrcp(Uq[0]);  // |m|^2 / rho with one reciprocal per point
-        const double pq = (g.gamma - 1.0) * (Uq[D + 1] - 0.5 * ke);
-        if (pq < eps) th2 = fmin(th2, tau_root<D>(Ub, Uq, g.gamma, eps));
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v)
-#pragma unroll
-        for (int l = 1; l < N; ++l) wc[v][l] *= th2;
+      } pts{tab};
+      positivity_cell<D, N>(fine ? w + (long)NW * ag.ncc + cell : w + cell, fine ? ag.ncf : ag.ncc, hm, pts,
+                            ag.gamma, eps);
     }
   }
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-#pragma unroll
-    for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = wc[v][l];
 }
 
 }  // namespace dg
@@ -3807,19 +3885,43 @@ struct LimitLaunch {
   int run() {
     const bool chr = c->cfg.slope_limiter == DG_LIM_CHAR;
     const int slope = c->cfg.slope_limiter != DG_LIM_NONE;
-    if (c->amr) {
-      if constexpr (K > 3) {
-        return DG_EUNSUPPORTED;
-      } else {
-        hipLaunchKernelGGL((chr ? dg::k_limit_amr<D, K, true> : dg::k_limit_amr<D, K, false>),
-                           dim3(nblocks(c->ncc + c->ncf)), dim3(kBlock), 0, s, c->tab, w, make_amr_grid(c), slope,
-                           c->cfg.beta, c->cfg.m_tilde, c->cfg.positivity, c->cfg.eps, c->flag);
-      }
-    } else {
-      hipLaunchKernelGGL((chr ? dg::k_limit<D, K, true> : dg::k_limit<D, K, false>), dim3(nblocks(c->ncell)),
-                         dim3(kBlock), 0, s, c->tab, w, make_grid(c), slope, c->cfg.beta, c->cfg.m_tilde * c->dx,
-                         c->cfg.positivity, c->cfg.eps, c->flag);
+    const int posit = c->cfg.positivity;
+    if constexpr (K > 3) {
+      if (c->amr) return DG_EUNSUPPORTED;
     }
+    // positivity: the limiter lists the cells that need the point loop,
+    // k_positivity runs it (a fill kernel clears the count: no memset, so
+    // the sequence can be captured in a graph)
+    if (posit) {
+      hipLaunchKernelGGL(dg::k_zero_count, dim3(1), dim3(1), 0, s, c->plist);
+      HIP_TRY(hipGetLastError());
+    }
+    // waves of the point-loop kernel: a grid-stride over the listed cells
+    const unsigned npos = (unsigned)std::min<long>(1024, std::max<long>(1, (c->ncell + 255) / 256));
+    if constexpr (K <= 3) {
+      if (c->amr) {
+        // the fine block first: its boundary cells read whole coarse polynomials
+        const long part[2][2] = {{c->ncc, c->ncf}, {0, c->ncc}};
+        for (const auto &pt : part) {
+          hipLaunchKernelGGL((chr ? dg::k_limit_amr<D, K, true> : dg::k_limit_amr<D, K, false>),
+                             dim3(nblocks(pt[1])), dim3(kBlock), 0, s, c->tab, w, make_amr_grid(c), pt[0], pt[1],
+                             slope, c->cfg.beta, c->cfg.m_tilde, posit, c->cfg.eps, c->flag, c->plist);
+          HIP_TRY(hipGetLastError());
+        }
+        if (posit)
+          hipLaunchKernelGGL((dg::k_positivity<D, K, true>), dim3(npos), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
+                             make_amr_grid(c), c->plist, c->cfg.eps);
+        HIP_TRY(hipGetLastError());
+        return DG_OK;
+      }
+    }
+    hipLaunchKernelGGL((chr ? dg::k_limit<D, K, true> : dg::k_limit<D, K, false>), dim3(nblocks(c->ncell)),
+                       dim3(kBlock), 0, s, c->tab, w, make_grid(c), slope, c->cfg.beta, c->cfg.m_tilde * c->dx,
+                       posit, c->cfg.eps, c->flag, c->plist);
+    HIP_TRY(hipGetLastError());
+    if (posit)
+      hipLaunchKernelGGL((dg::k_positivity<D, K, false>), dim3(npos), dim3(kBlock), 0, s, c->tab, w, make_grid(c),
+                         dg::AmrGrid{}, c->plist, c->cfg.eps);
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
@@ -4306,6 +4408,8 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
   if ((e = hipMalloc((void **)&c->tab32, nt * sizeof(float))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->partial, DG_RATE_STATE * sizeof(double))) != hipSuccess) return fail(e);
   if ((e = hipMalloc((void **)&c->flag, sizeof(int))) != hipSuccess) return fail(e);
+  if (cfg->positivity && (e = hipMalloc((void **)&c->plist, (size_t)(c->ncell + 1) * sizeof(int))) != hipSuccess)
+    return fail(e);
   std::vector<float> t32(nt);
   for (size_t i = 0; i < nt; ++i) t32[i] = (float)c->host_tab[i];
   if ((e = hipMemcpy(c->tab, c->host_tab.data(), nt * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
@@ -4379,6 +4483,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->vscratch) (void)hipFree(c->vscratch);
   if (c->partial) (void)hipFree(c->partial);
   if (c->flag) (void)hipFree(c->flag);
+  if (c->plist) (void)hipFree(c->plist);
   if (c->grav) (void)hipFree(c->grav);
   if (c->gmax) (void)hipFree(c->gmax);
   if (c->prmat) (void)hipFree(c->prmat);
