@@ -138,15 +138,29 @@ def test_step_matches_oracle(case, spec, precision):
     assert s.status() == 0
 
 
-def test_step_graph_replays():
+GRAPH_CASES = [
+    ("vortex", dict(name="vortex", n=(48, 40, 1), length=(12.0, 10.0, 1.0))),
+    # limiters with many cells in the positivity point-loop pass (its list
+    # count is cleared by a kernel inside the graph) on the refined box
+    ("blast_box_k3", dict(name="blast_amr", k=3, n=(8, 8, 8), length=(1.0, 1.0, 1.0), refine_lo=(2, 2, 2),
+                          refine_hi=(6, 6, 6), eps=1e-3)),
+]
+
+
+@pytest.mark.parametrize("case,spec", GRAPH_CASES, ids=[c[0] for c in GRAPH_CASES])
+def test_step_graph_replays(case, spec):
     # two chained steps captured into a graph (ping-pong A -> B -> A) and
     # replayed three times, with eager work and synchronisation in between;
     # every replay equals the eager chain bit for bit
     import torch
-    wl = workloads.workload("vortex", n=(48, 40, 1), length=(12.0, 10.0, 1.0))
-    o = oracle.Oracle(wl)
+    spec = dict(spec)
+    wl = workloads.workload(spec.pop("name"), **spec)
+    o = oracle.make(wl)
     s = __import__("paper_1506_06140_amd").Solver(wl)
     w0 = o.initial_state()
+    if wl["limiter"] or wl["positivity"]:
+        w0, st = o.limit(w0)
+        assert st == 0
     # eager reference: 8 steps
     fb = [s.empty() for _ in range(3)]
     dt, rate = s.scalar(), s.rate_state()
