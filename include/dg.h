@@ -309,7 +309,10 @@ int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *
  * in place, as configured.  Cell means are never changed.  A cell whose mean
  * density or pressure is <= eps sets the DG_ENEGATIVE flag and is left
  * unlimited; the characteristic limiter also leaves alone a mean without a
- * positive density and pressure. */
+ * positive density and pressure.  With positivity on, the call runs the
+ * point loop of the cells it cannot prove positive in a second pass, through
+ * a list in the context: calls on one context (dg_limit, dg_rk_step,
+ * dg_tableau_step) must be ordered, not overlapped on different streams. */
 int dg_limit(dg_ctx *ctx, double *w, void *stream);
 
 /* Discrete adjoint of dg_rhs: mu = (dL/dw)^T lam at the state w (all
