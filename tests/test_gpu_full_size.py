@@ -213,6 +213,29 @@ def test_full_size_blast_amr_limited_step_sampled():
     w1 = _host(_limited_step_parts("blast 64^3 + box", o, s, w0, cells))
     tot0 = o.totals(w0)
     np.testing.assert_allclose(o.totals(w1), tot0, rtol=0, atol=1e-12 * np.abs(tot0).max())
+    # FP32 contractions at full size, on both FP32 kernels of the refined box
+    # (MFMA, and the vector-ALU one): RHS within 1e-5 of |V| + |S| on the
+    # sampled cells (the blast's mass flux at rest comes from HLLC's contact
+    # speed, a difference of pressure-driven O(1) terms across a 10:1 jump,
+    # whose FP32 rounding is tens of ulps of the mass terms: 2.4e-6 measured
+    # on both kernels, against 1e-7 for the momenta and 3e-7 on the shear
+    # layer), the two kernels within 3x of each other, means conservative
+    d0 = _dev(w0)
+    dg.Solver(wl).limit(d0)
+    V, S = o.terms_cells(_host(d0), cells)
+    errs = {}
+    for path in (0, 1):
+        L = _host(dg.Solver(dict(wl, path3d=path), "fp32").rhs(d0))
+        Lc = o.cells_of(L, cells)
+        err = np.abs(Lc - (V - S)).reshape(o.nvar, -1).sum(1) / (np.abs(V) + np.abs(S)).reshape(o.nvar, -1).sum(1)
+        say("blast 64^3 + box fp32 path3d", path, "sampled rhs error / (|V|+|S|)", err)
+        assert np.all(err <= 1e-5), err
+        Lb, Lf = o.blocks(L)
+        tot = Lb[:, 0, ~o.hole].sum(axis=1) * o.dx ** 3 + Lf[:, 0, :].sum(axis=1) * o.dxf ** 3
+        scale = np.abs(Lb[:, 0, ~o.hole]).sum(axis=1) * o.dx ** 3 + np.abs(Lf[:, 0, :]).sum(axis=1) * o.dxf ** 3
+        assert np.all(np.abs(tot) <= 1e-13 * scale), tot / scale
+        errs[path] = err
+    assert np.all(errs[0] <= 3 * errs[1] + 1e-9) and np.all(errs[1] <= 3 * errs[0] + 1e-9), errs
 
 
 def test_full_size_blast_amr_reduced_precision():
