@@ -1190,13 +1190,14 @@ struct Mf3 {
   static constexpr int FBASE = SPLIT ? EF : 0;  // LDS block of face-phase operand o: o - FBASE
 };
 
-// Two waves per SIMD at k = 2 (<= 256 registers per lane): at one wave the
-// matrix pipe idled while the wave waited on its own MFMA results and loads
-// (5.3 ms against 3.2 ms per 128^3 launch).  FP64 at k = 3 and on the
-// refined box at k = 2 runs one wave (two would spill).  FP32 and BF16 run
-// two waves at k = 3 as well, where the uniform-grid kernels spill 12 to 19
-// registers but still gain (96^3, k = 3: 3.09 -> 2.35 ms FP32, 3.26 -> 2.26
-// ms BF16); three FP32 waves at k = 2 were slower (2.56 against 2.39 ms).
+// Two waves per SIMD (<= 256 registers per lane) wherever they do not spill
+// heavily: at one wave the matrix pipe idled while the wave waited on its
+// own MFMA results and loads (128^3, k = 2: 5.3 ms against 3.2 ms per
+// launch; refined blast, k = 2: 1.50 against 0.99 ms).  Uniform grids at
+// k = 3 spill 12 to 90 registers at two waves and still gain (96^3, FP64
+// 4.06 -> 3.52 ms, FP32 3.09 -> 2.35 ms, BF16 3.26 -> 2.26 ms); only FP64 on
+// the refined box at k = 3 keeps one wave (two would spill ~460 registers).
+// Three FP32 waves at k = 2 were slower (2.56 against 2.39 ms).
 //
 // AMR: the refined box of Sec. 4 (static 2:1 box; state = coarse block, then
 // fine block).  Blocks of the grid cover the coarse block's cells, then the
@@ -1228,7 +1229,7 @@ struct Mf3 {
 // of tile 2 tp + e / 4 in lane (g, c): the FP32 evaluation result is the B
 // operand without moving data between lanes).
 template <int K, int FX, bool AMR, class R = double, bool VB = false>
-__global__ __launch_bounds__(256, (sizeof(R) == 4 || (K == 2 && !AMR)) ? 2 : 1) void k_rhs_mfma3d(
+__global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) void k_rhs_mfma3d(
     const R *__restrict__ tmf, const double *__restrict__ tlw, const bf16x8 *__restrict__ tvb,
     const double *__restrict__ w, double *__restrict__ out, const double *__restrict__ dtp, Grid g, AmrGrid ag,
     int mode, Mix mx, int *__restrict__ flag) {
