@@ -1231,8 +1231,9 @@ struct Mf3 {
 // BLK (refined box): 0 one launch over both blocks, 1 the coarse block's
 // cells only, 2 the fine block's only (the other block's face kinds are then
 // compiled out: a coarse cell never has a coarse neighbour across the
-// refinement boundary, a fine cell never a hanging face).
-template <int K, int FX, bool AMR, class R = double, bool VB = false, int BLK = 0>
+// refinement boundary, a fine cell never a hanging face).  PER (uniform
+// grid): every axis periodic, so no wall faces (their selects compiled out).
+template <int K, int FX, bool AMR, class R = double, bool VB = false, int BLK = 0, bool PER = false>
 __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0) ? 2 : 1) void k_rhs_mfma3d(
     const R *__restrict__ tmf, const double *__restrict__ tlw, const bf16x8 *__restrict__ tvb,
     const double *__restrict__ w, double *__restrict__ out, const double *__restrict__ dtp, Grid g, AmrGrid ag,
@@ -1522,7 +1523,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0)
       const int n = bn[a], i2 = j2[a] + dir;
       const bool outside = (i2 < 0) | (i2 >= n);
       j2[a] = i2 < 0 ? i2 + n : (i2 >= n ? i2 - n : i2);
-      kind = (outside & (g.bc[a] == DG_BC_TRANSMISSIVE)) ? 1 : 0;
+      kind = (!PER && (outside & (g.bc[a] == DG_BC_TRANSMISSIVE))) ? 1 : 0;
       const long nb = ((long)j2[2] * bn[1] + j2[1]) * bn[0] + j2[0];
       src = kind ? cs : nb;
     }
@@ -3620,6 +3621,13 @@ dg::Grid make_grid(const dg_ctx *c) {
 
 unsigned nblocks(long n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// every axis of the context's grid periodic (no wall faces)
+bool periodic(const dg_ctx *c) {
+  for (int a = 0; a < c->sh.d; ++a)
+    if (c->cfg.bc[a] != DG_BC_PERIODIC) return false;
+  return true;
+}
+
 dg::AmrGrid make_amr_grid(const dg_ctx *c) {
   dg::AmrGrid g;
   g.n[0] = (int)c->nx;
@@ -3778,8 +3786,13 @@ struct StageLaunch {
       }
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
-      hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+      if (periodic(c))
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false, double, false, 0, true>),
+                           dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w,
+                           out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+      else
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
+                           s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(float) && !c->gravity && !vext && c->tabmf32) {
       // contractions on FP32 MFMA, 16 cells per wave, the mean's lift in FP64
       // (at k = 2 the one-thread-per-cell FP32 kernel is faster: 1.77 ms
@@ -3798,8 +3811,13 @@ struct StageLaunch {
                          w, out, dt, make_uniform_amr_grid(c), mode, mx, c->flag);
     } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
-      hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
-                         s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+      if (periodic(c))
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false, double, false, 0, true>),
+                           dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w,
+                           out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
+      else
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false>), dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0,
+                           s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
     } else {
       if (c->gravity) {
         if constexpr (sizeof(R) == sizeof(double)) {
