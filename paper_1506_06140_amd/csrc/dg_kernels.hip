@@ -2254,29 +2254,42 @@ struct BasisBounds {
 // is skipped.  Bounds: |u(xi) - u_mean| <= sum_{l>=1} |w_l| max|phi_l| per
 // variable, and p = (gamma-1)(E - |m|^2 / (2 rho)) >= (gamma-1)(E_lo -
 // |m|_hi^2 / (2 rho_lo)).
+// sum_{l>=1} |w_l| max|phi_l| of one variable's coefficients c
 template <int D, int N>
-__device__ inline bool positivity_certain(const double (&wc)[D + 2][N], double gamma, double eps) {
+__device__ inline double basis_excursion(const double *c) {
   constexpr BasisBounds<D, N> bb;
-  double R[D + 2];
+  double r = 0.0;
 #pragma unroll
-  for (int v = 0; v < D + 2; ++v) {
-    double r = 0.0;
-#pragma unroll
-    for (int l = 1; l < N; ++l) r = fma(fabs(wc[v][l]), bb.b[l], r);
-    R[v] = r;
-  }
-  const double rlo = wc[0][0] - R[0];
-  if (!(rlo > eps + 1e-10 * (fabs(wc[0][0]) + R[0]))) return false;
+  for (int l = 1; l < N; ++l) r = fma(fabs(c[l]), bb.b[l], r);
+  return r;
+}
+
+// the test above from the means and excursions R of the D + 2 variables
+template <int D>
+__device__ inline bool positivity_certain_mr(const double *mean, const double *R, double gamma, double eps) {
+  const double rlo = mean[0] - R[0];
+  if (!(rlo > eps + 1e-10 * (fabs(mean[0]) + R[0]))) return false;
   double m2 = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    const double m = fabs(wc[1 + a][0]) + R[1 + a];
+    const double m = fabs(mean[1 + a]) + R[1 + a];
     m2 = fma(m, m, m2);
   }
   const double ke = 0.5 * m2 / rlo;
-  const double plo = (gamma - 1.0) * ((wc[D + 1][0] - R[D + 1]) - ke);
-  const double scale = (gamma - 1.0) * (fabs(wc[D + 1][0]) + R[D + 1] + ke);
+  const double plo = (gamma - 1.0) * ((mean[D + 1] - R[D + 1]) - ke);
+  const double scale = (gamma - 1.0) * (fabs(mean[D + 1]) + R[D + 1] + ke);
   return plo > eps + 1e-10 * scale;
+}
+
+template <int D, int N>
+__device__ inline bool positivity_certain(const double (&wc)[D + 2][N], double gamma, double eps) {
+  double mean[D + 2], R[D + 2];
+#pragma unroll
+  for (int v = 0; v < D + 2; ++v) {
+    mean[v] = wc[v][0];
+    R[v] = basis_excursion<D, N>(wc[v]);
+  }
+  return positivity_certain_mr<D>(mean, R, gamma, eps);
 }
 
 template <int D, int K, bool CHAR>
@@ -3379,8 +3392,149 @@ __global__ __launch_bounds__(256, 2) void k_limit_amr(const double *__restrict__
   const int bn0 = fine ? g.nf[0] : g.n[0], bn1 = fine ? g.nf[1] : g.n[1];
   int i[3] = {(int)(cell % bn0), (int)((cell / bn0) % bn1), (int)(cell / ((long)bn0 * bn1))};
   const bool act = tid0 < t0 + tn && (fine || !amr_in_hole<D>(g, i));
-  // means and slopes first; the higher modes after the slope pass (as in k_limit)
   constexpr int NL = D + 1 < N ? D + 1 : N;
+  const double dx = fine ? g.dxf : g.dxc;
+  if constexpr (!CHAR && D == 3 && K == 3) {
+    // component-wise at 3D k = 3: one variable at a time (only its N
+    // coefficients live, not all (D+2) N: 144 registers and three waves per
+    // SIMD instead of 256 and two; at lower degree the compiler keeps the
+    // all-variables form below in fewer registers).  Per side
+    // of the cell, once: what the neighbour mean is (0 the own mean at a
+    // wall, 1 the average of the 2^d children of a refined coarse neighbour,
+    // first child fine cell snb, 2 the mean of cell snb of block sfine,
+    // 3 the coarse polynomial of coarse cell snb over child sch)
+    int sk[2 * D], sch[2 * D];
+    long snb[2 * D];
+    bool sfine[2 * D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * a + s;
+        sk[f] = 0; sch[f] = 0; snb[f] = 0; sfine[f] = fine;
+        if (!fine) {
+          int j[3];
+          if (!amr_coarse_nb<D>(g, i, a, s ? 1 : -1, j)) {
+            sk[f] = 0;
+          } else if (amr_in_hole<D>(g, j)) {
+            int fi[3] = {0, 0, 0};
+#pragma unroll
+            for (int b = 0; b < D; ++b) fi[b] = 2 * (j[b] - g.lo[b]);
+            sk[f] = 1;
+            snb[f] = ((long)fi[2] * g.nf[1] + fi[1]) * g.nf[0] + fi[0];
+          } else {
+            sk[f] = 2;
+            snb[f] = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+          }
+        } else {
+          int f2[3] = {i[0], i[1], i[2]};
+          f2[a] += s ? 1 : -1;
+          if (f2[a] >= 0 && f2[a] < g.nf[a]) {
+            sk[f] = 2;
+            snb[f] = ((long)f2[2] * g.nf[1] + f2[1]) * g.nf[0] + f2[0];
+          } else {
+            int base[3] = {0, 0, 0}, j[3];
+#pragma unroll
+            for (int b = 0; b < D; ++b) base[b] = g.lo[b] + i[b] / 2;
+            amr_coarse_nb<D>(g, base, a, s ? 1 : -1, j);
+            sk[f] = 3;
+            snb[f] = ((long)j[2] * g.n[1] + j[1]) * g.n[0] + j[0];
+            int ch = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) ch |= ((b == a) ? (s ? 0 : 1) : (i[b] & 1)) << b;
+            sch[f] = ch;
+          }
+        }
+      }
+    const long cstr[3] = {1, (long)g.nf[0], (long)g.nf[0] * g.nf[1]};  // fine-cell strides of the children
+    // what the positivity bounds need, accumulated in variable order (the
+    // order of positivity_certain_mr): density mean and excursion, energy
+    // mean and excursion, sum (|m_a| + R_a)^2 and |m|^2
+    double m0 = 0.0, r0 = 0.0, mE = 0.0, rE = 0.0, m2 = 0.0, keb = 0.0;
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+      double c[N];
+#pragma unroll
+      for (int l = 0; l < NL; ++l) c[l] = wb[(long)(v * N + l) * ncb + cell];
+      bool limited = false;
+      if (slope && K >= 1) {
+        double nbv[2 * D];
+#pragma unroll
+        for (int f = 0; f < 2 * D; ++f) {
+          double m = c[0];
+          if (sk[f] == 1) {
+            m = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < (1 << D); ++ch) {
+              long o = snb[f];
+#pragma unroll
+              for (int b = 0; b < D; ++b) o += ((ch >> b) & 1) * cstr[b];
+              m += wfb[(long)(v * N) * g.ncf + o];
+            }
+            m = m / (double)(1 << D);
+          } else if (sk[f] == 2) {
+            m = sfine[f] ? wfb[(long)(v * N) * g.ncf + snb[f]] : wcb[(long)(v * N) * g.ncc + snb[f]];
+          } else if (sk[f] == 3) {
+            m = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) m = fma(wcb[(long)(v * N + l) * g.ncc + snb[f]], tab[C::CM + sch[f] * N + l], m);
+          }
+          nbv[f] = m;
+        }
+        const double r3 = sqrt(3.0), bound = mtilde * dx;
+        const double mn = c[0];
+        double mt[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const double A = r3 * c[1 + a];
+          const double m = (fabs(A) <= bound) ? A : minmod3(A, beta * (mn - nbv[2 * a]), beta * (nbv[2 * a + 1] - mn));
+          mt[a] = m;
+          limited |= (m != A);
+        }
+        if (limited) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) c[1 + a] = mt[a] / r3;
+        }
+      }
+#pragma unroll
+      for (int l = NL; l < N; ++l) c[l] = limited ? 0.0 : wb[(long)(v * N + l) * ncb + cell];
+      const double Rv = basis_excursion<D, N>(c);
+      if (v == 0) {
+        m0 = c[0];
+        r0 = Rv;
+      } else if (v == NV - 1) {
+        mE = c[0];
+        rE = Rv;
+      } else {
+        const double m = fabs(c[0]) + Rv;
+        m2 = fma(m, m, m2);
+        keb = fma(c[0], c[0], keb);
+      }
+      if (act) {
+#pragma unroll
+        for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = c[l];
+      }
+    }
+    if (posit) {
+      keb *= vrcp(m0);
+      const double pb = (g.gamma - 1.0) * (mE - 0.5 * keb);
+      const bool bad = !(m0 > eps) || !(pb > eps);
+      if (bad && act) atomicOr(flag, FLAG_NEGATIVE);
+      // positivity_certain_mr on the accumulated quantities
+      bool certain = false;
+      const double rlo = m0 - r0;
+      if (rlo > eps + 1e-10 * (fabs(m0) + r0)) {
+        const double ke = 0.5 * m2 / rlo;
+        const double plo = (g.gamma - 1.0) * ((mE - rE) - ke);
+        const double scale = (g.gamma - 1.0) * (fabs(mE) + rE + ke);
+        certain = plo > eps + 1e-10 * scale;
+      }
+      wave_append(act && !bad && !certain, (int)tid, plist);
+    }
+    return;
+  }
+  // characteristic: means and slopes first; the higher modes after the slope
+  // pass (as in k_limit)
   double wc[NV][N];
   bool dropped[NV];
 #pragma unroll
@@ -3443,7 +3597,6 @@ __global__ __launch_bounds__(256, 2) void k_limit_amr(const double *__restrict__
         }
       }
     }
-  const double dx = fine ? g.dxf : g.dxc;
   if (slope && K >= 1) {
     const double r3 = sqrt(3.0), bound = mtilde * dx;
     if constexpr (CHAR) {
