@@ -1228,13 +1228,10 @@ struct Mf3 {
 // 8 g + e = node 16 (2 tp + e / 4) + 4 (e % 4) + g, which is register e % 4
 // of tile 2 tp + e / 4 in lane (g, c): the FP32 evaluation result is the B
 // operand without moving data between lanes).
-// BLK (refined box): 0 one launch over both blocks, 1 the coarse block's
-// cells only, 2 the fine block's only (the other block's face kinds are then
-// compiled out: a coarse cell never has a coarse neighbour across the
-// refinement boundary, a fine cell never a hanging face).  PER (uniform
-// grid): every axis periodic, so no wall faces (their selects compiled out).
-template <int K, int FX, bool AMR, class R = double, bool VB = false, int BLK = 0, bool PER = false>
-__global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0) ? 2 : 1) void k_rhs_mfma3d(
+// PER (uniform grid): every axis periodic, so no wall faces (their selects
+// compiled out).
+template <int K, int FX, bool AMR, class R = double, bool VB = false, bool PER = false>
+__global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) void k_rhs_mfma3d(
     const R *__restrict__ tmf, const double *__restrict__ tlw, const bf16x8 *__restrict__ tvb,
     const double *__restrict__ w, double *__restrict__ out, const double *__restrict__ dtp, Grid g, AmrGrid ag,
     int mode, Mix mx, int *__restrict__ flag) {
@@ -1267,13 +1264,9 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0)
   int bn[3];
   double fac, gam;
   if constexpr (AMR) {
-    if constexpr (BLK == 0) {
-      const long nbc = (ag.ncc + 63) / 64;
-      fine = blk >= nbc;
-      if (fine) blk -= nbc;
-    } else {
-      fine = BLK == 2;
-    }
+    const long nbc = (ag.ncc + 63) / 64;
+    fine = blk >= nbc;
+    if (fine) blk -= nbc;
     nc = fine ? ag.ncf : ag.ncc;
     boff = fine ? (long)NW * ag.ncc : 0;
 #pragma unroll
@@ -1548,7 +1541,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0)
         const V4 zn = chain(opf, M::EF + ((a * 2 + (1 - s)) * M::NFT + ft) * NKS, nbw[v]);
         Tn[v] = kind == 0 ? zn : To[v];  // wall: ghost trace = own trace
       }
-      if constexpr (AMR && BLK != 1) {
+      if constexpr (AMR) {
         // a fine cell facing the coarse block: the coarse neighbour's trace
         // at this cell's sub-face points
 #pragma unroll 1
@@ -1564,7 +1557,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR || BLK != 0)
       solve_lift(opf, M::LF + (((a * 2 + s) * M::NFT + ft) * 4) * NMT,
                  LO64 ? lws + ((a * 2 + s) * M::NFT + ft) * 16 : nullptr, a, s, ft, To, Tn, kind == 2);
     }
-    if constexpr (AMR && BLK != 2) {
+    if constexpr (AMR) {
       // a coarse cell facing the fine block: its 2^(d-1) sub-faces
       if (__any(kind == 2)) {
         const int t0 = (a == 0) ? 1 : 0, t1 = (a == 2) ? 1 : 2;
@@ -3876,22 +3869,10 @@ struct StageLaunch {
         }
       } else if constexpr (D == 3 && (K == 2 || K == 3) && sizeof(R) == sizeof(double)) {
         if (c->tabmf && !vext) {
-          // contractions on FP64 MFMA: coarse-block cells, then fine-block
-          // cells (k = 3: one launch per block, each without the other
-          // block's face kinds, two waves per SIMD)
-          if constexpr (K == 3) {
-            hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true, double, false, 1>), dim3((unsigned)((c->ncc + 63) / 64)),
-                               dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c),
-                               make_amr_grid(c), mode, mx, c->flag);
-            HIP_TRY(hipGetLastError());
-            hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true, double, false, 2>), dim3((unsigned)((c->ncf + 63) / 64)),
-                               dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w, out, dt, make_grid(c),
-                               make_amr_grid(c), mode, mx, c->flag);
-          } else {
-            const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
-            hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, nullptr,
-                               nullptr, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
-          }
+          // contractions on FP64 MFMA: coarse-block cells, then fine-block cells
+          const unsigned nb = (unsigned)((c->ncc + 63) / 64 + (c->ncf + 63) / 64);
+          hipLaunchKernelGGL((dg::k_rhs_mfma3d<K, FX, true>), dim3(nb), dim3(kBlock), 0, s, c->tabmf, nullptr,
+                             nullptr, w, out, dt, make_grid(c), make_amr_grid(c), mode, mx, c->flag);
         } else if constexpr (K == 3) {
           // four lanes per cell (the one-thread kernel would spill)
           hipLaunchKernelGGL((dg::k_rhs_amr_quad<K, FX, false>), dim3(nblocks(4 * (c->ncc + c->ncf))), dim3(kBlock),
@@ -3940,7 +3921,7 @@ struct StageLaunch {
     } else if (D == 3 && K == 3 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       if (periodic(c))
-        hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false, double, false, 0, true>),
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<3, FX, false, double, false, true>),
                            dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w,
                            out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
       else
@@ -3965,7 +3946,7 @@ struct StageLaunch {
     } else if (D == 3 && K == 2 && sizeof(R) == sizeof(double) && !c->gravity && !vext && c->tabmf) {
       // contractions on FP64 MFMA, 16 cells per wave
       if (periodic(c))
-        hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false, double, false, 0, true>),
+        hipLaunchKernelGGL((dg::k_rhs_mfma3d<2, FX, false, double, false, true>),
                            dim3((unsigned)((c->ncell + 63) / 64)), dim3(kBlock), 0, s, c->tabmf, nullptr, nullptr, w,
                            out, dt, make_grid(c), dg::AmrGrid{}, mode, mx, c->flag);
       else
