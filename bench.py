@@ -187,6 +187,63 @@ def cpu_baseline(wl, slab: int = 64):
                       f"C oracle pinned to core {core} (sched_setaffinity, as taskset) of {len(aff)}"}
 
 
+def cpu_other_workloads():
+    """The oracle, pinned to one host core, on bounded samples of the two
+    other 3D/adjoint workloads (context beside the headline's CPU leg):
+    the refined blast (64^3 + the 64^3-cell fine box, k=3): one SSP-RK3
+    stage (RHS, update, limiters) of two coarse z-planes through the box
+    and two fine z-planes, on the full-size initial projection (the
+    whole-mesh limiting that precedes the run, about 45 s on one core, is
+    left out); and one whole-mesh stage of the 2D vortex at 512^2, k=3 (the
+    adjoint workload's forward pass)."""
+    import oracle
+    aff = os.sched_getaffinity(0)
+    core = min(aff)
+    out = {}
+    wl = workloads.workload("blast_amr")
+    o = oracle.AmrOracle(wl)
+    w0 = o.initial_state()
+    dt = o.max_dt(w0)
+    n, (nfx, nfy, nfz) = wl["n"], o.nf
+    zc = (wl["refine_lo"][2] + wl["refine_hi"][2]) // 2
+    cc = np.arange((zc - 1) * n[0] * n[1], (zc + 1) * n[0] * n[1], dtype=np.int64)
+    cc = cc[~o.hole[cc]]
+    cf = o.ncoarse + np.arange((nfz // 2 - 1) * nfx * nfy, (nfz // 2 + 1) * nfx * nfy, dtype=np.int64)
+    cells = np.concatenate([cc, cf])
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        L = o.rhs_cells(w0, cells)
+        wc = o.cells_of(w0, cells)
+        oracle.rk3_combine(1, dt, wc, wc, L)
+        t1 = time.perf_counter()
+        o.limit_cells(w0, cells)
+        t2 = time.perf_counter()
+    finally:
+        os.sched_setaffinity(0, aff)
+    out["blast_amr_64box_k3"] = {
+        "value": cells.size * o.N / (t2 - t0), "unit": METRIC, "cores": 1, "kind": "oracle",
+        "sample": f"one limited SSP-RK3 stage (RHS + update {t1 - t0:.2f} s, limiters {t2 - t1:.2f} s) of "
+                  f"{cc.size} coarse cells (2 z-planes through the box) and {cf.size} fine cells (2 z-planes) of the "
+                  f"full-size k=3 blast, single-threaded C oracle pinned to core {core}"}
+    wl = workloads.workload("vortex_adjoint")
+    o = oracle.Oracle(wl)
+    w0 = o.initial_state()
+    dt = o.max_dt(w0)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        o.rk3_stage(1, dt, w0, w0)
+        el = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, aff)
+    out["vortex512_k3"] = {
+        "value": o.ncell * o.N / el, "unit": METRIC, "cores": 1, "kind": "oracle",
+        "sample": f"one SSP-RK3 stage of the full {wl['n'][0]}^2 k={wl['k']} vortex state ({el:.2f} s; the "
+                  f"adjoint workload's forward pass), single-threaded C oracle pinned to core {core}"}
+    return out
+
+
 def cpu_baseline_2d(wl, budget_s: float = 8.0):
     """The oracle on whole-mesh SSP-RK3 stages of the 2D vortex (256^2, k=2)."""
     import oracle
@@ -567,6 +624,7 @@ def main():
         rec["variants"].update(variants())
     if not args.no_cpu and args.workload == "kh3d":
         rec["cpu_baseline"] = cpu_baseline(wl)
+        rec["cpu_baseline"]["other_workloads"] = cpu_other_workloads()
     print(json.dumps(rec), flush=True)
 
 
