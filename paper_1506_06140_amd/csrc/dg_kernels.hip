@@ -54,7 +54,28 @@ struct Grid {
   int bc[3];
   double fac;    // (2/dx) 2^-d
   double gamma;
+  // block order of the 3D MFMA stage kernel (block_order): strips of xg
+  // blocks, xzc planes per XCD, xp blocks per plane; xg = 0: launch order
+  int xg, xzc, xp;
 };
+
+// The launch's blocks go to the eight XCDs in turn (block b to XCD b mod 8),
+// each XCD with its own L2.  For a 3D grid of whole 64-cell blocks per plane
+// (xp of them) and a multiple of eight planes, XCD x takes the planes
+// [x xzc, (x + 1) xzc), and its j-th block is strip lo of plane zz of
+// strip row hi, strips (xg blocks, one x-row when the row is whole blocks)
+// fastest, then the planes, then the strip rows: a block's z neighbours ran
+// xg blocks earlier on the same XCD and its y neighbours xg xzc blocks
+// earlier, so both are mostly still in that XCD's L2 (in launch order the
+// y neighbours sit on another XCD).  A permutation of the blocks whatever
+// the dispatch does.
+__device__ inline long block_order(const Grid &g, long b) {
+  if (g.xg == 0) return b;
+  const long x = b & 7, j = b >> 3;
+  const long lo = j % g.xg, r = j / g.xg;
+  const long zz = r % g.xzc, hi = r / g.xzc;
+  return (x * g.xzc + zz) * g.xp + hi * g.xg + lo;
+}
 
 enum : int { FLAG_NEGATIVE = 1, FLAG_NAN = 2 };
 
@@ -1274,6 +1295,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
     fac = fine ? ag.facf : ag.facc;
     gam = ag.gamma;
   } else {
+    blk = block_order(g, blk);
     nc = g.ncell;
     bn[0] = g.nx;
     bn[1] = g.ny;
@@ -3762,6 +3784,16 @@ dg::Grid make_grid(const dg_ctx *c) {
   for (int a = 0; a < 3; ++a) g.bc[a] = c->cfg.bc[a];
   g.fac = 2.0 / c->dx / (double)(1 << c->sh.d);
   g.gamma = c->cfg.gamma;
+  g.xg = g.xzc = g.xp = 0;
+  const long plane = c->nx * c->ny;
+  if (c->sh.d == 3 && plane % 64 == 0 && c->nz % 8 == 0) {
+    const long xg = c->nx % 64 == 0 ? c->nx / 64 : 1;
+    if ((plane / 64) % xg == 0) {
+      g.xg = (int)xg;
+      g.xzc = (int)(c->nz / 8);
+      g.xp = (int)(plane / 64);
+    }
+  }
   return g;
 }
 

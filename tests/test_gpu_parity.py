@@ -92,6 +92,14 @@ CASES = [
                                            bc=(1, 1, 0), flux=1)),
     ("blast_k3_valu", dict(name="blast_amr", k=3, n=(8, 7, 6), length=(1.0, 7 / 8, 6 / 8), limiter=0, positivity=0,
                            refine_lo=(0, 0, 0), refine_hi=(0, 0, 0), path3d=1)),
+    # MFMA kernel with its XCD-aware block order (whole 64-cell blocks per
+    # plane, a multiple of eight planes): periodic k = 2 and k = 3, and
+    # transmissive walls
+    ("kh3d_k2_block_order", dict(name="kh3d", k=2, n=(16, 8, 16), length=(1.6, 0.8, 1.6), limiter=0, positivity=0)),
+    ("kh3d_k3_block_order", dict(name="kh3d", k=3, n=(16, 8, 8), length=(1.6, 0.8, 0.8), limiter=0, positivity=0)),
+    ("blast3d_k2_transmissive_block_order", dict(name="blast_amr", k=2, n=(16, 4, 8), length=(1.0, 0.25, 0.5),
+                                                 x0=(0.0, 0.375, 0.25), limiter=0, positivity=0,
+                                                 refine_lo=(0, 0, 0), refine_hi=(0, 0, 0), bc=(1, 1, 0))),
 ]
 
 
