@@ -569,8 +569,10 @@ def main():
     alg_flops = f * cells
     alg_bytes = b * cells
     achieved = alg_flops / (k_ms * 1e-3) / 1e12
-    # limiter: reads every coefficient once, writes the modes >= 1
-    lim_bytes = (2 * s.N - 1) * s.nvar * 8 * cells
+    # limiter: reads every coefficient once; it writes back only the
+    # variables it changed (data-dependent, few cells of a smooth flow), which
+    # the figure leaves out: its HBM fraction is a lower bound
+    lim_bytes = s.N * s.nvar * 8 * cells
 
     rec = {
         "metric": METRIC,

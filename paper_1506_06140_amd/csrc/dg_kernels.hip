@@ -2395,12 +2395,15 @@ __global__ __launch_bounds__(256) void k_limit(const double *__restrict__ tab, d
     // a cell whose bounds leave positivity open goes to k_positivity's list
     wave_append(act && !bad && !positivity_certain<D, C::N>(wc, g.gamma, eps), (int)cell, plist);
   }
-  // write back the modes j >= 1 (the means are unchanged)
+  // write back the modes j >= 1 of the variables the slope pass changed
+  // (the means are never changed; an unlimited variable's coefficients are
+  // the ones in memory, so most cells of a smooth flow store nothing)
   if (act) {
 #pragma unroll
     for (int v = 0; v < C::NV; ++v)
+      if (dropped[v])
 #pragma unroll
-      for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
+        for (int l = 1; l < C::N; ++l) w[(long)(v * C::N + l) * nc + cell] = wc[v][l];
   }
 }
 
@@ -3525,7 +3528,7 @@ __global__ __launch_bounds__(256, 2) void k_limit_amr(const double *__restrict__
         m2 = fma(m, m, m2);
         keb = fma(c[0], c[0], keb);
       }
-      if (act) {
+      if (act && limited) {  // an unlimited variable is unchanged in memory
 #pragma unroll
         for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = c[l];
       }
@@ -3662,11 +3665,12 @@ __global__ __launch_bounds__(256, 2) void k_limit_amr(const double *__restrict__
     // (ids over both blocks: the coarse cells, then the fine cells)
     wave_append(act && !bad && !positivity_certain<D, N>(wc, g.gamma, eps), (int)tid, plist);
   }
-  if (act) {
+  if (act) {  // the variables the slope pass changed (as in k_limit)
 #pragma unroll
     for (int v = 0; v < NV; ++v)
+      if (dropped[v])
 #pragma unroll
-      for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = wc[v][l];
+        for (int l = 1; l < N; ++l) wb[(long)(v * N + l) * ncb + cell] = wc[v][l];
   }
 }
 
