@@ -1638,6 +1638,12 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
   bool bad = false;
   const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
   const long ol = boff + (long)gq * nc + cs;  // this lane's part of the output index
+  // REUSE (FP64): the stage update takes the cell's own coefficient from the
+  // B operand wb (mode 4 ks + gq in register ks, the same double) instead of
+  // reading it again after the face phase, when it has mostly left the
+  // caches (128^3, k=2: 2.84 -> 2.67 ms).  Not where keeping wb live to the
+  // end spills (uniform grids at k = 3: 90 -> 146 registers).
+  constexpr bool REUSE = sizeof(R) == sizeof(double) && (AMR ? K == 3 : K == 2);
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -1650,7 +1656,8 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
           const double Lv = (LO64 && jm == 0) ? acc0[v] : (double)acc[v][mt][r];
           const double L = hole ? 0.0 : fac * Lv;
           bad |= (L != L);
-          out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, hole ? 0.0 : cldt, i);
+          const double u = REUSE ? (double)wb[v][4 * mt + r] : w[i];
+          out[i] = (mode == 0) ? L : mix_out(mx, u, L, hole ? 0.0 : cldt, i);
         }
       }
   if (bad) atomicOr(flag, FLAG_NAN);
