@@ -710,7 +710,9 @@ __global__ __launch_bounds__(256) void k_rhs_stage(const double *__restrict__ ta
       const long i = (long)(v * C::N + l) * nc + cell;
       const double L = g.fac * (l == 0 ? acc0[v] : (double)acc[v][l]);
       bad |= (L != L);
-      out[i] = (mode == 0) ? L : mix_out(mx, w[i], L, cldt, i);
+      // FP64: the coefficient loaded at the start, not read again
+      const double u = sizeof(R) == sizeof(double) ? (double)wc[v][l] : w[i];
+      out[i] = (mode == 0) ? L : mix_out(mx, u, L, cldt, i);
     }
   if (bad) atomicOr(flag, FLAG_NAN);
 }
@@ -1260,12 +1262,26 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
   using V4 = typename Mv4<R>::T;
   constexpr int N = M::N, NV = M::NV, NKS = M::NKS, NMT = M::NMT, QF = M::QF, Q = M::Q, NW = NV * N;
   constexpr bool LO64 = sizeof(R) == sizeof(float);  // mode 0 lifted in FP64
+  // REUSE (FP64): the stage update takes the cell's own coefficient from the
+  // B operand wb (mode 4 ks + gq in register ks, the same double) instead of
+  // reading it again after the face phase, when it has mostly left the
+  // caches (128^3, k=2: 2.84 -> 2.67 ms; refined blast, k=3: 2.68 -> 2.59
+  // ms).  Not where keeping wb live to the end spills (uniform grids at
+  // k = 3: 90 -> 146 registers).  PREY (refined box, one block per CU): the
+  // first extra state of the stage combination (the step's initial state in
+  // SSP-RK3 stages 2 and 3) is loaded with the cell's own and parked in LDS
+  // (ysl) for the update (2.59 -> 2.44 ms; at k = 2 on uniform grids, two
+  // blocks per CU, the 31 KB more LDS per block cost more than it saved:
+  // 2.66 -> 2.99 ms).
+  constexpr bool REUSE = sizeof(R) == sizeof(double) && (AMR ? K == 3 : K == 2);
+  constexpr bool PREY = REUSE && AMR;
   static_assert(!VB || (LO64 && N <= 32), "BF16 volume: FP32 kernel, at most 32 modes");
   // VB: LDS holds the face phase's FP32 operands and the BF16 volume operands
   constexpr int FB = VB ? M::EF : M::FBASE;  // LDS block of face-phase operand o: o - FB
   __shared__ R tl[(VB ? M::FOPS : M::LDSOPS) * 64];
   __shared__ double lws[LO64 ? M::LW : 1];
   __shared__ bf16x8 tvl[VB ? M::BOPS * 64 : 1];
+  __shared__ double ysl[PREY ? 4 * NV * NKS * 64 : 1];  // per wave, variable, K step, lane
   if constexpr (VB) {
     for (int i = threadIdx.x; i < M::FOPS * 64; i += blockDim.x) tl[i] = tmf[M::EF * 64 + i];
     for (int i = threadIdx.x; i < M::BOPS * 64; i += blockDim.x) tvl[i] = tvb[i];
@@ -1341,6 +1357,16 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
         const double x = wbk[(long)(v * N) * nc + o[ks]];
         wb[v][ks] = (4 * ks + gq < N && valid) ? (R)x : R(0);
       }
+  }
+  const bool pre = PREY && mode != 0 && mx.n > 0;
+  if (pre) {
+    long o[NKS];
+    lane_offsets(nc, cs, o);
+    const double *y0 = mx.y[0] + boff;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+      for (int ks = 0; ks < NKS; ++ks) ysl[((wv * NV + v) * NKS + ks) * 64 + lane] = y0[(long)(v * N) * nc + o[ks]];
   }
 
   V4 acc[NV][NMT];
@@ -1638,12 +1664,6 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
   bool bad = false;
   const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
   const long ol = boff + (long)gq * nc + cs;  // this lane's part of the output index
-  // REUSE (FP64): the stage update takes the cell's own coefficient from the
-  // B operand wb (mode 4 ks + gq in register ks, the same double) instead of
-  // reading it again after the face phase, when it has mostly left the
-  // caches (128^3, k=2: 2.84 -> 2.67 ms).  Not where keeping wb live to the
-  // end spills (uniform grids at k = 3: 90 -> 146 registers).
-  constexpr bool REUSE = sizeof(R) == sizeof(double) && (AMR ? K == 3 : K == 2);
 #pragma unroll
   for (int v = 0; v < NV; ++v)
 #pragma unroll
@@ -1656,8 +1676,16 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 || K == 2 || !AMR) ? 2 : 1) vo
           const double Lv = (LO64 && jm == 0) ? acc0[v] : (double)acc[v][mt][r];
           const double L = hole ? 0.0 : fac * Lv;
           bad |= (L != L);
-          const double u = REUSE ? (double)wb[v][4 * mt + r] : w[i];
-          out[i] = (mode == 0) ? L : mix_out(mx, u, L, hole ? 0.0 : cldt, i);
+          // mode 4 ks + gq of the cell in K step ks = 4 mt + r (< NKS for jm < N)
+          const int ks = 4 * mt + r < NKS ? 4 * mt + r : NKS - 1;
+          const double u = REUSE ? (double)wb[v][ks] : w[i];
+          double o = L;
+          if (mode != 0) {  // mix_out, with the first extra term from LDS when parked
+            o = fma(hole ? 0.0 : cldt, L, mx.cu * u);
+            if (pre) o = fma(mx.a[0], ysl[((wv * NV + v) * NKS + ks) * 64 + lane], o);
+            o = mix_tail(mx, o, i, pre ? 1 : 0);
+          }
+          out[i] = o;
         }
       }
   if (bad) atomicOr(flag, FLAG_NAN);
