@@ -117,6 +117,10 @@ def _load():
             "orc_amr_tableau_stage": [cp, C.c_int, dp, dp, C.c_int, C.c_double, dp, dp],
             "orc_amr_flags": [cp, dp, C.c_double, C.c_double, ip],
             "orc_amr_regrid": [cp, dp, cp, dp],
+            "orc_tree_rhs": [cp, C.c_long, ip, lp, lp, dp, dp],
+            "orc_tree_max_dt": [cp, C.c_long, ip, lp, lp, dp, dp],
+            "orc_tree_node_coords": [cp, C.c_long, ip, lp, lp, dp],
+            "orc_tree_project": [cp, C.c_long, ip, lp, lp, dp, dp],
         }.items():
             getattr(_lib, name).argtypes = args
             getattr(_lib, name).restype = C.c_int
@@ -680,3 +684,66 @@ class AmrOracle(Oracle):
         P = np.zeros((self.N, self.N))
         _check(lib.orc_refine_matrix(C.byref(self.c), child, P), "refine_matrix")
         return P
+
+
+class TreeOracle(Oracle):
+    """A 2D run on a quadtree of leaves (Sec. 4): `leaves` is an integer array
+    [nleaf][3] of (level, ix, iy), level 0 the workload's base grid.  The state
+    is [nvar][N][nleaf] in leaf order."""
+
+    def __init__(self, wl: dict, leaves):
+        if wl["dim"] != 2:
+            raise ValueError("the quadtree oracle is 2D")
+        super().__init__(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)))
+        lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int64).reshape(-1, 3))
+        self.leaves = lv
+        self.nleaf = lv.shape[0]
+        self._lev = np.ascontiguousarray(lv[:, 0], dtype=np.int32)
+        self._ix = np.ascontiguousarray(lv[:, 1], dtype=np.int64)
+        self._iy = np.ascontiguousarray(lv[:, 2], dtype=np.int64)
+        self.shape = (self.nvar, self.N, self.nleaf)
+        self.ncell = self.nleaf
+
+    def _a(self):
+        return (C.byref(self.c), self.nleaf, self._lev, self._ix, self._iy)
+
+    def node_coords(self) -> np.ndarray:
+        """[nleaf][Q][3] physical coordinates of the leaves' volume nodes."""
+        lib, _ = _load()
+        x = np.zeros((2, self.Q, self.nleaf))
+        _check(lib.orc_tree_node_coords(*self._a(), x), "tree_node_coords")
+        out = np.zeros((self.nleaf, self.Q, 3))
+        out[..., 0] = x[0].T
+        out[..., 1] = x[1].T
+        return out
+
+    def project_prim(self, prim: np.ndarray) -> np.ndarray:
+        lib, _ = _load()
+        prim = np.ascontiguousarray(prim, dtype=np.float64)
+        assert prim.shape == (self.nleaf, self.Q, 5)
+        w = np.zeros(self.shape)
+        _check(lib.orc_tree_project(*self._a(), prim, w), "tree_project")
+        return w
+
+    def rhs(self, w: np.ndarray) -> np.ndarray:
+        lib, _ = _load()
+        L = np.zeros(self.shape)
+        _check(lib.orc_tree_rhs(*self._a(), self._s(w), L), "tree_rhs")
+        return L
+
+    def max_dt(self, w: np.ndarray) -> float:
+        lib, _ = _load()
+        dt = np.zeros(1)
+        _check(lib.orc_tree_max_dt(*self._a(), self._s(w), dt), "tree_max_dt")
+        return float(dt[0])
+
+    def rk3_stage(self, stage: int, dt: float, wn, wp) -> np.ndarray:
+        return rk3_combine(stage, dt, wn, wp, self.rhs(wp))
+
+    def step(self, w0: np.ndarray, dt: float | None = None):
+        """One SSP-RK3 step (App. D, table RK_3); returns (w1, dt)."""
+        if dt is None:
+            dt = self.max_dt(w0)
+        w1 = self.rk3_stage(1, dt, w0, w0)
+        w2 = self.rk3_stage(2, dt, w0, w1)
+        return self.rk3_stage(3, dt, w0, w2), dt

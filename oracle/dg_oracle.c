@@ -37,6 +37,7 @@
  *                                     and rhs; tables RK_2, RK_4
  *   gravity source and time step .... Sec. 2.4 eq. gravity_term; Sec. 2.5
  *   refinement criterion ............ Sec. 4.1 eqs. cell_ref, node_ref
+ *   2D quadtree of leaves (any depth, level jump <= 1 across faces) ... Sec. 4
  *   refine / derefine projections ... Sec. 4.2 eqs. ref_pa_integral,
  *                                     ref_weights; Sec. 4.3 eq. deref_weights
  * The HLLC Riemann solver is cited by the paper to Toro's textbook only; the
@@ -2004,6 +2005,246 @@ int orc_amr_regrid(const orc_config *c_old, const double *w_old, const orc_confi
     }
   }
   free(P); free(A); free(B);
+  return ORC_OK;
+}
+
+
+/* ------------------------------------------------------------------------ */
+/* Quadtree of leaf cells in 2D (Sec. 4: cells split into 2^d children at any */
+/* level, the level jump across a face at most one)                          */
+/*                                                                            */
+/* Leaf i has level lev[i] >= 0 and integer position (ix[i], iy[i]) on its     */
+/* level: level 0 is the base grid n[], a level-l cell has edge dx / 2^l and  */
+/* covers [x0 + ix h, x0 + (ix + 1) h) x [y0 + iy h, y0 + (iy + 1) h).  The     */
+/* state is [nvar][N][nleaf] in leaf order.  Written from the geometry alone: */
+/* every face of a leaf is cut into the overlaps with the leaves across it    */
+/* (found by brute force), each overlap integrated with the (k+1)-point Gauss */
+/* rule mapped onto it, both traces evaluated at the physical node through    */
+/* each cell's own reference coordinates, and the lifted flux weighted by the */
+/* overlap's share of the leaf's face.  With 2:1 balance this is the          */
+/* hanging-face quadrature of Sec. 4 (coarse trace at (eta + sigma)/2, weight */
+/* w_r / 2 on the coarse side).                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  ctx X;          /* tables; X.ncell = nleaf, X.dx = base edge              */
+  long nleaf;
+  int lmax;
+  long NX, NY;    /* domain in units of the finest level                   */
+  long *bx0, *bx1, *by0, *by1; /* leaf boxes in those units                */
+} tree;
+
+static void tree_free(tree *T) { free(T->bx0); free(T->bx1); free(T->by0); free(T->by1); }
+
+static int tree_init(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, tree *T) {
+  memset(T, 0, sizeof(*T));
+  if (c->dim != 2 || c->accel || nleaf < 1) return ORC_EINVAL;
+  int st = ctx_init(c, &T->X);
+  if (st != ORC_OK) return st;
+  T->nleaf = nleaf;
+  T->X.ncell = nleaf;
+  T->lmax = 0;
+  for (long i = 0; i < nleaf; ++i) {
+    if (lev[i] < 0 || lev[i] > 20) return ORC_EINVAL;
+    if (lev[i] > T->lmax) T->lmax = lev[i];
+  }
+  T->NX = (long)c->n[0] << T->lmax;
+  T->NY = (long)c->n[1] << T->lmax;
+  T->bx0 = malloc(sizeof(long) * nleaf); T->bx1 = malloc(sizeof(long) * nleaf);
+  T->by0 = malloc(sizeof(long) * nleaf); T->by1 = malloc(sizeof(long) * nleaf);
+  long area = 0;
+  for (long i = 0; i < nleaf; ++i) {
+    long s = 1L << (T->lmax - lev[i]);
+    if (ix[i] < 0 || iy[i] < 0 || ix[i] >= ((long)c->n[0] << lev[i]) || iy[i] >= ((long)c->n[1] << lev[i])) {
+      tree_free(T);
+      return ORC_EINVAL;
+    }
+    T->bx0[i] = ix[i] * s; T->bx1[i] = (ix[i] + 1) * s;
+    T->by0[i] = iy[i] * s; T->by1[i] = (iy[i] + 1) * s;
+    area += s * s;
+  }
+  /* a tiling: no two leaves overlap and together they cover the domain */
+  for (long i = 0; i < nleaf; ++i)
+    for (long j = i + 1; j < nleaf; ++j)
+      if (T->bx0[i] < T->bx1[j] && T->bx0[j] < T->bx1[i] && T->by0[i] < T->by1[j] && T->by0[j] < T->by1[i]) {
+        tree_free(T);
+        return ORC_EINVAL;
+      }
+  if (area != T->NX * T->NY) { tree_free(T); return ORC_EINVAL; }
+  return ORC_OK;
+}
+
+/* The leaves across face (a, s) of leaf i and their overlaps [o0, o1) with it
+ * along the tangential axis, sorted by o0; returns the count (0 at a
+ * transmissive wall).  Periodic axes wrap. */
+static int tree_across(const tree *T, long i, int a, int s, long *nb, long *o0, long *o1) {
+  const long *n0 = a == 0 ? T->bx0 : T->by0, *n1 = a == 0 ? T->bx1 : T->by1;
+  const long *t0 = a == 0 ? T->by0 : T->bx0, *t1 = a == 0 ? T->by1 : T->bx1;
+  long L = a == 0 ? T->NX : T->NY;
+  long f = s ? n1[i] : n0[i];
+  if ((f == 0 || f == L) && T->X.c.bc[a] == 1) return 0;
+  f = ((f % L) + L) % L;
+  int m = 0;
+  for (long j = 0; j < T->nleaf; ++j) {
+    long g = s ? n0[j] : n1[j] % L;
+    if (g != f) continue;
+    long lo = t0[i] > t0[j] ? t0[i] : t0[j], hi = t1[i] < t1[j] ? t1[i] : t1[j];
+    if (hi <= lo) continue;
+    if (m == 4) return -1;
+    nb[m] = j; o0[m] = lo; o1[m] = hi; ++m;
+  }
+  for (int p = 1; p < m; ++p)
+    for (int q = p; q > 0 && o0[q] < o0[q - 1]; --q) {
+      long t;
+      t = nb[q]; nb[q] = nb[q - 1]; nb[q - 1] = t;
+      t = o0[q]; o0[q] = o0[q - 1]; o0[q - 1] = t;
+      t = o1[q]; o1[q] = o1[q - 1]; o1[q - 1] = t;
+    }
+  return m;
+}
+
+/* value of leaf i's polynomial (all variables) at reference point xi */
+static void tree_eval(const tree *T, const double *w, long i, const double *xi, double *U) {
+  const ctx *X = &T->X;
+  for (int v = 0; v < X->nvar; ++v) {
+    double s = 0.0;
+    for (int l = 0; l < X->N; ++l) s += W(v, l, i) * phi_at(X, l, xi);
+    U[v] = s;
+  }
+}
+
+/* Surface term of leaf i (eq. dg_term3 over the overlaps of its faces). */
+static int tree_surface(const tree *T, const double *w, long i, double S[MAXV][MAXN]) {
+  const ctx *X = &T->X;
+  for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
+  for (int a = 0; a < 2; ++a) {
+    int b = 1 - a; /* tangential axis */
+    const long *t0 = b == 0 ? T->bx0 : T->by0, *t1 = b == 0 ? T->bx1 : T->by1;
+    for (int s = 0; s < 2; ++s) {
+      long nb[4], o0[4], o1[4];
+      int m = tree_across(T, i, a, s, nb, o0, o1);
+      if (m < 0) return ORC_EINVAL;
+      int wall = (m == 0);
+      if (wall) { nb[0] = i; o0[0] = t0[i]; o1[0] = t1[i]; m = 1; }
+      for (int p = 0; p < m; ++p) {
+        long j = nb[p];
+        double ratio = (double)(o1[p] - o0[p]) / (double)(t1[i] - t0[i]);
+        for (int r = 0; r < X->n1; ++r) {
+          /* reference coordinates of the node in leaf i and in leaf j */
+          double xi[3] = {0, 0, 0}, xj[3] = {0, 0, 0};
+          xi[a] = s ? 1.0 : -1.0;
+          xj[a] = s ? -1.0 : 1.0;
+          xi[b] = ((double)(o0[p] + o1[p] - t0[i] - t1[i]) + (double)(o1[p] - o0[p]) * X->gx[r]) /
+                  (double)(t1[i] - t0[i]);
+          xj[b] = ((double)(o0[p] + o1[p] - t0[j] - t1[j]) + (double)(o1[p] - o0[p]) * X->gx[r]) /
+                  (double)(t1[j] - t0[j]);
+          double Uo[MAXV], Un[MAXV], F[MAXV];
+          tree_eval(T, w, i, xi, Uo);
+          if (wall) for (int v = 0; v < X->nvar; ++v) Un[v] = Uo[v];
+          else tree_eval(T, w, j, xj, Un);
+          if (s) hllc(X, Uo, Un, a, F); else hllc(X, Un, Uo, a, F);
+          for (int v = 0; v < X->nvar; ++v)
+            for (int l = 0; l < X->N; ++l) {
+              double tt = F[v] * phi_at(X, l, xi) * (X->gw[r] * ratio);
+              if (s) S[v][l] += tt; else S[v][l] -= tt;
+            }
+        }
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* L = dw/dt on every leaf: (2/dx_i) 2^-d (V - S) with the leaf's own edge. */
+int orc_tree_rhs(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                 const double *w, double *L) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  for (long i = 0; i < nleaf && st == ORC_OK; ++i) {
+    double V[MAXV][MAXN], S[MAXV][MAXN];
+    volume_term(X, w, i, V, NULL);
+    st = tree_surface(T, w, i, S);
+    double dxi = X->dx / (double)(1L << lev[i]);
+    double fac = 2.0 / dxi / 4.0;
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) L[((long)v * X->N + j) * nleaf + i] = fac * (V[v][j] - S[v][j]);
+  }
+  tree_free(T); free(T);
+  return st;
+}
+
+/* dt = CFL f_k / max over leaves of sum_a (|v_a| + c)/dx_i of the leaf mean. */
+int orc_tree_max_dt(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                    const double *w, double *dt_out) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  double fk = 1.0 / (2.0 * X->k + 1.0);
+  if (c->positivity && X->lw[0] / 2.0 < fk) fk = X->lw[0] / 2.0;
+  double dt = INFINITY;
+  for (long i = 0; i < nleaf; ++i) {
+    double U[MAXV];
+    for (int v = 0; v < X->nvar; ++v) U[v] = W(v, 0, i);
+    double p = pressure(X, U);
+    double cs = sqrt(c->gamma * p / U[0]);
+    double dxi = X->dx / (double)(1L << lev[i]);
+    double rate = 0.0;
+    for (int a = 0; a < X->d; ++a) rate += (fabs(U[1 + a] / U[0]) + cs) / dxi;
+    double dtc = c->cfl * fk / rate;
+    if (dtc < dt) dt = dtc;
+  }
+  *dt_out = dt;
+  tree_free(T); free(T);
+  return ORC_OK;
+}
+
+/* Physical coordinates of every leaf's volume nodes, x[2][Q][nleaf]. */
+int orc_tree_node_coords(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                         double *x) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  for (long i = 0; i < nleaf; ++i) {
+    double h = X->dx / (double)(1L << lev[i]);
+    for (int q = 0; q < X->Q; ++q) {
+      int iq[2] = {q % X->n1, q / X->n1};
+      x[((long)0 * X->Q + q) * nleaf + i] = c->x0[0] + h * (ix[i] + 0.5 * (1.0 + X->gx[iq[0]]));
+      x[((long)1 * X->Q + q) * nleaf + i] = c->x0[1] + h * (iy[i] + 0.5 * (1.0 + X->gx[iq[1]]));
+    }
+  }
+  tree_free(T); free(T);
+  return ORC_OK;
+}
+
+/* L2 projection (Sec. 2.3) of primitives prim[nleaf][Q][5] = (rho, vx, vy, vz,
+ * p) at each leaf's volume nodes: the same per-cell projection as on a
+ * uniform grid, the leaf edge does not enter. */
+int orc_tree_project(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                     const double *prim, double *w) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  for (long i = 0; i < nleaf; ++i) {
+    double acc[MAXV][MAXN];
+    memset(acc, 0, sizeof(acc));
+    for (int q = 0; q < X->Q; ++q) {
+      const double *pr = prim + (i * X->Q + q) * 5;
+      double U[MAXV], ke = 0.0;
+      U[0] = pr[0];
+      for (int b = 0; b < 2; ++b) { U[1 + b] = pr[0] * pr[1 + b]; ke += pr[1 + b] * pr[1 + b]; }
+      U[3] = pr[4] / (c->gamma - 1.0) + 0.5 * pr[0] * ke;
+      for (int v = 0; v < X->nvar; ++v)
+        for (int j = 0; j < X->N; ++j) acc[v][j] += U[v] * X->phiV[q][j] * X->wV[q];
+    }
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) W(v, j, i) = 0.25 * acc[v][j];
+  }
+  tree_free(T); free(T);
   return ORC_OK;
 }
 

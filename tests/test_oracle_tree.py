@@ -1,0 +1,117 @@
+"""Pins of the oracle's 2D quadtree path (Sec. 4: leaves of any depth, level
+jump at most one across a face) against results fixed independently of it:
+
+* a tree whose leaves all sit on one level is a uniform grid: its RHS equals
+  the uniform oracle's (base grid, or the grid of twice the resolution);
+* a tree shaped like one 2:1 box equals the refined-box oracle, whose
+  hanging-face quadrature is pinned on its own;
+* on any periodic tree the face fluxes cancel in the area-weighted sum of the
+  cell means (conservation), and a constant state has L = 0;
+* the time step of a one-level tree equals the uniform oracle's, and halves
+  when every leaf is split.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+
+def _wl(n=(6, 5), k=2, ic="vortex", **kw):
+    base = dict(n=(n[0], n[1], 1), length=(10.0 * n[0] / max(n), 10.0 * n[1] / max(n), 1.0),
+                x0=(-5.0, -5.0, 0.0), k=k, limiter=0, positivity=0)
+    base.update(kw)
+    return workloads.workload("vortex", **base) if ic == "vortex" else workloads.workload(ic, **base)
+
+
+def _grid_leaves(n, level):
+    nx, ny = n[0] << level, n[1] << level
+    return np.array([(level, x, y) for y in range(ny) for x in range(nx)], dtype=np.int64)
+
+
+def _close(a, b, tol):
+    a = np.asarray(a).reshape(a.shape[0], -1) if a.ndim > 1 else a
+    scale = np.abs(b).reshape(b.shape[0], -1).max(axis=1, keepdims=True)
+    err = np.abs(np.asarray(a).reshape(b.shape[0], -1) - b.reshape(b.shape[0], -1)) / scale
+    assert err.max() <= tol, err.max()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_one_level_tree_is_the_uniform_grid(k):
+    wl = _wl(k=k)
+    u = oracle.Oracle(wl)
+    w = u.initial_state()
+    t = oracle.TreeOracle(wl, _grid_leaves((6, 5), 0))
+    Lu = u.rhs(w).reshape(u.nvar, u.N, -1)
+    Lt = t.rhs(w.reshape(u.nvar, u.N, -1))
+    _close(Lt, Lu, 1e-14)
+    assert t.max_dt(w.reshape(u.nvar, u.N, -1)) == pytest.approx(u.max_dt(w), rel=1e-15)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_split_tree_is_the_fine_grid(k):
+    """Every base cell split once: the uniform grid of twice the resolution."""
+    wl = _wl(k=k)
+    fine = dict(wl, n=(12, 10, 1))
+    u = oracle.Oracle(fine)
+    w = u.initial_state()
+    t = oracle.TreeOracle(wl, _grid_leaves((6, 5), 1))
+    wt = w.reshape(u.nvar, u.N, -1)
+    _close(t.rhs(wt), u.rhs(w).reshape(u.nvar, u.N, -1), 1e-14)
+    assert t.max_dt(wt) == pytest.approx(u.max_dt(w), rel=1e-15)
+    coarse = oracle.TreeOracle(wl, _grid_leaves((6, 5), 0))
+    wc = oracle.Oracle(wl).initial_state().reshape(u.nvar, u.N, -1)
+    assert coarse.max_dt(wc) > t.max_dt(wt)
+
+
+@pytest.mark.parametrize("k,bc", [(1, (0, 0, 0)), (2, (0, 0, 0)), (3, (1, 0, 0)), (2, (1, 1, 0))])
+def test_box_shaped_tree_is_the_refined_box(k, bc):
+    n, lo, hi = (8, 6), (2, 1), (5, 4)
+    wl = _wl(n=n, k=k, bc=bc, refine_lo=(lo[0], lo[1], 0), refine_hi=(hi[0], hi[1], 1))
+    box = oracle.AmrOracle(wl)
+    w = box.initial_state()
+    wc, wf = box.blocks(w)
+    leaves, cols = [], []
+    for c in range(box.ncoarse):
+        x, y = c % n[0], c // n[0]
+        if not box.hole[c]:
+            leaves.append((0, x, y)); cols.append(("c", c))
+    nfx = box.nf[0]
+    for f in range(box.nfine):
+        fx, fy = f % nfx, f // nfx
+        leaves.append((1, 2 * lo[0] + fx, 2 * lo[1] + fy)); cols.append(("f", f))
+    wt = np.stack([wc[:, :, i] if b == "c" else wf[:, :, i] for b, i in cols], axis=2)
+    t = oracle.TreeOracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)), np.array(leaves))
+    Lc, Lf = box.blocks(box.rhs(w))
+    Lb = np.stack([Lc[:, :, i] if b == "c" else Lf[:, :, i] for b, i in cols], axis=2)
+    _close(t.rhs(wt), Lb, 1e-14)
+    assert t.max_dt(wt) == pytest.approx(box.max_dt(w), rel=1e-15)
+
+
+@pytest.mark.parametrize("seed,k", [(3, 1), (11, 2), (5, 3)])
+def test_random_tree_conserves_and_keeps_free_stream(seed, k):
+    n = (4, 4)
+    wl = _wl(n=n, k=k)
+    leaves = workloads.random_tree(n, 3, 0.45, seed)
+    assert leaves[:, 0].max() == 3
+    t = oracle.TreeOracle(wl, leaves)
+    w = t.initial_state()
+    L = t.rhs(w)
+    area = (wl["length"][0] / n[0] / 2.0 ** leaves[:, 0]) ** 2
+    total = (L[:, 0, :] * area).sum(axis=1)
+    scale = (np.abs(L[:, 0, :]) * area).sum(axis=1)
+    assert np.all(np.abs(total) <= 1e-13 * scale), total / scale
+    # a constant state: every trace equals it, fluxes cancel, V is zero
+    wc = np.zeros_like(w)
+    wc[:, 0, :] = np.array([1.3, 0.4, -0.7, 3.1])[:, None]
+    assert np.abs(t.rhs(wc)).max() <= 1e-12
+
+
+def test_tree_rejects_gaps_and_overlaps():
+    wl = _wl(n=(2, 2))
+    good = _grid_leaves((2, 2), 0)
+    with pytest.raises(RuntimeError):
+        oracle.TreeOracle(wl, good[:3]).rhs(np.zeros((4, 6, 3)))
+    bad = np.concatenate([good, [[1, 0, 0]]])
+    with pytest.raises(RuntimeError):
+        oracle.TreeOracle(wl, bad).rhs(np.zeros((4, 6, 5)))

@@ -266,3 +266,105 @@ def primitives(wl: dict, x, y, z, cell=None, node=None, t: float = 0.0):
         return (zeros + rho0, zeros + vel[0], zeros + vel[1], zeros + vel[2],
                 zeros + p0)
     raise ValueError(f"unknown initial condition {ic!r}")
+
+
+# ---------------------------------------------------------------------------
+# Quadtree leaf sets (2D): seeded synthetic meshes with several refinement
+# levels for the tree path.  A leaf is (level, ix, iy), level 0 the base grid
+# n, a level-l leaf one of the 4^l cells of a base cell.  These are inputs
+# (which cells exist), not the method's refinement logic: the generator refines
+# where a predicate or a seeded coin says so and then splits any leaf whose
+# eight neighbours (faces and corners) are more than one level finer.
+# ---------------------------------------------------------------------------
+
+def _balance(leaves: set, n, periodic=(True, True)) -> set:
+    """Split leaves until every leaf's face and corner neighbours differ from
+    it by at most one level."""
+    leaves = set(leaves)
+
+    def covering(l, x, y):
+        # the leaf containing cell (x, y) of level l, if it is that cell or coarser
+        for m in range(l, -1, -1):
+            key = (m, x >> (l - m), y >> (l - m))
+            if key in leaves:
+                return key
+        return None
+
+    changed = True
+    while changed:
+        changed = False
+        for (l, x, y) in sorted(leaves, key=lambda t: -t[0]):
+            if l < 2 or (l, x, y) not in leaves:
+                continue
+            nx, ny = n[0] << l, n[1] << l
+            for dx in (-1, 0, 1):
+                for dy in (-1, 0, 1):
+                    if dx == 0 and dy == 0:
+                        continue
+                    xx, yy = x + dx, y + dy
+                    if not (0 <= xx < nx):
+                        if not periodic[0]:
+                            continue
+                        xx %= nx
+                    if not (0 <= yy < ny):
+                        if not periodic[1]:
+                            continue
+                        yy %= ny
+                    c = covering(l, xx, yy)
+                    if c is not None and c[0] < l - 1:
+                        leaves.discard(c)
+                        cl, cx, cy = c
+                        for q in range(4):
+                            leaves.add((cl + 1, 2 * cx + (q & 1), 2 * cy + (q >> 1)))
+                        changed = True
+    return leaves
+
+
+def _morton(leaves, lmax):
+    def key(t):
+        l, x, y = t
+        x <<= lmax - l
+        y <<= lmax - l
+        k = 0
+        for b in range(40):
+            k |= ((x >> b) & 1) << (2 * b) | ((y >> b) & 1) << (2 * b + 1)
+        return k
+    return sorted(leaves, key=key)
+
+
+def tree_leaves(n, levels: int, refine, periodic=(True, True)) -> np.ndarray:
+    """Leaf array [nleaf][3] of (level, ix, iy) in Morton order: starting from
+    the base grid n (2D), `levels` passes each split the leaves of the current
+    finest level for which refine(level, ix, iy) is true, followed by the
+    one-level balance of faces and corners."""
+    leaves = {(0, x, y) for x in range(n[0]) for y in range(n[1])}
+    for l in range(levels):
+        new = set()
+        for t in leaves:
+            if t[0] == l and refine(*t):
+                new.update((l + 1, 2 * t[1] + (q & 1), 2 * t[2] + (q >> 1)) for q in range(4))
+            else:
+                new.add(t)
+        leaves = _balance(new, n, periodic)
+    lmax = max(t[0] for t in leaves)
+    return np.array(_morton(leaves, lmax), dtype=np.int64).reshape(-1, 3)
+
+
+def random_tree(n, levels: int, frac: float, seed: int, periodic=(True, True)) -> np.ndarray:
+    """Seeded random quadtree: each pass splits a leaf of the finest level with
+    probability `frac` (draw = the leaf's own index on its level)."""
+    def refine(l, x, y):
+        idx = (y * (n[0] << l) + x) + sum((n[0] * n[1]) << (2 * m) for m in range(l))
+        return float(uniform_pm1(seed, idx)) < 2.0 * frac - 1.0
+    return tree_leaves(n, levels, refine, periodic)
+
+
+def band_tree(n, levels: int, y_bands=(0.25, 0.75), width: float = 0.0, length=(1.0, 1.0)) -> np.ndarray:
+    """Quadtree refined around horizontal lines y = y_b (the two shear layers
+    of the KH setup): a leaf is split if its y range comes within `width` of a
+    line."""
+    def refine(l, x, y):
+        h = length[1] / (n[1] << l)
+        y0, y1 = y * h, (y + 1) * h
+        return any(y0 - width <= yb <= y1 + width for yb in y_bands)
+    return tree_leaves(n, levels, refine)
