@@ -18,6 +18,7 @@
  *   - gravity source and step .... Sec. 2.4 (eq. gravity_term), Sec. 2.5
  *   - adaptive refinement ........ Sec. 4.1-4.3 (eqs. cell_ref, node_ref,
  *                                  ref_pa_integral, ref_weights, deref_weights)
+ *   - 2D quadtree meshes ......... Sec. 4 (leaves of any depth, hanging faces)
  * and a hand-written discrete adjoint of the right-hand side and of the
  * SSP-RK3 stages (not part of the paper).
  *
@@ -329,6 +330,65 @@ int dg_adjoint_rhs(dg_ctx *ctx, const double *w, const double *lam, double *mu, 
 int dg_adjoint_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *u,
                         const double *lam, const double *acc, double *lam_out,
                         double *acc_out, void *stream);
+
+/* ---- 2D quadtree meshes (Sec. 4) ------------------------------------------
+ * A tree-based mesh of leaf cells: every cell can be split into four children
+ * at any level (Sec. 4), leaf (level, ix, iy) covering
+ * [x0 + ix h, x0 + (ix+1) h) x [y0 + iy h, y0 + (iy+1) h) with h = dx / 2^level
+ * over the context's base grid (level 0).  Across a face the level jump is
+ * at most one: a side has one neighbour or two finer ones, whose faces are
+ * integrated with the coarse trace at the mapped nodes (eta + sigma)/2 and the
+ * weight w_r / 2 on the coarse side (Sec. 4).  A tree *state* is a device
+ * array [nvar][N][nleaf] in leaf order, same modes as above.  FP64, dim = 2,
+ * k = 1..3, no refined box, no gravity (else DG_EUNSUPPORTED). */
+
+/* Makes `leaves` (host, [nleaf][3] ints: level, ix, iy; any order) the
+ * context's mesh.  DG_EINVAL unless the leaves tile the base grid without
+ * overlap and every face sees a level jump of at most one (periodic axes
+ * wrap).  Builds and uploads the neighbour tables: allocates on growth and
+ * waits for the device to be idle (a mesh change, not a per-step call). */
+int dg_tree_set(dg_ctx *ctx, int64_t nleaf, const int32_t *leaves);
+
+/* Number of leaves of the current mesh, and the leaves themselves (host
+ * [nleaf][3]: level, ix, iy, in the mesh's order). */
+int dg_tree_size(const dg_ctx *ctx, int64_t *nleaf);
+int dg_tree_leaves(const dg_ctx *ctx, int32_t *leaves);
+
+/* dw/dt on every leaf (Sec. 2.4 eqs. dg_term2, dg_term3 with each leaf's own
+ * edge in the factor (2/h) 2^-d; hanging faces as above).  L must not alias w. */
+int dg_tree_rhs(dg_ctx *ctx, const double *w, double *L, void *stream);
+
+/* One SSP-RK3 stage (App. D, table RK_3) on the tree, as dg_rk_stage. */
+int dg_tree_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double *w_n,
+                     const double *w_prev, double *w_out, void *stream);
+
+/* Time step of the tree (Sec. 2.5 eq. time_step with each leaf's own edge):
+ * CFL f_k / max over leaves of sum_a (|v_a| + c)/h into the device scalar. */
+int dg_tree_max_dt(dg_ctx *ctx, const double *w, double *dt_dev, void *stream);
+
+/* Plans the next mesh (Sec. 4.1): on the device, per leaf, the refinement
+ * criterion max_a |w_rho,1+a| > alpha wt (eq. cell_ref) and, for a complete
+ * group of four sibling leaves, whether its node weights (eq. deref_weights)
+ * keep it refined, max_a > wt / alpha (eq. node_ref); then on the host:
+ * flagged leaves below max_level are split together with the neighbour
+ * leaves of the same or a coarser level among their eight face and corner
+ * neighbours (the buffer layer of Sec. 4); splits propagate to coarser face
+ * and corner neighbours until every jump is at most one; a complete group of
+ * unsplit siblings that fails eq. node_ref and has no finer face or corner
+ * neighbour is merged.  New leaves are in Morton order of their lower-left
+ * corners.  Synchronises `stream`; *nleaf_new receives the new count: the
+ * caller allocates the new state and calls dg_tree_regrid.  The paper's
+ * values are wt = 0.01, alpha = 1.1.  DG_EINVAL for wt <= 0, alpha < 1 or
+ * max_level outside 0..24. */
+int dg_tree_adapt(dg_ctx *ctx, const double *w, double wt, double alpha, int max_level,
+                  int64_t *nleaf_new, void *stream);
+
+/* Moves the state onto the mesh planned by dg_tree_adapt and makes that mesh
+ * current: kept leaves are copied, children of a split leaf are the L2
+ * projections of its polynomial (Sec. 4.2 eq. ref_weights), a merged group
+ * becomes the projection of its four children (Sec. 4.3 eq. deref_weights).
+ * w_new ([nvar][N][nleaf_new]) must not alias w_old.  Synchronises. */
+int dg_tree_regrid(dg_ctx *ctx, const double *w_old, double *w_new, void *stream);
 
 /* Synchronises `stream`, returns the sticky device flag (DG_OK,
  * DG_ENEGATIVE or DG_ENAN) and clears it. */

@@ -118,6 +118,7 @@ def _load():
             "orc_amr_flags": [cp, dp, C.c_double, C.c_double, ip],
             "orc_amr_regrid": [cp, dp, cp, dp],
             "orc_tree_rhs": [cp, C.c_long, ip, lp, lp, dp, dp],
+            "orc_tree_terms": [cp, C.c_long, ip, lp, lp, dp, dp, dp, dp],
             "orc_tree_max_dt": [cp, C.c_long, ip, lp, lp, dp, dp],
             "orc_tree_node_coords": [cp, C.c_long, ip, lp, lp, dp],
             "orc_tree_project": [cp, C.c_long, ip, lp, lp, dp, dp],
@@ -731,6 +732,14 @@ class TreeOracle(Oracle):
         _check(lib.orc_tree_rhs(*self._a(), self._s(w), L), "tree_rhs")
         return L
 
+    def terms(self, w: np.ndarray):
+        """(fac V, fac S, fac A) of every leaf, each [nvar][N][nleaf] (L = V - S;
+        A the summed magnitudes of the summands)."""
+        lib, _ = _load()
+        V, S, A = np.zeros(self.shape), np.zeros(self.shape), np.zeros(self.shape)
+        _check(lib.orc_tree_terms(*self._a(), self._s(w), V, S, A), "tree_terms")
+        return V, S, A
+
     def max_dt(self, w: np.ndarray) -> float:
         lib, _ = _load()
         dt = np.zeros(1)
@@ -747,3 +756,139 @@ class TreeOracle(Oracle):
         w1 = self.rk3_stage(1, dt, w0, w0)
         w2 = self.rk3_stage(2, dt, w0, w1)
         return self.rk3_stage(3, dt, w0, w2), dt
+
+
+def _tree_refine_mats(wl: dict):
+    """P_c (eq. ref_pa_integral) of the 4 children, each [N][N] with
+    (P_c)[j][l] the weight of coarse mode l in child mode j."""
+    lib, _ = _load()
+    o = Oracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)))
+    P = []
+    for ch in range(4):
+        m = np.zeros(o.N * o.N)
+        _check(lib.orc_refine_matrix(C.byref(o.c), ch, m), "refine_matrix")
+        P.append(m.reshape(o.N, o.N))
+    return P
+
+
+def tree_adapt(wl: dict, leaves, w, wt: float = 0.01, alpha: float = 1.1, max_level: int = 3):
+    """One adaptation of a 2D quadtree (Sec. 4, 4.1-4.3): returns (new leaves
+    [n][3] in Morton order of their lower-left corners, new state
+    [nvar][N][n]).  Steps, in this order:
+      1. a leaf is flagged if max_a |w_rho,1+a| > alpha wt (eq. cell_ref); a
+         flagged leaf below max_level is split, and so is every leaf of the
+         same or a coarser level (below max_level) that covers one of the
+         eight cells around it on its level (one buffer layer);
+      2. a split leaf forces the split of any coarser leaf covering one of the
+         eight cells around it on its level (level jump at most one to face and
+         corner neighbours), repeated until nothing changes;
+      3. four sibling leaves (all leaves, none split) whose node weights
+         2^-d sum_c P_c^T w^c (eq. deref_weights) have max_a |w_rho,1+a| <=
+         wt / alpha (eq. node_ref fails) are merged when no cell around any of
+         them on their level is finer than them after step 2; all such merges
+         at once.
+    Split leaves' children get P_c w (eq. ref_weights), merged groups the
+    node weights, other leaves keep their weights."""
+    lv = [tuple(int(v) for v in t) for t in np.asarray(leaves).reshape(-1, 3)]
+    w = np.asarray(w, dtype=np.float64)
+    nvar, N, nl = w.shape
+    n = wl["n"]
+    bc = wl.get("bc", (0, 0, 0))
+    where = {t: i for i, t in enumerate(lv)}
+    P = _tree_refine_mats(wl)
+
+    def wrap(l, x, y):
+        nx, ny = n[0] << l, n[1] << l
+        if not 0 <= x < nx:
+            if bc[0] != 0:
+                return None
+            x %= nx
+        if not 0 <= y < ny:
+            if bc[1] != 0:
+                return None
+            y %= ny
+        return x, y
+
+    def covering(l, x, y):
+        for q in range(l, -1, -1):
+            j = where.get((q, x >> (l - q), y >> (l - q)))
+            if j is not None:
+                return j
+        return None
+
+    def around(i):
+        l, x, y = lv[i]
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                if dx or dy:
+                    p = wrap(l, x + dx, y + dy)
+                    if p is not None:
+                        yield l, p[0], p[1]
+
+    flag = [max(abs(w[0, 1, i]), abs(w[0, 2, i])) > alpha * wt for i in range(nl)]
+    split = [False] * nl
+    for i in range(nl):
+        if flag[i] and lv[i][0] < max_level:
+            split[i] = True
+            for c in around(i):
+                j = covering(*c)
+                if j is not None and lv[j][0] < max_level:
+                    split[j] = True
+    changed = True
+    while changed:
+        changed = False
+        for i in range(nl):
+            if not split[i]:
+                continue
+            for c in around(i):
+                j = covering(*c)
+                if j is not None and lv[j][0] < lv[i][0] and not split[j]:
+                    split[j] = True
+                    changed = True
+
+    def level_after(l, x, y):
+        j = covering(l, x, y)
+        return l + 1 if j is None else lv[j][0] + int(split[j])
+
+    groups = {}
+    for i, (l, x, y) in enumerate(lv):
+        if l < 1:
+            continue
+        sib = [where.get((l, 2 * (x >> 1) + (c & 1), 2 * (y >> 1) + (c >> 1))) for c in range(4)]
+        if all(s is not None for s in sib) and sib[0] == i:
+            groups[i] = sib
+    merged = {}
+    for i0, sib in groups.items():
+        node = sum(P[c].T @ w[:, :, sib[c]].T for c in range(4)).T / 4.0  # [nvar][N]
+        if max(abs(node[0, 1]), abs(node[0, 2])) > wt / alpha:
+            continue
+        if any(split[m] for m in sib):
+            continue
+        l = lv[i0][0]
+        if any(level_after(*c) > l for m in sib for c in around(m)):
+            continue
+        merged[i0] = (sib, node)
+    members = {m for sib, _ in merged.values() for m in sib}
+    new = []  # (leaf, state [nvar][N])
+    for i, (l, x, y) in enumerate(lv):
+        if split[i]:
+            for c in range(4):
+                new.append(((l + 1, 2 * x + (c & 1), 2 * y + (c >> 1)), (P[c] @ w[:, :, i].T).T))
+        elif i in merged:
+            new.append(((l - 1, x >> 1, y >> 1), merged[i][1]))
+        elif i not in members:
+            new.append(((l, x, y), w[:, :, i]))
+    L = max(t[0][0] for t in new)
+
+    def morton(t):
+        l, x, y = t[0]
+        x <<= L - l
+        y <<= L - l
+        k = 0
+        for b in range(60):
+            k |= ((x >> b) & 1) << (2 * b) | ((y >> b) & 1) << (2 * b + 1)
+        return k
+    new.sort(key=morton)
+    out_l = np.array([t[0] for t in new], dtype=np.int64)
+    out_w = np.ascontiguousarray(np.stack([t[1] for t in new], axis=2))
+    return out_l, out_w

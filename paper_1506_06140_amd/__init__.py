@@ -67,6 +67,8 @@ EXPORTS = (
     "dg_init", "dg_state_size", "dg_sizes", "dg_amr_sizes", "dg_quadrature", "dg_project", "dg_rhs", "dg_rhs_noalloc",
     "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
     "dg_set_gravity", "dg_amr_flags", "dg_amr_regrid", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
+    "dg_tree_set", "dg_tree_size", "dg_tree_leaves", "dg_tree_rhs", "dg_tree_rk_stage", "dg_tree_max_dt",
+    "dg_tree_adapt", "dg_tree_regrid",
 )
 
 _lib = None
@@ -104,6 +106,15 @@ def load_library(path: str = LIB_PATH):
     lib.dg_adjoint_rhs.argtypes = [ctxp, dp, dp, dp, vp]
     lib.dg_adjoint_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, dp, dp, vp]
     lib.dg_status.argtypes = [ctxp, vp]
+    ip32 = C.POINTER(C.c_int32)
+    lib.dg_tree_set.argtypes = [ctxp, C.c_int64, ip32]
+    lib.dg_tree_size.argtypes = [ctxp, C.POINTER(C.c_int64)]
+    lib.dg_tree_leaves.argtypes = [ctxp, ip32]
+    lib.dg_tree_rhs.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_tree_rk_stage.argtypes = [ctxp, C.c_int, dp, dp, dp, dp, vp]
+    lib.dg_tree_max_dt.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_tree_adapt.argtypes = [ctxp, dp, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int64), vp]
+    lib.dg_tree_regrid.argtypes = [ctxp, dp, dp, vp]
     lib.dg_destroy.argtypes = [ctxp]
     lib.dg_destroy.restype = None
     lib.dg_strerror.argtypes = [C.c_int]
@@ -425,3 +436,71 @@ class Solver:
         if self.limited:
             self.limit(u3, stream)
         return u3
+
+
+class TreeSolver(Solver):
+    """A 2D run on a quadtree of leaves (Sec. 4) over the workload's base
+    grid: `leaves` is an integer array [nleaf][3] of (level, ix, iy).  States
+    are device tensors [nvar][N][nleaf] in the mesh's leaf order (after an
+    adaptation, the Morton order the library chose: see `leaves`)."""
+
+    def __init__(self, wl: dict, leaves):
+        if wl["dim"] != 2:
+            raise ValueError("quadtree meshes are 2D")
+        super().__init__(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)))
+        self.set_leaves(leaves)
+
+    def set_leaves(self, leaves):
+        lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 3))
+        _check(self.lib.dg_tree_set(self.ctx, lv.shape[0], lv.ctypes.data_as(C.POINTER(C.c_int32))), "dg_tree_set")
+        self._sync_leaves()
+
+    def _sync_leaves(self):
+        n = C.c_int64()
+        _check(self.lib.dg_tree_size(self.ctx, C.byref(n)), "dg_tree_size")
+        lv = np.zeros((n.value, 3), dtype=np.int32)
+        _check(self.lib.dg_tree_leaves(self.ctx, lv.ctypes.data_as(C.POINTER(C.c_int32))), "dg_tree_leaves")
+        self.leaves = lv.astype(np.int64)
+        self.nleaf = n.value
+        self.shape = (self.nvar, self.N, self.nleaf)
+        self.size = self.nvar * self.N * self.nleaf
+
+    def rhs(self, w, out=None, stream=None):
+        out = self.empty() if out is None else out
+        _check(self.lib.dg_tree_rhs(self.ctx, self._s(w), self._s(out), _stream(stream)), "dg_tree_rhs")
+        return out
+
+    def max_dt(self, w, dt=None, stream=None):
+        dt = self.scalar() if dt is None else dt
+        _check(self.lib.dg_tree_max_dt(self.ctx, self._s(w), _ptr(dt, 1), _stream(stream)), "dg_tree_max_dt")
+        return dt
+
+    def rk_stage(self, stage, dt, wn, wp, out=None, stream=None):
+        out = self.empty() if out is None else out
+        wn_p = self._s(wn) if wn is not None else None
+        _check(self.lib.dg_tree_rk_stage(self.ctx, stage, _ptr(dt, 1), wn_p, self._s(wp), self._s(out),
+                                         _stream(stream)), "dg_tree_rk_stage")
+        return out
+
+    def step(self, w, bufs, dt=None, stream=None):
+        """One SSP-RK3 step from w into bufs[2] (bufs[0..1] stage buffers,
+        bufs[3] the time step when dt is None)."""
+        if dt is None:
+            dt = self.max_dt(w, bufs[3], stream)
+        self.rk_stage(1, dt, None, w, bufs[0], stream)
+        self.rk_stage(2, dt, w, bufs[0], bufs[1], stream)
+        self.rk_stage(3, dt, w, bufs[1], bufs[2], stream)
+        return bufs[2]
+
+    def adapt(self, w, wt=0.01, alpha=1.1, max_level=3, stream=None):
+        """Plans the next mesh from w and moves w onto it (Sec. 4.1-4.3);
+        returns the new state tensor (the mesh in `leaves` is updated)."""
+        import torch
+        n = C.c_int64()
+        _check(self.lib.dg_tree_adapt(self.ctx, self._s(w), wt, alpha, max_level, C.byref(n), _stream(stream)),
+               "dg_tree_adapt")
+        out = torch.empty((self.nvar, self.N, n.value), dtype=torch.float64, device="cuda")
+        _check(self.lib.dg_tree_regrid(self.ctx, self._s(w), _ptr(out, self.nvar * self.N * n.value),
+                                       _stream(stream)), "dg_tree_regrid")
+        self._sync_leaves()
+        return out

@@ -95,4 +95,12 @@ struct dg_ctx {
   // for k = 4 on grids with fewer 16x8 tiles than CUs), 0 always the large
   // tiles, 1 always 8x8 (dg_config.tile2d)
   int tile_small = -1;
+  // 2D quadtree mesh (dg_tree_set): the leaves (level, ix, iy) on the host,
+  // their device tables (level, face kinds, neighbours, sibling groups), and
+  // the next mesh of dg_tree_adapt with its regrid map until dg_tree_regrid
+  bool tree = false;
+  std::vector<int32_t> tleaves, tnext;
+  std::vector<int> trk, tsrc;
+  int *ttab = nullptr, *tmap = nullptr, *tflags = nullptr;
+  long ttab_cap = 0, tmap_cap = 0, tflags_cap = 0;
 };

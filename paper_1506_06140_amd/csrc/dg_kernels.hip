@@ -21,6 +21,10 @@
 #include <cstdlib>
 #include <new>
 #include <type_traits>
+#include <algorithm>
+#include <unordered_map>
+#include <utility>
+#include <vector>
 
 #include "dg_internal.h"
 
@@ -3779,6 +3783,219 @@ __global__ __launch_bounds__(256) void k_positivity(const double *__restrict__ t
 }  // namespace dg
 
 // ===========================================================================
+// Quadtree meshes in 2D (Sec. 4): leaves of any level, the level jump across
+// a face and a corner at most one.  One thread per leaf, FP64.  The leaf
+// tables (built on the host by dg_tree_set) give per leaf its level and per
+// side (a, s) the face kind: 0 one neighbour of the same level, 1 a
+// transmissive wall, 2 two finer neighbours (this leaf is the coarse side:
+// its trace at the mapped points (eta + sigma)/2 of each half, lifted with
+// w_r / 2), 3 one coarser neighbour (whose trace is taken at this leaf's
+// half of its face, `sub`).  Both leaves of a face form the traces from the
+// same weights and tables in the same order, so they obtain the same flux.
+// ===========================================================================
+namespace dg {
+
+struct TreeGrid {
+  long nleaf;
+  const int *lev;   // [nleaf]
+  const int *info;  // [4][nleaf]: kind | sub << 2, side 2a + s
+  const int *nb;    // [8][nleaf]: neighbour (2 side + half)
+  const int *grp;   // [4][nleaf]: the four leaves of this leaf's sibling group (child order), or -1
+  double fac0;      // (2/dx) 2^-d of level 0
+  double dx0;
+  double gamma;
+};
+
+template <int K, int FX>
+__global__ __launch_bounds__(256) void k_rhs_tree(const double *__restrict__ tab, const double *__restrict__ w,
+                                                  double *__restrict__ out, const double *__restrict__ dtp,
+                                                  TreeGrid g, int mode, Mix mx, int *__restrict__ flag) {
+  using C = Cfg<2, K>;
+  constexpr int NV = C::NV, N = C::N, QF = C::QF;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.nleaf) return;
+  const long nl = g.nleaf;
+  const double gm1 = g.gamma - 1.0;
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
+  double wc[NV][N], acc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      wc[v][l] = w[(long)(v * N + l) * nl + cell];
+      acc[v][l] = 0.0;
+    }
+  // volume integral (eq. dg_term2); the mean's gradient is zero
+#pragma unroll 1
+  for (int q = 0; q < C::Q; ++q) {
+    double U[NV];
+    const double *bq = tab + C::B + q * N;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < N; ++l) s = fma(wc[v][l], bq[l], s);
+      U[v] = s;
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double F[NV];
+      euler_flux<2, double>(U, a, gm1, F);
+      const double *dw = tab + C::DW + (a * C::Q + q) * N;
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 1; l < N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+    }
+  }
+  // face integrals (eq. dg_term3) over the sides' halves
+#pragma unroll 1
+  for (int side = 0; side < 4; ++side) {
+    const int a = side >> 1, s = side & 1;
+    const int inf = g.info[(long)side * nl + cell];
+    const int kind = inf & 3, sub = inf >> 2;
+    const int nsub = (kind == 2) ? 2 : 1;
+#pragma unroll 1
+    for (int sb = 0; sb < nsub; ++sb) {
+      const long nbc = (kind == 1) ? cell : (long)g.nb[(long)(2 * side + sb) * nl + cell];
+      const int hs = (kind == 2) ? sb : sub;
+      double wnb[NV][N];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int l = 0; l < N; ++l) wnb[v][l] = w[(long)(v * N + l) * nl + nbc];
+      const double *to = (kind == 2) ? tab + C::HG + ((a * 2 + s) * 4 + hs) * QF * N : tab + C::TF + (a * 2 + s) * QF * N;
+      const double *tn = (kind == 3) ? tab + C::HG + ((a * 2 + (1 - s)) * 4 + hs) * QF * N
+                                     : tab + C::TF + (a * 2 + (1 - s)) * QF * N;
+      const double *tw = (kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + hs) * QF * N : tab + C::TW + (a * 2 + s) * QF * N;
+#pragma unroll 1
+      for (int r = 0; r < QF; ++r) {
+        double UL[NV], UR[NV], F[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          double so = 0.0, sn = 0.0;
+#pragma unroll
+          for (int l = 0; l < N; ++l) {
+            so = fma(wc[v][l], to[r * N + l], so);
+            sn = fma(wnb[v][l], tn[r * N + l], sn);
+          }
+          const double un = (kind == 1) ? so : sn;
+          UL[v] = s ? so : un;
+          UR[v] = s ? un : so;
+        }
+        hllc<double, 2, FX>(UL, UR, a, g.gamma, F);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const double f = s ? -F[v] : F[v];
+#pragma unroll
+          for (int l = 0; l < N; ++l) acc[v][l] = fma(f, tw[r * N + l], acc[v][l]);
+        }
+      }
+    }
+  }
+  const double fac = g.fac0 * (double)(1 << g.lev[cell]);
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) {
+      const long ii = (long)(v * N + l) * nl + cell;
+      const double L = fac * acc[v][l];
+      bad |= (L != L);
+      out[ii] = (mode == 0) ? L : mix_out(mx, w[ii], L, cldt, ii);
+    }
+  if (bad) atomicOr(flag, FLAG_NAN);
+}
+
+// largest signal rate of the leaves' means with each leaf's own edge
+__global__ __launch_bounds__(256) void k_rate_tree(const double *__restrict__ w, TreeGrid g, int N,
+                                                   unsigned long long *ratemax, int *__restrict__ flag) {
+  double m = 0.0;
+  bool bad = false;
+  for (long cell = (long)blockIdx.x * blockDim.x + threadIdx.x; cell < g.nleaf; cell += (long)gridDim.x * blockDim.x) {
+    double U[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) U[v] = w[(long)v * N * g.nleaf + cell];
+    m = fmax(m, cell_rate<2>(U, g.gamma, g.dx0 / (double)(1 << g.lev[cell]), bad));
+  }
+  if (bad) atomicOr(flag, FLAG_NEGATIVE);
+  m = block_max(m);
+  if (threadIdx.x == 0) atomicMax(rate_slot(ratemax, blockIdx.x), (unsigned long long)__double_as_longlong(m));
+}
+
+// Refinement criterion per leaf (Sec. 4.1): bit 0 if max_a |w_rho,1+a| >
+// thr_cell (eq. cell_ref); bit 1 if the node weights of the leaf's sibling
+// group, 2^-d sum_c P_c^T w^c (eq. deref_weights), satisfy max_a > thr_node
+// (eq. node_ref); bit 2 if the four siblings are all leaves.
+template <int K>
+__global__ __launch_bounds__(256) void k_tree_flags(const double *__restrict__ w, const double *__restrict__ P,
+                                                    TreeGrid g, double thr_cell, double thr_node,
+                                                    int *__restrict__ flags) {
+  constexpr int N = Cfg<2, K>::N;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.nleaf) return;
+  const long nl = g.nleaf;
+  double m = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) m = fmax(m, fabs(w[(long)(1 + a) * nl + cell]));
+  int f = m > thr_cell ? 1 : 0;
+  if (g.grp[cell] >= 0) {
+    f |= 4;
+    double mn = 0.0;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double node = 0.0;
+      for (int ch = 0; ch < 4; ++ch) {
+        const long s = g.grp[(long)ch * nl + cell];
+        for (int l = 0; l < N; ++l) node = fma(P[((long)ch * N + l) * N + 1 + a], w[(long)l * nl + s], node);
+      }
+      mn = fmax(mn, fabs(node / 4.0));
+    }
+    if (mn > thr_node) f |= 2;
+  }
+  flags[cell] = f;
+}
+
+// New state after an adaptation (Sec. 4.2, 4.3): per new leaf rk = kind |
+// child << 2 with kind 0 a copy of old leaf src[0], 1 child `child` of old
+// leaf src[0] (eq. ref_weights, w^c = P_c w), 2 the merge of the old leaves
+// src[0..3] in child order (eq. deref_weights, 2^-d sum_c P_c^T w^c).
+template <int K>
+__global__ __launch_bounds__(256) void k_tree_regrid(const double *__restrict__ wa, long na,
+                                                     const double *__restrict__ P, const int *__restrict__ rk,
+                                                     const int *__restrict__ src, double *__restrict__ wb, long nb) {
+  constexpr int NV = 4, N = Cfg<2, K>::N;
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  const int kind = rk[i] & 3, ch = rk[i] >> 2;
+  const long s0 = src[i];
+  if (kind == 0) {
+    for (int vl = 0; vl < NV * N; ++vl) wb[(long)vl * nb + i] = wa[(long)vl * na + s0];
+  } else if (kind == 1) {
+    for (int v = 0; v < NV; ++v)
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+        for (int l = 0; l < N; ++l) acc = fma(P[((long)ch * N + j) * N + l], wa[(long)(v * N + l) * na + s0], acc);
+        wb[(long)(v * N + j) * nb + i] = acc;
+      }
+  } else {
+    long sc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sc[c] = src[(long)c * nb + i];
+    for (int v = 0; v < NV; ++v)
+      for (int j = 0; j < N; ++j) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          for (int l = 0; l < N; ++l) acc = fma(P[((long)c * N + l) * N + j], wa[(long)(v * N + l) * na + sc[c]], acc);
+        wb[(long)(v * N + j) * nb + i] = acc / 4.0;
+      }
+  }
+}
+
+}  // namespace dg
+
+// ===========================================================================
 // C ABI
 // ===========================================================================
 
@@ -4735,6 +4952,9 @@ void dg_destroy(dg_ctx *c) {
   if (c->tabmf32) (void)hipFree(c->tabmf32);
   if (c->tablw) (void)hipFree(c->tablw);
   if (c->tabvb) (void)hipFree(c->tabvb);
+  if (c->ttab) (void)hipFree(c->ttab);
+  if (c->tmap) (void)hipFree(c->tmap);
+  if (c->tflags) (void)hipFree(c->tflags);
   delete c;
 }
 
@@ -4997,6 +5217,439 @@ int dg_status(dg_ctx *c, void *stream) {
   if (f & dg::FLAG_NEGATIVE) return DG_ENEGATIVE;
   if (f & dg::FLAG_NAN) return DG_ENAN;
   return DG_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Quadtree meshes (host side): leaf tables, adaptation, C ABI
+// ===========================================================================
+namespace {
+
+inline uint64_t tkey(int l, long x, long y) { return ((uint64_t)l << 58) | ((uint64_t)x << 29) | (uint64_t)y; }
+
+constexpr int kTreeInts = 17;  // per leaf: level, 4 face infos, 8 neighbours, 4 group members
+
+struct TreeIndex {
+  std::unordered_map<uint64_t, int> m;
+  long nx = 0, ny = 0;
+  int bc[2] = {0, 0};
+  // level-l cell (x, y) wrapped onto the periodic domain; false outside a wall
+  bool wrap(int l, long &x, long &y) const {
+    const long nxl = nx << l, nyl = ny << l;
+    if (x < 0 || x >= nxl) {
+      if (bc[0] != DG_BC_PERIODIC) return false;
+      x = ((x % nxl) + nxl) % nxl;
+    }
+    if (y < 0 || y >= nyl) {
+      if (bc[1] != DG_BC_PERIODIC) return false;
+      y = ((y % nyl) + nyl) % nyl;
+    }
+    return true;
+  }
+  int find(int l, long x, long y) const {
+    auto it = m.find(tkey(l, x, y));
+    return it == m.end() ? -1 : it->second;
+  }
+  // the leaf that covers level-l cell (x, y) if it is that cell or coarser, else -1
+  int covering(int l, long x, long y) const {
+    for (int q = l; q >= 0; --q) {
+      const int j = find(q, x >> (l - q), y >> (l - q));
+      if (j >= 0) return j;
+    }
+    return -1;
+  }
+};
+
+// Validates a leaf set (a tiling of the base grid, the level jump across every
+// face at most one) and builds its device tables: level [nl], face info
+// [4][nl] (kind | sub << 2), neighbours [8][nl], sibling groups [4][nl].
+int tree_tables(const dg_ctx *c, const std::vector<int32_t> &lv, TreeIndex &ix, std::vector<int> &T) {
+  const long nl = (long)lv.size() / 3;
+  if (nl < 1 || nl > (1L << 30)) return DG_EINVAL;
+  ix.m.clear();
+  ix.m.reserve((size_t)nl * 2);
+  ix.nx = c->nx;
+  ix.ny = c->ny;
+  ix.bc[0] = c->cfg.bc[0];
+  ix.bc[1] = c->cfg.bc[1];
+  int L = 0;
+  for (long i = 0; i < nl; ++i) {
+    const int l = lv[3 * i];
+    const long x = lv[3 * i + 1], y = lv[3 * i + 2];
+    if (l < 0 || l > 24 || (c->nx << l) >= (1L << 29) || (c->ny << l) >= (1L << 29)) return DG_EINVAL;
+    if (x < 0 || y < 0 || x >= (c->nx << l) || y >= (c->ny << l)) return DG_EINVAL;
+    if (!ix.m.emplace(tkey(l, x, y), (int)i).second) return DG_EINVAL;
+    L = l > L ? l : L;
+  }
+  unsigned __int128 area = 0;
+  for (long i = 0; i < nl; ++i) {
+    const int l = lv[3 * i];
+    for (int q = 0; q < l; ++q)  // no leaf inside another
+      if (ix.find(q, lv[3 * i + 1] >> (l - q), lv[3 * i + 2] >> (l - q)) >= 0) return DG_EINVAL;
+    area += (unsigned __int128)1 << (2 * (L - l));
+  }
+  if (area != ((unsigned __int128)(c->nx * c->ny) << (2 * L))) return DG_EINVAL;
+  T.assign((size_t)kTreeInts * nl, -1);
+  int *lev = T.data(), *info = lev + nl, *nb = info + 4 * nl, *grp = nb + 8 * nl;
+  for (long i = 0; i < nl; ++i) {
+    const int l = lv[3 * i];
+    const long x = lv[3 * i + 1], y = lv[3 * i + 2];
+    lev[i] = l;
+    for (int side = 0; side < 4; ++side) {
+      const int a = side >> 1, s = side & 1;
+      long X = x + (a == 0 ? (s ? 1 : -1) : 0), Y = y + (a == 1 ? (s ? 1 : -1) : 0);
+      int kind, sub = 0, n0 = -1, n1 = -1;
+      if (!ix.wrap(l, X, Y)) {
+        kind = 1;
+      } else if ((n0 = ix.find(l, X, Y)) >= 0) {
+        kind = 0;
+      } else if (l > 0 && (n0 = ix.find(l - 1, X >> 1, Y >> 1)) >= 0) {
+        kind = 3;
+        sub = (int)((a == 0 ? y : x) & 1);
+      } else {
+        kind = 2;
+        // the two children of the same-level neighbour that touch this face
+        const long cx = 2 * X + (a == 0 ? (s ? 0 : 1) : 0), cy = 2 * Y + (a == 1 ? (s ? 0 : 1) : 0);
+        n0 = ix.find(l + 1, cx, cy);
+        n1 = ix.find(l + 1, cx + (a == 0 ? 0 : 1), cy + (a == 0 ? 1 : 0));
+        if (n0 < 0 || n1 < 0) return DG_EINVAL;  // a level jump above one
+      }
+      info[(long)side * nl + i] = kind | (sub << 2);
+      nb[(long)(2 * side) * nl + i] = n0;
+      nb[(long)(2 * side + 1) * nl + i] = n1;
+    }
+    if (l > 0) {
+      int g[4];
+      bool all = true;
+      for (int ch = 0; ch < 4; ++ch) {
+        g[ch] = ix.find(l, 2 * (x >> 1) + (ch & 1), 2 * (y >> 1) + (ch >> 1));
+        all &= g[ch] >= 0;
+      }
+      if (all)
+        for (int ch = 0; ch < 4; ++ch) grp[(long)ch * nl + i] = g[ch];
+    }
+  }
+  return DG_OK;
+}
+
+dg::TreeGrid make_tree_grid(const dg_ctx *c) {
+  dg::TreeGrid g;
+  g.nleaf = (long)c->tleaves.size() / 3;
+  g.lev = c->ttab;
+  g.info = c->ttab + g.nleaf;
+  g.nb = c->ttab + 5 * g.nleaf;
+  g.grp = c->ttab + 13 * g.nleaf;
+  g.fac0 = 2.0 / c->dx / 4.0;
+  g.dx0 = c->dx;
+  g.gamma = c->cfg.gamma;
+  return g;
+}
+
+// grow a device int buffer to at least n ints
+int grow_ints(int *&p, long &cap, long n) {
+  if (n <= cap) return DG_OK;
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  cap = 0;
+  HIP_TRY(hipMalloc((void **)&p, (size_t)n * sizeof(int)));
+  cap = n;
+  return DG_OK;
+}
+
+// makes `lv` the context's mesh (device tables replaced after the device is idle)
+int tree_install(dg_ctx *c, std::vector<int32_t> lv) {
+  TreeIndex ix;
+  std::vector<int> T;
+  int st = tree_tables(c, lv, ix, T);
+  if (st != DG_OK) return st;
+  HIP_TRY(hipDeviceSynchronize());
+  st = grow_ints(c->ttab, c->ttab_cap, (long)T.size());
+  if (st != DG_OK) return st;
+  HIP_TRY(hipMemcpy(c->ttab, T.data(), T.size() * sizeof(int), hipMemcpyHostToDevice));
+  c->tleaves = std::move(lv);
+  c->tree = true;
+  c->tnext.clear();
+  return DG_OK;
+}
+
+// Morton order of the leaves' lower-left corners on the finest level
+void tree_sort(std::vector<int32_t> &lv, std::vector<int> *perm_src = nullptr) {
+  const long nl = (long)lv.size() / 3;
+  int L = 0;
+  for (long i = 0; i < nl; ++i) L = lv[3 * i] > L ? lv[3 * i] : L;
+  std::vector<std::pair<unsigned __int128, long>> keys((size_t)nl);
+  for (long i = 0; i < nl; ++i) {
+    const uint64_t x = (uint64_t)lv[3 * i + 1] << (L - lv[3 * i]), y = (uint64_t)lv[3 * i + 2] << (L - lv[3 * i]);
+    unsigned __int128 k = 0;
+    for (int b = 0; b < 60; ++b)
+      k |= ((unsigned __int128)((x >> b) & 1) << (2 * b)) | ((unsigned __int128)((y >> b) & 1) << (2 * b + 1));
+    keys[(size_t)i] = {k, i};
+  }
+  std::sort(keys.begin(), keys.end());
+  std::vector<int32_t> out(lv.size());
+  std::vector<int> ps;
+  for (long j = 0; j < nl; ++j) {
+    const long i = keys[(size_t)j].second;
+    for (int e = 0; e < 3; ++e) out[3 * j + e] = lv[3 * i + e];
+    ps.push_back((int)i);
+  }
+  lv.swap(out);
+  if (perm_src) *perm_src = ps;
+}
+
+// The next mesh from the current leaves and their flags (k_tree_flags):
+//  1. leaves flagged by eq. cell_ref below max_level are split, and with them
+//     the leaves of the same or a coarser level among the eight neighbour
+//     cells of each flagged leaf (the one buffer layer of Sec. 4);
+//  2. split leaves force the split of any coarser face or corner neighbour
+//     (level jump at most one to all neighbours, Sec. 4), until none is left;
+//  3. a complete sibling group of unsplit leaves whose node weights fail
+//     eq. node_ref is merged, if no face or corner neighbour of its members is
+//     finer than them in the mesh of step 2 (all such merges at once).
+// New leaves in Morton order; rk/src: the regrid map of k_tree_regrid.
+int tree_plan(const dg_ctx *c, const std::vector<int> &flags, int max_level, std::vector<int32_t> &next,
+              std::vector<int> &rk, std::vector<int> &src) {
+  const std::vector<int32_t> &lv = c->tleaves;
+  const long nl = (long)lv.size() / 3;
+  TreeIndex ix;
+  std::vector<int> T;
+  int st = tree_tables(c, lv, ix, T);
+  if (st != DG_OK) return st;
+  auto L = [&](long i) { return lv[3 * i]; };
+  auto X = [&](long i) { return (long)lv[3 * i + 1]; };
+  auto Y = [&](long i) { return (long)lv[3 * i + 2]; };
+  std::vector<char> split((size_t)nl, 0);
+  std::vector<long> work;
+  for (long i = 0; i < nl; ++i) {
+    if (!(flags[(size_t)i] & 1) || L(i) >= max_level) continue;
+    if (!split[(size_t)i]) { split[(size_t)i] = 1; work.push_back(i); }
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        long xx = X(i) + dx, yy = Y(i) + dy;
+        if ((dx == 0 && dy == 0) || !ix.wrap(L(i), xx, yy)) continue;
+        const long j = ix.covering(L(i), xx, yy);
+        if (j >= 0 && L(j) < max_level && !split[(size_t)j]) { split[(size_t)j] = 1; work.push_back(j); }
+      }
+  }
+  while (!work.empty()) {
+    const long i = work.back();
+    work.pop_back();
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy) {
+        long xx = X(i) + dx, yy = Y(i) + dy;
+        if ((dx == 0 && dy == 0) || !ix.wrap(L(i), xx, yy)) continue;
+        const long j = ix.covering(L(i), xx, yy);
+        if (j >= 0 && L(j) < L(i) && !split[(size_t)j]) { split[(size_t)j] = 1; work.push_back(j); }
+      }
+  }
+  // level of level-l cell (x, y) after step 2: finer than l -> l + 1
+  auto level_after = [&](int l, long x, long y) {
+    const long j = ix.covering(l, x, y);
+    if (j < 0) return l + 1;
+    return L(j) + split[(size_t)j];
+  };
+  std::vector<char> merge((size_t)nl, 0);
+  for (long i = 0; i < nl; ++i) {
+    if (!(flags[(size_t)i] & 4) || (flags[(size_t)i] & 2) || L(i) < 1) continue;
+    const int *grp = T.data() + 13 * nl;
+    if (grp[i] != i) continue;  // the group's child 0 decides
+    bool ok = true;
+    for (int ch = 0; ch < 4 && ok; ++ch) {
+      const long m = grp[(long)ch * nl + i];
+      if (split[(size_t)m] || (flags[(size_t)m] & 2)) { ok = false; break; }
+      for (int dx = -1; dx <= 1 && ok; ++dx)
+        for (int dy = -1; dy <= 1 && ok; ++dy) {
+          long xx = X(m) + dx, yy = Y(m) + dy;
+          if ((dx == 0 && dy == 0) || !ix.wrap(L(m), xx, yy)) continue;
+          if (level_after(L(m), xx, yy) > L(m)) ok = false;
+        }
+    }
+    if (ok)
+      for (int ch = 0; ch < 4; ++ch) merge[(size_t)grp[(long)ch * nl + i]] = 1;
+  }
+  // new leaves with their sources, then Morton order
+  std::vector<int32_t> nx;
+  std::vector<int> k0, s0;  // kind | child << 2, and 4 sources
+  for (long i = 0; i < nl; ++i) {
+    if (split[(size_t)i]) {
+      for (int ch = 0; ch < 4; ++ch) {
+        nx.insert(nx.end(), {L(i) + 1, (int32_t)(2 * X(i) + (ch & 1)), (int32_t)(2 * Y(i) + (ch >> 1))});
+        k0.push_back(1 | (ch << 2));
+        s0.insert(s0.end(), {(int)i, -1, -1, -1});
+      }
+    } else if (merge[(size_t)i]) {
+      const int *grp = T.data() + 13 * nl;
+      if (grp[i] != i) continue;
+      nx.insert(nx.end(), {L(i) - 1, (int32_t)(X(i) >> 1), (int32_t)(Y(i) >> 1)});
+      k0.push_back(2);
+      s0.insert(s0.end(), {grp[i], grp[nl + i], grp[2 * nl + i], grp[3 * nl + i]});
+    } else {
+      nx.insert(nx.end(), {L(i), (int32_t)X(i), (int32_t)Y(i)});
+      k0.push_back(0);
+      s0.insert(s0.end(), {(int)i, -1, -1, -1});
+    }
+  }
+  std::vector<int> perm;
+  tree_sort(nx, &perm);
+  const long nn = (long)perm.size();
+  rk.assign((size_t)nn, 0);
+  src.assign((size_t)4 * nn, -1);
+  for (long j = 0; j < nn; ++j) {
+    const long i = perm[(size_t)j];
+    rk[(size_t)j] = k0[(size_t)i];
+    for (int e = 0; e < 4; ++e) src[(size_t)(e * nn + j)] = s0[(size_t)(4 * i + e)];
+  }
+  next.swap(nx);
+  return DG_OK;
+}
+
+bool tree_ok(const dg_ctx *c) {
+  return c->sh.d == 2 && c->sh.k <= 3 && !c->amr && !c->gravity && c->cfg.precision == DG_FP64;
+}
+
+template <class F>
+int tree_dispatch(const dg_ctx *c, F &&f) {
+  switch (c->sh.k) {
+    case 1: return f.template run<1>();
+    case 2: return f.template run<2>();
+    case 3: return f.template run<3>();
+    default: return DG_EUNSUPPORTED;
+  }
+}
+
+struct TreeStage {
+  dg_ctx *c;
+  const double *w, *dt;
+  double *out;
+  int mode;
+  dg::Mix mx;
+  hipStream_t s;
+  template <int K>
+  int run() {
+    const dg::TreeGrid g = make_tree_grid(c);
+    if (c->cfg.flux == DG_HLLC_DAVIS)
+      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_DAVIS>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w,
+                         out, dt, g, mode, mx, c->flag);
+    else
+      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_BATTEN>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w,
+                         out, dt, g, mode, mx, c->flag);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+struct TreeFlags {
+  dg_ctx *c;
+  const double *w;
+  double tc, tn;
+  hipStream_t s;
+  template <int K>
+  int run() {
+    const dg::TreeGrid g = make_tree_grid(c);
+    hipLaunchKernelGGL((dg::k_tree_flags<K>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, w, c->prmat, g, tc, tn,
+                       c->tflags);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+struct TreeRegrid {
+  dg_ctx *c;
+  const double *wa;
+  double *wb;
+  long na, nb;
+  hipStream_t s;
+  template <int K>
+  int run() {
+    hipLaunchKernelGGL((dg::k_tree_regrid<K>), dim3(nblocks(nb)), dim3(kBlock), 0, s, wa, na, c->prmat, c->tmap,
+                       c->tmap + nb, wb, nb);
+    HIP_TRY(hipGetLastError());
+    return DG_OK;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int dg_tree_set(dg_ctx *c, int64_t nleaf, const int32_t *leaves) {
+  if (!c || !leaves || nleaf < 1) return DG_EINVAL;
+  if (!tree_ok(c)) return DG_EUNSUPPORTED;
+  return tree_install(c, std::vector<int32_t>(leaves, leaves + 3 * nleaf));
+}
+
+int dg_tree_size(const dg_ctx *c, int64_t *nleaf) {
+  if (!c || !nleaf || !c->tree) return DG_EINVAL;
+  *nleaf = (int64_t)c->tleaves.size() / 3;
+  return DG_OK;
+}
+
+int dg_tree_leaves(const dg_ctx *c, int32_t *leaves) {
+  if (!c || !leaves || !c->tree) return DG_EINVAL;
+  std::memcpy(leaves, c->tleaves.data(), c->tleaves.size() * sizeof(int32_t));
+  return DG_OK;
+}
+
+int dg_tree_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
+  if (!c || !w || !L || w == L || !c->tree) return DG_EINVAL;
+  return tree_dispatch(c, TreeStage{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
+}
+
+int dg_tree_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const double *wp, double *out,
+                     void *stream) {
+  if (!c || !dt || !wp || !out || stage < 1 || stage > 3 || !c->tree) return DG_EINVAL;
+  if (stage > 1 && !wn) return DG_EINVAL;
+  if (out == wp || out == wn) return DG_EINVAL;
+  return tree_dispatch(c, TreeStage{c, wp, dt, out, 1, rk3_mix(stage, wn), (hipStream_t)stream});
+}
+
+int dg_tree_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
+  if (!c || !w || !dt || !c->tree) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const dg::TreeGrid g = make_tree_grid(c);
+  unsigned long long *rm = reinterpret_cast<unsigned long long *>(c->partial);
+  const unsigned nb = nblocks(g.nleaf) < 1024u ? nblocks(g.nleaf) : 1024u;
+  hipLaunchKernelGGL(dg::k_rate_tree, dim3(nb), dim3(kBlock), 0, s, w, g, c->sh.N, rm, c->flag);
+  HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(dg::k_dt_final, dim3(1), dim3(64), 0, s, rm, c->cfl_fk, dt);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+int dg_tree_adapt(dg_ctx *c, const double *w, double wt, double alpha, int max_level, int64_t *nleaf_new,
+                  void *stream) {
+  if (!c || !w || !nleaf_new || !c->tree || !(wt > 0.0) || !(alpha >= 1.0) || max_level < 0 || max_level > 24)
+    return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const long nl = (long)c->tleaves.size() / 3;
+  int st = grow_ints(c->tflags, c->tflags_cap, nl);
+  if (st != DG_OK) return st;
+  st = tree_dispatch(c, TreeFlags{c, w, alpha * wt, wt / alpha, s});
+  if (st != DG_OK) return st;
+  std::vector<int> flags((size_t)nl);
+  HIP_TRY(hipStreamSynchronize(s));
+  HIP_TRY(hipMemcpy(flags.data(), c->tflags, (size_t)nl * sizeof(int), hipMemcpyDeviceToHost));
+  std::vector<int32_t> next;
+  st = tree_plan(c, flags, max_level, next, c->trk, c->tsrc);
+  if (st != DG_OK) return st;
+  c->tnext.swap(next);
+  *nleaf_new = (int64_t)c->tnext.size() / 3;
+  return DG_OK;
+}
+
+int dg_tree_regrid(dg_ctx *c, const double *w_old, double *w_new, void *stream) {
+  if (!c || !w_old || !w_new || w_old == w_new || !c->tree || c->tnext.empty()) return DG_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const long na = (long)c->tleaves.size() / 3, nb = (long)c->tnext.size() / 3;
+  HIP_TRY(hipStreamSynchronize(s));
+  int st = grow_ints(c->tmap, c->tmap_cap, 5 * nb);
+  if (st != DG_OK) return st;
+  HIP_TRY(hipMemcpy(c->tmap, c->trk.data(), (size_t)nb * sizeof(int), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->tmap + nb, c->tsrc.data(), (size_t)4 * nb * sizeof(int), hipMemcpyHostToDevice));
+  st = tree_dispatch(c, TreeRegrid{c, w_old, w_new, na, nb, s});
+  if (st != DG_OK) return st;
+  return tree_install(c, c->tnext);
 }
 
 }  // extern "C"

@@ -1,0 +1,123 @@
+"""2D quadtree meshes on the GPU (Sec. 4: leaves of any depth, hanging faces,
+refinement criterion, refine/derefine projections) against the oracle's
+quadtree path, under the comparison rules of tests/parity.py."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1506_06140_amd as dg
+import workloads
+from parity import check_rhs_modes, check_state_modes, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _vortex(n, k, **kw):
+    base = dict(n=(n[0], n[1], 1), length=(10.0 * n[0] / max(n), 10.0 * n[1] / max(n), 1.0),
+                x0=(-5.0, -5.0, 0.0), k=k, limiter=0, positivity=0)
+    base.update(kw)
+    return workloads.workload("vortex", **base)
+
+
+def _kh(n, k, **kw):
+    base = dict(n=(n[0], n[1], 1), k=k, limiter=0, positivity=0, rk="rk3")
+    base.update(kw)
+    return workloads.workload("kh2d", **base)
+
+
+CASES = {
+    "k1_random3": (lambda: _vortex((6, 5), 1), lambda: workloads.random_tree((6, 5), 3, 0.45, 3)),
+    "k2_random3": (lambda: _vortex((6, 5), 2), lambda: workloads.random_tree((6, 5), 3, 0.45, 11)),
+    "k3_random3": (lambda: _vortex((6, 5), 3), lambda: workloads.random_tree((6, 5), 3, 0.45, 5)),
+    "k2_walls": (lambda: _vortex((6, 5), 2, bc=(1, 1, 0)), lambda: workloads.random_tree((6, 5), 3, 0.5, 21,
+                                                                                          periodic=(False, False))),
+    "k3_davis_kh": (lambda: _kh((10, 10), 3, flux=1), lambda: workloads.band_tree((10, 10), 3)),
+    "k2_random4_large": (lambda: _vortex((16, 16), 2), lambda: workloads.random_tree((16, 16), 4, 0.35, 2)),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_tree_rhs_matches_oracle(case):
+    wl = CASES[case][0]()
+    leaves = CASES[case][1]()
+    say(case, "leaves", len(leaves), "per level", np.bincount(leaves[:, 0]))
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    V, S, A = o.terms(w)
+    s = dg.TreeSolver(wl, leaves)
+    assert np.array_equal(s.leaves, leaves)
+    L = s.rhs(torch.from_numpy(w).cuda()).cpu().numpy()
+    assert s.status() == 0
+    check_rhs_modes(L, V, S, A, case)
+
+
+@pytest.mark.parametrize("case", ["k1_random3", "k3_random3", "k2_walls", "k3_davis_kh"])
+def test_tree_steps_match_oracle(case):
+    wl = CASES[case][0]()
+    leaves = CASES[case][1]()
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    s = dg.TreeSolver(wl, leaves)
+    wg = torch.from_numpy(w).cuda()
+    bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+    ref = w
+    for it in range(3):
+        ref, dt = o.step(ref)
+        out = s.step(wg, bufs)
+        dtg = float(bufs[3].item())
+        assert dtg == pytest.approx(dt, rel=1e-14), (dtg, dt)
+        check_state_modes(out.cpu().numpy(), ref, f"{case} step {it + 1}")
+        wg = out.clone()
+    assert s.status() == 0
+
+
+def _refined_fraction(leaves):
+    return float((0.25 ** leaves[:, 0] * (leaves[:, 0] > 0)).sum() / (0.25 ** leaves[:, 0]).sum())
+
+
+@pytest.mark.parametrize("n,start,max_level,steps", [((10, 10), 1, 3, 4), ((16, 16), 2, 4, 2)])
+def test_adaptive_kh_matches_oracle_step_for_step(n, start, max_level, steps):
+    """The KH setup (Validation, KH instability) on a quadtree that adapts
+    before every step (Sec. 4.1-4.3, wt = 0.01, alpha = 1.1): the GPU's leaf
+    sets equal the oracle's exactly and the states agree under the parity
+    rules, step after step."""
+    # origin shifted by a fraction of the finest cell, so that the shear
+    # layers cut cells on every level (on a face the density has no slope)
+    wl = _kh(n, 3, x0=(0.0, -0.01, 0.0))
+    leaves = workloads.band_tree(n, start)
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    s = dg.TreeSolver(wl, leaves)
+    wg = torch.from_numpy(w).cuda()
+    for it in range(steps):
+        leaves_o, w = oracle.tree_adapt(wl, o.leaves, w, 0.01, 1.1, max_level)
+        wg = s.adapt(wg, 0.01, 1.1, max_level)
+        assert np.array_equal(s.leaves, leaves_o), f"mesh differs after adaptation {it + 1}"
+        check_state_modes(wg.cpu().numpy(), w, f"regrid {it + 1}")
+        o = oracle.TreeOracle(wl, leaves_o)
+        w, dt = o.step(w)
+        bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+        out = s.step(wg, bufs)
+        assert float(bufs[3].item()) == pytest.approx(dt, rel=1e-14)
+        check_state_modes(out.cpu().numpy(), w, f"step {it + 1}")
+        wg = out.clone()
+        say(f"step {it + 1}: {len(leaves_o)} leaves, per level {np.bincount(leaves_o[:, 0])}, "
+            f"refined area fraction {_refined_fraction(leaves_o):.3f}")
+    assert s.leaves[:, 0].max() == max_level
+    assert s.status() == 0
+
+
+def test_tree_set_rejects_invalid_meshes():
+    wl = _vortex((4, 4), 2)
+    good = np.array([(0, x, y) for y in range(4) for x in range(4)])
+    s = dg.TreeSolver(wl, good)
+    gap = good[1:]
+    overlap = np.concatenate([good, [[1, 0, 0]]])
+    jump = np.concatenate([good[good[:, 1] + 4 * good[:, 2] != 5],
+                           [(2, 4 + (q & 3), 4 + (q >> 2)) for q in range(16)]])
+    for bad in (gap, overlap, jump):
+        with pytest.raises(dg.DGError):
+            s.set_leaves(bad)
+    s.set_leaves(good)
+    assert s.nleaf == 16

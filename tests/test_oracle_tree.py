@@ -115,3 +115,82 @@ def test_tree_rejects_gaps_and_overlaps():
     bad = np.concatenate([good, [[1, 0, 0]]])
     with pytest.raises(RuntimeError):
         oracle.TreeOracle(wl, bad).rhs(np.zeros((4, 6, 5)))
+
+
+def _balanced(leaves, n):
+    """Brute force: every pair of leaves that touch (faces or corners, periodic)
+    differs by at most one level."""
+    lv = np.asarray(leaves)
+    L = lv[:, 0].max()
+    s = 1 << (L - lv[:, 0])
+    x0, y0 = lv[:, 1] * s, lv[:, 2] * s
+    NX, NY = n[0] << L, n[1] << L
+    for i in range(len(lv)):
+        for j in range(i + 1, len(lv)):
+            if abs(lv[i, 0] - lv[j, 0]) <= 1:
+                continue
+            for ox in (-NX, 0, NX):
+                for oy in (-NY, 0, NY):
+                    if (x0[i] <= x0[j] + ox + s[j] and x0[j] + ox <= x0[i] + s[i]
+                            and y0[i] <= y0[j] + oy + s[j] and y0[j] + oy <= y0[i] + s[i]):
+                        return False
+    return True
+
+
+def test_adapt_refines_flagged_leaves_with_a_buffer_and_balances():
+    n = (10, 10)
+    wl = _wl(n=n, k=2, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0))
+    t = oracle.TreeOracle(wl, _grid_leaves(n, 0))
+    w = t.initial_state()
+    new, w1 = oracle.tree_adapt(wl, t.leaves, w, max_level=2)
+    assert _balanced(new, n)
+    flagged = np.maximum(np.abs(w[0, 1]), np.abs(w[0, 2])) > 1.1 * 0.01
+    assert flagged.any() and not flagged.all()
+    have = {tuple(r) for r in new}
+    for i in np.flatnonzero(flagged):
+        l, x, y = t.leaves[i]
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                xx, yy = (x + dx) % n[0], (y + dy) % n[1]
+                assert (0, xx, yy) not in have  # the flagged leaf and its buffer ring are split
+    # a second pass may refine to level 2, still balanced
+    t1 = oracle.TreeOracle(wl, new)
+    new2, w2 = oracle.tree_adapt(wl, new, w1, max_level=2)
+    assert new2[:, 0].max() == 2 and _balanced(new2, n)
+    # the projections keep mass, momentum and energy: sum of area * mean
+    for (lvs, ws), (lvb, wb) in (((t.leaves, w), (new, w1)), ((new, w1), (new2, w2))):
+        a0 = (0.25 ** lvs[:, 0] * ws[:, 0, :]).sum(axis=1)
+        a1 = (0.25 ** lvb[:, 0] * wb[:, 0, :]).sum(axis=1)
+        assert np.all(np.abs(a0 - a1) <= 1e-14 * np.abs(a0).max())
+    assert t1.nleaf == len(new)
+
+
+def test_adapt_merges_smooth_groups_and_refine_merge_is_identity():
+    """A state with no density slope merges every complete sibling group whose
+    neighbours allow it; splitting a leaf and merging its children gives its
+    polynomial back (degree k is exact on the children)."""
+    n = (4, 4)
+    wl = _wl(n=n, k=3, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0))
+    leaves = workloads.random_tree(n, 2, 0.5, 9)
+    t = oracle.TreeOracle(wl, leaves)
+    w = t.initial_state()
+    flat = w.copy()
+    flat[:, 1:, :] = 0.0
+    new, wn = oracle.tree_adapt(wl, leaves, flat, max_level=2)
+    assert len(new) < len(leaves) and _balanced(new, n)
+    # refine everything once from a coarse mesh, then merge back: w returns
+    base = _grid_leaves(n, 0)
+    tb = oracle.TreeOracle(wl, base)
+    wb = tb.initial_state()
+    P = oracle._tree_refine_mats(wl)
+    kids = np.stack([(P[c] @ wb[:, :, i].T).T for i in range(len(base)) for c in range(4)], axis=2)
+    kl = np.array([(1, 2 * x + (c & 1), 2 * y + (c >> 1)) for (_, x, y) in base for c in range(4)])
+    back, wback = oracle.tree_adapt(wl, kl, np.where(np.arange(wb.shape[1])[None, :, None] == 0, kids, 0.0),
+                                    wt=1e9, max_level=1)
+    assert len(back) == len(base)
+    # merging the projected children of the means alone returns the means
+    order = {tuple(r): i for i, r in enumerate(base)}
+    idx = [order[tuple(r)] for r in back]
+    assert np.allclose(wback[:, 0, :], wb[:, 0, idx], rtol=1e-14, atol=1e-15)
+    node = sum(P[c].T @ kids[:, :, 4 * 5 + c].T for c in range(4)).T / 4.0
+    assert np.allclose(node, wb[:, :, 5], rtol=0, atol=1e-13)
