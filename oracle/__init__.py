@@ -119,6 +119,7 @@ def _load():
             "orc_amr_regrid": [cp, dp, cp, dp],
             "orc_tree_rhs": [cp, C.c_long, ip, lp, lp, dp, dp],
             "orc_tree_terms": [cp, C.c_long, ip, lp, lp, dp, dp, dp, dp],
+            "orc_tree_limit": [cp, C.c_long, ip, lp, lp, dp],
             "orc_tree_max_dt": [cp, C.c_long, ip, lp, lp, dp, dp],
             "orc_tree_node_coords": [cp, C.c_long, ip, lp, lp, dp],
             "orc_tree_project": [cp, C.c_long, ip, lp, lp, dp, dp],
@@ -749,13 +750,26 @@ class TreeOracle(Oracle):
     def rk3_stage(self, stage: int, dt: float, wn, wp) -> np.ndarray:
         return rk3_combine(stage, dt, wn, wp, self.rhs(wp))
 
+    def limit(self, w: np.ndarray):
+        """Slope then positivity limiter with the AMR rules of Sec. 4.4:
+        (limited copy, status)."""
+        lib, _ = _load()
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_tree_limit(*self._a(), out)
+        return out, st
+
     def step(self, w0: np.ndarray, dt: float | None = None):
-        """One SSP-RK3 step (App. D, table RK_3); returns (w1, dt)."""
+        """One SSP-RK3 step (App. D, table RK_3), the limiters after every
+        stage when the workload asks for them; returns (w1, dt)."""
         if dt is None:
             dt = self.max_dt(w0)
-        w1 = self.rk3_stage(1, dt, w0, w0)
-        w2 = self.rk3_stage(2, dt, w0, w1)
-        return self.rk3_stage(3, dt, w0, w2), dt
+        lim = self.wl.get("limiter", 0) or self.wl.get("positivity", 0)
+
+        def L(x):
+            return self.limit(x)[0] if lim else x
+        w1 = L(self.rk3_stage(1, dt, w0, w0))
+        w2 = L(self.rk3_stage(2, dt, w0, w1))
+        return L(self.rk3_stage(3, dt, w0, w2)), dt
 
 
 def _tree_refine_mats(wl: dict):

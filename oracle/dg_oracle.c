@@ -2114,7 +2114,7 @@ static void tree_eval(const tree *T, const double *w, long i, const double *xi, 
 }
 
 /* Surface term of leaf i (eq. dg_term3 over the overlaps of its faces). */
-static int tree_surface(const tree *T, const double *w, long i, double S[MAXV][MAXN]) {
+static int tree_surface(const tree *T, const double *w, long i, double S[MAXV][MAXN], double (*A)[MAXN]) {
   const ctx *X = &T->X;
   for (int v = 0; v < X->nvar; ++v) for (int j = 0; j < X->N; ++j) S[v][j] = 0.0;
   for (int a = 0; a < 2; ++a) {
@@ -2147,12 +2147,41 @@ static int tree_surface(const tree *T, const double *w, long i, double S[MAXV][M
             for (int l = 0; l < X->N; ++l) {
               double tt = F[v] * phi_at(X, l, xi) * (X->gw[r] * ratio);
               if (s) S[v][l] += tt; else S[v][l] -= tt;
+              if (A) A[v][l] += fabs(tt);
             }
         }
       }
     }
   }
   return ORC_OK;
+}
+
+/* fac V and fac S of every leaf (L = V - S), fac = (2/dx_i) 2^-d with the
+ * leaf's own edge; Ao (may be NULL): fac times the summed magnitudes of every
+ * summand of V and S (the rounding scale of each element). */
+int orc_tree_terms(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                   const double *w, double *Vo, double *So, double *Ao) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  for (long i = 0; i < nleaf && st == ORC_OK; ++i) {
+    double V[MAXV][MAXN], S[MAXV][MAXN], A[MAXV][MAXN];
+    memset(A, 0, sizeof(A));
+    volume_term(X, w, i, V, A);
+    st = tree_surface(T, w, i, S, A);
+    double dxi = X->dx / (double)(1L << lev[i]);
+    double fac = 2.0 / dxi / 4.0;
+    for (int v = 0; v < X->nvar; ++v)
+      for (int j = 0; j < X->N; ++j) {
+        long e = ((long)v * X->N + j) * nleaf + i;
+        Vo[e] = fac * V[v][j];
+        So[e] = fac * S[v][j];
+        if (Ao) Ao[e] = fac * A[v][j];
+      }
+  }
+  tree_free(T); free(T);
+  return st;
 }
 
 /* L = dw/dt on every leaf: (2/dx_i) 2^-d (V - S) with the leaf's own edge. */
@@ -2165,7 +2194,7 @@ int orc_tree_rhs(const orc_config *c, long nleaf, const int *lev, const long *ix
   for (long i = 0; i < nleaf && st == ORC_OK; ++i) {
     double V[MAXV][MAXN], S[MAXV][MAXN];
     volume_term(X, w, i, V, NULL);
-    st = tree_surface(T, w, i, S);
+    st = tree_surface(T, w, i, S, NULL);
     double dxi = X->dx / (double)(1L << lev[i]);
     double fac = 2.0 / dxi / 4.0;
     for (int v = 0; v < X->nvar; ++v)
@@ -2199,6 +2228,109 @@ int orc_tree_max_dt(const orc_config *c, long nleaf, const int *lev, const long 
   *dt_out = dt;
   tree_free(T); free(T);
   return ORC_OK;
+}
+
+
+/* Mean over the level-l cell (X, Y) of the piecewise polynomial solution
+ * (the neighbour value of the limiters at refinement boundaries, Sec. 4.4):
+ * a leaf of the same level gives its mean; a coarser leaf the mean of its
+ * polynomial over that cell (its projection onto the smaller volume, here by
+ * the (k+1)^2-point Gauss rule on the sub-box, exact for the degree); finer
+ * leaves inside the cell their area-weighted means (the node weights). */
+static void tree_region_mean(const tree *T, const double *w, const int *lev, int l, long X0, long Y0, double *m) {
+  const ctx *X = &T->X;
+  long s = 1L << (T->lmax - l);
+  long r0 = X0 * s, r1 = r0 + s, q0 = Y0 * s, q1 = q0 + s;
+  for (int v = 0; v < X->nvar; ++v) m[v] = 0.0;
+  for (long j = 0; j < T->nleaf; ++j) {
+    if (!(T->bx0[j] < r1 && r0 < T->bx1[j] && T->by0[j] < q1 && q0 < T->by1[j])) continue;
+    if (lev[j] == l) {
+      for (int v = 0; v < X->nvar; ++v) m[v] = W(v, 0, j);
+      return;
+    }
+    if (lev[j] < l) {
+      double js = (double)(T->bx1[j] - T->bx0[j]);
+      double lo[2] = {(2.0 * (r0 - T->bx0[j])) / js - 1.0, (2.0 * (q0 - T->by0[j])) / js - 1.0};
+      double hs = (double)s / js; /* half-width of the sub-box in j's reference coordinates */
+      for (int q = 0; q < X->Q; ++q) {
+        double xi[3] = {lo[0] + hs * (1.0 + X->gx[q % X->n1]), lo[1] + hs * (1.0 + X->gx[q / X->n1]), 0.0};
+        for (int v = 0; v < X->nvar; ++v) {
+          double u = 0.0;
+          for (int ll = 0; ll < X->N; ++ll) u += W(v, ll, j) * phi_at(X, ll, xi);
+          m[v] += u * X->wV[q] / 4.0;
+        }
+      }
+      return;
+    }
+    double frac = 1.0 / (double)(1L << (2 * (lev[j] - l)));
+    for (int v = 0; v < X->nvar; ++v) m[v] += W(v, 0, j) * frac;
+  }
+}
+
+/* Slope limiter (Sec. 3.1-3.3) and positivity limiter (Sec. 3.4) on a
+ * quadtree, in place, with the AMR rules of Sec. 4.4: the neighbour value on
+ * each side is the mean of the solution over the cell of the leaf's own size
+ * there (tree_region_mean, from the state before any limiting), the TVB
+ * bound uses the leaf's own edge, and a leaf with finer neighbours also
+ * checks positivity at its trace points on the faces to them. */
+int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, double *w) {
+  tree *T = malloc(sizeof(tree));
+  int st = tree_init(c, nleaf, lev, ix, iy, T);
+  if (st != ORC_OK) { free(T); return st; }
+  const ctx *X = &T->X;
+  int nv = X->nvar, N = X->N;
+  long bad = 0;
+  if (c->limiter) {
+    double *nbm = malloc(sizeof(double) * 4 * nv * nleaf);
+    double *dxc = malloc(sizeof(double) * nleaf);
+    for (long i = 0; i < nleaf; ++i) {
+      dxc[i] = X->dx / (double)(1L << lev[i]);
+      for (int a = 0; a < 2; ++a)
+        for (int s = 0; s < 2; ++s) {
+          long Xn = ix[i] + (a == 0 ? (s ? 1 : -1) : 0), Yn = iy[i] + (a == 1 ? (s ? 1 : -1) : 0);
+          long nxl = (long)c->n[0] << lev[i], nyl = (long)c->n[1] << lev[i];
+          int wall = 0;
+          if (Xn < 0 || Xn >= nxl) { if (c->bc[0] == 1) wall = 1; else Xn = (Xn + nxl) % nxl; }
+          if (Yn < 0 || Yn >= nyl) { if (c->bc[1] == 1) wall = 1; else Yn = (Yn + nyl) % nyl; }
+          double m[MAXV];
+          if (wall) for (int v = 0; v < nv; ++v) m[v] = W(v, 0, i);
+          else tree_region_mean(T, w, lev, lev[i], Xn, Yn, m);
+          for (int v = 0; v < nv; ++v) nbm[((long)(2 * a + s) * nv + v) * nleaf + i] = m[v];
+        }
+    }
+    if (c->limiter == 2) char_limit(X, w, nbm, dxc, NULL);
+    else slope_limit(X, w, nbm, dxc, NULL);
+    free(nbm); free(dxc);
+  }
+  if (c->positivity) {
+    int xmax = 4 * 4 * X->n1;
+    int *xcnt = calloc(nleaf, sizeof(int));
+    double *xphi = malloc(sizeof(double) * nleaf * xmax * N);
+    for (long i = 0; i < nleaf; ++i)
+      for (int a = 0; a < 2; ++a) {
+        int b = 1 - a;
+        const long *t0 = b == 0 ? T->bx0 : T->by0, *t1 = b == 0 ? T->bx1 : T->by1;
+        for (int s = 0; s < 2; ++s) {
+          long nb[4], o0[4], o1[4];
+          int m = tree_across(T, i, a, s, nb, o0, o1);
+          for (int p = 0; p < m; ++p) {
+            if (o1[p] - o0[p] == t1[i] - t0[i]) continue; /* not a smaller neighbour */
+            for (int r = 0; r < X->n1; ++r) {
+              double xi[3] = {0, 0, 0};
+              xi[a] = s ? 1.0 : -1.0;
+              xi[b] = ((double)(o0[p] + o1[p] - t0[i] - t1[i]) + (double)(o1[p] - o0[p]) * X->gx[r]) /
+                      (double)(t1[i] - t0[i]);
+              for (int l = 0; l < N; ++l) xphi[((long)i * xmax + xcnt[i]) * N + l] = phi_at(X, l, xi);
+              ++xcnt[i];
+            }
+          }
+        }
+      }
+    bad = positivity_limit(X, w, xcnt, xphi, xmax, NULL);
+    free(xcnt); free(xphi);
+  }
+  tree_free(T); free(T);
+  return bad ? ORC_ENEGATIVE : ORC_OK;
 }
 
 /* Physical coordinates of every leaf's volume nodes, x[2][Q][nleaf]. */

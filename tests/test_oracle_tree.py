@@ -194,3 +194,95 @@ def test_adapt_merges_smooth_groups_and_refine_merge_is_identity():
     assert np.allclose(wback[:, 0, :], wb[:, 0, idx], rtol=1e-14, atol=1e-15)
     node = sum(P[c].T @ kids[:, :, 4 * 5 + c].T for c in range(4)).T / 4.0
     assert np.allclose(node, wb[:, :, 5], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("limiter", [1, 2])
+def test_one_level_tree_limiter_is_the_uniform_limiter(limiter):
+    n = (10, 10)
+    wl = _wl(n=n, k=2, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0), limiter=limiter, positivity=1,
+             eps=1e-8)
+    u = oracle.Oracle(wl)
+    w = u.initial_state()
+    ref, st = u.limit(w)
+    t = oracle.TreeOracle(wl, _grid_leaves(n, 0))
+    got, st2 = t.limit(w.reshape(u.nvar, u.N, -1))
+    assert st == st2 == 0
+    assert np.abs(ref.reshape(got.shape) - w.reshape(got.shape)).max() > 1e-3  # the limiters act
+    assert np.array_equal(got, ref.reshape(got.shape))
+
+
+@pytest.mark.parametrize("k,limiter,bc", [(2, 1, (0, 0, 0)), (3, 2, (0, 0, 0)), (2, 2, (1, 1, 0))])
+def test_box_shaped_tree_limiter_is_the_refined_box_limiter(k, limiter, bc):
+    """Neighbour means across the refinement boundary (children's average on
+    the coarse side, the coarse polynomial's mean over the adjacent child on
+    the fine side) and the extra positivity points of the hanging faces."""
+    # the box's x faces cross the lower shear layer; eps just below the outer
+    # density makes the positivity limiter act near the jump
+    n, lo, hi = (10, 10), (2, 1), (6, 4)
+    wl = _wl(n=n, k=k, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0), bc=bc, limiter=limiter,
+             positivity=1, eps=0.95, refine_lo=(lo[0], lo[1], 0), refine_hi=(hi[0], hi[1], 1))
+    box = oracle.AmrOracle(wl)
+    w = box.initial_state()
+    wc, wf = box.blocks(w)
+    leaves, cols = [], []
+    for c in range(box.ncoarse):
+        if not box.hole[c]:
+            leaves.append((0, c % n[0], c // n[0])); cols.append(("c", c))
+    for f in range(box.nfine):
+        leaves.append((1, 2 * lo[0] + f % box.nf[0], 2 * lo[1] + f // box.nf[0])); cols.append(("f", f))
+    pick = lambda x: np.stack([x[0][:, :, i] if b == "c" else x[1][:, :, i] for b, i in cols], axis=2)
+    ref, st = box.limit(w)
+    t = oracle.TreeOracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)), np.array(leaves))
+    got, st2 = t.limit(pick((wc, wf)))
+    r = pick(box.blocks(ref))
+    assert st == st2 == 0
+    assert np.abs(r - pick((wc, wf))).max() > 1e-3
+    scale = np.abs(r).reshape(r.shape[0], -1).max(axis=1)[:, None, None]
+    assert np.abs(got - r).max(axis=(1, 2)).max() <= 0 or np.all(np.abs(got - r) <= 1e-13 * scale)
+
+
+def test_tree_positivity_checks_the_hanging_face_points():
+    """A coarse leaf next to finer ones whose density dips lowest at a trace
+    point of a half face (eta = (0.86 + 1)/2 = 0.93, k = 3), which is none of
+    the union points S (Gauss 0.34, 0.86 and GLL 0, 1 in y): with eps between
+    the dip and the lowest S value only the extra points of Sec. 4.4 make the
+    limiter act; the box oracle, pinned on its own, agrees."""
+    n, lo, hi = (6, 6), (2, 2), (4, 4)
+    wl = _wl(n=n, k=3, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, 0.0, 0.0), limiter=0, positivity=1,
+             eps=0.52, refine_lo=(lo[0], lo[1], 0), refine_hi=(hi[0], hi[1], 1))
+    box = oracle.AmrOracle(wl)
+    xi, _ = oracle.Oracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0))).volume_rule()
+    g, _ = oracle.gauss(4)
+    eta = 0.5 * (g.max() + 1.0)
+    ncell = box.ncoarse + box.nfine
+    prim = np.zeros((ncell, box.Q, 5))
+    prim[..., 0] = 1.0
+    prim[..., 4] = 2.5
+    target = [c for c in range(box.ncoarse) if c % n[0] == lo[0] - 1 and lo[1] <= c // n[0] < hi[1]]
+    for c in target:  # coarse leaves on the box's low x face
+        prim[c, :, 0] = 1.0 + 10.0 * ((xi[:, 1] - eta) ** 2 - 0.05)
+    w = np.zeros(box.size)
+    lib, _ = oracle._load()
+    assert lib.orc_amr_project(oracle.C.byref(box.c), np.ascontiguousarray(prim), w) == 0
+    ref, st = box.limit(w)
+    assert st == 0
+    wc, wf = box.blocks(w)
+    rc, _ = box.blocks(ref)
+    assert np.abs(rc[:, :, target] - wc[:, :, target]).max() > 1e-3  # the box limiter acts there
+    leaves, cols = [], []
+    for c in range(box.ncoarse):
+        if not box.hole[c]:
+            leaves.append((0, c % n[0], c // n[0])); cols.append(("c", c))
+    for f in range(box.nfine):
+        leaves.append((1, 2 * lo[0] + f % box.nf[0], 2 * lo[1] + f // box.nf[0])); cols.append(("f", f))
+    pick = lambda x: np.stack([x[0][:, :, i] if b == "c" else x[1][:, :, i] for b, i in cols], axis=2)
+    t = oracle.TreeOracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)), np.array(leaves))
+    got, st2 = t.limit(pick((wc, wf)))
+    r = pick(box.blocks(ref))
+    assert st2 == 0
+    assert np.all(np.abs(got - r) <= 1e-13 * np.abs(r).max())
+    # the same leaves on a one-level mesh (no finer neighbour): nothing to do
+    flat = oracle.TreeOracle(dict(wl, refine_lo=(0, 0, 0), refine_hi=(0, 0, 0)), _grid_leaves(n, 0))
+    wu = np.where(box.hole[None, None, :], wc[:, :, [0]], wc)  # hole cells: a plain cell's state
+    gotu, _ = flat.limit(wu)
+    assert np.array_equal(gotu[:, :, target], wc[:, :, target])
