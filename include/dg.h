@@ -366,6 +366,18 @@ int dg_tree_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const double 
  * CFL f_k / max over leaves of sum_a (|v_a| + c)/h into the device scalar. */
 int dg_tree_max_dt(dg_ctx *ctx, const double *w, double *dt_dev, void *stream);
 
+/* Slope limiter then positivity limiter on the tree, in place, as
+ * configured (as dg_limit), with the AMR rules of Sec. 4.4: the neighbour
+ * value on each side of a leaf is the mean of the solution over the cell of
+ * the leaf's own size there (a same-level leaf's mean, a coarser leaf's
+ * polynomial averaged over that cell, or the area-weighted means of the finer
+ * leaves inside it), all taken from the state before limiting; the TVB bound
+ * uses the leaf's own edge; a leaf with finer neighbours also checks
+ * positivity at its trace points on the half faces to them.  A mean density
+ * or pressure <= eps sets the DG_ENEGATIVE flag and is left alone.  Uses the
+ * context's neighbour-value scratch: calls on one context must be ordered. */
+int dg_tree_limit(dg_ctx *ctx, double *w, void *stream);
+
 /* Plans the next mesh (Sec. 4.1): on the device, per leaf, the refinement
  * criterion max_a |w_rho,1+a| > alpha wt (eq. cell_ref) and, for a complete
  * group of four sibling leaves, whether its node weights (eq. deref_weights)

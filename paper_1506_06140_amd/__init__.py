@@ -68,7 +68,7 @@ EXPORTS = (
     "dg_max_dt", "dg_rk_stage", "dg_max_rate", "dg_rk_step", "dg_set_tableau", "dg_tableau_stage", "dg_tableau_step",
     "dg_set_gravity", "dg_amr_flags", "dg_amr_regrid", "dg_limit", "dg_adjoint_rhs", "dg_adjoint_rk_stage", "dg_status", "dg_destroy", "dg_strerror",
     "dg_tree_set", "dg_tree_size", "dg_tree_leaves", "dg_tree_rhs", "dg_tree_rk_stage", "dg_tree_max_dt",
-    "dg_tree_adapt", "dg_tree_regrid",
+    "dg_tree_adapt", "dg_tree_regrid", "dg_tree_limit",
 )
 
 _lib = None
@@ -115,6 +115,7 @@ def load_library(path: str = LIB_PATH):
     lib.dg_tree_max_dt.argtypes = [ctxp, dp, dp, vp]
     lib.dg_tree_adapt.argtypes = [ctxp, dp, C.c_double, C.c_double, C.c_int, C.POINTER(C.c_int64), vp]
     lib.dg_tree_regrid.argtypes = [ctxp, dp, dp, vp]
+    lib.dg_tree_limit.argtypes = [ctxp, dp, vp]
     lib.dg_destroy.argtypes = [ctxp]
     lib.dg_destroy.restype = None
     lib.dg_strerror.argtypes = [C.c_int]
@@ -482,14 +483,25 @@ class TreeSolver(Solver):
                                          _stream(stream)), "dg_tree_rk_stage")
         return out
 
+    def limit(self, w, stream=None):
+        _check(self.lib.dg_tree_limit(self.ctx, self._s(w), _stream(stream)), "dg_tree_limit")
+        return w
+
     def step(self, w, bufs, dt=None, stream=None):
         """One SSP-RK3 step from w into bufs[2] (bufs[0..1] stage buffers,
-        bufs[3] the time step when dt is None)."""
+        bufs[3] the time step when dt is None), the limiters after every stage
+        when configured."""
         if dt is None:
             dt = self.max_dt(w, bufs[3], stream)
         self.rk_stage(1, dt, None, w, bufs[0], stream)
+        if self.limited:
+            self.limit(bufs[0], stream)
         self.rk_stage(2, dt, w, bufs[0], bufs[1], stream)
+        if self.limited:
+            self.limit(bufs[1], stream)
         self.rk_stage(3, dt, w, bufs[1], bufs[2], stream)
+        if self.limited:
+            self.limit(bufs[2], stream)
         return bufs[2]
 
     def adapt(self, w, wt=0.01, alpha=1.1, max_level=3, stream=None):

@@ -3798,7 +3798,7 @@ namespace dg {
 struct TreeGrid {
   long nleaf;
   const int *lev;   // [nleaf]
-  const int *info;  // [4][nleaf]: kind | sub << 2, side 2a + s
+  const int *info;  // [4][nleaf]: kind | sub << 2 | ch << 3, side 2a + s (ch: kind 3's child for the limiters)
   const int *nb;    // [8][nleaf]: neighbour (2 side + half)
   const int *grp;   // [4][nleaf]: the four leaves of this leaf's sibling group (child order), or -1
   double fac0;      // (2/dx) 2^-d of level 0
@@ -3853,7 +3853,7 @@ __global__ __launch_bounds__(256) void k_rhs_tree(const double *__restrict__ tab
   for (int side = 0; side < 4; ++side) {
     const int a = side >> 1, s = side & 1;
     const int inf = g.info[(long)side * nl + cell];
-    const int kind = inf & 3, sub = inf >> 2;
+    const int kind = inf & 3, sub = (inf >> 2) & 1;
     const int nsub = (kind == 2) ? 2 : 1;
 #pragma unroll 1
     for (int sb = 0; sb < nsub; ++sb) {
@@ -3990,6 +3990,165 @@ __global__ __launch_bounds__(256) void k_tree_regrid(const double *__restrict__ 
           for (int l = 0; l < N; ++l) acc = fma(P[((long)c * N + l) * N + j], wa[(long)(v * N + l) * na + sc[c]], acc);
         wb[(long)(v * N + j) * nb + i] = acc / 4.0;
       }
+  }
+}
+
+}  // namespace dg
+
+namespace dg {
+
+// Neighbour values of the limiters on a quadtree (Sec. 4.4), from the state
+// before limiting, per side (a, s) of each leaf: the mean over the cell of
+// the leaf's own size there, i.e. the same-level leaf's mean, the coarser
+// leaf's polynomial averaged over that cell (table CM, child `ch`), the
+// area-weighted means of the finer leaves inside it (list `reg`), or at a
+// transmissive wall the leaf's own mean.  nbm[(side NV + v) nleaf + leaf].
+template <int K>
+__global__ __launch_bounds__(256) void k_tree_nbmean(const double *__restrict__ tab, const double *__restrict__ w,
+                                                     TreeGrid g, const int *__restrict__ reg,
+                                                     double *__restrict__ nbm) {
+  using C = Cfg<2, K>;
+  constexpr int NV = C::NV, N = C::N;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.nleaf) return;
+  const long nl = g.nleaf;
+  const int *roff = reg, *rcnt = reg + 4 * nl, *rlist = reg + 8 * nl;
+  for (int side = 0; side < 4; ++side) {
+    const int inf = g.info[(long)side * nl + cell];
+    const int kind = inf & 3, ch = (inf >> 3) & 3;
+    double m[NV];
+    if (kind == 0 || kind == 1) {
+      const long j = kind == 1 ? cell : (long)g.nb[(long)(2 * side) * nl + cell];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) m[v] = w[(long)(v * N) * nl + j];
+    } else if (kind == 3) {
+      const long j = g.nb[(long)(2 * side) * nl + cell];
+      const double *cm = tab + C::CM + ch * N;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < N; ++l) s = fma(w[(long)(v * N + l) * nl + j], cm[l], s);
+        m[v] = s;
+      }
+    } else {
+      const int o = roff[(long)side * nl + cell], n = rcnt[(long)side * nl + cell];
+      const int l0 = g.lev[cell];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) m[v] = 0.0;
+      for (int e = 0; e < n; ++e) {
+        const long j = rlist[o + e];
+        const double frac = 1.0 / (double)(1L << (2 * (g.lev[j] - l0)));
+#pragma unroll
+        for (int v = 0; v < NV; ++v) m[v] = fma(w[(long)(v * N) * nl + j], frac, m[v]);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) nbm[(long)(side * NV + v) * nl + cell] = m[v];
+  }
+}
+
+// Slope limiter on a quadtree (component-wise, eq. comp_limiter, or on the
+// characteristic variables, eq. char_limiter) against the neighbour values
+// of k_tree_nbmean, with the TVB bound of the leaf's own edge (Sec. 3.3).
+template <int K, bool CHAR>
+__global__ __launch_bounds__(256) void k_limit_tree(double *__restrict__ w, TreeGrid g, const double *__restrict__ nbm,
+                                                    double beta, double mtilde) {
+  using C = Cfg<2, K>;
+  constexpr int NV = C::NV, N = C::N;
+  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= g.nleaf) return;
+  const long nl = g.nleaf;
+  const double bound = mtilde * (g.dx0 / (double)(1 << g.lev[cell]));
+  double wc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) wc[v][l] = w[(long)(v * N + l) * nl + cell];
+  bool dropped[NV];
+  if constexpr (CHAR) {
+    auto nbmean = [&](int a, int s, double *m) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) m[v] = nbm[(long)((2 * a + s) * NV + v) * nl + cell];
+    };
+    const bool lim = char_limit_cell<2, N>(wc, nbmean, g.gamma, beta, bound);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) dropped[v] = lim;
+  } else {
+    const double r3 = sqrt(3.0);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const double mean = wc[i][0];
+      double mt[2];
+      bool limited = false;
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const double mlo = nbm[(long)((2 * a) * NV + i) * nl + cell];
+        const double mhi = nbm[(long)((2 * a + 1) * NV + i) * nl + cell];
+        const double A = r3 * wc[i][1 + a];
+        const double m = (fabs(A) <= bound) ? A : minmod3(A, beta * (mean - mlo), beta * (mhi - mean));
+        mt[a] = m;
+        limited |= (m != A);
+      }
+      if (limited) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a) wc[i][1 + a] = mt[a] / r3;
+#pragma unroll
+        for (int l = 3; l < N; ++l) wc[i][l] = 0.0;
+      }
+      dropped[i] = limited;
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    if (dropped[v])
+#pragma unroll
+      for (int l = 1; l < N; ++l) w[(long)(v * N + l) * nl + cell] = wc[v][l];
+}
+
+// Positivity limiter (Sec. 3.4) on a quadtree, one wave per leaf: the union
+// points S and, on each side with finer neighbours, the leaf's trace points
+// on the two half faces (table HG; Sec. 4.4).  A mean without positive
+// density and pressure (<= eps) sets the flag and is left alone.
+template <int K>
+__global__ __launch_bounds__(256) void k_positivity_tree(const double *__restrict__ tab, double *__restrict__ w,
+                                                         TreeGrid g, double eps, int *__restrict__ flag) {
+  using C = Cfg<2, K>;
+  constexpr int N = C::N;
+  const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+  const long nl = g.nleaf;
+  for (long cell = wave; cell < nl; cell += nwaves) {
+    double Ub[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Ub[v] = w[(long)(v * N) * nl + cell];
+    const double ke = (Ub[1] * Ub[1] + Ub[2] * Ub[2]) / Ub[0];
+    const double pb = (g.gamma - 1.0) * (Ub[3] - 0.5 * ke);
+    if (!(Ub[0] > eps) || !(pb > eps)) {
+      if ((threadIdx.x & 63) == 0) atomicOr(flag, FLAG_NEGATIVE);
+      continue;
+    }
+    int hm = 0;
+#pragma unroll
+    for (int side = 0; side < 4; ++side)
+      if ((g.info[(long)side * nl + cell] & 3) == 2) hm |= 1 << side;
+    struct {
+      const double *t;
+      __device__ int count(int h) const { return C::NS + __popc(h) * 2 * C::QF; }
+      __device__ const double *row(int h, int i) const {
+        if (i < C::NS) return t + C::PS + i * N;
+        const int e = i - C::NS, k = e / (2 * C::QF), rem = e % (2 * C::QF);
+        int f = 0, seen = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if ((h >> b) & 1) {
+            if (seen == k) f = b;
+            ++seen;
+          }
+        return t + C::HG + (f * 4 + rem / C::QF) * C::QF * N + (rem % C::QF) * N;
+      }
+    } pts{tab};
+    positivity_cell<2, N>(w + cell, nl, hm, pts, g.gamma, eps);
   }
 }
 
@@ -4955,6 +5114,8 @@ void dg_destroy(dg_ctx *c) {
   if (c->ttab) (void)hipFree(c->ttab);
   if (c->tmap) (void)hipFree(c->tmap);
   if (c->tflags) (void)hipFree(c->tflags);
+  if (c->treg) (void)hipFree(c->treg);
+  if (c->tnbm) (void)hipFree(c->tnbm);
   delete c;
 }
 
@@ -5307,6 +5468,8 @@ int tree_tables(const dg_ctx *c, const std::vector<int32_t> &lv, TreeIndex &ix, 
       } else if (l > 0 && (n0 = ix.find(l - 1, X >> 1, Y >> 1)) >= 0) {
         kind = 3;
         sub = (int)((a == 0 ? y : x) & 1);
+        // the child of the coarse leaf that the same-level cell (X, Y) is (limiters)
+        sub |= (int)(((X & 1) | ((Y & 1) << 1)) << 1);
       } else {
         kind = 2;
         // the two children of the same-level neighbour that touch this face
@@ -5367,6 +5530,46 @@ int tree_install(dg_ctx *c, std::vector<int32_t> lv) {
   st = grow_ints(c->ttab, c->ttab_cap, (long)T.size());
   if (st != DG_OK) return st;
   HIP_TRY(hipMemcpy(c->ttab, T.data(), T.size() * sizeof(int), hipMemcpyHostToDevice));
+  // limiters: per side with finer neighbours the leaves inside the same-level
+  // cell there, in leaf order ([4][nl] offsets, [4][nl] counts, the lists)
+  const long nl = (long)lv.size() / 3;
+  std::vector<int> R((size_t)8 * nl, 0);
+  const int *info = T.data() + nl;
+  for (long i = 0; i < nl; ++i)
+    for (int side = 0; side < 4; ++side) {
+      if ((info[(long)side * nl + i] & 3) != 2) continue;
+      const int a = side >> 1, sd = side & 1, l = lv[3 * i];
+      long X = lv[3 * i + 1] + (a == 0 ? (sd ? 1 : -1) : 0), Y = lv[3 * i + 2] + (a == 1 ? (sd ? 1 : -1) : 0);
+      ix.wrap(l, X, Y);
+      std::vector<int> in;
+      std::vector<std::pair<int, std::pair<long, long>>> st{{l, {X, Y}}};
+      while (!st.empty()) {
+        const auto e = st.back();
+        st.pop_back();
+        const int j = ix.find(e.first, e.second.first, e.second.second);
+        if (j >= 0) {
+          in.push_back(j);
+          continue;
+        }
+        if (e.first >= 24) return DG_EINVAL;
+        for (int ch = 0; ch < 4; ++ch)
+          st.push_back({e.first + 1, {2 * e.second.first + (ch & 1), 2 * e.second.second + (ch >> 1)}});
+      }
+      std::sort(in.begin(), in.end());
+      R[(size_t)(side * nl + i)] = (int)(R.size() - 8 * nl);
+      R[(size_t)(4 * nl + side * nl + i)] = (int)in.size();
+      R.insert(R.end(), in.begin(), in.end());
+    }
+  st = grow_ints(c->treg, c->treg_cap, (long)R.size());
+  if (st != DG_OK) return st;
+  HIP_TRY(hipMemcpy(c->treg, R.data(), R.size() * sizeof(int), hipMemcpyHostToDevice));
+  if (16 * nl > c->tnbm_cap) {
+    if (c->tnbm) (void)hipFree(c->tnbm);
+    c->tnbm = nullptr;
+    c->tnbm_cap = 0;
+    HIP_TRY(hipMalloc((void **)&c->tnbm, (size_t)16 * nl * sizeof(double)));
+    c->tnbm_cap = 16 * nl;
+  }
   c->tleaves = std::move(lv);
   c->tree = true;
   c->tnext.clear();
@@ -5569,9 +5772,38 @@ struct TreeRegrid {
   }
 };
 
+struct TreeLimit {
+  dg_ctx *c;
+  double *w;
+  hipStream_t s;
+  template <int K>
+  int run() {
+    const dg::TreeGrid g = make_tree_grid(c);
+    if (c->cfg.slope_limiter != DG_LIM_NONE) {
+      hipLaunchKernelGGL((dg::k_tree_nbmean<K>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w, g, c->treg,
+                         c->tnbm);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL((c->cfg.slope_limiter == DG_LIM_CHAR ? dg::k_limit_tree<K, true> : dg::k_limit_tree<K, false>),
+                         dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, w, g, c->tnbm, c->cfg.beta, c->cfg.m_tilde);
+      HIP_TRY(hipGetLastError());
+    }
+    if (c->cfg.positivity) {
+      const unsigned nb = (unsigned)std::min<long>(4096, (g.nleaf + 3) / 4);
+      hipLaunchKernelGGL((dg::k_positivity_tree<K>), dim3(nb), dim3(kBlock), 0, s, c->tab, w, g, c->cfg.eps, c->flag);
+      HIP_TRY(hipGetLastError());
+    }
+    return DG_OK;
+  }
+};
+
 }  // namespace
 
 extern "C" {
+
+int dg_tree_limit(dg_ctx *c, double *w, void *stream) {
+  if (!c || !w || !c->tree) return DG_EINVAL;
+  return tree_dispatch(c, TreeLimit{c, w, (hipStream_t)stream});
+}
 
 int dg_tree_set(dg_ctx *c, int64_t nleaf, const int32_t *leaves) {
   if (!c || !leaves || nleaf < 1) return DG_EINVAL;

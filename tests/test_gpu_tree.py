@@ -121,3 +121,103 @@ def test_tree_set_rejects_invalid_meshes():
             s.set_leaves(bad)
     s.set_leaves(good)
     assert s.nleaf == 16
+
+
+LIMITED = {
+    # KH with the shear layers cutting cells; eps just below the outer density
+    # makes the positivity limiter act near the jumps
+    "k2_minmod_random3": (lambda: _kh((10, 10), 2, limiter=1, positivity=1, eps=0.95, x0=(0.0, -0.01, 0.0)),
+                          lambda: workloads.random_tree((10, 10), 3, 0.4, 17)),
+    "k3_char_band3": (lambda: _kh((10, 10), 3, limiter=2, positivity=1, eps=0.95, x0=(0.0, -0.01, 0.0)),
+                      lambda: workloads.band_tree((10, 10), 3)),
+    "k1_minmod_walls": (lambda: _kh((10, 10), 1, limiter=1, positivity=1, eps=0.95, bc=(1, 1, 0),
+                                    x0=(0.0, -0.01, 0.0)),
+                        lambda: workloads.random_tree((10, 10), 2, 0.5, 4, periodic=(False, False))),
+}
+
+
+@pytest.mark.parametrize("case", list(LIMITED))
+def test_tree_limiter_matches_oracle(case):
+    wl = LIMITED[case][0]()
+    leaves = LIMITED[case][1]()
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    ref, st = o.limit(w)
+    assert st == 0
+    assert np.abs(ref - w).max() > 1e-3
+    s = dg.TreeSolver(wl, leaves)
+    got = s.limit(torch.from_numpy(w).cuda()).cpu().numpy()
+    assert s.status() == 0
+    check_state_modes(got, ref, case)
+    assert np.array_equal(got[:, 0], w[:, 0])  # means are never changed
+
+
+@pytest.mark.parametrize("case", list(LIMITED))
+def test_tree_limited_steps_match_oracle(case):
+    wl = LIMITED[case][0]()
+    leaves = LIMITED[case][1]()
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    s = dg.TreeSolver(wl, leaves)
+    wg = torch.from_numpy(w).cuda()
+    bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+    ref = w
+    for it in range(2):
+        ref, dt = o.step(ref)
+        out = s.step(wg, bufs)
+        assert float(bufs[3].item()) == pytest.approx(dt, rel=1e-14)
+        check_state_modes(out.cpu().numpy(), ref, f"{case} limited step {it + 1}")
+        wg = out.clone()
+    assert s.status() == 0
+
+
+def test_tree_positivity_at_hanging_face_points():
+    """A coarse leaf next to finer ones whose density dips lowest at a trace
+    point of a half face, not at a union point: only the extra points of the
+    refinement boundary make the positivity limiter act (oracle pin
+    test_tree_positivity_checks_the_hanging_face_points, same input)."""
+    n = (6, 6)
+    wl = _kh(n, 3, limiter=0, positivity=1, eps=0.52)
+    leaves = [(0, x, y) for y in range(6) for x in range(6) if not (2 <= x < 4 and 2 <= y < 4)]
+    leaves += [(1, x, y) for y in range(4, 8) for x in range(4, 8)]
+    leaves = np.array(leaves)
+    o = oracle.TreeOracle(wl, leaves)
+    xi, _ = o.volume_rule()
+    g, _ = oracle.gauss(4)
+    eta = 0.5 * (g.max() + 1.0)
+    prim = np.zeros((len(leaves), o.Q, 5))
+    prim[..., 0] = 1.0
+    prim[..., 4] = 2.5
+    target = [i for i, (l, x, y) in enumerate(leaves) if l == 0 and x == 1 and 2 <= y < 4]
+    for i in target:
+        prim[i, :, 0] = 1.0 + 10.0 * ((xi[:, 1] - eta) ** 2 - 0.05)
+    w = o.project_prim(prim)
+    ref, st = o.limit(w)
+    assert st == 0 and np.abs(ref[:, :, target] - w[:, :, target]).max() > 1e-3
+    s = dg.TreeSolver(wl, leaves)
+    got = s.limit(torch.from_numpy(w).cuda()).cpu().numpy()
+    check_state_modes(got, ref, "hanging-face positivity")
+
+
+def test_adaptive_limited_kh_matches_oracle():
+    """The KH run as the paper sets it up (characteristic limiter and
+    positivity after every stage, adaptation before every step), three steps
+    to four levels."""
+    n = (10, 10)
+    wl = _kh(n, 3, limiter=2, positivity=1, eps=1e-8, x0=(0.0, -0.01, 0.0))
+    leaves = workloads.band_tree(n, 1)
+    o = oracle.TreeOracle(wl, leaves)
+    w = o.initial_state()
+    s = dg.TreeSolver(wl, leaves)
+    wg = torch.from_numpy(w).cuda()
+    for it in range(3):
+        leaves_o, w = oracle.tree_adapt(wl, o.leaves, w, 0.01, 1.1, 3)
+        wg = s.adapt(wg, 0.01, 1.1, 3)
+        assert np.array_equal(s.leaves, leaves_o)
+        o = oracle.TreeOracle(wl, leaves_o)
+        w, dt = o.step(w)
+        bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+        wg = s.step(wg, bufs).clone()
+        check_state_modes(wg.cpu().numpy(), w, f"limited adaptive step {it + 1}")
+        say(f"step {it + 1}: {len(leaves_o)} leaves, per level {np.bincount(leaves_o[:, 0])}")
+    assert s.status() == 0
