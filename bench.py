@@ -431,6 +431,8 @@ def variants():
                                  "adapt_ms_per_check": t_adapt / (nsteps // every) * 1e3, "status": st}
     del s
     torch.cuda.empty_cache()
+    out["kh2d_tree_fp64"] = tree_variant()
+    torch.cuda.empty_cache()
     # adjoint: 512^2, k=3, J = int rho^2 after 400 steps at fixed dt, checkpoint 20
     wl = workloads.workload("vortex_adjoint")
     s = dg.Solver(wl)
@@ -466,6 +468,94 @@ def variants():
                                    "fd_directions": len(fd), "fd_rel_err_max_h1e-6": max(fd),
                                    "fd_rel_err_median_h1e-6": float(np.median(fd))}
     return out
+
+
+def tree_variant(max_level: int = 5, steps: int = 100, reps: int = 30):
+    """The KH setup on the quadtree (Sec. 4): base 64^2 (the paper's level 6),
+    k = 3, SSP-RK3, characteristic limiter and positivity after every stage,
+    the mesh adapted to the criterion (w_t = 0.01, alpha = 1.1) down to
+    max_level levels below the base (the origin shifted by 0.3 base cells in
+    y, so that the sharp layers cut cells on every level).  Times the step
+    (time step, three fused RHS/stage launches, three limiter passes; graph
+    replay, state resident), one adaptation (criterion, plan, regrid) and the
+    stage kernel alone (HIP events)."""
+    import torch
+    import paper_1506_06140_amd as dg
+    n = 64
+    wl = workloads.workload("kh2d", rk="rk3", x0=(0.0, -0.3 / n, 0.0))
+    leaves = np.array([(0, x, y) for y in range(n) for x in range(n)])
+    s = dg.TreeSolver(wl, leaves)
+    w = s.project(torch.from_numpy(np.ascontiguousarray(np.stack(
+        _tree_prims(s, wl)))).cuda())
+    s.limit(w)
+    for _ in range(max_level + 1):
+        w = s.adapt(w, wl["wt"], wl["alpha"], max_level)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    w = s.adapt(w, wl["wt"], wl["alpha"], max_level)
+    torch.cuda.synchronize()
+    t_adapt = time.perf_counter() - t0
+    A, B = w, s.empty()
+    bufs = [s.empty(), s.empty()]
+    dt = s.scalar()
+
+    def two_steps():
+        s.step(A, bufs + [B, dt])
+        s.step(B, bufs + [A, dt])
+    two_steps()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        two_steps()
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        two_steps()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps // 2):
+        g.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    st = s.status()
+    # the stage kernel alone: HIP events around `reps` launches on the stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.rk_stage(1, dt, None, A, bufs[0])
+    ev0.record()
+    for _ in range(reps):
+        s.rk_stage(1, dt, None, A, bufs[0])
+    ev1.record()
+    torch.cuda.synchronize()
+    kms = ev0.elapsed_time(ev1) / reps
+    lv = s.leaves[:, 0]
+    _, f3 = alg_work(2, 3)
+    cells = int(s.nleaf)
+    area = 0.25 ** lv
+    rec = {"base": [n, n], "k": 3, "max_level": max_level, "leaves": cells,
+           "leaves_per_level": np.bincount(lv).tolist(),
+           "refined_leaf_fraction": float((lv > 0).mean()), "refined_area_fraction": float(area[lv > 0].sum() / area.sum()),
+           "uniform_equivalent_cells": (n << max_level) ** 2,
+           "ms_per_step": ms, "dof_updates_per_s": cells * s.N * 3 / (ms * 1e-3),
+           "adapt_ms": t_adapt * 1e3, "stage_kernel": "k_rhs_tree<3,0>", "stage_kernel_ms": kms,
+           "stage_kernel_alu_frac": f3 * cells / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, "status": st}
+    del s, A, B, bufs
+    torch.cuda.empty_cache()
+    return rec
+
+
+def _tree_prims(s, wl):
+    """Primitive fields of the workload at every leaf's volume nodes,
+    [5][Q][nleaf] (the library projects them)."""
+    xi, _ = s.quadrature()
+    lv = s.leaves
+    h = wl["length"][0] / wl["n"][0] / (2.0 ** lv[:, 0])
+    x = wl["x0"][0] + h[None, :] * (lv[:, 1][None, :] + 0.5 * (1.0 + xi[:, 0][:, None]))
+    y = wl["x0"][1] + h[None, :] * (lv[:, 2][None, :] + 0.5 * (1.0 + xi[:, 1][:, None]))
+    wlq = dict(wl, nq=s.Q)
+    return workloads.primitives(wlq, x, y, np.zeros_like(x))
 
 
 def kernel_ms(s, w, bufs, reps, limiter=False):

@@ -152,7 +152,8 @@ int dg_quadrature(const dg_ctx *ctx, double *xi, double *w);
 /* L2 projection of initial data (Sec. 2.3): prim is a device array
  * [5][Q][cells] of primitive values (rho, v_x, v_y, v_z, p) at the Gauss
  * volume nodes of every cell (with a refined box: the coarse block's cells,
- * then the fine block's); w receives the state. */
+ * then the fine block's; on a quadtree mesh set by dg_tree_set: the leaves
+ * in mesh order); w receives the state. */
 int dg_project(dg_ctx *ctx, const double *prim, double *w, void *stream);
 
 /* L = dw/dt = -R_K of eq. spatial_discretisation for every cell: volume

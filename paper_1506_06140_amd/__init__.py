@@ -463,6 +463,7 @@ class TreeSolver(Solver):
         _check(self.lib.dg_tree_leaves(self.ctx, lv.ctypes.data_as(C.POINTER(C.c_int32))), "dg_tree_leaves")
         self.leaves = lv.astype(np.int64)
         self.nleaf = n.value
+        self.ncell = self.nleaf
         self.shape = (self.nvar, self.N, self.nleaf)
         self.size = self.nvar * self.N * self.nleaf
 

@@ -4481,7 +4481,11 @@ struct ProjectLaunch {
   hipStream_t s;
   template <int D, int K>
   int run() {
-    if (!c->amr) {
+    if (c->tree) {
+      const long nl = (long)c->tleaves.size() / 3;
+      hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(nl)), dim3(kBlock), 0, s, c->tab, prim, nl, 0L, w, nl,
+                         c->cfg.gamma);
+    } else if (!c->amr) {
       hipLaunchKernelGGL((dg::k_project<D, K>), dim3(nblocks(c->ncell)), dim3(kBlock), 0, s, c->tab, prim, c->ncell,
                          0L, w, c->ncell, c->cfg.gamma);
     } else {
@@ -5387,6 +5391,12 @@ int dg_status(dg_ctx *c, void *stream) {
 // ===========================================================================
 namespace {
 
+// Tree kernels run one thread per leaf; a mesh of tens of thousands of
+// leaves is a few hundred waves, so blocks of one wave spread them over all
+// 256 CUs (256-thread blocks left a third of the CUs without work).
+constexpr int kTreeBlock = 64;
+unsigned tree_blocks(long n) { return (unsigned)((n + kTreeBlock - 1) / kTreeBlock); }
+
 inline uint64_t tkey(int l, long x, long y) { return ((uint64_t)l << 58) | ((uint64_t)x << 29) | (uint64_t)y; }
 
 constexpr int kTreeInts = 17;  // per leaf: level, 4 face infos, 8 neighbours, 4 group members
@@ -5732,11 +5742,11 @@ struct TreeStage {
   int run() {
     const dg::TreeGrid g = make_tree_grid(c);
     if (c->cfg.flux == DG_HLLC_DAVIS)
-      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_DAVIS>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w,
-                         out, dt, g, mode, mx, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_DAVIS>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s,
+                         c->tab, w, out, dt, g, mode, mx, c->flag);
     else
-      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_BATTEN>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w,
-                         out, dt, g, mode, mx, c->flag);
+      hipLaunchKernelGGL((dg::k_rhs_tree<K, DG_HLLC_BATTEN>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s,
+                         c->tab, w, out, dt, g, mode, mx, c->flag);
     HIP_TRY(hipGetLastError());
     return DG_OK;
   }
@@ -5780,11 +5790,12 @@ struct TreeLimit {
   int run() {
     const dg::TreeGrid g = make_tree_grid(c);
     if (c->cfg.slope_limiter != DG_LIM_NONE) {
-      hipLaunchKernelGGL((dg::k_tree_nbmean<K>), dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, c->tab, w, g, c->treg,
-                         c->tnbm);
+      hipLaunchKernelGGL((dg::k_tree_nbmean<K>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, c->tab, w, g,
+                         c->treg, c->tnbm);
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL((c->cfg.slope_limiter == DG_LIM_CHAR ? dg::k_limit_tree<K, true> : dg::k_limit_tree<K, false>),
-                         dim3(nblocks(g.nleaf)), dim3(kBlock), 0, s, w, g, c->tnbm, c->cfg.beta, c->cfg.m_tilde);
+                         dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, w, g, c->tnbm, c->cfg.beta,
+                         c->cfg.m_tilde);
       HIP_TRY(hipGetLastError());
     }
     if (c->cfg.positivity) {

@@ -221,3 +221,16 @@ def test_adaptive_limited_kh_matches_oracle():
         check_state_modes(wg.cpu().numpy(), w, f"limited adaptive step {it + 1}")
         say(f"step {it + 1}: {len(leaves_o)} leaves, per level {np.bincount(leaves_o[:, 0])}")
     assert s.status() == 0
+
+
+def test_tree_projection_matches_oracle():
+    wl = _kh((10, 10), 3, x0=(0.0, -0.01, 0.0))
+    leaves = workloads.random_tree((10, 10), 3, 0.4, 8)
+    o = oracle.TreeOracle(wl, leaves)
+    x = o.node_coords()  # [nleaf][Q][3]
+    wlq = dict(wl, nq=o.Q)
+    prim = np.stack(workloads.primitives(wlq, x[..., 0], x[..., 1], x[..., 2]), axis=-1)  # [nleaf][Q][5]
+    ref = o.project_prim(prim)
+    s = dg.TreeSolver(wl, leaves)
+    got = s.project(torch.from_numpy(np.ascontiguousarray(prim.transpose(2, 1, 0))).cuda()).cpu().numpy()
+    check_state_modes(got, ref, "tree projection")
