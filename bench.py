@@ -591,25 +591,28 @@ def kernel_ms(s, w, bufs, reps, limiter=False):
     return timed(True) - t_stage if limiter else t_stage
 
 
-def vortex2d_line(steps=400, warmup=20, with_cpu=True, reps=300):
-    """The 2D vortex (256^2, k = 2, FP64, no limiter) with its stage kernel's
-    HBM roofline: the state (12.6 MB) stays in the 256 MB Infinity Cache."""
+def vortex2d_line(steps=400, warmup=20, with_cpu=True, reps=300, n=256, k=2, precision="fp64"):
+    """The 2D vortex (n^2, degree k, no limiter) with its stage kernel's HBM
+    roofline.  256^2, k = 2 (12.6 MB) stays in the 256 MB Infinity Cache;
+    512^2, k = 3 is the adjoint workload's grid (84 MB, three states 252 MB)."""
     import paper_1506_06140_amd as dg
-    wl = workloads.workload("vortex")
-    s = dg.Solver(wl)
+    wl = workloads.workload("vortex", n=(n, n, 1), k=k)
+    s = dg.Solver(wl, precision)
     ms, w = time_steps(s, wl, steps, warmup)
     bufs = [s.empty(), s.empty(), s.empty(), s.scalar()]
-    k = kernel_ms(s, w, bufs, reps)
-    b, f = alg_work(2, 2)
+    kms = kernel_ms(s, w, bufs, reps)
+    b, f = alg_work(2, k)
     alg_bytes = b * s.ncell
-    achieved = alg_bytes / (k * 1e-3) / 1e9
-    out = {"workload": "isentropic vortex 2D, 256x256 cells, k=2 (N=6), FP64, SSP-RK3, CFL 0.2, no limiter, "
-                       "seeded 1e-3 density noise",
+    achieved = alg_bytes / (kms * 1e-3) / 1e9
+    base = (n, k, precision) == (256, 2, "fp64")
+    out = {"workload": f"isentropic vortex 2D, {n}x{n} cells, k={k} (N={s.N}), {precision.upper()}, SSP-RK3, "
+                       "CFL 0.2, no limiter, seeded 1e-3 density noise",
            "ms_per_step": ms, "dof_updates_per_s": s.ncell * s.N * 3 / (ms * 1e-3),
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("tile2d"),
-                        "kernel": KERNELS["tile2d"]["name"], "kernel_ms": k, "alg_bytes_per_launch": alg_bytes,
-                        "fp64_frac": f * s.ncell / (k * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic("tile2d") if base else None,
+                        "kernel": f"k_rhs_tile2d<{k},{'double' if precision == 'fp64' else 'float'}>",
+                        "kernel_ms": kms, "alg_bytes_per_launch": alg_bytes,
+                        "fp64_frac": f * s.ncell / (kms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS}}
     if with_cpu:
         out["cpu_baseline"] = cpu_baseline_2d(wl)
     return out
@@ -624,7 +627,8 @@ def main():
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a HIP graph")
     ap.add_argument("--variants", type=int, default=1, help="also time FP32, the 3D workload and the adjoint")
     ap.add_argument("--kernel-reps", type=int, default=30, help="launches per kernel timing")
-    ap.add_argument("--workload", default="kh3d", choices=("kh3d", "blast_amr", "vortex"),
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"), help="2D vortex lines only")
+    ap.add_argument("--workload", default="kh3d", choices=("kh3d", "blast_amr", "vortex", "vortex512"),
                     help="the timed workload: the 128^3 shear layer (the headline), the 64^3 blast with its refined "
                          "box (k = 3), or the 2D vortex 256^2 (its line alone, for profiling the 2D kernel)")
     args = ap.parse_args()
@@ -635,9 +639,11 @@ def main():
     import torch
     import paper_1506_06140_amd as dg
 
-    if args.workload == "vortex":
-        print(json.dumps(vortex2d_line(steps=args.steps, warmup=args.warmup, with_cpu=not args.no_cpu,
-                                       reps=args.kernel_reps)), flush=True)
+    if args.workload in ("vortex", "vortex512"):
+        n, k = (256, 2) if args.workload == "vortex" else (512, 3)
+        print(json.dumps(vortex2d_line(steps=args.steps, warmup=args.warmup,
+                                       with_cpu=not args.no_cpu and args.workload == "vortex",
+                                       reps=args.kernel_reps, n=n, k=k, precision=args.precision)), flush=True)
         return
 
     wl = workloads.workload(args.workload)
