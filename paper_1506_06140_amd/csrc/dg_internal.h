@@ -102,7 +102,8 @@ struct dg_ctx {
   std::vector<int32_t> tleaves, tnext;
   std::vector<int> trk, tsrc;
   int *ttab = nullptr, *tmap = nullptr, *tflags = nullptr, *treg = nullptr;
-  long ttab_cap = 0, tmap_cap = 0, tflags_cap = 0, treg_cap = 0;
+  int *tplist = nullptr;  // positivity: count, then the leaves that need the point loop
+  long ttab_cap = 0, tmap_cap = 0, tflags_cap = 0, treg_cap = 0, tplist_cap = 0;
   double *tnbm = nullptr;  // limiters' neighbour values [4][nvar][nleaf]
   long tnbm_cap = 0;
 };

@@ -4106,28 +4106,48 @@ __global__ __launch_bounds__(256) void k_limit_tree(double *__restrict__ w, Tree
       for (int l = 1; l < N; ++l) w[(long)(v * N + l) * nl + cell] = wc[v][l];
 }
 
-// Positivity limiter (Sec. 3.4) on a quadtree, one wave per leaf: the union
-// points S and, on each side with finer neighbours, the leaf's trace points
-// on the two half faces (table HG; Sec. 4.4).  A mean without positive
-// density and pressure (<= eps) sets the flag and is left alone.
+// Positivity limiter (Sec. 3.4) on a quadtree, in two passes as on uniform
+// grids.  k_tree_poscheck, one thread per leaf: a mean without positive
+// density and pressure (<= eps) sets the flag and is left alone; a leaf whose
+// polynomial provably stays above eps everywhere in the cell (basis bounds,
+// positivity_certain: theta_1 = theta_2 = 1 exactly) needs nothing; the
+// others go to the list plist.  k_positivity_tree, one wave per listed leaf:
+// the points S and, on each side with finer neighbours, the leaf's trace
+// points on the two half faces (table HG; Sec. 4.4).
+template <int K>
+__global__ __launch_bounds__(256) void k_tree_poscheck(const double *__restrict__ w, TreeGrid g, double eps,
+                                                       int *__restrict__ flag, int *__restrict__ plist) {
+  using C = Cfg<2, K>;
+  constexpr int NV = C::NV, N = C::N;
+  // lanes past the mesh stay in the wave (the list is appended per wave) on a
+  // copy of the last leaf, and append nothing
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = tid < g.nleaf;
+  const long cell = act ? tid : g.nleaf - 1;
+  const long nl = g.nleaf;
+  double wc[NV][N];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+#pragma unroll
+    for (int l = 0; l < N; ++l) wc[v][l] = w[(long)(v * N + l) * nl + cell];
+  const double ke = (wc[1][0] * wc[1][0] + wc[2][0] * wc[2][0]) / wc[0][0];
+  const double pb = (g.gamma - 1.0) * (wc[3][0] - 0.5 * ke);
+  const bool bad = !(wc[0][0] > eps) || !(pb > eps);
+  if (bad && act) atomicOr(flag, FLAG_NEGATIVE);
+  wave_append(act && !bad && !positivity_certain<2, N>(wc, g.gamma, eps), (int)cell, plist);
+}
+
 template <int K>
 __global__ __launch_bounds__(256) void k_positivity_tree(const double *__restrict__ tab, double *__restrict__ w,
-                                                         TreeGrid g, double eps, int *__restrict__ flag) {
+                                                         TreeGrid g, const int *__restrict__ plist, double eps) {
   using C = Cfg<2, K>;
   constexpr int N = C::N;
   const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
   const long nl = g.nleaf;
-  for (long cell = wave; cell < nl; cell += nwaves) {
-    double Ub[4];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Ub[v] = w[(long)(v * N) * nl + cell];
-    const double ke = (Ub[1] * Ub[1] + Ub[2] * Ub[2]) / Ub[0];
-    const double pb = (g.gamma - 1.0) * (Ub[3] - 0.5 * ke);
-    if (!(Ub[0] > eps) || !(pb > eps)) {
-      if ((threadIdx.x & 63) == 0) atomicOr(flag, FLAG_NEGATIVE);
-      continue;
-    }
+  const int cnt = plist[0];
+  for (long t = wave; t < cnt; t += nwaves) {
+    const long cell = plist[1 + t];
     int hm = 0;
 #pragma unroll
     for (int side = 0; side < 4; ++side)
@@ -5119,6 +5139,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->tmap) (void)hipFree(c->tmap);
   if (c->tflags) (void)hipFree(c->tflags);
   if (c->treg) (void)hipFree(c->treg);
+  if (c->tplist) (void)hipFree(c->tplist);
   if (c->tnbm) (void)hipFree(c->tnbm);
   delete c;
 }
@@ -5570,6 +5591,8 @@ int tree_install(dg_ctx *c, std::vector<int32_t> lv) {
       R[(size_t)(4 * nl + side * nl + i)] = (int)in.size();
       R.insert(R.end(), in.begin(), in.end());
     }
+  st = grow_ints(c->tplist, c->tplist_cap, nl + 1);
+  if (st != DG_OK) return st;
   st = grow_ints(c->treg, c->treg_cap, (long)R.size());
   if (st != DG_OK) return st;
   HIP_TRY(hipMemcpy(c->treg, R.data(), R.size() * sizeof(int), hipMemcpyHostToDevice));
@@ -5799,8 +5822,15 @@ struct TreeLimit {
       HIP_TRY(hipGetLastError());
     }
     if (c->cfg.positivity) {
-      const unsigned nb = (unsigned)std::min<long>(4096, (g.nleaf + 3) / 4);
-      hipLaunchKernelGGL((dg::k_positivity_tree<K>), dim3(nb), dim3(kBlock), 0, s, c->tab, w, g, c->cfg.eps, c->flag);
+      // the count is cleared by a kernel (no memset), so the pass can be captured
+      hipLaunchKernelGGL(dg::k_zero_count, dim3(1), dim3(1), 0, s, c->tplist);
+      HIP_TRY(hipGetLastError());
+      hipLaunchKernelGGL((dg::k_tree_poscheck<K>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, w, g,
+                         c->cfg.eps, c->flag, c->tplist);
+      HIP_TRY(hipGetLastError());
+      const unsigned nb = (unsigned)std::min<long>(1024, std::max<long>(1, (g.nleaf + 255) / 256));
+      hipLaunchKernelGGL((dg::k_positivity_tree<K>), dim3(nb), dim3(kBlock), 0, s, c->tab, w, g, c->tplist,
+                         c->cfg.eps);
       HIP_TRY(hipGetLastError());
     }
     return DG_OK;
