@@ -4003,13 +4003,16 @@ namespace dg {
 // leaf's polynomial averaged over that cell (table CM, child `ch`), the
 // area-weighted means of the finer leaves inside it (list `reg`), or at a
 // transmissive wall the leaf's own mean.  nbm[(side NV + v) nleaf + leaf].
+// plist (may be null): the positivity list, whose count this pass clears for
+// the slope pass after it (kernel boundaries order the two).
 template <int K>
 __global__ __launch_bounds__(256) void k_tree_nbmean(const double *__restrict__ tab, const double *__restrict__ w,
                                                      TreeGrid g, const int *__restrict__ reg,
-                                                     double *__restrict__ nbm) {
+                                                     double *__restrict__ nbm, int *__restrict__ plist) {
   using C = Cfg<2, K>;
   constexpr int NV = C::NV, N = C::N;
   const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (plist && cell == 0) plist[0] = 0;
   if (cell >= g.nleaf) return;
   const long nl = g.nleaf;
   const int *roff = reg, *rcnt = reg + 4 * nl, *rlist = reg + 8 * nl;
@@ -4051,13 +4054,18 @@ __global__ __launch_bounds__(256) void k_tree_nbmean(const double *__restrict__ 
 // Slope limiter on a quadtree (component-wise, eq. comp_limiter, or on the
 // characteristic variables, eq. char_limiter) against the neighbour values
 // of k_tree_nbmean, with the TVB bound of the leaf's own edge (Sec. 3.3).
+// With plist set it also does k_tree_poscheck's work on the limited leaf.
 template <int K, bool CHAR>
 __global__ __launch_bounds__(256) void k_limit_tree(double *__restrict__ w, TreeGrid g, const double *__restrict__ nbm,
-                                                    double beta, double mtilde) {
+                                                    double beta, double mtilde, double eps, int *__restrict__ flag,
+                                                    int *__restrict__ plist) {
   using C = Cfg<2, K>;
   constexpr int NV = C::NV, N = C::N;
-  const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= g.nleaf) return;
+  // lanes past the mesh stay in the wave (the list is appended per wave) on a
+  // copy of the last leaf, and store nothing
+  const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = tid < g.nleaf;
+  const long cell = act ? tid : g.nleaf - 1;
   const long nl = g.nleaf;
   const double bound = mtilde * (g.dx0 / (double)(1 << g.lev[cell]));
   double wc[NV][N];
@@ -4099,11 +4107,19 @@ __global__ __launch_bounds__(256) void k_limit_tree(double *__restrict__ w, Tree
       dropped[i] = limited;
     }
   }
+  if (act)
 #pragma unroll
-  for (int v = 0; v < NV; ++v)
-    if (dropped[v])
+    for (int v = 0; v < NV; ++v)
+      if (dropped[v])
 #pragma unroll
-      for (int l = 1; l < N; ++l) w[(long)(v * N + l) * nl + cell] = wc[v][l];
+        for (int l = 1; l < N; ++l) w[(long)(v * N + l) * nl + cell] = wc[v][l];
+  if (plist) {
+    const double ke = (wc[1][0] * wc[1][0] + wc[2][0] * wc[2][0]) / wc[0][0];
+    const double pb = (g.gamma - 1.0) * (wc[3][0] - 0.5 * ke);
+    const bool bad = !(wc[0][0] > eps) || !(pb > eps);
+    if (bad && act) atomicOr(flag, FLAG_NEGATIVE);
+    wave_append(act && !bad && !positivity_certain<2, N>(wc, g.gamma, eps), (int)cell, plist);
+  }
 }
 
 // Positivity limiter (Sec. 3.4) on a quadtree, in two passes as on uniform
@@ -5812,22 +5828,27 @@ struct TreeLimit {
   template <int K>
   int run() {
     const dg::TreeGrid g = make_tree_grid(c);
+    const bool posit = c->cfg.positivity != 0;
+    // the positivity list's count is cleared by a kernel (no memset), so the
+    // pass can be captured; with the slope limiter on, its two kernels clear
+    // the count and fill the list themselves
+    int *pl = posit ? c->tplist : nullptr;
     if (c->cfg.slope_limiter != DG_LIM_NONE) {
       hipLaunchKernelGGL((dg::k_tree_nbmean<K>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, c->tab, w, g,
-                         c->treg, c->tnbm);
+                         c->treg, c->tnbm, pl);
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL((c->cfg.slope_limiter == DG_LIM_CHAR ? dg::k_limit_tree<K, true> : dg::k_limit_tree<K, false>),
                          dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, w, g, c->tnbm, c->cfg.beta,
-                         c->cfg.m_tilde);
+                         c->cfg.m_tilde, c->cfg.eps, c->flag, pl);
       HIP_TRY(hipGetLastError());
-    }
-    if (c->cfg.positivity) {
-      // the count is cleared by a kernel (no memset), so the pass can be captured
+    } else if (posit) {
       hipLaunchKernelGGL(dg::k_zero_count, dim3(1), dim3(1), 0, s, c->tplist);
       HIP_TRY(hipGetLastError());
       hipLaunchKernelGGL((dg::k_tree_poscheck<K>), dim3(tree_blocks(g.nleaf)), dim3(kTreeBlock), 0, s, w, g,
                          c->cfg.eps, c->flag, c->tplist);
       HIP_TRY(hipGetLastError());
+    }
+    if (posit) {
       const unsigned nb = (unsigned)std::min<long>(1024, std::max<long>(1, (g.nleaf + 255) / 256));
       hipLaunchKernelGGL((dg::k_positivity_tree<K>), dim3(nb), dim3(kBlock), 0, s, c->tab, w, g, c->tplist,
                          c->cfg.eps);
