@@ -120,6 +120,8 @@ def _load():
             "orc_tree_rhs": [cp, C.c_long, ip, lp, lp, dp, dp],
             "orc_tree_terms": [cp, C.c_long, ip, lp, lp, dp, dp, dp, dp],
             "orc_tree_limit": [cp, C.c_long, ip, lp, lp, dp],
+            "orc_tree_terms_cells": [cp, C.c_long, ip, lp, lp, dp, C.c_long, lp, dp, dp, dp],
+            "orc_tree_limit_cells": [cp, C.c_long, ip, lp, lp, dp, C.c_long, lp],
             "orc_tree_max_dt": [cp, C.c_long, ip, lp, lp, dp, dp],
             "orc_tree_node_coords": [cp, C.c_long, ip, lp, lp, dp],
             "orc_tree_project": [cp, C.c_long, ip, lp, lp, dp, dp],
@@ -749,6 +751,24 @@ class TreeOracle(Oracle):
 
     def rk3_stage(self, stage: int, dt: float, wn, wp) -> np.ndarray:
         return rk3_combine(stage, dt, wn, wp, self.rhs(wp))
+
+    def terms_cells(self, w: np.ndarray, cells):
+        """(fac V, fac S, fac A) of the listed leaves, each [nvar][N][len(cells)]."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        sh = (self.nvar, self.N, cells.size)
+        V, S, A = np.zeros(sh), np.zeros(sh), np.zeros(sh)
+        _check(lib.orc_tree_terms_cells(*self._a(), self._s(w), cells.size, cells, V, S, A), "tree_terms_cells")
+        return V, S, A
+
+    def limit_cells(self, w: np.ndarray, cells):
+        """The limiters on the listed leaves of w (neighbour values from w):
+        ([nvar][N][len(cells)], status)."""
+        lib, _ = _load()
+        cells = np.ascontiguousarray(cells, dtype=np.int64)
+        out = np.array(self._s(w), copy=True)
+        st = lib.orc_tree_limit_cells(*self._a(), out, cells.size, cells)
+        return out[:, :, cells], st
 
     def limit(self, w: np.ndarray):
         """Slope then positivity limiter with the AMR rules of Sec. 4.4:

@@ -2156,16 +2156,19 @@ static int tree_surface(const tree *T, const double *w, long i, double S[MAXV][M
   return ORC_OK;
 }
 
-/* fac V and fac S of every leaf (L = V - S), fac = (2/dx_i) 2^-d with the
- * leaf's own edge; Ao (may be NULL): fac times the summed magnitudes of every
- * summand of V and S (the rounding scale of each element). */
-int orc_tree_terms(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
-                   const double *w, double *Vo, double *So, double *Ao) {
+/* fac V and fac S (L = V - S), fac = (2/dx_i) 2^-d with the leaf's own
+ * edge, of the listed leaves (cells[0..ncells), all leaves if cells is NULL),
+ * out[nvar][N][ncells]; Ao (may be NULL): fac times the summed magnitudes of
+ * every summand of V and S (the rounding scale of each element). */
+static int tree_terms(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                      const double *w, long ncells, const long *cells, double *Vo, double *So, double *Ao) {
   tree *T = malloc(sizeof(tree));
   int st = tree_init(c, nleaf, lev, ix, iy, T);
   if (st != ORC_OK) { free(T); return st; }
   const ctx *X = &T->X;
-  for (long i = 0; i < nleaf && st == ORC_OK; ++i) {
+  for (long k = 0; k < ncells && st == ORC_OK; ++k) {
+    long i = cells ? cells[k] : k;
+    if (i < 0 || i >= nleaf) { st = ORC_EINVAL; break; }
     double V[MAXV][MAXN], S[MAXV][MAXN], A[MAXV][MAXN];
     memset(A, 0, sizeof(A));
     volume_term(X, w, i, V, A);
@@ -2174,7 +2177,7 @@ int orc_tree_terms(const orc_config *c, long nleaf, const int *lev, const long *
     double fac = 2.0 / dxi / 4.0;
     for (int v = 0; v < X->nvar; ++v)
       for (int j = 0; j < X->N; ++j) {
-        long e = ((long)v * X->N + j) * nleaf + i;
+        long e = ((long)v * X->N + j) * ncells + k;
         Vo[e] = fac * V[v][j];
         So[e] = fac * S[v][j];
         if (Ao) Ao[e] = fac * A[v][j];
@@ -2182,6 +2185,17 @@ int orc_tree_terms(const orc_config *c, long nleaf, const int *lev, const long *
   }
   tree_free(T); free(T);
   return st;
+}
+
+int orc_tree_terms(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                   const double *w, double *Vo, double *So, double *Ao) {
+  return tree_terms(c, nleaf, lev, ix, iy, w, nleaf, NULL, Vo, So, Ao);
+}
+
+/* The same for the listed leaves only (sampled checks of large meshes). */
+int orc_tree_terms_cells(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy,
+                         const double *w, long ncells, const long *cells, double *Vo, double *So, double *Ao) {
+  return tree_terms(c, nleaf, lev, ix, iy, w, ncells, cells, Vo, So, Ao);
 }
 
 /* L = dw/dt on every leaf: (2/dx_i) 2^-d (V - S) with the leaf's own edge. */
@@ -2273,7 +2287,8 @@ static void tree_region_mean(const tree *T, const double *w, const int *lev, int
  * there (tree_region_mean, from the state before any limiting), the TVB
  * bound uses the leaf's own edge, and a leaf with finer neighbours also
  * checks positivity at its trace points on the faces to them. */
-int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, double *w) {
+static int tree_limit(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, double *w,
+                      const unsigned char *skip) {
   tree *T = malloc(sizeof(tree));
   int st = tree_init(c, nleaf, lev, ix, iy, T);
   if (st != ORC_OK) { free(T); return st; }
@@ -2281,10 +2296,11 @@ int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *
   int nv = X->nvar, N = X->N;
   long bad = 0;
   if (c->limiter) {
-    double *nbm = malloc(sizeof(double) * 4 * nv * nleaf);
+    double *nbm = calloc((size_t)4 * nv * nleaf, sizeof(double));
     double *dxc = malloc(sizeof(double) * nleaf);
     for (long i = 0; i < nleaf; ++i) {
       dxc[i] = X->dx / (double)(1L << lev[i]);
+      if (skip && skip[i]) continue;
       for (int a = 0; a < 2; ++a)
         for (int s = 0; s < 2; ++s) {
           long Xn = ix[i] + (a == 0 ? (s ? 1 : -1) : 0), Yn = iy[i] + (a == 1 ? (s ? 1 : -1) : 0);
@@ -2298,8 +2314,8 @@ int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *
           for (int v = 0; v < nv; ++v) nbm[((long)(2 * a + s) * nv + v) * nleaf + i] = m[v];
         }
     }
-    if (c->limiter == 2) char_limit(X, w, nbm, dxc, NULL);
-    else slope_limit(X, w, nbm, dxc, NULL);
+    if (c->limiter == 2) char_limit(X, w, nbm, dxc, skip);
+    else slope_limit(X, w, nbm, dxc, skip);
     free(nbm); free(dxc);
   }
   if (c->positivity) {
@@ -2307,7 +2323,7 @@ int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *
     int *xcnt = calloc(nleaf, sizeof(int));
     double *xphi = malloc(sizeof(double) * nleaf * xmax * N);
     for (long i = 0; i < nleaf; ++i)
-      for (int a = 0; a < 2; ++a) {
+      for (int a = 0; a < 2 && !(skip && skip[i]); ++a) {
         int b = 1 - a;
         const long *t0 = b == 0 ? T->bx0 : T->by0, *t1 = b == 0 ? T->bx1 : T->by1;
         for (int s = 0; s < 2; ++s) {
@@ -2326,11 +2342,31 @@ int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *
           }
         }
       }
-    bad = positivity_limit(X, w, xcnt, xphi, xmax, NULL);
+    bad = positivity_limit(X, w, xcnt, xphi, xmax, skip);
     free(xcnt); free(xphi);
   }
   tree_free(T); free(T);
   return bad ? ORC_ENEGATIVE : ORC_OK;
+}
+
+int orc_tree_limit(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, double *w) {
+  return tree_limit(c, nleaf, lev, ix, iy, w, NULL);
+}
+
+/* The limiters on the listed leaves only (neighbour values from the state as
+ * given; the other leaves are left as they are). */
+int orc_tree_limit_cells(const orc_config *c, long nleaf, const int *lev, const long *ix, const long *iy, double *w,
+                         long ncells, const long *cells) {
+  unsigned char *skip = malloc(nleaf);
+  if (!skip) return ORC_ENOMEM;
+  memset(skip, 1, nleaf);
+  for (long k = 0; k < ncells; ++k) {
+    if (cells[k] < 0 || cells[k] >= nleaf) { free(skip); return ORC_EINVAL; }
+    skip[cells[k]] = 0;
+  }
+  int st = tree_limit(c, nleaf, lev, ix, iy, w, skip);
+  free(skip);
+  return st;
 }
 
 /* Physical coordinates of every leaf's volume nodes, x[2][Q][nleaf]. */

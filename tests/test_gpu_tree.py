@@ -234,3 +234,62 @@ def test_tree_projection_matches_oracle():
     s = dg.TreeSolver(wl, leaves)
     got = s.project(torch.from_numpy(np.ascontiguousarray(prim.transpose(2, 1, 0))).cuda()).cpu().numpy()
     check_state_modes(got, ref, "tree projection")
+
+
+@pytest.mark.slow
+def test_full_size_kh_tree_matches_oracle():
+    """The benchmark's quadtree KH mesh at full size (64^2 base adapted to the
+    criterion with up to 5 levels below it, 42 112 leaves): every adaptation's
+    leaf set equals the oracle's and every moved state matches it; then one
+    limited stage, checked on a seeded sample of leaves plus leaves on the
+    refinement boundaries against the oracle's per-leaf entries applied to the
+    GPU's own input (RHS per element, time step, stage, limiters)."""
+    n = 64
+    wl = workloads.workload("kh2d", rk="rk3", x0=(0.0, -0.3 / n, 0.0))
+    leaves = np.array([(0, x, y) for y in range(n) for x in range(n)])
+    o = oracle.TreeOracle(wl, leaves)
+    w0 = o.initial_state()
+    w, st = o.limit(w0)
+    assert st == 0
+    s = dg.TreeSolver(wl, leaves)
+    wg = s.limit(torch.from_numpy(w0).cuda())
+    check_state_modes(wg.cpu().numpy(), w, "limited initial state")
+    for it in range(6):
+        leaves, w = oracle.tree_adapt(wl, leaves, w, wl["wt"], wl["alpha"], 5)
+        wg = s.adapt(wg, wl["wt"], wl["alpha"], 5)
+        assert np.array_equal(s.leaves, leaves), f"mesh differs after adaptation {it + 1}"
+        check_state_modes(wg.cpu().numpy(), w, f"regrid {it + 1}")
+    nl = len(leaves)
+    say("leaves", nl, "per level", np.bincount(leaves[:, 0]))
+    assert nl > 40000 and leaves[:, 0].max() >= 4
+    o = oracle.TreeOracle(wl, leaves)
+    # the sample: seeded leaves and leaves with a face neighbour on another level
+    where = {tuple(t): i for i, t in enumerate(leaves)}
+    edge = []
+    for i, (l, x, y) in enumerate(leaves):
+        for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+            key = (l, (x + dx) % (n << l), (y + dy) % (n << l))
+            if key not in where:
+                edge.append(i)
+                break
+    rng = workloads.splitmix64(2015, np.arange(1500)) % np.uint64(nl)
+    cells = np.unique(np.concatenate([rng.astype(np.int64), np.array(edge[::max(1, len(edge) // 1500)])]))
+    say("sampled leaves", cells.size, "on refinement boundaries", len(edge))
+    wnp = wg.cpu().numpy()
+    V, S, A = o.terms_cells(wnp, cells)
+    L = s.rhs(wg).cpu().numpy()
+    check_rhs_modes(L[:, :, cells], V, S, A, "full-size tree RHS")
+    dt = s.max_dt(wg)
+    dto = o.max_dt(wnp)
+    assert float(dt.item()) == pytest.approx(dto, rel=1e-14)
+    u1 = s.rk_stage(1, dt, None, wg)
+    ref = wnp[:, :, cells] + dto * (V - S)
+    from parity import stage_scale
+    check_state_modes(u1.cpu().numpy()[:, :, cells], ref, "full-size tree stage",
+                      scale=stage_scale(0.0, 1.0, dto, wnp[:, :, cells], wnp[:, :, cells], A))
+    u1np = u1.cpu().numpy()
+    lim = s.limit(u1).cpu().numpy()
+    refl, st = o.limit_cells(u1np, cells)
+    assert st == 0
+    check_state_modes(lim[:, :, cells], refl, "full-size tree limiters")
+    assert s.status() == 0

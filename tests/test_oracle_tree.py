@@ -286,3 +286,18 @@ def test_tree_positivity_checks_the_hanging_face_points():
     wu = np.where(box.hole[None, None, :], wc[:, :, [0]], wc)  # hole cells: a plain cell's state
     gotu, _ = flat.limit(wu)
     assert np.array_equal(gotu[:, :, target], wc[:, :, target])
+
+
+def test_per_leaf_entries_equal_whole_mesh_calls():
+    n = (10, 10)
+    wl = _wl(n=n, k=2, ic="kh2d", length=(1.0, 1.0, 1.0), x0=(0.0, -0.01, 0.0), limiter=2, positivity=1, eps=0.95)
+    leaves = workloads.random_tree(n, 3, 0.4, 17)
+    t = oracle.TreeOracle(wl, leaves)
+    w = t.initial_state()
+    cells = np.array([0, 5, 17, len(leaves) // 2, len(leaves) - 1])
+    V, S, A = t.terms(w)
+    Vc, Sc, Ac = t.terms_cells(w, cells)
+    assert np.array_equal(Vc, V[:, :, cells]) and np.array_equal(Sc, S[:, :, cells]) and np.array_equal(Ac, A[:, :, cells])
+    full, st = t.limit(w)
+    part, st2 = t.limit_cells(w, cells)
+    assert st == st2 == 0 and np.array_equal(part, full[:, :, cells])
