@@ -336,7 +336,11 @@ int dg_adjoint_rk_stage(dg_ctx *ctx, int stage, const double *dt_dev, const doub
  * A tree-based mesh of leaf cells: every cell can be split into four children
  * at any level (Sec. 4), leaf (level, ix, iy) covering
  * [x0 + ix h, x0 + (ix+1) h) x [y0 + iy h, y0 + (iy+1) h) with h = dx / 2^level
- * over the context's base grid (level 0).  Across a face the level jump is
+ * over the context's base grid (level 0).  Once dg_tree_set has given a
+ * context a tree, the grid calls above (dg_rhs, dg_rk_stage, dg_max_dt,
+ * dg_max_rate, dg_rk_step, dg_tableau_*, dg_limit, dg_set_gravity,
+ * dg_amr_*, dg_adjoint_*, dg_rhs_noalloc) return DG_EINVAL on it, and
+ * dg_state_size and dg_project count leaves.  Across a face the level jump is
  * at most one: a side has one neighbour or two finer ones, whose faces are
  * integrated with the coarse trace at the mapped nodes (eta + sigma)/2 and the
  * weight w_r / 2 on the coarse side (Sec. 4).  A tree *state* is a device

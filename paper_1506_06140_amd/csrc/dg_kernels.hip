@@ -5162,7 +5162,7 @@ void dg_destroy(dg_ctx *c) {
 
 int dg_state_size(const dg_ctx *c, int64_t *n) {
   if (!c || !n) return DG_EINVAL;
-  *n = (int64_t)c->sh.nv * c->sh.N * c->ncell;
+  *n = (int64_t)c->sh.nv * c->sh.N * (c->tree ? (long)c->tleaves.size() / 3 : c->ncell);
   return DG_OK;
 }
 
@@ -5200,12 +5200,12 @@ int dg_project(dg_ctx *c, const double *prim, double *w, void *stream) {
 }
 
 int dg_rhs(dg_ctx *c, const double *w, double *L, void *stream) {
-  if (!c || !w || !L || w == L) return DG_EINVAL;
+  if (!c || !w || !L || w == L || c->tree) return DG_EINVAL;
   return dispatch(c, StageLaunch{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
 }
 
 int dg_rhs_noalloc(dg_ctx *c, const double *w, double *L, void *stream) {
-  if (!c || !w || !L || w == L) return DG_EINVAL;
+  if (!c || !w || !L || w == L || c->tree) return DG_EINVAL;
   if (c->cfg.precision != DG_BF16_VOL) return DG_EINVAL;
   // the fused 3D kernel keeps its volume term in registers: nothing to stage
   if (c->tabvb) return dispatch(c, StageLaunch{c, w, nullptr, L, 0, dg::Mix{}, (hipStream_t)stream});
@@ -5224,7 +5224,7 @@ int dg_rhs_noalloc(dg_ctx *c, const double *w, double *L, void *stream) {
 
 int dg_rk_stage(dg_ctx *c, int stage, const double *dt, const double *wn, const double *wp, double *out,
                 void *stream) {
-  if (!c || !dt || !wp || !out || stage < 1 || stage > 3) return DG_EINVAL;
+  if (!c || !dt || !wp || !out || stage < 1 || stage > 3 || c->tree) return DG_EINVAL;
   if (stage > 1 && !wn) return DG_EINVAL;
   if (out == wp || out == wn) return DG_EINVAL;
   return dispatch(c, StageLaunch{c, wp, dt, out, 1, rk3_mix(stage, wn), (hipStream_t)stream});
@@ -5236,7 +5236,7 @@ int dg_set_tableau(dg_ctx *c, int stages, const double *a, const double *b) {
 }
 
 int dg_tableau_stage(dg_ctx *c, int m, const double *dt, const double *const *y, double *out, void *stream) {
-  if (!c || !dt || !y || !out || m < 1 || m > c->rk_s) return DG_EINVAL;
+  if (!c || !dt || !y || !out || m < 1 || m > c->rk_s || c->tree) return DG_EINVAL;
   for (int j = 0; j < m; ++j)
     if (!y[j] || y[j] == out) return DG_EINVAL;
   return dispatch(c, StageLaunch{c, y[m - 1], dt, out, 1, tableau_mix(c, m, y), (hipStream_t)stream});
@@ -5244,7 +5244,7 @@ int dg_tableau_stage(dg_ctx *c, int m, const double *dt, const double *const *y,
 
 
 int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
-  if (!c || !w || !dt) return DG_EINVAL;
+  if (!c || !w || !dt || c->tree) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long *rm = reinterpret_cast<unsigned long long *>(c->partial);
   int st = rate_fold(c, w, rm, s);
@@ -5255,7 +5255,7 @@ int dg_max_dt(dg_ctx *c, const double *w, double *dt, void *stream) {
 }
 
 int dg_max_rate(dg_ctx *c, const double *w, double *rate, void *stream) {
-  if (!c || !w || !rate) return DG_EINVAL;
+  if (!c || !w || !rate || c->tree) return DG_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   unsigned long long *rm = reinterpret_cast<unsigned long long *>(rate);
   hipLaunchKernelGGL(dg::k_rate_zero, dim3(1), dim3(64), 0, s, rm);
@@ -5265,7 +5265,7 @@ int dg_max_rate(dg_ctx *c, const double *w, double *rate, void *stream) {
 
 int dg_rk_step(dg_ctx *c, const double *w, double *u1, double *u2, double *out, double *dt, double *rate,
                void *stream) {
-  if (!c || !w || !u1 || !u2 || !out || !dt || !rate) return DG_EINVAL;
+  if (!c || !w || !u1 || !u2 || !out || !dt || !rate || c->tree) return DG_EINVAL;
   const void *st_ptr[4] = {w, u1, u2, out};
   for (int i = 0; i < 4; ++i)
     for (int j = i + 1; j < 4; ++j)
@@ -5293,7 +5293,7 @@ int dg_rk_step(dg_ctx *c, const double *w, double *u1, double *u2, double *out, 
 
 int dg_tableau_step(dg_ctx *c, const double *w, double *const *stage, double *out, double *dt, double *rate,
                     void *stream) {
-  if (!c || !w || !out || !dt || !rate) return DG_EINVAL;
+  if (!c || !w || !out || !dt || !rate || c->tree) return DG_EINVAL;
   const int ns = c->rk_s;
   if (ns > 1 && !stage) return DG_EINVAL;
   const double *Y[DG_MAX_STAGES + 1];
@@ -5337,13 +5337,13 @@ int dg_tableau_step(dg_ctx *c, const double *w, double *const *stage, double *ou
 }
 
 int dg_limit(dg_ctx *c, double *w, void *stream) {
-  if (!c || !w) return DG_EINVAL;
+  if (!c || !w || c->tree) return DG_EINVAL;
   if (c->cfg.slope_limiter == DG_LIM_NONE && !c->cfg.positivity) return DG_OK;
   return dispatch(c, LimitLaunch{c, w, (hipStream_t)stream});
 }
 
 int dg_set_gravity(dg_ctx *c, const double *accel, void *stream) {
-  if (!c) return DG_EINVAL;
+  if (!c || c->tree) return DG_EINVAL;
   if (!accel) {
     c->gravity = false;
     return DG_OK;
@@ -5374,13 +5374,13 @@ int dg_set_gravity(dg_ctx *c, const double *accel, void *stream) {
 }
 
 int dg_amr_flags(dg_ctx *c, const double *w, double wt, double alpha, int *flags, int *box, void *stream) {
-  if (!c || !w || !flags || !box || !(wt > 0.0) || !(alpha >= 1.0)) return DG_EINVAL;
+  if (!c || !w || !flags || !box || !(wt > 0.0) || !(alpha >= 1.0) || c->tree) return DG_EINVAL;
   if (c->sh.k > 3) return DG_EUNSUPPORTED;
   return dispatch(c, AmrFlagsLaunch{c, w, alpha * wt, wt / alpha, flags, box, (hipStream_t)stream});
 }
 
 int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *w_to, void *stream) {
-  if (!from || !to || !w_from || !w_to || w_from == w_to) return DG_EINVAL;
+  if (!from || !to || !w_from || !w_to || w_from == w_to || from->tree || to->tree) return DG_EINVAL;
   if (from->sh.d != to->sh.d || from->sh.k != to->sh.k || from->nx != to->nx || from->ny != to->ny ||
       from->nz != to->nz || from->dx != to->dx || from->device != to->device)
     return DG_EINVAL;
@@ -5391,14 +5391,14 @@ int dg_amr_regrid(const dg_ctx *from, const double *w_from, dg_ctx *to, double *
 }
 
 int dg_adjoint_rhs(dg_ctx *c, const double *w, const double *lam, double *mu, void *stream) {
-  if (!c || !w || !lam || !mu || mu == w || mu == lam) return DG_EINVAL;
+  if (!c || !w || !lam || !mu || mu == w || mu == lam || c->tree) return DG_EINVAL;
   if (c->amr || c->gravity) return DG_EUNSUPPORTED;
   return dispatch(c, AdjointLaunch{c, w, lam, nullptr, mu, nullptr, nullptr, 0, 0.0, 0.0, (hipStream_t)stream});
 }
 
 int dg_adjoint_rk_stage(dg_ctx *c, int stage, const double *dt, const double *u, const double *lam,
                         const double *acc, double *lam_out, double *acc_out, void *stream) {
-  if (!c || !dt || !u || !lam || !lam_out || stage < 1 || stage > 3) return DG_EINVAL;
+  if (!c || !dt || !u || !lam || !lam_out || stage < 1 || stage > 3 || c->tree) return DG_EINVAL;
   if (c->amr || c->gravity) return DG_EUNSUPPORTED;
   if (lam_out == lam || lam_out == u || (acc && lam_out == acc)) return DG_EINVAL;
   if (stage != 3 && !acc) return DG_EINVAL;

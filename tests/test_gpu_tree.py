@@ -293,3 +293,45 @@ def test_full_size_kh_tree_matches_oracle():
     assert st == 0
     check_state_modes(lim[:, :, cells], refl, "full-size tree limiters")
     assert s.status() == 0
+
+
+def test_tree_step_graph_replays_match_eager():
+    """The limited tree step (time step, three stages, limiters with their
+    positivity list) captured in a HIP graph: several replays, with eager
+    work and synchronisations between them, each equal to the eager step
+    bit for bit."""
+    wl, leaves = LIMITED["k3_char_band3"][0](), LIMITED["k3_char_band3"][1]()
+    o = oracle.TreeOracle(wl, leaves)
+    w0 = torch.from_numpy(o.initial_state()).cuda()
+    s = dg.TreeSolver(wl, leaves)
+    bufs = [s.empty() for _ in range(3)] + [s.scalar()]
+    eager = s.step(w0, bufs).clone()
+    src = w0.clone()
+    stream = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        s.step(src, bufs)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        s.step(src, bufs)
+    for rep in range(4):
+        s.rhs(w0)  # eager work between the replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(bufs[2], eager), f"replay {rep + 1} differs from the eager step"
+    assert s.status() == 0
+
+
+def test_grid_calls_refuse_a_tree_context():
+    import ctypes as C
+    wl = _vortex((4, 4), 2)
+    s = dg.TreeSolver(wl, workloads.random_tree((4, 4), 2, 0.5, 3))
+    w = s.empty()
+    with pytest.raises(dg.DGError):
+        dg.Solver.rhs(s, w)
+    n = C.c_int64()
+    assert s.lib.dg_state_size(s.ctx, C.byref(n)) == 0 and n.value == w.numel()
