@@ -5567,12 +5567,29 @@ int grow_ints(int *&p, long &cap, long n) {
   return DG_OK;
 }
 
-// makes `lv` the context's mesh (device tables replaced after the device is idle)
+int tree_upload(dg_ctx *c, std::vector<int32_t> &lv, TreeIndex &ix, const std::vector<int> &T);
+
+// makes `lv` the context's mesh (device tables replaced after the device is
+// idle).  An invalid mesh leaves the context as it was; a failure while the
+// device tables are replaced leaves it without a mesh (the tree calls then
+// refuse with DG_EINVAL) rather than with tables of one mesh and leaves of
+// another.
 int tree_install(dg_ctx *c, std::vector<int32_t> lv) {
   TreeIndex ix;
   std::vector<int> T;
   int st = tree_tables(c, lv, ix, T);
   if (st != DG_OK) return st;
+  st = tree_upload(c, lv, ix, T);
+  if (st != DG_OK) {
+    c->tree = false;
+    c->tleaves.clear();
+    c->tnext.clear();
+  }
+  return st;
+}
+
+int tree_upload(dg_ctx *c, std::vector<int32_t> &lv, TreeIndex &ix, const std::vector<int> &T) {
+  int st = DG_OK;
   HIP_TRY(hipDeviceSynchronize());
   st = grow_ints(c->ttab, c->ttab_cap, (long)T.size());
   if (st != DG_OK) return st;
