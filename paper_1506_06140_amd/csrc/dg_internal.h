@@ -45,6 +45,7 @@ Layout make_layout(const Shape &s);
 // Host tables for (d, k); also returns the first GLL weight.
 std::vector<double> build_tables(const Shape &s, double *gll_w1);
 std::vector<double> refine_matrices(const Shape &s);  // [2^d][N][N] (eq. ref_pa_integral)
+std::vector<double> tables_1d(int k);  // 1D tables of the quadtree stage kernel (2D)
 
 // Exponent triples of the modes in the library's mode order.
 std::vector<int> mode_exponents(int d, int k);
@@ -105,5 +106,6 @@ struct dg_ctx {
   int *tplist = nullptr;  // positivity: count, then the leaves that need the point loop
   long ttab_cap = 0, tmap_cap = 0, tflags_cap = 0, treg_cap = 0, tplist_cap = 0;
   double *tnbm = nullptr;  // limiters' neighbour values [4][nvar][nleaf]
+  double *t1d = nullptr;   // 1D tables of the quadtree stage kernel (dg::tables_1d; 2D, k <= 3)
   long tnbm_cap = 0;
 };

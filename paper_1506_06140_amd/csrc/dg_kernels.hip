@@ -3804,19 +3804,78 @@ struct TreeGrid {
   double fac0;      // (2/dx) 2^-d of level 0
   double dx0;
   double gamma;
+  const double *t1; // 1D tables (tables_1d)
 };
+
+// Right-hand side and fused stage on the quadtree, one thread per leaf.
+// Volume integral as on uniform grids; each side is one face (same level,
+// wall), two half faces (finer neighbours: this leaf's trace at the mapped
+// nodes (eta + sigma)/2, lifted with w_r / 2) or one face against a coarser
+// neighbour (its trace at this leaf's half).  The contractions are
+// sum-factorised along one axis.  The total-degree basis is not a tensor product, but each of its
+// modes is P~_ex(xi) P~_ey(eta): a trace on a face normal to x is
+// sum_ey P~_ey(eta) [sum over the modes of that ey of w_l P~_ex(+-1)], the
+// lift the transpose of that, and the volume integral goes one column of
+// x-nodes at a time, contracting over ex first (tables_1d).  Both leaves of a
+// face form a trace with the same function (tree_trace), weights and tables,
+// so they obtain the same flux bit for bit.
+// f(std::integral_constant<int, I>) for I = B .. E-1: the mode index is a
+// compile-time constant, so register arrays indexed by a mode's exponents
+// stay in registers
+template <int B, int E, class F>
+__device__ inline void static_for(F &&f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+template <int K>
+struct Tree1D {
+  static constexpr int n1 = K + 1, PG = 0, DG = n1 * n1, GW = 2 * n1 * n1, PB = GW + n1, PH = PB + 2 * n1;
+};
+
+// values of the four variables of weights ws at the n1 nodes of a face
+// normal to axis a at xi_a = -1 (s = 0) or +1 (s = 1), the tangential node
+// coordinates' Legendre values in rows of tt ([n1][n1]); out[r][v]
+template <int K, int A>
+__device__ inline void tree_trace(const double (&ws)[4][Cfg<2, K>::N], const double *t1, int s, const double *tt,
+                                  double (&out)[K + 1][4]) {
+  using T = Tree1D<K>;
+  constexpr int N = Cfg<2, K>::N, n1 = K + 1;
+  const double *pb = t1 + T::PB + s * n1;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double c[n1];
+#pragma unroll
+    for (int e = 0; e < n1; ++e) c[e] = 0.0;
+    static_for<0, N>([&](auto L_) {
+      // normal and tangential exponents of mode l on a face normal to axis A
+      constexpr int l = decltype(L_)::value, nrm = mode_exp<2>(l, A), tan = mode_exp<2>(l, 1 - A);
+      c[tan] = fma(ws[v][l], pb[nrm], c[tan]);
+    });
+#pragma unroll
+    for (int r = 0; r < n1; ++r) {
+      double u = 0.0;
+#pragma unroll
+      for (int e = 0; e < n1; ++e) u = fma(c[e], tt[r * n1 + e], u);
+      out[r][v] = u;
+    }
+  }
+}
 
 template <int K, int FX>
 __global__ __launch_bounds__(256) void k_rhs_tree(const double *__restrict__ tab, const double *__restrict__ w,
-                                                  double *__restrict__ out, const double *__restrict__ dtp,
-                                                  TreeGrid g, int mode, Mix mx, int *__restrict__ flag) {
+                                                     double *__restrict__ out, const double *__restrict__ dtp,
+                                                     TreeGrid g, int mode, Mix mx, int *__restrict__ flag) {
   using C = Cfg<2, K>;
-  constexpr int NV = C::NV, N = C::N, QF = C::QF;
+  using T = Tree1D<K>;
+  constexpr int NV = C::NV, N = C::N, n1 = K + 1;
   const long cell = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= g.nleaf) return;
   const long nl = g.nleaf;
   const double gm1 = g.gamma - 1.0;
-  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
+  const double *t1 = g.t1;
   double wc[NV][N], acc[NV][N];
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -3825,28 +3884,60 @@ __global__ __launch_bounds__(256) void k_rhs_tree(const double *__restrict__ tab
       wc[v][l] = w[(long)(v * N + l) * nl + cell];
       acc[v][l] = 0.0;
     }
-  // volume integral (eq. dg_term2); the mean's gradient is zero
+  // volume integral (eq. dg_term2), one column of x-nodes (index i) at a time
 #pragma unroll 1
-  for (int q = 0; q < C::Q; ++q) {
-    double U[NV];
-    const double *bq = tab + C::B + q * N;
+  for (int i = 0; i < n1; ++i) {
+    const double *pgi = t1 + T::PG + i * n1;
+    const double *dgi = t1 + T::DG + i * n1;
+    const double wi = t1[T::GW + i];
+    // t[v][ey] = sum over the modes of exponent ey of w_l P~_ex(g_i)
+    double tc[NV][n1], rx[NV][n1], ry[NV][n1];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      double s = 0.0;
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-      for (int l = 0; l < N; ++l) s = fma(wc[v][l], bq[l], s);
-      U[v] = s;
-    }
+      for (int e = 0; e < n1; ++e) {
+        tc[v][e] = 0.0;
+        rx[v][e] = 0.0;
+        ry[v][e] = 0.0;
+      }
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      double F[NV];
-      euler_flux<2, double>(U, a, gm1, F);
-      const double *dw = tab + C::DW + (a * C::Q + q) * N;
+    for (int v = 0; v < NV; ++v)
+      static_for<0, N>([&](auto L_) {
+        constexpr int l = decltype(L_)::value, ex = mode_exp<2>(l, 0), ey = mode_exp<2>(l, 1);
+        tc[v][ey] = fma(wc[v][l], pgi[ex], tc[v][ey]);
+      });
+#pragma unroll 1
+    for (int j = 0; j < n1; ++j) {
+      const double *pgj = t1 + T::PG + j * n1;
+      const double *dgj = t1 + T::DG + j * n1;
+      const double wj = t1[T::GW + j];
+      double U[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double u = 0.0;
+#pragma unroll
+        for (int e = 0; e < n1; ++e) u = fma(tc[v][e], pgj[e], u);
+        U[v] = u;
+      }
+      double Fx[NV], Fy[NV];
+      euler_flux<2, double>(U, 0, gm1, Fx);
+      euler_flux<2, double>(U, 1, gm1, Fy);
+      // rx[v][ey] += F_x P~_ey(g_j) w_j,  ry[v][ey] += F_y P~_ey'(g_j) w_j
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int l = 1; l < N; ++l) acc[v][l] = fma(F[v], dw[l], acc[v][l]);
+        for (int e = 0; e < n1; ++e) {
+          rx[v][e] = fma(Fx[v] * wj, pgj[e], rx[v][e]);
+          ry[v][e] = fma(Fy[v] * wj, dgj[e], ry[v][e]);
+        }
     }
+    // V_l += w_i (P~_ex'(g_i) rx[ey] + P~_ex(g_i) ry[ey])
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      static_for<1, N>([&](auto L_) {
+        constexpr int l = decltype(L_)::value, ex = mode_exp<2>(l, 0), ey = mode_exp<2>(l, 1);
+        acc[v][l] = fma(wi, fma(dgi[ex], rx[v][ey], pgi[ex] * ry[v][ey]), acc[v][l]);
+      });
   }
   // face integrals (eq. dg_term3) over the sides' halves
 #pragma unroll 1
@@ -3859,41 +3950,69 @@ __global__ __launch_bounds__(256) void k_rhs_tree(const double *__restrict__ tab
     for (int sb = 0; sb < nsub; ++sb) {
       const long nbc = (kind == 1) ? cell : (long)g.nb[(long)(2 * side + sb) * nl + cell];
       const int hs = (kind == 2) ? sb : sub;
-      double wnb[NV][N];
+      const double *tto = (kind == 2) ? t1 + T::PH + hs * n1 * n1 : t1 + T::PG;
+      const double *ttn = (kind == 3) ? t1 + T::PH + hs * n1 * n1 : t1 + T::PG;
+      double Uo[n1][NV], Un[n1][NV];
+      if (a == 0)
+        tree_trace<K, 0>(wc, t1, s, tto, Uo);
+      else
+        tree_trace<K, 1>(wc, t1, s, tto, Uo);
+      {
+        double wn[NV][N];
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+          for (int l = 0; l < N; ++l) wn[v][l] = w[(long)(v * N + l) * nl + nbc];
+        if (a == 0)
+          tree_trace<K, 0>(wn, t1, 1 - s, ttn, Un);
+        else
+          tree_trace<K, 1>(wn, t1, 1 - s, ttn, Un);
+      }
+      const double half = (kind == 2) ? 0.5 : 1.0;
+      double m[NV][n1];
 #pragma unroll
       for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int l = 0; l < N; ++l) wnb[v][l] = w[(long)(v * N + l) * nl + nbc];
-      const double *to = (kind == 2) ? tab + C::HG + ((a * 2 + s) * 4 + hs) * QF * N : tab + C::TF + (a * 2 + s) * QF * N;
-      const double *tn = (kind == 3) ? tab + C::HG + ((a * 2 + (1 - s)) * 4 + hs) * QF * N
-                                     : tab + C::TF + (a * 2 + (1 - s)) * QF * N;
-      const double *tw = (kind == 2) ? tab + C::HW + ((a * 2 + s) * 4 + hs) * QF * N : tab + C::TW + (a * 2 + s) * QF * N;
-#pragma unroll 1
-      for (int r = 0; r < QF; ++r) {
+        for (int e = 0; e < n1; ++e) m[v][e] = 0.0;
+#pragma unroll
+      for (int r = 0; r < n1; ++r) {
         double UL[NV], UR[NV], F[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          double so = 0.0, sn = 0.0;
-#pragma unroll
-          for (int l = 0; l < N; ++l) {
-            so = fma(wc[v][l], to[r * N + l], so);
-            sn = fma(wnb[v][l], tn[r * N + l], sn);
-          }
-          const double un = (kind == 1) ? so : sn;
-          UL[v] = s ? so : un;
-          UR[v] = s ? un : so;
+          const double un = (kind == 1) ? Uo[r][v] : Un[r][v];
+          UL[v] = s ? Uo[r][v] : un;
+          UR[v] = s ? un : Uo[r][v];
         }
         hllc<double, 2, FX>(UL, UR, a, g.gamma, F);
+        const double wr = half * t1[T::GW + r];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-          const double f = s ? -F[v] : F[v];
+          const double f = (s ? -F[v] : F[v]) * wr;
 #pragma unroll
-          for (int l = 0; l < N; ++l) acc[v][l] = fma(f, tw[r * N + l], acc[v][l]);
+          for (int e = 0; e < n1; ++e) m[v][e] = fma(f, tto[r * n1 + e], m[v][e]);
         }
+      }
+      // lift: acc_l += P~_(normal exponent)(+-1) m[tangential exponent]
+      const double *pb = t1 + T::PB + s * n1;
+      if (a == 0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          static_for<0, N>([&](auto L_) {
+            constexpr int l = decltype(L_)::value, en = mode_exp<2>(l, 0), et = mode_exp<2>(l, 1);
+            acc[v][l] = fma(pb[en], m[v][et], acc[v][l]);
+          });
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+          static_for<0, N>([&](auto L_) {
+            constexpr int l = decltype(L_)::value, en = mode_exp<2>(l, 0), et = mode_exp<2>(l, 1);
+            acc[v][l] = fma(pb[et], m[v][en], acc[v][l]);
+          });
       }
     }
   }
   const double fac = g.fac0 * (double)(1 << g.lev[cell]);
+  const double cldt = (mode == 0) ? 0.0 : mx.cl * *dtp;
   bool bad = false;
 #pragma unroll
   for (int v = 0; v < NV; ++v)
@@ -5130,6 +5249,13 @@ int dg_init(const dg_config *cfg, dg_ctx **out) {
     if ((e = hipMalloc((void **)&c->prmat, P.size() * sizeof(double))) != hipSuccess) return fail(e);
     if ((e = hipMemcpy(c->prmat, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
       return fail(e);
+    if (cfg->dim == 2) {
+      // 1D tables of the quadtree stage kernel
+      const std::vector<double> t1 = dg::tables_1d(cfg->k);
+      if ((e = hipMalloc((void **)&c->t1d, t1.size() * sizeof(double))) != hipSuccess) return fail(e);
+      if ((e = hipMemcpy(c->t1d, t1.data(), t1.size() * sizeof(double), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    }
   }
   *out = c;
   return DG_OK;
@@ -5156,6 +5282,7 @@ void dg_destroy(dg_ctx *c) {
   if (c->tflags) (void)hipFree(c->tflags);
   if (c->treg) (void)hipFree(c->treg);
   if (c->tplist) (void)hipFree(c->tplist);
+  if (c->t1d) (void)hipFree(c->t1d);
   if (c->tnbm) (void)hipFree(c->tnbm);
   delete c;
 }
@@ -5553,6 +5680,7 @@ dg::TreeGrid make_tree_grid(const dg_ctx *c) {
   g.fac0 = 2.0 / c->dx / 4.0;
   g.dx0 = c->dx;
   g.gamma = c->cfg.gamma;
+  g.t1 = c->t1d;
   return g;
 }
 

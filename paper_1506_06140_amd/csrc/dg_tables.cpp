@@ -288,4 +288,32 @@ std::vector<double> refine_matrices(const Shape &s) {
   return P;
 }
 
+// One-dimensional tables of the quadtree stage kernel (2D, sum-factorised
+// along one axis): with n1 = k + 1 Gauss nodes g_i and weights w_i,
+//   PG [n1][n1]  P~_e(g_i)          DG [n1][n1]  P~_e'(g_i)
+//   GW [n1]      w_i                PB [2][n1]   P~_e(-1), P~_e(+1)
+//   PH [2][n1][n1] P~_e((g_r + sigma)/2), sigma = -1 (lower half), +1 (upper)
+std::vector<double> tables_1d(int k) {
+  const int n1 = k + 1;
+  std::vector<double> t((size_t)(4 * n1 * n1 + 3 * n1), 0.0);
+  double g[8], gw[8];
+  gauss_legendre(n1, g, gw);
+  const int PG = 0, DG = n1 * n1, GW = 2 * n1 * n1, PB = GW + n1, PH = PB + 2 * n1;
+  for (int i = 0; i < n1; ++i) {
+    t[GW + i] = gw[i];
+    for (int e = 0; e < n1; ++e) {
+      t[PG + i * n1 + e] = pt(e, g[i]);
+      t[DG + i * n1 + e] = dpt(e, g[i]);
+    }
+  }
+  for (int e = 0; e < n1; ++e) {
+    t[PB + e] = pt(e, -1.0);
+    t[PB + n1 + e] = pt(e, 1.0);
+  }
+  for (int h = 0; h < 2; ++h)
+    for (int r = 0; r < n1; ++r)
+      for (int e = 0; e < n1; ++e) t[PH + (h * n1 + r) * n1 + e] = pt(e, 0.5 * (g[r] + (h ? 1.0 : -1.0)));
+  return t;
+}
+
 }  // namespace dg
