@@ -194,8 +194,9 @@ def cpu_other_workloads():
     stage (RHS, update, limiters) of two coarse z-planes through the box
     and two fine z-planes, on the full-size initial projection (the
     whole-mesh limiting that precedes the run, about 45 s on one core, is
-    left out); and one whole-mesh stage of the 2D vortex at 512^2, k=3 (the
-    adjoint workload's forward pass)."""
+    left out); one whole-mesh stage of the 2D vortex at 512^2, k=3 (the
+    adjoint workload's forward pass); and one limited stage of 2 000 leaves
+    of the quadtree KH mesh."""
     import oracle
     aff = os.sched_getaffinity(0)
     core = min(aff)
@@ -241,6 +242,34 @@ def cpu_other_workloads():
         "value": o.ncell * o.N / el, "unit": METRIC, "cores": 1, "kind": "oracle",
         "sample": f"one SSP-RK3 stage of the full {wl['n'][0]}^2 k={wl['k']} vortex state ({el:.2f} s; the "
                   f"adjoint workload's forward pass), single-threaded C oracle pinned to core {core}"}
+    # the quadtree KH mesh of the tree variant, built by the oracle's own
+    # adaptation; one limited stage on 2 000 seeded leaves
+    n = 64
+    wl = workloads.workload("kh2d", rk="rk3", x0=(0.0, -0.3 / n, 0.0))
+    leaves = np.array([(0, x, y) for y in range(n) for x in range(n)])
+    o = oracle.TreeOracle(wl, leaves)
+    w, _ = o.limit(o.initial_state())
+    for _ in range(6):
+        leaves, w = oracle.tree_adapt(wl, leaves, w, wl["wt"], wl["alpha"], 5)
+    o = oracle.TreeOracle(wl, leaves)
+    cells = np.unique((workloads.splitmix64(2015, np.arange(2000)) % np.uint64(len(leaves))).astype(np.int64))
+    dt = o.max_dt(w)
+    os.sched_setaffinity(0, {core})
+    try:
+        t0 = time.perf_counter()
+        V, S, _ = o.terms_cells(w, cells)
+        oracle.rk3_combine(1, dt, w[:, :, cells], w[:, :, cells], V - S)
+        t1 = time.perf_counter()
+        o.limit_cells(w, cells)
+        t2 = time.perf_counter()
+    finally:
+        os.sched_setaffinity(0, aff)
+    out["kh2d_tree_k3"] = {
+        "value": cells.size * o.N / (t2 - t0), "unit": METRIC, "cores": 1, "kind": "oracle",
+        "sample": f"one limited SSP-RK3 stage (RHS + update {t1 - t0:.2f} s, limiters {t2 - t1:.2f} s) of "
+                  f"{cells.size} seeded leaves of the {len(leaves)}-leaf quadtree KH mesh (k=3); the oracle finds "
+                  f"neighbours by a brute-force search over all leaves, so its cost per leaf grows with the mesh; "
+                  f"single-threaded C oracle pinned to core {core}"}
     return out
 
 
